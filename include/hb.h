@@ -1,0 +1,201 @@
+/*
+ * hb.h -- C ABI of libhb, an MI355X (gfx950) implementation of the
+ * harmonic-balance (HB) Navier-Stokes residual and its explicit
+ * Runge-Kutta pseudo-time iteration on structured multi-block grids.
+ *
+ * The problem statement follows the paper (Jackson & Campobasso, COSA):
+ * a structured multi-block grid whose blocks meet at "cuts" (orphan
+ * paragraph after the Introduction, and the cut pseudo code in
+ * §MPI Optimisations), nharms harmonics per block giving the snapshots
+ * n = 0..2*nharms, npde = 4 conserved variables per snapshot (state array
+ * q(i, j, ipde, n) in the same section), bodies with lift/drag/moment per
+ * snapshot (cl(n, ibody), cd(n, ibody), cm(n, ibody), the force reduction
+ * in §MPI Optimisations) and Runge-Kutta steps.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - State layout (public, FP64): blocks one after another; within block b
+ *    q[n][v][j][i], n = 0..2*N_H, v = (rho, rho u, rho v, rho E), j = 0..nj-1,
+ *    i = 0..ni-1 (i fastest) -- the paper's q(i, j, ipde, n) in C order.
+ *    hb_state_size() gives the number of doubles.
+ *  - Non-dimensionalisation: rho_inf = 1, c_inf = 1, p_inf = 1/gamma,
+ *    |V_inf| = mach, reference length l_ref; angles in radians.
+ *  - Residual sign: R*_n = R(Q_n) + V (D Q)_n, with R the net outflow of
+ *    the cell and D the HB time-derivative matrix; V dQ/dtau = -R*.
+ *  - Device pointers: q, r, rbar, qbar, xybar, flowbar, cf, cfbar, resnorm,
+ *    forces are device memory owned by the caller (e.g. torch tensors).  They
+ *    must not alias each other unless stated.
+ *  - Streams: every call enqueues its work on `stream` (a hipStream_t passed
+ *    as void*, NULL = the null stream) and returns without synchronising,
+ *    except hb_grid_create, hb_grid_destroy and hb_get_status.
+ *  - Errors: a negative return code plus a thread-local message from
+ *    hb_last_error().  Argument checks run before any device work, so an
+ *    HB_ERR_ARG return leaves every buffer untouched.  No C++ exception
+ *    crosses this interface.  A grid handle is not thread-safe.
+ */
+#ifndef HB_H_
+#define HB_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hb_grid hb_grid;   /* opaque, owned by libhb */
+
+enum {
+    HB_OK = 0,
+    HB_ERR_ARG = -1,          /* invalid argument; nothing was done      */
+    HB_ERR_DEVICE = -2,       /* a HIP call failed                       */
+    HB_ERR_OOM = -3,          /* device allocation failed                */
+    HB_ERR_NONFINITE = -4,    /* a non-finite or non-physical state seen */
+    HB_ERR_UNSUPPORTED = -5   /* valid request this build does not do    */
+};
+
+/* Boundary kinds, per block side (imin, imax, jmin, jmax). */
+enum {
+    HB_BC_WALL = 1,       /* no-slip adiabatic wall: ghost k mirrors cell k   */
+    HB_BC_FARFIELD = 2,   /* both ghost layers = free stream at alpha(t_n)    */
+    HB_BC_PERIODIC = 3,   /* the block wraps onto itself (O-grid in i)        */
+    HB_BC_CUT = 4,        /* glued to another block side (see hb_cut)         */
+    HB_BC_WAKECUT = 5     /* jmin only: C-grid wake (cells i < wake_ncells and
+                             i >= ni - wake_ncells face each other), wall in
+                             between                                         */
+};
+
+enum { HB_FP64 = 0, HB_FP32_BULK = 1 };
+
+/* One structured block.  xy is HOST memory, [2][nj+1][ni+1] (x then y,
+ * i fastest), right-handed (i along the body, j outward); it is copied by
+ * hb_grid_create.  n_harm = N_H in 0..4 (N_s = 2 N_H + 1 snapshots).
+ * body_id >= 0 names the body whose loads this block's wall faces carry;
+ * bodies are numbered 0..nbody-1 without gaps, and all blocks of one body
+ * share n_harm. */
+typedef struct {
+    int32_t ni, nj;
+    int32_t n_harm;
+    const double *xy;
+    int32_t bc[4];
+    int32_t wake_ncells;
+    int32_t body_id;
+} hb_block;
+
+/* A cut glues the whole side `side_a` (0..3 = imin, imax, jmin, jmax) of
+ * block blk_a to the whole side side_b of block blk_b: the ghosts of each
+ * side are the other block's interior cells (Jacobi: both read the same
+ * stage input).  Supported: imax<->imin with equal nj and jmax<->jmin with
+ * equal ni, both with `reversed` = 0. */
+typedef struct {
+    int32_t blk_a, side_a, blk_b, side_b, reversed;
+} hb_cut;
+
+/* Free stream and forcing.  alpha(t) = alpha0 + alpha_amp sin(omega t),
+ * omega = 2 k_red mach / l_ref; snapshot n is at omega t_n = 2 pi n / N_s.
+ * mu = mach l_ref / reynolds (constant), Stokes hypothesis, heat flux
+ * -mu/((gamma-1) prandtl) grad(gamma p / rho).  (x_mom, y_mom): moment
+ * reference point. */
+typedef struct {
+    double mach, reynolds, prandtl, gamma;
+    double alpha0, alpha_amp, k_red, l_ref;
+    double x_mom, y_mom;
+} hb_flow;
+
+/* Pseudo-time and scheme settings.
+ *   cfl, n_stages (1..8), rk_alpha[n_stages]: Q(k) = Q(0) - a_k (dtau/V) R*(Q(k-1))
+ *   precision: HB_FP64, or HB_FP32_BULK (flux, source and time step in
+ *     FP32; state, update, norms and forces in FP64)
+ *   entropy_delta: Harten fix width as a fraction of the Roe sound speed
+ *   limiter_eps: van Albada epsilon
+ *   batched: 1 = all blocks in one persistent launch per stage (fused
+ *     line-tile kernel); 0 = plain per-block launches (separate ghost,
+ *     face-flux and update kernels, FP64 only)
+ *   graph_iters: iterations captured per HIP graph replay (>= 1) */
+typedef struct {
+    double cfl;
+    int32_t n_stages;
+    double rk_alpha[8];
+    int32_t precision;
+    double entropy_delta, limiter_eps;
+    int32_t batched, graph_iters;
+} hb_solver;
+
+/* Build a grid: copies the host arrays, computes the metrics on the device
+ * (FP64), allocates all scratch.  Validation (HB_ERR_ARG): nblocks >= 1,
+ * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
+ * [0, ni/2] and only with a WAKECUT jmin, cut sides consistent, bodies
+ * numbered without gaps with one n_harm each, every cell area > 0.
+ * Synchronises the current device.  *out is NULL on failure. */
+int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts,
+                   int32_t ncuts, const hb_flow *flow, const hb_solver *solver,
+                   hb_grid **out);
+
+/* Free everything hb_grid_create allocated (synchronises).  NULL is a no-op. */
+int hb_grid_destroy(hb_grid *g);
+
+/* Doubles in the state: sum over blocks of N_s * 4 * nj * ni.  -1 if g is NULL. */
+int64_t hb_state_size(const hb_grid *g);
+
+/* Doubles in a force array: 3 * sum over bodies of N_s(body); -1 if NULL. */
+int64_t hb_forces_size(const hb_grid *g);
+
+/* Doubles in the node-coordinate array: sum over blocks 2 (nj+1)(ni+1). */
+int64_t hb_xy_size(const hb_grid *g);
+
+/* r = R*(q), the HB residual of every cell and snapshot (public layout).
+ * q, r: device, hb_state_size() doubles each, must not overlap. */
+int hb_residual(hb_grid *g, const double *q, double *r, void *stream);
+
+/* n_iter pseudo-time iterations in place on q (device, public layout).
+ * resnorm (device, n_iter doubles, may be NULL): RMS of R*_rho / V over all
+ * cells and snapshots at the first stage of each iteration.
+ * forces (device, hb_forces_size() doubles, may be NULL): cl, cd, cm of the
+ * final state, layout [body][n][3].
+ * Non-finite states are flagged in a device status word, read by
+ * hb_get_status(). */
+int hb_rk_iterate(hb_grid *g, double *q, int32_t n_iter, double *resnorm,
+                  double *forces, void *stream);
+
+/* cf = (cl, cd, cm) per body and snapshot, layout [body][n][3] (bodies in
+ * id order, each with its own N_s); drag along the mean free stream
+ * (cos alpha0, sin alpha0), lift normal to it, cm positive nose-up, all on
+ * q_inf = mach^2/2 and l_ref.  Wall faces: -(p_w - p_inf) S + tau.S with
+ * p_w the adjacent cell's pressure.  FP64. */
+int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
+
+/* Reverse-mode (Jacobian-transpose) products of the residual R* = hb_residual:
+ *   qbar    = J_Q^T rbar,  J_Q = d R* / d Q        (state size, overwritten)
+ *   xybar   = J_X^T rbar,  X = node coordinates    (hb_xy_size(), may be NULL)
+ *   flowbar = J_a^T rbar,  a = alpha0              (1 double, may be NULL)
+ * The reconstruction is recomputed, nothing is stored between calls.
+ * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid). */
+int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar,
+                        double *qbar, double *xybar, double *flowbar, void *stream);
+
+/* Reverse-mode products of the force coefficients: with cfbar of the
+ * hb_forces layout, qbar/xybar/flowbar receive (d cf/d .)^T cfbar
+ * (overwritten; xybar and flowbar may be NULL). */
+int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
+                      double *qbar, double *xybar, double *flowbar, void *stream);
+
+/* Replace the node coordinates (device, hb_xy_size() doubles, same layout as
+ * the blocks' xy, concatenated) and recompute the metrics on `stream`. */
+int hb_set_xy(hb_grid *g, const double *xy, void *stream);
+
+/* Replace the mean incidence alpha0 (radians); takes effect for work
+ * enqueued afterwards. */
+int hb_set_alpha0(hb_grid *g, double alpha0);
+
+/* Synchronise and return HB_ERR_NONFINITE if any iteration since the last
+ * call met a non-finite residual or a non-positive density or pressure
+ * (the flag is then cleared), else HB_OK. */
+int hb_get_status(hb_grid *g);
+
+/* Message of the last error on this thread ("" if none). */
+const char *hb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H_ */

@@ -1,0 +1,486 @@
+// C ABI of libhb: argument validation, grid construction (device memory,
+// block table, per-snapshot tables, HB matrices, metrics) and dispatch of
+// each entry point to the plain or the fused kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hb_internal.hpp"
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace hb {
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return HB_OK;
+    return fail(e == hipErrorOutOfMemory ? HB_ERR_OOM : HB_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+template <class T>
+int dalloc(T **p, int64_t n) {
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(HB_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return HB_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_all(hb_grid *g) {
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
+    dfree(g->blk_d);
+    dfree(g->xy_d);
+    dfree(g->SI_d); dfree(g->dI_d); dfree(g->SJ_d); dfree(g->dJ_d);
+    dfree(g->V_d); dfree(g->C_d);
+    dfree(g->SI_f); dfree(g->dI_f); dfree(g->SJ_f); dfree(g->dJ_f); dfree(g->V_f);
+    dfree(g->D_d); dfree(g->D_f);
+    dfree(g->ffw_d); dfree(g->ffq_d); dfree(g->dqinf_d);
+    dfree(g->ffw_f); dfree(g->ffq_f); dfree(g->dqinf_f);
+    dfree(g->ext_d); dfree(g->FI_d); dfree(g->FJ_d);
+    dfree(g->q0_d); dfree(g->qa_d); dfree(g->qb_d);
+    dfree(g->sa_f); dfree(g->sb_f);
+    dfree(g->partials_d); dfree(g->fpart_d); dfree(g->norm_tmp_d);
+    dfree(g->status_d); dfree(g->ctr_d);
+    dfree(g->body_off_d); dfree(g->body_ns_d);
+    dfree(g->tiles_d);
+    dfree(g->adj_d);
+}
+
+bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_WAKECUT; }
+
+// HB time-derivative matrix, closed form of the odd-N spectral
+// differentiation matrix: D[n][m] = (omega/2) (-1)^(n-m) / sin(pi (n-m) / N).
+void hb_matrix(int nh, double omega, double *D /* kNsPad x kNsPad */) {
+    const int ns = 2 * nh + 1;
+    for (int k = 0; k < kNsPad * kNsPad; ++k) D[k] = 0.0;
+    for (int n = 0; n < ns; ++n)
+        for (int m = 0; m < ns; ++m) {
+            if (n == m) continue;
+            const int d = n - m;
+            const double sgn = (d % 2 == 0) ? 1.0 : -1.0;
+            D[n * kNsPad + m] = 0.5 * omega * sgn / std::sin(M_PI * d / ns);
+        }
+}
+
+}  // namespace
+
+// Per-snapshot tables: free stream at alpha(t_n) and sum_m D[n][m] Q_inf(m).
+int upload_snapshot_tables(hb_grid *g) {
+    const hb_flow &f = g->flow;
+    const double omega = 2.0 * f.k_red * f.mach / f.l_ref;
+    std::vector<double> ffw(4 * g->n_snap), ffq(4 * g->n_snap), dq(4 * g->n_snap);
+    std::vector<double> D(kNsPad * kNsPad);
+    for (const BlockDesc &B : g->blk) {
+        hb_matrix(B.nh, omega, D.data());
+        for (int n = 0; n < B.ns; ++n) {
+            const double a = f.alpha0 + f.alpha_amp * std::sin(2.0 * M_PI * n / B.ns);
+            const double u = f.mach * std::cos(a), v = f.mach * std::sin(a), p = 1.0 / f.gamma;
+            double *w = &ffw[4 * (B.snap_off + n)];
+            double *q = &ffq[4 * (B.snap_off + n)];
+            w[0] = 1.0; w[1] = u; w[2] = v; w[3] = p;
+            q[0] = 1.0; q[1] = u; q[2] = v; q[3] = p / (f.gamma - 1.0) + 0.5 * (u * u + v * v);
+        }
+        for (int n = 0; n < B.ns; ++n)
+            for (int c = 0; c < 4; ++c) {
+                double s = 0.0;
+                for (int m = 0; m < B.ns; ++m) s += D[n * kNsPad + m] * ffq[4 * (B.snap_off + m) + c];
+                dq[4 * (B.snap_off + n) + c] = s;
+            }
+    }
+    std::vector<float> tmp(4 * g->n_snap);
+    int rc = check_hip(hipMemcpy(g->ffw_d, ffw.data(), sizeof(double) * ffw.size(), hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->ffq_d, ffq.data(), sizeof(double) * ffq.size(), hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->dqinf_d, dq.data(), sizeof(double) * dq.size(), hipMemcpyHostToDevice), "upload");
+    for (size_t k = 0; k < tmp.size() && !rc; ++k) tmp[k] = (float)ffw[k];
+    rc = rc ? rc : check_hip(hipMemcpy(g->ffw_f, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice), "upload");
+    for (size_t k = 0; k < tmp.size() && !rc; ++k) tmp[k] = (float)ffq[k];
+    rc = rc ? rc : check_hip(hipMemcpy(g->ffq_f, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice), "upload");
+    for (size_t k = 0; k < tmp.size() && !rc; ++k) tmp[k] = (float)dq[k];
+    rc = rc ? rc : check_hip(hipMemcpy(g->dqinf_f, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice), "upload");
+    return rc;
+}
+
+}  // namespace hb
+
+using namespace hb;
+
+extern "C" {
+
+const char *hb_last_error(void) { return g_err.c_str(); }
+
+int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, int32_t ncuts,
+                   const hb_flow *flow, const hb_solver *solver, hb_grid **out) {
+    g_err.clear();
+    if (!out) return fail(HB_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!blocks || nblocks < 1) return fail(HB_ERR_ARG, "need at least one block");
+    if (!flow || !solver) return fail(HB_ERR_ARG, "flow and solver must not be NULL");
+    if (ncuts < 0 || (ncuts > 0 && !cuts)) return fail(HB_ERR_ARG, "bad cut list");
+    if (!(flow->mach > 0) || !(flow->reynolds > 0) || !(flow->prandtl > 0) ||
+        !(flow->gamma > 1) || !(flow->l_ref > 0) || !std::isfinite(flow->alpha0) ||
+        !std::isfinite(flow->alpha_amp) || !std::isfinite(flow->k_red) || flow->k_red < 0)
+        return fail(HB_ERR_ARG, "invalid flow settings");
+    if (solver->n_stages < 1 || solver->n_stages > 8 || !(solver->cfl > 0) ||
+        (solver->precision != HB_FP64 && solver->precision != HB_FP32_BULK) ||
+        !(solver->entropy_delta >= 0) || !(solver->limiter_eps > 0) || solver->graph_iters < 1 ||
+        (solver->batched != 0 && solver->batched != 1))
+        return fail(HB_ERR_ARG, "invalid solver settings");
+    if (solver->precision == HB_FP32_BULK && !solver->batched)
+        return fail(HB_ERR_ARG, "FP32-bulk precision needs the batched (fused) path");
+    int nbody = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const hb_block &B = blocks[b];
+        char msg[160];
+        if (B.ni < 4 || B.nj < 4) {
+            std::snprintf(msg, sizeof msg, "block %d: ni, nj must be >= 4", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if ((int64_t)B.ni * B.nj > (int64_t)1 << 28) {
+            std::snprintf(msg, sizeof msg, "block %d: too many cells", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if (B.n_harm < 0 || B.n_harm > 4) {
+            std::snprintf(msg, sizeof msg, "block %d: n_harm must be in [0, 4]", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if (!B.xy) {
+            std::snprintf(msg, sizeof msg, "block %d: xy is NULL", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        for (int s = 0; s < 4; ++s)
+            if (!known_bc(B.bc[s]) || (B.bc[s] == HB_BC_WAKECUT && s != 2)) {
+                std::snprintf(msg, sizeof msg, "block %d: bad boundary kind on side %d", b, s);
+                return fail(HB_ERR_ARG, msg);
+            }
+        if ((B.bc[0] == HB_BC_PERIODIC) != (B.bc[1] == HB_BC_PERIODIC) ||
+            (B.bc[2] == HB_BC_PERIODIC) != (B.bc[3] == HB_BC_PERIODIC)) {
+            std::snprintf(msg, sizeof msg, "block %d: periodic sides must come in pairs", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if (B.wake_ncells < 0 || B.wake_ncells > B.ni / 2 ||
+            (B.wake_ncells > 0 && B.bc[2] != HB_BC_WAKECUT)) {
+            std::snprintf(msg, sizeof msg, "block %d: bad wake_ncells", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if (B.body_id < 0 || B.body_id >= nblocks) {
+            std::snprintf(msg, sizeof msg, "block %d: bad body_id", b);
+            return fail(HB_ERR_ARG, msg);
+        }
+        if (B.body_id + 1 > nbody) nbody = B.body_id + 1;
+        // positive areas (FP64, host)
+        const int W = B.ni + 1;
+        const int64_t nn = (int64_t)W * (B.nj + 1);
+        const double *x = B.xy, *y = B.xy + nn;
+        for (int j = 0; j < B.nj; ++j)
+            for (int i = 0; i < B.ni; ++i) {
+                const double x1 = x[j * W + i], y1 = y[j * W + i];
+                const double x2 = x[j * W + i + 1], y2 = y[j * W + i + 1];
+                const double x3 = x[(j + 1) * W + i + 1], y3 = y[(j + 1) * W + i + 1];
+                const double x4 = x[(j + 1) * W + i], y4 = y[(j + 1) * W + i];
+                const double v = 0.5 * ((x3 - x1) * (y4 - y2) - (y3 - y1) * (x4 - x2));
+                if (!(v > 0.0)) {
+                    std::snprintf(msg, sizeof msg, "block %d: cell (%d, %d) has area %g <= 0", b, i,
+                                  j, v);
+                    return fail(HB_ERR_ARG, msg);
+                }
+            }
+    }
+    std::vector<int> body_nh(nbody, -1);
+    for (int b = 0; b < nblocks; ++b) {
+        int &h = body_nh[blocks[b].body_id];
+        if (h >= 0 && h != blocks[b].n_harm) return fail(HB_ERR_ARG, "blocks of one body differ in n_harm");
+        h = blocks[b].n_harm;
+    }
+    for (int k = 0; k < nbody; ++k)
+        if (body_nh[k] < 0) return fail(HB_ERR_ARG, "body ids must be numbered without gaps");
+    // cuts
+    std::vector<int> cut_blk(4 * nblocks, -1), cut_side(4 * nblocks, -1);
+    for (int c = 0; c < ncuts; ++c) {
+        hb_cut k = cuts[c];
+        if (k.blk_a < 0 || k.blk_a >= nblocks || k.blk_b < 0 || k.blk_b >= nblocks ||
+            k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3 || k.reversed != 0)
+            return fail(HB_ERR_ARG, "bad cut");
+        if (k.side_a % 2 == 0) {   // normalise to (max side of a) <-> (min side of b)
+            std::swap(k.blk_a, k.blk_b);
+            std::swap(k.side_a, k.side_b);
+        }
+        const hb_block &A = blocks[k.blk_a], &B = blocks[k.blk_b];
+        const bool iok = k.side_a == 1 && k.side_b == 0 && A.nj == B.nj;
+        const bool jok = k.side_a == 3 && k.side_b == 2 && A.ni == B.ni;
+        if (!(iok || jok) || A.n_harm != B.n_harm)
+            return fail(HB_ERR_UNSUPPORTED, "only imax<->imin (equal nj) and jmax<->jmin (equal ni) "
+                                            "cuts between blocks of equal n_harm are supported");
+        if (A.bc[k.side_a] != HB_BC_CUT || B.bc[k.side_b] != HB_BC_CUT)
+            return fail(HB_ERR_ARG, "cut sides must have boundary kind HB_BC_CUT");
+        if (cut_blk[4 * k.blk_a + k.side_a] >= 0 || cut_blk[4 * k.blk_b + k.side_b] >= 0)
+            return fail(HB_ERR_ARG, "a block side is used by two cuts");
+        cut_blk[4 * k.blk_a + k.side_a] = k.blk_b;
+        cut_side[4 * k.blk_a + k.side_a] = k.side_b;
+        cut_blk[4 * k.blk_b + k.side_b] = k.blk_a;
+        cut_side[4 * k.blk_b + k.side_b] = k.side_a;
+    }
+    for (int b = 0; b < nblocks; ++b)
+        for (int s = 0; s < 4; ++s)
+            if (blocks[b].bc[s] == HB_BC_CUT && cut_blk[4 * b + s] < 0)
+                return fail(HB_ERR_ARG, "a HB_BC_CUT side has no cut");
+
+    // ---- device work starts here --------------------------------------
+    hb_grid *g = new (std::nothrow) hb_grid();
+    if (!g) return fail(HB_ERR_OOM, "host allocation failed");
+    int rc = check_hip(hipGetDevice(&g->device), "hipGetDevice");
+    if (rc) {
+        delete g;
+        return rc;
+    }
+    g->nblocks = nblocks;
+    g->nbody = nbody;
+    g->flow = *flow;
+    g->solver = *solver;
+    const double mu = flow->mach * flow->l_ref / flow->reynolds;
+    g->consts = Consts{flow->gamma, mu, mu / ((flow->gamma - 1.0) * flow->prandtl), flow->prandtl,
+                       solver->cfl, solver->entropy_delta, solver->limiter_eps, 1.0 / flow->gamma};
+    const double omega = 2.0 * flow->k_red * flow->mach / flow->l_ref;
+    g->blk.resize(nblocks);
+    int64_t part = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const hb_block &S = blocks[b];
+        BlockDesc &B = g->blk[b];
+        std::memset(&B, 0, sizeof B);
+        B.ni = S.ni; B.nj = S.nj; B.nh = S.n_harm; B.ns = 2 * S.n_harm + 1;
+        for (int s = 0; s < 4; ++s) {
+            B.bc[s] = S.bc[s];
+            B.cut_blk[s] = cut_blk[4 * b + s];
+            B.cut_side[s] = cut_side[4 * b + s];
+        }
+        B.wake = S.wake_ncells;
+        B.body = S.body_id;
+        B.snap_off = g->n_snap;
+        B.d_off = b * kNsPad * kNsPad;
+        B.q_off = g->n_state;
+        B.cell_off = g->n_cells;
+        B.node_off = g->n_nodes;
+        B.fi_off = g->n_fi;
+        B.fj_off = g->n_fj;
+        B.ext_off = g->n_ext;
+        B.fiq_off = g->n_fiq;
+        B.fjq_off = g->n_fjq;
+        B.part_off = part;
+        B.omega_nh = omega * S.n_harm;
+        const int64_t cells = (int64_t)S.ni * S.nj;
+        g->n_snap += B.ns;
+        g->n_state += (int64_t)B.ns * 4 * cells;
+        g->n_cells += cells;
+        g->n_nodes += (int64_t)(S.ni + 1) * (S.nj + 1);
+        g->n_fi += (int64_t)(S.ni + 1) * S.nj;
+        g->n_fj += (int64_t)S.ni * (S.nj + 1);
+        g->n_ext += (int64_t)B.ns * 4 * (S.ni + 4) * (S.nj + 4);
+        g->n_fiq += (int64_t)B.ns * 4 * (S.ni + 1) * S.nj;
+        g->n_fjq += (int64_t)B.ns * 4 * S.ni * (S.nj + 1);
+        g->total_cs += (int64_t)B.ns * cells;
+        part += plain_partials(B);
+    }
+    g->body_ns.resize(nbody);
+    g->body_off.resize(nbody);
+    for (int k = 0; k < nbody; ++k) {
+        g->body_ns[k] = 2 * body_nh[k] + 1;
+        g->body_off[k] = (int)g->n_forces;
+        g->n_forces += 3 * g->body_ns[k];
+    }
+    const bool plain = !solver->batched;
+    const bool f32 = solver->precision == HB_FP32_BULK;
+    rc = dalloc(&g->blk_d, nblocks);
+    rc = rc ? rc : dalloc(&g->xy_d, 2 * g->n_nodes);
+    rc = rc ? rc : dalloc(&g->SI_d, 2 * g->n_fi);
+    rc = rc ? rc : dalloc(&g->dI_d, 2 * g->n_fi);
+    rc = rc ? rc : dalloc(&g->SJ_d, 2 * g->n_fj);
+    rc = rc ? rc : dalloc(&g->dJ_d, 2 * g->n_fj);
+    rc = rc ? rc : dalloc(&g->V_d, g->n_cells);
+    rc = rc ? rc : dalloc(&g->C_d, 2 * g->n_cells);
+    rc = rc ? rc : dalloc(&g->SI_f, 2 * g->n_fi);
+    rc = rc ? rc : dalloc(&g->dI_f, 2 * g->n_fi);
+    rc = rc ? rc : dalloc(&g->SJ_f, 2 * g->n_fj);
+    rc = rc ? rc : dalloc(&g->dJ_f, 2 * g->n_fj);
+    rc = rc ? rc : dalloc(&g->V_f, g->n_cells);
+    rc = rc ? rc : dalloc(&g->D_d, (int64_t)nblocks * kNsPad * kNsPad);
+    rc = rc ? rc : dalloc(&g->D_f, (int64_t)nblocks * kNsPad * kNsPad);
+    rc = rc ? rc : dalloc(&g->ffw_d, 4 * g->n_snap);
+    rc = rc ? rc : dalloc(&g->ffq_d, 4 * g->n_snap);
+    rc = rc ? rc : dalloc(&g->dqinf_d, 4 * g->n_snap);
+    rc = rc ? rc : dalloc(&g->ffw_f, 4 * g->n_snap);
+    rc = rc ? rc : dalloc(&g->ffq_f, 4 * g->n_snap);
+    rc = rc ? rc : dalloc(&g->dqinf_f, 4 * g->n_snap);
+    if (plain) {
+        rc = rc ? rc : dalloc(&g->ext_d, g->n_ext);
+        rc = rc ? rc : dalloc(&g->FI_d, g->n_fiq);
+        rc = rc ? rc : dalloc(&g->FJ_d, g->n_fjq);
+    }
+    if (!f32) {
+        rc = rc ? rc : dalloc(&g->qa_d, g->n_state);
+        rc = rc ? rc : dalloc(&g->qb_d, g->n_state);
+    } else {
+        rc = rc ? rc : dalloc(&g->sa_f, g->n_state);
+        rc = rc ? rc : dalloc(&g->sb_f, g->n_state);
+    }
+    rc = rc ? rc : dalloc(&g->fpart_d, (int64_t)nblocks * kMaxNs * 3);
+    rc = rc ? rc : dalloc(&g->status_d, 1);
+    rc = rc ? rc : dalloc(&g->ctr_d, 1);
+    rc = rc ? rc : dalloc(&g->body_off_d, nbody);
+    rc = rc ? rc : dalloc(&g->body_ns_d, nbody);
+    if (!rc && !plain) rc = fused_build_tiles(g);
+    g->n_partials = plain ? part : g->n_tiles;
+    rc = rc ? rc : dalloc(&g->partials_d, g->n_partials);
+    if (rc) {
+        free_all(g);
+        delete g;
+        return rc;
+    }
+    // uploads
+    std::vector<double> xy(2 * g->n_nodes);
+    for (int b = 0; b < nblocks; ++b) {
+        const int64_t nn = (int64_t)(blocks[b].ni + 1) * (blocks[b].nj + 1);
+        std::memcpy(&xy[2 * g->blk[b].node_off], blocks[b].xy, sizeof(double) * 2 * nn);
+    }
+    std::vector<double> D((size_t)nblocks * kNsPad * kNsPad);
+    std::vector<float> Df(D.size());
+    for (int b = 0; b < nblocks; ++b) hb_matrix(g->blk[b].nh, omega, &D[(size_t)b * kNsPad * kNsPad]);
+    for (size_t k = 0; k < D.size(); ++k) Df[k] = (float)D[k];
+    rc = check_hip(hipMemcpy(g->blk_d, g->blk.data(), sizeof(BlockDesc) * nblocks, hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->xy_d, xy.data(), sizeof(double) * xy.size(), hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->D_d, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->D_f, Df.data(), sizeof(float) * Df.size(), hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->body_off_d, g->body_off.data(), sizeof(int) * nbody, hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemcpy(g->body_ns_d, g->body_ns.data(), sizeof(int) * nbody, hipMemcpyHostToDevice), "upload");
+    rc = rc ? rc : check_hip(hipMemset(g->status_d, 0, sizeof(int)), "memset");
+    rc = rc ? rc : check_hip(hipMemset(g->fpart_d, 0, sizeof(double) * nblocks * kMaxNs * 3), "memset");
+    rc = rc ? rc : upload_snapshot_tables(g);
+    rc = rc ? rc : launch_metrics(g, nullptr);
+    rc = rc ? rc : check_hip(hipDeviceSynchronize(), "metrics");
+    if (rc) {
+        free_all(g);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return HB_OK;
+}
+
+int hb_grid_destroy(hb_grid *g) {
+    if (!g) return HB_OK;
+    (void)hipDeviceSynchronize();
+    free_all(g);
+    delete g;
+    return HB_OK;
+}
+
+int64_t hb_state_size(const hb_grid *g) { return g ? g->n_state : -1; }
+int64_t hb_forces_size(const hb_grid *g) { return g ? g->n_forces : -1; }
+int64_t hb_xy_size(const hb_grid *g) { return g ? 2 * g->n_nodes : -1; }
+
+int hb_residual(hb_grid *g, const double *q, double *r, void *stream) {
+    g_err.clear();
+    if (!g || !q || !r) return fail(HB_ERR_ARG, "NULL argument");
+    if (q == r) return fail(HB_ERR_ARG, "q and r must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    if (g->solver.batched) return fused_residual(g, q, r, s);
+    return plain_residual(g, q, r, s);
+}
+
+int hb_rk_iterate(hb_grid *g, double *q, int32_t n_iter, double *resnorm, double *forces,
+                  void *stream) {
+    g_err.clear();
+    if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");
+    if (n_iter < 0) return fail(HB_ERR_ARG, "n_iter must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = HB_OK;
+    if (n_iter > 0)
+        rc = g->solver.batched ? fused_rk_iterate(g, q, n_iter, resnorm, s)
+                               : plain_rk_iterate(g, q, n_iter, resnorm, s);
+    if (!rc && forces) rc = launch_forces(g, q, forces, s);
+    return rc;
+}
+
+int hb_forces(hb_grid *g, const double *q, double *cf, void *stream) {
+    g_err.clear();
+    if (!g || !q || !cf) return fail(HB_ERR_ARG, "NULL argument");
+    return launch_forces(g, q, cf, (hipStream_t)stream);
+}
+
+int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double *qbar,
+                        double *xybar, double *flowbar, void *stream) {
+    g_err.clear();
+    if (!g || !q || !rbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
+    if (qbar == q || qbar == rbar) return fail(HB_ERR_ARG, "qbar must not alias q or rbar");
+    if (g->solver.precision != HB_FP64)
+        return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    return launch_residual_adjoint(g, q, rbar, qbar, xybar, flowbar, (hipStream_t)stream);
+}
+
+int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
+                      double *xybar, double *flowbar, void *stream) {
+    g_err.clear();
+    if (!g || !q || !cfbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
+    if (qbar == q) return fail(HB_ERR_ARG, "qbar must not alias q");
+    return launch_forces_adjoint(g, q, cfbar, qbar, xybar, flowbar, (hipStream_t)stream);
+}
+
+int hb_set_xy(hb_grid *g, const double *xy, void *stream) {
+    g_err.clear();
+    if (!g || !xy) return fail(HB_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_hip(hipMemcpyAsync(g->xy_d, xy, sizeof(double) * 2 * g->n_nodes,
+                                      hipMemcpyDeviceToDevice, s), "xy copy");
+    return rc ? rc : launch_metrics(g, s);
+}
+
+int hb_set_alpha0(hb_grid *g, double alpha0) {
+    g_err.clear();
+    if (!g || !std::isfinite(alpha0)) return fail(HB_ERR_ARG, "bad argument");
+    int rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc) return rc;
+    g->flow.alpha0 = alpha0;
+    return upload_snapshot_tables(g);
+}
+
+int hb_get_status(hb_grid *g) {
+    g_err.clear();
+    if (!g) return fail(HB_ERR_ARG, "NULL grid");
+    int rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc) return rc;
+    int st = 0;
+    rc = check_hip(hipMemcpy(&st, g->status_d, sizeof(int), hipMemcpyDeviceToHost), "status read");
+    if (rc) return rc;
+    if (st) {
+        rc = check_hip(hipMemset(g->status_d, 0, sizeof(int)), "status clear");
+        if (rc) return rc;
+        return fail(HB_ERR_NONFINITE, "non-finite residual or non-positive density/pressure met");
+    }
+    return HB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Device functions shared by the kernels of libhb: ghost resolution,
+// MUSCL / van Albada reconstruction, Roe flux, diamond-path viscous flux,
+// local time step.  Templated on the arithmetic type T (double or float).
+//
+// Face geometry: S is the face normal scaled by the face length, pointing
+// from cell L to cell R; d = (centre of R) - (centre of L).  The edge of an
+// i-face runs from node (i, j) to node (i, j+1); that of a j-face from node
+// (i+1, j) to node (i, j), so that in both cases rot(end - start) = S with
+// rot(x, y) = (y, -x).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hb_internal.hpp"
+
+namespace hb {
+
+template <class T>
+struct W4 {
+    T r, u, v, p;
+};
+
+template <class T>
+__device__ __forceinline__ W4<T> prim_from_cons(T q0, T q1, T q2, T q3, T gm1) {
+    W4<T> w;
+    T ir = T(1) / q0;
+    w.r = q0;
+    w.u = q1 * ir;
+    w.v = q2 * ir;
+    w.p = gm1 * (q3 - T(0.5) * q0 * (w.u * w.u + w.v * w.v));
+    return w;
+}
+
+template <class T>
+__device__ __forceinline__ W4<T> mirror(W4<T> w) {
+    w.u = -w.u;
+    w.v = -w.v;
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost resolution.  A cell index (i, j) with i in [-2, ni+2), j in [-2, nj+2)
+// is mapped to a value: interior cells are read, the i sides are resolved
+// first (rows 0..nj-1), and the j sides apply their rule to the i-resolved
+// rows (which defines the corner ghosts).  `Interior` is a functor
+// (block, i, j) -> W4<T> reading an interior cell of any block; `ff` returns
+// the block's free stream of the current snapshot.
+// ---------------------------------------------------------------------------
+template <class T, class Interior, class FF>
+__device__ __forceinline__ W4<T> value_i(const BlockDesc *blks, int b, int i, int j,
+                                         const Interior &cell, const FF &ff) {
+    const BlockDesc &B = blks[b];
+    if (i >= 0 && i < B.ni) return cell(b, i, j);
+    const int side = i < 0 ? 0 : 1;
+    const int k = i < 0 ? -1 - i : i - B.ni;
+    switch (B.bc[side]) {
+        case HB_BC_PERIODIC:
+            return cell(b, i < 0 ? i + B.ni : i - B.ni, j);
+        case HB_BC_WALL:
+            return mirror(cell(b, side == 0 ? k : B.ni - 1 - k, j));
+        case HB_BC_CUT: {
+            const int a = B.cut_blk[side];
+            return cell(a, side == 0 ? blks[a].ni - 1 - k : k, j);
+        }
+        default:
+            return ff(b);
+    }
+}
+
+template <class T, class Interior, class FF>
+__device__ __forceinline__ W4<T> value_ij(const BlockDesc *blks, int b, int i, int j,
+                                          const Interior &cell, const FF &ff) {
+    const BlockDesc &B = blks[b];
+    if (j >= 0 && j < B.nj) return value_i<T>(blks, b, i, j, cell, ff);
+    const int side = j < 0 ? 2 : 3;
+    const int k = j < 0 ? -1 - j : j - B.nj;
+    switch (B.bc[side]) {
+        case HB_BC_PERIODIC:
+            return value_i<T>(blks, b, i, j < 0 ? j + B.nj : j - B.nj, cell, ff);
+        case HB_BC_WALL:
+            return mirror(value_i<T>(blks, b, i, side == 2 ? k : B.nj - 1 - k, cell, ff));
+        case HB_BC_WAKECUT: {
+            if (i < B.wake || i >= B.ni - B.wake)
+                return value_i<T>(blks, b, B.ni - 1 - i, k, cell, ff);
+            return mirror(value_i<T>(blks, b, i, k, cell, ff));
+        }
+        case HB_BC_CUT: {
+            const int a = B.cut_blk[side];
+            return value_i<T>(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k, cell, ff);
+        }
+        default:
+            return ff(b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T van_albada(T a, T b, T eps) {
+    return (a + b) * (a * b + eps) / (a * a + b * b + T(2) * eps);
+}
+
+// Face states between cells m1 and p0 of a grid line m2, m1, p0, p1.
+template <class T>
+__device__ __forceinline__ void muscl(const W4<T> &m2, const W4<T> &m1, const W4<T> &p0,
+                                      const W4<T> &p1, T eps, W4<T> &L, W4<T> &R) {
+    L.r = m1.r + T(0.5) * van_albada(m1.r - m2.r, p0.r - m1.r, eps);
+    L.u = m1.u + T(0.5) * van_albada(m1.u - m2.u, p0.u - m1.u, eps);
+    L.v = m1.v + T(0.5) * van_albada(m1.v - m2.v, p0.v - m1.v, eps);
+    L.p = m1.p + T(0.5) * van_albada(m1.p - m2.p, p0.p - m1.p, eps);
+    R.r = p0.r - T(0.5) * van_albada(p0.r - m1.r, p1.r - p0.r, eps);
+    R.u = p0.u - T(0.5) * van_albada(p0.u - m1.u, p1.u - p0.u, eps);
+    R.v = p0.v - T(0.5) * van_albada(p0.v - m1.v, p1.v - p0.v, eps);
+    R.p = p0.p - T(0.5) * van_albada(p0.p - m1.p, p1.p - p0.p, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Roe flux on full primitive states, times the face length.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T sy, T g,
+                                         T delta_frac, T f[4]) {
+    const T area = sqrt(sx * sx + sy * sy);
+    const T ia = T(1) / area;
+    const T nx = sx * ia, ny = sy * ia;
+    const T gg = g / (g - T(1));
+    const T hl = gg * L.p / L.r + T(0.5) * (L.u * L.u + L.v * L.v);
+    const T hr = gg * R.p / R.r + T(0.5) * (R.u * R.u + R.v * R.v);
+    const T sl = sqrt(L.r), sr = sqrt(R.r);
+    const T iw = T(1) / (sl + sr);
+    const T rt = sl * sr;
+    const T ut = (sl * L.u + sr * R.u) * iw;
+    const T vt = (sl * L.v + sr * R.v) * iw;
+    const T ht = (sl * hl + sr * hr) * iw;
+    const T q2t = ut * ut + vt * vt;
+    const T ct = sqrt((g - T(1)) * (ht - T(0.5) * q2t));
+    const T qnt = ut * nx + vt * ny;
+    const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
+    const T dqn = du * nx + dv * ny;
+    const T ic2 = T(1) / (ct * ct);
+    const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
+    const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
+    const T a2 = dr - dp * ic2;
+    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
+    const T l2 = fabs(qnt);
+    if (delta_frac > T(0)) {
+        const T d = delta_frac * ct;
+        if (l1 < d) l1 = (l1 * l1 + d * d) / (T(2) * d);
+        if (l4 < d) l4 = (l4 * l4 + d * d) / (T(2) * d);
+    }
+    const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
+    const T d0 = b1 + b4 + b2;
+    const T d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
+    const T d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
+    const T d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (T(0.5) * q2t) +
+                 bs * (ut * du + vt * dv - qnt * dqn);
+    const T qnl = L.u * nx + L.v * ny, qnr = R.u * nx + R.v * ny;
+    const T ml = L.r * qnl, mr = R.r * qnr;
+    const T f0 = ml + mr;
+    const T f1 = ml * L.u + mr * R.u + (L.p + R.p) * nx;
+    const T f2 = ml * L.v + mr * R.v + (L.p + R.p) * ny;
+    const T f3 = ml * hl + mr * hr;
+    f[0] = T(0.5) * area * (f0 - d0);
+    f[1] = T(0.5) * area * (f1 - d1);
+    f[2] = T(0.5) * area * (f2 - d2);
+    f[3] = T(0.5) * area * (f3 - d3);
+}
+
+// ---------------------------------------------------------------------------
+// Viscous flux (diamond path), times the face length.  Inputs are (u, v, T)
+// triples at L, R and the edge end points P (start) and Q (end).
+// grad phi = [(phi_R - phi_L) S + (phi_P - phi_Q) rot(d)] / (d . S).
+// fv receives (tau.S)_x, (tau.S)_y and the energy term.
+// ---------------------------------------------------------------------------
+template <class T>
+struct UVT {
+    T u, v, t;
+};
+
+template <class T>
+__device__ __forceinline__ void viscous_flux(const UVT<T> &L, const UVT<T> &R, const UVT<T> &P,
+                                             const UVT<T> &Q, T sx, T sy, T dx, T dy, T mu,
+                                             T kappa, T fv[3]) {
+    const T iden = T(1) / (dx * sx + dy * sy);
+    const T ax = sx * iden, ay = sy * iden;     // S / (d.S)
+    const T bx = dy * iden, by = -dx * iden;    // rot(d) / (d.S)
+    const T du = R.u - L.u, dv = R.v - L.v, dt = R.t - L.t;
+    const T eu = P.u - Q.u, ev = P.v - Q.v, et = P.t - Q.t;
+    const T ux = du * ax + eu * bx, uy = du * ay + eu * by;
+    const T vx = dv * ax + ev * bx, vy = dv * ay + ev * by;
+    const T tx = dt * ax + et * bx, ty = dt * ay + et * by;
+    const T div = ux + vy;
+    const T txx = mu * (T(2) * ux - T(2.0 / 3.0) * div);
+    const T tyy = mu * (T(2) * vy - T(2.0 / 3.0) * div);
+    const T txy = mu * (uy + vx);
+    const T fx = txx * sx + txy * sy;
+    const T fy = txy * sx + tyy * sy;
+    const T uf = T(0.5) * (L.u + R.u), vf = T(0.5) * (L.v + R.v);
+    fv[0] = fx;
+    fv[1] = fy;
+    fv[2] = uf * fx + vf * fy + kappa * (tx * sx + ty * sy);
+}
+
+template <class T>
+__device__ __forceinline__ UVT<T> uvt(const W4<T> &w, T g) {
+    return UVT<T>{w.u, w.v, g * w.p / w.r};
+}
+
+template <class T>
+__device__ __forceinline__ UVT<T> avg4(const UVT<T> &a, const UVT<T> &b, const UVT<T> &c,
+                                       const UVT<T> &d) {
+    return UVT<T>{T(0.25) * (a.u + b.u + c.u + d.u), T(0.25) * (a.v + b.v + c.v + d.v),
+                  T(0.25) * (a.t + b.t + c.t + d.t)};
+}
+
+// ---------------------------------------------------------------------------
+// Local time step of one cell and snapshot.
+// dtau = CFL V / (L_I + L_J + 4 (Lv_I + Lv_J) + V omega N_H)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T local_dt(const W4<T> &w, T six, T siy, T sjx, T sjy, T V, T g,
+                                      T mu_pr, T cfl, T omega_nh) {
+    const T c = sqrt(g * w.p / w.r);
+    const T ai2 = six * six + siy * siy, aj2 = sjx * sjx + sjy * sjy;
+    const T li = fabs(w.u * six + w.v * siy) + c * sqrt(ai2);
+    const T lj = fabs(w.u * sjx + w.v * sjy) + c * sqrt(aj2);
+    const T fac = fmax(T(4.0 / 3.0) / w.r, g / w.r) * mu_pr;
+    const T lv = fac * (ai2 + aj2) / V;
+    return cfl * V / (li + lj + T(4) * lv + V * omega_nh);
+}
+
+}  // namespace hb

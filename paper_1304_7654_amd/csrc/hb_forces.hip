@@ -1,0 +1,146 @@
+// Force coefficients per body and snapshot, FP64 (the paper's
+// cl(n, ibody), cd(n, ibody), cm(n, ibody) and their single aggregated
+// reduction per Runge-Kutta step, §MPI Optimisations).  One workgroup per
+// (block, snapshot) sums its wall faces in a fixed order; a second kernel
+// adds the blocks of each body in block order and rotates to wind axes.
+// No atomics: results are bitwise reproducible.
+#include "hb_device.hpp"
+
+namespace hb {
+namespace {
+
+constexpr int kBS = 256;
+
+struct CellQ {
+    const BlockDesc *blks;
+    const double *q;
+    int n;
+    double gm1;
+    __device__ W4<double> operator()(int b, int i, int j) const {
+        const BlockDesc &B = blks[b];
+        const int64_t plane = (int64_t)B.ni * B.nj;
+        const double *p = q + B.q_off + (int64_t)n * 4 * plane + (int64_t)j * B.ni + i;
+        return prim_from_cons<double>(p[0], p[plane], p[2 * plane], p[3 * plane], gm1);
+    }
+};
+
+struct FF {
+    const BlockDesc *blks;
+    const double *ffw;
+    int n;
+    __device__ W4<double> operator()(int b) const {
+        const double *f = ffw + 4 * (blks[b].snap_off + n);
+        return W4<double>{f[0], f[1], f[2], f[3]};
+    }
+};
+
+__device__ inline bool is_wall_face(const BlockDesc &B, int i) {
+    if (B.bc[2] == HB_BC_WALL) return true;
+    if (B.bc[2] == HB_BC_WAKECUT) return i >= B.wake && i < B.ni - B.wake;
+    return false;
+}
+
+// Loads of one jmin wall face: (Fx, Fy, Mz).
+__device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, const double *q,
+                                 const double *ffw, const double *xy, const double *SJ,
+                                 const double *dJ, const Consts &c, double xm, double ym,
+                                 double out[3]) {
+    const BlockDesc &B = blks[b];
+    CellQ cell{blks, q, n, c.gamma - 1.0};
+    FF ff{blks, ffw, n};
+    const double g = c.gamma;
+    const W4<double> wR = value_ij<double>(blks, b, i, 0, cell, ff);
+    const W4<double> wL = value_ij<double>(blks, b, i, -1, cell, ff);
+    const UVT<double> uL = uvt(wL, g), uR = uvt(wR, g);
+    const UVT<double> nA = avg4(uvt(value_ij<double>(blks, b, i - 1, -1, cell, ff), g), uL,
+                                uvt(value_ij<double>(blks, b, i - 1, 0, cell, ff), g), uR);
+    const UVT<double> nB = avg4(uL, uvt(value_ij<double>(blks, b, i + 1, -1, cell, ff), g), uR,
+                                uvt(value_ij<double>(blks, b, i + 1, 0, cell, ff), g));
+    const int64_t nf = (int64_t)B.ni * (B.nj + 1);
+    const double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
+    const double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    double fv[3];
+    viscous_flux(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fv);
+    const double dp = wR.p - c.pinf;
+    const double fx = -dp * sx + fv[0];
+    const double fy = -dp * sy + fv[1];
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off;
+    const double *y = x + nn;
+    const double mx = 0.5 * (x[i] + x[i + 1]) - xm;
+    const double my = 0.5 * (y[i] + y[i + 1]) - ym;
+    out[0] = fx;
+    out[1] = fy;
+    out[2] = mx * fy - my * fx;
+}
+
+__global__ void k_block_loads(const BlockDesc *blks, const double *q, const double *ffw,
+                              const double *xy, const double *SJ, const double *dJ, Consts c,
+                              double xm, double ym, double *part) {
+    const int b = blockIdx.x;
+    const int n = blockIdx.y;
+    const BlockDesc &B = blks[b];
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (n < B.ns) {
+        for (int i = threadIdx.x; i < B.ni; i += kBS) {
+            if (!is_wall_face(B, i)) continue;
+            double l[3];
+            face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, l);
+            acc[0] += l[0];
+            acc[1] += l[1];
+            acc[2] += l[2];
+        }
+    }
+    __shared__ double red[3][kBS];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && n < B.ns)
+        for (int k = 0; k < 3; ++k) part[((int64_t)b * kMaxNs + n) * 3 + k] = red[k][0];
+}
+
+// One thread per (body, snapshot) entry of the output.
+__global__ void k_body_coeffs(const BlockDesc *blks, int nblocks, const int *body_off,
+                              const int *body_ns, int nbody, const double *part, double ca,
+                              double sa, double qinf_l, double qinf_l2, double *cf) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int body = 0, n = t;
+    while (body < nbody && n >= body_ns[body]) {
+        n -= body_ns[body];
+        ++body;
+    }
+    if (body >= nbody) return;
+    double fx = 0.0, fy = 0.0, mz = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (blks[b].body != body) continue;
+        const double *p = part + ((int64_t)b * kMaxNs + n) * 3;
+        fx += p[0];
+        fy += p[1];
+        mz += p[2];
+    }
+    double *o = cf + body_off[body] + 3 * n;
+    o[0] = (-fx * sa + fy * ca) / qinf_l;
+    o[1] = (fx * ca + fy * sa) / qinf_l;
+    o[2] = -mz / qinf_l2;
+}
+
+}  // namespace
+
+int launch_forces(hb_grid *g, const double *q, double *cf, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_loads, dim3(g->nblocks, kMaxNs), dim3(kBS), 0, s, g->blk_d, q,
+                       g->ffw_d, g->xy_d, g->SJ_d, g->dJ_d, g->consts, g->flow.x_mom,
+                       g->flow.y_mom, g->fpart_d);
+    const int total = (int)(g->n_forces / 3);
+    const double qinf = 0.5 * g->flow.mach * g->flow.mach;
+    const double L = g->flow.l_ref;
+    hipLaunchKernelGGL(k_body_coeffs, dim3((total + 63) / 64), dim3(64), 0, s, g->blk_d,
+                       g->nblocks, g->body_off_d, g->body_ns_d, g->nbody, g->fpart_d,
+                       cos(g->flow.alpha0), sin(g->flow.alpha0), qinf * L, qinf * L * L, cf);
+    return check_hip(hipGetLastError(), "forces launch");
+}
+
+}  // namespace hb

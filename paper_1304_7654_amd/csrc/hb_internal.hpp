@@ -1,0 +1,158 @@
+// Internal declarations of libhb: the grid object, the device-side block
+// descriptor and the launch helpers of each kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+
+namespace hb {
+
+constexpr int kMaxNs = 9;        // N_H <= 4
+constexpr int kNsPad = 16;       // padded D (MFMA tile)
+
+// Device-side description of one block.  Offsets index the flat arrays
+// of the grid (all blocks concatenated).
+struct BlockDesc {
+    int32_t ni, nj, ns, nh;
+    int32_t bc[4];
+    int32_t wake;
+    int32_t body;
+    int32_t cut_blk[4];      // neighbour block across a CUT side, else -1
+    int32_t cut_side[4];
+    int32_t snap_off;        // per-snapshot tables: entries snap_off .. +ns
+    int32_t d_off;           // D table (kNsPad x kNsPad per block)
+    int64_t q_off;           // state (doubles): ns*4*nj*ni
+    int64_t cell_off;        // per-cell arrays: nj*ni
+    int64_t node_off;        // per-node arrays: (nj+1)*(ni+1)
+    int64_t fi_off;          // i-faces: nj*(ni+1)
+    int64_t fj_off;          // j-faces: (nj+1)*ni
+    int64_t ext_off;         // plain path ghost-extended primitives: ns*4*(nj+4)*(ni+4)
+    int64_t fiq_off;         // plain path i-face fluxes: ns*4*nj*(ni+1)
+    int64_t fjq_off;         // plain path j-face fluxes: ns*4*(nj+1)*ni
+    int64_t part_off;        // plain path norm partials of this block
+    double omega_nh;         // omega * N_H (time-step bound of the HB term)
+};
+
+// One fused-kernel work item: a tile of cells of one block.
+struct Tile {
+    int32_t blk;
+    int32_t i0, j0;
+    int32_t ns;
+};
+
+// Geometry and flow constants passed by value to kernels.
+struct Consts {
+    double gamma, mu, kappa, prandtl, cfl, delta_frac, eps, pinf;
+};
+
+// Pointers to the FP64 metrics (see metrics kernels for layouts).
+template <class T>
+struct Metrics {
+    const T *SI, *dI;    // [2][nj][ni+1] per block at 2*fi_off
+    const T *SJ, *dJ;    // [2][nj+1][ni] per block at 2*fj_off
+    const T *V;          // [nj][ni] at cell_off
+};
+
+// Per-snapshot tables: free-stream primitives (rho, u, v, p), free-stream
+// conserved variables, and c_n = sum_m D[n][m] Q_inf(m).
+template <class T>
+struct SnapTables {
+    const T *ffw;        // [snap][4]
+    const T *ffq;        // [snap][4]
+    const T *dqinf;      // [snap][4]
+};
+
+}  // namespace hb
+
+struct hb_grid {
+    int device = 0;
+    int nblocks = 0;
+    int nbody = 0;
+    std::vector<hb::BlockDesc> blk;
+    std::vector<std::vector<double>> xy_host;
+    std::vector<int> body_ns, body_off;          // force layout
+    hb_flow flow{};
+    hb_solver solver{};
+    hb::Consts consts{};
+    int64_t n_state = 0, n_cells = 0, n_nodes = 0, n_fi = 0, n_fj = 0, n_ext = 0;
+    int64_t n_fiq = 0, n_fjq = 0;
+    int n_snap = 0;
+    int64_t n_forces = 0;
+    int64_t total_cs = 0;                          // cell-snapshots
+
+    // device memory
+    hb::BlockDesc *blk_d = nullptr;
+    double *xy_d = nullptr;
+    double *SI_d = nullptr, *dI_d = nullptr, *SJ_d = nullptr, *dJ_d = nullptr;
+    double *V_d = nullptr, *C_d = nullptr;
+    float *SI_f = nullptr, *dI_f = nullptr, *SJ_f = nullptr, *dJ_f = nullptr, *V_f = nullptr;
+    double *D_d = nullptr;
+    float *D_f = nullptr;
+    double *ffw_d = nullptr, *ffq_d = nullptr, *dqinf_d = nullptr;
+    float *ffw_f = nullptr, *ffq_f = nullptr, *dqinf_f = nullptr;
+    // scratch
+    double *ext_d = nullptr;      // plain path ghost-extended primitives
+    double *FI_d = nullptr, *FJ_d = nullptr;   // plain path face fluxes [ns][4][faces]
+    double *q0_d = nullptr;       // RK base state copy (plain path)
+    double *qa_d = nullptr, *qb_d = nullptr;   // stage ping-pong (FP64)
+    float *sa_f = nullptr, *sb_f = nullptr;    // stage ping-pong shadows (FP32 bulk)
+    double *partials_d = nullptr; int64_t n_partials = 0;
+    double *fpart_d = nullptr;    // force partials [block][kMaxNs][3]
+    double *norm_tmp_d = nullptr;
+    int *status_d = nullptr;
+    int *body_off_d = nullptr, *body_ns_d = nullptr;
+    int *ctr_d = nullptr;
+    // fused path
+    hb::Tile *tiles_d = nullptr;
+    int n_tiles = 0;
+    int tile_ti = 32, tile_tj = 8;
+    int fused_grid = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double *graph_q = nullptr, *graph_norm = nullptr;
+    int graph_iters = 0;
+    // adjoint scratch
+    double *adj_d = nullptr;
+    int64_t n_adj = 0;
+};
+
+namespace hb {
+
+// error helpers (capi.cpp)
+int upload_snapshot_tables(hb_grid *g);
+int fail(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+
+// metrics.hip
+int launch_metrics(hb_grid *g, hipStream_t s);
+
+// plain.hip (FP64 per-block launches)
+int64_t plain_partials(const BlockDesc &B);
+int plain_residual(hb_grid *g, const double *q, double *r, hipStream_t s);
+int plain_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s);
+
+// fused.hip (batched tile kernel)
+int fused_build_tiles(hb_grid *g);
+int fused_residual(hb_grid *g, const double *q, double *r, hipStream_t s);
+int fused_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s);
+
+// forces.hip
+int launch_forces(hb_grid *g, const double *q, double *cf, hipStream_t s);
+
+// adjoint.hip
+int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double *qbar,
+                            double *xybar, double *flowbar, hipStream_t s);
+int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
+                          double *xybar, double *flowbar, hipStream_t s);
+
+// reduce.hip
+int launch_norm_finalize(hb_grid *g, const double *partials, int64_t n, double *out,
+                         int *ctr, hipStream_t s);
+int launch_reset_ctr(int *ctr, hipStream_t s);
+
+}  // namespace hb

@@ -1,0 +1,266 @@
+// Plain FP64 path: one block per launch, separate kernels for ghost
+// synthesis, i-face fluxes, j-face fluxes and the cell update.  Every
+// intermediate goes through HBM.  It is the straightforward baseline that
+// the fused batched kernel is measured against, and a second, independently
+// structured GPU evaluation of the same residual.
+#include "hb_device.hpp"
+
+namespace hb {
+namespace {
+
+constexpr int kBS = 256;
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
+
+struct CellFromState {
+    const BlockDesc *blks;
+    const double *q;
+    int n;
+    double gm1;
+    __device__ W4<double> operator()(int b, int i, int j) const {
+        const BlockDesc &B = blks[b];
+        const int64_t plane = (int64_t)B.ni * B.nj;
+        const double *p = q + B.q_off + (int64_t)n * 4 * plane + (int64_t)j * B.ni + i;
+        return prim_from_cons<double>(p[0], p[plane], p[2 * plane], p[3 * plane], gm1);
+    }
+};
+
+struct FreeStream {
+    const BlockDesc *blks;
+    const double *ffw;
+    int n;
+    __device__ W4<double> operator()(int b) const {
+        const double *f = ffw + 4 * (blks[b].snap_off + n);
+        return W4<double>{f[0], f[1], f[2], f[3]};
+    }
+};
+
+// Ghost-extended primitives ext[n][4][nj+4][ni+4] of one block.
+__global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const double *ffw,
+                        double gm1, double *ext) {
+    const BlockDesc &B = blks[b];
+    const int we = B.ni + 4, he = B.nj + 4;
+    const int64_t plane = (int64_t)we * he;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane * B.ns) return;
+    const int n = (int)(t / plane);
+    const int64_t r = t % plane;
+    const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
+    CellFromState cell{blks, q, n, gm1};
+    FreeStream ff{blks, ffw, n};
+    const W4<double> w = value_ij<double>(blks, b, i, j, cell, ff);
+    double *e = ext + B.ext_off + (int64_t)n * 4 * plane + r;
+    e[0] = w.r;
+    e[plane] = w.u;
+    e[2 * plane] = w.v;
+    e[3 * plane] = w.p;
+}
+
+__device__ inline W4<double> ld(const double *e, int64_t plane, int64_t idx) {
+    return W4<double>{e[idx], e[plane + idx], e[2 * plane + idx], e[3 * plane + idx]};
+}
+
+__global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
+                         const double *dI, Consts c, double *FI) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nf = (int64_t)W * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * B.ns) return;
+    const int n = (int)(t / nf);
+    const int64_t f = t % nf;
+    const int i = (int)(f % W), j = (int)(f / W);
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    const int64_t row = (int64_t)(j + 2) * we;
+    const W4<double> m2 = ld(e, plane, row + i), m1 = ld(e, plane, row + i + 1);
+    const W4<double> p0 = ld(e, plane, row + i + 2), p1 = ld(e, plane, row + i + 3);
+    W4<double> L, R;
+    muscl(m2, m1, p0, p1, c.eps, L, R);
+    const double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
+    const double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    double fl[4];
+    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl);
+    // viscous: L = cell (i-1, j), R = cell (i, j); edge from node (i, j) to (i, j+1)
+    const double g = c.gamma;
+    const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
+    const int64_t lo = (int64_t)(j + 1) * we, hi = (int64_t)(j + 3) * we;
+    const UVT<double> nA = avg4(uvt(ld(e, plane, lo + i + 1), g), uvt(ld(e, plane, lo + i + 2), g),
+                                uL, uR);
+    const UVT<double> nB = avg4(uL, uR, uvt(ld(e, plane, hi + i + 1), g),
+                                uvt(ld(e, plane, hi + i + 2), g));
+    double fv[3];
+    viscous_flux(uL, uR, nA, nB, sx, sy, dx, dy, c.mu, c.kappa, fv);
+    double *o = FI + B.fiq_off + (int64_t)n * 4 * nf + f;
+    o[0] = fl[0];
+    o[nf] = fl[1] - fv[0];
+    o[2 * nf] = fl[2] - fv[1];
+    o[3 * nf] = fl[3] - fv[2];
+}
+
+__global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
+                         const double *dJ, Consts c, double *FJ) {
+    const BlockDesc &B = blks[b];
+    const int64_t nf = (int64_t)B.ni * (B.nj + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * B.ns) return;
+    const int n = (int)(t / nf);
+    const int64_t f = t % nf;
+    const int i = (int)(f % B.ni), j = (int)(f / B.ni);
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    const int col = i + 2;
+    const W4<double> m2 = ld(e, plane, (int64_t)j * we + col);
+    const W4<double> m1 = ld(e, plane, (int64_t)(j + 1) * we + col);
+    const W4<double> p0 = ld(e, plane, (int64_t)(j + 2) * we + col);
+    const W4<double> p1 = ld(e, plane, (int64_t)(j + 3) * we + col);
+    W4<double> L, R;
+    muscl(m2, m1, p0, p1, c.eps, L, R);
+    const double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
+    const double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    double fl[4];
+    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl);
+    // viscous: L = cell (i, j-1), R = cell (i, j); edge from node (i+1, j) to (i, j)
+    const double g = c.gamma;
+    const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
+    const int64_t r1 = (int64_t)(j + 1) * we, r2 = (int64_t)(j + 2) * we;
+    const UVT<double> nA = avg4(uvt(ld(e, plane, r1 + col - 1), g), uL,
+                                uvt(ld(e, plane, r2 + col - 1), g), uR);          // node (i, j)
+    const UVT<double> nB = avg4(uL, uvt(ld(e, plane, r1 + col + 1), g), uR,
+                                uvt(ld(e, plane, r2 + col + 1), g));              // node (i+1, j)
+    double fv[3];
+    viscous_flux(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fv);
+    double *o = FJ + B.fjq_off + (int64_t)n * 4 * nf + f;
+    o[0] = fl[0];
+    o[nf] = fl[1] - fv[0];
+    o[2 * nf] = fl[2] - fv[1];
+    o[3 * nf] = fl[3] - fv[2];
+}
+
+// Cell update.  mode 0: out = R*(qin).  mode 1: out = q0 - alpha (dtau/V) R*(qin),
+// dtau from q0; with `norm` set, the block's partial sums of (R*_rho/V)^2
+// go to partials[part_off + blockIdx.x].
+__global__ void k_update(const BlockDesc *blks, int b, const double *FI, const double *FJ,
+                         const double *SI, const double *SJ, const double *V, const double *D,
+                         const double *qin, const double *q0, double *out, int mode, double alpha,
+                         int norm, double *partials, int *status, Consts c) {
+    const BlockDesc &B = blks[b];
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (t < plane) {
+        const int i = (int)(t % B.ni), j = (int)(t / B.ni);
+        const int W = B.ni + 1;
+        const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
+        const int64_t fi0 = (int64_t)j * W + i, fj0 = t;
+        const double vol = V[B.cell_off + t];
+        const double *dm = D + B.d_off;
+        const double *qi = qin + B.q_off + t;
+        const double sxi = 0.5 * (SI[2 * B.fi_off + fi0] + SI[2 * B.fi_off + fi0 + 1]);
+        const double syi = 0.5 * (SI[2 * B.fi_off + nfi + fi0] + SI[2 * B.fi_off + nfi + fi0 + 1]);
+        const double sxj = 0.5 * (SJ[2 * B.fj_off + fj0] + SJ[2 * B.fj_off + fj0 + B.ni]);
+        const double syj = 0.5 * (SJ[2 * B.fj_off + nfj + fj0] + SJ[2 * B.fj_off + nfj + fj0 + B.ni]);
+        int bad = 0;
+        for (int n = 0; n < B.ns; ++n) {
+            double rs[4];
+            for (int v = 0; v < 4; ++v) {
+                const double *fi = FI + B.fiq_off + ((int64_t)n * 4 + v) * nfi;
+                const double *fj = FJ + B.fjq_off + ((int64_t)n * 4 + v) * nfj;
+                double src = 0.0;
+                for (int m = 0; m < B.ns; ++m)
+                    src += dm[n * kNsPad + m] * qi[((int64_t)m * 4 + v) * plane];
+                rs[v] = (fi[fi0 + 1] - fi[fi0]) + (fj[fj0 + B.ni] - fj[fj0]) + vol * src;
+            }
+            const int64_t o = B.q_off + (int64_t)n * 4 * plane + t;
+            if (mode == 0) {
+                for (int v = 0; v < 4; ++v) out[o + v * plane] = rs[v];
+            } else {
+                const double *b0 = q0 + o;
+                const W4<double> w0 = prim_from_cons<double>(b0[0], b0[plane], b0[2 * plane],
+                                                             b0[3 * plane], c.gamma - 1.0);
+                const double dt = local_dt<double>(w0, sxi, syi, sxj, syj, vol, c.gamma,
+                                                   c.mu / c.prandtl, c.cfl, B.omega_nh);
+                const double fac = alpha * dt / vol;
+                double nq[4];
+                for (int v = 0; v < 4; ++v) nq[v] = b0[v * plane] - fac * rs[v];
+                for (int v = 0; v < 4; ++v) out[o + v * plane] = nq[v];
+                const double pn = (c.gamma - 1.0) * (nq[3] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]) / nq[0]);
+                if (!(nq[0] > 0.0) || !(pn > 0.0) || !isfinite(rs[0] + rs[1] + rs[2] + rs[3])) bad = 1;
+            }
+            const double rr = rs[0] / vol;
+            acc += rr * rr;
+        }
+        if (bad) atomicOr(status, 1);
+    }
+    if (!norm) return;
+    __shared__ double red[kBS];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[B.part_off + blockIdx.x] = red[0];
+}
+
+Metrics<double> fp64_metrics(hb_grid *g) {
+    return Metrics<double>{g->SI_d, g->dI_d, g->SJ_d, g->dJ_d, g->V_d};
+}
+
+int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode, double alpha,
+          int norm, hipStream_t s) {
+    const Consts c = g->consts;
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
+        hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
+                           c.gamma - 1.0, g->ext_d);
+        hipLaunchKernelGGL(k_flux_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d);
+        hipLaunchKernelGGL(k_flux_j, dim3(nblk((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d);
+        hipLaunchKernelGGL(k_update, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+                           g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
+                           alpha, norm, g->partials_d, g->status_d, c);
+    }
+    return check_hip(hipGetLastError(), "plain stage launch");
+}
+
+}  // namespace
+
+// Number of norm partials the plain path writes for a block.
+int64_t plain_partials(const BlockDesc &B) { return nblk((int64_t)B.ni * B.nj); }
+
+int plain_residual(hb_grid *g, const double *q, double *r, hipStream_t s) {
+    return stage(g, q, q, r, 0, 0.0, 0, s);
+}
+
+int plain_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s) {
+    const int ns = g->solver.n_stages;
+    int rc = launch_reset_ctr(g->ctr_d, s);
+    if (rc) return rc;
+    for (int it = 0; it < n_iter; ++it) {
+        const double *in = q;
+        for (int k = 0; k < ns; ++k) {
+            // the last stage writes q in place (q is read pointwise only);
+            // a one-stage scheme reads q as its stencil input, so it goes
+            // through a scratch buffer
+            double *out = (k == ns - 1 && ns > 1) ? q : ((k % 2 == 0) ? g->qa_d : g->qb_d);
+            rc = stage(g, in, q, out, 1, g->solver.rk_alpha[k], k == 0, s);
+            if (rc) return rc;
+            in = out;
+        }
+        if (ns == 1) {
+            rc = check_hip(hipMemcpyAsync(q, g->qa_d, sizeof(double) * g->n_state,
+                                          hipMemcpyDeviceToDevice, s), "copy");
+            if (rc) return rc;
+        }
+        rc = launch_norm_finalize(g, g->partials_d, g->n_partials, resnorm, g->ctr_d, s);
+        if (rc) return rc;
+    }
+    return HB_OK;
+}
+
+}  // namespace hb
