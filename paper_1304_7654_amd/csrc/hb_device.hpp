@@ -42,13 +42,14 @@ __device__ __forceinline__ W4<T> mirror(W4<T> w) {
 // Ghost resolution.  A cell index (i, j) with i in [-2, ni+2), j in [-2, nj+2)
 // is mapped to a value: interior cells are read, the i sides are resolved
 // first (rows 0..nj-1), and the j sides apply their rule to the i-resolved
-// rows (which defines the corner ghosts).  `Interior` is a functor
-// (block, i, j) -> W4<T> reading an interior cell of any block; `ff` returns
-// the block's free stream of the current snapshot.
+// rows (which defines the corner ghosts).  `cell` is a functor
+// (block, i, j) -> value reading an interior cell of any block; `ff(b)`
+// returns the block's free stream of the current snapshot and `mir` the
+// no-slip wall image of a value.
 // ---------------------------------------------------------------------------
-template <class T, class Interior, class FF>
-__device__ __forceinline__ W4<T> value_i(const BlockDesc *blks, int b, int i, int j,
-                                         const Interior &cell, const FF &ff) {
+template <class V, class Interior, class FF, class Mir>
+__device__ __forceinline__ V value_i(const BlockDesc *blks, int b, int i, int j,
+                                     const Interior &cell, const FF &ff, const Mir &mir) {
     const BlockDesc &B = blks[b];
     if (i >= 0 && i < B.ni) return cell(b, i, j);
     const int side = i < 0 ? 0 : 1;
@@ -57,7 +58,7 @@ __device__ __forceinline__ W4<T> value_i(const BlockDesc *blks, int b, int i, in
         case HB_BC_PERIODIC:
             return cell(b, i < 0 ? i + B.ni : i - B.ni, j);
         case HB_BC_WALL:
-            return mirror(cell(b, side == 0 ? k : B.ni - 1 - k, j));
+            return mir(cell(b, side == 0 ? k : B.ni - 1 - k, j));
         case HB_BC_CUT: {
             const int a = B.cut_blk[side];
             return cell(a, side == 0 ? blks[a].ni - 1 - k : k, j);
@@ -67,31 +68,37 @@ __device__ __forceinline__ W4<T> value_i(const BlockDesc *blks, int b, int i, in
     }
 }
 
-template <class T, class Interior, class FF>
-__device__ __forceinline__ W4<T> value_ij(const BlockDesc *blks, int b, int i, int j,
-                                          const Interior &cell, const FF &ff) {
+template <class V, class Interior, class FF, class Mir>
+__device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j,
+                                      const Interior &cell, const FF &ff, const Mir &mir) {
     const BlockDesc &B = blks[b];
-    if (j >= 0 && j < B.nj) return value_i<T>(blks, b, i, j, cell, ff);
+    if (j >= 0 && j < B.nj) return value_i<V>(blks, b, i, j, cell, ff, mir);
     const int side = j < 0 ? 2 : 3;
     const int k = j < 0 ? -1 - j : j - B.nj;
     switch (B.bc[side]) {
         case HB_BC_PERIODIC:
-            return value_i<T>(blks, b, i, j < 0 ? j + B.nj : j - B.nj, cell, ff);
+            return value_i<V>(blks, b, i, j < 0 ? j + B.nj : j - B.nj, cell, ff, mir);
         case HB_BC_WALL:
-            return mirror(value_i<T>(blks, b, i, side == 2 ? k : B.nj - 1 - k, cell, ff));
+            return mir(value_i<V>(blks, b, i, side == 2 ? k : B.nj - 1 - k, cell, ff, mir));
         case HB_BC_WAKECUT: {
             if (i < B.wake || i >= B.ni - B.wake)
-                return value_i<T>(blks, b, B.ni - 1 - i, k, cell, ff);
-            return mirror(value_i<T>(blks, b, i, k, cell, ff));
+                return value_i<V>(blks, b, B.ni - 1 - i, k, cell, ff, mir);
+            return mir(value_i<V>(blks, b, i, k, cell, ff, mir));
         }
         case HB_BC_CUT: {
             const int a = B.cut_blk[side];
-            return value_i<T>(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k, cell, ff);
+            return value_i<V>(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k, cell, ff, mir);
         }
         default:
             return ff(b);
     }
 }
+
+// Wall image of full primitives.
+template <class T>
+struct MirrorFull {
+    __device__ W4<T> operator()(W4<T> w) const { return mirror(w); }
+};
 
 // ---------------------------------------------------------------------------
 // Reconstruction
@@ -181,7 +188,7 @@ struct UVT {
 template <class T>
 __device__ __forceinline__ void viscous_flux(const UVT<T> &L, const UVT<T> &R, const UVT<T> &P,
                                              const UVT<T> &Q, T sx, T sy, T dx, T dy, T mu,
-                                             T kappa, T fv[3]) {
+                                             T kappa, T fv[3], T u0 = T(0), T v0 = T(0)) {
     const T iden = T(1) / (dx * sx + dy * sy);
     const T ax = sx * iden, ay = sy * iden;     // S / (d.S)
     const T bx = dy * iden, by = -dx * iden;    // rot(d) / (d.S)
@@ -196,7 +203,8 @@ __device__ __forceinline__ void viscous_flux(const UVT<T> &L, const UVT<T> &R, c
     const T txy = mu * (uy + vx);
     const T fx = txx * sx + txy * sy;
     const T fy = txy * sx + tyy * sy;
-    const T uf = T(0.5) * (L.u + R.u), vf = T(0.5) * (L.v + R.v);
+    // face velocity; (u0, v0) is added back when L and R hold perturbations
+    const T uf = u0 + T(0.5) * (L.u + R.u), vf = v0 + T(0.5) * (L.v + R.v);
     fv[0] = fx;
     fv[1] = fy;
     fv[2] = uf * fx + vf * fy + kappa * (tx * sx + ty * sy);
@@ -228,6 +236,113 @@ __device__ __forceinline__ T local_dt(const W4<T> &w, T six, T siy, T sjx, T sjy
     const T fac = fmax(T(4.0 / 3.0) / w.r, g / w.r) * mu_pr;
     const T lv = fac * (ai2 + aj2) / V;
     return cfl * V / (li + lj + T(4) * lv + V * omega_nh);
+}
+
+// ---------------------------------------------------------------------------
+// Perturbation form.  The fused kernels carry every snapshot's state as the
+// deviation from that snapshot's free stream (rho_inf = 1, c_inf = 1,
+// p_inf = 1/gamma, T_inf = 1).  Differences of O(1) quantities that cancel
+// are then never formed in the working precision: the flux of a face is
+// F(W) - F(W_inf) (the free-stream flux sums to zero over a closed cell),
+// and the HB source is D (Q - Q_inf) + D Q_inf.  In exact arithmetic the
+// results equal the plain form.
+// ---------------------------------------------------------------------------
+template <class T>
+struct FS {
+    T u, v, p, h;          // free-stream velocity, pressure, total enthalpy
+};
+
+// conserved perturbation (d rho, d rho u, d rho v, d rho E) -> primitive
+// perturbation (d rho, d u, d v, d p)
+template <class T>
+__device__ __forceinline__ W4<T> pert_prim(T dr, T dmx, T dmy, T de, T fu, T fv, T gm1) {
+    const T rho = T(1) + dr;
+    const T ir = T(1) / rho;
+    W4<T> w;
+    w.r = dr;
+    w.u = (dmx - fu * dr) * ir;
+    w.v = (dmy - fv * dr) * ir;
+    const T dk = w.u * (T(2) * fu + w.u) + w.v * (T(2) * fv + w.v);    // |u|^2 - |u_inf|^2
+    w.p = gm1 * (de - T(0.5) * (dr * (fu * fu + fv * fv) + rho * dk));
+    return w;
+}
+
+// wall image of a primitive perturbation: full velocity reversed
+template <class T>
+struct MirrorPert {
+    T fu, fv;
+    __device__ W4<T> operator()(W4<T> w) const {
+        w.u = -w.u - T(2) * fu;
+        w.v = -w.v - T(2) * fv;
+        return w;
+    }
+};
+
+// temperature perturbation T - 1 = (gamma dp - drho) / rho
+template <class T>
+__device__ __forceinline__ T pert_temp(const W4<T> &w, T g) {
+    return (g * w.p - w.r) / (T(1) + w.r);
+}
+
+// Roe flux minus the free-stream flux, times the face length; L and R are
+// primitive perturbations of the same snapshot.
+template <class T>
+__device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, const FS<T> &f,
+                                              T sx, T sy, T g, T delta_frac, T out[4]) {
+    const T area = sqrt(sx * sx + sy * sy);
+    const T ia = T(1) / area;
+    const T nx = sx * ia, ny = sy * ia;
+    const T gg = g / (g - T(1));
+    const T rl = T(1) + L.r, rr = T(1) + R.r;
+    const T ul = f.u + L.u, vl = f.v + L.v, ur = f.u + R.u, vr = f.v + R.v;
+    // enthalpy deviation: gg (p'/rho - p_inf rho'/rho) + (|u|^2 - |u_inf|^2)/2
+    const T dhl = gg * (L.p - f.p * L.r) / rl +
+                  T(0.5) * (L.u * (T(2) * f.u + L.u) + L.v * (T(2) * f.v + L.v));
+    const T dhr = gg * (R.p - f.p * R.r) / rr +
+                  T(0.5) * (R.u * (T(2) * f.u + R.u) + R.v * (T(2) * f.v + R.v));
+    const T hl = f.h + dhl, hr = f.h + dhr;
+    const T sl = sqrt(rl), sr = sqrt(rr);
+    const T iw = T(1) / (sl + sr);
+    const T rt = sl * sr;
+    const T ut = (sl * ul + sr * ur) * iw;
+    const T vt = (sl * vl + sr * vr) * iw;
+    const T ht = (sl * hl + sr * hr) * iw;
+    const T q2t = ut * ut + vt * vt;
+    const T ct = sqrt((g - T(1)) * (ht - T(0.5) * q2t));
+    const T qnt = ut * nx + vt * ny;
+    const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
+    const T dqn = du * nx + dv * ny;
+    const T ic2 = T(1) / (ct * ct);
+    const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
+    const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
+    const T a2 = dr - dp * ic2;
+    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
+    const T l2 = fabs(qnt);
+    if (delta_frac > T(0)) {
+        const T d = delta_frac * ct;
+        if (l1 < d) l1 = (l1 * l1 + d * d) / (T(2) * d);
+        if (l4 < d) l4 = (l4 * l4 + d * d) / (T(2) * d);
+    }
+    const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
+    const T d0 = b1 + b4 + b2;
+    const T d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
+    const T d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
+    const T d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (T(0.5) * q2t) +
+                 bs * (ut * du + vt * dv - qnt * dqn);
+    // F(W) - F(W_inf) per side: with m = rho q_n (m_inf = q_n,inf),
+    // dm = rho' q_n + q_n', then (dm u + m_inf u' + p' n, dm h + m_inf h')
+    const T qni = f.u * nx + f.v * ny;
+    const T qpl = L.u * nx + L.v * ny, qpr = R.u * nx + R.v * ny;
+    const T dml = L.r * (qni + qpl) + qpl;
+    const T dmr = R.r * (qni + qpr) + qpr;
+    const T f0 = dml + dmr;
+    const T f1 = dml * ul + dmr * ur + qni * (L.u + R.u) + (L.p + R.p) * nx;
+    const T f2 = dml * vl + dmr * vr + qni * (L.v + R.v) + (L.p + R.p) * ny;
+    const T f3 = dml * hl + dmr * hr + qni * (dhl + dhr);
+    out[0] = T(0.5) * area * (f0 - d0);
+    out[1] = T(0.5) * area * (f1 - d1);
+    out[2] = T(0.5) * area * (f2 - d2);
+    out[3] = T(0.5) * area * (f3 - d3);
 }
 
 }  // namespace hb

@@ -49,13 +49,13 @@ __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, con
     CellQ cell{blks, q, n, c.gamma - 1.0};
     FF ff{blks, ffw, n};
     const double g = c.gamma;
-    const W4<double> wR = value_ij<double>(blks, b, i, 0, cell, ff);
-    const W4<double> wL = value_ij<double>(blks, b, i, -1, cell, ff);
+    const W4<double> wR = value_ij<W4<double>>(blks, b, i, 0, cell, ff, MirrorFull<double>());
+    const W4<double> wL = value_ij<W4<double>>(blks, b, i, -1, cell, ff, MirrorFull<double>());
     const UVT<double> uL = uvt(wL, g), uR = uvt(wR, g);
-    const UVT<double> nA = avg4(uvt(value_ij<double>(blks, b, i - 1, -1, cell, ff), g), uL,
-                                uvt(value_ij<double>(blks, b, i - 1, 0, cell, ff), g), uR);
-    const UVT<double> nB = avg4(uL, uvt(value_ij<double>(blks, b, i + 1, -1, cell, ff), g), uR,
-                                uvt(value_ij<double>(blks, b, i + 1, 0, cell, ff), g));
+    const UVT<double> nA = avg4(uvt(value_ij<W4<double>>(blks, b, i - 1, -1, cell, ff, MirrorFull<double>()), g), uL,
+                                uvt(value_ij<W4<double>>(blks, b, i - 1, 0, cell, ff, MirrorFull<double>()), g), uR);
+    const UVT<double> nB = avg4(uL, uvt(value_ij<W4<double>>(blks, b, i + 1, -1, cell, ff, MirrorFull<double>()), g), uR,
+                                uvt(value_ij<W4<double>>(blks, b, i + 1, 0, cell, ff, MirrorFull<double>()), g));
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
     const double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];

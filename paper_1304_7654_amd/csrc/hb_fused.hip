@@ -1,12 +1,560 @@
-// Fused batched line-tile kernel (placeholder until written).
+// Fused, batched residual / Runge-Kutta stage kernel.
+//
+// One persistent launch per stage covers every block of the grid: the
+// blocks are cut into TI x TJ tiles (one thread per cell, 256 threads),
+// listed in a flat tile table; each workgroup walks the table with a fixed
+// stride.  Per tile:
+//   A. every thread loads its cell's state for all N_s snapshots (as the
+//      deviation from each snapshot's free stream);
+//   B. the HB source D (Q - Q_inf) of the tile, a [cells x N_s] x [N_s x N_s]
+//      product, runs on the matrix cores (FP32: v_mfma 16x16x4, operands
+//      staged through LDS); FP64 tiles use FMA;
+//   C. for each snapshot: the ghost-extended tile (2-cell halo, boundary
+//      rules applied on the fly) is staged in LDS as primitive perturbations,
+//      node averages of (u, v, T) are formed, each i- and j-face flux
+//      (MUSCL/van Albada + Roe, diamond-path viscous) is computed once, and
+//      each cell sums its four faces, adds V (D Q), and either writes R* or
+//      performs the Runge-Kutta update in FP64 from the iteration's base
+//      state, with the local time step recomputed from that base state.
+// The per-tile partial of sum (R*_rho / V)^2 goes to partials[tile]; a second
+// kernel sums the partials in a fixed order (deterministic norm).
 #include "hb_device.hpp"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace hb {
-int fused_build_tiles(hb_grid *g) { g->n_tiles = 1; return HB_OK; }
-int fused_residual(hb_grid *, const double *, double *, hipStream_t) {
-    return fail(HB_ERR_UNSUPPORTED, "fused path not built");
+namespace {
+
+constexpr int kThreads = 256;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct FusedArgs {
+    const BlockDesc *blks;
+    const Tile *tiles;
+    int n_tiles;
+    const double *q0;      // FP64 base state Q(0); also the stencil input of stage 1
+    const T *sin;          // stencil input of later stages (perturbation form)
+    T *sout;               // perturbation output of intermediate stages
+    double *qout;          // FP64 output: R* (residual mode) or the new state (last stage)
+    const T *SI, *dI, *SJ, *dJ, *V;
+    const T *D;            // kNsPad x kNsPad per block
+    const T *ffw;          // free-stream primitives per snapshot
+    const T *dqinf;        // sum_m D[n][m] Q_inf(m) per snapshot
+    const double *ffq;     // free-stream conserved variables per snapshot (FP64)
+    double *partials;      // per tile
+    int *status;
+    T gamma, mu, kappa, mu_pr, cfl, delta, eps;
+    double alpha;
+    int norm;
+};
+
+// Interior cell of any block as a primitive perturbation of snapshot n.
+template <class T, bool FIRST>
+struct CellPert {
+    const BlockDesc *blks;
+    const double *q0;
+    const T *sin;
+    const double *ffq;
+    int n;
+    T gm1, fu, fv;
+    __device__ W4<T> operator()(int b, int i, int j) const {
+        const BlockDesc &B = blks[b];
+        const int64_t plane = (int64_t)B.ni * B.nj;
+        const int64_t idx = B.q_off + (int64_t)n * 4 * plane + (int64_t)j * B.ni + i;
+        T d0, d1, d2, d3;
+        if constexpr (FIRST) {
+            const double *f = ffq + 4 * (B.snap_off + n);
+            d0 = (T)(q0[idx] - f[0]);
+            d1 = (T)(q0[idx + plane] - f[1]);
+            d2 = (T)(q0[idx + 2 * plane] - f[2]);
+            d3 = (T)(q0[idx + 3 * plane] - f[3]);
+        } else {
+            d0 = sin[idx];
+            d1 = sin[idx + plane];
+            d2 = sin[idx + 2 * plane];
+            d3 = sin[idx + 3 * plane];
+        }
+        return pert_prim<T>(d0, d1, d2, d3, fu, fv, gm1);
+    }
+};
+
+template <class T>
+struct ZeroPert {
+    __device__ W4<T> operator()(int) const { return W4<T>{T(0), T(0), T(0), T(0)}; }
+};
+
+template <int TI, int TJ>
+struct Geo {
+    static constexpr int WE = TI + 4;                  // ext row length
+    static constexpr int EXT = (TI + 4) * (TJ + 4);
+    static constexpr int NOD = (TI + 1) * (TJ + 1);
+    static constexpr int NFI = (TI + 1) * TJ;
+    static constexpr int NFJ = TI * (TJ + 1);
+    static constexpr int SCRATCH = 5 * EXT + 3 * NOD + 4 * NFI + 4 * NFJ;   // elements
+};
+
+template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
+__device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem) {
+    using G = Geo<TI, TJ>;
+    static_assert(TI * TJ == kThreads, "one thread per cell");
+    const BlockDesc &B = a.blks[tl.blk];
+    const int ni = B.ni, nj = B.nj;
+    const int tid = threadIdx.x;
+    const int ti = tid % TI, tj = tid / TI;
+    const int i = tl.i0 + ti, j = tl.j0 + tj;
+    const bool valid = i < ni && j < nj;
+    const int64_t plane = (int64_t)ni * nj;
+    const int64_t cidx = (int64_t)j * ni + i;
+    const T g = a.gamma, gm1 = a.gamma - T(1);
+
+    // ---- A: own-cell state of every snapshot (perturbation form) ---------
+    T dq[NS][4];
+    {
+        T qp[NS][4];
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            const int64_t idx = B.q_off + (int64_t)m * 4 * plane + cidx;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T x = T(0);
+                if (valid) {
+                    if constexpr (FIRST)
+                        x = (T)(a.q0[idx + v * plane] - a.ffq[4 * (B.snap_off + m) + v]);
+                    else
+                        x = a.sin[idx + v * plane];
+                }
+                qp[m][v] = x;
+            }
+        }
+        // ---- B: D (Q - Q_inf) ---------------------------------------------
+        if constexpr (NS == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dq[0][v] = T(0);
+        } else if constexpr (std::is_same<T, float>::value) {
+            // matrix cores: per var v and 16-cell group cb, the 16x16 block
+            // (cells x n) = Q^T[cells x m] * D^T[m x n], K = m in steps of 4
+            float *Qs = reinterpret_cast<float *>(smem);   // [NS][4][256]
+#pragma unroll
+            for (int m = 0; m < NS; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Qs[(m * 4 + v) * kThreads + tid] = qp[m][v];
+            __syncthreads();
+            const int lane = tid & 63, wave = tid >> 6;
+            const int row = lane & 15, kq = lane >> 4;
+            constexpr int KS = (NS + 3) / 4;
+            float bD[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int m = 4 * s + kq;
+                bD[s] = (row < NS && m < NS) ? a.D[B.d_off + row * kNsPad + m] : 0.0f;
+            }
+            for (int grp = wave; grp < 4 * (kThreads / 16); grp += kThreads / 64) {
+                const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int m = 4 * s + kq;
+                    const float av = (m < NS) ? Qs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
+                }
+                // lane holds (cell cb*16 + 4 kq + r, n = row); write in place:
+                // this wave is the only reader/writer of group (v, cb)
+                if (row < NS) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Qs[(row * 4 + v) * kThreads + cb * 16 + 4 * kq + r] = acc[r];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int n = 0; n < NS; ++n)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dq[n][v] = Qs[(n * 4 + v) * kThreads + tid];
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int n = 0; n < NS; ++n)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    T s = T(0);
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) s += a.D[B.d_off + n * kNsPad + m] * qp[m][v];
+                    dq[n][v] = s;
+                }
+        }
+    }
+
+    // geometry of the own cell (time step): mean face normals and area
+    T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
+    if (valid) {
+        const int64_t nfi = (int64_t)(ni + 1) * nj, nfj = (int64_t)ni * (nj + 1);
+        const int64_t fi0 = (int64_t)j * (ni + 1) + i;
+        const T *SIb = a.SI + 2 * B.fi_off, *SJb = a.SJ + 2 * B.fj_off;
+        sxi = T(0.5) * (SIb[fi0] + SIb[fi0 + 1]);
+        syi = T(0.5) * (SIb[nfi + fi0] + SIb[nfi + fi0 + 1]);
+        sxj = T(0.5) * (SJb[cidx] + SJb[cidx + ni]);
+        syj = T(0.5) * (SJb[nfj + cidx] + SJb[nfj + cidx + ni]);
+        vol = a.V[B.cell_off + cidx];
+    }
+
+    // ---- C: snapshot loop -----------------------------------------------
+    T *P = reinterpret_cast<T *>(smem);          // [5][EXT]: rho', u', v', p', T'
+    T *Nd = P + 5 * G::EXT;                      // [3][NOD]: u', v', T' at nodes
+    T *FIs = Nd + 3 * G::NOD;                    // [4][NFI]
+    T *FJs = FIs + 4 * G::NFI;                   // [4][NFJ]
+    double nacc = 0.0;
+    int bad = 0;
+    const int64_t nfi_g = (int64_t)(ni + 1) * nj, nfj_g = (int64_t)ni * (nj + 1);
+    for (int n = 0; n < NS; ++n) {
+        const T *fw = a.ffw + 4 * (B.snap_off + n);
+        FS<T> f;
+        f.u = fw[1];
+        f.v = fw[2];
+        f.p = fw[3];
+        f.h = g / gm1 * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
+        // C1: ghost-extended tile
+        {
+            CellPert<T, FIRST> cell{a.blks, a.q0, a.sin, a.ffq, n, gm1, f.u, f.v};
+            ZeroPert<T> ff;
+            MirrorPert<T> mir{f.u, f.v};
+            for (int e = tid; e < G::EXT; e += kThreads) {
+                const int gi = tl.i0 + e % G::WE - 2, gj = tl.j0 + e / G::WE - 2;
+                W4<T> w{T(0), T(0), T(0), T(0)};
+                if (gi < ni + 2 && gj < nj + 2) w = value_ij<W4<T>>(a.blks, tl.blk, gi, gj, cell, ff, mir);
+                P[e] = w.r;
+                P[G::EXT + e] = w.u;
+                P[2 * G::EXT + e] = w.v;
+                P[3 * G::EXT + e] = w.p;
+                P[4 * G::EXT + e] = pert_temp(w, g);
+            }
+        }
+        __syncthreads();
+        // C2: node averages of (u', v', T')
+        for (int k = tid; k < G::NOD; k += kThreads) {
+            const int a0 = k % (TI + 1), b0 = k / (TI + 1);
+            const int e00 = (b0 + 1) * G::WE + a0 + 1;
+            const int e01 = e00 + G::WE;
+            Nd[k] = T(0.25) * (P[G::EXT + e00] + P[G::EXT + e00 + 1] + P[G::EXT + e01] + P[G::EXT + e01 + 1]);
+            Nd[G::NOD + k] = T(0.25) * (P[2 * G::EXT + e00] + P[2 * G::EXT + e00 + 1] +
+                                        P[2 * G::EXT + e01] + P[2 * G::EXT + e01 + 1]);
+            Nd[2 * G::NOD + k] = T(0.25) * (P[4 * G::EXT + e00] + P[4 * G::EXT + e00 + 1] +
+                                            P[4 * G::EXT + e01] + P[4 * G::EXT + e01 + 1]);
+        }
+        __syncthreads();
+        // C3: face fluxes, each face once
+        for (int k = tid; k < G::NFI + G::NFJ; k += kThreads) {
+            int e0, es, nA, nB;           // first line cell, line stride, edge start/end nodes
+            int64_t fg;
+            const T *Sb, *db;
+            int64_t nf;
+            bool ok;
+            if (k < G::NFI) {
+                const int fi = k % (TI + 1), fj = k / (TI + 1);
+                const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+                ok = gi <= ni && gj < nj;
+                e0 = (fj + 2) * G::WE + fi;
+                es = 1;
+                nA = fj * (TI + 1) + fi;            // node (i, j): edge start
+                nB = nA + (TI + 1);                 // node (i, j+1): edge end
+                fg = (int64_t)gj * (ni + 1) + gi;
+                Sb = a.SI + 2 * B.fi_off;
+                db = a.dI + 2 * B.fi_off;
+                nf = nfi_g;
+            } else {
+                const int k2 = k - G::NFI;
+                const int fi = k2 % TI, fj = k2 / TI;
+                const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+                ok = gi < ni && gj <= nj;
+                e0 = fj * G::WE + fi + 2;
+                es = G::WE;
+                nB = fj * (TI + 1) + fi;            // node (i, j): edge end
+                nA = nB + 1;                        // node (i+1, j): edge start
+                fg = (int64_t)gj * ni + gi;
+                Sb = a.SJ + 2 * B.fj_off;
+                db = a.dJ + 2 * B.fj_off;
+                nf = nfj_g;
+            }
+            if (!ok) continue;
+            W4<T> m2, m1, p0, p1;
+            const int ex[4] = {e0, e0 + es, e0 + 2 * es, e0 + 3 * es};
+            m2 = W4<T>{P[ex[0]], P[G::EXT + ex[0]], P[2 * G::EXT + ex[0]], P[3 * G::EXT + ex[0]]};
+            m1 = W4<T>{P[ex[1]], P[G::EXT + ex[1]], P[2 * G::EXT + ex[1]], P[3 * G::EXT + ex[1]]};
+            p0 = W4<T>{P[ex[2]], P[G::EXT + ex[2]], P[2 * G::EXT + ex[2]], P[3 * G::EXT + ex[2]]};
+            p1 = W4<T>{P[ex[3]], P[G::EXT + ex[3]], P[2 * G::EXT + ex[3]], P[3 * G::EXT + ex[3]]};
+            W4<T> L, R;
+            muscl(m2, m1, p0, p1, a.eps, L, R);
+            const T sx = Sb[fg], sy = Sb[nf + fg];
+            const T dx = db[fg], dy = db[nf + fg];
+            T fl[4];
+            roe_flux_pert(L, R, f, sx, sy, g, a.delta, fl);
+            const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + ex[1]]};
+            const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + ex[2]]};
+            const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
+            const UVT<T> nb{Nd[nB], Nd[G::NOD + nB], Nd[2 * G::NOD + nB]};
+            T fv[3];
+            viscous_flux(uL, uR, na, nb, sx, sy, dx, dy, a.mu, a.kappa, fv, f.u, f.v);
+            T *F = (k < G::NFI) ? FIs + k : FJs + (k - G::NFI);
+            const int st = (k < G::NFI) ? G::NFI : G::NFJ;
+            F[0] = fl[0];
+            F[st] = fl[1] - fv[0];
+            F[2 * st] = fl[2] - fv[1];
+            F[3 * st] = fl[3] - fv[2];
+        }
+        __syncthreads();
+        // C4: cell residual and update
+        if (valid) {
+            const int iw = tj * (TI + 1) + ti, js = tj * TI + ti;
+            T rs[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T r = (FIs[v * G::NFI + iw + 1] - FIs[v * G::NFI + iw]) +
+                            (FJs[v * G::NFJ + js + TI] - FJs[v * G::NFJ + js]);
+                rs[v] = r + vol * (dq[0][v] + a.dqinf[4 * (B.snap_off + n) + v]);
+            }
+            const int64_t o = B.q_off + (int64_t)n * 4 * plane + cidx;
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a.qout[o + v * plane] = (double)rs[v];
+            } else {
+                const double *fq = a.ffq + 4 * (B.snap_off + n);
+                double b0[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) b0[v] = a.q0[o + v * plane];
+                const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
+                                              (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
+                const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
+                const T dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl,
+                                         (T)B.omega_nh);
+                const double fac = a.alpha * (double)dt / (double)vol;
+                double nq[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) nq[v] = b0[v] - fac * (double)rs[v];
+                if constexpr (MODE == 1) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a.sout[o + v * plane] = (T)(nq[v] - fq[v]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a.qout[o + v * plane] = nq[v];
+                }
+                const double pn = (double)gm1 * (nq[3] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]) / nq[0]);
+                if (!(nq[0] > 0.0) || !(pn > 0.0) || !isfinite((double)(rs[0] + rs[1] + rs[2] + rs[3])))
+                    bad = 1;
+            }
+            const double rr = (double)rs[0] / (double)vol;
+            nacc += rr * rr;
+        }
+        // rotate the HB source so that dq[0] belongs to the next snapshot
+#pragma unroll
+        for (int m = 0; m + 1 < NS; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dq[m][v] = dq[m + 1][v];
+    }
+    if (bad) atomicOr(a.status, 1);
+    if (a.norm) {
+        // deterministic tile partial: wave reduction, then 4 waves in order
+        for (int off = 32; off > 0; off >>= 1) nacc += __shfl_xor(nacc, off, 64);
+        __shared__ double wsum[kThreads / 64];
+        __syncthreads();
+        if ((tid & 63) == 0) wsum[tid >> 6] = nacc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) s += wsum[w];
+            a.partials[tile_id] = s;
+        }
+    }
 }
-int fused_rk_iterate(hb_grid *, double *, int, double *, hipStream_t) {
-    return fail(HB_ERR_UNSUPPORTED, "fused path not built");
+
+template <class T, int TI, int TJ, bool FIRST, int MODE>
+__global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const Tile tl = a.tiles[t];
+        switch (tl.ns) {
+            case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem); break;
+            case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem); break;
+            case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem); break;
+            case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem); break;
+            default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem); break;
+        }
+        __syncthreads();
+    }
 }
+
+template <class T, int TI, int TJ>
+size_t smem_bytes(int ns_max) {
+    size_t s = sizeof(T) * (size_t)Geo<TI, TJ>::SCRATCH;
+    if (std::is_same<T, float>::value) s = std::max(s, sizeof(float) * (size_t)ns_max * 4 * kThreads);
+    return s;
+}
+
+template <class T>
+FusedArgs<T> make_args(hb_grid *g);
+
+template <>
+FusedArgs<float> make_args<float>(hb_grid *g) {
+    FusedArgs<float> a{};
+    const Consts &c = g->consts;
+    a.blks = g->blk_d; a.tiles = g->tiles_d; a.n_tiles = g->n_tiles;
+    a.SI = g->SI_f; a.dI = g->dI_f; a.SJ = g->SJ_f; a.dJ = g->dJ_f; a.V = g->V_f;
+    a.D = g->D_f; a.ffw = g->ffw_f; a.dqinf = g->dqinf_f; a.ffq = g->ffq_d;
+    a.partials = g->partials_d; a.status = g->status_d;
+    a.gamma = (float)c.gamma; a.mu = (float)c.mu; a.kappa = (float)c.kappa;
+    a.mu_pr = (float)(c.mu / c.prandtl); a.cfl = (float)c.cfl; a.delta = (float)c.delta_frac;
+    a.eps = (float)c.eps;
+    return a;
+}
+
+template <>
+FusedArgs<double> make_args<double>(hb_grid *g) {
+    FusedArgs<double> a{};
+    const Consts &c = g->consts;
+    a.blks = g->blk_d; a.tiles = g->tiles_d; a.n_tiles = g->n_tiles;
+    a.SI = g->SI_d; a.dI = g->dI_d; a.SJ = g->SJ_d; a.dJ = g->dJ_d; a.V = g->V_d;
+    a.D = g->D_d; a.ffw = g->ffw_d; a.dqinf = g->dqinf_d; a.ffq = g->ffq_d;
+    a.partials = g->partials_d; a.status = g->status_d;
+    a.gamma = c.gamma; a.mu = c.mu; a.kappa = c.kappa; a.mu_pr = c.mu / c.prandtl; a.cfl = c.cfl;
+    a.delta = c.delta_frac; a.eps = c.eps;
+    return a;
+}
+
+int ns_max(const hb_grid *g) {
+    int m = 1;
+    for (const BlockDesc &B : g->blk) m = std::max(m, B.ns);
+    return m;
+}
+
+template <class T, int TI, int TJ, bool FIRST, int MODE>
+int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
+    const size_t sm = smem_bytes<T, TI, TJ>(ns_max(g));
+    auto kern = k_fused<T, TI, TJ, FIRST, MODE>;
+    hipLaunchKernelGGL(kern, dim3(g->fused_grid), dim3(kThreads), sm, s, a);
+    return check_hip(hipGetLastError(), "fused launch");
+}
+
+template <class T, bool FIRST, int MODE>
+int launch_shape(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
+    if (g->tile_ti == 64) return launch_t<T, 64, 4, FIRST, MODE>(g, a, s);
+    if (g->tile_ti == 16) return launch_t<T, 16, 16, FIRST, MODE>(g, a, s);
+    return launch_t<T, 32, 8, FIRST, MODE>(g, a, s);
+}
+
+// one stage: k = stage index, input/output buffers chosen by the caller
+template <class T>
+int stage(hb_grid *g, bool first, int mode, const double *q0, const T *sin, T *sout, double *qout,
+          double alpha, int norm, hipStream_t s) {
+    FusedArgs<T> a = make_args<T>(g);
+    a.q0 = q0; a.sin = sin; a.sout = sout; a.qout = qout; a.alpha = alpha; a.norm = norm;
+    if (first) {
+        if (mode == 0) return launch_shape<T, true, 0>(g, a, s);
+        if (mode == 1) return launch_shape<T, true, 1>(g, a, s);
+        return fail(HB_ERR_UNSUPPORTED, "one-stage schemes are not supported by the fused path");
+    }
+    if (mode == 1) return launch_shape<T, false, 1>(g, a, s);
+    return launch_shape<T, false, 2>(g, a, s);
+}
+
+template <class T>
+int one_iteration(hb_grid *g, double *q, T *sa, T *sb, double *resnorm, hipStream_t s) {
+    const int ns = g->solver.n_stages;
+    const T *in = nullptr;
+    for (int k = 0; k < ns; ++k) {
+        const bool last = k == ns - 1;
+        T *out = (k % 2 == 0) ? sa : sb;
+        int rc = stage<T>(g, k == 0, last ? 2 : 1, q, in, last ? nullptr : out, last ? q : nullptr,
+                          g->solver.rk_alpha[k], k == 0, s);
+        if (rc) return rc;
+        in = out;
+    }
+    return launch_norm_finalize(g, g->partials_d, g->n_tiles, resnorm, g->ctr_d, s);
+}
+
+template <class T>
+int rk_graph(hb_grid *g, double *q, int n_iter, double *resnorm, T *sa, T *sb, hipStream_t s) {
+    int rc = launch_reset_ctr(g->ctr_d, s);
+    if (rc) return rc;
+    const int per = std::max(1, g->solver.graph_iters);
+    if (!g->graph_exec || g->graph_q != q || g->graph_norm != resnorm || g->graph_iters != per) {
+        if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+        g->graph_exec = nullptr;
+        if (!g->cap_stream) {
+            rc = check_hip(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking), "stream");
+            if (rc) return rc;
+        }
+        rc = check_hip(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
+        if (rc) return rc;
+        for (int k = 0; k < per && !rc; ++k) rc = one_iteration<T>(g, q, sa, sb, resnorm, g->cap_stream);
+        hipGraph_t graph = nullptr;
+        const int rc2 = check_hip(hipStreamEndCapture(g->cap_stream, &graph), "end capture");
+        if (rc || rc2) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc ? rc : rc2;
+        }
+        rc = check_hip(hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0), "instantiate");
+        (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+        g->graph_q = q;
+        g->graph_norm = resnorm;
+        g->graph_iters = per;
+    }
+    int done = 0;
+    for (; done + per <= n_iter; done += per) {
+        rc = check_hip(hipGraphLaunch(g->graph_exec, s), "graph launch");
+        if (rc) return rc;
+    }
+    for (; done < n_iter; ++done) {
+        rc = one_iteration<T>(g, q, sa, sb, resnorm, s);
+        if (rc) return rc;
+    }
+    return HB_OK;
+}
+
+}  // namespace
+
+int fused_build_tiles(hb_grid *g) {
+    if (g->solver.n_stages < 2)
+        return fail(HB_ERR_UNSUPPORTED, "the fused path needs at least two Runge-Kutta stages");
+    const char *env = getenv("HB_TILE");
+    int ti = 32;
+    if (env) ti = atoi(env);
+    if (ti != 16 && ti != 32 && ti != 64) ti = 32;
+    g->tile_ti = ti;
+    g->tile_tj = kThreads / ti;
+    std::vector<Tile> tiles;
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        for (int j0 = 0; j0 < B.nj; j0 += g->tile_tj)
+            for (int i0 = 0; i0 < B.ni; i0 += g->tile_ti) tiles.push_back(Tile{b, i0, j0, B.ns});
+    }
+    // heavier tiles first: the static stride then hands every workgroup a
+    // similar mix of snapshot counts
+    std::stable_sort(tiles.begin(), tiles.end(), [](const Tile &x, const Tile &y) { return x.ns > y.ns; });
+    g->n_tiles = (int)tiles.size();
+    hipDeviceProp_t prop;
+    int rc = check_hip(hipGetDeviceProperties(&prop, g->device), "device properties");
+    if (rc) return rc;
+    const int wg_per_cu = 4;
+    g->fused_grid = std::max(1, std::min(g->n_tiles, prop.multiProcessorCount * wg_per_cu));
+    if (g->tiles_d) (void)hipFree(g->tiles_d);
+    g->tiles_d = nullptr;
+    rc = check_hip(hipMalloc((void **)&g->tiles_d, sizeof(Tile) * tiles.size()), "tiles alloc");
+    if (rc) return rc;
+    return check_hip(hipMemcpy(g->tiles_d, tiles.data(), sizeof(Tile) * tiles.size(),
+                               hipMemcpyHostToDevice), "tiles upload");
+}
+
+int fused_residual(hb_grid *g, const double *q, double *r, hipStream_t s) {
+    if (g->solver.precision == HB_FP32_BULK)
+        return stage<float>(g, true, 0, q, nullptr, nullptr, r, 0.0, 0, s);
+    return stage<double>(g, true, 0, q, nullptr, nullptr, r, 0.0, 0, s);
+}
+
+int fused_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s) {
+    if (g->solver.precision == HB_FP32_BULK)
+        return rk_graph<float>(g, q, n_iter, resnorm, g->sa_f, g->sb_f, s);
+    return rk_graph<double>(g, q, n_iter, resnorm, g->qa_d, g->qb_d, s);
+}
+
 }  // namespace hb

@@ -48,7 +48,7 @@ __global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const dou
     const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
     CellFromState cell{blks, q, n, gm1};
     FreeStream ff{blks, ffw, n};
-    const W4<double> w = value_ij<double>(blks, b, i, j, cell, ff);
+    const W4<double> w = value_ij<W4<double>>(blks, b, i, j, cell, ff, MirrorFull<double>());
     double *e = ext + B.ext_off + (int64_t)n * 4 * plane + r;
     e[0] = w.r;
     e[plane] = w.u;

@@ -88,3 +88,99 @@ def test_forces_fp64(name):
     cf = g.forces(q1.to(DEV)).cpu()
     torch.cuda.synchronize()
     assert torch.allclose(cf, ref, rtol=1e-11, atol=1e-13 * float(ref.abs().max()))
+
+
+# --------------------------------------------------------------------------
+# Fused batched path
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+def test_fused_fp64_residual(name):
+    _say("case", name, "fused FP64 residual")
+    p = synth.make_problem(name)
+    blocks, flow, solver = O.from_synth(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    ref = O.residual_all(blocks, q, flow, solver)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    r = g.residual(q.to(DEV)).cpu()
+    torch.cuda.synchronize()
+    assert per_var_rel(blocks, r, ref) <= 1e-12
+    assert elem_rel(blocks, r, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fused_fp32_residual(name):
+    """FP32 bulk: flux and source arithmetic in FP32 (perturbation form),
+    R* stated relative to the FP64 oracle per variable: <= 1e-5."""
+    _say("case", name, "fused FP32 residual")
+    p = synth.make_problem(name)
+    blocks, flow, solver = O.from_synth(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    ref = O.residual_all(blocks, q, flow, solver)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+    r = g.residual(q.to(DEV)).cpu()
+    torch.cuda.synchronize()
+    err = per_var_rel(blocks, r, ref)
+    _say("  FP32 residual rel error", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["cyl_tiny", "batch_tiny", "cyl64x32_nh1"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_rk_iterate(name, prec):
+    _say("case", name, "fused RK precision", prec)
+    p = synth.make_problem(name)
+    blocks, flow, solver = O.from_synth(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    n_it = 3
+    qref, nref = O.rk_iterate(blocks, q, flow, solver, n_it)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=1)
+    qd = q.to(DEV)
+    norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    g.rk_iterate(qd, n_it, norms)
+    torch.cuda.synchronize()
+    assert g.status() == hb.HB_OK
+    tol = 1e-11 if prec == 0 else 1e-5
+    err = per_var_rel(blocks, (qd.cpu() - q), (qref - q))
+    nerr = float(((norms.cpu() - nref).abs() / nref).max())
+    _say("  state-change rel error", err, "norm rel error", nerr)
+    assert err <= tol
+    assert nerr <= (1e-12 if prec == 0 else 1e-5)
+
+
+def test_fused_deterministic_and_tile_independent():
+    """Repeated runs are bitwise identical; other tile shapes give the same
+    residual (each face flux is the same function of the same inputs)."""
+    import os
+    p = synth.make_problem("batch_tiny")
+    q = torch.as_tensor(synth.initial_state(p)).to(DEV)
+    outs = []
+    for tile in ("32", "16", "64"):
+        os.environ["HB_TILE"] = tile
+        g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+        r1 = g.residual(q).clone()
+        r2 = g.residual(q).clone()
+        q1 = q.clone()
+        n1 = torch.zeros(2, dtype=torch.float64, device=DEV)
+        g.rk_iterate(q1, 2, n1)
+        q2 = q.clone()
+        n2 = torch.zeros(2, dtype=torch.float64, device=DEV)
+        g.rk_iterate(q2, 2, n2)
+        torch.cuda.synchronize()
+        assert torch.equal(r1, r2) and torch.equal(q1, q2) and torch.equal(n1, n2)
+        outs.append(r1.cpu())
+        g.close()
+    os.environ.pop("HB_TILE")
+    for o in outs[1:]:
+        rel = float((o - outs[0]).norm() / outs[0].norm())
+        _say("  tile shape difference", rel, "bitwise" if torch.equal(o, outs[0]) else "")
+        assert rel <= 1e-6
+
+
+def test_fused_matches_plain_fp64():
+    p = synth.make_problem("naca4blk_nh2")
+    q = torch.as_tensor(synth.initial_state(p)).to(DEV)
+    gp = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    gf = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    rp, rf = gp.residual(q), gf.residual(q)
+    torch.cuda.synchronize()
+    assert float((rp - rf).norm() / rp.norm()) <= 1e-13
