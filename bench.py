@@ -1,0 +1,229 @@
+"""Benchmark of the HB residual + Runge-Kutta hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch32_mixed]
+
+One step = one pseudo-time iteration of the whole hot path over the
+workload: four Runge-Kutta stages (ghosts, MUSCL/Roe and viscous fluxes, HB
+source D.Q, local time step, update), the residual norm and the force
+coefficients of every body, as hb_rk_iterate(q, 1, resnorm, forces).
+Inputs are seeded and synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: the FP32-bulk batched rate (value), the plain FP64
+per-block rate beside it, the live roofline of the fused stage kernel
+(HIP events around each stage launch on the launch stream), the HBM traffic
+of that kernel from the committed rocprofv3 counter summary (when it was
+taken on the current kernel source), and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = ("cell-snapshot RK-stage updates/s (FP32+batched vs FP64 plain); "
+          "adjoint/primal time")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_traffic.txt")
+KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per fused stage launch from the committed counter summary,
+    or None when it is missing or was taken on another kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def algorithmic_bytes_per_iteration(problem) -> float:
+    """Bytes the FP32-bulk iteration must move (4 stages), the design doc table:
+    stage 1 reads Q (FP64, 32 B/cs) and writes the FP32 stage state (16);
+    stages 2-3 read the stage state (16) and Q (32) and write (16); stage 4
+    reads the stage state (16) and Q (32) and writes Q (32).  Each stage also
+    reads 9 FP32 metric words per cell (two face normals, two centre
+    offsets, the area)."""
+    cs = problem.cell_snapshots
+    cells = sum(b.ni * b.nj for b in problem.blocks)
+    return cs * (48 + 64 + 64 + 80) + 4 * 36 * cells
+
+
+def time_steps(torch, g, q, steps, forces=True):
+    cf = torch.empty(g.n_forces, dtype=torch.float64, device=q.device) if forces else None
+    norms = torch.empty(steps, dtype=torch.float64, device=q.device)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        g.rk_iterate(q, 1, norms[k:k + 1], cf)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1000.0, norms
+
+
+def cpu_baseline(problem, q_host, target_s=12.0):
+    """FP64 oracle (as is) on a bounded sample of the workload's blocks."""
+    import torch
+    from oracle import hb_oracle as O
+    blocks, flow, solver = O.from_synth(problem)
+    qs = O.split(blocks, torch.as_tensor(q_host))
+    # sample: blocks in order until ~1.2M cell-snapshots, one iteration first
+    sel, cs = [], 0
+    for k, b in enumerate(blocks):
+        sel.append(k)
+        cs += b.ns * b.ni * b.nj
+        if cs >= 1_200_000:
+            break
+    sb = [blocks[k] for k in sel]
+    sq = O.join([qs[k] for k in sel])
+    t0 = time.perf_counter()
+    O.rk_iterate(sb, sq, flow, solver, 1)
+    dt = time.perf_counter() - t0
+    iters = 1
+    if dt < target_s / 2:
+        extra = max(1, int(target_s / dt) - 1)
+        t0 = time.perf_counter()
+        O.rk_iterate(sb, sq, flow, solver, extra)
+        dt = time.perf_counter() - t0
+        iters = extra
+    units = cs * len(solver.rk_alpha) * iters
+    return {"value": units / dt, "unit": "cell-snapshot RK-stage updates/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "%d of %d blocks (%d cell-snapshots), %d iteration(s), %.1f s"
+                      % (len(sel), len(blocks), cs, iters, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch32_mixed")
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU block decomposition is described in DESIGN.md, not built)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1304_7654_amd import hb, synth
+
+    dev = torch.device("cuda:0")
+    problem = synth.make_problem(args.workload)
+    q_host = synth.initial_state(problem)
+    q0 = torch.as_tensor(q_host).to(dev)
+    cs = problem.cell_snapshots
+    stages = len(problem.solver.rk_alpha)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ---- FP32-bulk batched (the product path) ------------------------------
+    g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=1, batched=1)
+    q = q0.clone()
+    time_steps(torch, g, q, args.warmup)
+    q = q0.clone()
+    t, norms = time_steps(torch, g, q, args.steps)
+    assert g.status() == hb.HB_OK, "non-finite state in the FP32 run"
+    value = cs * stages * args.steps / t
+    # live roofline of the fused stage kernel: events around each stage launch
+    q = q0.clone()
+    g.profile_stages(True)
+    time_steps(torch, g, q, args.steps, forces=False)
+    st_ms, st_n = g.stage_stats()
+    g.profile_stages(False)
+    stage_s = st_ms / 1000.0 / st_n
+    bytes_launch = algorithmic_bytes_per_iteration(problem) / stages
+    achieved = bytes_launch / stage_s / 1e9
+    traffic = read_traffic()
+    g.close()
+
+    # ---- plain FP64, per-block launches (baseline on the same GPU) ---------
+    gp = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=0)
+    q = q0.clone()
+    time_steps(torch, gp, q, 1)
+    q = q0.clone()
+    tp, _ = time_steps(torch, gp, q, args.plain_steps)
+    plain = cs * stages * args.plain_steps / tp
+    gp.close()
+    # ---- fused FP64 (same kernel design, FP64 arithmetic) ------------------
+    gf = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=1)
+    q = q0.clone()
+    time_steps(torch, gf, q, 1)
+    q = q0.clone()
+    tf, _ = time_steps(torch, gf, q, args.plain_steps)
+    fused64 = cs * stages * args.plain_steps / tf
+    gf.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-snapshot RK-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 flux/source, f64 state/update/norms/forces",
+        "data": "synthetic (seeded O-grid blocks, free stream + 1e-3 Gaussian perturbation)",
+        "config": {"workload": args.workload, "blocks": len(problem.blocks),
+                   "cell_snapshots": cs, "stages_per_step": stages,
+                   "parallelism": "single GPU, one persistent launch per stage"},
+        "fp64_plain_per_block": {"value": plain, "ms_per_step": 1000.0 * tp / args.plain_steps,
+                                 "speedup_of_value": value / plain},
+        "fp64_fused_batched": {"value": fused64, "ms_per_step": 1000.0 * tf / args.plain_steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "adjoint_over_primal": None,
+        "resnorm_last": float(norms[-1].item()),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(problem, q_host)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -191,6 +191,15 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
  * (the flag is then cleared), else HB_OK. */
 int hb_get_status(hb_grid *g);
 
+/* Instrumentation for benchmarks.  With enable = 1, hb_rk_iterate runs its
+ * stages one launch at a time (no graph replay) and brackets each stage's
+ * kernel launches with a pair of HIP events recorded on the caller's stream.
+ * hb_stage_stats synchronises on the last event, returns the summed
+ * elapsed milliseconds of all bracketed stages and their number since the
+ * previous call, and resets both.  Either pointer may be NULL. */
+int hb_profile_stages(hb_grid *g, int32_t enable);
+int hb_stage_stats(hb_grid *g, double *total_ms, int64_t *stages);
+
 /* Message of the last error on this thread ("" if none). */
 const char *hb_last_error(void);
 

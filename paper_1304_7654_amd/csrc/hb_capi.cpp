@@ -50,6 +50,8 @@ void dfree(T *&p) {
 }
 
 void free_all(hb_grid *g) {
+    for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+    g->prof_ev.clear();
     if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
     g->graph_exec = nullptr;
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
@@ -124,6 +126,26 @@ int upload_snapshot_tables(hb_grid *g) {
     for (size_t k = 0; k < tmp.size() && !rc; ++k) tmp[k] = (float)dq[k];
     rc = rc ? rc : check_hip(hipMemcpy(g->dqinf_f, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice), "upload");
     return rc;
+}
+
+int prof_begin(hb_grid *g, hipStream_t s, hipEvent_t *end) {
+    *end = nullptr;
+    if (!g->prof) return HB_OK;
+    while (g->prof_ev.size() < g->prof_used + 2) {
+        hipEvent_t e;
+        int rc = check_hip(hipEventCreate(&e), "event create");
+        if (rc) return rc;
+        g->prof_ev.push_back(e);
+    }
+    hipEvent_t b = g->prof_ev[g->prof_used];
+    *end = g->prof_ev[g->prof_used + 1];
+    g->prof_used += 2;
+    return check_hip(hipEventRecord(b, s), "event record");
+}
+
+int prof_end(hipEvent_t end, hipStream_t s) {
+    if (!end) return HB_OK;
+    return check_hip(hipEventRecord(end, s), "event record");
 }
 
 }  // namespace hb
@@ -465,6 +487,31 @@ int hb_set_alpha0(hb_grid *g, double alpha0) {
     if (rc) return rc;
     g->flow.alpha0 = alpha0;
     return upload_snapshot_tables(g);
+}
+
+int hb_profile_stages(hb_grid *g, int32_t enable) {
+    g_err.clear();
+    if (!g) return fail(HB_ERR_ARG, "NULL grid");
+    g->prof = enable ? 1 : 0;
+    return HB_OK;
+}
+
+int hb_stage_stats(hb_grid *g, double *total_ms, int64_t *stages) {
+    g_err.clear();
+    if (!g) return fail(HB_ERR_ARG, "NULL grid");
+    double ms = 0.0;
+    for (size_t k = 0; k + 1 < g->prof_used; k += 2) {
+        int rc = check_hip(hipEventSynchronize(g->prof_ev[k + 1]), "event sync");
+        if (rc) return rc;
+        float t = 0.0f;
+        rc = check_hip(hipEventElapsedTime(&t, g->prof_ev[k], g->prof_ev[k + 1]), "elapsed");
+        if (rc) return rc;
+        ms += t;
+    }
+    if (total_ms) *total_ms = ms;
+    if (stages) *stages = (int64_t)(g->prof_used / 2);
+    g->prof_used = 0;
+    return HB_OK;
 }
 
 int hb_get_status(hb_grid *g) {

@@ -20,6 +20,18 @@ struct W4 {
     T r, u, v, p;
 };
 
+// Reciprocal and square root: exact IEEE operations in FP64; in FP32 the
+// hardware v_rcp_f32 / v_sqrt_f32 (1 ulp), well inside the FP32 budget
+// and much shorter than the correctly rounded sequences.
+template <class T>
+__device__ __forceinline__ T frcp(T x) { return T(1) / x; }
+template <>
+__device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <class T>
+__device__ __forceinline__ T fsqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <class T>
 __device__ __forceinline__ W4<T> prim_from_cons(T q0, T q1, T q2, T q3, T gm1) {
     W4<T> w;
@@ -105,7 +117,7 @@ struct MirrorFull {
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ T van_albada(T a, T b, T eps) {
-    return (a + b) * (a * b + eps) / (a * a + b * b + T(2) * eps);
+    return (a + b) * (a * b + eps) * frcp(a * a + b * b + T(2) * eps);
 }
 
 // Face states between cells m1 and p0 of a grid line m2, m1, p0, p1.
@@ -128,8 +140,8 @@ __device__ __forceinline__ void muscl(const W4<T> &m2, const W4<T> &m1, const W4
 template <class T>
 __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T sy, T g,
                                          T delta_frac, T f[4]) {
-    const T area = sqrt(sx * sx + sy * sy);
-    const T ia = T(1) / area;
+    const T area = fsqrt(sx * sx + sy * sy);
+    const T ia = frcp(area);
     const T nx = sx * ia, ny = sy * ia;
     const T gg = g / (g - T(1));
     const T hl = gg * L.p / L.r + T(0.5) * (L.u * L.u + L.v * L.v);
@@ -141,11 +153,11 @@ __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T
     const T vt = (sl * L.v + sr * R.v) * iw;
     const T ht = (sl * hl + sr * hr) * iw;
     const T q2t = ut * ut + vt * vt;
-    const T ct = sqrt((g - T(1)) * (ht - T(0.5) * q2t));
+    const T ct = fsqrt((g - T(1)) * (ht - T(0.5) * q2t));
     const T qnt = ut * nx + vt * ny;
     const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
     const T dqn = du * nx + dv * ny;
-    const T ic2 = T(1) / (ct * ct);
+    const T ic2 = frcp(ct * ct);
     const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
     const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
     const T a2 = dr - dp * ic2;
@@ -153,8 +165,9 @@ __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T
     const T l2 = fabs(qnt);
     if (delta_frac > T(0)) {
         const T d = delta_frac * ct;
-        if (l1 < d) l1 = (l1 * l1 + d * d) / (T(2) * d);
-        if (l4 < d) l4 = (l4 * l4 + d * d) / (T(2) * d);
+        const T i2d = frcp(T(2) * d);
+        if (l1 < d) l1 = (l1 * l1 + d * d) * i2d;
+        if (l4 < d) l4 = (l4 * l4 + d * d) * i2d;
     }
     const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
     const T d0 = b1 + b4 + b2;
@@ -189,7 +202,7 @@ template <class T>
 __device__ __forceinline__ void viscous_flux(const UVT<T> &L, const UVT<T> &R, const UVT<T> &P,
                                              const UVT<T> &Q, T sx, T sy, T dx, T dy, T mu,
                                              T kappa, T fv[3], T u0 = T(0), T v0 = T(0)) {
-    const T iden = T(1) / (dx * sx + dy * sy);
+    const T iden = frcp(dx * sx + dy * sy);
     const T ax = sx * iden, ay = sy * iden;     // S / (d.S)
     const T bx = dy * iden, by = -dx * iden;    // rot(d) / (d.S)
     const T du = R.u - L.u, dv = R.v - L.v, dt = R.t - L.t;
@@ -229,13 +242,14 @@ __device__ __forceinline__ UVT<T> avg4(const UVT<T> &a, const UVT<T> &b, const U
 template <class T>
 __device__ __forceinline__ T local_dt(const W4<T> &w, T six, T siy, T sjx, T sjy, T V, T g,
                                       T mu_pr, T cfl, T omega_nh) {
-    const T c = sqrt(g * w.p / w.r);
+    const T ir = frcp(w.r);
+    const T c = fsqrt(g * w.p * ir);
     const T ai2 = six * six + siy * siy, aj2 = sjx * sjx + sjy * sjy;
-    const T li = fabs(w.u * six + w.v * siy) + c * sqrt(ai2);
-    const T lj = fabs(w.u * sjx + w.v * sjy) + c * sqrt(aj2);
-    const T fac = fmax(T(4.0 / 3.0) / w.r, g / w.r) * mu_pr;
-    const T lv = fac * (ai2 + aj2) / V;
-    return cfl * V / (li + lj + T(4) * lv + V * omega_nh);
+    const T li = fabs(w.u * six + w.v * siy) + c * fsqrt(ai2);
+    const T lj = fabs(w.u * sjx + w.v * sjy) + c * fsqrt(aj2);
+    const T fac = fmax(T(4.0 / 3.0) * ir, g * ir) * mu_pr;
+    const T lv = fac * (ai2 + aj2) * frcp(V);
+    return cfl * V * frcp(li + lj + T(4) * lv + V * omega_nh);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,6 +264,7 @@ __device__ __forceinline__ T local_dt(const W4<T> &w, T six, T siy, T sjx, T sjy
 template <class T>
 struct FS {
     T u, v, p, h;          // free-stream velocity, pressure, total enthalpy
+    T gg;                  // gamma / (gamma - 1)
 };
 
 // conserved perturbation (d rho, d rho u, d rho v, d rho E) -> primitive
@@ -257,7 +272,7 @@ struct FS {
 template <class T>
 __device__ __forceinline__ W4<T> pert_prim(T dr, T dmx, T dmy, T de, T fu, T fv, T gm1) {
     const T rho = T(1) + dr;
-    const T ir = T(1) / rho;
+    const T ir = frcp(rho);
     W4<T> w;
     w.r = dr;
     w.u = (dmx - fu * dr) * ir;
@@ -281,7 +296,7 @@ struct MirrorPert {
 // temperature perturbation T - 1 = (gamma dp - drho) / rho
 template <class T>
 __device__ __forceinline__ T pert_temp(const W4<T> &w, T g) {
-    return (g * w.p - w.r) / (T(1) + w.r);
+    return (g * w.p - w.r) * frcp(T(1) + w.r);
 }
 
 // Roe flux minus the free-stream flux, times the face length; L and R are
@@ -289,30 +304,30 @@ __device__ __forceinline__ T pert_temp(const W4<T> &w, T g) {
 template <class T>
 __device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, const FS<T> &f,
                                               T sx, T sy, T g, T delta_frac, T out[4]) {
-    const T area = sqrt(sx * sx + sy * sy);
-    const T ia = T(1) / area;
+    const T area = fsqrt(sx * sx + sy * sy);
+    const T ia = frcp(area);
     const T nx = sx * ia, ny = sy * ia;
-    const T gg = g / (g - T(1));
+    const T gg = f.gg;
     const T rl = T(1) + L.r, rr = T(1) + R.r;
     const T ul = f.u + L.u, vl = f.v + L.v, ur = f.u + R.u, vr = f.v + R.v;
     // enthalpy deviation: gg (p'/rho - p_inf rho'/rho) + (|u|^2 - |u_inf|^2)/2
-    const T dhl = gg * (L.p - f.p * L.r) / rl +
+    const T dhl = gg * (L.p - f.p * L.r) * frcp(rl) +
                   T(0.5) * (L.u * (T(2) * f.u + L.u) + L.v * (T(2) * f.v + L.v));
-    const T dhr = gg * (R.p - f.p * R.r) / rr +
+    const T dhr = gg * (R.p - f.p * R.r) * frcp(rr) +
                   T(0.5) * (R.u * (T(2) * f.u + R.u) + R.v * (T(2) * f.v + R.v));
     const T hl = f.h + dhl, hr = f.h + dhr;
-    const T sl = sqrt(rl), sr = sqrt(rr);
-    const T iw = T(1) / (sl + sr);
+    const T sl = fsqrt(rl), sr = fsqrt(rr);
+    const T iw = frcp(sl + sr);
     const T rt = sl * sr;
     const T ut = (sl * ul + sr * ur) * iw;
     const T vt = (sl * vl + sr * vr) * iw;
     const T ht = (sl * hl + sr * hr) * iw;
     const T q2t = ut * ut + vt * vt;
-    const T ct = sqrt((g - T(1)) * (ht - T(0.5) * q2t));
+    const T ct = fsqrt((g - T(1)) * (ht - T(0.5) * q2t));
     const T qnt = ut * nx + vt * ny;
     const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
     const T dqn = du * nx + dv * ny;
-    const T ic2 = T(1) / (ct * ct);
+    const T ic2 = frcp(ct * ct);
     const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
     const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
     const T a2 = dr - dp * ic2;
@@ -320,8 +335,9 @@ __device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, co
     const T l2 = fabs(qnt);
     if (delta_frac > T(0)) {
         const T d = delta_frac * ct;
-        if (l1 < d) l1 = (l1 * l1 + d * d) / (T(2) * d);
-        if (l4 < d) l4 = (l4 * l4 + d * d) / (T(2) * d);
+        const T i2d = frcp(T(2) * d);
+        if (l1 < d) l1 = (l1 * l1 + d * d) * i2d;
+        if (l4 < d) l4 = (l4 * l4 + d * d) * i2d;
     }
     const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
     const T d0 = b1 + b4 + b2;

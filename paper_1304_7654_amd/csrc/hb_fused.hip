@@ -48,6 +48,7 @@ struct FusedArgs {
     T gamma, mu, kappa, mu_pr, cfl, delta, eps;
     double alpha;
     int norm;
+    int dq_bytes;          // FP32: bytes of the LDS HB-source area before the scratch
 };
 
 // Interior cell of any block as a primitive perturbation of snapshot n.
@@ -92,13 +93,78 @@ struct Geo {
     static constexpr int NOD = (TI + 1) * (TJ + 1);
     static constexpr int NFI = (TI + 1) * TJ;
     static constexpr int NFJ = TI * (TJ + 1);
-    static constexpr int SCRATCH = 5 * EXT + 3 * NOD + 4 * NFI + 4 * NFJ;   // elements
+    static constexpr int NFMAX = NFI > NFJ ? NFI : NFJ;
+    static constexpr int SCRATCH = 5 * EXT + 3 * NOD + 4 * NFMAX;   // elements
 };
+
+// Flux of one face of the tile (perturbation form, times the face length),
+// written to F[v * NFMAX + k].  IFACE: i-face k = fj*(TI+1) + fi between
+// cells fi-1 and fi of row fj; else j-face k = fj*TI + fi between rows fj-1
+// and fj of column fi.  Returns without writing for faces outside the block.
+template <class T, int TI, int TJ, bool IFACE>
+__device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const BlockDesc &B, const Tile &tl,
+                                          int k, const T *P, const T *Nd, T *F, const FS<T> &f) {
+    using G = Geo<TI, TJ>;
+    const int ni = B.ni, nj = B.nj;
+    int e0, es, nA, nB;
+    int64_t fg, nf;
+    const T *Sb, *db;
+    if constexpr (IFACE) {
+        const int fi = k % (TI + 1), fj = k / (TI + 1);
+        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        if (!(gi <= ni && gj < nj)) return;
+        e0 = (fj + 2) * G::WE + fi;
+        es = 1;
+        nA = fj * (TI + 1) + fi;            // node (i, j): edge start
+        nB = nA + (TI + 1);                 // node (i, j+1): edge end
+        fg = (int64_t)gj * (ni + 1) + gi;
+        nf = (int64_t)(ni + 1) * nj;
+        Sb = a.SI + 2 * B.fi_off;
+        db = a.dI + 2 * B.fi_off;
+    } else {
+        const int fi = k % TI, fj = k / TI;
+        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        if (!(gi < ni && gj <= nj)) return;
+        e0 = fj * G::WE + fi + 2;
+        es = G::WE;
+        nB = fj * (TI + 1) + fi;            // node (i, j): edge end
+        nA = nB + 1;                        // node (i+1, j): edge start
+        fg = (int64_t)gj * ni + gi;
+        nf = (int64_t)ni * (nj + 1);
+        Sb = a.SJ + 2 * B.fj_off;
+        db = a.dJ + 2 * B.fj_off;
+    }
+    const T sx = Sb[fg], sy = Sb[nf + fg];
+    const T dx = db[fg], dy = db[nf + fg];
+    const int x0 = e0, x1 = e0 + es, x2 = e0 + 2 * es, x3 = e0 + 3 * es;
+    const W4<T> m2{P[x0], P[G::EXT + x0], P[2 * G::EXT + x0], P[3 * G::EXT + x0]};
+    const W4<T> m1{P[x1], P[G::EXT + x1], P[2 * G::EXT + x1], P[3 * G::EXT + x1]};
+    const W4<T> p0{P[x2], P[G::EXT + x2], P[2 * G::EXT + x2], P[3 * G::EXT + x2]};
+    const W4<T> p1{P[x3], P[G::EXT + x3], P[2 * G::EXT + x3], P[3 * G::EXT + x3]};
+    W4<T> L, R;
+    muscl(m2, m1, p0, p1, a.eps, L, R);
+    T fl[4];
+    roe_flux_pert(L, R, f, sx, sy, a.gamma, a.delta, fl);
+    const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + x1]};
+    const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + x2]};
+    const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
+    const UVT<T> nb{Nd[nB], Nd[G::NOD + nB], Nd[2 * G::NOD + nB]};
+    T fv[3];
+    viscous_flux(uL, uR, na, nb, sx, sy, dx, dy, a.mu, a.kappa, fv, f.u, f.v);
+    F[k] = fl[0];
+    F[G::NFMAX + k] = fl[1] - fv[0];
+    F[2 * G::NFMAX + k] = fl[2] - fv[1];
+    F[3 * G::NFMAX + k] = fl[3] - fv[2];
+}
 
 template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
 __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem) {
     using G = Geo<TI, TJ>;
     static_assert(TI * TJ == kThreads, "one thread per cell");
+    // FP32: the HB source goes through the matrix cores and stays in LDS
+    // (DQs, [N_s][4][cells]) for the whole snapshot loop; FP64: FMA, held in
+    // registers.
+    constexpr bool MF = std::is_same<T, float>::value;
     const BlockDesc &B = a.blks[tl.blk];
     const int ni = B.ni, nj = B.nj;
     const int tid = threadIdx.x;
@@ -108,39 +174,32 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     const int64_t plane = (int64_t)ni * nj;
     const int64_t cidx = (int64_t)j * ni + i;
     const T g = a.gamma, gm1 = a.gamma - T(1);
+    T *DQs = reinterpret_cast<T *>(smem);
+    T *P = reinterpret_cast<T *>(smem + (MF ? a.dq_bytes : 0));   // [5][EXT]: rho', u', v', p', T'
+    T *Nd = P + 5 * G::EXT;                                        // [3][NOD]: u', v', T' at nodes
+    T *F = Nd + 3 * G::NOD;                                        // [4][NFMAX]
 
-    // ---- A: own-cell state of every snapshot (perturbation form) ---------
-    T dq[NS][4];
-    {
-        T qp[NS][4];
-#pragma unroll
-        for (int m = 0; m < NS; ++m) {
-            const int64_t idx = B.q_off + (int64_t)m * 4 * plane + cidx;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                T x = T(0);
-                if (valid) {
-                    if constexpr (FIRST)
-                        x = (T)(a.q0[idx + v * plane] - a.ffq[4 * (B.snap_off + m) + v]);
-                    else
-                        x = a.sin[idx + v * plane];
-                }
-                qp[m][v] = x;
-            }
-        }
-        // ---- B: D (Q - Q_inf) ---------------------------------------------
-        if constexpr (NS == 1) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dq[0][v] = T(0);
-        } else if constexpr (std::is_same<T, float>::value) {
-            // matrix cores: per var v and 16-cell group cb, the 16x16 block
-            // (cells x n) = Q^T[cells x m] * D^T[m x n], K = m in steps of 4
-            float *Qs = reinterpret_cast<float *>(smem);   // [NS][4][256]
+    // own-cell state of snapshot m, variable v (perturbation form)
+    auto load_own = [&](int m, int v) -> T {
+        if (!valid) return T(0);
+        const int64_t idx = B.q_off + ((int64_t)m * 4 + v) * plane + cidx;
+        if constexpr (FIRST)
+            return (T)(a.q0[idx] - a.ffq[4 * (B.snap_off + m) + v]);
+        else
+            return a.sin[idx];
+    };
+
+    // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
+    T dq[MF ? 1 : NS][4];
+    if constexpr (MF) {
+        if constexpr (NS > 1) {
 #pragma unroll
             for (int m = 0; m < NS; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Qs[(m * 4 + v) * kThreads + tid] = qp[m][v];
+                for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kThreads + tid] = load_own(m, v);
             __syncthreads();
+            // per var v and 16-cell group cb: the 16x16 block (cells x n) =
+            // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4)
             const int lane = tid & 63, wave = tid >> 6;
             const int row = lane & 15, kq = lane >> 4;
             constexpr int KS = (NS + 3) / 4;
@@ -156,38 +215,41 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     const int m = 4 * s + kq;
-                    const float av = (m < NS) ? Qs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
+                    const float av = (m < NS) ? DQs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
                     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
                 }
-                // lane holds (cell cb*16 + 4 kq + r, n = row); write in place:
-                // this wave is the only reader/writer of group (v, cb)
+                // lane holds (cell cb*16 + 4 kq + r, n = row); written in
+                // place: only this wave reads or writes group (v, cb), and
+                // every read feeds the MFMAs before the results exist
                 if (row < NS) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        Qs[(row * 4 + v) * kThreads + cb * 16 + 4 * kq + r] = acc[r];
+                        DQs[(row * 4 + v) * kThreads + cb * 16 + 4 * kq + r] = acc[r];
                 }
             }
-            __syncthreads();
-#pragma unroll
-            for (int n = 0; n < NS; ++n)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) dq[n][v] = Qs[(n * 4 + v) * kThreads + tid];
-            __syncthreads();
-        } else {
-#pragma unroll
-            for (int n = 0; n < NS; ++n)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    T s = T(0);
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) s += a.D[B.d_off + n * kNsPad + m] * qp[m][v];
-                    dq[n][v] = s;
-                }
+            // the first barrier of the snapshot loop orders these writes
+            // before their reads
         }
+    } else {
+        T qp[NS][4];
+#pragma unroll
+        for (int m = 0; m < NS; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) qp[m][v] = load_own(m, v);
+#pragma unroll
+        for (int n = 0; n < NS; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                T s = T(0);
+#pragma unroll
+                for (int m = 0; m < NS; ++m) s += a.D[B.d_off + n * kNsPad + m] * qp[m][v];
+                dq[n][v] = s;
+            }
     }
 
     // geometry of the own cell (time step): mean face normals and area
     T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
+    double ivol = 1.0;
     if (valid) {
         const int64_t nfi = (int64_t)(ni + 1) * nj, nfj = (int64_t)ni * (nj + 1);
         const int64_t fi0 = (int64_t)j * (ni + 1) + i;
@@ -197,23 +259,21 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         sxj = T(0.5) * (SJb[cidx] + SJb[cidx + ni]);
         syj = T(0.5) * (SJb[nfj + cidx] + SJb[nfj + cidx + ni]);
         vol = a.V[B.cell_off + cidx];
+        ivol = 1.0 / (double)vol;
     }
 
     // ---- C: snapshot loop -----------------------------------------------
-    T *P = reinterpret_cast<T *>(smem);          // [5][EXT]: rho', u', v', p', T'
-    T *Nd = P + 5 * G::EXT;                      // [3][NOD]: u', v', T' at nodes
-    T *FIs = Nd + 3 * G::NOD;                    // [4][NFI]
-    T *FJs = FIs + 4 * G::NFI;                   // [4][NFJ]
     double nacc = 0.0;
     int bad = 0;
-    const int64_t nfi_g = (int64_t)(ni + 1) * nj, nfj_g = (int64_t)ni * (nj + 1);
+    const int iw = tj * (TI + 1) + ti, js = tj * TI + ti;
     for (int n = 0; n < NS; ++n) {
         const T *fw = a.ffw + 4 * (B.snap_off + n);
         FS<T> f;
         f.u = fw[1];
         f.v = fw[2];
         f.p = fw[3];
-        f.h = g / gm1 * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
+        f.gg = g / gm1;
+        f.h = f.gg * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
         // C1: ghost-extended tile
         {
             CellPert<T, FIRST> cell{a.blks, a.q0, a.sin, a.ffq, n, gm1, f.u, f.v};
@@ -236,82 +296,33 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             const int a0 = k % (TI + 1), b0 = k / (TI + 1);
             const int e00 = (b0 + 1) * G::WE + a0 + 1;
             const int e01 = e00 + G::WE;
-            Nd[k] = T(0.25) * (P[G::EXT + e00] + P[G::EXT + e00 + 1] + P[G::EXT + e01] + P[G::EXT + e01 + 1]);
-            Nd[G::NOD + k] = T(0.25) * (P[2 * G::EXT + e00] + P[2 * G::EXT + e00 + 1] +
-                                        P[2 * G::EXT + e01] + P[2 * G::EXT + e01 + 1]);
-            Nd[2 * G::NOD + k] = T(0.25) * (P[4 * G::EXT + e00] + P[4 * G::EXT + e00 + 1] +
-                                            P[4 * G::EXT + e01] + P[4 * G::EXT + e01 + 1]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T *pc = P + (c == 2 ? 4 : c + 1) * G::EXT;
+                Nd[c * G::NOD + k] = T(0.25) * (pc[e00] + pc[e00 + 1] + pc[e01] + pc[e01 + 1]);
+            }
         }
         __syncthreads();
-        // C3: face fluxes, each face once
-        for (int k = tid; k < G::NFI + G::NFJ; k += kThreads) {
-            int e0, es, nA, nB;           // first line cell, line stride, edge start/end nodes
-            int64_t fg;
-            const T *Sb, *db;
-            int64_t nf;
-            bool ok;
-            if (k < G::NFI) {
-                const int fi = k % (TI + 1), fj = k / (TI + 1);
-                const int gi = tl.i0 + fi, gj = tl.j0 + fj;
-                ok = gi <= ni && gj < nj;
-                e0 = (fj + 2) * G::WE + fi;
-                es = 1;
-                nA = fj * (TI + 1) + fi;            // node (i, j): edge start
-                nB = nA + (TI + 1);                 // node (i, j+1): edge end
-                fg = (int64_t)gj * (ni + 1) + gi;
-                Sb = a.SI + 2 * B.fi_off;
-                db = a.dI + 2 * B.fi_off;
-                nf = nfi_g;
-            } else {
-                const int k2 = k - G::NFI;
-                const int fi = k2 % TI, fj = k2 / TI;
-                const int gi = tl.i0 + fi, gj = tl.j0 + fj;
-                ok = gi < ni && gj <= nj;
-                e0 = fj * G::WE + fi + 2;
-                es = G::WE;
-                nB = fj * (TI + 1) + fi;            // node (i, j): edge end
-                nA = nB + 1;                        // node (i+1, j): edge start
-                fg = (int64_t)gj * ni + gi;
-                Sb = a.SJ + 2 * B.fj_off;
-                db = a.dJ + 2 * B.fj_off;
-                nf = nfj_g;
-            }
-            if (!ok) continue;
-            W4<T> m2, m1, p0, p1;
-            const int ex[4] = {e0, e0 + es, e0 + 2 * es, e0 + 3 * es};
-            m2 = W4<T>{P[ex[0]], P[G::EXT + ex[0]], P[2 * G::EXT + ex[0]], P[3 * G::EXT + ex[0]]};
-            m1 = W4<T>{P[ex[1]], P[G::EXT + ex[1]], P[2 * G::EXT + ex[1]], P[3 * G::EXT + ex[1]]};
-            p0 = W4<T>{P[ex[2]], P[G::EXT + ex[2]], P[2 * G::EXT + ex[2]], P[3 * G::EXT + ex[2]]};
-            p1 = W4<T>{P[ex[3]], P[G::EXT + ex[3]], P[2 * G::EXT + ex[3]], P[3 * G::EXT + ex[3]]};
-            W4<T> L, R;
-            muscl(m2, m1, p0, p1, a.eps, L, R);
-            const T sx = Sb[fg], sy = Sb[nf + fg];
-            const T dx = db[fg], dy = db[nf + fg];
-            T fl[4];
-            roe_flux_pert(L, R, f, sx, sy, g, a.delta, fl);
-            const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + ex[1]]};
-            const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + ex[2]]};
-            const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
-            const UVT<T> nb{Nd[nB], Nd[G::NOD + nB], Nd[2 * G::NOD + nB]};
-            T fv[3];
-            viscous_flux(uL, uR, na, nb, sx, sy, dx, dy, a.mu, a.kappa, fv, f.u, f.v);
-            T *F = (k < G::NFI) ? FIs + k : FJs + (k - G::NFI);
-            const int st = (k < G::NFI) ? G::NFI : G::NFJ;
-            F[0] = fl[0];
-            F[st] = fl[1] - fv[0];
-            F[2 * st] = fl[2] - fv[1];
-            F[3 * st] = fl[3] - fv[2];
-        }
+        // C3a: i-face fluxes, each face once
+        for (int k = tid; k < G::NFI; k += kThreads) face_flux<T, TI, TJ, true>(a, B, tl, k, P, Nd, F, f);
+        __syncthreads();
+        T rs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            rs[v] = valid ? F[v * G::NFMAX + iw + 1] - F[v * G::NFMAX + iw] : T(0);
+        __syncthreads();
+        // C3b: j-face fluxes
+        for (int k = tid; k < G::NFJ; k += kThreads) face_flux<T, TI, TJ, false>(a, B, tl, k, P, Nd, F, f);
         __syncthreads();
         // C4: cell residual and update
         if (valid) {
-            const int iw = tj * (TI + 1) + ti, js = tj * TI + ti;
-            T rs[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const T r = (FIs[v * G::NFI + iw + 1] - FIs[v * G::NFI + iw]) +
-                            (FJs[v * G::NFJ + js + TI] - FJs[v * G::NFJ + js]);
-                rs[v] = r + vol * (dq[0][v] + a.dqinf[4 * (B.snap_off + n) + v]);
+                T dqv;
+                if constexpr (MF) dqv = (NS > 1) ? DQs[(n * 4 + v) * kThreads + tid] : T(0);
+                else dqv = dq[0][v];
+                rs[v] += (F[v * G::NFMAX + js + TI] - F[v * G::NFMAX + js]) +
+                         vol * (dqv + a.dqinf[4 * (B.snap_off + n) + v]);
             }
             const int64_t o = B.q_off + (int64_t)n * 4 * plane + cidx;
             if constexpr (MODE == 0) {
@@ -327,7 +338,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
                 const T dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl,
                                          (T)B.omega_nh);
-                const double fac = a.alpha * (double)dt / (double)vol;
+                const double fac = a.alpha * (double)dt * ivol;
                 double nq[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) nq[v] = b0[v] - fac * (double)rs[v];
@@ -338,18 +349,21 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll
                     for (int v = 0; v < 4; ++v) a.qout[o + v * plane] = nq[v];
                 }
-                const double pn = (double)gm1 * (nq[3] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]) / nq[0]);
-                if (!(nq[0] > 0.0) || !(pn > 0.0) || !isfinite((double)(rs[0] + rs[1] + rs[2] + rs[3])))
+                // density > 0 and pressure > 0 (rho E rho > |rho u|^2 / 2), finite residual
+                const double pr = nq[3] * nq[0] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]);
+                if (!(nq[0] > 0.0) || !(pr > 0.0) || !isfinite((double)(rs[0] + rs[1] + rs[2] + rs[3])))
                     bad = 1;
             }
-            const double rr = (double)rs[0] / (double)vol;
+            const double rr = (double)rs[0] * ivol;
             nacc += rr * rr;
         }
-        // rotate the HB source so that dq[0] belongs to the next snapshot
+        if constexpr (!MF) {
+            // rotate the HB source so that dq[0] belongs to the next snapshot
 #pragma unroll
-        for (int m = 0; m + 1 < NS; ++m)
+            for (int m = 0; m + 1 < NS; ++m)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dq[m][v] = dq[m + 1][v];
+                for (int v = 0; v < 4; ++v) dq[m][v] = dq[m + 1][v];
+        }
     }
     if (bad) atomicOr(a.status, 1);
     if (a.norm) {
@@ -384,10 +398,13 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
 }
 
 template <class T, int TI, int TJ>
+size_t dq_bytes(int ns_max) {
+    return std::is_same<T, float>::value && ns_max > 1 ? sizeof(float) * (size_t)ns_max * 4 * kThreads : 0;
+}
+
+template <class T, int TI, int TJ>
 size_t smem_bytes(int ns_max) {
-    size_t s = sizeof(T) * (size_t)Geo<TI, TJ>::SCRATCH;
-    if (std::is_same<T, float>::value) s = std::max(s, sizeof(float) * (size_t)ns_max * 4 * kThreads);
-    return s;
+    return dq_bytes<T, TI, TJ>(ns_max) + sizeof(T) * (size_t)Geo<TI, TJ>::SCRATCH;
 }
 
 template <class T>
@@ -429,16 +446,30 @@ int ns_max(const hb_grid *g) {
 template <class T, int TI, int TJ, bool FIRST, int MODE>
 int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
     const size_t sm = smem_bytes<T, TI, TJ>(ns_max(g));
+    FusedArgs<T> b = a;
+    b.dq_bytes = (int)dq_bytes<T, TI, TJ>(ns_max(g));
     auto kern = k_fused<T, TI, TJ, FIRST, MODE>;
-    hipLaunchKernelGGL(kern, dim3(g->fused_grid), dim3(kThreads), sm, s, a);
+    // persistent grid: as many workgroups as can be resident at once
+    static int cached_occ[2][2] = {{0, 0}, {0, 0}};
+    static size_t cached_sm[2][2] = {{0, 0}, {0, 0}};
+    int &occ = cached_occ[FIRST][MODE == 2];
+    if (!occ || cached_sm[FIRST][MODE == 2] != sm) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kThreads, sm) != hipSuccess || nb < 1)
+            nb = 1;
+        occ = nb;
+        cached_sm[FIRST][MODE == 2] = sm;
+    }
+    const int grid = std::max(1, std::min(g->n_tiles, g->n_cu * occ));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), sm, s, b);
     return check_hip(hipGetLastError(), "fused launch");
 }
 
 template <class T, bool FIRST, int MODE>
 int launch_shape(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
     if (g->tile_ti == 64) return launch_t<T, 64, 4, FIRST, MODE>(g, a, s);
-    if (g->tile_ti == 16) return launch_t<T, 16, 16, FIRST, MODE>(g, a, s);
-    return launch_t<T, 32, 8, FIRST, MODE>(g, a, s);
+    if (g->tile_ti == 32) return launch_t<T, 32, 8, FIRST, MODE>(g, a, s);
+    return launch_t<T, 16, 16, FIRST, MODE>(g, a, s);
 }
 
 // one stage: k = stage index, input/output buffers chosen by the caller
@@ -463,8 +494,13 @@ int one_iteration(hb_grid *g, double *q, T *sa, T *sb, double *resnorm, hipStrea
     for (int k = 0; k < ns; ++k) {
         const bool last = k == ns - 1;
         T *out = (k % 2 == 0) ? sa : sb;
-        int rc = stage<T>(g, k == 0, last ? 2 : 1, q, in, last ? nullptr : out, last ? q : nullptr,
-                          g->solver.rk_alpha[k], k == 0, s);
+        hipEvent_t end;
+        int rc = prof_begin(g, s, &end);
+        if (rc) return rc;
+        rc = stage<T>(g, k == 0, last ? 2 : 1, q, in, last ? nullptr : out, last ? q : nullptr,
+                      g->solver.rk_alpha[k], k == 0, s);
+        if (rc) return rc;
+        rc = prof_end(end, s);
         if (rc) return rc;
         in = out;
     }
@@ -475,6 +511,10 @@ template <class T>
 int rk_graph(hb_grid *g, double *q, int n_iter, double *resnorm, T *sa, T *sb, hipStream_t s) {
     int rc = launch_reset_ctr(g->ctr_d, s);
     if (rc) return rc;
+    if (g->prof) {            // instrumented: stage by stage, no graph
+        for (int it = 0; it < n_iter && !rc; ++it) rc = one_iteration<T>(g, q, sa, sb, resnorm, s);
+        return rc;
+    }
     const int per = std::max(1, g->solver.graph_iters);
     if (!g->graph_exec || g->graph_q != q || g->graph_norm != resnorm || g->graph_iters != per) {
         if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
@@ -517,9 +557,9 @@ int fused_build_tiles(hb_grid *g) {
     if (g->solver.n_stages < 2)
         return fail(HB_ERR_UNSUPPORTED, "the fused path needs at least two Runge-Kutta stages");
     const char *env = getenv("HB_TILE");
-    int ti = 32;
+    int ti = 16;
     if (env) ti = atoi(env);
-    if (ti != 16 && ti != 32 && ti != 64) ti = 32;
+    if (ti != 16 && ti != 32 && ti != 64) ti = 16;
     g->tile_ti = ti;
     g->tile_tj = kThreads / ti;
     std::vector<Tile> tiles;
@@ -535,8 +575,7 @@ int fused_build_tiles(hb_grid *g) {
     hipDeviceProp_t prop;
     int rc = check_hip(hipGetDeviceProperties(&prop, g->device), "device properties");
     if (rc) return rc;
-    const int wg_per_cu = 4;
-    g->fused_grid = std::max(1, std::min(g->n_tiles, prop.multiProcessorCount * wg_per_cu));
+    g->n_cu = prop.multiProcessorCount;
     if (g->tiles_d) (void)hipFree(g->tiles_d);
     g->tiles_d = nullptr;
     rc = check_hip(hipMalloc((void **)&g->tiles_d, sizeof(Tile) * tiles.size()), "tiles alloc");

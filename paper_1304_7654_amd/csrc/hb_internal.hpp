@@ -111,11 +111,15 @@ struct hb_grid {
     hb::Tile *tiles_d = nullptr;
     int n_tiles = 0;
     int tile_ti = 32, tile_tj = 8;
-    int fused_grid = 0;
+    int n_cu = 0;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     double *graph_q = nullptr, *graph_norm = nullptr;
     int graph_iters = 0;
+    // stage instrumentation
+    int prof = 0;
+    std::vector<hipEvent_t> prof_ev;     // pairs (start, end), reused
+    size_t prof_used = 0;
     // adjoint scratch
     double *adj_d = nullptr;
     int64_t n_adj = 0;
@@ -149,6 +153,10 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
                             double *xybar, double *flowbar, hipStream_t s);
 int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
                           double *xybar, double *flowbar, hipStream_t s);
+
+// instrumentation (capi.cpp): event pair around one stage, or no-op
+int prof_begin(hb_grid *g, hipStream_t s, hipEvent_t *end);
+int prof_end(hipEvent_t end, hipStream_t s);
 
 // reduce.hip
 int launch_norm_finalize(hb_grid *g, const double *partials, int64_t n, double *out,

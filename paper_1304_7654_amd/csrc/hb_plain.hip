@@ -248,7 +248,12 @@ int plain_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStre
             // a one-stage scheme reads q as its stencil input, so it goes
             // through a scratch buffer
             double *out = (k == ns - 1 && ns > 1) ? q : ((k % 2 == 0) ? g->qa_d : g->qb_d);
+            hipEvent_t end;
+            rc = prof_begin(g, s, &end);
+            if (rc) return rc;
             rc = stage(g, in, q, out, 1, g->solver.rk_alpha[k], k == 0, s);
+            if (rc) return rc;
+            rc = prof_end(end, s);
             if (rc) return rc;
             in = out;
         }

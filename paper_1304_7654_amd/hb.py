@@ -23,7 +23,7 @@ HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
            "hb_forces_adjoint", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
-           "hb_last_error"]
+           "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
 
 class HBError(RuntimeError):
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.hb_set_xy.argtypes = [vp, vp, vp]
     L.hb_set_alpha0.argtypes = [vp, dp]
     L.hb_get_status.argtypes = [vp]
+    L.hb_profile_stages.argtypes = [vp, i32]
+    L.hb_stage_stats.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i64)]
     L.hb_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
         if f not in ("hb_state_size", "hb_forces_size", "hb_xy_size", "hb_last_error"):
@@ -214,3 +216,12 @@ class Grid:
 
     def status(self) -> int:
         return lib().hb_get_status(self.h)
+
+    def profile_stages(self, enable: bool):
+        _check(lib().hb_profile_stages(self.h, 1 if enable else 0))
+
+    def stage_stats(self):
+        """(summed milliseconds, number of stages) since the last call."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().hb_stage_stats(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
