@@ -183,7 +183,7 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
             std::snprintf(msg, sizeof msg, "block %d: ni, nj must be >= 4", b);
             return fail(HB_ERR_ARG, msg);
         }
-        if ((int64_t)B.ni * B.nj > (int64_t)1 << 28) {
+        if ((int64_t)B.ni * B.nj > (int64_t)1 << 24) {
             std::snprintf(msg, sizeof msg, "block %d: too many cells", b);
             return fail(HB_ERR_ARG, msg);
         }

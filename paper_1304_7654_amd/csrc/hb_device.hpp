@@ -20,6 +20,30 @@ struct W4 {
     T r, u, v, p;
 };
 
+// Values that are the same in every lane (block descriptors, tile table
+// entries) are read with ordinary loads; readfirstlane makes that known to
+// the compiler, which then keeps them, and addresses built from them, in
+// scalar registers.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Global load/store at (uniform base)[lane index] with a 32-bit byte offset,
+// so that the address is a scalar base plus one 32-bit VGPR (valid while
+// idx * sizeof(T) < 2^32: in-plane indices of one block).
+template <class T>
+__device__ __forceinline__ T ldg(const T *base, unsigned idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (unsigned)sizeof(T)) = v;
+}
+
 // Reciprocal and square root: exact IEEE operations in FP64; in FP32 the
 // hardware v_rcp_f32 / v_sqrt_f32 (1 ulp), well inside the FP32 budget
 // and much shorter than the correctly rounded sequences.
@@ -279,6 +303,22 @@ __device__ __forceinline__ W4<T> pert_prim(T dr, T dmx, T dmy, T de, T fu, T fv,
     w.v = (dmy - fv * dr) * ir;
     const T dk = w.u * (T(2) * fu + w.u) + w.v * (T(2) * fv + w.v);    // |u|^2 - |u_inf|^2
     w.p = gm1 * (de - T(0.5) * (dr * (fu * fu + fv * fv) + rho * dk));
+    return w;
+}
+
+// pert_prim plus the temperature perturbation T - 1, sharing 1/rho
+template <class T>
+__device__ __forceinline__ W4<T> pert_prim_t(T dr, T dmx, T dmy, T de, T fu, T fv, T gm1, T g,
+                                             T &tp) {
+    const T rho = T(1) + dr;
+    const T ir = frcp(rho);
+    W4<T> w;
+    w.r = dr;
+    w.u = (dmx - fu * dr) * ir;
+    w.v = (dmy - fv * dr) * ir;
+    const T dk = w.u * (T(2) * fu + w.u) + w.v * (T(2) * fv + w.v);
+    w.p = gm1 * (de - T(0.5) * (dr * (fu * fu + fv * fv) + rho * dk));
+    tp = (g * w.p - w.r) * ir;
     return w;
 }
 

@@ -101,41 +101,48 @@ struct Geo {
 // written to F[v * NFMAX + k].  IFACE: i-face k = fj*(TI+1) + fi between
 // cells fi-1 and fi of row fj; else j-face k = fj*TI + fi between rows fj-1
 // and fj of column fi.  Returns without writing for faces outside the block.
+// Uniform per-tile data used by the face loops.
+template <class T>
+struct TileU {
+    int ni, nj, i0, j0;
+    const T *SI, *dI, *SJ, *dJ;      // block's face metrics
+};
+
 template <class T, int TI, int TJ, bool IFACE>
-__device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const BlockDesc &B, const Tile &tl,
-                                          int k, const T *P, const T *Nd, T *F, const FS<T> &f) {
+__device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const TileU<T> &u, int k,
+                                          const T *P, const T *Nd, T *F, const FS<T> &f) {
     using G = Geo<TI, TJ>;
-    const int ni = B.ni, nj = B.nj;
-    int e0, es, nA, nB;
-    int64_t fg, nf;
+    const int ni = u.ni, nj = u.nj;
+    int e0, es, nA, nB, nf;
+    unsigned fg;
     const T *Sb, *db;
     if constexpr (IFACE) {
         const int fi = k % (TI + 1), fj = k / (TI + 1);
-        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        const int gi = u.i0 + fi, gj = u.j0 + fj;
         if (!(gi <= ni && gj < nj)) return;
         e0 = (fj + 2) * G::WE + fi;
         es = 1;
         nA = fj * (TI + 1) + fi;            // node (i, j): edge start
         nB = nA + (TI + 1);                 // node (i, j+1): edge end
-        fg = (int64_t)gj * (ni + 1) + gi;
-        nf = (int64_t)(ni + 1) * nj;
-        Sb = a.SI + 2 * B.fi_off;
-        db = a.dI + 2 * B.fi_off;
+        fg = (unsigned)(gj * (ni + 1) + gi);
+        nf = (ni + 1) * nj;
+        Sb = u.SI;
+        db = u.dI;
     } else {
         const int fi = k % TI, fj = k / TI;
-        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        const int gi = u.i0 + fi, gj = u.j0 + fj;
         if (!(gi < ni && gj <= nj)) return;
         e0 = fj * G::WE + fi + 2;
         es = G::WE;
         nB = fj * (TI + 1) + fi;            // node (i, j): edge end
         nA = nB + 1;                        // node (i+1, j): edge start
-        fg = (int64_t)gj * ni + gi;
-        nf = (int64_t)ni * (nj + 1);
-        Sb = a.SJ + 2 * B.fj_off;
-        db = a.dJ + 2 * B.fj_off;
+        fg = (unsigned)(gj * ni + gi);
+        nf = ni * (nj + 1);
+        Sb = u.SJ;
+        db = u.dJ;
     }
-    const T sx = Sb[fg], sy = Sb[nf + fg];
-    const T dx = db[fg], dy = db[nf + fg];
+    const T sx = ldg(Sb, fg), sy = ldg(Sb + nf, fg);
+    const T dx = ldg(db, fg), dy = ldg(db + nf, fg);
     const int x0 = e0, x1 = e0 + es, x2 = e0 + 2 * es, x3 = e0 + 3 * es;
     const W4<T> m2{P[x0], P[G::EXT + x0], P[2 * G::EXT + x0], P[3 * G::EXT + x0]};
     const W4<T> m1{P[x1], P[G::EXT + x1], P[2 * G::EXT + x1], P[3 * G::EXT + x1]};
@@ -157,6 +164,13 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const BlockDesc
     F[3 * G::NFMAX + k] = fl[3] - fv[2];
 }
 
+// Scalar copy of the block descriptor fields the tile body uses.
+struct BlockU {
+    int ni, nj, snap_off, d_off;
+    int64_t q_off, cell_off, fi_off, fj_off;
+    double omega_nh;
+};
+
 template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
 __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem) {
     using G = Geo<TI, TJ>;
@@ -165,14 +179,30 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // (DQs, [N_s][4][cells]) for the whole snapshot loop; FP64: FMA, held in
     // registers.
     constexpr bool MF = std::is_same<T, float>::value;
-    const BlockDesc &B = a.blks[tl.blk];
+    const BlockDesc &Bg = a.blks[tl.blk];
+    BlockU B;
+    B.ni = uni(Bg.ni);
+    B.nj = uni(Bg.nj);
+    B.snap_off = uni(Bg.snap_off);
+    B.d_off = uni(Bg.d_off);
+    B.q_off = uni(Bg.q_off);
+    B.cell_off = uni(Bg.cell_off);
+    B.fi_off = uni(Bg.fi_off);
+    B.fj_off = uni(Bg.fj_off);
+    B.omega_nh = Bg.omega_nh;
     const int ni = B.ni, nj = B.nj;
+    const TileU<T> tu{ni, nj, tl.i0, tl.j0, a.SI + 2 * B.fi_off, a.dI + 2 * B.fi_off,
+                      a.SJ + 2 * B.fj_off, a.dJ + 2 * B.fj_off};
     const int tid = threadIdx.x;
     const int ti = tid % TI, tj = tid / TI;
     const int i = tl.i0 + ti, j = tl.j0 + tj;
     const bool valid = i < ni && j < nj;
-    const int64_t plane = (int64_t)ni * nj;
-    const int64_t cidx = (int64_t)j * ni + i;
+    // per-block offsets fit in 32 bits (ni nj <= 2^24, N_s <= 9).  Loads are
+    // written as (uniform base pointer)[unsigned lane offset] so that the
+    // address stays a scalar base plus one 32-bit VGPR offset.
+    const int plane = ni * nj;
+    const unsigned cidx = valid ? (unsigned)(j * ni + i) : 0u;
+    const bool inner = tl.i0 >= 2 && tl.i0 + TI + 2 <= ni && tl.j0 >= 2 && tl.j0 + TJ + 2 <= nj;
     const T g = a.gamma, gm1 = a.gamma - T(1);
     T *DQs = reinterpret_cast<T *>(smem);
     T *P = reinterpret_cast<T *>(smem + (MF ? a.dq_bytes : 0));   // [5][EXT]: rho', u', v', p', T'
@@ -180,13 +210,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     T *F = Nd + 3 * G::NOD;                                        // [4][NFMAX]
 
     // own-cell state of snapshot m, variable v (perturbation form)
+    const double *q0b = a.q0 + B.q_off;
     auto load_own = [&](int m, int v) -> T {
         if (!valid) return T(0);
-        const int64_t idx = B.q_off + ((int64_t)m * 4 + v) * plane + cidx;
         if constexpr (FIRST)
-            return (T)(a.q0[idx] - a.ffq[4 * (B.snap_off + m) + v]);
+            return (T)(ldg(q0b + (m * 4 + v) * plane, cidx) - a.ffq[4 * (B.snap_off + m) + v]);
         else
-            return a.sin[idx];
+            return ldg(a.sin + B.q_off + (m * 4 + v) * plane, cidx);
     };
 
     // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
@@ -251,14 +281,15 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
     double ivol = 1.0;
     if (valid) {
-        const int64_t nfi = (int64_t)(ni + 1) * nj, nfj = (int64_t)ni * (nj + 1);
-        const int64_t fi0 = (int64_t)j * (ni + 1) + i;
-        const T *SIb = a.SI + 2 * B.fi_off, *SJb = a.SJ + 2 * B.fj_off;
-        sxi = T(0.5) * (SIb[fi0] + SIb[fi0 + 1]);
-        syi = T(0.5) * (SIb[nfi + fi0] + SIb[nfi + fi0 + 1]);
-        sxj = T(0.5) * (SJb[cidx] + SJb[cidx + ni]);
-        syj = T(0.5) * (SJb[nfj + cidx] + SJb[nfj + cidx + ni]);
-        vol = a.V[B.cell_off + cidx];
+        const int nfi = (ni + 1) * nj, nfj = ni * (nj + 1);
+        const unsigned fi0 = (unsigned)(j * (ni + 1) + i);
+        const T *SIx = a.SI + 2 * B.fi_off, *SIy = SIx + nfi;
+        const T *SJx = a.SJ + 2 * B.fj_off, *SJy = SJx + nfj;
+        sxi = T(0.5) * (ldg(SIx, fi0) + ldg(SIx + 1, fi0));
+        syi = T(0.5) * (ldg(SIy, fi0) + ldg(SIy + 1, fi0));
+        sxj = T(0.5) * (ldg(SJx, cidx) + ldg(SJx + ni, cidx));
+        syj = T(0.5) * (ldg(SJy, cidx) + ldg(SJy + ni, cidx));
+        vol = ldg(a.V + B.cell_off, cidx);
         ivol = 1.0 / (double)vol;
     }
 
@@ -275,7 +306,38 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         f.gg = g / gm1;
         f.h = f.gg * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
         // C1: ghost-extended tile
-        {
+        if (inner) {
+            // the whole halo lies inside the block: plain loads, 32-bit offsets
+            // from the snapshot's base address
+            const int sn = n * 4 * plane;
+            const double *qn = a.q0 + B.q_off + sn;
+            const T *tn = a.sin + (FIRST ? 0 : B.q_off + sn);
+            const double *fq = a.ffq + 4 * (B.snap_off + n);
+            // tile origin (i0-2, j0-2) is inside the block here
+            const unsigned org = (unsigned)((tl.j0 - 2) * ni + tl.i0 - 2);
+            for (int e = tid; e < G::EXT; e += kThreads) {
+                const unsigned off = org + (unsigned)((e / G::WE) * ni + e % G::WE);
+                T d0, d1, d2, d3;
+                if constexpr (FIRST) {
+                    d0 = (T)(ldg(qn, off) - fq[0]);
+                    d1 = (T)(ldg(qn + plane, off) - fq[1]);
+                    d2 = (T)(ldg(qn + 2 * plane, off) - fq[2]);
+                    d3 = (T)(ldg(qn + 3 * plane, off) - fq[3]);
+                } else {
+                    d0 = ldg(tn, off);
+                    d1 = ldg(tn + plane, off);
+                    d2 = ldg(tn + 2 * plane, off);
+                    d3 = ldg(tn + 3 * plane, off);
+                }
+                T tp;
+                const W4<T> w = pert_prim_t<T>(d0, d1, d2, d3, f.u, f.v, gm1, g, tp);
+                P[e] = w.r;
+                P[G::EXT + e] = w.u;
+                P[2 * G::EXT + e] = w.v;
+                P[3 * G::EXT + e] = w.p;
+                P[4 * G::EXT + e] = tp;
+            }
+        } else {
             CellPert<T, FIRST> cell{a.blks, a.q0, a.sin, a.ffq, n, gm1, f.u, f.v};
             ZeroPert<T> ff;
             MirrorPert<T> mir{f.u, f.v};
@@ -304,7 +366,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         }
         __syncthreads();
         // C3a: i-face fluxes, each face once
-        for (int k = tid; k < G::NFI; k += kThreads) face_flux<T, TI, TJ, true>(a, B, tl, k, P, Nd, F, f);
+        for (int k = tid; k < G::NFI; k += kThreads) face_flux<T, TI, TJ, true>(a, tu, k, P, Nd, F, f);
         __syncthreads();
         T rs[4];
 #pragma unroll
@@ -312,7 +374,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             rs[v] = valid ? F[v * G::NFMAX + iw + 1] - F[v * G::NFMAX + iw] : T(0);
         __syncthreads();
         // C3b: j-face fluxes
-        for (int k = tid; k < G::NFJ; k += kThreads) face_flux<T, TI, TJ, false>(a, B, tl, k, P, Nd, F, f);
+        for (int k = tid; k < G::NFJ; k += kThreads) face_flux<T, TI, TJ, false>(a, tu, k, P, Nd, F, f);
         __syncthreads();
         // C4: cell residual and update
         if (valid) {
@@ -324,15 +386,16 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 rs[v] += (F[v * G::NFMAX + js + TI] - F[v * G::NFMAX + js]) +
                          vol * (dqv + a.dqinf[4 * (B.snap_off + n) + v]);
             }
-            const int64_t o = B.q_off + (int64_t)n * 4 * plane + cidx;
+            const int so = n * 4 * plane;     // snapshot offset (uniform)
             if constexpr (MODE == 0) {
+                double *ob = a.qout + B.q_off + so;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) a.qout[o + v * plane] = (double)rs[v];
+                for (int v = 0; v < 4; ++v) stg(ob + v * plane, cidx, (double)rs[v]);
             } else {
                 const double *fq = a.ffq + 4 * (B.snap_off + n);
                 double b0[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) b0[v] = a.q0[o + v * plane];
+                for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
                 const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
                                               (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
                 const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
@@ -343,11 +406,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll
                 for (int v = 0; v < 4; ++v) nq[v] = b0[v] - fac * (double)rs[v];
                 if constexpr (MODE == 1) {
+                    T *sb = a.sout + B.q_off + so;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) a.sout[o + v * plane] = (T)(nq[v] - fq[v]);
+                    for (int v = 0; v < 4; ++v) stg(sb + v * plane, cidx, (T)(nq[v] - fq[v]));
                 } else {
+                    double *ob = a.qout + B.q_off + so;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) a.qout[o + v * plane] = nq[v];
+                    for (int v = 0; v < 4; ++v) stg(ob + v * plane, cidx, nq[v]);
                 }
                 // density > 0 and pressure > 0 (rho E rho > |rho u|^2 / 2), finite residual
                 const double pr = nq[3] * nq[0] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]);
@@ -384,8 +449,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 template <class T, int TI, int TJ, bool FIRST, int MODE>
 __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-        const Tile tl = a.tiles[t];
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its
+    // own L2).  Renumber them so that the workgroups of one XCD take
+    // consecutive tiles of the list at the same time: neighbouring tiles,
+    // whose halos overlap, then share an L2.  (Only when the grid is a
+    // multiple of 8, where the renumbering is a permutation.)
+    const int G = gridDim.x;
+    int v0 = blockIdx.x;
+    if (G % 8 == 0) v0 = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+    for (int t = v0; t < a.n_tiles; t += G) {
+        const Tile tg = a.tiles[t];
+        const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns)};
         switch (tl.ns) {
             case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem); break;
             case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem); break;
