@@ -1,7 +1,8 @@
 // Fused, batched residual / Runge-Kutta stage kernel.
 //
 // One persistent launch per stage covers every block of the grid: the
-// blocks are cut into TI x TJ tiles (one thread per cell, 256 threads),
+// blocks are cut into tiles of 16 x 15 cells (256 threads, one per cell of a
+// 16 x 16 thread grid whose last row only helps),
 // listed in a flat tile table; each workgroup walks the table with a fixed
 // stride.  Per tile:
 //   A. every thread loads its cell's state for all N_s snapshots (as the
@@ -86,13 +87,18 @@ struct ZeroPert {
     __device__ W4<T> operator()(int) const { return W4<T>{T(0), T(0), T(0), T(0)}; }
 };
 
+// Threads form a TI x TJ grid; the tile's output cells are TI x (TJ - 1):
+// the last thread row only helps with loads, nodes and faces.  With
+// TI = 16, TJ = 16 a tile has 255 i-faces and 256 j-faces, so each face
+// pass is one round over the 256 threads (no wave gets a second round).
 template <int TI, int TJ>
 struct Geo {
+    static constexpr int OJ = TJ - 1;                  // output rows
     static constexpr int WE = TI + 4;                  // ext row length
-    static constexpr int EXT = (TI + 4) * (TJ + 4);
-    static constexpr int NOD = (TI + 1) * (TJ + 1);
-    static constexpr int NFI = (TI + 1) * TJ;
-    static constexpr int NFJ = TI * (TJ + 1);
+    static constexpr int EXT = (TI + 4) * (OJ + 4);
+    static constexpr int NOD = (TI + 1) * (OJ + 1);
+    static constexpr int NFI = (TI + 1) * OJ;
+    static constexpr int NFJ = TI * (OJ + 1);
     static constexpr int NFMAX = NFI > NFJ ? NFI : NFJ;
     static constexpr int SCRATCH = 5 * EXT + 3 * NOD + 4 * NFMAX;   // elements
 };
@@ -171,6 +177,9 @@ struct BlockU {
     double omega_nh;
 };
 
+// NS > 0: snapshot count fixed at compile time (FP64 tiles, whose HB source
+// lives in registers); NS = 0: taken from the tile at run time (FP32 tiles:
+// one body serves every snapshot count).
 template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
 __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem) {
     using G = Geo<TI, TJ>;
@@ -179,6 +188,8 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // (DQs, [N_s][4][cells]) for the whole snapshot loop; FP64: FMA, held in
     // registers.
     constexpr bool MF = std::is_same<T, float>::value;
+    static_assert(MF || NS > 0, "FP64 tiles need a compile-time snapshot count");
+    const int ns = NS > 0 ? NS : tl.ns;
     const BlockDesc &Bg = a.blks[tl.blk];
     BlockU B;
     B.ni = uni(Bg.ni);
@@ -196,13 +207,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     const int tid = threadIdx.x;
     const int ti = tid % TI, tj = tid / TI;
     const int i = tl.i0 + ti, j = tl.j0 + tj;
-    const bool valid = i < ni && j < nj;
+    const bool valid = tj < G::OJ && i < ni && j < nj;
     // per-block offsets fit in 32 bits (ni nj <= 2^24, N_s <= 9).  Loads are
     // written as (uniform base pointer)[unsigned lane offset] so that the
     // address stays a scalar base plus one 32-bit VGPR offset.
     const int plane = ni * nj;
     const unsigned cidx = valid ? (unsigned)(j * ni + i) : 0u;
-    const bool inner = tl.i0 >= 2 && tl.i0 + TI + 2 <= ni && tl.j0 >= 2 && tl.j0 + TJ + 2 <= nj;
+    const bool inner = tl.i0 >= 2 && tl.i0 + TI + 2 <= ni && tl.j0 >= 2 && tl.j0 + G::OJ + 2 <= nj;
     const T g = a.gamma, gm1 = a.gamma - T(1);
     T *DQs = reinterpret_cast<T *>(smem);
     T *P = reinterpret_cast<T *>(smem + (MF ? a.dq_bytes : 0));   // [5][EXT]: rho', u', v', p', T'
@@ -220,11 +231,11 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     };
 
     // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
-    T dq[MF ? 1 : NS][4];
+    T dq[MF ? 1 : (NS > 0 ? NS : 1)][4];
     if constexpr (MF) {
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int m = 0; m < NS; ++m)
+        if (ns > 1) {
+#pragma unroll 3
+            for (int m = 0; m < ns; ++m)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kThreads + tid] = load_own(m, v);
             __syncthreads();
@@ -232,26 +243,28 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4)
             const int lane = tid & 63, wave = tid >> 6;
             const int row = lane & 15, kq = lane >> 4;
-            constexpr int KS = (NS + 3) / 4;
-            float bD[KS];
+            const int KS = (ns + 3) / 4;            // <= 3
+            float bD[3];
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
+            for (int s = 0; s < 3; ++s) {
                 const int m = 4 * s + kq;
-                bD[s] = (row < NS && m < NS) ? a.D[B.d_off + row * kNsPad + m] : 0.0f;
+                bD[s] = (row < ns && m < ns) ? a.D[B.d_off + row * kNsPad + m] : 0.0f;
             }
             for (int grp = wave; grp < 4 * (kThreads / 16); grp += kThreads / 64) {
                 const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
                 floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const int m = 4 * s + kq;
-                    const float av = (m < NS) ? DQs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
+                for (int s = 0; s < 3; ++s) {
+                    if (s < KS) {
+                        const int m = 4 * s + kq;
+                        const float av = (m < ns) ? DQs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
+                    }
                 }
                 // lane holds (cell cb*16 + 4 kq + r, n = row); written in
                 // place: only this wave reads or writes group (v, cb), and
                 // every read feeds the MFMAs before the results exist
-                if (row < NS) {
+                if (row < ns) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         DQs[(row * 4 + v) * kThreads + cb * 16 + 4 * kq + r] = acc[r];
@@ -297,7 +310,42 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     double nacc = 0.0;
     int bad = 0;
     const int iw = tj * (TI + 1) + ti, js = tj * TI + ti;
-    for (int n = 0; n < NS; ++n) {
+    // Interior tiles: the ext-tile values of the next snapshot are loaded
+    // into registers while the current one is processed (each thread owns
+    // ext cells tid and tid + 256).
+    static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
+    using LT = std::conditional_t<FIRST, double, T>;
+    LT pf[2][4];
+    const int e1 = tid, e2 = tid + kThreads;
+    const bool has2 = e2 < G::EXT;
+    unsigned off1 = 0, off2 = 0;
+    if (inner) {
+        const unsigned org = (unsigned)((tl.j0 - 2) * ni + tl.i0 - 2);
+        off1 = org + (unsigned)((e1 / G::WE) * ni + e1 % G::WE);
+        off2 = has2 ? org + (unsigned)((e2 / G::WE) * ni + e2 % G::WE) : org;
+    }
+    auto prefetch = [&](int m) {
+        const LT *base;
+        if constexpr (FIRST) base = a.q0 + B.q_off + m * 4 * plane;
+        else base = a.sin + B.q_off + m * 4 * plane;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pf[0][v] = ldg(base + v * plane, off1);
+        if (has2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pf[1][v] = ldg(base + v * plane, off2);
+        }
+    };
+    if (inner) prefetch(0);
+    for (int n = 0; n < ns; ++n) {
+        // base state of this snapshot for the update (loaded early)
+        const int so = n * 4 * plane;     // snapshot offset (uniform)
+        double b0[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (MODE != 0) {
+            if (valid) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
+            }
+        }
         const T *fw = a.ffw + 4 * (B.snap_off + n);
         FS<T> f;
         f.u = fw[1];
@@ -307,36 +355,28 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         f.h = f.gg * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
         // C1: ghost-extended tile
         if (inner) {
-            // the whole halo lies inside the block: plain loads, 32-bit offsets
-            // from the snapshot's base address
-            const int sn = n * 4 * plane;
-            const double *qn = a.q0 + B.q_off + sn;
-            const T *tn = a.sin + (FIRST ? 0 : B.q_off + sn);
+            // the whole halo lies inside the block: values come from the
+            // prefetch registers; then the next snapshot's loads are issued
             const double *fq = a.ffq + 4 * (B.snap_off + n);
-            // tile origin (i0-2, j0-2) is inside the block here
-            const unsigned org = (unsigned)((tl.j0 - 2) * ni + tl.i0 - 2);
-            for (int e = tid; e < G::EXT; e += kThreads) {
-                const unsigned off = org + (unsigned)((e / G::WE) * ni + e % G::WE);
-                T d0, d1, d2, d3;
-                if constexpr (FIRST) {
-                    d0 = (T)(ldg(qn, off) - fq[0]);
-                    d1 = (T)(ldg(qn + plane, off) - fq[1]);
-                    d2 = (T)(ldg(qn + 2 * plane, off) - fq[2]);
-                    d3 = (T)(ldg(qn + 3 * plane, off) - fq[3]);
-                } else {
-                    d0 = ldg(tn, off);
-                    d1 = ldg(tn + plane, off);
-                    d2 = ldg(tn + 2 * plane, off);
-                    d3 = ldg(tn + 3 * plane, off);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int e = c ? e2 : e1;
+                if (c && !has2) break;
+                T d[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if constexpr (FIRST) d[v] = (T)(pf[c][v] - fq[v]);
+                    else d[v] = pf[c][v];
                 }
                 T tp;
-                const W4<T> w = pert_prim_t<T>(d0, d1, d2, d3, f.u, f.v, gm1, g, tp);
+                const W4<T> w = pert_prim_t<T>(d[0], d[1], d[2], d[3], f.u, f.v, gm1, g, tp);
                 P[e] = w.r;
                 P[G::EXT + e] = w.u;
                 P[2 * G::EXT + e] = w.v;
                 P[3 * G::EXT + e] = w.p;
                 P[4 * G::EXT + e] = tp;
             }
+            if (n + 1 < ns) prefetch(n + 1);
         } else {
             CellPert<T, FIRST> cell{a.blks, a.q0, a.sin, a.ffq, n, gm1, f.u, f.v};
             ZeroPert<T> ff;
@@ -381,21 +421,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 T dqv;
-                if constexpr (MF) dqv = (NS > 1) ? DQs[(n * 4 + v) * kThreads + tid] : T(0);
+                if constexpr (MF) dqv = (ns > 1) ? DQs[(n * 4 + v) * kThreads + tid] : T(0);
                 else dqv = dq[0][v];
                 rs[v] += (F[v * G::NFMAX + js + TI] - F[v * G::NFMAX + js]) +
                          vol * (dqv + a.dqinf[4 * (B.snap_off + n) + v]);
             }
-            const int so = n * 4 * plane;     // snapshot offset (uniform)
             if constexpr (MODE == 0) {
                 double *ob = a.qout + B.q_off + so;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) stg(ob + v * plane, cidx, (double)rs[v]);
             } else {
                 const double *fq = a.ffq + 4 * (B.snap_off + n);
-                double b0[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
                 const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
                                               (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
                 const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
@@ -460,12 +496,16 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     for (int t = v0; t < a.n_tiles; t += G) {
         const Tile tg = a.tiles[t];
         const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns)};
-        switch (tl.ns) {
-            case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem); break;
-            case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem); break;
-            case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem); break;
-            case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem); break;
-            default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem); break;
+        if constexpr (std::is_same<T, float>::value) {
+            tile_body<T, TI, TJ, FIRST, MODE, 0>(a, tl, t, smem);
+        } else {
+            switch (tl.ns) {
+                case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem); break;
+                case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem); break;
+                case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem); break;
+                case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem); break;
+                default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem); break;
+            }
         }
         __syncthreads();
     }
@@ -541,7 +581,6 @@ int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
 
 template <class T, bool FIRST, int MODE>
 int launch_shape(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
-    if (g->tile_ti == 64) return launch_t<T, 64, 4, FIRST, MODE>(g, a, s);
     if (g->tile_ti == 32) return launch_t<T, 32, 8, FIRST, MODE>(g, a, s);
     return launch_t<T, 16, 16, FIRST, MODE>(g, a, s);
 }
@@ -633,9 +672,9 @@ int fused_build_tiles(hb_grid *g) {
     const char *env = getenv("HB_TILE");
     int ti = 16;
     if (env) ti = atoi(env);
-    if (ti != 16 && ti != 32 && ti != 64) ti = 16;
+    if (ti != 16 && ti != 32) ti = 16;
     g->tile_ti = ti;
-    g->tile_tj = kThreads / ti;
+    g->tile_tj = kThreads / ti - 1;        // output rows per tile
     std::vector<Tile> tiles;
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
