@@ -725,3 +725,28 @@ def harmonics(c: torch.Tensor) -> torch.Tensor:
         out.append(2.0 / ns * (c * torch.cos(2 * math.pi * k * n / ns)).sum())
         out.append(2.0 / ns * (c * torch.sin(2 * math.pi * k * n / ns)).sum())
     return torch.stack(out)
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode (for checking the adjoint)
+# ---------------------------------------------------------------------------
+def residual_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, rbar: torch.Tensor):
+    """Products of the transposed Jacobians of R* (all blocks) with rbar, by
+    automatic differentiation of this module's residual: returns
+    (qbar, [xybar per block], alpha0bar).  Pinned against central finite
+    differences in the tests."""
+    qv = q.detach().clone().requires_grad_(True)
+    xys = [b.xy.detach().clone().requires_grad_(True) for b in blocks]
+    a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
+    parts = [residual(b, qb, flow, solver, alpha0=a0, xy=xy)
+             for b, qb, xy in zip(blocks, split(blocks, qv), xys)]
+    (join(parts) * rbar).sum().backward()
+    return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()
+
+
+def residual_with(blocks, q, flow, solver, xys=None, alpha0=None):
+    """R* of all blocks with node coordinates and/or alpha0 overridden."""
+    xys = [b.xy for b in blocks] if xys is None else xys
+    a0 = None if alpha0 is None else torch.as_tensor(alpha0, dtype=DT)
+    return join([residual(b, qb, flow, solver, alpha0=a0, xy=xy)
+                 for b, qb, xy in zip(blocks, split(blocks, q), xys)])

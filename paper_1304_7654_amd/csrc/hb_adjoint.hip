@@ -1,13 +1,699 @@
-// Reverse-mode residual and force kernels (placeholder until written).
+// Reverse mode of the HB residual (FP64): products with the transposed
+// Jacobians of R* with respect to the state, the node coordinates and the
+// mean incidence.  Nothing from the forward evaluation is stored: each face
+// recomputes its reconstruction, Roe and viscous fluxes from the state.
+//
+// Steps (one block per launch, all snapshots):
+//  1. ghost-extended primitives of q (the plain path's ghost kernel);
+//  2. face kernels: the adjoint of each face flux is rbar(L) - rbar(R); the
+//     reverse sweep through Roe, MUSCL and the viscous flux gives adjoint
+//     terms for the face's four line cells, its two edge nodes, its normal S
+//     and its centre offset d, stored per face (kAF doubles);
+//  3. node gather: each node sums the (u, v, T) adjoints of the faces
+//     that use it;
+//  4. cell gather over the ghost-extended index range: each cell sums the
+//     terms of the faces whose stencils contain it and a quarter of each of
+//     its four nodes (converted to primitives);
+//  5. fold: each interior cell adds the adjoints of the ghost cells that
+//     copy it (periodic, wake cut, wall mirror, block cut; a host-built
+//     inverse of the ghost rules, so no atomics), converts to conserved
+//     variables and adds the HB source term V D^T rbar;
+//  6. far-field ghosts carry the incidence: their adjoints reduce to the
+//     alpha0 derivative (one partial per block, summed in block order);
+//  7. node coordinates: the metric adjoints (S, d per face, V per cell) are
+//     chained to the nodes with FP64 atomic adds (summation order, hence the
+//     last bits of xybar, may vary from run to run).
 #include "hb_device.hpp"
 
+#include <vector>
+
 namespace hb {
-int launch_residual_adjoint(hb_grid *, const double *, const double *, double *, double *,
-                            double *, hipStream_t) {
-    return fail(HB_ERR_UNSUPPORTED, "adjoint not built");
+
+int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_t s);
+
+namespace {
+
+constexpr int kBS = 256;
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
+
+__device__ inline W4<double> ldw(const double *e, int64_t plane, int64_t idx) {
+    return W4<double>{e[idx], e[plane + idx], e[2 * plane + idx], e[3 * plane + idx]};
 }
-int launch_forces_adjoint(hb_grid *, const double *, const double *, double *, double *,
-                          double *, hipStream_t) {
+
+// r_bar of interior cell (i, j) of snapshot n, all 4 variables (0 outside)
+__device__ inline void rbar_cell(const BlockDesc &B, const double *rbar, int n, int i, int j,
+                                 double out[4]) {
+    if (i < 0 || i >= B.ni || j < 0 || j >= B.nj) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const double *r = rbar + B.q_off + (int64_t)n * 4 * plane + (int64_t)j * B.ni + i;
+    out[0] = r[0];
+    out[1] = r[plane];
+    out[2] = r[2 * plane];
+    out[3] = r[3 * plane];
+}
+
+// Reverse sweep of one face.  Line cells m2, m1, p0, p1 (ext indices x0..x3),
+// node values at the edge start P and end Q.  Fb: adjoint of the net face
+// flux.  Writes the kAF adjoint terms to out[k * nf] (k = component).
+__device__ inline void face_rev(const double *e, int64_t plane, const int x[4], const UVT<double> &P,
+                                const UVT<double> &Q, double sx, double sy, double dx, double dy,
+                                const double Fb[4], const Consts &c, double *out, int64_t nf) {
+    const double g = c.gamma;
+    const W4<double> m2 = ldw(e, plane, x[0]), m1 = ldw(e, plane, x[1]);
+    const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
+    W4<double> L, R;
+    muscl(m2, m1, p0, p1, c.eps, L, R);
+    W4<double> Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
+    double sxb = 0.0, syb = 0.0, dxb = 0.0, dyb = 0.0;
+    roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb);
+    // net flux = Roe - viscous: the viscous part sees -Fb (its mass term is 0)
+    const double fvb[3] = {-Fb[1], -Fb[2], -Fb[3]};
+    const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
+    UVT<double> uLb{0, 0, 0}, uRb{0, 0, 0}, Pb{0, 0, 0}, Qb{0, 0, 0};
+    viscous_flux_rev(uL, uR, P, Q, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
+                     dxb, dyb);
+    double cb[4][4] = {{0}};
+    const double Lv[4] = {Lb.r, Lb.u, Lb.v, Lb.p}, Rv[4] = {Rb.r, Rb.u, Rb.v, Rb.p};
+    const double M2[4] = {m2.r, m2.u, m2.v, m2.p}, M1[4] = {m1.r, m1.u, m1.v, m1.p};
+    const double P0[4] = {p0.r, p0.u, p0.v, p0.p}, P1[4] = {p1.r, p1.u, p1.v, p1.p};
+    for (int v = 0; v < 4; ++v)
+        muscl_rev1(M2[v], M1[v], P0[v], P1[v], c.eps, Lv[v], Rv[v], cb[0][v], cb[1][v], cb[2][v],
+                   cb[3][v]);
+    W4<double> w1{cb[1][0], cb[1][1], cb[1][2], cb[1][3]};
+    uvt_rev(m1, uLb, g, w1);
+    W4<double> w2{cb[2][0], cb[2][1], cb[2][2], cb[2][3]};
+    uvt_rev(p0, uRb, g, w2);
+    cb[1][0] = w1.r; cb[1][1] = w1.u; cb[1][2] = w1.v; cb[1][3] = w1.p;
+    cb[2][0] = w2.r; cb[2][1] = w2.u; cb[2][2] = w2.v; cb[2][3] = w2.p;
+    for (int r = 0; r < 4; ++r)
+        for (int v = 0; v < 4; ++v) out[(r * 4 + v) * nf] = cb[r][v];
+    out[16 * nf] = Pb.u;
+    out[17 * nf] = Pb.v;
+    out[18 * nf] = Pb.t;
+    out[19 * nf] = Qb.u;
+    out[20 * nf] = Qb.v;
+    out[21 * nf] = Qb.t;
+    out[22 * nf] = sxb;
+    out[23 * nf] = syb;
+    out[24 * nf] = dxb;
+    out[25 * nf] = dyb;
+}
+
+// Node slots: i-faces store node (i, j) [edge start] in slot 0 (components
+// 16..18) and node (i, j+1) [end] in slot 1 (19..21); j-faces store node
+// (i+1, j) [start] in slot 0 and node (i, j) [end] in slot 1.
+__global__ void k_adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
+                             const double *dI, const double *rbar, Consts c, double *AF) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nf = (int64_t)W * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * B.ns) return;
+    const int n = (int)(t / nf);
+    const int64_t f = t % nf;
+    const int i = (int)(f % W), j = (int)(f / W);
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    const int64_t row = (int64_t)(j + 2) * we;
+    const int x[4] = {(int)(row + i), (int)(row + i + 1), (int)(row + i + 2), (int)(row + i + 3)};
+    const double g = c.gamma;
+    const int64_t lo = (int64_t)(j + 1) * we, hi = (int64_t)(j + 3) * we;
+    const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
+    const UVT<double> nA = avg4(uvt(ldw(e, plane, lo + i + 1), g), uvt(ldw(e, plane, lo + i + 2), g), uL, uR);
+    const UVT<double> nB = avg4(uL, uR, uvt(ldw(e, plane, hi + i + 1), g), uvt(ldw(e, plane, hi + i + 2), g));
+    double rl[4], rr[4];
+    rbar_cell(B, rbar, n, i - 1, j, rl);
+    rbar_cell(B, rbar, n, i, j, rr);
+    const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
+    const double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
+    const double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    face_rev(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
+             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf);
+}
+
+__global__ void k_adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
+                             const double *dJ, const double *rbar, Consts c, double *AF) {
+    const BlockDesc &B = blks[b];
+    const int64_t nf = (int64_t)B.ni * (B.nj + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf * B.ns) return;
+    const int n = (int)(t / nf);
+    const int64_t f = t % nf;
+    const int i = (int)(f % B.ni), j = (int)(f / B.ni);
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    const int col = i + 2;
+    const int x[4] = {(int)((int64_t)j * we + col), (int)((int64_t)(j + 1) * we + col),
+                      (int)((int64_t)(j + 2) * we + col), (int)((int64_t)(j + 3) * we + col)};
+    const double g = c.gamma;
+    const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
+    const int64_t r1 = (int64_t)(j + 1) * we, r2 = (int64_t)(j + 2) * we;
+    const UVT<double> nA = avg4(uvt(ldw(e, plane, r1 + col - 1), g), uL,
+                                uvt(ldw(e, plane, r2 + col - 1), g), uR);          // node (i, j)
+    const UVT<double> nB = avg4(uL, uvt(ldw(e, plane, r1 + col + 1), g), uR,
+                                uvt(ldw(e, plane, r2 + col + 1), g));              // node (i+1, j)
+    double rl[4], rr[4];
+    rbar_cell(B, rbar, n, i, j - 1, rl);
+    rbar_cell(B, rbar, n, i, j, rr);
+    const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
+    const double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
+    const double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    face_rev(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
+             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf);
+}
+
+// node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
+__global__ void k_adj_nodes(const BlockDesc *blks, int b, const double *AFI, const double *AFJ,
+                            double *NB) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * B.ns) return;
+    const int n = (int)(t / nn);
+    const int64_t k = t % nn;
+    const int i = (int)(k % W), j = (int)(k / W);
+    const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
+    const double *ai = AFI + B.afi_off + (int64_t)n * kAF * nfi;
+    const double *aj = AFJ + B.afj_off + (int64_t)n * kAF * nfj;
+    double s[3] = {0.0, 0.0, 0.0};
+    if (j < B.nj) {                          // i-face (i, j): node (i, j) is slot 0
+        const int64_t f = (int64_t)j * W + i;
+        for (int v = 0; v < 3; ++v) s[v] += ai[(16 + v) * nfi + f];
+    }
+    if (j >= 1) {                            // i-face (i, j-1): node (i, j) is slot 1
+        const int64_t f = (int64_t)(j - 1) * W + i;
+        for (int v = 0; v < 3; ++v) s[v] += ai[(19 + v) * nfi + f];
+    }
+    if (i < B.ni) {                          // j-face (i, j): node (i, j) is slot 1
+        const int64_t f = (int64_t)j * B.ni + i;
+        for (int v = 0; v < 3; ++v) s[v] += aj[(19 + v) * nfj + f];
+    }
+    if (i >= 1) {                            // j-face (i-1, j): node (i, j) is slot 0
+        const int64_t f = (int64_t)j * B.ni + i - 1;
+        for (int v = 0; v < 3; ++v) s[v] += aj[(16 + v) * nfj + f];
+    }
+    double *o = NB + B.nodeq_off + (int64_t)n * 3 * nn + k;
+    for (int v = 0; v < 3; ++v) o[v * nn] = s[v];
+}
+
+// primitive adjoints of every ghost-extended cell: [ns][4][nj+4][ni+4]
+__global__ void k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
+                            const double *AFJ, const double *NB, Consts c, double *WB) {
+    const BlockDesc &B = blks[b];
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane * B.ns) return;
+    const int n = (int)(t / plane);
+    const int64_t r = t % plane;
+    const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
+    const int W = B.ni + 1;
+    const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    const double *ai = AFI + B.afi_off + (int64_t)n * kAF * nfi;
+    const double *aj = AFJ + B.afj_off + (int64_t)n * kAF * nfj;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    // line stencils: this cell is m2 of face +2, m1 of +1, p0 of +0, p1 of -1
+    if (j >= 0 && j < B.nj) {
+        for (int role = 0; role < 4; ++role) {
+            const int f = i + 2 - role;
+            if (f < 0 || f > B.ni) continue;
+            const int64_t fi = (int64_t)j * W + f;
+            for (int v = 0; v < 4; ++v) s[v] += ai[(role * 4 + v) * nfi + fi];
+        }
+    }
+    if (i >= 0 && i < B.ni) {
+        for (int role = 0; role < 4; ++role) {
+            const int f = j + 2 - role;
+            if (f < 0 || f > B.nj) continue;
+            const int64_t fj = (int64_t)f * B.ni + i;
+            for (int v = 0; v < 4; ++v) s[v] += aj[(role * 4 + v) * nfj + fj];
+        }
+    }
+    // nodes (i, j), (i+1, j), (i, j+1), (i+1, j+1) average this cell
+    UVT<double> nb{0.0, 0.0, 0.0};
+    const double *nq = NB + B.nodeq_off + (int64_t)n * 3 * nn;
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            const int a = i + di, bb = j + dj;
+            if (a < 0 || a > B.ni || bb < 0 || bb > B.nj) continue;
+            const int64_t k = (int64_t)bb * W + a;
+            nb.u += 0.25 * nq[k];
+            nb.v += 0.25 * nq[nn + k];
+            nb.t += 0.25 * nq[2 * nn + k];
+        }
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    W4<double> wb{s[0], s[1], s[2], s[3]};
+    uvt_rev(ldw(e, plane, r), nb, c.gamma, wb);
+    double *o = WB + B.ext_off + (int64_t)n * 4 * plane + r;
+    o[0] = wb.r;
+    o[plane] = wb.u;
+    o[2 * plane] = wb.v;
+    o[3 * plane] = wb.p;
+}
+
+// interior cells: own adjoint + ghost copies -> conserved adjoint + HB source
+__global__ void k_adj_fold(const BlockDesc *blks, int b, const double *q, const double *rbar,
+                           const double *WB, const int *fptr, const int *fb, const int *fp,
+                           const int *fm, const double *V, const double *D, Consts c,
+                           double *qbar) {
+    const BlockDesc &B = blks[b];
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
+    const int we = B.ni + 4;
+    const int64_t eplane = (int64_t)we * (B.nj + 4);
+    const int64_t own = (int64_t)(j + 2) * we + i + 2;
+    const int64_t gc = B.cell_off + t;
+    const double vol = V[gc];
+    const double *dm = D + B.d_off;
+    const double gm1 = c.gamma - 1.0;
+    for (int n = 0; n < B.ns; ++n) {
+        const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
+        double wbv[4];
+        for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
+        for (int k = fptr[gc]; k < fptr[gc + 1]; ++k) {
+            const BlockDesc &S = blks[fb[k]];
+            const int64_t sp = (int64_t)(S.ni + 4) * (S.nj + 4);
+            const double *ws = WB + S.ext_off + (int64_t)n * 4 * sp + fp[k];
+            const double sg = fm[k] ? -1.0 : 1.0;
+            wbv[0] += ws[0];
+            wbv[1] += sg * ws[sp];
+            wbv[2] += sg * ws[2 * sp];
+            wbv[3] += ws[3 * sp];
+        }
+        const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
+        const W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane], gm1);
+        double qb[4];
+        prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
+        // HB source: d/dQ_n of sum_m rbar_m V D[m][n] Q_n
+        for (int v = 0; v < 4; ++v) {
+            double sacc = 0.0;
+            for (int m = 0; m < B.ns; ++m)
+                sacc += dm[m * kNsPad + n] * rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t];
+            qb[v] += vol * sacc;
+        }
+        double *o = qbar + B.q_off + (int64_t)n * 4 * plane + t;
+        for (int v = 0; v < 4; ++v) o[v * plane] = qb[v];
+    }
+}
+
+// alpha0: far-field ghost adjoints . d w_inf / d alpha0, one partial per block
+__global__ void k_adj_alpha(const BlockDesc *blks, int b, const double *WB, const int *ffptr,
+                            const int *ffp, const int *ffm, const double *ffw, double *part) {
+    const BlockDesc &B = blks[b];
+    const int we = B.ni + 4;
+    const int64_t eplane = (int64_t)we * (B.nj + 4);
+    double acc = 0.0;
+    const int k0 = ffptr[b], k1 = ffptr[b + 1];
+    for (int n = 0; n < B.ns; ++n) {
+        const double *w = ffw + 4 * (B.snap_off + n);
+        // d(u, v)/d alpha = (-v_inf, u_inf)
+        const double du = -w[2], dv = w[1];
+        const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kBS) {
+            const double sg = ffm[k] ? -1.0 : 1.0;
+            acc += sg * (wbn[eplane + ffp[k]] * du + wbn[2 * eplane + ffp[k]] * dv);
+        }
+    }
+    __shared__ double red[kBS];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b] = red[0];
+}
+
+__global__ void k_sum_parts(const double *part, int n, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += part[k];
+        *out = s;
+    }
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+// ---- node coordinates ------------------------------------------------------
+__device__ inline void xadd(double *xb, int64_t idx, double v) { unsafeAtomicAdd(xb + idx, v); }
+
+// add a centre adjoint (cx, cy) of cell (i, j) of block b to its four nodes
+__device__ inline void centre_to_nodes(const BlockDesc *blks, int b, int i, int j, double cx,
+                                       double cy, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    double *xb = xyb + 2 * B.node_off;
+    double *yb = xb + nn;
+    const int64_t k0 = (int64_t)j * W + i;
+    const int64_t ks[4] = {k0, k0 + 1, k0 + W, k0 + W + 1};
+    for (int k = 0; k < 4; ++k) {
+        xadd(xb, ks[k], 0.25 * cx);
+        xadd(yb, ks[k], 0.25 * cy);
+    }
+}
+
+// adjoint of P' = reflect(P, A, B) -> P, A, B
+__device__ inline void reflect_rev(double px, double py, double ax, double ay, double bx, double by,
+                                   double rbx, double rby, double &pbx, double &pby, double &abx,
+                                   double &aby, double &bbx, double &bby) {
+    const double ex = bx - ax, ey = by - ay;
+    const double num = (px - ax) * ex + (py - ay) * ey;
+    const double den = ex * ex + ey * ey;
+    const double t = num / den;
+    abx += 2.0 * rbx;
+    aby += 2.0 * rby;
+    pbx -= rbx;
+    pby -= rby;
+    double ebx = 2.0 * t * rbx, eby = 2.0 * t * rby;
+    const double tb = 2.0 * (rbx * ex + rby * ey);
+    const double numb = tb / den, denb = -tb * num / (den * den);
+    pbx += numb * ex;
+    pby += numb * ey;
+    abx -= numb * ex;
+    aby -= numb * ey;
+    ebx += numb * (px - ax) + 2.0 * denb * ex;
+    eby += numb * (py - ay) + 2.0 * denb * ey;
+    bbx += ebx;
+    bby += eby;
+    abx -= ebx;
+    aby -= eby;
+}
+
+// Ghost-centre adjoint of a boundary face: (gx, gy) is the adjoint of the
+// ghost cell's centre; side = block side; (ii, jj) = the interior cell next
+// to the face; A, B = face end nodes (indices into the block's nodes).
+__device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, int ii, int jj,
+                                        int kA, int kB, double gx, double gy, const double *xy,
+                                        const double *C, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int kind = B.bc[side];
+    const bool wake = side == 2 && kind == HB_BC_WAKECUT && (ii < B.wake || ii >= B.ni - B.wake);
+    if (kind == HB_BC_PERIODIC) {
+        const int pi = side == 0 ? B.ni - 1 : side == 1 ? 0 : ii;
+        const int pj = side == 2 ? B.nj - 1 : side == 3 ? 0 : jj;
+        centre_to_nodes(blks, b, pi, pj, gx, gy, xyb);
+    } else if (wake) {
+        centre_to_nodes(blks, b, B.ni - 1 - ii, 0, gx, gy, xyb);
+    } else if (kind == HB_BC_CUT) {
+        const int a = B.cut_blk[side];
+        const int pi = side == 0 ? blks[a].ni - 1 : side == 1 ? 0 : ii;
+        const int pj = side == 2 ? blks[a].nj - 1 : side == 3 ? 0 : jj;
+        centre_to_nodes(blks, a, pi, pj, gx, gy, xyb);
+    } else {   // wall or far field: mirror of the interior centre across the face
+        const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+        const double *x = xy + 2 * B.node_off, *y = x + nn;
+        const int64_t nc = (int64_t)B.ni * B.nj;
+        const int64_t ci = B.cell_off + (int64_t)jj * B.ni + ii;
+        const double px = C[2 * B.cell_off + (ci - B.cell_off)];
+        const double py = C[2 * B.cell_off + nc + (ci - B.cell_off)];
+        double pbx = 0, pby = 0, abx = 0, aby = 0, bbx = 0, bby = 0;
+        reflect_rev(px, py, x[kA], y[kA], x[kB], y[kB], gx, gy, pbx, pby, abx, aby, bbx, bby);
+        centre_to_nodes(blks, b, ii, jj, pbx, pby, xyb);
+        double *xb = xyb + 2 * B.node_off;
+        double *yb = xb + nn;
+        xadd(xb, kA, abx);
+        xadd(yb, kA, aby);
+        xadd(xb, kB, bbx);
+        xadd(yb, kB, bby);
+    }
+}
+
+// i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
+// d = centre(R) - centre(L)
+__global__ void k_adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
+                           const double *C, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nf = (int64_t)W * B.nj;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const int i = (int)(f % W), j = (int)(f / W);
+    double sxb = 0, syb = 0, dxb = 0, dyb = 0;
+    for (int n = 0; n < B.ns; ++n) {
+        const double *a = AF + B.afi_off + (int64_t)n * kAF * nf + f;
+        sxb += a[22 * nf];
+        syb += a[23 * nf];
+        dxb += a[24 * nf];
+        dyb += a[25 * nf];
+    }
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    double *xb = xyb + 2 * B.node_off;
+    double *yb = xb + nn;
+    const int64_t kA = (int64_t)j * W + i, kB = kA + W;
+    xadd(yb, kB, sxb);
+    xadd(yb, kA, -sxb);
+    xadd(xb, kA, syb);
+    xadd(xb, kB, -syb);
+    // d = C_R - C_L
+    if (i < B.ni) centre_to_nodes(blks, b, i, j, dxb, dyb, xyb);
+    else ghost_centre_rev(blks, b, 1, B.ni - 1, j, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
+    if (i > 0) centre_to_nodes(blks, b, i - 1, j, -dxb, -dyb, xyb);
+    else ghost_centre_rev(blks, b, 0, 0, j, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
+}
+
+// j-faces: S_J = (yA - yB, xB - xA), A = node (i, j), B = node (i+1, j)
+__global__ void k_adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
+                           const double *C, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int W = B.ni + 1;
+    const int64_t nf = (int64_t)B.ni * (B.nj + 1);
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const int i = (int)(f % B.ni), j = (int)(f / B.ni);
+    double sxb = 0, syb = 0, dxb = 0, dyb = 0;
+    for (int n = 0; n < B.ns; ++n) {
+        const double *a = AF + B.afj_off + (int64_t)n * kAF * nf + f;
+        sxb += a[22 * nf];
+        syb += a[23 * nf];
+        dxb += a[24 * nf];
+        dyb += a[25 * nf];
+    }
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    double *xb = xyb + 2 * B.node_off;
+    double *yb = xb + nn;
+    const int64_t kA = (int64_t)j * W + i, kB = kA + 1;
+    xadd(yb, kA, sxb);
+    xadd(yb, kB, -sxb);
+    xadd(xb, kB, syb);
+    xadd(xb, kA, -syb);
+    if (j < B.nj) centre_to_nodes(blks, b, i, j, dxb, dyb, xyb);
+    else ghost_centre_rev(blks, b, 3, i, B.nj - 1, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
+    if (j > 0) centre_to_nodes(blks, b, i, j - 1, -dxb, -dyb, xyb);
+    else ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
+}
+
+// cell areas: V enters through the HB source V (D Q)
+__global__ void k_adj_xy_vol(const BlockDesc *blks, int b, const double *q, const double *rbar,
+                             const double *D, const double *xy, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
+    const double *dm = D + B.d_off;
+    double vb = 0.0;
+    for (int n = 0; n < B.ns; ++n)
+        for (int v = 0; v < 4; ++v) {
+            double s = 0.0;
+            for (int m = 0; m < B.ns; ++m) s += dm[n * kNsPad + m] * q[B.q_off + ((int64_t)m * 4 + v) * plane + t];
+            vb += rbar[B.q_off + ((int64_t)n * 4 + v) * plane + t] * s;
+        }
+    const int W = B.ni + 1;
+    const int64_t nn = (int64_t)W * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    double *xb = xyb + 2 * B.node_off;
+    double *yb = xb + nn;
+    const int64_t k1 = (int64_t)j * W + i, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
+    // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2
+    const double h = 0.5 * vb;
+    xadd(xb, k3, h * (y[k4] - y[k2]));
+    xadd(xb, k1, -h * (y[k4] - y[k2]));
+    xadd(yb, k4, h * (x[k3] - x[k1]));
+    xadd(yb, k2, -h * (x[k3] - x[k1]));
+    xadd(yb, k3, -h * (x[k4] - x[k2]));
+    xadd(yb, k1, h * (x[k4] - x[k2]));
+    xadd(xb, k4, -h * (y[k3] - y[k1]));
+    xadd(xb, k2, h * (y[k3] - y[k1]));
+}
+
+// ---- host: inverse of the ghost rules ----------------------------------------
+struct GSrc {
+    int cell;    // 1: an interior cell, 0: the far field
+    int b, i, j;
+    int mir;     // number of wall mirrors, mod 2
+};
+
+GSrc res_i(const std::vector<BlockDesc> &B, int b, int i, int j) {
+    const BlockDesc &K = B[b];
+    if (i >= 0 && i < K.ni) return GSrc{1, b, i, j, 0};
+    const int side = i < 0 ? 0 : 1;
+    const int k = i < 0 ? -1 - i : i - K.ni;
+    switch (K.bc[side]) {
+        case HB_BC_PERIODIC: return GSrc{1, b, i < 0 ? i + K.ni : i - K.ni, j, 0};
+        case HB_BC_WALL: return GSrc{1, b, side == 0 ? k : K.ni - 1 - k, j, 1};
+        case HB_BC_CUT: {
+            const int a = K.cut_blk[side];
+            return GSrc{1, a, side == 0 ? B[a].ni - 1 - k : k, j, 0};
+        }
+        default: return GSrc{0, b, 0, 0, 0};
+    }
+}
+
+GSrc res_ij(const std::vector<BlockDesc> &B, int b, int i, int j) {
+    const BlockDesc &K = B[b];
+    if (j >= 0 && j < K.nj) return res_i(B, b, i, j);
+    const int side = j < 0 ? 2 : 3;
+    const int k = j < 0 ? -1 - j : j - K.nj;
+    GSrc s;
+    switch (K.bc[side]) {
+        case HB_BC_PERIODIC: return res_i(B, b, i, j < 0 ? j + K.nj : j - K.nj);
+        case HB_BC_WALL:
+            s = res_i(B, b, i, side == 2 ? k : K.nj - 1 - k);
+            s.mir ^= 1;
+            return s;
+        case HB_BC_WAKECUT:
+            if (i < K.wake || i >= K.ni - K.wake) return res_i(B, b, K.ni - 1 - i, k);
+            s = res_i(B, b, i, k);
+            s.mir ^= 1;
+            return s;
+        case HB_BC_CUT: {
+            const int a = K.cut_blk[side];
+            return res_i(B, a, i, side == 2 ? B[a].nj - 1 - k : k);
+        }
+        default: return GSrc{0, b, 0, 0, 0};
+    }
+}
+
+template <class T>
+int upload(T **d, const std::vector<T> &h) {
+    *d = nullptr;
+    int rc = check_hip(hipMalloc((void **)d, sizeof(T) * std::max<size_t>(1, h.size())), "adjoint alloc");
+    if (rc) return rc;
+    if (h.empty()) return HB_OK;
+    return check_hip(hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice), "upload");
+}
+
+int adjoint_setup(hb_grid *g) {
+    if (g->AFI_d) return HB_OK;
+    // inverse ghost map (CSR over global cells) and far-field ghost lists
+    std::vector<std::vector<int>> eb(g->n_cells), ep(g->n_cells), em(g->n_cells);
+    std::vector<int> ffptr(1, 0), ffp, ffm;
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &K = g->blk[b];
+        const int we = K.ni + 4;
+        for (int je = 0; je < K.nj + 4; ++je)
+            for (int ie = 0; ie < we; ++ie) {
+                const int i = ie - 2, j = je - 2;
+                if (i >= 0 && i < K.ni && j >= 0 && j < K.nj) continue;
+                const GSrc s = res_ij(g->blk, b, i, j);
+                const int p = je * we + ie;
+                if (s.cell) {
+                    const BlockDesc &S = g->blk[s.b];
+                    const int64_t gc = S.cell_off + (int64_t)s.j * S.ni + s.i;
+                    eb[gc].push_back(b);
+                    ep[gc].push_back(p);
+                    em[gc].push_back(s.mir);
+                } else {
+                    ffp.push_back(p);
+                    ffm.push_back(s.mir);
+                }
+            }
+        ffptr.push_back((int)ffp.size());
+    }
+    std::vector<int> fptr(g->n_cells + 1, 0), fb, fp, fm;
+    for (int64_t c = 0; c < g->n_cells; ++c) {
+        fptr[c + 1] = fptr[c] + (int)eb[c].size();
+        fb.insert(fb.end(), eb[c].begin(), eb[c].end());
+        fp.insert(fp.end(), ep[c].begin(), ep[c].end());
+        fm.insert(fm.end(), em[c].begin(), em[c].end());
+    }
+    int rc = upload(&g->fold_ptr_d, fptr);
+    rc = rc ? rc : upload(&g->fold_b_d, fb);
+    rc = rc ? rc : upload(&g->fold_p_d, fp);
+    rc = rc ? rc : upload(&g->fold_m_d, fm);
+    rc = rc ? rc : upload(&g->ff_ptr_d, ffptr);
+    rc = rc ? rc : upload(&g->ff_p_d, ffp);
+    rc = rc ? rc : upload(&g->ff_m_d, ffm);
+    if (rc) return rc;
+    auto alloc = [&](double **p, int64_t n) {
+        return check_hip(hipMalloc((void **)p, sizeof(double) * std::max<int64_t>(1, n)), "adjoint alloc");
+    };
+    rc = alloc(&g->AFI_d, g->n_afi);
+    rc = rc ? rc : alloc(&g->AFJ_d, g->n_afj);
+    rc = rc ? rc : alloc(&g->NB_d, g->n_nodeq);
+    rc = rc ? rc : alloc(&g->WBext_d, g->n_ext);
+    rc = rc ? rc : alloc(&g->adj_part_d, g->nblocks);
+    if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
+    return rc;
+}
+
+}  // namespace
+
+int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double *qbar,
+                            double *xybar, double *flowbar, hipStream_t s) {
+    int rc = adjoint_setup(g);
+    if (rc) return rc;
+    double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
+    const Consts c = g->consts;
+    for (int b = 0; b < g->nblocks; ++b) {
+        rc = plain_ghost_fill(g, b, q, ext, s);
+        if (rc) return rc;
+    }
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_face_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, ext, g->SI_d, g->dI_d, rbar, c, g->AFI_d);
+        hipLaunchKernelGGL(k_adj_face_j, dim3(nblk((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, ext, g->SJ_d, g->dJ_d, rbar, c, g->AFJ_d);
+        hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
+                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d);
+        hipLaunchKernelGGL(k_adj_cells, dim3(nblk((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
+                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d);
+    }
+    // every block's extended adjoints exist before any fold (cuts read neighbours)
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+                           q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
+                           g->V_d, g->D_d, c, qbar);
+    }
+    if (flowbar) {
+        for (int b = 0; b < g->nblocks; ++b)
+            hipLaunchKernelGGL(k_adj_alpha, dim3(1), dim3(kBS), 0, s, g->blk_d, b, g->WBext_d,
+                               g->ff_ptr_d, g->ff_p_d, g->ff_m_d, g->ffw_d, g->adj_part_d);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->nblocks, flowbar);
+    }
+    if (xybar) {
+        hipLaunchKernelGGL(k_zero, dim3(nblk(2 * g->n_nodes)), dim3(kBS), 0, s, xybar, 2 * g->n_nodes);
+        for (int b = 0; b < g->nblocks; ++b) {
+            const BlockDesc &B = g->blk[b];
+            hipLaunchKernelGGL(k_adj_xy_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj)), dim3(kBS), 0, s,
+                               g->blk_d, b, g->AFI_d, g->xy_d, g->C_d, xybar);
+            hipLaunchKernelGGL(k_adj_xy_j, dim3(nblk((int64_t)B.ni * (B.nj + 1))), dim3(kBS), 0, s,
+                               g->blk_d, b, g->AFJ_d, g->xy_d, g->C_d, xybar);
+            hipLaunchKernelGGL(k_adj_xy_vol, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d,
+                               b, q, rbar, g->D_d, g->xy_d, xybar);
+        }
+    }
+    return check_hip(hipGetLastError(), "adjoint launch");
+}
+
+int launch_forces_adjoint(hb_grid *, const double *, const double *, double *, double *, double *,
+                          hipStream_t) {
     return fail(HB_ERR_UNSUPPORTED, "forces adjoint not built");
 }
+
 }  // namespace hb

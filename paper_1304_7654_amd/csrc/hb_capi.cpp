@@ -72,6 +72,10 @@ void free_all(hb_grid *g) {
     dfree(g->body_off_d); dfree(g->body_ns_d);
     dfree(g->tiles_d);
     dfree(g->adj_d);
+    dfree(g->AFI_d); dfree(g->AFJ_d); dfree(g->NB_d); dfree(g->WBext_d); dfree(g->adj_part_d);
+    dfree(g->fold_ptr_d); dfree(g->fold_b_d); dfree(g->fold_p_d); dfree(g->fold_m_d);
+    dfree(g->ff_ptr_d); dfree(g->ff_p_d); dfree(g->ff_m_d);
+    dfree(g->ext_adj_d);
 }
 
 bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_WAKECUT; }
@@ -313,6 +317,9 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         B.fiq_off = g->n_fiq;
         B.fjq_off = g->n_fjq;
         B.part_off = part;
+        B.afi_off = g->n_afi;
+        B.afj_off = g->n_afj;
+        B.nodeq_off = g->n_nodeq;
         B.omega_nh = omega * S.n_harm;
         const int64_t cells = (int64_t)S.ni * S.nj;
         g->n_snap += B.ns;
@@ -325,6 +332,9 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         g->n_fiq += (int64_t)B.ns * 4 * (S.ni + 1) * S.nj;
         g->n_fjq += (int64_t)B.ns * 4 * S.ni * (S.nj + 1);
         g->total_cs += (int64_t)B.ns * cells;
+        g->n_afi += (int64_t)B.ns * kAF * (S.ni + 1) * S.nj;
+        g->n_afj += (int64_t)B.ns * kAF * S.ni * (S.nj + 1);
+        g->n_nodeq += (int64_t)B.ns * 3 * (S.ni + 1) * (S.nj + 1);
         part += plain_partials(B);
     }
     g->body_ns.resize(nbody);

@@ -401,4 +401,313 @@ __device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, co
     out[3] = T(0.5) * area * (f3 - d3);
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode (adjoint) of the FP64 face operators above.  Each *_rev
+// function takes the forward inputs (recomputing what it needs) and the
+// adjoint of the outputs, and ADDS the adjoints of the inputs.
+// ---------------------------------------------------------------------------
+
+// van Albada: returns v = VA(a, b) and its partial derivatives.
+__device__ __forceinline__ double van_albada_d(double a, double b, double eps, double &da,
+                                               double &db) {
+    const double N = (a + b) * (a * b + eps);
+    const double Dn = a * a + b * b + 2.0 * eps;
+    const double iD = 1.0 / Dn;
+    const double v = N * iD;
+    da = ((a * b + eps) + (a + b) * b - v * 2.0 * a) * iD;
+    db = ((a * b + eps) + (a + b) * a - v * 2.0 * b) * iD;
+    return v;
+}
+
+// MUSCL reverse for one variable: L = m1 + VA(m1-m2, p0-m1)/2,
+// R = p0 - VA(p0-m1, p1-p0)/2.
+__device__ __forceinline__ void muscl_rev1(double m2, double m1, double p0, double p1, double eps,
+                                           double Lb, double Rb, double &m2b, double &m1b,
+                                           double &p0b, double &p1b) {
+    double da, db;
+    van_albada_d(m1 - m2, p0 - m1, eps, da, db);
+    const double va = 0.5 * Lb;
+    m1b += Lb + va * (da - db);
+    m2b -= va * da;
+    p0b += va * db;
+    double ea, eb;
+    van_albada_d(p0 - m1, p1 - p0, eps, ea, eb);
+    const double vb = -0.5 * Rb;
+    p0b += Rb + vb * (ea - eb);
+    m1b -= vb * ea;
+    p1b += vb * eb;
+}
+
+// Roe flux reverse (full primitive states, FP64).  Fb: adjoint of the 4 flux
+// components; adds to Lb, Rb (primitive adjoints) and sxb, syb.
+__device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, double sx,
+                                    double sy, double g, double delta_frac, const double Fb[4],
+                                    W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb) {
+    // ---- forward recomputation
+    const double area = sqrt(sx * sx + sy * sy);
+    const double ia = 1.0 / area;
+    const double nx = sx * ia, ny = sy * ia;
+    const double gg = g / (g - 1.0);
+    const double irl = 1.0 / L.r, irr = 1.0 / R.r;
+    const double hl = gg * L.p * irl + 0.5 * (L.u * L.u + L.v * L.v);
+    const double hr = gg * R.p * irr + 0.5 * (R.u * R.u + R.v * R.v);
+    const double sl = sqrt(L.r), sr = sqrt(R.r);
+    const double iw = 1.0 / (sl + sr);
+    const double rt = sl * sr;
+    const double ut = (sl * L.u + sr * R.u) * iw;
+    const double vt = (sl * L.v + sr * R.v) * iw;
+    const double ht = (sl * hl + sr * hr) * iw;
+    const double q2t = ut * ut + vt * vt;
+    const double ct = sqrt((g - 1.0) * (ht - 0.5 * q2t));
+    const double qnt = ut * nx + vt * ny;
+    const double dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
+    const double dqn = du * nx + dv * ny;
+    const double ic2 = 1.0 / (ct * ct);
+    const double X = rt * ct * dqn;
+    const double a1 = (dp - X) * 0.5 * ic2;
+    const double a4 = (dp + X) * 0.5 * ic2;
+    const double a2 = dr - dp * ic2;
+    const double lam1 = qnt - ct, lam4 = qnt + ct;
+    const double r1 = fabs(lam1), r4 = fabs(lam4);
+    double l1 = r1, l4 = r4;
+    const double dd = delta_frac * ct;
+    const bool fix1 = delta_frac > 0.0 && r1 < dd, fix4 = delta_frac > 0.0 && r4 < dd;
+    if (fix1) l1 = (r1 * r1 + dd * dd) / (2.0 * dd);
+    if (fix4) l4 = (r4 * r4 + dd * dd) / (2.0 * dd);
+    const double l2 = fabs(qnt);
+    const double b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
+    const double d0 = b1 + b4 + b2;
+    const double d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
+    const double d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
+    const double d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (0.5 * q2t) +
+                      bs * (ut * du + vt * dv - qnt * dqn);
+    const double qnl = L.u * nx + L.v * ny, qnr = R.u * nx + R.v * ny;
+    const double ml = L.r * qnl, mr = R.r * qnr;
+    const double f0 = ml + mr;
+    const double f1 = ml * L.u + mr * R.u + (L.p + R.p) * nx;
+    const double f2 = ml * L.v + mr * R.v + (L.p + R.p) * ny;
+    const double f3 = ml * hl + mr * hr;
+    // ---- reverse sweep
+    double areab = 0.5 * (Fb[0] * (f0 - d0) + Fb[1] * (f1 - d1) + Fb[2] * (f2 - d2) + Fb[3] * (f3 - d3));
+    const double f0b = 0.5 * area * Fb[0], f1b = 0.5 * area * Fb[1];
+    const double f2b = 0.5 * area * Fb[2], f3b = 0.5 * area * Fb[3];
+    const double d0b = -f0b, d1b = -f1b, d2b = -f2b, d3b = -f3b;
+    double nxb = 0.0, nyb = 0.0;
+    double hlb = 0.0, hrb = 0.0;
+    // central part
+    const double mlb = f0b + f1b * L.u + f2b * L.v + f3b * hl;
+    const double mrb = f0b + f1b * R.u + f2b * R.v + f3b * hr;
+    Lb.u += f1b * ml;
+    Rb.u += f1b * mr;
+    Lb.v += f2b * ml;
+    Rb.v += f2b * mr;
+    Lb.p += f1b * nx + f2b * ny;
+    Rb.p += f1b * nx + f2b * ny;
+    nxb += f1b * (L.p + R.p);
+    nyb += f2b * (L.p + R.p);
+    hlb += f3b * ml;
+    hrb += f3b * mr;
+    Lb.r += mlb * qnl;
+    Rb.r += mrb * qnr;
+    const double qnlb = mlb * L.r, qnrb = mrb * R.r;
+    Lb.u += qnlb * nx;
+    Lb.v += qnlb * ny;
+    Rb.u += qnrb * nx;
+    Rb.v += qnrb * ny;
+    nxb += qnlb * L.u + qnrb * R.u;
+    nyb += qnlb * L.v + qnrb * R.v;
+    // dissipation
+    const double b1b = d0b + d1b * (ut - ct * nx) + d2b * (vt - ct * ny) + d3b * (ht - qnt * ct);
+    const double b4b = d0b + d1b * (ut + ct * nx) + d2b * (vt + ct * ny) + d3b * (ht + qnt * ct);
+    const double b2b = d0b + d1b * ut + d2b * vt + d3b * (0.5 * q2t);
+    const double bsb = d1b * (du - nx * dqn) + d2b * (dv - ny * dqn) + d3b * (ut * du + vt * dv - qnt * dqn);
+    const double bsum = b1 + b4 + b2;
+    double utb = bsum * d1b + bs * du * d3b;
+    double vtb = bsum * d2b + bs * dv * d3b;
+    double ctb = (b4 - b1) * (d1b * nx + d2b * ny + d3b * qnt);
+    nxb += d1b * (ct * (b4 - b1) - bs * dqn);
+    nyb += d2b * (ct * (b4 - b1) - bs * dqn);
+    double htb = d3b * (b1 + b4);
+    double q2tb = d3b * 0.5 * b2;
+    double qntb = d3b * (ct * (b4 - b1) - bs * dqn);
+    double dub = d1b * bs + d3b * bs * ut;
+    double dvb = d2b * bs + d3b * bs * vt;
+    double dqnb = -bs * (d1b * nx + d2b * ny + d3b * qnt);
+    const double l1b = b1b * a1, a1b = b1b * l1;
+    const double l4b = b4b * a4, a4b = b4b * l4;
+    const double l2b = b2b * a2 + bsb * rt;
+    const double a2b = b2b * l2;
+    double rtb = bsb * l2;
+    // eigenvalues with Harten's fix
+    double ddb = 0.0;
+    double r1b = l1b, r4b = l4b;
+    if (fix1) {
+        r1b = l1b * r1 / dd;
+        ddb += l1b * (dd * dd - r1 * r1) / (2.0 * dd * dd);
+    }
+    if (fix4) {
+        r4b = l4b * r4 / dd;
+        ddb += l4b * (dd * dd - r4 * r4) / (2.0 * dd * dd);
+    }
+    // d|x|/dx taken as sign(x) with sign(0) = 0, the average of the one-sided
+    // derivatives (a wall face has q~_n = 0 exactly by symmetry)
+    auto sgn = [](double x) { return (double)((x > 0.0) - (x < 0.0)); };
+    const double lam1b = r1b * sgn(lam1);
+    const double lam4b = r4b * sgn(lam4);
+    qntb += lam1b + lam4b + l2b * sgn(qnt);
+    ctb += -lam1b + lam4b + delta_frac * ddb;
+    // wave strengths
+    double dpb = 0.5 * ic2 * (a1b + a4b) - ic2 * a2b;
+    double drb = a2b;
+    const double Xb = 0.5 * ic2 * (a4b - a1b);
+    rtb += Xb * ct * dqn;
+    ctb += Xb * rt * dqn;
+    dqnb += Xb * rt * ct;
+    const double ic2b = 0.5 * (dp - X) * a1b + 0.5 * (dp + X) * a4b - dp * a2b;
+    ctb += ic2b * (-2.0 * ic2 / ct);
+    // qnt, dqn
+    utb += qntb * nx;
+    vtb += qntb * ny;
+    nxb += qntb * ut + dqnb * du;
+    nyb += qntb * vt + dqnb * dv;
+    dub += dqnb * nx;
+    dvb += dqnb * ny;
+    Rb.r += drb;
+    Lb.r -= drb;
+    Rb.u += dub;
+    Lb.u -= dub;
+    Rb.v += dvb;
+    Lb.v -= dvb;
+    Rb.p += dpb;
+    Lb.p -= dpb;
+    // ct = sqrt((g-1)(ht - q2t/2))
+    const double c2b = ctb / (2.0 * ct);
+    htb += (g - 1.0) * c2b;
+    q2tb -= 0.5 * (g - 1.0) * c2b;
+    utb += 2.0 * ut * q2tb;
+    vtb += 2.0 * vt * q2tb;
+    // Roe averages
+    double slb = rtb * sr, srb = rtb * sl;
+    Lb.u += utb * sl * iw;
+    Rb.u += utb * sr * iw;
+    slb += utb * (L.u - ut) * iw;
+    srb += utb * (R.u - ut) * iw;
+    Lb.v += vtb * sl * iw;
+    Rb.v += vtb * sr * iw;
+    slb += vtb * (L.v - vt) * iw;
+    srb += vtb * (R.v - vt) * iw;
+    hlb += htb * sl * iw;
+    hrb += htb * sr * iw;
+    slb += htb * (hl - ht) * iw;
+    srb += htb * (hr - ht) * iw;
+    Lb.r += slb / (2.0 * sl);
+    Rb.r += srb / (2.0 * sr);
+    // enthalpies
+    Lb.p += hlb * gg * irl;
+    Lb.r -= hlb * gg * L.p * irl * irl;
+    Lb.u += hlb * L.u;
+    Lb.v += hlb * L.v;
+    Rb.p += hrb * gg * irr;
+    Rb.r -= hrb * gg * R.p * irr * irr;
+    Rb.u += hrb * R.u;
+    Rb.v += hrb * R.v;
+    // unit normal and face length
+    sxb += (nxb * (1.0 - nx * nx) - nyb * nx * ny) * ia + areab * nx;
+    syb += (nyb * (1.0 - ny * ny) - nxb * nx * ny) * ia + areab * ny;
+}
+
+// Viscous flux reverse.  fvb: adjoint of (fx, fy, fe); adds to the (u, v, T)
+// adjoints at L, R, P (edge start), Q (edge end) and to S, d.
+__device__ inline void viscous_flux_rev(const UVT<double> &L, const UVT<double> &R,
+                                        const UVT<double> &P, const UVT<double> &Q, double sx,
+                                        double sy, double dx, double dy, double mu, double kappa,
+                                        const double fvb[3], UVT<double> &Lb, UVT<double> &Rb,
+                                        UVT<double> &Pb, UVT<double> &Qb, double &sxb, double &syb,
+                                        double &dxb, double &dyb) {
+    const double den = dx * sx + dy * sy;
+    const double iden = 1.0 / den;
+    const double ax = sx * iden, ay = sy * iden, bx = dy * iden, by = -dx * iden;
+    const double du = R.u - L.u, dv = R.v - L.v, dt = R.t - L.t;
+    const double eu = P.u - Q.u, ev = P.v - Q.v, et = P.t - Q.t;
+    const double ux = du * ax + eu * bx, uy = du * ay + eu * by;
+    const double vx = dv * ax + ev * bx, vy = dv * ay + ev * by;
+    const double tx = dt * ax + et * bx, ty = dt * ay + et * by;
+    const double div = ux + vy;
+    const double txx = mu * (2.0 * ux - (2.0 / 3.0) * div);
+    const double tyy = mu * (2.0 * vy - (2.0 / 3.0) * div);
+    const double txy = mu * (uy + vx);
+    const double fx = txx * sx + txy * sy;
+    const double fy = txy * sx + tyy * sy;
+    const double uf = 0.5 * (L.u + R.u), vf = 0.5 * (L.v + R.v);
+    const double gx = fvb[0], gy = fvb[1], ge = fvb[2];
+    // fe = uf fx + vf fy + kappa (tx sx + ty sy)
+    const double ufb = ge * fx, vfb = ge * fy;
+    const double fxb = gx + ge * uf, fyb = gy + ge * vf;
+    const double txb = ge * kappa * sx, tyb = ge * kappa * sy;
+    sxb += ge * kappa * tx;
+    syb += ge * kappa * ty;
+    // fx = txx sx + txy sy ; fy = txy sx + tyy sy
+    const double txxb = fxb * sx, tyyb = fyb * sy, txyb = fxb * sy + fyb * sx;
+    sxb += fxb * txx + fyb * txy;
+    syb += fxb * txy + fyb * tyy;
+    const double uxb = mu * ((4.0 / 3.0) * txxb - (2.0 / 3.0) * tyyb);
+    const double vyb = mu * ((4.0 / 3.0) * tyyb - (2.0 / 3.0) * txxb);
+    const double uyb = mu * txyb, vxb = mu * txyb;
+    Lb.u += 0.5 * ufb;
+    Rb.u += 0.5 * ufb;
+    Lb.v += 0.5 * vfb;
+    Rb.v += 0.5 * vfb;
+    // gradients
+    const double dub = uxb * ax + uyb * ay, eub = uxb * bx + uyb * by;
+    const double dvb = vxb * ax + vyb * ay, evb = vxb * bx + vyb * by;
+    const double dtb = txb * ax + tyb * ay, etb = txb * bx + tyb * by;
+    const double axb = uxb * du + vxb * dv + txb * dt;
+    const double ayb = uyb * du + vyb * dv + tyb * dt;
+    const double bxb = uxb * eu + vxb * ev + txb * et;
+    const double byb = uyb * eu + vyb * ev + tyb * et;
+    Rb.u += dub;
+    Lb.u -= dub;
+    Rb.v += dvb;
+    Lb.v -= dvb;
+    Rb.t += dtb;
+    Lb.t -= dtb;
+    Pb.u += eub;
+    Qb.u -= eub;
+    Pb.v += evb;
+    Qb.v -= evb;
+    Pb.t += etb;
+    Qb.t -= etb;
+    // geometry
+    const double idenb = axb * sx + ayb * sy + bxb * dy - byb * dx;
+    sxb += axb * iden;
+    syb += ayb * iden;
+    dyb += bxb * iden;
+    dxb -= byb * iden;
+    const double denb = -iden * iden * idenb;
+    dxb += denb * sx;
+    sxb += denb * dx;
+    dyb += denb * sy;
+    syb += denb * dy;
+}
+
+// (u, v, T = gamma p / rho) adjoint -> primitive adjoint
+__device__ __forceinline__ void uvt_rev(const W4<double> &w, const UVT<double> &b, double g,
+                                        W4<double> &wb) {
+    wb.u += b.u;
+    wb.v += b.v;
+    const double ir = 1.0 / w.r;
+    wb.p += b.t * g * ir;
+    wb.r -= b.t * g * w.p * ir * ir;
+}
+
+// primitive adjoint -> conserved adjoint (rho, rho u, rho v, rho E)
+__device__ __forceinline__ void prim_rev(const W4<double> &w, const W4<double> &wb, double gm1,
+                                         double qb[4]) {
+    const double ir = 1.0 / w.r;
+    qb[0] = wb.r - wb.u * w.u * ir - wb.v * w.v * ir + wb.p * gm1 * 0.5 * (w.u * w.u + w.v * w.v);
+    qb[1] = wb.u * ir - wb.p * gm1 * w.u;
+    qb[2] = wb.v * ir - wb.p * gm1 * w.v;
+    qb[3] = wb.p * gm1;
+}
+
 }  // namespace hb

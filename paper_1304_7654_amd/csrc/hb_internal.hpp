@@ -14,6 +14,7 @@ namespace hb {
 
 constexpr int kMaxNs = 9;        // N_H <= 4
 constexpr int kNsPad = 16;       // padded D (MFMA tile)
+constexpr int kAF = 26;          // adjoint terms stored per face and snapshot
 
 // Device-side description of one block.  Offsets index the flat arrays
 // of the grid (all blocks concatenated).
@@ -35,6 +36,9 @@ struct BlockDesc {
     int64_t fiq_off;         // plain path i-face fluxes: ns*4*nj*(ni+1)
     int64_t fjq_off;         // plain path j-face fluxes: ns*4*(nj+1)*ni
     int64_t part_off;        // plain path norm partials of this block
+    int64_t afi_off;         // adjoint: per-face adjoint terms of i-faces, ns*kAF*nj*(ni+1)
+    int64_t afj_off;         // adjoint: same for j-faces, ns*kAF*(nj+1)*ni
+    int64_t nodeq_off;       // adjoint: node (u, v, T) adjoints, ns*3*(nj+1)*(ni+1)
     double omega_nh;         // omega * N_H (time-step bound of the HB term)
 };
 
@@ -120,9 +124,15 @@ struct hb_grid {
     int prof = 0;
     std::vector<hipEvent_t> prof_ev;     // pairs (start, end), reused
     size_t prof_used = 0;
-    // adjoint scratch
+    // adjoint scratch (allocated on first use)
     double *adj_d = nullptr;
     int64_t n_adj = 0;
+    int64_t n_afi = 0, n_afj = 0, n_nodeq = 0;
+    double *AFI_d = nullptr, *AFJ_d = nullptr, *NB_d = nullptr, *WBext_d = nullptr;
+    double *adj_part_d = nullptr;         // alpha0 partials, one per block
+    int *fold_ptr_d = nullptr, *fold_b_d = nullptr, *fold_p_d = nullptr, *fold_m_d = nullptr;
+    int *ff_ptr_d = nullptr, *ff_p_d = nullptr, *ff_m_d = nullptr;
+    double *ext_adj_d = nullptr;          // ghost-extended primitives for the adjoint
 };
 
 namespace hb {

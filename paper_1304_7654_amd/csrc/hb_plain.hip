@@ -230,6 +230,15 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
 
 }  // namespace
 
+// Ghost-extended primitives of block b (also used by the adjoint).
+int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_t s) {
+    const BlockDesc &B = g->blk[b];
+    const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
+    hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
+                       g->consts.gamma - 1.0, ext);
+    return check_hip(hipGetLastError(), "ghost launch");
+}
+
 // Number of norm partials the plain path writes for a block.
 int64_t plain_partials(const BlockDesc &B) { return nblk((int64_t)B.ni * B.nj); }
 
