@@ -63,8 +63,7 @@ def read_traffic():
 
 
 def algorithmic_bytes_per_iteration(problem) -> float:
-    """Bytes the FP32-bulk iteration must move (4 stages), the design doc table:
-    stage 1 reads Q (FP64, 32 B/cs) and writes the FP32 stage state (16);
+    """Bytes the FP32-bulk iteration must move (4 stages): stage 1 reads Q (FP64, 32 B/cs) and writes the FP32 stage state (16);
     stages 2-3 read the stage state (16) and Q (32) and write (16); stage 4
     reads the stage state (16) and Q (32) and writes Q (32).  Each stage also
     reads 9 FP32 metric words per cell (two face normals, two centre
@@ -86,6 +85,39 @@ def time_steps(torch, g, q, steps, forces=True):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1000.0, norms
+
+
+def adjoint_over_primal(torch, hb, synth, name, reps):
+    """t(hb_residual_adjoint with state, coordinate and incidence bars) over
+    t(hb_residual), both FP64 on the same grid and state, HIP events."""
+    p = synth.make_problem(name)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    dev = torch.device("cuda:0")
+    q = torch.as_tensor(synth.initial_state(p)).to(dev)
+    gen = torch.Generator().manual_seed(1307)
+    rbar = torch.randn(q.shape, generator=gen, dtype=torch.float64).to(dev)
+    r, qb = torch.empty_like(q), torch.empty_like(q)
+    xyb = torch.empty(g.n_xy, dtype=torch.float64, device=dev)
+    ab = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        fn()
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    tp = timed(lambda: g.residual(q, r))
+    ta = timed(lambda: g.residual_adjoint(q, rbar, qb, xyb, ab))
+    g.close()
+    return {"primal_ms": tp, "adjoint_ms": ta, "ratio": ta / tp,
+            "cell_snapshots": p.cell_snapshots}
 
 
 def cpu_baseline(problem, q_host, target_s=12.0):
@@ -128,12 +160,13 @@ def main():
     ap.add_argument("--workload", default="batch32_mixed")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/primal timing")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the multi-GPU block decomposition is described in DESIGN.md, not built)"
+              "(the block decomposition over several GPUs is not built)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -217,7 +250,9 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,
                      "algorithmic_bytes_per_launch": bytes_launch},
-        "adjoint_over_primal": None,
+        "adjoint_over_primal": None if args.no_adjoint else {
+            name: adjoint_over_primal(torch, hb, synth, name, reps)
+            for name, reps in (("naca256x128_hh64", 50), ("naca1024x512_nh4", 10))},
         "resnorm_last": float(norms[-1].item()),
     }
     if not args.no_cpu:
