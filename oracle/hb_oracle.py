@@ -201,22 +201,43 @@ def mirror_prim(w: torch.Tensor) -> torch.Tensor:
 # ---------------------------------------------------------------------------
 # Ghost cells (two layers per side; the paper's "cuts" are block-edge halos)
 # ---------------------------------------------------------------------------
-def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
-    """Primitive field w[ns][4][nj][ni] -> ghost-extended we[ns][4][nj+4][ni+4]
-    (cell (i, j) at index (j+2, i+2)).
+def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
+    """(block, side) -> (neighbour block, neighbour side) for every glued side.
 
-    Rules (the paper gives none; reading):
-      periodic:  copy of the cells one period away;
-      farfield:  both layers = free stream of the snapshot's incidence;
-      wall:      ghost k (k = 0 nearest) mirrors interior cell k;
-      wake cut:  C-grid jmin: ghost (i, -1-k) = cell (ni-1-i, k) for i in the
-                 wake (i < wake_ncells or i >= ni - wake_ncells), wall otherwise.
-    The i sides are filled first (rows 0..nj-1); the j sides then apply their
-    rule to the i-extended rows, which also defines the corner ghosts.
-    """
+    A cut joins two block edges (the paper's "cuts" between blocks, whose
+    halos are exchanged every Runge-Kutta step, §MPI Optimisations).  Read
+    here as whole sides of equal length, imax of one block to imin of the
+    other (equal nj) or jmax to jmin (equal ni), not reversed, both sides of
+    kind CUT.  Sides are numbered 0..3 = imin, imax, jmin, jmax."""
+    m = {}
+    for c in cuts:
+        a, sa, b, sb = int(c[0]), int(c[1]), int(c[2]), int(c[3])
+        if len(c) > 4 and c[4]:
+            raise ValueError("reversed cuts are not supported")
+        if {sa, sb} not in ({0, 1}, {2, 3}):
+            raise ValueError("a cut joins imax to imin or jmax to jmin")
+        A, B = blocks[a], blocks[b]
+        if A.bc[sa] != CUT or B.bc[sb] != CUT or A.n_harm != B.n_harm:
+            raise ValueError("cut sides must be of kind CUT with equal n_harm")
+        if (sa < 2 and A.nj != B.nj) or (sa >= 2 and A.ni != B.ni):
+            raise ValueError("cut sides must have equal length")
+        if (a, sa) in m or (b, sb) in m:
+            raise ValueError("a block side is used by two cuts")
+        m[(a, sa)] = (b, sb)
+        m[(b, sb)] = (a, sa)
+    for k, blk in enumerate(blocks):
+        for side in range(4):
+            if blk.bc[side] == CUT and (k, side) not in m:
+                raise ValueError("a CUT side has no cut")
+    return m
+
+
+def extend_i(b: OBlock, w: torch.Tensor, winf: torch.Tensor, nbr=None) -> torch.Tensor:
+    """Ghost columns of the i sides: w[ns][4][nj][ni] -> [ns][4][nj][ni+4]
+    (cell i at column i+2).  `nbr` maps a CUT side (0 or 1) to the
+    neighbour block's interior field."""
     ns, _, nj, ni = w.shape
     ff = winf[:, :, None, None]
-    # --- i sides ---------------------------------------------------------
     cols = [None] * (ni + 4)
     for k in range(ni):
         cols[k + 2] = w[..., k]
@@ -231,11 +252,22 @@ def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
             elif kind == WALL:
                 src = k if side == 0 else ni - 1 - k
                 c = mirror_prim(w[..., src:src + 1])[..., 0]
+            elif kind == CUT:
+                wa = nbr[side]                 # glued to the other block's imax / imin
+                c = wa[..., wa.shape[-1] - 1 - k] if side == 0 else wa[..., k]
             else:
                 raise ValueError("unsupported i-side boundary %d" % kind)
             cols[gi + 2] = c
-    wi = torch.stack(cols, dim=-1)             # [ns][4][nj][ni+4]
-    # --- j sides (over the i-extended rows) ------------------------------
+    return torch.stack(cols, dim=-1)
+
+
+def extend_j(b: OBlock, wi: torch.Tensor, winf: torch.Tensor, nbr=None) -> torch.Tensor:
+    """Ghost rows of the j sides over the i-extended rows wi[ns][4][nj][ni+4]
+    -> [ns][4][nj+4][ni+4]; this also defines the corner ghosts.  `nbr` maps
+    a CUT side (2 or 3) to the neighbour block's i-extended field."""
+    ns, _, nj, nie = wi.shape
+    ni = nie - 4
+    ff = winf[:, :, None, None]
     rows = [None] * (nj + 4)
     for k in range(nj):
         rows[k + 2] = wi[..., k, :]
@@ -260,10 +292,43 @@ def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
                     else:
                         parts.append(wall[..., ie])
                 r = torch.stack(parts, dim=-1)
+            elif kind == CUT:
+                wa = nbr[side]
+                r = wa[..., wa.shape[-2] - 1 - k, :] if side == 2 else wa[..., k, :]
             else:
                 raise ValueError("unsupported j-side boundary %d" % kind)
             rows[gj + 2] = r
-    return torch.stack(rows, dim=-2)          # [ns][4][nj+4][ni+4]
+    return torch.stack(rows, dim=-2)
+
+
+def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
+    """Primitive field w[ns][4][nj][ni] -> ghost-extended we[ns][4][nj+4][ni+4]
+    (cell (i, j) at index (j+2, i+2)) of a block without cuts.
+
+    Rules (the paper gives none; reading):
+      periodic:  copy of the cells one period away;
+      farfield:  both layers = free stream of the snapshot's incidence;
+      wall:      ghost k (k = 0 nearest) mirrors interior cell k;
+      wake cut:  C-grid jmin: ghost (i, -1-k) = cell (ni-1-i, k) for i in the
+                 wake (i < wake_ncells or i >= ni - wake_ncells), wall otherwise;
+      cut:       the glued block's cells (extend_all).
+    The i sides are filled first (rows 0..nj-1); the j sides then apply their
+    rule to the i-extended rows, which also defines the corner ghosts.
+    """
+    return extend_j(b, extend_i(b, w, winf), winf)
+
+
+def extend_all(blocks, ws, winfs, partners):
+    """Ghost-extended primitive fields of all blocks.  A cut ghost is a cell
+    of the glued block taken from the same input (Jacobi exchange): i-side
+    ghosts from the neighbour's interior, j-side ghosts (and corners) from
+    the neighbour's i-extended rows."""
+    wis = [extend_i(b, w, wf, {s: ws[partners[(k, s)][0]] for s in (0, 1)
+                               if (k, s) in partners})
+           for k, (b, w, wf) in enumerate(zip(blocks, ws, winfs))]
+    return [extend_j(b, wi, wf, {s: wis[partners[(k, s)][0]] for s in (2, 3)
+                                 if (k, s) in partners})
+            for k, (b, wi, wf) in enumerate(zip(blocks, wis, winfs))]
 
 
 def reflect(p: torch.Tensor, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
@@ -274,11 +339,12 @@ def reflect(p: torch.Tensor, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     return 2.0 * foot - p
 
 
-def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor):
+def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor, nbrC=None):
     """Centres of the first ghost layer on each side (for the viscous diamond
-    of boundary faces).  Periodic and wake-cut ghosts are real cells, so their
-    centre is the partner cell's centre; wall and farfield ghost centres are
-    the interior centre mirrored across the boundary face.
+    of boundary faces).  Periodic, wake-cut and cut ghosts are real cells, so
+    their centre is the partner cell's centre (`nbrC` maps a CUT side to the
+    glued block's cell centres); wall and farfield ghost centres are the
+    interior centre mirrored across the boundary face.
     Returns (c_imin [nj][2], c_imax [nj][2], c_jmin [ni][2], c_jmax [ni][2])."""
     nj, ni = C.shape[0], C.shape[1]
     P = xy.permute(1, 2, 0)                   # nodes [nj+1][ni+1][2]
@@ -299,6 +365,9 @@ def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor):
             mir = reflect(C[nj - 1, :], P[nj, :-1], P[nj, 1:])
         if kind == PERIODIC:
             out.append(real)
+        elif kind == CUT:
+            Ca = nbrC[side]
+            out.append((Ca[:, Ca.shape[1] - 1], Ca[:, 0], Ca[Ca.shape[0] - 1, :], Ca[0, :])[side])
         elif kind in (WALL, FARFIELD):
             out.append(mir)
         elif kind == WAKECUT:
@@ -450,19 +519,23 @@ def uvt(w: torch.Tensor, gamma: float) -> torch.Tensor:
 # ---------------------------------------------------------------------------
 def face_fluxes(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver,
                 alpha0: Optional[torch.Tensor] = None, xy: Optional[torch.Tensor] = None,
-                winf: Optional[torch.Tensor] = None):
+                winf: Optional[torch.Tensor] = None, we: Optional[torch.Tensor] = None,
+                nbrC=None):
     """Net face fluxes (inviscid minus viscous, times face length) of every
     i-face FI[ns][4][nj][ni+1] and j-face FJ[ns][4][nj+1][ni] of one block,
     for all snapshots; q is the conserved state q[ns][4][nj][ni].  `winf`
-    overrides the far-field primitives per snapshot ([ns][4])."""
+    overrides the far-field primitives per snapshot ([ns][4]); a block with
+    cuts passes its ghost-extended primitives `we` and the glued blocks'
+    centres `nbrC` (extend_all)."""
     g = flow.gamma
     xy = b.xy if xy is None else xy
     SI, SJ, V, C = metrics(xy)
     ns, _, nj, ni = q.shape
-    w = primitives(q, g)
-    if winf is None:
-        winf = freestream_prim(flow, ns, alpha0)
-    we = extend(b, w, winf)                           # [ns][4][nj+4][ni+4]
+    if we is None:
+        w = primitives(q, g)
+        if winf is None:
+            winf = freestream_prim(flow, ns, alpha0)
+        we = extend(b, w, winf)                       # [ns][4][nj+4][ni+4]
     eps = solver.limiter_eps
     # ---- inviscid: MUSCL along grid lines + Roe --------------------------
     # i-face i (0..ni) between cells i-1 and i, rows j = 0..nj-1
@@ -483,7 +556,7 @@ def face_fluxes(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver,
     # node (i, j), i = 0..ni, j = 0..nj: mean of cells (i-1..i, j-1..j)
     nodev = 0.25 * (t[:, :, 1:nj + 2, 1:ni + 2] + t[:, :, 1:nj + 2, 2:ni + 3]
                     + t[:, :, 2:nj + 3, 1:ni + 2] + t[:, :, 2:nj + 3, 2:ni + 3])
-    cim, cip, cjm, cjp = ghost_centres(b, xy, C)
+    cim, cip, cjm, cjp = ghost_centres(b, xy, C, nbrC)
     # extended centres for the cells L/R of i-faces: [nj][ni+2][2]
     ce_i = torch.cat([cim[:, None, :], C, cip[:, None, :]], dim=1)
     ce_j = torch.cat([cjm[None, :, :], C, cjp[None, :, :]], dim=0)   # [nj+2][ni][2]
@@ -513,9 +586,10 @@ def face_fluxes(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver,
     return FI - GI, FJ - GJ
 
 
-def spatial_residual(b, q, flow, solver, alpha0=None, xy=None, winf=None) -> torch.Tensor:
+def spatial_residual(b, q, flow, solver, alpha0=None, xy=None, winf=None, we=None,
+                     nbrC=None) -> torch.Tensor:
     """R(i,j) = F(i+1,j) - F(i,j) + G(i,j+1) - G(i,j): net outflow of the cell."""
-    FI, FJ = face_fluxes(b, q, flow, solver, alpha0, xy, winf)
+    FI, FJ = face_fluxes(b, q, flow, solver, alpha0, xy, winf, we, nbrC)
     return (FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :])
 
 
@@ -529,14 +603,36 @@ def hb_source(b: OBlock, q: torch.Tensor, flow: OFlow, xy=None) -> torch.Tensor:
     return V * dq
 
 
-def residual(b, q, flow, solver, alpha0=None, xy=None) -> torch.Tensor:
+def residual(b, q, flow, solver, alpha0=None, xy=None, we=None, nbrC=None) -> torch.Tensor:
     """HB residual R*_n = R(Q_n) + V (D Q)_n of one block.  The pseudo-time
     system is V dQ/dtau = -R*."""
-    return spatial_residual(b, q, flow, solver, alpha0, xy) + hb_source(b, q, flow, xy)
+    return (spatial_residual(b, q, flow, solver, alpha0, xy, None, we, nbrC)
+            + hb_source(b, q, flow, xy))
 
 
-def residual_all(blocks, q, flow, solver) -> torch.Tensor:
-    return join([residual(b, qb, flow, solver) for b, qb in zip(blocks, split(blocks, q))])
+def _halos(blocks, qs, flow, cuts, alpha0=None, xys=None):
+    """Ghost-extended primitives and glued-block centres of all blocks, or
+    (None, None) per block when there are no cuts."""
+    if not cuts:
+        return [None] * len(blocks), [None] * len(blocks)
+    xys = [b.xy for b in blocks] if xys is None else xys
+    P = cut_partners(blocks, cuts)
+    ws = [primitives(qb, flow.gamma) for qb in qs]
+    winfs = [freestream_prim(flow, b.ns, alpha0) for b in blocks]
+    wes = extend_all(blocks, ws, winfs, P)
+    Cs = [metrics(xy)[3] for xy in xys]
+    nbr = [{s: Cs[P[(k, s)][0]] for s in range(4) if (k, s) in P} for k in range(len(blocks))]
+    return wes, nbr
+
+
+def residual_all(blocks, q, flow, solver, cuts=(), alpha0=None, xys=None) -> torch.Tensor:
+    """R* of all blocks (concatenated public layout); `cuts` glue block sides
+    (cut_partners), `xys`/`alpha0` override node coordinates / incidence."""
+    xys = [b.xy for b in blocks] if xys is None else xys
+    qs = split(blocks, q)
+    wes, nbr = _halos(blocks, qs, flow, cuts, alpha0, xys)
+    return join([residual(b, qb, flow, solver, alpha0, xy, we, nc)
+                 for b, qb, xy, we, nc in zip(blocks, qs, xys, wes, nbr)])
 
 
 # ---------------------------------------------------------------------------
@@ -580,7 +676,7 @@ def rk_stages(q0, dt_over_v, resid, alphas):
     return qk, r0
 
 
-def rk_iterate(blocks, q: torch.Tensor, flow, solver, n_iter: int):
+def rk_iterate(blocks, q: torch.Tensor, flow, solver, n_iter: int, cuts=()):
     """Explicit multistage Runge-Kutta pseudo-time iterations (the paper's
     "Runge-Kutta step", §MPI Optimisations; coefficients not given there).
 
@@ -598,7 +694,7 @@ def rk_iterate(blocks, q: torch.Tensor, flow, solver, n_iter: int):
         q0 = split(blocks, q)
         dtv = join([(local_dt(b, qb, flow, solver) / V)[:, None].expand(-1, 4, -1, -1)
                     for b, qb, V in zip(blocks, q0, vols)])
-        resid = lambda x: residual_all(blocks, x, flow, solver)
+        resid = lambda x: residual_all(blocks, x, flow, solver, cuts)
         q, r0 = rk_stages(q, dtv, resid, solver.rk_alpha)
         s = sum(float(((r[:, 0] / V) ** 2).sum())
                 for r, V in zip(split(blocks, r0), vols))
@@ -646,7 +742,8 @@ def wall_face_mask(b: OBlock) -> torch.Tensor:
 
 
 def block_loads(b: OBlock, q: torch.Tensor, flow: OFlow,
-                alpha0: Optional[torch.Tensor] = None, xy: Optional[torch.Tensor] = None):
+                alpha0: Optional[torch.Tensor] = None, xy: Optional[torch.Tensor] = None,
+                we: Optional[torch.Tensor] = None, nbrC=None):
     """Force (Fx, Fy) and moment Mz (counter-clockwise positive, about
     (x_mom, y_mom)) on the wall faces of one block, per snapshot, [ns][3].
 
@@ -659,13 +756,13 @@ def block_loads(b: OBlock, q: torch.Tensor, flow: OFlow,
     SI, SJ, V, C = metrics(xy)
     ns = q.shape[0]
     w = primitives(q, g)
-    winf = freestream_prim(flow, ns, alpha0)
-    we = extend(b, w, winf)
+    if we is None:
+        we = extend(b, w, freestream_prim(flow, ns, alpha0))
     t = uvt(we, g)
     ni, nj = b.ni, b.nj
     nodev = 0.25 * (t[:, :, 1:3, 1:ni + 2] + t[:, :, 1:3, 2:ni + 3]
                     + t[:, :, 2:4, 1:ni + 2] + t[:, :, 2:4, 2:ni + 3])   # nodes j = 0, 1
-    cjm = ghost_centres(b, xy, C)[2]
+    cjm = ghost_centres(b, xy, C, nbrC)[2]
     S = SJ[0].permute(1, 0)                          # [2][ni]
     tL = t[:, :, 1, 2:ni + 2]
     tR = t[:, :, 2, 2:ni + 2]
@@ -689,7 +786,7 @@ def block_loads(b: OBlock, q: torch.Tensor, flow: OFlow,
 
 
 def forces(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver,
-           alpha0: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+           alpha0: Optional[torch.Tensor] = None, cuts=(), xys=None) -> List[torch.Tensor]:
     """Lift, drag and moment coefficients per body and snapshot (the paper's
     cl(n, ibody), cd(n, ibody), cm(n, ibody), §MPI Optimisations, force
     reduction).  Axes of the mean free stream: drag along (cos a0, sin a0),
@@ -701,8 +798,11 @@ def forces(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver,
     qinf = 0.5 * flow.mach ** 2
     nbody = max(b.body_id for b in blocks) + 1
     acc = [None] * nbody
-    for b, qb in zip(blocks, split(blocks, q)):
-        L = block_loads(b, qb, flow, alpha0)
+    xys = [b.xy for b in blocks] if xys is None else xys
+    qs = split(blocks, q)
+    wes, nbr = _halos(blocks, qs, flow, cuts, alpha0, xys)
+    for b, qb, xy, we, nc in zip(blocks, qs, xys, wes, nbr):
+        L = block_loads(b, qb, flow, alpha0, xy, we, nc)
         acc[b.body_id] = L if acc[b.body_id] is None else acc[b.body_id] + L
     out = []
     for L in acc:
@@ -730,7 +830,8 @@ def harmonics(c: torch.Tensor) -> torch.Tensor:
 # ---------------------------------------------------------------------------
 # Reverse mode (for checking the adjoint)
 # ---------------------------------------------------------------------------
-def residual_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, rbar: torch.Tensor):
+def residual_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, rbar: torch.Tensor,
+                 cuts=()):
     """Products of the transposed Jacobians of R* (all blocks) with rbar, by
     automatic differentiation of this module's residual: returns
     (qbar, [xybar per block], alpha0bar).  Pinned against central finite
@@ -738,15 +839,11 @@ def residual_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, rbar: to
     qv = q.detach().clone().requires_grad_(True)
     xys = [b.xy.detach().clone().requires_grad_(True) for b in blocks]
     a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
-    parts = [residual(b, qb, flow, solver, alpha0=a0, xy=xy)
-             for b, qb, xy in zip(blocks, split(blocks, qv), xys)]
-    (join(parts) * rbar).sum().backward()
+    (residual_all(blocks, qv, flow, solver, cuts, a0, xys) * rbar).sum().backward()
     return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()
 
 
-def residual_with(blocks, q, flow, solver, xys=None, alpha0=None):
+def residual_with(blocks, q, flow, solver, xys=None, alpha0=None, cuts=()):
     """R* of all blocks with node coordinates and/or alpha0 overridden."""
-    xys = [b.xy for b in blocks] if xys is None else xys
     a0 = None if alpha0 is None else torch.as_tensor(alpha0, dtype=DT)
-    return join([residual(b, qb, flow, solver, alpha0=a0, xy=xy)
-                 for b, qb, xy in zip(blocks, split(blocks, q), xys)])
+    return residual_all(blocks, q, flow, solver, cuts, a0, xys)

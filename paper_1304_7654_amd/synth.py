@@ -106,6 +106,7 @@ class Problem:
     seed: int
     design: Optional[dict] = None        # Hicks-Henne data (cfg4)
     notes: str = ""
+    cuts: List[Tuple[int, int, int, int]] = field(default_factory=list)
 
     @property
     def cell_snapshots(self) -> int:
@@ -297,6 +298,58 @@ def split_state(problem: Problem, q: np.ndarray) -> List[np.ndarray]:
     for b, o in zip(problem.blocks, block_offsets(problem)):
         res.append(q[o:o + b.n_state].reshape(b.ns, 4, b.nj, b.ni))
     return res
+
+
+def split_problem(problem: Problem, parts_i: int, parts_j: int):
+    """Cut every block into parts_i x parts_j pieces glued by cuts (sides
+    0..3 = imin, imax, jmin, jmax; a cut is (block_a, side_a, block_b,
+    side_b), imax of a to imin of b or jmax of a to jmin of b).  A periodic
+    side of a block that is cut along that direction becomes a cut between
+    its first and last pieces.  Pieces are numbered block by block, j-piece
+    major.  Returns (problem, perm) with state_split = state[perm].  A C-grid
+    (wake-cut jmin) can only be cut along j."""
+    blocks, cuts, perm = [], [], []
+    off = 0
+    for b in problem.blocks:
+        if parts_i > 1 and b.bc[2] == WAKECUT:
+            raise ValueError("a wake-cut block can only be split along j")
+        ib = [round(k * b.ni / parts_i) for k in range(parts_i + 1)]
+        jb = [round(k * b.nj / parts_j) for k in range(parts_j + 1)]
+        base = len(blocks)
+        idx = lambda pi, pj: base + pj * parts_i + pi
+        for pj in range(parts_j):
+            for pi in range(parts_i):
+                i0, i1, j0, j1 = ib[pi], ib[pi + 1], jb[pj], jb[pj + 1]
+                bc = list(b.bc)
+                if parts_i > 1:
+                    if pi > 0 or b.bc[0] == PERIODIC:
+                        bc[0] = CUT
+                    if pi < parts_i - 1 or b.bc[1] == PERIODIC:
+                        bc[1] = CUT
+                if parts_j > 1:
+                    if pj > 0 or b.bc[2] == PERIODIC:
+                        bc[2] = CUT
+                    if pj < parts_j - 1 or b.bc[3] == PERIODIC:
+                        bc[3] = CUT
+                wake = b.wake_ncells if bc[2] == WAKECUT else 0
+                xy = np.ascontiguousarray(b.xy[:, j0:j1 + 1, i0:i1 + 1])
+                blocks.append(Block(i1 - i0, j1 - j0, b.n_harm, xy, tuple(bc), wake, b.body_id))
+                n, v, j, i = np.meshgrid(np.arange(b.ns), np.arange(4), np.arange(j0, j1),
+                                         np.arange(i0, i1), indexing="ij")
+                perm.append((off + ((n * 4 + v) * b.nj + j) * b.ni + i).reshape(-1))
+                if pi + 1 < parts_i:
+                    cuts.append((idx(pi, pj), 1, idx(pi + 1, pj), 0))
+                elif parts_i > 1 and b.bc[1] == PERIODIC:
+                    cuts.append((idx(pi, pj), 1, idx(0, pj), 0))
+                if pj + 1 < parts_j:
+                    cuts.append((idx(pi, pj), 3, idx(pi, pj + 1), 2))
+                elif parts_j > 1 and b.bc[3] == PERIODIC:
+                    cuts.append((idx(pi, 0), 2, idx(pi, pj), 3))
+        off += b.n_state
+    out = Problem(problem.name + "_split%dx%d" % (parts_i, parts_j), blocks, problem.flow,
+                  problem.solver, problem.n_iter, problem.seed, problem.design, problem.notes,
+                  cuts)
+    return out, np.concatenate(perm)
 
 
 # --------------------------------------------------------------------------

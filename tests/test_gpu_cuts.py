@@ -1,0 +1,101 @@
+"""GPU parity on grids cut into glued blocks (the multi-block halo of the
+paper, §MPI Optimisations): the HIP library on the split grid against the
+FP64 oracle on the same split grid, and against the HIP library on the
+uncut grid, for the residual, the pseudo-time iteration, the forces and
+the reverse-mode residual."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hb_oracle as O
+from paper_1304_7654_amd import hb, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+CASES = [("cyl_tiny", 2, 2), ("naca_tiny", 1, 2), ("cyl64x32_nh1", 3, 2)]
+PATHS = [(0, 0), (0, 1), (1, 1)]          # (precision, batched)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+def _setup(name, pi, pj):
+    p = synth.make_problem(name)
+    p.flow.alpha0 = 0.03
+    sp, perm = synth.split_problem(p, pi, pj)
+    q = torch.as_tensor(synth.initial_state(p))
+    return p, sp, torch.as_tensor(perm), q
+
+
+@pytest.mark.parametrize("prec,batched", PATHS)
+@pytest.mark.parametrize("name,pi,pj", CASES)
+def test_split_residual(name, pi, pj, prec, batched):
+    _say("cuts residual", name, pi, pj, "prec", prec, "batched", batched)
+    p, sp, perm, q = _setup(name, pi, pj)
+    sblocks, flow, solver = O.from_synth(sp)
+    ref = O.residual_all(sblocks, q[perm], flow, solver, sp.cuts)
+    gs = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=prec, batched=batched)
+    g1 = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
+    rs = gs.residual(q[perm].to(DEV)).cpu()
+    r1 = g1.residual(q.to(DEV)).cpu()[perm]
+    torch.cuda.synchronize()
+    e_or, e_un = _rel(rs, ref), _rel(rs, r1)
+    _say("  rel vs oracle", e_or, "vs uncut", e_un)
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert e_or <= tol
+    assert e_un <= (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec,batched", PATHS)
+def test_split_iteration_and_forces(prec, batched):
+    name, pi, pj = "cyl64x32_nh1", 3, 2
+    _say("cuts RK", name, "prec", prec, "batched", batched)
+    p, sp, perm, q = _setup(name, pi, pj)
+    sblocks, flow, solver = O.from_synth(sp)
+    n_it = 3
+    qref, nref = O.rk_iterate(sblocks, q[perm], flow, solver, n_it, sp.cuts)
+    gs = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=prec, batched=batched)
+    qd = q[perm].contiguous().to(DEV)
+    norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    cf = torch.zeros(gs.n_forces, dtype=torch.float64, device=DEV)
+    gs.rk_iterate(qd, n_it, norms, cf)
+    torch.cuda.synchronize()
+    assert gs.status() == hb.HB_OK
+    dq = _rel(qd.cpu() - q[perm], qref - q[perm])
+    dn = float(((norms.cpu() - nref).abs() / nref).max())
+    cref = torch.cat([c.reshape(-1) for c in O.forces(sblocks, qref, flow, solver,
+                                                       cuts=sp.cuts)])
+    dc = float((cf.cpu() - cref).abs().max() / cref.abs().max())
+    _say("  state", dq, "norms", dn, "forces", dc)
+    assert dq <= (1e-11 if prec == 0 else 1e-5)
+    assert dn <= (1e-12 if prec == 0 else 1e-5)
+    assert dc <= (1e-10 if prec == 0 else 1e-4)
+
+
+@pytest.mark.parametrize("name,pi,pj", CASES[:2])
+def test_split_adjoint(name, pi, pj):
+    _say("cuts adjoint", name, pi, pj)
+    p, sp, perm, q = _setup(name, pi, pj)
+    sblocks, flow, solver = O.from_synth(sp)
+    rbar = torch.randn(q.shape, generator=torch.Generator().manual_seed(9), dtype=torch.float64)
+    qs = q[perm].contiguous()
+    rbs = rbar[perm].contiguous()
+    qref, xref, aref = O.residual_vjp(sblocks, qs, flow, solver, rbs, sp.cuts)
+    gs = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=0, batched=1)
+    xyb = torch.empty(gs.n_xy, dtype=torch.float64, device=DEV)
+    ab = torch.empty(1, dtype=torch.float64, device=DEV)
+    qb = gs.residual_adjoint(qs.to(DEV), rbs.to(DEV), None, xyb, ab)
+    torch.cuda.synchronize()
+    xr = torch.cat([x.reshape(-1) for x in xref])
+    _say("  qbar", _rel(qb.cpu(), qref), "xybar", _rel(xyb.cpu(), xr), "alpha",
+         float(ab), float(aref))
+    assert _rel(qb.cpu(), qref) <= 1e-11
+    assert _rel(xyb.cpu(), xr) <= 1e-11
+    assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
