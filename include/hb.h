@@ -173,11 +173,33 @@ int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
 int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar,
                         double *qbar, double *xybar, double *flowbar, void *stream);
 
-/* Reverse-mode products of the force coefficients: with cfbar of the
- * hb_forces layout, qbar/xybar/flowbar receive (d cf/d .)^T cfbar
- * (overwritten; xybar and flowbar may be NULL). */
+/* Reverse-mode products of the force coefficients of hb_forces (the
+ * paper's per-body, per-snapshot cl/cd/cm, §MPI Optimisations, force
+ * reduction): with cfbar of the hb_forces layout (device), qbar (device,
+ * state size), xybar (device, hb_xy_size(), may be NULL) and flowbar
+ * (device, 1 double: d/d alpha0, may be NULL) receive (d cf / d .)^T cfbar,
+ * overwritten.  Only wall faces contribute; alpha0 enters through the wind
+ * axes and the far-field ghosts.  FP64 arithmetic on any grid.  qbar must
+ * not alias q. */
 int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
                       double *qbar, double *xybar, double *flowbar, void *stream);
+
+/* Adjoint pseudo-time iteration at a fixed (converged) state q: n_iter
+ * iterations in place on lambda of
+ *   lambda(k) = lambda(0) - a_k (dtau/V) (J_Q^T lambda(k-1) + gq),
+ * the multistage scheme of hb_rk_iterate (the paper's Runge-Kutta step,
+ * §MPI Optimisations) with the same coefficients and the same local steps
+ * dtau(q), so it converges as the forward iteration does, to
+ * J_Q^T lambda = -gq.  With gq = (dJ/dQ)^T of an objective J, the total
+ * derivative of J at a steady state is dJ/dX + lambda^T (d R* / d X) (X = node
+ * coordinates or alpha0: hb_residual_adjoint with rbar = lambda).
+ * q, gq: device, state size, read only; lambda: device, state size, in/out
+ * (must alias neither); resnorm (device, n_iter doubles, may be NULL): RMS
+ * over cells, snapshots and variables of (J_Q^T lambda + gq)/V at the first
+ * stage of each iteration.  FP64 grids only (HB_ERR_UNSUPPORTED otherwise).
+ * Scratch of 2.25 state sizes is allocated on the first call. */
+int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
+                       int32_t n_iter, double *resnorm, void *stream);
 
 /* Replace the node coordinates (device, hb_xy_size() doubles, same layout as
  * the blocks' xy, concatenated) and recompute the metrics on `stream`. */

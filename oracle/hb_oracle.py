@@ -843,6 +843,26 @@ def residual_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, rbar: to
     return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()
 
 
+def forces_vjp(blocks, q: torch.Tensor, flow: OFlow, solver: OSolver, cfbar: torch.Tensor,
+               cuts=()):
+    """Products of the transposed Jacobians of the force coefficients (all
+    bodies, [body][n][3] flattened) with cfbar, by automatic differentiation
+    of forces(): returns (qbar, [xybar per block], alpha0bar)."""
+    qv = q.detach().clone().requires_grad_(True)
+    xys = [b.xy.detach().clone().requires_grad_(True) for b in blocks]
+    a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
+    cf = torch.cat([c.reshape(-1) for c in forces(blocks, qv, flow, solver, a0, cuts, xys)])
+    (cf * cfbar).sum().backward()
+    return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()
+
+
+def forces_with(blocks, q, flow, solver, xys=None, alpha0=None, cuts=()):
+    """Force coefficients (flattened [body][n][3]) with node coordinates
+    and/or alpha0 overridden."""
+    a0 = None if alpha0 is None else torch.as_tensor(alpha0, dtype=DT)
+    return torch.cat([c.reshape(-1) for c in forces(blocks, q, flow, solver, a0, cuts, xys)])
+
+
 def residual_with(blocks, q, flow, solver, xys=None, alpha0=None, cuts=()):
     """R* of all blocks with node coordinates and/or alpha0 overridden."""
     a0 = None if alpha0 is None else torch.as_tensor(alpha0, dtype=DT)

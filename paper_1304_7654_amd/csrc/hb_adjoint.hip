@@ -23,6 +23,14 @@
 //  7. node coordinates: the metric adjoints (S, d per face, V per cell) are
 //     chained to the nodes with FP64 atomic adds (summation order, hence the
 //     last bits of xybar, may vary from run to run).
+//
+// The force coefficients are a functional of the wall faces only (jmin,
+// j = 0): the adjoint of the wall-cell pressure, of the wall-face viscous
+// flux and of the face normal are written into the same per-face records
+// (all other records are zero), the face-midpoint moment arms go to the
+// nodes directly, and steps 3-7 run unchanged without the HB source and cell
+// area terms.  The incidence also enters through the wind axes:
+// d cd / d alpha0 = cl and d cl / d alpha0 = -cd.
 #include "hb_device.hpp"
 
 #include <vector>
@@ -293,8 +301,8 @@ __global__ void k_adj_fold(const BlockDesc *blks, int b, const double *q, const 
         const W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane], gm1);
         double qb[4];
         prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
-        // HB source: d/dQ_n of sum_m rbar_m V D[m][n] Q_n
-        for (int v = 0; v < 4; ++v) {
+        // HB source: d/dQ_n of sum_m rbar_m V D[m][n] Q_n (none for the forces)
+        for (int v = 0; v < 4 && rbar; ++v) {
             double sacc = 0.0;
             for (int m = 0; m < B.ns; ++m)
                 sacc += dm[m * kNsPad + n] * rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t];
@@ -529,6 +537,183 @@ __global__ void k_adj_xy_vol(const BlockDesc *blks, int b, const double *q, cons
     xadd(xb, k2, h * (y[k3] - y[k1]));
 }
 
+// ---- force coefficients ------------------------------------------------------
+__device__ inline bool wall_face(const BlockDesc &B, int i) {
+    if (B.bc[2] == HB_BC_WALL) return true;
+    if (B.bc[2] == HB_BC_WAKECUT) return i >= B.wake && i < B.ni - B.wake;
+    return false;
+}
+
+struct ForceAdj {
+    const double *cfbar;      // [body][n][3] = (cl, cd, cm) adjoints
+    const int *body_off;      // first entry of each body in cf
+    double ca, sa;            // cos / sin of alpha0
+    double qinf_l, qinf_l2;   // q_inf L, q_inf L^2
+    double xm, ym;            // moment reference point
+};
+
+// One thread per jmin face and snapshot: the per-face record of the wall
+// loads (zero for faces that are not wall), and the moment-arm adjoints.
+// Face (i, 0): line cells (i, -2), (i, -1) [ghost, L], (i, 0) [wall cell, R],
+// (i, 1); slot 0 = node (i+1, 0), slot 1 = node (i, 0), as in k_adj_face_j.
+__global__ void k_adj_force_face(const BlockDesc *blks, int b, const double *ext, const double *xy,
+                                 const double *SJ, const double *dJ, ForceAdj fa, Consts c,
+                                 double *AF, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int64_t nf = (int64_t)B.ni * (B.nj + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)B.ni * B.ns) return;
+    const int n = (int)(t / B.ni), i = (int)(t % B.ni);
+    if (!wall_face(B, i)) return;
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
+    const int col = i + 2;
+    const int64_t r1 = we, r2 = 2 * (int64_t)we;          // rows of cells j = -1 and j = 0
+    const double g = c.gamma;
+    const W4<double> wL = ldw(e, plane, r1 + col), wR = ldw(e, plane, r2 + col);
+    const UVT<double> uL = uvt(wL, g), uR = uvt(wR, g);
+    const UVT<double> nA = avg4(uvt(ldw(e, plane, r1 + col - 1), g), uL,
+                                uvt(ldw(e, plane, r2 + col - 1), g), uR);          // node (i, 0)
+    const UVT<double> nB = avg4(uL, uvt(ldw(e, plane, r1 + col + 1), g), uR,
+                                uvt(ldw(e, plane, r2 + col + 1), g));              // node (i+1, 0)
+    const double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
+    const double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    double fv[3];
+    viscous_flux(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fv);
+    const double dp = wR.p - c.pinf;
+    const double fx = -dp * sx + fv[0], fy = -dp * sy + fv[1];
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    const double mx = 0.5 * (x[i] + x[i + 1]) - fa.xm, my = 0.5 * (y[i] + y[i + 1]) - fa.ym;
+    // coefficient adjoints -> (Fx, Fy, Mz) adjoints of this body and snapshot
+    const double *cb = fa.cfbar + fa.body_off[B.body] + 3 * n;
+    const double Fxb = (-cb[0] * fa.sa + cb[1] * fa.ca) / fa.qinf_l;
+    const double Fyb = (cb[0] * fa.ca + cb[1] * fa.sa) / fa.qinf_l;
+    const double Mzb = -cb[2] / fa.qinf_l2;
+    // Mz = mx fy - my fx
+    const double fxb = Fxb - my * Mzb, fyb = Fyb + mx * Mzb;
+    if (xyb) {
+        const double mxb = 0.5 * Mzb * fy, myb = -0.5 * Mzb * fx;
+        double *xb = xyb + 2 * B.node_off, *yb = xb + nn;
+        xadd(xb, i, mxb);
+        xadd(xb, i + 1, mxb);
+        xadd(yb, i, myb);
+        xadd(yb, i + 1, myb);
+    }
+    const double fvb[3] = {fxb, fyb, 0.0};
+    UVT<double> uLb{0, 0, 0}, uRb{0, 0, 0}, Pb{0, 0, 0}, Qb{0, 0, 0};
+    double sxb = -dp * fxb, syb = -dp * fyb, dxb = 0.0, dyb = 0.0;
+    viscous_flux_rev(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
+                     dxb, dyb);
+    W4<double> w1{0, 0, 0, 0}, w2{0, 0, 0, -(fxb * sx + fyb * sy)};
+    uvt_rev(wL, uLb, g, w1);
+    uvt_rev(wR, uRb, g, w2);
+    double *o = AF + B.afj_off + (int64_t)n * kAF * nf + i;    // face (i, 0)
+    const double cm1[4] = {w1.r, w1.u, w1.v, w1.p}, cp0[4] = {w2.r, w2.u, w2.v, w2.p};
+    for (int v = 0; v < 4; ++v) {
+        o[(4 + v) * nf] = cm1[v];
+        o[(8 + v) * nf] = cp0[v];
+    }
+    o[16 * nf] = Pb.u;
+    o[17 * nf] = Pb.v;
+    o[18 * nf] = Pb.t;
+    o[19 * nf] = Qb.u;
+    o[20 * nf] = Qb.v;
+    o[21 * nf] = Qb.t;
+    o[22 * nf] = sxb;
+    o[23 * nf] = syb;
+    o[24 * nf] = dxb;
+    o[25 * nf] = dyb;
+}
+
+// alpha0 through the wind axes: sum over entries of cdbar * cl - clbar * cd
+__global__ void k_adj_force_axes(const double *cf, const double *cfbar, int n, double *out) {
+    __shared__ double red[kBS];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += kBS) acc += cfbar[3 * k + 1] * cf[3 * k] - cfbar[3 * k] * cf[3 * k + 1];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---- adjoint pseudo-time iteration --------------------------------------------
+// dtau / V per cell and snapshot of the (fixed) state q: the forward
+// iteration's local step, laid out like one variable of the state.
+__global__ void k_adj_dtv(const BlockDesc *blks, int b, const double *q, const double *SI,
+                          const double *SJ, const double *V, Consts c, double *dtv) {
+    const BlockDesc &B = blks[b];
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
+    const int W = B.ni + 1;
+    const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
+    const int64_t fi0 = (int64_t)j * W + i;
+    const double vol = V[B.cell_off + t];
+    const double sxi = 0.5 * (SI[2 * B.fi_off + fi0] + SI[2 * B.fi_off + fi0 + 1]);
+    const double syi = 0.5 * (SI[2 * B.fi_off + nfi + fi0] + SI[2 * B.fi_off + nfi + fi0 + 1]);
+    const double sxj = 0.5 * (SJ[2 * B.fj_off + t] + SJ[2 * B.fj_off + t + B.ni]);
+    const double syj = 0.5 * (SJ[2 * B.fj_off + nfj + t] + SJ[2 * B.fj_off + nfj + t + B.ni]);
+    for (int n = 0; n < B.ns; ++n) {
+        const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
+        const W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane],
+                                                    c.gamma - 1.0);
+        const double dt = local_dt<double>(w, sxi, syi, sxj, syj, vol, c.gamma, c.mu / c.prandtl,
+                                           c.cfl, B.omega_nh);
+        dtv[B.q_off / 4 + (int64_t)n * plane + t] = dt / vol;
+    }
+}
+
+// lam = lam0 - alpha (dtau/V) (J^T lam_in + gq); at the first stage the
+// workgroup's partial sum of ((J^T lam_in + gq) / V)^2 goes to part[blockIdx.x].
+__global__ void k_adj_rk(const BlockDesc *blks, int b, const double *lam0, const double *qbar,
+                         const double *gq, const double *dtv, const double *V, double alpha,
+                         double *lam, double *part) {
+    const BlockDesc &B = blks[b];
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (t < plane) {
+        const double iv = 1.0 / V[B.cell_off + t];
+        for (int n = 0; n < B.ns; ++n) {
+            const double f = alpha * dtv[B.q_off / 4 + (int64_t)n * plane + t];
+            for (int v = 0; v < 4; ++v) {
+                const int64_t o = B.q_off + ((int64_t)n * 4 + v) * plane + t;
+                const double r = qbar[o] + gq[o];
+                lam[o] = lam0[o] - f * r;
+                acc += (r * iv) * (r * iv);
+            }
+        }
+    }
+    if (!part) return;
+    __shared__ double red[kBS];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adj_norm(const double *part, int64_t n, double inv_count, double *out) {
+    __shared__ double red[kBS];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += kBS) acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0] * inv_count);
+}
+
 // ---- host: inverse of the ghost rules ----------------------------------------
 struct GSrc {
     int cell;    // 1: an interior cell, 0: the far field
@@ -635,7 +820,8 @@ int adjoint_setup(hb_grid *g) {
     rc = rc ? rc : alloc(&g->AFJ_d, g->n_afj);
     rc = rc ? rc : alloc(&g->NB_d, g->n_nodeq);
     rc = rc ? rc : alloc(&g->WBext_d, g->n_ext);
-    rc = rc ? rc : alloc(&g->adj_part_d, g->nblocks);
+    rc = rc ? rc : alloc(&g->adj_part_d, g->nblocks + 1);
+    rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
     return rc;
 }
@@ -691,9 +877,113 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     return check_hip(hipGetLastError(), "adjoint launch");
 }
 
-int launch_forces_adjoint(hb_grid *, const double *, const double *, double *, double *, double *,
-                          hipStream_t) {
-    return fail(HB_ERR_UNSUPPORTED, "forces adjoint not built");
+// Adjoint pseudo-time iteration for (dR*/dQ)^T lam = -gq at a fixed state q:
+// the forward multistage scheme with the same frozen local steps,
+//   lam(k) = lam(0) - alpha_k (dtau/V) (J^T lam(k-1) + gq),
+// whose iteration matrix has the eigenvalues of the forward linearisation.
+// resnorm[it] = RMS over cells, snapshots and variables of (J^T lam + gq)/V
+// at the first stage.
+int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const double *gq,
+                           int n_iter, double *resnorm, hipStream_t s) {
+    int rc = adjoint_setup(g);
+    if (rc) return rc;
+    if (!g->it_lam0_d) {
+        int64_t np = 0;
+        for (int b = 0; b < g->nblocks; ++b) np += nblk((int64_t)g->blk[b].ni * g->blk[b].nj);
+        g->n_it_part = np;
+        auto alloc = [&](double **p, int64_t n) {
+            return check_hip(hipMalloc((void **)p, sizeof(double) * std::max<int64_t>(1, n)),
+                             "adjoint iteration alloc");
+        };
+        rc = alloc(&g->it_lam0_d, g->n_state);
+        rc = rc ? rc : alloc(&g->it_qbar_d, g->n_state);
+        rc = rc ? rc : alloc(&g->it_dtv_d, g->n_state / 4);
+        rc = rc ? rc : alloc(&g->it_part_d, np);
+        if (rc) return rc;
+    }
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_dtv, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+                           q, g->SI_d, g->SJ_d, g->V_d, g->consts, g->it_dtv_d);
+    }
+    const int ns = g->solver.n_stages;
+    for (int it = 0; it < n_iter; ++it) {
+        rc = check_hip(hipMemcpyAsync(g->it_lam0_d, lam, sizeof(double) * g->n_state,
+                                      hipMemcpyDeviceToDevice, s), "lambda copy");
+        if (rc) return rc;
+        for (int k = 0; k < ns; ++k) {
+            rc = launch_residual_adjoint(g, q, lam, g->it_qbar_d, nullptr, nullptr, s);
+            if (rc) return rc;
+            int64_t po = 0;
+            const bool norm = (k == 0) && resnorm;
+            for (int b = 0; b < g->nblocks; ++b) {
+                const BlockDesc &B = g->blk[b];
+                const unsigned nb = nblk((int64_t)B.ni * B.nj);
+                hipLaunchKernelGGL(k_adj_rk, dim3(nb), dim3(kBS), 0, s, g->blk_d, b, g->it_lam0_d,
+                                   g->it_qbar_d, gq, g->it_dtv_d, g->V_d, g->solver.rk_alpha[k], lam,
+                                   norm ? g->it_part_d + po : nullptr);
+                po += nb;
+            }
+            if (norm)
+                hipLaunchKernelGGL(k_adj_norm, dim3(1), dim3(kBS), 0, s, g->it_part_d, g->n_it_part,
+                                   1.0 / (double)g->n_state, resnorm + it);
+        }
+    }
+    return check_hip(hipGetLastError(), "adjoint iteration launch");
+}
+
+int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
+                          double *xybar, double *flowbar, hipStream_t s) {
+    int rc = adjoint_setup(g);
+    if (rc) return rc;
+    double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
+    const Consts c = g->consts;
+    const double qinf = 0.5 * g->flow.mach * g->flow.mach, L = g->flow.l_ref;
+    const ForceAdj fa{cfbar, g->body_off_d, cos(g->flow.alpha0), sin(g->flow.alpha0), qinf * L,
+                      qinf * L * L, g->flow.x_mom, g->flow.y_mom};
+    if (xybar)
+        hipLaunchKernelGGL(k_zero, dim3(nblk(2 * g->n_nodes)), dim3(kBS), 0, s, xybar, 2 * g->n_nodes);
+    hipLaunchKernelGGL(k_zero, dim3(nblk(g->n_afi)), dim3(kBS), 0, s, g->AFI_d, g->n_afi);
+    hipLaunchKernelGGL(k_zero, dim3(nblk(g->n_afj)), dim3(kBS), 0, s, g->AFJ_d, g->n_afj);
+    for (int b = 0; b < g->nblocks; ++b) {
+        rc = plain_ghost_fill(g, b, q, ext, s);
+        if (rc) return rc;
+    }
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_force_face, dim3(nblk((int64_t)B.ni * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, ext, g->xy_d, g->SJ_d, g->dJ_d, fa, c, g->AFJ_d, xybar);
+        hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
+                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d);
+        hipLaunchKernelGGL(k_adj_cells, dim3(nblk((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
+                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d);
+    }
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+                           q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
+                           g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, c, qbar);
+    }
+    if (flowbar) {
+        for (int b = 0; b < g->nblocks; ++b)
+            hipLaunchKernelGGL(k_adj_alpha, dim3(1), dim3(kBS), 0, s, g->blk_d, b, g->WBext_d,
+                               g->ff_ptr_d, g->ff_p_d, g->ff_m_d, g->ffw_d, g->adj_part_d);
+        rc = launch_forces(g, q, g->cf_adj_d, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_adj_force_axes, dim3(1), dim3(kBS), 0, s, g->cf_adj_d, cfbar,
+                           (int)(g->n_forces / 3), g->adj_part_d + g->nblocks);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->nblocks + 1, flowbar);
+    }
+    if (xybar) {
+        for (int b = 0; b < g->nblocks; ++b) {
+            const BlockDesc &B = g->blk[b];
+            hipLaunchKernelGGL(k_adj_xy_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj)), dim3(kBS), 0, s,
+                               g->blk_d, b, g->AFI_d, g->xy_d, g->C_d, xybar);
+            hipLaunchKernelGGL(k_adj_xy_j, dim3(nblk((int64_t)B.ni * (B.nj + 1))), dim3(kBS), 0, s,
+                               g->blk_d, b, g->AFJ_d, g->xy_d, g->C_d, xybar);
+        }
+    }
+    return check_hip(hipGetLastError(), "forces adjoint launch");
 }
 
 }  // namespace hb

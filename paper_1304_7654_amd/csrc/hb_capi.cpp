@@ -76,6 +76,8 @@ void free_all(hb_grid *g) {
     dfree(g->fold_ptr_d); dfree(g->fold_b_d); dfree(g->fold_p_d); dfree(g->fold_m_d);
     dfree(g->ff_ptr_d); dfree(g->ff_p_d); dfree(g->ff_m_d);
     dfree(g->ext_adj_d);
+    dfree(g->cf_adj_d);
+    dfree(g->it_lam0_d); dfree(g->it_qbar_d); dfree(g->it_dtv_d); dfree(g->it_part_d);
 }
 
 bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_WAKECUT; }
@@ -479,6 +481,17 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *
     if (!g || !q || !cfbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
     if (qbar == q) return fail(HB_ERR_ARG, "qbar must not alias q");
     return launch_forces_adjoint(g, q, cfbar, qbar, xybar, flowbar, (hipStream_t)stream);
+}
+
+int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
+                       int32_t n_iter, double *resnorm, void *stream) {
+    g_err.clear();
+    if (!g || !q || !lambda || !gq) return fail(HB_ERR_ARG, "NULL argument");
+    if (n_iter < 0) return fail(HB_ERR_ARG, "n_iter must be >= 0");
+    if (lambda == q || lambda == gq) return fail(HB_ERR_ARG, "lambda must not alias q or gq");
+    if (g->solver.precision != HB_FP64)
+        return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
 }
 
 int hb_set_xy(hb_grid *g, const double *xy, void *stream) {

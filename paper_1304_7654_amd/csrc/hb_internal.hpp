@@ -129,7 +129,11 @@ struct hb_grid {
     int64_t n_adj = 0;
     int64_t n_afi = 0, n_afj = 0, n_nodeq = 0;
     double *AFI_d = nullptr, *AFJ_d = nullptr, *NB_d = nullptr, *WBext_d = nullptr;
-    double *adj_part_d = nullptr;         // alpha0 partials, one per block
+    double *adj_part_d = nullptr;         // alpha0 partials, one per block + 1
+    double *cf_adj_d = nullptr;           // forward force coefficients (forces adjoint)
+    // adjoint pseudo-time iteration scratch (allocated on first use)
+    double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
+    int64_t n_it_part = 0;
     int *fold_ptr_d = nullptr, *fold_b_d = nullptr, *fold_p_d = nullptr, *fold_m_d = nullptr;
     int *ff_ptr_d = nullptr, *ff_p_d = nullptr, *ff_m_d = nullptr;
     double *ext_adj_d = nullptr;          // ghost-extended primitives for the adjoint
@@ -163,6 +167,8 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
                             double *xybar, double *flowbar, hipStream_t s);
 int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
                           double *xybar, double *flowbar, hipStream_t s);
+int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const double *gq,
+                           int n_iter, double *resnorm, hipStream_t s);
 
 // instrumentation (capi.cpp): event pair around one stage, or no-op
 int prof_begin(hb_grid *g, hipStream_t s, hipEvent_t *end);

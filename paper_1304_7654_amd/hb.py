@@ -22,7 +22,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORT
 HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
 
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
     L.hb_forces.argtypes = [vp, vp, vp, vp]
     L.hb_residual_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hb_forces_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.hb_adjoint_iterate.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.hb_set_xy.argtypes = [vp, vp, vp]
     L.hb_set_alpha0.argtypes = [vp, dp]
     L.hb_get_status.argtypes = [vp]
@@ -207,6 +208,15 @@ class Grid:
                                        _ptr(xybar, self.n_xy, "xybar"),
                                        _ptr(flowbar, 1, "flowbar"), _stream()))
         return qbar
+
+    def adjoint_iterate(self, q, lam, gq, n_iter: int, resnorm=None):
+        """n_iter adjoint pseudo-time iterations in place on lam towards
+        J_Q^T lam = -gq at the state q."""
+        _check(lib().hb_adjoint_iterate(self.h, _ptr(q, self.n_state, "q"),
+                                        _ptr(lam, self.n_state, "lam"),
+                                        _ptr(gq, self.n_state, "gq"), int(n_iter),
+                                        _ptr(resnorm, n_iter, "resnorm"), _stream()))
+        return lam
 
     def set_xy(self, xy: torch.Tensor):
         _check(lib().hb_set_xy(self.h, _ptr(xy, self.n_xy, "xy"), _stream()))
