@@ -120,6 +120,23 @@ typedef struct {
     int32_t batched, graph_iters;
 } hb_solver;
 
+/* Launch configuration of the batched stage kernel (batched = 1).
+ *   tile_i:     threads along i per 256-thread workgroup, 16 or 32; the
+ *               output tile is tile_i x (256/tile_i - 1) cells
+ *   wg_per_cu:  resident workgroups per CU of the persistent grid
+ *               (0 = the occupancy maximum; larger values are capped by it)
+ *   xcd_order:  1 = renumber workgroups so that the workgroups of one XCD
+ *               (one L2) take consecutive tiles
+ *   tile_order: 0 = tiles of a block row by row, 1 = column by column
+ *   stage_ms:   measured mean stage time (output; 0 when not measured)
+ * The tuning changes which workgroup computes which tile, never a cell's
+ * arithmetic: states are bitwise identical across tunings with the same
+ * tile_i, and equal to rounding in the norm partial order otherwise. */
+typedef struct {
+    int32_t tile_i, wg_per_cu, xcd_order, tile_order;
+    double stage_ms;
+} hb_tuning;
+
 /* Build a grid: copies the host arrays, computes the metrics on the device
  * (FP64), allocates all scratch.  Validation (HB_ERR_ARG): nblocks >= 1,
  * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
@@ -200,6 +217,25 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
  * Scratch of 2.25 state sizes is allocated on the first call. */
 int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
                        int32_t n_iter, double *resnorm, void *stream);
+
+/* Autotune the batched stage kernel (the paper's per-block work, batched
+ * over blocks of uneven size and N_H in one launch per Runge-Kutta step,
+ * §MPI Optimisations): with cache_path (may be NULL) holding an entry for
+ * this device and workload and force = 0, apply it; otherwise time every
+ * candidate (tile_i in {16, 32} x tile_order in {0, 1} x xcd_order in
+ * {1, 0} x wg_per_cu in {max, 2, 1}) over full pseudo-time iterations on a
+ * scratch copy of q (device, state size, not modified), apply the fastest
+ * and, with cache_path, store it (JSON, one entry per device/workload key).
+ * out (host, may be NULL) receives the applied tuning.  Synchronises;
+ * allocates one state-size scratch buffer for the duration of the call.
+ * HB_ERR_UNSUPPORTED for a grid with batched = 0. */
+int hb_autotune(hb_grid *g, const double *q, const char *cache_path, int32_t force,
+                hb_tuning *out, void *stream);
+
+/* Apply (synchronises; a tile change rebuilds the tile list) or read the
+ * tuning of a batched grid. */
+int hb_set_tuning(hb_grid *g, const hb_tuning *t);
+int hb_get_tuning(const hb_grid *g, hb_tuning *t);
 
 /* Replace the node coordinates (device, hb_xy_size() doubles, same layout as
  * the blocks' xy, concatenated) and recompute the metrics on `stream`. */

@@ -386,8 +386,8 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     rc = rc ? rc : dalloc(&g->ctr_d, 1);
     rc = rc ? rc : dalloc(&g->body_off_d, nbody);
     rc = rc ? rc : dalloc(&g->body_ns_d, nbody);
-    if (!rc && !plain) rc = fused_build_tiles(g);
-    g->n_partials = plain ? part : g->n_tiles;
+    if (!rc && !plain) rc = fused_build_tiles(g, 16, 0);
+    g->n_partials = plain ? part : fused_max_tiles(g);
     rc = rc ? rc : dalloc(&g->partials_d, g->n_partials);
     if (rc) {
         free_all(g);
@@ -492,6 +492,28 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
+}
+
+int hb_autotune(hb_grid *g, const double *q, const char *cache_path, int32_t force,
+                hb_tuning *out, void *stream) {
+    g_err.clear();
+    if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");
+    if (!g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "tuning applies to batched grids");
+    return tune_run(g, q, cache_path, force, out, (hipStream_t)stream);
+}
+
+int hb_set_tuning(hb_grid *g, const hb_tuning *t) {
+    g_err.clear();
+    if (!g || !t) return fail(HB_ERR_ARG, "NULL argument");
+    if (!g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "tuning applies to batched grids");
+    return tune_set(g, t);
+}
+
+int hb_get_tuning(const hb_grid *g, hb_tuning *t) {
+    g_err.clear();
+    if (!g || !t) return fail(HB_ERR_ARG, "NULL argument");
+    if (!g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "tuning applies to batched grids");
+    return tune_get(g, t);
 }
 
 int hb_set_xy(hb_grid *g, const double *xy, void *stream) {

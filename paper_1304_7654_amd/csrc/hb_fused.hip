@@ -50,6 +50,7 @@ struct FusedArgs {
     double alpha;
     int norm;
     int dq_bytes;          // FP32: bytes of the LDS HB-source area before the scratch
+    int xcd;               // 1: XCD-aware workgroup renumbering
 };
 
 // Interior cell of any block as a primitive perturbation of snapshot n.
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     // multiple of 8, where the renumbering is a permutation.)
     const int G = gridDim.x;
     int v0 = blockIdx.x;
-    if (G % 8 == 0) v0 = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+    if (a.xcd && G % 8 == 0) v0 = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
     for (int t = v0; t < a.n_tiles; t += G) {
         const Tile tg = a.tiles[t];
         const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns)};
@@ -574,7 +575,9 @@ int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
         occ = nb;
         cached_sm[FIRST][MODE == 2] = sm;
     }
-    const int grid = std::max(1, std::min(g->n_tiles, g->n_cu * occ));
+    const int per_cu = g->tune_wg_per_cu > 0 ? std::min(g->tune_wg_per_cu, occ) : occ;
+    const int grid = std::max(1, std::min(g->n_tiles, g->n_cu * per_cu));
+    b.xcd = g->tune_xcd;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), sm, s, b);
     return check_hip(hipGetLastError(), "fused launch");
 }
@@ -666,35 +669,95 @@ int rk_graph(hb_grid *g, double *q, int n_iter, double *resnorm, T *sa, T *sb, h
 
 }  // namespace
 
-int fused_build_tiles(hb_grid *g) {
-    if (g->solver.n_stages < 2)
-        return fail(HB_ERR_UNSUPPORTED, "the fused path needs at least two Runge-Kutta stages");
-    const char *env = getenv("HB_TILE");
-    int ti = 16;
-    if (env) ti = atoi(env);
-    if (ti != 16 && ti != 32) ti = 16;
-    g->tile_ti = ti;
-    g->tile_tj = kThreads / ti - 1;        // output rows per tile
+namespace {
+std::vector<Tile> make_tiles(const hb_grid *g, int ti, int order) {
+    const int tj = kThreads / ti - 1;        // output rows per tile
     std::vector<Tile> tiles;
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
-        for (int j0 = 0; j0 < B.nj; j0 += g->tile_tj)
-            for (int i0 = 0; i0 < B.ni; i0 += g->tile_ti) tiles.push_back(Tile{b, i0, j0, B.ns});
+        if (order == 0) {
+            for (int j0 = 0; j0 < B.nj; j0 += tj)
+                for (int i0 = 0; i0 < B.ni; i0 += ti) tiles.push_back(Tile{b, i0, j0, B.ns});
+        } else {
+            for (int i0 = 0; i0 < B.ni; i0 += ti)
+                for (int j0 = 0; j0 < B.nj; j0 += tj) tiles.push_back(Tile{b, i0, j0, B.ns});
+        }
     }
     // heavier tiles first: the static stride then hands every workgroup a
     // similar mix of snapshot counts
     std::stable_sort(tiles.begin(), tiles.end(), [](const Tile &x, const Tile &y) { return x.ns > y.ns; });
-    g->n_tiles = (int)tiles.size();
+    return tiles;
+}
+}  // namespace
+
+// Largest tile list over the supported shapes (sizes the per-tile partials).
+int64_t fused_max_tiles(const hb_grid *g) {
+    return (int64_t)std::max(make_tiles(g, 16, 0).size(), make_tiles(g, 32, 0).size());
+}
+
+void fused_drop_graph(hb_grid *g) {
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+    g->graph_q = g->graph_norm = nullptr;
+}
+
+// Tile list of the given shape (tile_i threads along i: 16 or 32) and order;
+// synchronous upload.  Drops a captured graph (it holds the old list).
+int fused_build_tiles(hb_grid *g, int tile_i, int order) {
+    if (g->solver.n_stages < 2)
+        return fail(HB_ERR_UNSUPPORTED, "the fused path needs at least two Runge-Kutta stages");
+    if ((tile_i != 16 && tile_i != 32) || (order != 0 && order != 1))
+        return fail(HB_ERR_ARG, "tile_i must be 16 or 32 and tile_order 0 or 1");
+    const std::vector<Tile> tiles = make_tiles(g, tile_i, order);
     hipDeviceProp_t prop;
     int rc = check_hip(hipGetDeviceProperties(&prop, g->device), "device properties");
     if (rc) return rc;
     g->n_cu = prop.multiProcessorCount;
+    rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc) return rc;
+    fused_drop_graph(g);
     if (g->tiles_d) (void)hipFree(g->tiles_d);
     g->tiles_d = nullptr;
     rc = check_hip(hipMalloc((void **)&g->tiles_d, sizeof(Tile) * tiles.size()), "tiles alloc");
     if (rc) return rc;
-    return check_hip(hipMemcpy(g->tiles_d, tiles.data(), sizeof(Tile) * tiles.size(),
-                               hipMemcpyHostToDevice), "tiles upload");
+    rc = check_hip(hipMemcpy(g->tiles_d, tiles.data(), sizeof(Tile) * tiles.size(),
+                             hipMemcpyHostToDevice), "tiles upload");
+    if (rc) return rc;
+    g->tile_ti = tile_i;
+    g->tile_tj = kThreads / tile_i - 1;
+    g->tune_order = order;
+    g->n_tiles = (int)tiles.size();
+    return HB_OK;
+}
+
+// n_iter eager iterations (no graph, no norm output) on q; the mean time of
+// one stage launch in milliseconds, from HIP events around the whole run.
+int fused_time_iterations(hb_grid *g, double *q, int n_iter, double *ms_per_stage, hipStream_t s) {
+    hipEvent_t e0, e1;
+    int rc = check_hip(hipEventCreate(&e0), "event");
+    if (rc) return rc;
+    rc = check_hip(hipEventCreate(&e1), "event");
+    if (rc) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    const int prof = g->prof;
+    g->prof = 0;
+    rc = launch_reset_ctr(g->ctr_d, s);
+    rc = rc ? rc : check_hip(hipEventRecord(e0, s), "event record");
+    for (int it = 0; it < n_iter && !rc; ++it) {
+        if (g->solver.precision == HB_FP32_BULK) rc = one_iteration<float>(g, q, g->sa_f, g->sb_f, nullptr, s);
+        else rc = one_iteration<double>(g, q, g->qa_d, g->qb_d, nullptr, s);
+    }
+    rc = rc ? rc : check_hip(hipEventRecord(e1, s), "event record");
+    rc = rc ? rc : check_hip(hipEventSynchronize(e1), "event sync");
+    float ms = 0.0f;
+    rc = rc ? rc : check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    g->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) *ms_per_stage = (double)ms / std::max(1, n_iter * g->solver.n_stages);
+    return rc;
 }
 
 int fused_residual(hb_grid *g, const double *q, double *r, hipStream_t s) {

@@ -114,8 +114,13 @@ struct hb_grid {
     // fused path
     hb::Tile *tiles_d = nullptr;
     int n_tiles = 0;
-    int tile_ti = 32, tile_tj = 8;
+    int tile_ti = 16, tile_tj = 15;
     int n_cu = 0;
+    // tuning of the fused path (hb_set_tuning / hb_autotune)
+    int tune_wg_per_cu = 0;      // resident workgroups per CU, 0 = occupancy maximum
+    int tune_xcd = 1;            // XCD-aware workgroup renumbering
+    int tune_order = 0;          // 0: tiles row by row (j outer), 1: column by column
+    double tune_ms = 0.0;        // measured stage time of the applied tuning (0 = not measured)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     double *graph_q = nullptr, *graph_norm = nullptr;
@@ -155,7 +160,15 @@ int plain_residual(hb_grid *g, const double *q, double *r, hipStream_t s);
 int plain_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s);
 
 // fused.hip (batched tile kernel)
-int fused_build_tiles(hb_grid *g);
+int fused_build_tiles(hb_grid *g, int tile_i, int order);
+int64_t fused_max_tiles(const hb_grid *g);
+int fused_time_iterations(hb_grid *g, double *q, int n_iter, double *ms_per_stage, hipStream_t s);
+void fused_drop_graph(hb_grid *g);
+// tune.cpp
+int tune_get(const hb_grid *g, hb_tuning *t);
+int tune_set(hb_grid *g, const hb_tuning *t);
+int tune_run(hb_grid *g, const double *q, const char *cache_path, int force, hb_tuning *out,
+             hipStream_t s);
 int fused_residual(hb_grid *g, const double *q, double *r, hipStream_t s);
 int fused_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStream_t s);
 

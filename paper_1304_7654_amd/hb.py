@@ -22,7 +22,8 @@ HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORT
 HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_autotune", "hb_set_tuning",
+           "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
 
@@ -41,6 +42,15 @@ class c_block(ctypes.Structure):
 class c_cut(ctypes.Structure):
     _fields_ = [("blk_a", ctypes.c_int32), ("side_a", ctypes.c_int32), ("blk_b", ctypes.c_int32),
                 ("side_b", ctypes.c_int32), ("reversed", ctypes.c_int32)]
+
+
+class c_tuning(ctypes.Structure):
+    _fields_ = [("tile_i", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("xcd_order", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("stage_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class c_flow(ctypes.Structure):
@@ -81,6 +91,9 @@ def lib() -> ctypes.CDLL:
     L.hb_residual_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hb_forces_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hb_adjoint_iterate.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+    L.hb_autotune.argtypes = [vp, vp, ctypes.c_char_p, i32, ctypes.POINTER(c_tuning), vp]
+    L.hb_set_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
+    L.hb_get_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
     L.hb_set_xy.argtypes = [vp, vp, vp]
     L.hb_set_alpha0.argtypes = [vp, dp]
     L.hb_get_status.argtypes = [vp]
@@ -217,6 +230,25 @@ class Grid:
                                         _ptr(gq, self.n_state, "gq"), int(n_iter),
                                         _ptr(resnorm, n_iter, "resnorm"), _stream()))
         return lam
+
+    def autotune(self, q: torch.Tensor, cache_path: Optional[str] = None, force: bool = False):
+        """Time the launch configurations of the batched kernel on a scratch
+        copy of q, apply the fastest (or the cached choice); returns it."""
+        t = c_tuning()
+        _check(lib().hb_autotune(self.h, _ptr(q, self.n_state, "q"),
+                                 None if cache_path is None else cache_path.encode(),
+                                 1 if force else 0, ctypes.byref(t), _stream()))
+        return t.as_dict()
+
+    def set_tuning(self, tile_i: int = 16, wg_per_cu: int = 0, xcd_order: int = 1,
+                   tile_order: int = 0):
+        t = c_tuning(tile_i, wg_per_cu, xcd_order, tile_order, 0.0)
+        _check(lib().hb_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = c_tuning()
+        _check(lib().hb_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
 
     def set_xy(self, xy: torch.Tensor):
         _check(lib().hb_set_xy(self.h, _ptr(xy, self.n_xy, "xy"), _stream()))

@@ -44,6 +44,8 @@ int main(void) {
          offsetof(hb_block, wake_ncells), offsetof(hb_block, body_id));
   printf("%zu %zu %zu %zu\n", offsetof(hb_solver, rk_alpha), offsetof(hb_solver, precision),
          offsetof(hb_solver, limiter_eps), offsetof(hb_solver, graph_iters));
+  printf("%zu %zu %zu\n", sizeof(hb_tuning), offsetof(hb_tuning, tile_order),
+         offsetof(hb_tuning, stage_ms));
   return 0;
 }
 '''
@@ -59,7 +61,8 @@ int main(void) {
            hb.c_block.xy.offset, hb.c_block.bc.offset, hb.c_block.wake_ncells.offset,
            hb.c_block.body_id.offset,
            hb.c_solver.rk_alpha.offset, hb.c_solver.precision.offset,
-           hb.c_solver.limiter_eps.offset, hb.c_solver.graph_iters.offset]
+           hb.c_solver.limiter_eps.offset, hb.c_solver.graph_iters.offset,
+           ctypes.sizeof(hb.c_tuning), hb.c_tuning.tile_order.offset, hb.c_tuning.stage_ms.offset]
     assert got == ref
 
 

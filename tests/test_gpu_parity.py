@@ -148,15 +148,14 @@ def test_fused_rk_iterate(name, prec):
 
 
 def test_fused_deterministic_and_tile_independent():
-    """Repeated runs are bitwise identical; other tile shapes give the same
-    residual (each face flux is the same function of the same inputs)."""
-    import os
+    """Repeated runs are bitwise identical; the other tile shape gives the
+    same residual (each face flux is the same function of the same inputs)."""
     p = synth.make_problem("batch_tiny")
     q = torch.as_tensor(synth.initial_state(p)).to(DEV)
     outs = []
-    for tile in ("16", "32"):
-        os.environ["HB_TILE"] = tile
+    for tile in (16, 32):
         g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+        g.set_tuning(tile_i=tile)
         r1 = g.residual(q).clone()
         r2 = g.residual(q).clone()
         q1 = q.clone()
@@ -169,7 +168,6 @@ def test_fused_deterministic_and_tile_independent():
         assert torch.equal(r1, r2) and torch.equal(q1, q2) and torch.equal(n1, n2)
         outs.append(r1.cpu())
         g.close()
-    os.environ.pop("HB_TILE")
     for o in outs[1:]:
         rel = float((o - outs[0]).norm() / outs[0].norm())
         _say("  tile shape difference", rel, "bitwise" if torch.equal(o, outs[0]) else "")

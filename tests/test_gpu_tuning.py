@@ -1,0 +1,105 @@
+"""The batched kernel's launch configurations (tile shape, tile order,
+XCD-aware renumbering, resident workgroups per CU) and the autotuner that
+picks one: every configuration gives the same states, the autotuner applies
+the fastest and caches it per device and workload."""
+import json
+import os
+import tempfile
+
+import pytest
+import torch
+
+from paper_1304_7654_amd import hb, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run(g, q0, n_it=2):
+    q = q0.clone()
+    n = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    g.rk_iterate(q, n_it, n)
+    r = g.residual(q0)
+    torch.cuda.synchronize()
+    return q.cpu(), n.cpu(), r.cpu()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_tuning_gives_the_same_states(prec):
+    """Within a tile shape every configuration gives bitwise identical
+    states and residuals (norms up to the order of the per-tile partials).
+    Across tile shapes FP64 is bitwise identical too; in FP32 the two kernel
+    instantiations may contract multiply-adds differently, so states agree
+    to FP32 rounding."""
+    _say("tunings, precision", prec)
+    p = synth.make_problem("batch_tiny")
+    q0 = torch.as_tensor(synth.initial_state(p)).to(DEV)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=1)
+    first = {}
+    for ti in (16, 32):
+        for order in (0, 1):
+            for xcd in (1, 0):
+                for wg in (0, 2, 1):
+                    g.set_tuning(ti, wg, xcd, order)
+                    t = g.get_tuning()
+                    assert (t["tile_i"], t["wg_per_cu"], t["xcd_order"], t["tile_order"]) == \
+                        (ti, wg, xcd, order)
+                    q, n, r = _run(g, q0)
+                    ref = first.setdefault(ti, (q, n, r))
+                    assert torch.equal(q, ref[0]) and torch.equal(r, ref[2]), (ti, order, xcd, wg)
+                    assert float(((n - ref[1]).abs() / ref[1]).max()) <= 1e-13
+    a, b = first[16], first[32]
+    dq = float((a[0] - b[0]).norm() / (a[0] - q0.cpu()).norm())
+    dr = float((a[2] - b[2]).norm() / a[2].norm())
+    _say("  tile shapes: state update", dq, "residual", dr)
+    if prec == 0:
+        assert torch.equal(a[0], b[0]) and torch.equal(a[2], b[2])
+    else:
+        assert dq <= 1e-6 and dr <= 1e-6
+    assert g.status() == hb.HB_OK
+
+
+def test_autotune_applies_the_fastest_and_caches_it():
+    p = synth.make_problem("batch_tiny")
+    q0 = torch.as_tensor(synth.initial_state(p)).to(DEV)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        t = g.autotune(q0, path, force=True)
+        _say("  chosen", t)
+        assert t["stage_ms"] > 0 and g.get_tuning() == t
+        entries = json.load(open(path))
+        assert len(entries) == 1 and list(entries.values())[0]["tile_i"] == t["tile_i"]
+        # a second grid on the same workload takes the cached choice
+        g2 = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+        t2 = g2.autotune(q0, path)
+        cfg = ("tile_i", "wg_per_cu", "xcd_order", "tile_order")
+        assert [t2[k] for k in cfg] == [t[k] for k in cfg]
+        assert abs(t2["stage_ms"] - t["stage_ms"]) <= 1e-6 * t["stage_ms"]
+        # another workload adds its own entry
+        p3 = synth.make_problem("cyl_tiny")
+        g3 = hb.Grid(p3.blocks, p3.flow, p3.solver, precision=1, batched=1)
+        g3.autotune(torch.as_tensor(synth.initial_state(p3)).to(DEV), path, force=True)
+        assert len(json.load(open(path))) == 2
+    # the tuned grid computes what an untuned grid of the same tile shape does
+    g4 = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+    g4.set_tuning(tile_i=t["tile_i"])
+    ref = _run(g4, q0)
+    got = _run(g, q0)
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[2], ref[2])
+    assert g.status() == hb.HB_OK
+
+
+def test_tuning_rejects_bad_values():
+    p = synth.make_problem("cyl_tiny")
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+    for bad in ((24, 0, 1, 0), (16, -1, 1, 0), (16, 0, 2, 0), (16, 0, 1, 3)):
+        with pytest.raises(hb.HBError):
+            g.set_tuning(*bad)
+    gp = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    with pytest.raises(hb.HBError):
+        gp.get_tuning()
