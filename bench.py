@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/primal timing")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (JSON); default: tune afresh, no cache")
+    ap.add_argument("--tuning", default=None,
+                    help="tile_i,wg_per_cu,xcd_order,tile_order: set instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -195,7 +197,11 @@ def main():
 
     # ---- FP32-bulk batched (the product path) ------------------------------
     g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=1, batched=1)
-    tuning = g.autotune(q0, args.tune_cache, force=args.tune_cache is None)
+    if args.tuning:
+        g.set_tuning(*[int(x) for x in args.tuning.split(",")])
+        tuning = g.get_tuning()
+    else:
+        tuning = g.autotune(q0, args.tune_cache, force=args.tune_cache is None)
     q = q0.clone()
     time_steps(torch, g, q, args.warmup)
     q = q0.clone()

@@ -277,6 +277,14 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         for (int s = 0; s < 4; ++s)
             if (blocks[b].bc[s] == HB_BC_CUT && cut_blk[4 * b + s] < 0)
                 return fail(HB_ERR_ARG, "a HB_BC_CUT side has no cut");
+    if (solver->batched) {
+        // the batched kernel addresses the state with signed 32-bit byte offsets
+        int64_t total = 0;
+        for (int b = 0; b < nblocks; ++b)
+            total += (int64_t)(2 * blocks[b].n_harm + 1) * 4 * blocks[b].ni * blocks[b].nj;
+        if (total * (int64_t)sizeof(double) >= ((int64_t)1 << 31))
+            return fail(HB_ERR_UNSUPPORTED, "state of 2 GiB or more: use batched = 0");
+    }
 
     // ---- device work starts here --------------------------------------
     hb_grid *g = new (std::nothrow) hb_grid();

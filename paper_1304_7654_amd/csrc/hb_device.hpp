@@ -130,6 +130,60 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
     }
 }
 
+// The same rules as value_i / value_ij, resolved to where the value comes
+// from: an interior cell (b, i, j) of some block, or the far field (ff = 1),
+// with the parity of the wall mirrors met on the way (mir).
+struct GhostSrc {
+    int b, i, j, mir, ff;
+};
+
+__device__ __forceinline__ GhostSrc resolve_i(const BlockDesc *blks, int b, int i, int j) {
+    const BlockDesc &B = blks[b];
+    if (i >= 0 && i < B.ni) return GhostSrc{b, i, j, 0, 0};
+    const int side = i < 0 ? 0 : 1;
+    const int k = i < 0 ? -1 - i : i - B.ni;
+    switch (B.bc[side]) {
+        case HB_BC_PERIODIC: return GhostSrc{b, i < 0 ? i + B.ni : i - B.ni, j, 0, 0};
+        case HB_BC_WALL: return GhostSrc{b, side == 0 ? k : B.ni - 1 - k, j, 1, 0};
+        case HB_BC_CUT: {
+            const int a = B.cut_blk[side];
+            return GhostSrc{a, side == 0 ? blks[a].ni - 1 - k : k, j, 0, 0};
+        }
+        default: return GhostSrc{b, 0, 0, 0, 1};
+    }
+}
+
+__device__ __forceinline__ GhostSrc resolve_ij(const BlockDesc *blks, int b, int i, int j) {
+    const BlockDesc &B = blks[b];
+    if (j >= 0 && j < B.nj) return resolve_i(blks, b, i, j);
+    const int side = j < 0 ? 2 : 3;
+    const int k = j < 0 ? -1 - j : j - B.nj;
+    GhostSrc s;
+    switch (B.bc[side]) {
+        case HB_BC_PERIODIC: return resolve_i(blks, b, i, j < 0 ? j + B.nj : j - B.nj);
+        case HB_BC_WALL:
+            s = resolve_i(blks, b, i, side == 2 ? k : B.nj - 1 - k);
+            s.mir ^= 1;
+            return s;
+        case HB_BC_WAKECUT:
+            if (i < B.wake || i >= B.ni - B.wake) return resolve_i(blks, b, B.ni - 1 - i, k);
+            s = resolve_i(blks, b, i, k);
+            s.mir ^= 1;
+            return s;
+        case HB_BC_CUT: {
+            const int a = B.cut_blk[side];
+            return resolve_i(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k);
+        }
+        default: return GhostSrc{b, 0, 0, 0, 1};
+    }
+}
+
+// Load through a uniform base pointer and a signed 32-bit element offset.
+template <class T>
+__device__ __forceinline__ T ldgs(const T *base, int idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (int)sizeof(T));
+}
+
 // Wall image of full primitives.
 template <class T>
 struct MirrorFull {
@@ -399,6 +453,114 @@ __device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, co
     out[1] = T(0.5) * area * (f1 - d1);
     out[2] = T(0.5) * area * (f2 - d2);
     out[3] = T(0.5) * area * (f3 - d3);
+}
+
+// Face geometry in the form the batched kernel keeps in registers for a
+// whole tile: unit normal, length, and the diamond-gradient coefficients
+// g1 = |S| / (d.S) and rot(d) / (d.S) (grad phi = (phi_R - phi_L) g1 n
+// + (phi_P - phi_Q) b).
+template <class T>
+struct FaceGeo {
+    T nx, ny, area, g1, bx, by;
+};
+
+template <class T>
+__device__ __forceinline__ FaceGeo<T> face_geo(T sx, T sy, T dx, T dy) {
+    FaceGeo<T> f;
+    f.area = fsqrt(sx * sx + sy * sy);
+    const T ia = frcp(f.area);
+    f.nx = sx * ia;
+    f.ny = sy * ia;
+    const T iden = frcp(dx * sx + dy * sy);
+    f.g1 = f.area * iden;
+    f.bx = dy * iden;
+    f.by = -dx * iden;
+    return f;
+}
+
+// viscous_flux with the face geometry of FaceGeo (same quantities, the
+// products regrouped).
+template <class T>
+__device__ __forceinline__ void viscous_flux_g(const UVT<T> &L, const UVT<T> &R, const UVT<T> &P,
+                                               const UVT<T> &Q, const FaceGeo<T> &fg, T mu,
+                                               T kappa, T fv[3], T u0, T v0) {
+    const T du = (R.u - L.u) * fg.g1, dv = (R.v - L.v) * fg.g1, dt = (R.t - L.t) * fg.g1;
+    const T eu = P.u - Q.u, ev = P.v - Q.v, et = P.t - Q.t;
+    const T ux = du * fg.nx + eu * fg.bx, uy = du * fg.ny + eu * fg.by;
+    const T vx = dv * fg.nx + ev * fg.bx, vy = dv * fg.ny + ev * fg.by;
+    const T tx = dt * fg.nx + et * fg.bx, ty = dt * fg.ny + et * fg.by;
+    const T div = ux + vy;
+    const T txx = mu * (T(2) * ux - T(2.0 / 3.0) * div);
+    const T tyy = mu * (T(2) * vy - T(2.0 / 3.0) * div);
+    const T txy = mu * (uy + vx);
+    const T fx = fg.area * (txx * fg.nx + txy * fg.ny);
+    const T fy = fg.area * (txy * fg.nx + tyy * fg.ny);
+    const T uf = u0 + T(0.5) * (L.u + R.u), vf = v0 + T(0.5) * (L.v + R.v);
+    fv[0] = fx;
+    fv[1] = fy;
+    fv[2] = uf * fx + vf * fy + kappa * fg.area * (tx * fg.nx + ty * fg.ny);
+}
+
+// roe_flux_pert with a unit normal and length given, and fewer reciprocals
+// and roots: the Roe weights use r = sqrt(rho_R / rho_L) (sharing 1/rho_L
+// with the enthalpy), so u~ = (u_L + r u_R) / (1 + r) and rho~ = rho_L r;
+// 1/c~^2 gives the Harten width's reciprocal, h2d = 1 / (2 delta_frac).
+template <class T>
+__device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, const FS<T> &f,
+                                                T nx, T ny, T area, T g, T delta_frac, T h2d,
+                                                T out[4]) {
+    const T gg = f.gg;
+    const T rl = T(1) + L.r, rr = T(1) + R.r;
+    const T irl = frcp(rl), irr = frcp(rr);
+    const T ul = f.u + L.u, vl = f.v + L.v, ur = f.u + R.u, vr = f.v + R.v;
+    const T dhl = gg * (L.p - f.p * L.r) * irl +
+                  T(0.5) * (L.u * (T(2) * f.u + L.u) + L.v * (T(2) * f.v + L.v));
+    const T dhr = gg * (R.p - f.p * R.r) * irr +
+                  T(0.5) * (R.u * (T(2) * f.u + R.u) + R.v * (T(2) * f.v + R.v));
+    const T hl = f.h + dhl, hr = f.h + dhr;
+    const T rw = fsqrt(rr * irl);
+    const T iw = frcp(T(1) + rw);
+    const T rt = rl * rw;
+    const T ut = (ul + rw * ur) * iw;
+    const T vt = (vl + rw * vr) * iw;
+    const T ht = (hl + rw * hr) * iw;
+    const T q2t = ut * ut + vt * vt;
+    const T c2 = (g - T(1)) * (ht - T(0.5) * q2t);
+    const T ct = fsqrt(c2);
+    const T ic2 = frcp(c2);
+    const T qnt = ut * nx + vt * ny;
+    const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
+    const T dqn = du * nx + dv * ny;
+    const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
+    const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
+    const T a2 = dr - dp * ic2;
+    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
+    const T l2 = fabs(qnt);
+    if (delta_frac > T(0)) {
+        const T d = delta_frac * ct;
+        const T i2d = h2d * ct * ic2;           // 1 / (2 d)
+        if (l1 < d) l1 = (l1 * l1 + d * d) * i2d;
+        if (l4 < d) l4 = (l4 * l4 + d * d) * i2d;
+    }
+    const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
+    const T d0 = b1 + b4 + b2;
+    const T d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
+    const T d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
+    const T d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (T(0.5) * q2t) +
+                 bs * (ut * du + vt * dv - qnt * dqn);
+    const T qni = f.u * nx + f.v * ny;
+    const T qpl = L.u * nx + L.v * ny, qpr = R.u * nx + R.v * ny;
+    const T dml = L.r * (qni + qpl) + qpl;
+    const T dmr = R.r * (qni + qpr) + qpr;
+    const T f0 = dml + dmr;
+    const T f1 = dml * ul + dmr * ur + qni * (L.u + R.u) + (L.p + R.p) * nx;
+    const T f2 = dml * vl + dmr * vr + qni * (L.v + R.v) + (L.p + R.p) * ny;
+    const T f3 = dml * hl + dmr * hr + qni * (dhl + dhr);
+    const T ha = T(0.5) * area;
+    out[0] = ha * (f0 - d0);
+    out[1] = ha * (f1 - d1);
+    out[2] = ha * (f2 - d2);
+    out[3] = ha * (f3 - d3);
 }
 
 // ---------------------------------------------------------------------------

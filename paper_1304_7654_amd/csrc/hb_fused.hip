@@ -51,42 +51,13 @@ struct FusedArgs {
     int norm;
     int dq_bytes;          // FP32: bytes of the LDS HB-source area before the scratch
     int xcd;               // 1: XCD-aware workgroup renumbering
+    T h2d;                 // 1 / (2 delta_frac) (Harten width), 0 without the fix
 };
 
-// Interior cell of any block as a primitive perturbation of snapshot n.
-template <class T, bool FIRST>
-struct CellPert {
-    const BlockDesc *blks;
-    const double *q0;
-    const T *sin;
-    const double *ffq;
-    int n;
-    T gm1, fu, fv;
-    __device__ W4<T> operator()(int b, int i, int j) const {
-        const BlockDesc &B = blks[b];
-        const int64_t plane = (int64_t)B.ni * B.nj;
-        const int64_t idx = B.q_off + (int64_t)n * 4 * plane + (int64_t)j * B.ni + i;
-        T d0, d1, d2, d3;
-        if constexpr (FIRST) {
-            const double *f = ffq + 4 * (B.snap_off + n);
-            d0 = (T)(q0[idx] - f[0]);
-            d1 = (T)(q0[idx + plane] - f[1]);
-            d2 = (T)(q0[idx + 2 * plane] - f[2]);
-            d3 = (T)(q0[idx + 3 * plane] - f[3]);
-        } else {
-            d0 = sin[idx];
-            d1 = sin[idx + plane];
-            d2 = sin[idx + 2 * plane];
-            d3 = sin[idx + 3 * plane];
-        }
-        return pert_prim<T>(d0, d1, d2, d3, fu, fv, gm1);
-    }
-};
-
-template <class T>
-struct ZeroPert {
-    __device__ W4<T> operator()(int) const { return W4<T>{T(0), T(0), T(0), T(0)}; }
-};
+// Row stride (floats) of the LDS HB-source array DQs[N_s][4][cells].  (A
+// stride of 258 with float2 write-back, which spreads the MFMA result rows
+// over the LDS banks, measured 12% slower per stage.)
+constexpr int kDqS = 256;
 
 // Threads form a TI x TJ grid; the tile's output cells are TI x (TJ - 1):
 // the last thread row only helps with loads, nodes and faces.  With
@@ -115,41 +86,26 @@ struct TileU {
     const T *SI, *dI, *SJ, *dJ;      // block's face metrics
 };
 
+// Face k of the tile (the caller has checked that it lies in the block),
+// geometry fg held in registers for the whole tile.
 template <class T, int TI, int TJ, bool IFACE>
-__device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const TileU<T> &u, int k,
-                                          const T *P, const T *Nd, T *F, const FS<T> &f) {
+__device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T *P, const T *Nd,
+                                          T *F, const FS<T> &f, const FaceGeo<T> &fg) {
     using G = Geo<TI, TJ>;
-    const int ni = u.ni, nj = u.nj;
-    int e0, es, nA, nB, nf;
-    unsigned fg;
-    const T *Sb, *db;
+    int e0, es, nA, nB;
     if constexpr (IFACE) {
         const int fi = k % (TI + 1), fj = k / (TI + 1);
-        const int gi = u.i0 + fi, gj = u.j0 + fj;
-        if (!(gi <= ni && gj < nj)) return;
         e0 = (fj + 2) * G::WE + fi;
         es = 1;
         nA = fj * (TI + 1) + fi;            // node (i, j): edge start
         nB = nA + (TI + 1);                 // node (i, j+1): edge end
-        fg = (unsigned)(gj * (ni + 1) + gi);
-        nf = (ni + 1) * nj;
-        Sb = u.SI;
-        db = u.dI;
     } else {
         const int fi = k % TI, fj = k / TI;
-        const int gi = u.i0 + fi, gj = u.j0 + fj;
-        if (!(gi < ni && gj <= nj)) return;
         e0 = fj * G::WE + fi + 2;
         es = G::WE;
         nB = fj * (TI + 1) + fi;            // node (i, j): edge end
         nA = nB + 1;                        // node (i+1, j): edge start
-        fg = (unsigned)(gj * ni + gi);
-        nf = ni * (nj + 1);
-        Sb = u.SJ;
-        db = u.dJ;
     }
-    const T sx = ldg(Sb, fg), sy = ldg(Sb + nf, fg);
-    const T dx = ldg(db, fg), dy = ldg(db + nf, fg);
     const int x0 = e0, x1 = e0 + es, x2 = e0 + 2 * es, x3 = e0 + 3 * es;
     const W4<T> m2{P[x0], P[G::EXT + x0], P[2 * G::EXT + x0], P[3 * G::EXT + x0]};
     const W4<T> m1{P[x1], P[G::EXT + x1], P[2 * G::EXT + x1], P[3 * G::EXT + x1]};
@@ -158,13 +114,13 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, const TileU<T> 
     W4<T> L, R;
     muscl(m2, m1, p0, p1, a.eps, L, R);
     T fl[4];
-    roe_flux_pert(L, R, f, sx, sy, a.gamma, a.delta, fl);
+    roe_flux_pert_n(L, R, f, fg.nx, fg.ny, fg.area, a.gamma, a.delta, a.h2d, fl);
     const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + x1]};
     const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + x2]};
     const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
     const UVT<T> nb{Nd[nB], Nd[G::NOD + nB], Nd[2 * G::NOD + nB]};
     T fv[3];
-    viscous_flux(uL, uR, na, nb, sx, sy, dx, dy, a.mu, a.kappa, fv, f.u, f.v);
+    viscous_flux_g(uL, uR, na, nb, fg, a.mu, a.kappa, fv, f.u, f.v);
     F[k] = fl[0];
     F[G::NFMAX + k] = fl[1] - fv[0];
     F[2 * G::NFMAX + k] = fl[2] - fv[1];
@@ -182,7 +138,8 @@ struct BlockU {
 // lives in registers); NS = 0: taken from the tile at run time (FP32 tiles:
 // one body serves every snapshot count).
 template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
-__device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem) {
+__device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem,
+                          int &bad) {
     using G = Geo<TI, TJ>;
     static_assert(TI * TJ == kThreads, "one thread per cell");
     // FP32: the HB source goes through the matrix cores and stays in LDS
@@ -214,22 +171,116 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // address stays a scalar base plus one 32-bit VGPR offset.
     const int plane = ni * nj;
     const unsigned cidx = valid ? (unsigned)(j * ni + i) : 0u;
-    const bool inner = tl.i0 >= 2 && tl.i0 + TI + 2 <= ni && tl.j0 >= 2 && tl.j0 + G::OJ + 2 <= nj;
     const T g = a.gamma, gm1 = a.gamma - T(1);
     T *DQs = reinterpret_cast<T *>(smem);
     T *P = reinterpret_cast<T *>(smem + (MF ? a.dq_bytes : 0));   // [5][EXT]: rho', u', v', p', T'
     T *Nd = P + 5 * G::EXT;                                        // [3][NOD]: u', v', T' at nodes
     T *F = Nd + 3 * G::NOD;                                        // [4][NFMAX]
+    // per-snapshot constants of the block, loaded once per tile:
+    // Tf[n][8] = free-stream (u, v, p, -), D Q_inf (4); Td[n][4] = free-stream Q (FP64)
+    T *Tf = F + 4 * G::NFMAX;
+    double *Td = reinterpret_cast<double *>(Tf + 8 * kMaxNs);
+    if (tid < 8 * ns) {
+        const int n = tid >> 3, c = tid & 7;
+        const int sn = 4 * (B.snap_off + n);
+        Tf[tid] = c < 3 ? a.ffw[sn + 1 + c] : (c == 3 ? T(0) : a.dqinf[sn + c - 4]);
+    } else if (tid >= 128 && tid < 128 + 4 * ns) {
+        Td[tid - 128] = a.ffq[4 * B.snap_off + tid - 128];
+    }
+    // geometry of this thread's i-face and j-face (one of each per thread)
+    static_assert(G::NFI <= kThreads && G::NFJ <= kThreads, "one face per thread and pass");
+    FaceGeo<T> gI{T(1), T(0), T(1), T(0), T(0), T(0)}, gJ = gI;
+    bool hasI, hasJ;
+    {
+        const int fi = tid % (TI + 1), fj = tid / (TI + 1);
+        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        hasI = tid < G::NFI && gi <= ni && gj < nj;
+        if (hasI) {
+            const unsigned fg = (unsigned)(gj * (ni + 1) + gi);
+            const int nf = (ni + 1) * nj;
+            gI = face_geo<T>(ldg(tu.SI, fg), ldg(tu.SI + nf, fg), ldg(tu.dI, fg), ldg(tu.dI + nf, fg));
+        }
+    }
+    {
+        const int fi = tid % TI, fj = tid / TI;
+        const int gi = tl.i0 + fi, gj = tl.j0 + fj;
+        hasJ = tid < G::NFJ && gi < ni && gj <= nj;
+        if (hasJ) {
+            const unsigned fg = (unsigned)(gj * ni + gi);
+            const int nf = ni * (nj + 1);
+            gJ = face_geo<T>(ldg(tu.SJ, fg), ldg(tu.SJ + nf, fg), ldg(tu.dJ, fg), ldg(tu.dJ + nf, fg));
+        }
+    }
+    __syncthreads();
 
     // own-cell state of snapshot m, variable v (perturbation form)
     const double *q0b = a.q0 + B.q_off;
     auto load_own = [&](int m, int v) -> T {
         if (!valid) return T(0);
         if constexpr (FIRST)
-            return (T)(ldg(q0b + (m * 4 + v) * plane, cidx) - a.ffq[4 * (B.snap_off + m) + v]);
+            return (T)(ldg(q0b + (m * 4 + v) * plane, cidx) - Td[4 * m + v]);
         else
             return ldg(a.sin + B.q_off + (m * 4 + v) * plane, cidx);
     };
+
+    // geometry of the own cell (time step): mean face normals and area
+    T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
+    double ivol = 1.0;
+    if (valid) {
+        const int nfi = (ni + 1) * nj, nfj = ni * (nj + 1);
+        const unsigned fi0 = (unsigned)(j * (ni + 1) + i);
+        const T *SIx = a.SI + 2 * B.fi_off, *SIy = SIx + nfi;
+        const T *SJx = a.SJ + 2 * B.fj_off, *SJy = SJx + nfj;
+        sxi = T(0.5) * (ldg(SIx, fi0) + ldg(SIx + 1, fi0));
+        syi = T(0.5) * (ldg(SIy, fi0) + ldg(SIy + 1, fi0));
+        sxj = T(0.5) * (ldg(SJx, cidx) + ldg(SJx + ni, cidx));
+        syj = T(0.5) * (ldg(SJy, cidx) + ldg(SJy + ni, cidx));
+        vol = ldg(a.V + B.cell_off, cidx);
+        ivol = 1.0 / (double)vol;
+    }
+
+    // Sources of this thread's two ghost-extended cells (tid and tid + 256),
+    // the same for every snapshot: resolved once per tile through the ghost
+    // rules to an interior cell of some block (offset from this block's
+    // state, plane of the source block) or the far field, with the parity of
+    // wall mirrors.  Every snapshot's values are then loaded one snapshot
+    // ahead into registers, for boundary and interior tiles alike.
+    static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
+    using LT = std::conditional_t<FIRST, double, T>;
+    LT pf[2][4];
+    const int e1 = tid, e2 = tid + kThreads;
+    const bool has2 = e2 < G::EXT;
+    int srel[2] = {0, 0}, spl[2] = {plane, plane};
+    int sff[2] = {1, 1}, smir[2] = {0, 0};       // far field (or beyond the halo): no load
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int e = c ? e2 : e1;
+        if (c && !has2) break;
+        const int gi = tl.i0 + e % G::WE - 2, gj = tl.j0 + e / G::WE - 2;
+        if (gi < ni + 2 && gj < nj + 2) {
+            const GhostSrc gs = resolve_ij(a.blks, tl.blk, gi, gj);
+            sff[c] = gs.ff;
+            smir[c] = gs.mir;
+            if (!gs.ff) {
+                const BlockDesc &S = a.blks[gs.b];
+                srel[c] = (int)(S.q_off - B.q_off) + gs.j * S.ni + gs.i;
+                spl[c] = S.ni * S.nj;
+            }
+        }
+    }
+    const LT *src0;
+    if constexpr (FIRST) src0 = a.q0 + B.q_off;
+    else src0 = a.sin + B.q_off;
+    auto prefetch = [&](int m) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (!sff[c] && (c == 0 || has2)) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pf[c][v] = ldgs(src0, srel[c] + (m * 4 + v) * spl[c]);
+            }
+        }
+    };
+    prefetch(0);
 
     // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
     T dq[MF ? 1 : (NS > 0 ? NS : 1)][4];
@@ -238,7 +289,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll 3
             for (int m = 0; m < ns; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kThreads + tid] = load_own(m, v);
+                for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kDqS + tid] = load_own(m, v);
             __syncthreads();
             // per var v and 16-cell group cb: the 16x16 block (cells x n) =
             // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4)
@@ -258,7 +309,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 for (int s = 0; s < 3; ++s) {
                     if (s < KS) {
                         const int m = 4 * s + kq;
-                        const float av = (m < ns) ? DQs[(m * 4 + v) * kThreads + cb * 16 + row] : 0.0f;
+                        const float av = (m < ns) ? DQs[(m * 4 + v) * kDqS + cb * 16 + row] : 0.0f;
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
                     }
                 }
@@ -268,7 +319,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 if (row < ns) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        DQs[(row * 4 + v) * kThreads + cb * 16 + 4 * kq + r] = acc[r];
+                        DQs[(row * 4 + v) * kDqS + cb * 16 + 4 * kq + r] = acc[r];
                 }
             }
             // the first barrier of the snapshot loop orders these writes
@@ -291,52 +342,9 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             }
     }
 
-    // geometry of the own cell (time step): mean face normals and area
-    T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
-    double ivol = 1.0;
-    if (valid) {
-        const int nfi = (ni + 1) * nj, nfj = ni * (nj + 1);
-        const unsigned fi0 = (unsigned)(j * (ni + 1) + i);
-        const T *SIx = a.SI + 2 * B.fi_off, *SIy = SIx + nfi;
-        const T *SJx = a.SJ + 2 * B.fj_off, *SJy = SJx + nfj;
-        sxi = T(0.5) * (ldg(SIx, fi0) + ldg(SIx + 1, fi0));
-        syi = T(0.5) * (ldg(SIy, fi0) + ldg(SIy + 1, fi0));
-        sxj = T(0.5) * (ldg(SJx, cidx) + ldg(SJx + ni, cidx));
-        syj = T(0.5) * (ldg(SJy, cidx) + ldg(SJy + ni, cidx));
-        vol = ldg(a.V + B.cell_off, cidx);
-        ivol = 1.0 / (double)vol;
-    }
-
     // ---- C: snapshot loop -----------------------------------------------
     double nacc = 0.0;
-    int bad = 0;
     const int iw = tj * (TI + 1) + ti, js = tj * TI + ti;
-    // Interior tiles: the ext-tile values of the next snapshot are loaded
-    // into registers while the current one is processed (each thread owns
-    // ext cells tid and tid + 256).
-    static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
-    using LT = std::conditional_t<FIRST, double, T>;
-    LT pf[2][4];
-    const int e1 = tid, e2 = tid + kThreads;
-    const bool has2 = e2 < G::EXT;
-    unsigned off1 = 0, off2 = 0;
-    if (inner) {
-        const unsigned org = (unsigned)((tl.j0 - 2) * ni + tl.i0 - 2);
-        off1 = org + (unsigned)((e1 / G::WE) * ni + e1 % G::WE);
-        off2 = has2 ? org + (unsigned)((e2 / G::WE) * ni + e2 % G::WE) : org;
-    }
-    auto prefetch = [&](int m) {
-        const LT *base;
-        if constexpr (FIRST) base = a.q0 + B.q_off + m * 4 * plane;
-        else base = a.sin + B.q_off + m * 4 * plane;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pf[0][v] = ldg(base + v * plane, off1);
-        if (has2) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) pf[1][v] = ldg(base + v * plane, off2);
-        }
-    };
-    if (inner) prefetch(0);
     for (int n = 0; n < ns; ++n) {
         // base state of this snapshot for the update (loaded early)
         const int so = n * 4 * plane;     // snapshot offset (uniform)
@@ -347,18 +355,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
             }
         }
-        const T *fw = a.ffw + 4 * (B.snap_off + n);
+        const T *fw = Tf + 8 * n;
         FS<T> f;
-        f.u = fw[1];
-        f.v = fw[2];
-        f.p = fw[3];
+        f.u = fw[0];
+        f.v = fw[1];
+        f.p = fw[2];
         f.gg = g / gm1;
         f.h = f.gg * f.p + T(0.5) * (f.u * f.u + f.v * f.v);
-        // C1: ghost-extended tile
-        if (inner) {
-            // the whole halo lies inside the block: values come from the
-            // prefetch registers; then the next snapshot's loads are issued
-            const double *fq = a.ffq + 4 * (B.snap_off + n);
+        // C1: ghost-extended tile from the prefetch registers; then the next
+        // snapshot's loads are issued
+        {
+            const double *fq = Td + 4 * n;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int e = c ? e2 : e1;
@@ -366,11 +373,16 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 T d[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    if constexpr (FIRST) d[v] = (T)(pf[c][v] - fq[v]);
+                    if (sff[c]) d[v] = T(0);
+                    else if constexpr (FIRST) d[v] = (T)(pf[c][v] - fq[v]);
                     else d[v] = pf[c][v];
                 }
                 T tp;
-                const W4<T> w = pert_prim_t<T>(d[0], d[1], d[2], d[3], f.u, f.v, gm1, g, tp);
+                W4<T> w = pert_prim_t<T>(d[0], d[1], d[2], d[3], f.u, f.v, gm1, g, tp);
+                if (smir[c]) {                  // no-slip wall image: velocity reversed
+                    w.u = -w.u - T(2) * f.u;
+                    w.v = -w.v - T(2) * f.v;
+                }
                 P[e] = w.r;
                 P[G::EXT + e] = w.u;
                 P[2 * G::EXT + e] = w.v;
@@ -378,20 +390,6 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 P[4 * G::EXT + e] = tp;
             }
             if (n + 1 < ns) prefetch(n + 1);
-        } else {
-            CellPert<T, FIRST> cell{a.blks, a.q0, a.sin, a.ffq, n, gm1, f.u, f.v};
-            ZeroPert<T> ff;
-            MirrorPert<T> mir{f.u, f.v};
-            for (int e = tid; e < G::EXT; e += kThreads) {
-                const int gi = tl.i0 + e % G::WE - 2, gj = tl.j0 + e / G::WE - 2;
-                W4<T> w{T(0), T(0), T(0), T(0)};
-                if (gi < ni + 2 && gj < nj + 2) w = value_ij<W4<T>>(a.blks, tl.blk, gi, gj, cell, ff, mir);
-                P[e] = w.r;
-                P[G::EXT + e] = w.u;
-                P[2 * G::EXT + e] = w.v;
-                P[3 * G::EXT + e] = w.p;
-                P[4 * G::EXT + e] = pert_temp(w, g);
-            }
         }
         __syncthreads();
         // C2: node averages of (u', v', T')
@@ -407,7 +405,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         }
         __syncthreads();
         // C3a: i-face fluxes, each face once
-        for (int k = tid; k < G::NFI; k += kThreads) face_flux<T, TI, TJ, true>(a, tu, k, P, Nd, F, f);
+        if (hasI) face_flux<T, TI, TJ, true>(a, tid, P, Nd, F, f, gI);
         __syncthreads();
         T rs[4];
 #pragma unroll
@@ -415,24 +413,24 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             rs[v] = valid ? F[v * G::NFMAX + iw + 1] - F[v * G::NFMAX + iw] : T(0);
         __syncthreads();
         // C3b: j-face fluxes
-        for (int k = tid; k < G::NFJ; k += kThreads) face_flux<T, TI, TJ, false>(a, tu, k, P, Nd, F, f);
+        if (hasJ) face_flux<T, TI, TJ, false>(a, tid, P, Nd, F, f, gJ);
         __syncthreads();
         // C4: cell residual and update
         if (valid) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 T dqv;
-                if constexpr (MF) dqv = (ns > 1) ? DQs[(n * 4 + v) * kThreads + tid] : T(0);
+                if constexpr (MF) dqv = (ns > 1) ? DQs[(n * 4 + v) * kDqS + tid] : T(0);
                 else dqv = dq[0][v];
                 rs[v] += (F[v * G::NFMAX + js + TI] - F[v * G::NFMAX + js]) +
-                         vol * (dqv + a.dqinf[4 * (B.snap_off + n) + v]);
+                         vol * (dqv + fw[4 + v]);
             }
             if constexpr (MODE == 0) {
                 double *ob = a.qout + B.q_off + so;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) stg(ob + v * plane, cidx, (double)rs[v]);
             } else {
-                const double *fq = a.ffq + 4 * (B.snap_off + n);
+                const double *fq = Td + 4 * n;
                 const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
                                               (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
                 const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
@@ -467,7 +465,6 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 for (int v = 0; v < 4; ++v) dq[m][v] = dq[m + 1][v];
         }
     }
-    if (bad) atomicOr(a.status, 1);
     if (a.norm) {
         // deterministic tile partial: wave reduction, then 4 waves in order
         for (int off = 32; off > 0; off >>= 1) nacc += __shfl_xor(nacc, off, 64);
@@ -494,32 +491,38 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     const int G = gridDim.x;
     int v0 = blockIdx.x;
     if (a.xcd && G % 8 == 0) v0 = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+    int bad = 0;          // a cell of any of this workgroup's tiles went bad
     for (int t = v0; t < a.n_tiles; t += G) {
         const Tile tg = a.tiles[t];
         const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns)};
         if constexpr (std::is_same<T, float>::value) {
-            tile_body<T, TI, TJ, FIRST, MODE, 0>(a, tl, t, smem);
+            tile_body<T, TI, TJ, FIRST, MODE, 0>(a, tl, t, smem, bad);
         } else {
             switch (tl.ns) {
-                case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem); break;
-                case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem); break;
-                case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem); break;
-                case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem); break;
-                default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem); break;
+                case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem, bad); break;
+                case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem, bad); break;
+                case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem, bad); break;
+                case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem, bad); break;
+                default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem, bad); break;
             }
         }
         __syncthreads();
     }
+    // at most one atomic per wave and launch: a diverging state must not
+    // turn into one atomic per cell on a single word
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.status, 1);
 }
 
 template <class T, int TI, int TJ>
 size_t dq_bytes(int ns_max) {
-    return std::is_same<T, float>::value && ns_max > 1 ? sizeof(float) * (size_t)ns_max * 4 * kThreads : 0;
+    return std::is_same<T, float>::value && ns_max > 1 ? sizeof(float) * (size_t)ns_max * 4 * kDqS : 0;
 }
 
 template <class T, int TI, int TJ>
 size_t smem_bytes(int ns_max) {
-    return dq_bytes<T, TI, TJ>(ns_max) + sizeof(T) * (size_t)Geo<TI, TJ>::SCRATCH;
+    // scratch, then the per-snapshot table (8 T + 4 doubles per snapshot)
+    return dq_bytes<T, TI, TJ>(ns_max) + sizeof(T) * ((size_t)Geo<TI, TJ>::SCRATCH + 8 * kMaxNs) +
+           sizeof(double) * 4 * kMaxNs;
 }
 
 template <class T>
@@ -536,6 +539,7 @@ FusedArgs<float> make_args<float>(hb_grid *g) {
     a.gamma = (float)c.gamma; a.mu = (float)c.mu; a.kappa = (float)c.kappa;
     a.mu_pr = (float)(c.mu / c.prandtl); a.cfl = (float)c.cfl; a.delta = (float)c.delta_frac;
     a.eps = (float)c.eps;
+    a.h2d = c.delta_frac > 0.0 ? (float)(0.5 / c.delta_frac) : 0.0f;
     return a;
 }
 
@@ -549,6 +553,7 @@ FusedArgs<double> make_args<double>(hb_grid *g) {
     a.partials = g->partials_d; a.status = g->status_d;
     a.gamma = c.gamma; a.mu = c.mu; a.kappa = c.kappa; a.mu_pr = c.mu / c.prandtl; a.cfl = c.cfl;
     a.delta = c.delta_frac; a.eps = c.eps;
+    a.h2d = c.delta_frac > 0.0 ? 0.5 / c.delta_frac : 0.0;
     return a;
 }
 

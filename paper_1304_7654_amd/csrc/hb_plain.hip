@@ -150,6 +150,7 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
+    int bad = 0;
     if (t < plane) {
         const int i = (int)(t % B.ni), j = (int)(t / B.ni);
         const int W = B.ni + 1;
@@ -162,7 +163,6 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
         const double syi = 0.5 * (SI[2 * B.fi_off + nfi + fi0] + SI[2 * B.fi_off + nfi + fi0 + 1]);
         const double sxj = 0.5 * (SJ[2 * B.fj_off + fj0] + SJ[2 * B.fj_off + fj0 + B.ni]);
         const double syj = 0.5 * (SJ[2 * B.fj_off + nfj + fj0] + SJ[2 * B.fj_off + nfj + fj0 + B.ni]);
-        int bad = 0;
         for (int n = 0; n < B.ns; ++n) {
             double rs[4];
             for (int v = 0; v < 4; ++v) {
@@ -192,8 +192,9 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
             const double rr = rs[0] / vol;
             acc += rr * rr;
         }
-        if (bad) atomicOr(status, 1);
     }
+    // one atomic per wave that met a bad cell
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, 1);
     if (!norm) return;
     __shared__ double red[kBS];
     red[threadIdx.x] = acc;
