@@ -19,10 +19,10 @@
 //     inverse of the ghost rules, so no atomics), converts to conserved
 //     variables and adds the HB source term V D^T rbar;
 //  6. far-field ghosts carry the incidence: their adjoints reduce to the
-//     alpha0 derivative (one partial per block, summed in block order);
-//  7. node coordinates: the metric adjoints (S, d per face, V per cell) are
-//     chained to the nodes with FP64 atomic adds (summation order, hence the
-//     last bits of xybar, may vary from run to run).
+//     alpha0 derivative (one partial per workgroup, summed in a fixed order);
+//  7. node coordinates: the metric adjoints (S, d per face; V per cell, taken
+//     in the fold) are chained to the nodes with FP64 atomic adds (summation
+//     order, hence the last bits of xybar, may vary from run to run).
 //
 // The force coefficients are a functional of the wall faces only (jmin,
 // j = 0): the adjoint of the wall-cell pressure, of the wall-face viscous
@@ -113,7 +113,7 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
 // Node slots: i-faces store node (i, j) [edge start] in slot 0 (components
 // 16..18) and node (i, j+1) [end] in slot 1 (19..21); j-faces store node
 // (i+1, j) [start] in slot 0 and node (i, j) [end] in slot 1.
-__global__ void k_adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
+__global__ void __launch_bounds__(kBS) k_adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
                              const double *dI, const double *rbar, Consts c, double *AF) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
@@ -143,7 +143,7 @@ __global__ void k_adj_face_i(const BlockDesc *blks, int b, const double *ext, co
              AF + B.afi_off + (int64_t)n * kAF * nf + f, nf);
 }
 
-__global__ void k_adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
+__global__ void __launch_bounds__(kBS) k_adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
                              const double *dJ, const double *rbar, Consts c, double *AF) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
@@ -176,7 +176,7 @@ __global__ void k_adj_face_j(const BlockDesc *blks, int b, const double *ext, co
 }
 
 // node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
-__global__ void k_adj_nodes(const BlockDesc *blks, int b, const double *AFI, const double *AFJ,
+__global__ void __launch_bounds__(kBS) k_adj_nodes(const BlockDesc *blks, int b, const double *AFI, const double *AFJ,
                             double *NB) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
@@ -211,7 +211,7 @@ __global__ void k_adj_nodes(const BlockDesc *blks, int b, const double *AFI, con
 }
 
 // primitive adjoints of every ghost-extended cell: [ns][4][nj+4][ni+4]
-__global__ void k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
+__global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
                             const double *AFJ, const double *NB, Consts c, double *WB) {
     const BlockDesc &B = blks[b];
     const int we = B.ni + 4;
@@ -266,11 +266,15 @@ __global__ void k_adj_cells(const BlockDesc *blks, int b, const double *ext, con
     o[3 * plane] = wb.p;
 }
 
-// interior cells: own adjoint + ghost copies -> conserved adjoint + HB source
-__global__ void k_adj_fold(const BlockDesc *blks, int b, const double *q, const double *rbar,
-                           const double *WB, const int *fptr, const int *fb, const int *fp,
-                           const int *fm, const double *V, const double *D, Consts c,
-                           double *qbar) {
+// interior cells: own adjoint + ghost copies -> conserved adjoint + HB
+// source D^T rbar; with xyb also the cell-area term of the HB source,
+// rbar . V (D Q) -> dV, as node adjoints (rbar == nullptr: no HB source).
+__global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, const double *q,
+                                                  const double *rbar, const double *WB,
+                                                  const int *fptr, const int *fb, const int *fp,
+                                                  const int *fm, const double *V, const double *D,
+                                                  const double *xy, Consts c, double *qbar,
+                                                  double *xyb) {
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,7 +287,16 @@ __global__ void k_adj_fold(const BlockDesc *blks, int b, const double *q, const 
     const double vol = V[gc];
     const double *dm = D + B.d_off;
     const double gm1 = c.gamma - 1.0;
-    for (int n = 0; n < B.ns; ++n) {
+    const int ns = B.ns;
+    // rbar of this cell, all snapshots, in registers (static indices only)
+    double rb[kMaxNs][4];
+#pragma unroll
+    for (int m = 0; m < kMaxNs; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            rb[m][v] = (rbar && m < ns) ? rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t] : 0.0;
+    double vb = 0.0;
+    for (int n = 0; n < ns; ++n) {
         const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
         double wbv[4];
         for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
@@ -298,38 +311,66 @@ __global__ void k_adj_fold(const BlockDesc *blks, int b, const double *q, const 
             wbv[3] += ws[3 * sp];
         }
         const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
-        const W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane], gm1);
+        const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
+        const W4<double> w = prim_from_cons<double>(qn[0], qn[1], qn[2], qn[3], gm1);
         double qb[4];
         prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
-        // HB source: d/dQ_n of sum_m rbar_m V D[m][n] Q_n (none for the forces)
-        for (int v = 0; v < 4 && rbar; ++v) {
-            double sacc = 0.0;
-            for (int m = 0; m < B.ns; ++m)
-                sacc += dm[m * kNsPad + n] * rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t];
-            qb[v] += vol * sacc;
+        // HB source: d/dQ_n of sum_m rbar_m V (D Q)_m = V (D^T rbar)_n
+        double hw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < kMaxNs; ++m) {
+            if (m < ns) {
+                const double d = dm[m * kNsPad + n];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hw[v] += d * rb[m][v];
+            }
         }
         double *o = qbar + B.q_off + (int64_t)n * 4 * plane + t;
-        for (int v = 0; v < 4; ++v) o[v * plane] = qb[v];
+        for (int v = 0; v < 4; ++v) {
+            o[v * plane] = qb[v] + vol * hw[v];
+            vb += qn[v] * hw[v];
+        }
+    }
+    if (xyb && rbar) {
+        // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over the cell's nodes
+        const int W = B.ni + 1;
+        const int64_t nn = (int64_t)W * (B.nj + 1);
+        const double *x = xy + 2 * B.node_off, *y = x + nn;
+        double *xb = xyb + 2 * B.node_off;
+        double *yb = xb + nn;
+        const int64_t k1 = (int64_t)j * W + i, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
+        const double h = 0.5 * vb;
+        unsafeAtomicAdd(xb + k3, h * (y[k4] - y[k2]));
+        unsafeAtomicAdd(xb + k1, -h * (y[k4] - y[k2]));
+        unsafeAtomicAdd(yb + k4, h * (x[k3] - x[k1]));
+        unsafeAtomicAdd(yb + k2, -h * (x[k3] - x[k1]));
+        unsafeAtomicAdd(yb + k3, -h * (x[k4] - x[k2]));
+        unsafeAtomicAdd(yb + k1, h * (x[k4] - x[k2]));
+        unsafeAtomicAdd(xb + k4, -h * (y[k3] - y[k1]));
+        unsafeAtomicAdd(xb + k2, h * (y[k3] - y[k1]));
     }
 }
 
-// alpha0: far-field ghost adjoints . d w_inf / d alpha0, one partial per block
-__global__ void k_adj_alpha(const BlockDesc *blks, int b, const double *WB, const int *ffptr,
-                            const int *ffp, const int *ffm, const double *ffw, double *part) {
+// alpha0: far-field ghost adjoints . d w_inf / d alpha0; one thread per
+// (far-field ghost, snapshot) of block b, one partial per workgroup (summed
+// in a fixed order afterwards)
+__global__ void __launch_bounds__(kBS) k_adj_alpha(const BlockDesc *blks, int b, const double *WB,
+                                                   const int *ffptr, const int *ffp, const int *ffm,
+                                                   const double *ffw, double *part) {
     const BlockDesc &B = blks[b];
+    const int k0 = ffptr[b], cnt = ffptr[b + 1] - k0;
     const int we = B.ni + 4;
     const int64_t eplane = (int64_t)we * (B.nj + 4);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    const int k0 = ffptr[b], k1 = ffptr[b + 1];
-    for (int n = 0; n < B.ns; ++n) {
+    if (cnt > 0 && t < (int64_t)cnt * B.ns) {
+        const int n = (int)(t / cnt), k = k0 + (int)(t % cnt);
         const double *w = ffw + 4 * (B.snap_off + n);
-        // d(u, v)/d alpha = (-v_inf, u_inf)
+        // d(u, v)/d alpha = (-v_inf, u_inf); a mirrored far-field ghost flips both
         const double du = -w[2], dv = w[1];
         const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
-        for (int k = k0 + (int)threadIdx.x; k < k1; k += kBS) {
-            const double sg = ffm[k] ? -1.0 : 1.0;
-            acc += sg * (wbn[eplane + ffp[k]] * du + wbn[2 * eplane + ffp[k]] * dv);
-        }
+        const double sg = ffm[k] ? -1.0 : 1.0;
+        acc = sg * (wbn[eplane + ffp[k]] * du + wbn[2 * eplane + ffp[k]] * dv);
     }
     __shared__ double red[kBS];
     red[threadIdx.x] = acc;
@@ -338,7 +379,7 @@ __global__ void k_adj_alpha(const BlockDesc *blks, int b, const double *WB, cons
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[b] = red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 __global__ void k_sum_parts(const double *part, int n, double *out) {
@@ -441,7 +482,7 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
 
 // i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
 // d = centre(R) - centre(L)
-__global__ void k_adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
+__global__ void __launch_bounds__(kBS) k_adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
                            const double *C, double *xyb) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
@@ -473,7 +514,7 @@ __global__ void k_adj_xy_i(const BlockDesc *blks, int b, const double *AF, const
 }
 
 // j-faces: S_J = (yA - yB, xB - xA), A = node (i, j), B = node (i+1, j)
-__global__ void k_adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
+__global__ void __launch_bounds__(kBS) k_adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
                            const double *C, double *xyb) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
@@ -503,40 +544,6 @@ __global__ void k_adj_xy_j(const BlockDesc *blks, int b, const double *AF, const
     else ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
-// cell areas: V enters through the HB source V (D Q)
-__global__ void k_adj_xy_vol(const BlockDesc *blks, int b, const double *q, const double *rbar,
-                             const double *D, const double *xy, double *xyb) {
-    const BlockDesc &B = blks[b];
-    const int64_t plane = (int64_t)B.ni * B.nj;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= plane) return;
-    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
-    const double *dm = D + B.d_off;
-    double vb = 0.0;
-    for (int n = 0; n < B.ns; ++n)
-        for (int v = 0; v < 4; ++v) {
-            double s = 0.0;
-            for (int m = 0; m < B.ns; ++m) s += dm[n * kNsPad + m] * q[B.q_off + ((int64_t)m * 4 + v) * plane + t];
-            vb += rbar[B.q_off + ((int64_t)n * 4 + v) * plane + t] * s;
-        }
-    const int W = B.ni + 1;
-    const int64_t nn = (int64_t)W * (B.nj + 1);
-    const double *x = xy + 2 * B.node_off, *y = x + nn;
-    double *xb = xyb + 2 * B.node_off;
-    double *yb = xb + nn;
-    const int64_t k1 = (int64_t)j * W + i, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
-    // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2
-    const double h = 0.5 * vb;
-    xadd(xb, k3, h * (y[k4] - y[k2]));
-    xadd(xb, k1, -h * (y[k4] - y[k2]));
-    xadd(yb, k4, h * (x[k3] - x[k1]));
-    xadd(yb, k2, -h * (x[k3] - x[k1]));
-    xadd(yb, k3, -h * (x[k4] - x[k2]));
-    xadd(yb, k1, h * (x[k4] - x[k2]));
-    xadd(xb, k4, -h * (y[k3] - y[k1]));
-    xadd(xb, k2, h * (y[k3] - y[k1]));
-}
-
 // ---- force coefficients ------------------------------------------------------
 __device__ inline bool wall_face(const BlockDesc &B, int i) {
     if (B.bc[2] == HB_BC_WALL) return true;
@@ -556,7 +563,7 @@ struct ForceAdj {
 // loads (zero for faces that are not wall), and the moment-arm adjoints.
 // Face (i, 0): line cells (i, -2), (i, -1) [ghost, L], (i, 0) [wall cell, R],
 // (i, 1); slot 0 = node (i+1, 0), slot 1 = node (i, 0), as in k_adj_face_j.
-__global__ void k_adj_force_face(const BlockDesc *blks, int b, const double *ext, const double *xy,
+__global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, int b, const double *ext, const double *xy,
                                  const double *SJ, const double *dJ, ForceAdj fa, Consts c,
                                  double *AF, double *xyb) {
     const BlockDesc &B = blks[b];
@@ -628,7 +635,7 @@ __global__ void k_adj_force_face(const BlockDesc *blks, int b, const double *ext
 }
 
 // alpha0 through the wind axes: sum over entries of cdbar * cl - clbar * cd
-__global__ void k_adj_force_axes(const double *cf, const double *cfbar, int n, double *out) {
+__global__ void __launch_bounds__(kBS) k_adj_force_axes(const double *cf, const double *cfbar, int n, double *out) {
     __shared__ double red[kBS];
     double acc = 0.0;
     for (int k = threadIdx.x; k < n; k += kBS) acc += cfbar[3 * k + 1] * cf[3 * k] - cfbar[3 * k] * cf[3 * k + 1];
@@ -644,7 +651,7 @@ __global__ void k_adj_force_axes(const double *cf, const double *cfbar, int n, d
 // ---- adjoint pseudo-time iteration --------------------------------------------
 // dtau / V per cell and snapshot of the (fixed) state q: the forward
 // iteration's local step, laid out like one variable of the state.
-__global__ void k_adj_dtv(const BlockDesc *blks, int b, const double *q, const double *SI,
+__global__ void __launch_bounds__(kBS) k_adj_dtv(const BlockDesc *blks, int b, const double *q, const double *SI,
                           const double *SJ, const double *V, Consts c, double *dtv) {
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
@@ -671,7 +678,7 @@ __global__ void k_adj_dtv(const BlockDesc *blks, int b, const double *q, const d
 
 // lam = lam0 - alpha (dtau/V) (J^T lam_in + gq); at the first stage the
 // workgroup's partial sum of ((J^T lam_in + gq) / V)^2 goes to part[blockIdx.x].
-__global__ void k_adj_rk(const BlockDesc *blks, int b, const double *lam0, const double *qbar,
+__global__ void __launch_bounds__(kBS) k_adj_rk(const BlockDesc *blks, int b, const double *lam0, const double *qbar,
                          const double *gq, const double *dtv, const double *V, double alpha,
                          double *lam, double *part) {
     const BlockDesc &B = blks[b];
@@ -701,7 +708,7 @@ __global__ void k_adj_rk(const BlockDesc *blks, int b, const double *lam0, const
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_adj_norm(const double *part, int64_t n, double inv_count, double *out) {
+__global__ void __launch_bounds__(kBS) k_adj_norm(const double *part, int64_t n, double inv_count, double *out) {
     __shared__ double red[kBS];
     double acc = 0.0;
     for (int64_t k = threadIdx.x; k < n; k += kBS) acc += part[k];
@@ -820,10 +827,27 @@ int adjoint_setup(hb_grid *g) {
     rc = rc ? rc : alloc(&g->AFJ_d, g->n_afj);
     rc = rc ? rc : alloc(&g->NB_d, g->n_nodeq);
     rc = rc ? rc : alloc(&g->WBext_d, g->n_ext);
-    rc = rc ? rc : alloc(&g->adj_part_d, g->nblocks + 1);
+    // alpha0 partials: one per workgroup of k_adj_alpha, blocks in order
+    g->apart_off.assign(g->nblocks, 0);
+    int np = 0;
+    for (int b = 0; b < g->nblocks; ++b) {
+        g->apart_off[b] = np;
+        np += (int)std::max<unsigned>(1u, nblk((int64_t)(ffptr[b + 1] - ffptr[b]) * g->blk[b].ns));
+    }
+    g->n_apart = np;
+    rc = rc ? rc : alloc(&g->adj_part_d, np + 1);
     rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
     return rc;
+}
+
+void launch_alpha(hb_grid *g, hipStream_t s) {
+    for (int b = 0; b < g->nblocks; ++b) {
+        const int next = b + 1 < g->nblocks ? g->apart_off[b + 1] : g->n_apart;
+        hipLaunchKernelGGL(k_adj_alpha, dim3(next - g->apart_off[b]), dim3(kBS), 0, s, g->blk_d, b,
+                           g->WBext_d, g->ff_ptr_d, g->ff_p_d, g->ff_m_d, g->ffw_d,
+                           g->adj_part_d + g->apart_off[b]);
+    }
 }
 
 }  // namespace
@@ -834,6 +858,8 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     if (rc) return rc;
     double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
     const Consts c = g->consts;
+    if (xybar)
+        hipLaunchKernelGGL(k_zero, dim3(nblk(2 * g->n_nodes)), dim3(kBS), 0, s, xybar, 2 * g->n_nodes);
     for (int b = 0; b < g->nblocks; ++b) {
         rc = plain_ghost_fill(g, b, q, ext, s);
         if (rc) return rc;
@@ -854,24 +880,19 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
-                           g->V_d, g->D_d, c, qbar);
+                           g->V_d, g->D_d, g->xy_d, c, qbar, xybar);
     }
     if (flowbar) {
-        for (int b = 0; b < g->nblocks; ++b)
-            hipLaunchKernelGGL(k_adj_alpha, dim3(1), dim3(kBS), 0, s, g->blk_d, b, g->WBext_d,
-                               g->ff_ptr_d, g->ff_p_d, g->ff_m_d, g->ffw_d, g->adj_part_d);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->nblocks, flowbar);
+        launch_alpha(g, s);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->n_apart, flowbar);
     }
     if (xybar) {
-        hipLaunchKernelGGL(k_zero, dim3(nblk(2 * g->n_nodes)), dim3(kBS), 0, s, xybar, 2 * g->n_nodes);
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
             hipLaunchKernelGGL(k_adj_xy_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj)), dim3(kBS), 0, s,
                                g->blk_d, b, g->AFI_d, g->xy_d, g->C_d, xybar);
             hipLaunchKernelGGL(k_adj_xy_j, dim3(nblk((int64_t)B.ni * (B.nj + 1))), dim3(kBS), 0, s,
                                g->blk_d, b, g->AFJ_d, g->xy_d, g->C_d, xybar);
-            hipLaunchKernelGGL(k_adj_xy_vol, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d,
-                               b, q, rbar, g->D_d, g->xy_d, xybar);
         }
     }
     return check_hip(hipGetLastError(), "adjoint launch");
@@ -962,17 +983,16 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
-                           g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, c, qbar);
+                           g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, g->xy_d, c, qbar,
+                           (double *)nullptr);
     }
     if (flowbar) {
-        for (int b = 0; b < g->nblocks; ++b)
-            hipLaunchKernelGGL(k_adj_alpha, dim3(1), dim3(kBS), 0, s, g->blk_d, b, g->WBext_d,
-                               g->ff_ptr_d, g->ff_p_d, g->ff_m_d, g->ffw_d, g->adj_part_d);
+        launch_alpha(g, s);
         rc = launch_forces(g, q, g->cf_adj_d, s);
         if (rc) return rc;
         hipLaunchKernelGGL(k_adj_force_axes, dim3(1), dim3(kBS), 0, s, g->cf_adj_d, cfbar,
-                           (int)(g->n_forces / 3), g->adj_part_d + g->nblocks);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->nblocks + 1, flowbar);
+                           (int)(g->n_forces / 3), g->adj_part_d + g->n_apart);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->n_apart + 1, flowbar);
     }
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {

@@ -134,7 +134,9 @@ struct hb_grid {
     int64_t n_adj = 0;
     int64_t n_afi = 0, n_afj = 0, n_nodeq = 0;
     double *AFI_d = nullptr, *AFJ_d = nullptr, *NB_d = nullptr, *WBext_d = nullptr;
-    double *adj_part_d = nullptr;         // alpha0 partials, one per block + 1
+    double *adj_part_d = nullptr;         // alpha0 partials (n_apart) + 1
+    std::vector<int> apart_off;           // first alpha0 partial of each block
+    int n_apart = 0;
     double *cf_adj_d = nullptr;           // forward force coefficients (forces adjoint)
     // adjoint pseudo-time iteration scratch (allocated on first use)
     double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
