@@ -187,9 +187,12 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     } else if (tid >= 128 && tid < 128 + 4 * ns) {
         Td[tid - 128] = a.ffq[4 * B.snap_off + tid - 128];
     }
-    // geometry of this thread's i-face and j-face (one of each per thread)
+    // geometry of this thread's i-face and j-face (one of each per thread):
+    // the loads are issued here, the derived quantities formed after the
+    // tile's first barrier, so that every load of the tile set-up (table,
+    // faces, halo, own cells) is in flight at once
     static_assert(G::NFI <= kThreads && G::NFJ <= kThreads, "one face per thread and pass");
-    FaceGeo<T> gI{T(1), T(0), T(1), T(0), T(0), T(0)}, gJ = gI;
+    T rI[4] = {T(1), T(0), T(1), T(0)}, rJ[4] = {T(1), T(0), T(1), T(0)};
     bool hasI, hasJ;
     {
         const int fi = tid % (TI + 1), fj = tid / (TI + 1);
@@ -198,7 +201,8 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         if (hasI) {
             const unsigned fg = (unsigned)(gj * (ni + 1) + gi);
             const int nf = (ni + 1) * nj;
-            gI = face_geo<T>(ldg(tu.SI, fg), ldg(tu.SI + nf, fg), ldg(tu.dI, fg), ldg(tu.dI + nf, fg));
+            rI[0] = ldg(tu.SI, fg); rI[1] = ldg(tu.SI + nf, fg);
+            rI[2] = ldg(tu.dI, fg); rI[3] = ldg(tu.dI + nf, fg);
         }
     }
     {
@@ -208,17 +212,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         if (hasJ) {
             const unsigned fg = (unsigned)(gj * ni + gi);
             const int nf = ni * (nj + 1);
-            gJ = face_geo<T>(ldg(tu.SJ, fg), ldg(tu.SJ + nf, fg), ldg(tu.dJ, fg), ldg(tu.dJ + nf, fg));
+            rJ[0] = ldg(tu.SJ, fg); rJ[1] = ldg(tu.SJ + nf, fg);
+            rJ[2] = ldg(tu.dJ, fg); rJ[3] = ldg(tu.dJ + nf, fg);
         }
     }
-    __syncthreads();
 
     // own-cell state of snapshot m, variable v (perturbation form)
     const double *q0b = a.q0 + B.q_off;
     auto load_own = [&](int m, int v) -> T {
         if (!valid) return T(0);
         if constexpr (FIRST)
-            return (T)(ldg(q0b + (m * 4 + v) * plane, cidx) - Td[4 * m + v]);
+            return (T)(ldg(q0b + (m * 4 + v) * plane, cidx) - a.ffq[4 * (B.snap_off + m) + v]);
         else
             return ldg(a.sin + B.q_off + (m * 4 + v) * plane, cidx);
     };
@@ -341,6 +345,12 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 dq[n][v] = s;
             }
     }
+
+    // the table (and, without the MFMA phase, everything else) must be
+    // visible before the snapshot loop
+    if (!(MF && ns > 1)) __syncthreads();
+    const FaceGeo<T> gI = face_geo<T>(rI[0], rI[1], rI[2], rI[3]);
+    const FaceGeo<T> gJ = face_geo<T>(rJ[0], rJ[1], rJ[2], rJ[3]);
 
     // ---- C: snapshot loop -----------------------------------------------
     double nacc = 0.0;
