@@ -226,6 +226,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         else
             return ldg(a.sin + B.q_off + (m * 4 + v) * plane, cidx);
     };
+    // Later stages (FP32): the own-cell state of every snapshot is loaded now,
+    // so that these loads are in flight together with the ghost-source
+    // resolution and the first halo prefetch below (their waits overlap).
+    constexpr bool EARLY = MF && !FIRST;
+    T own[EARLY ? kMaxNs : 1][4];
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int m = 0; m < kMaxNs; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) own[m][v] = (m < ns && ns > 1) ? load_own(m, v) : T(0);
+    }
 
     // geometry of the own cell (time step): mean face normals and area
     T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
@@ -290,10 +301,18 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     T dq[MF ? 1 : (NS > 0 ? NS : 1)][4];
     if constexpr (MF) {
         if (ns > 1) {
-#pragma unroll 3
-            for (int m = 0; m < ns; ++m)
+            if constexpr (EARLY) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kDqS + tid] = load_own(m, v);
+                for (int m = 0; m < kMaxNs; ++m)
+                    if (m < ns)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kDqS + tid] = own[m][v];
+            } else {
+#pragma unroll 3
+                for (int m = 0; m < ns; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) DQs[(m * 4 + v) * kDqS + tid] = load_own(m, v);
+            }
             __syncthreads();
             // per var v and 16-cell group cb: the 16x16 block (cells x n) =
             // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4)
