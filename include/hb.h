@@ -219,6 +219,19 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
 int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
                        int32_t n_iter, double *resnorm, void *stream);
 
+/* Time-domain march: the time-domain counterpart of the HB system (the
+ * paper's code solves unsteady flows in the time domain as well as by HB,
+ * §Introduction).  n_steps classical fourth-order Runge-Kutta steps of size
+ * dt in physical time on V dQ/dt = -R(Q, t), from time t0, with the far
+ * field at the instantaneous incidence alpha(t) = alpha0 + alpha_amp
+ * sin(omega t); R is the grid's residual path (batched or per-block, FP64
+ * or FP32 bulk), the stage combinations FP64.  Grids with n_harm = 0 in
+ * every block only (one snapshot per cell; HB_ERR_UNSUPPORTED otherwise).
+ * q: device, state size, advanced in place.  dt > 0 is the caller's
+ * (stability needs dt below about the smallest local step at CFL 1).
+ * Allocates three state-size scratch buffers on the first call. */
+int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream);
+
 /* Autotune the batched stage kernel (the paper's per-block work, batched
  * over blocks of uneven size and N_H in one launch per Runge-Kutta step,
  * §MPI Optimisations): with cache_path (may be NULL) holding an entry for

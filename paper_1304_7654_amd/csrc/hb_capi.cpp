@@ -78,6 +78,7 @@ void free_all(hb_grid *g) {
     dfree(g->ext_adj_d);
     dfree(g->cf_adj_d);
     dfree(g->it_lam0_d); dfree(g->it_qbar_d); dfree(g->it_dtv_d); dfree(g->it_part_d);
+    dfree(g->td_r_d); dfree(g->td_acc_d); dfree(g->td_qs_d);
 }
 
 bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_WAKECUT; }
@@ -500,6 +501,16 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
+}
+
+int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream) {
+    g_err.clear();
+    if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");
+    if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0))
+        return fail(HB_ERR_ARG, "need n_steps >= 0, finite t0 and dt > 0");
+    for (const BlockDesc &B : g->blk)
+        if (B.nh != 0) return fail(HB_ERR_UNSUPPORTED, "the time-domain march needs n_harm = 0 in every block");
+    return launch_td_march(g, q, t0, dt, n_steps, (hipStream_t)stream);
 }
 
 int hb_autotune(hb_grid *g, const double *q, const char *cache_path, int32_t force,

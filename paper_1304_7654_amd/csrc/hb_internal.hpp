@@ -141,6 +141,8 @@ struct hb_grid {
     // adjoint pseudo-time iteration scratch (allocated on first use)
     double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
     int64_t n_it_part = 0;
+    // time-domain march scratch (allocated on first use)
+    double *td_r_d = nullptr, *td_acc_d = nullptr, *td_qs_d = nullptr;
     int *fold_ptr_d = nullptr, *fold_b_d = nullptr, *fold_p_d = nullptr, *fold_m_d = nullptr;
     int *ff_ptr_d = nullptr, *ff_p_d = nullptr, *ff_m_d = nullptr;
     double *ext_adj_d = nullptr;          // ghost-extended primitives for the adjoint
@@ -166,6 +168,8 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order);
 int64_t fused_max_tiles(const hb_grid *g);
 int fused_time_iterations(hb_grid *g, double *q, int n_iter, double *ms_per_stage, hipStream_t s);
 void fused_drop_graph(hb_grid *g);
+// td.hip
+int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s);
 // tune.cpp
 int tune_get(const hb_grid *g, hb_tuning *t);
 int tune_set(hb_grid *g, const hb_tuning *t);
