@@ -219,6 +219,18 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
 int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
                        int32_t n_iter, double *resnorm, void *stream);
 
+/* Restart files (the paper's aggregated output of all blocks and harmonics,
+ * §I/O Optimisations): hb_save_state writes the whole state q (device,
+ * state size) and the caller's iteration counter to `path` in one write
+ * (header with a workload signature and the block table, the state in the
+ * public layout, a checksum; written to path.tmp, then renamed).
+ * hb_load_state reads such a file into q (device) and *iteration (may be
+ * NULL); HB_ERR_ARG for a missing file, another workload (signature, block
+ * sizes, N_H or boundary kinds differ) or a checksum mismatch.  Both
+ * synchronise `stream`. */
+int hb_save_state(hb_grid *g, const double *q, int64_t iteration, const char *path, void *stream);
+int hb_load_state(hb_grid *g, double *q, int64_t *iteration, const char *path, void *stream);
+
 /* Time-domain march: the time-domain counterpart of the HB system (the
  * paper's code solves unsteady flows in the time domain as well as by HB,
  * §Introduction).  n_steps classical fourth-order Runge-Kutta steps of size

@@ -503,6 +503,18 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
 }
 
+int hb_save_state(hb_grid *g, const double *q, int64_t iteration, const char *path, void *stream) {
+    g_err.clear();
+    if (!g || !q || !path) return fail(HB_ERR_ARG, "NULL argument");
+    return io_save(g, q, iteration, path, (hipStream_t)stream);
+}
+
+int hb_load_state(hb_grid *g, double *q, int64_t *iteration, const char *path, void *stream) {
+    g_err.clear();
+    if (!g || !q || !path) return fail(HB_ERR_ARG, "NULL argument");
+    return io_load(g, q, iteration, path, (hipStream_t)stream);
+}
+
 int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream) {
     g_err.clear();
     if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");

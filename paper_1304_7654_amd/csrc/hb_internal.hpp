@@ -168,6 +168,9 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order);
 int64_t fused_max_tiles(const hb_grid *g);
 int fused_time_iterations(hb_grid *g, double *q, int n_iter, double *ms_per_stage, hipStream_t s);
 void fused_drop_graph(hb_grid *g);
+// io.cpp
+int io_save(hb_grid *g, const double *q, int64_t iteration, const char *path, hipStream_t s);
+int io_load(hb_grid *g, double *q, int64_t *iteration, const char *path, hipStream_t s);
 // td.hip
 int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s);
 // tune.cpp

@@ -22,7 +22,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORT
 HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_autotune", "hb_set_tuning",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_save_state", "hb_load_state", "hb_autotune", "hb_set_tuning",
            "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
     L.hb_forces_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hb_adjoint_iterate.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.hb_td_march.argtypes = [vp, vp, dp, dp, i32, vp]
+    L.hb_save_state.argtypes = [vp, vp, i64, ctypes.c_char_p, vp]
+    L.hb_load_state.argtypes = [vp, vp, ctypes.POINTER(i64), ctypes.c_char_p, vp]
     L.hb_autotune.argtypes = [vp, vp, ctypes.c_char_p, i32, ctypes.POINTER(c_tuning), vp]
     L.hb_set_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
     L.hb_get_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
@@ -231,6 +233,17 @@ class Grid:
                                         _ptr(gq, self.n_state, "gq"), int(n_iter),
                                         _ptr(resnorm, n_iter, "resnorm"), _stream()))
         return lam
+
+    def save_state(self, q: torch.Tensor, path: str, iteration: int = 0):
+        _check(lib().hb_save_state(self.h, _ptr(q, self.n_state, "q"), int(iteration),
+                                   str(path).encode(), _stream()))
+
+    def load_state(self, q: torch.Tensor, path: str) -> int:
+        """Read a restart file into q; returns the stored iteration counter."""
+        it = ctypes.c_int64()
+        _check(lib().hb_load_state(self.h, _ptr(q, self.n_state, "q"), ctypes.byref(it),
+                                   str(path).encode(), _stream()))
+        return it.value
 
     def td_march(self, q: torch.Tensor, t0: float, dt: float, n_steps: int):
         """n_steps fourth-order Runge-Kutta steps in physical time from t0,
