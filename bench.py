@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0
 METRIC = ("cell-snapshot RK-stage updates/s (FP32+batched vs FP64 plain); "
           "adjoint/primal time")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_traffic.txt")
+TUNE_CACHE = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
 KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
 
 
@@ -45,9 +46,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(tuning):
     """HBM bytes per fused stage launch from the committed counter summary,
-    or None when it is missing or was taken on another kernel source."""
+    or None when it is missing or was taken on another kernel source or
+    launch configuration."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -56,6 +58,10 @@ def read_traffic():
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_hash") != kernel_hash():
+        return None
+    t = "%d,%d,%d,%d" % (tuning["tile_i"], tuning["wg_per_cu"], tuning["xcd_order"],
+                         tuning["tile_order"])
+    if kv.get("tuning") != t:
         return None
     try:
         return float(kv["bytes_per_launch"])
@@ -162,8 +168,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/primal timing")
-    ap.add_argument("--tune-cache", default=None,
-                    help="autotuner cache file (JSON); default: tune afresh, no cache")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache file (JSON); its entry for this device and workload "
+                         "is applied, else the autotuner runs and adds one")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even if cached")
     ap.add_argument("--tuning", default=None,
                     help="tile_i,wg_per_cu,xcd_order,tile_order: set instead of autotuning")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -201,7 +209,7 @@ def main():
         g.set_tuning(*[int(x) for x in args.tuning.split(",")])
         tuning = g.get_tuning()
     else:
-        tuning = g.autotune(q0, args.tune_cache, force=args.tune_cache is None)
+        tuning = g.autotune(q0, args.tune_cache, force=args.retune)
     q = q0.clone()
     time_steps(torch, g, q, args.warmup)
     q = q0.clone()
@@ -217,7 +225,7 @@ def main():
     stage_s = st_ms / 1000.0 / st_n
     bytes_launch = algorithmic_bytes_per_iteration(problem) / stages
     achieved = bytes_launch / stage_s / 1e9
-    traffic = read_traffic()
+    traffic = read_traffic(tuning)
     g.close()
 
     # ---- plain FP64, per-block launches (baseline on the same GPU) ---------
