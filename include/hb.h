@@ -124,7 +124,8 @@ typedef struct {
  *   tile_i:     threads along i per 256-thread workgroup, 16 or 32; the
  *               output tile is tile_i x (256/tile_i - 1) cells
  *   wg_per_cu:  resident workgroups per CU of the persistent grid
- *               (0 = the occupancy maximum; larger values are capped by it)
+ *               (0 = the occupancy maximum; larger values are capped by it;
+ *               -1 = no persistent grid, one workgroup per tile)
  *   xcd_order:  1 = renumber workgroups so that the workgroups of one XCD
  *               (one L2) take consecutive tiles
  *   tile_order: 0 = tiles of a block row by row, 1 = column by column
@@ -249,7 +250,7 @@ int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, vo
  * §MPI Optimisations): with cache_path (may be NULL) holding an entry for
  * this device and workload and force = 0, apply it; otherwise time every
  * candidate (tile_i in {16, 32} x tile_order in {0, 1} x xcd_order in
- * {1, 0} x wg_per_cu in {max, 2, 1}) over full pseudo-time iterations on a
+ * {1, 0} x wg_per_cu in {max, 2, 1, -1}) over full pseudo-time iterations on a
  * scratch copy of q (device, state size, not modified), apply the fastest
  * and, with cache_path, store it (JSON, one entry per device/workload key).
  * out (host, may be NULL) receives the applied tuning.  Synchronises;

@@ -609,8 +609,11 @@ int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
         occ = nb;
         cached_sm[FIRST][MODE == 2] = sm;
     }
+    // wg_per_cu < 0: one workgroup per tile (the dispatcher starts a tile
+    // whenever a workgroup slot frees); else a persistent grid
     const int per_cu = g->tune_wg_per_cu > 0 ? std::min(g->tune_wg_per_cu, occ) : occ;
-    const int grid = std::max(1, std::min(g->n_tiles, g->n_cu * per_cu));
+    const int grid = g->tune_wg_per_cu < 0 ? std::max(1, g->n_tiles)
+                                           : std::max(1, std::min(g->n_tiles, g->n_cu * per_cu));
     b.xcd = g->tune_xcd;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), sm, s, b);
     return check_hip(hipGetLastError(), "fused launch");

@@ -1,8 +1,8 @@
 // Autotuner of the batched stage kernel.  The tuning space is the tile shape
 // (16 x 15 or 32 x 7 output cells per 256-thread workgroup), the order of
 // the tile list (tile rows or tile columns within each block), the XCD-aware
-// workgroup renumbering, and the number of resident workgroups per CU of the
-// persistent grid.  Every candidate runs full pseudo-time iterations on a
+// workgroup renumbering, and the grid: persistent with a number of resident
+// workgroups per CU, or one workgroup per tile.  Every candidate runs full pseudo-time iterations on a
 // scratch copy of the caller's state, timed with HIP events; the fastest is
 // applied.  Results go to a small JSON cache keyed by the device and the
 // workload signature (block sizes, N_H, boundary kinds, precision), so a
@@ -105,8 +105,8 @@ int cache_store(const char *path, const std::string &key, const hb_tuning &t) {
 }
 
 int apply(hb_grid *g, const hb_tuning &t) {
-    if (t.wg_per_cu < 0 || t.wg_per_cu > 16 || (t.xcd_order != 0 && t.xcd_order != 1))
-        return fail(HB_ERR_ARG, "wg_per_cu must be in [0, 16] and xcd_order 0 or 1");
+    if (t.wg_per_cu < -1 || t.wg_per_cu > 16 || (t.xcd_order != 0 && t.xcd_order != 1))
+        return fail(HB_ERR_ARG, "wg_per_cu must be in [-1, 16] and xcd_order 0 or 1");
     if (t.tile_i != g->tile_ti || t.tile_order != g->tune_order) {
         const int rc = fused_build_tiles(g, t.tile_i, t.tile_order);
         if (rc) return rc;
@@ -152,7 +152,7 @@ int tune_run(hb_grid *g, const double *q, const char *cache_path, int force, hb_
     for (int ti : {16, 32})
         for (int order : {0, 1})
             for (int xcd : {1, 0})
-                for (int wg : {0, 2, 1}) cands.push_back(hb_tuning{ti, wg, xcd, order, 0.0});
+                for (int wg : {0, 2, 1, -1}) cands.push_back(hb_tuning{ti, wg, xcd, order, 0.0});
     best.stage_ms = 1e30;
     for (hb_tuning &c : cands) {
         rc = tune_set(g, &c);

@@ -43,7 +43,7 @@ def test_every_tuning_gives_the_same_states(prec):
     for ti in (16, 32):
         for order in (0, 1):
             for xcd in (1, 0):
-                for wg in (0, 2, 1):
+                for wg in (0, 2, 1, -1):
                     g.set_tuning(ti, wg, xcd, order)
                     t = g.get_tuning()
                     assert (t["tile_i"], t["wg_per_cu"], t["xcd_order"], t["tile_order"]) == \
@@ -97,7 +97,7 @@ def test_autotune_applies_the_fastest_and_caches_it():
 def test_tuning_rejects_bad_values():
     p = synth.make_problem("cyl_tiny")
     g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
-    for bad in ((24, 0, 1, 0), (16, -1, 1, 0), (16, 0, 2, 0), (16, 0, 1, 3)):
+    for bad in ((24, 0, 1, 0), (16, -2, 1, 0), (16, 0, 2, 0), (16, 0, 1, 3)):
         with pytest.raises(hb.HBError):
             g.set_tuning(*bad)
     gp = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
