@@ -113,12 +113,12 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
 // Node slots: i-faces store node (i, j) [edge start] in slot 0 (components
 // 16..18) and node (i, j+1) [end] in slot 1 (19..21); j-faces store node
 // (i+1, j) [start] in slot 0 and node (i, j) [end] in slot 1.
-__global__ void __launch_bounds__(kBS) k_adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
-                             const double *dI, const double *rbar, Consts c, double *AF) {
+__device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
+                             const double *dI, const double *rbar, Consts c, double *AF, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = tid_;
     if (t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
@@ -143,11 +143,11 @@ __global__ void __launch_bounds__(kBS) k_adj_face_i(const BlockDesc *blks, int b
              AF + B.afi_off + (int64_t)n * kAF * nf + f, nf);
 }
 
-__global__ void __launch_bounds__(kBS) k_adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
-                             const double *dJ, const double *rbar, Consts c, double *AF) {
+__device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
+                             const double *dJ, const double *rbar, Consts c, double *AF, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = tid_;
     if (t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
@@ -173,6 +173,18 @@ __global__ void __launch_bounds__(kBS) k_adj_face_j(const BlockDesc *blks, int b
     const double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
     face_rev(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
              AF + B.afj_off + (int64_t)n * kAF * nf + f, nf);
+}
+
+// one launch for both face families of block b: threads [0, nI) take the
+// i-faces (all snapshots), the rest the j-faces
+__global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b, const double *ext,
+                                                   const double *SI, const double *dI,
+                                                   const double *SJ, const double *dJ,
+                                                   const double *rbar, Consts c, double *AFI,
+                                                   double *AFJ, int64_t nI) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nI) adj_face_i(blks, b, ext, SI, dI, rbar, c, AFI, t);
+    else adj_face_j(blks, b, ext, SJ, dJ, rbar, c, AFJ, t - nI);
 }
 
 // node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
@@ -482,12 +494,12 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
 
 // i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
 // d = centre(R) - centre(L)
-__global__ void __launch_bounds__(kBS) k_adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb) {
+__device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
+                           const double *C, double *xyb, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = tid_;
     if (f >= nf) return;
     const int i = (int)(f % W), j = (int)(f / W);
     double sxb = 0, syb = 0, dxb = 0, dyb = 0;
@@ -514,12 +526,12 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_i(const BlockDesc *blks, int b, 
 }
 
 // j-faces: S_J = (yA - yB, xB - xA), A = node (i, j), B = node (i+1, j)
-__global__ void __launch_bounds__(kBS) k_adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb) {
+__device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
+                           const double *C, double *xyb, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = tid_;
     if (f >= nf) return;
     const int i = (int)(f % B.ni), j = (int)(f / B.ni);
     double sxb = 0, syb = 0, dxb = 0, dyb = 0;
@@ -544,6 +556,15 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_j(const BlockDesc *blks, int b, 
     else ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
+// one launch for the node-coordinate adjoints of both face families
+__global__ void __launch_bounds__(kBS) k_adj_xy(const BlockDesc *blks, int b, const double *AFI,
+                                                const double *AFJ, const double *xy, const double *C,
+                                                double *xyb, int64_t nI) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nI) adj_xy_i(blks, b, AFI, xy, C, xyb, t);
+    else adj_xy_j(blks, b, AFJ, xy, C, xyb, t - nI);
+}
+
 // ---- force coefficients ------------------------------------------------------
 __device__ inline bool wall_face(const BlockDesc &B, int i) {
     if (B.bc[2] == HB_BC_WALL) return true;
@@ -562,7 +583,7 @@ struct ForceAdj {
 // One thread per jmin face and snapshot: the per-face record of the wall
 // loads (zero for faces that are not wall), and the moment-arm adjoints.
 // Face (i, 0): line cells (i, -2), (i, -1) [ghost, L], (i, 0) [wall cell, R],
-// (i, 1); slot 0 = node (i+1, 0), slot 1 = node (i, 0), as in k_adj_face_j.
+// (i, 1); slot 0 = node (i+1, 0), slot 1 = node (i, 0), as in adj_face_j.
 __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, int b, const double *ext, const double *xy,
                                  const double *SJ, const double *dJ, ForceAdj fa, Consts c,
                                  double *AF, double *xyb) {
@@ -866,10 +887,9 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
-        hipLaunchKernelGGL(k_adj_face_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
-                           g->blk_d, b, ext, g->SI_d, g->dI_d, rbar, c, g->AFI_d);
-        hipLaunchKernelGGL(k_adj_face_j, dim3(nblk((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
-                           g->blk_d, b, ext, g->SJ_d, g->dJ_d, rbar, c, g->AFJ_d);
+        const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
+        hipLaunchKernelGGL(k_adj_faces, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d,
+                           g->dI_d, g->SJ_d, g->dJ_d, rbar, c, g->AFI_d, g->AFJ_d, nI);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d);
         hipLaunchKernelGGL(k_adj_cells, dim3(nblk((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
@@ -889,10 +909,9 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
-            hipLaunchKernelGGL(k_adj_xy_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj)), dim3(kBS), 0, s,
-                               g->blk_d, b, g->AFI_d, g->xy_d, g->C_d, xybar);
-            hipLaunchKernelGGL(k_adj_xy_j, dim3(nblk((int64_t)B.ni * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->AFJ_d, g->xy_d, g->C_d, xybar);
+            const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
+            hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
+                               g->AFJ_d, g->xy_d, g->C_d, xybar, nI);
         }
     }
     return check_hip(hipGetLastError(), "adjoint launch");
@@ -997,10 +1016,9 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
-            hipLaunchKernelGGL(k_adj_xy_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj)), dim3(kBS), 0, s,
-                               g->blk_d, b, g->AFI_d, g->xy_d, g->C_d, xybar);
-            hipLaunchKernelGGL(k_adj_xy_j, dim3(nblk((int64_t)B.ni * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->AFJ_d, g->xy_d, g->C_d, xybar);
+            const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
+            hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
+                               g->AFJ_d, g->xy_d, g->C_d, xybar, nI);
         }
     }
     return check_hip(hipGetLastError(), "forces adjoint launch");
