@@ -153,10 +153,35 @@ def cpu_baseline(problem, q_host, target_s=12.0):
         dt = time.perf_counter() - t0
         iters = extra
     units = cs * len(solver.rk_alpha) * iters
-    return {"value": units / dt, "unit": "cell-snapshot RK-stage updates/s",
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "%d of %d blocks (%d cell-snapshots), %d iteration(s), %.1f s"
-                      % (len(sel), len(blocks), cs, iters, dt)}
+    out = {"value": units / dt, "unit": "cell-snapshot RK-stage updates/s",
+           "cores": torch.get_num_threads(), "kind": "oracle",
+           "sample": "%d of %d blocks (%d cell-snapshots), %d iteration(s), %.1f s"
+                     % (len(sel), len(blocks), cs, iters, dt),
+           "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+    # the same oracle on one thread, first sampled block only, one iteration
+    nt = torch.get_num_threads()
+    torch.set_num_threads(1)
+    b1 = [blocks[sel[0]]]
+    q1 = qs[sel[0]].reshape(-1)
+    t0 = time.perf_counter()
+    O.rk_iterate(b1, q1, flow, solver, 1)
+    d1 = time.perf_counter() - t0
+    torch.set_num_threads(nt)
+    c1 = b1[0].ns * b1[0].ni * b1[0].nj
+    out["single_thread"] = {"value": c1 * len(solver.rk_alpha) / d1,
+                            "sample": "block %d (%d cell-snapshots), 1 iteration, %.1f s"
+                                      % (sel[0], c1, d1)}
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
