@@ -279,7 +279,7 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
             if (blocks[b].bc[s] == HB_BC_CUT && cut_blk[4 * b + s] < 0)
                 return fail(HB_ERR_ARG, "a HB_BC_CUT side has no cut");
     if (solver->batched) {
-        // the batched kernel addresses the state with signed 32-bit byte offsets
+        // the batched kernel addresses the state with 32-bit byte offsets
         int64_t total = 0;
         for (int b = 0; b < nblocks; ++b)
             total += (int64_t)(2 * blocks[b].n_harm + 1) * 4 * blocks[b].ni * blocks[b].nj;

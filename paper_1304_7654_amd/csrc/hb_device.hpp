@@ -178,10 +178,11 @@ __device__ __forceinline__ GhostSrc resolve_ij(const BlockDesc *blks, int b, int
     }
 }
 
-// Load through a uniform base pointer and a signed 32-bit element offset.
+// Load through a uniform base pointer and an unsigned 32-bit byte offset
+// (scalar base plus one VGPR in the address).
 template <class T>
-__device__ __forceinline__ T ldgs(const T *base, int idx) {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (int)sizeof(T));
+__device__ __forceinline__ T ldgb(const T *base, unsigned byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
 // Wall image of full primitives.
@@ -376,138 +377,77 @@ __device__ __forceinline__ W4<T> pert_prim_t(T dr, T dmx, T dmy, T de, T fu, T f
     return w;
 }
 
-// wall image of a primitive perturbation: full velocity reversed
-template <class T>
-struct MirrorPert {
-    T fu, fv;
-    __device__ W4<T> operator()(W4<T> w) const {
-        w.u = -w.u - T(2) * fu;
-        w.v = -w.v - T(2) * fv;
-        return w;
-    }
-};
-
-// temperature perturbation T - 1 = (gamma dp - drho) / rho
-template <class T>
-__device__ __forceinline__ T pert_temp(const W4<T> &w, T g) {
-    return (g * w.p - w.r) * frcp(T(1) + w.r);
-}
-
-// Roe flux minus the free-stream flux, times the face length; L and R are
-// primitive perturbations of the same snapshot.
-template <class T>
-__device__ __forceinline__ void roe_flux_pert(const W4<T> &L, const W4<T> &R, const FS<T> &f,
-                                              T sx, T sy, T g, T delta_frac, T out[4]) {
-    const T area = fsqrt(sx * sx + sy * sy);
-    const T ia = frcp(area);
-    const T nx = sx * ia, ny = sy * ia;
-    const T gg = f.gg;
-    const T rl = T(1) + L.r, rr = T(1) + R.r;
-    const T ul = f.u + L.u, vl = f.v + L.v, ur = f.u + R.u, vr = f.v + R.v;
-    // enthalpy deviation: gg (p'/rho - p_inf rho'/rho) + (|u|^2 - |u_inf|^2)/2
-    const T dhl = gg * (L.p - f.p * L.r) * frcp(rl) +
-                  T(0.5) * (L.u * (T(2) * f.u + L.u) + L.v * (T(2) * f.v + L.v));
-    const T dhr = gg * (R.p - f.p * R.r) * frcp(rr) +
-                  T(0.5) * (R.u * (T(2) * f.u + R.u) + R.v * (T(2) * f.v + R.v));
-    const T hl = f.h + dhl, hr = f.h + dhr;
-    const T sl = fsqrt(rl), sr = fsqrt(rr);
-    const T iw = frcp(sl + sr);
-    const T rt = sl * sr;
-    const T ut = (sl * ul + sr * ur) * iw;
-    const T vt = (sl * vl + sr * vr) * iw;
-    const T ht = (sl * hl + sr * hr) * iw;
-    const T q2t = ut * ut + vt * vt;
-    const T ct = fsqrt((g - T(1)) * (ht - T(0.5) * q2t));
-    const T qnt = ut * nx + vt * ny;
-    const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
-    const T dqn = du * nx + dv * ny;
-    const T ic2 = frcp(ct * ct);
-    const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
-    const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
-    const T a2 = dr - dp * ic2;
-    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
-    const T l2 = fabs(qnt);
-    if (delta_frac > T(0)) {
-        const T d = delta_frac * ct;
-        const T i2d = frcp(T(2) * d);
-        if (l1 < d) l1 = (l1 * l1 + d * d) * i2d;
-        if (l4 < d) l4 = (l4 * l4 + d * d) * i2d;
-    }
-    const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
-    const T d0 = b1 + b4 + b2;
-    const T d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
-    const T d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
-    const T d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (T(0.5) * q2t) +
-                 bs * (ut * du + vt * dv - qnt * dqn);
-    // F(W) - F(W_inf) per side: with m = rho q_n (m_inf = q_n,inf),
-    // dm = rho' q_n + q_n', then (dm u + m_inf u' + p' n, dm h + m_inf h')
-    const T qni = f.u * nx + f.v * ny;
-    const T qpl = L.u * nx + L.v * ny, qpr = R.u * nx + R.v * ny;
-    const T dml = L.r * (qni + qpl) + qpl;
-    const T dmr = R.r * (qni + qpr) + qpr;
-    const T f0 = dml + dmr;
-    const T f1 = dml * ul + dmr * ur + qni * (L.u + R.u) + (L.p + R.p) * nx;
-    const T f2 = dml * vl + dmr * vr + qni * (L.v + R.v) + (L.p + R.p) * ny;
-    const T f3 = dml * hl + dmr * hr + qni * (dhl + dhr);
-    out[0] = T(0.5) * area * (f0 - d0);
-    out[1] = T(0.5) * area * (f1 - d1);
-    out[2] = T(0.5) * area * (f2 - d2);
-    out[3] = T(0.5) * area * (f3 - d3);
-}
-
 // Face geometry in the form the batched kernel keeps in registers for a
-// whole tile: unit normal, length, and the diamond-gradient coefficients
-// g1 = |S| / (d.S) and rot(d) / (d.S) (grad phi = (phi_R - phi_L) g1 n
-// + (phi_P - phi_Q) b).
+// whole tile.  Diamond gradient: grad phi = (phi_R - phi_L) g1 n
+// + (phi_P - phi_Q) b with g1 = |S| / (d.S) and b = rot(d) / (d.S).  With
+// the velocity jump D = u_R - u_L and the edge difference e = u_P - u_Q the
+// velocity gradient is G = g1 D n^T + e b^T, so that
+//   (G + G^T) n - (2/3) tr(G) n
+//       = g1 D + (b.n) e + [(1/3) g1 (D.n) - (2/3) (e.b)] n + (e.n) b
+// and grad T . n = g1 (T_R - T_L) + (b.n) (T_P - T_Q).  The coefficients
+// carry mu |S| (stress) and kappa |S| (heat flux).
 template <class T>
 struct FaceGeo {
-    T nx, ny, area, g1, bx, by;
+    T nx, ny, ha;                 // unit normal, |S| / 2
+    T mg1, mg3, mbn, mbx, mby;    // mu |S| x (g1, g1 / 3, b.n, b)
+    T kg1, kbn;                   // kappa |S| x (g1, b.n)
 };
 
 template <class T>
-__device__ __forceinline__ FaceGeo<T> face_geo(T sx, T sy, T dx, T dy) {
+__device__ __forceinline__ FaceGeo<T> face_geo(T sx, T sy, T dx, T dy, T mu, T kappa) {
     FaceGeo<T> f;
-    f.area = fsqrt(sx * sx + sy * sy);
-    const T ia = frcp(f.area);
+    const T area = fsqrt(sx * sx + sy * sy);
+    const T ia = frcp(area);
     f.nx = sx * ia;
     f.ny = sy * ia;
+    f.ha = T(0.5) * area;
     const T iden = frcp(dx * sx + dy * sy);
-    f.g1 = f.area * iden;
-    f.bx = dy * iden;
-    f.by = -dx * iden;
+    const T g1 = area * iden;
+    const T bx = dy * iden, by = -dx * iden;
+    const T bn = bx * f.nx + by * f.ny;
+    const T ma = mu * area, ka = kappa * area;
+    f.mg1 = ma * g1;
+    f.mg3 = f.mg1 * T(1.0 / 3.0);
+    f.mbn = ma * bn;
+    f.mbx = ma * bx;
+    f.mby = ma * by;
+    f.kg1 = ka * g1;
+    f.kbn = ka * bn;
     return f;
 }
 
-// viscous_flux with the face geometry of FaceGeo (same quantities, the
-// products regrouped).
+// Viscous flux times the face length from FaceGeo (the same quantities as
+// viscous_flux, in the face-normal form above); u0, v0 are added back to
+// the face velocity when L and R hold perturbations.
 template <class T>
 __device__ __forceinline__ void viscous_flux_g(const UVT<T> &L, const UVT<T> &R, const UVT<T> &P,
-                                               const UVT<T> &Q, const FaceGeo<T> &fg, T mu,
-                                               T kappa, T fv[3], T u0, T v0) {
-    const T du = (R.u - L.u) * fg.g1, dv = (R.v - L.v) * fg.g1, dt = (R.t - L.t) * fg.g1;
+                                               const UVT<T> &Q, const FaceGeo<T> &fg, T fv[3],
+                                               T u0, T v0) {
+    const T du = R.u - L.u, dv = R.v - L.v, dt = R.t - L.t;
     const T eu = P.u - Q.u, ev = P.v - Q.v, et = P.t - Q.t;
-    const T ux = du * fg.nx + eu * fg.bx, uy = du * fg.ny + eu * fg.by;
-    const T vx = dv * fg.nx + ev * fg.bx, vy = dv * fg.ny + ev * fg.by;
-    const T tx = dt * fg.nx + et * fg.bx, ty = dt * fg.ny + et * fg.by;
-    const T div = ux + vy;
-    const T txx = mu * (T(2) * ux - T(2.0 / 3.0) * div);
-    const T tyy = mu * (T(2) * vy - T(2.0 / 3.0) * div);
-    const T txy = mu * (uy + vx);
-    const T fx = fg.area * (txx * fg.nx + txy * fg.ny);
-    const T fy = fg.area * (txy * fg.nx + tyy * fg.ny);
+    const T dn = du * fg.nx + dv * fg.ny;
+    const T en = eu * fg.nx + ev * fg.ny;
+    const T c = fg.mg3 * dn - T(2.0 / 3.0) * (eu * fg.mbx + ev * fg.mby);
+    const T fx = fg.mg1 * du + fg.mbn * eu + c * fg.nx + en * fg.mbx;
+    const T fy = fg.mg1 * dv + fg.mbn * ev + c * fg.ny + en * fg.mby;
     const T uf = u0 + T(0.5) * (L.u + R.u), vf = v0 + T(0.5) * (L.v + R.v);
     fv[0] = fx;
     fv[1] = fy;
-    fv[2] = uf * fx + vf * fy + kappa * fg.area * (tx * fg.nx + ty * fg.ny);
+    fv[2] = uf * fx + vf * fy + (fg.kg1 * dt + fg.kbn * et);
 }
 
-// roe_flux_pert with a unit normal and length given, and fewer reciprocals
-// and roots: the Roe weights use r = sqrt(rho_R / rho_L) (sharing 1/rho_L
-// with the enthalpy), so u~ = (u_L + r u_R) / (1 + r) and rho~ = rho_L r;
-// 1/c~^2 gives the Harten width's reciprocal, h2d = 1 / (2 delta_frac).
+// Roe flux minus the free-stream flux, times the face length (ha = |S| / 2);
+// L and R are primitive perturbations of the same snapshot.  The Roe
+// weights use r = sqrt(rho_R / rho_L) (sharing 1/rho_L with the enthalpy),
+// so u~ = (u_L + r u_R) / (1 + r) and rho~ = rho_L r; 1/c~^2 gives the
+// Harten width's reciprocal, h2d = 1 / (2 delta_frac).  The wave sum
+//   sum_k |lambda_k| alpha_k r_k
+// is regrouped around s14 = b1 + b4 and k = c~ (b4 - b1) - bs (dq_n):
+//   d0 = s14 + b2,  d_u = u~ d0 + n_x k + bs du,  d_v = v~ d0 + n_y k + bs dv,
+//   d_E = h~ s14 + q~_n k + b2 |u~|^2 / 2 + bs (u~ du + v~ dv).
 template <class T>
 __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, const FS<T> &f,
-                                                T nx, T ny, T area, T g, T delta_frac, T h2d,
+                                                T nx, T ny, T ha, T g, T delta_frac, T h2d,
                                                 T out[4]) {
     const T gg = f.gg;
     const T rl = T(1) + L.r, rr = T(1) + R.r;
@@ -543,11 +483,12 @@ __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, 
         if (l4 < d) l4 = (l4 * l4 + d * d) * i2d;
     }
     const T b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
-    const T d0 = b1 + b4 + b2;
-    const T d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
-    const T d2 = b1 * (vt - ct * ny) + b4 * (vt + ct * ny) + b2 * vt + bs * (dv - ny * dqn);
-    const T d3 = b1 * (ht - qnt * ct) + b4 * (ht + qnt * ct) + b2 * (T(0.5) * q2t) +
-                 bs * (ut * du + vt * dv - qnt * dqn);
+    const T s14 = b1 + b4;
+    const T d0 = s14 + b2;
+    const T kw = ct * (b4 - b1) - bs * dqn;
+    const T d1 = ut * d0 + nx * kw + bs * du;
+    const T d2 = vt * d0 + ny * kw + bs * dv;
+    const T d3 = ht * s14 + qnt * kw + b2 * (T(0.5) * q2t) + bs * (ut * du + vt * dv);
     const T qni = f.u * nx + f.v * ny;
     const T qpl = L.u * nx + L.v * ny, qpr = R.u * nx + R.v * ny;
     const T dml = L.r * (qni + qpl) + qpl;
@@ -556,7 +497,6 @@ __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, 
     const T f1 = dml * ul + dmr * ur + qni * (L.u + R.u) + (L.p + R.p) * nx;
     const T f2 = dml * vl + dmr * vr + qni * (L.v + R.v) + (L.p + R.p) * ny;
     const T f3 = dml * hl + dmr * hr + qni * (dhl + dhr);
-    const T ha = T(0.5) * area;
     out[0] = ha * (f0 - d0);
     out[1] = ha * (f1 - d1);
     out[2] = ha * (f2 - d2);

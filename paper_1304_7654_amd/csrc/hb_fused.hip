@@ -114,13 +114,13 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T 
     W4<T> L, R;
     muscl(m2, m1, p0, p1, a.eps, L, R);
     T fl[4];
-    roe_flux_pert_n(L, R, f, fg.nx, fg.ny, fg.area, a.gamma, a.delta, a.h2d, fl);
+    roe_flux_pert_n(L, R, f, fg.nx, fg.ny, fg.ha, a.gamma, a.delta, a.h2d, fl);
     const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + x1]};
     const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + x2]};
     const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
     const UVT<T> nb{Nd[nB], Nd[G::NOD + nB], Nd[2 * G::NOD + nB]};
     T fv[3];
-    viscous_flux_g(uL, uR, na, nb, fg, a.mu, a.kappa, fv, f.u, f.v);
+    viscous_flux_g(uL, uR, na, nb, fg, fv, f.u, f.v);
     F[k] = fl[0];
     F[G::NFMAX + k] = fl[1] - fv[0];
     F[2 * G::NFMAX + k] = fl[2] - fv[1];
@@ -256,16 +256,18 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 
     // Sources of this thread's two ghost-extended cells (tid and tid + 256),
     // the same for every snapshot: resolved once per tile through the ghost
-    // rules to an interior cell of some block (offset from this block's
-    // state, plane of the source block) or the far field, with the parity of
-    // wall mirrors.  Every snapshot's values are then loaded one snapshot
-    // ahead into registers, for boundary and interior tiles alike.
+    // rules to an interior cell of some block or the far field, with the
+    // parity of wall mirrors.  Every snapshot's values are then loaded one
+    // snapshot ahead into registers, for boundary and interior tiles alike.
+    // Each source is a byte offset into the whole state array (below 2 GiB,
+    // checked at grid creation) and its block's plane in bytes; the four
+    // variables of a snapshot are one plane apart, the next snapshot four.
     static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
     using LT = std::conditional_t<FIRST, double, T>;
-    LT pf[2][4];
+    LT pf[2][4] = {};         // never loaded for far-field sources
     const int e1 = tid, e2 = tid + kThreads;
     const bool has2 = e2 < G::EXT;
-    int srel[2] = {0, 0}, spl[2] = {plane, plane};
+    unsigned sbo[2] = {0u, 0u}, sbp[2] = {0u, 0u};
     int sff[2] = {1, 1}, smir[2] = {0, 0};       // far field (or beyond the halo): no load
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -278,24 +280,30 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             smir[c] = gs.mir;
             if (!gs.ff) {
                 const BlockDesc &S = a.blks[gs.b];
-                srel[c] = (int)(S.q_off - B.q_off) + gs.j * S.ni + gs.i;
-                spl[c] = S.ni * S.nj;
+                sbo[c] = (unsigned)(S.q_off + gs.j * S.ni + gs.i) * (unsigned)sizeof(LT);
+                sbp[c] = (unsigned)(S.ni * S.nj) * (unsigned)sizeof(LT);
             }
         }
     }
     const LT *src0;
-    if constexpr (FIRST) src0 = a.q0 + B.q_off;
-    else src0 = a.sin + B.q_off;
-    auto prefetch = [&](int m) {
+    if constexpr (FIRST) src0 = a.q0;
+    else src0 = a.sin;
+    // loads snapshot m's values and advances the offsets to snapshot m + 1
+    auto prefetch = [&]() {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             if (!sff[c] && (c == 0 || has2)) {
+                unsigned o = sbo[c];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) pf[c][v] = ldgs(src0, srel[c] + (m * 4 + v) * spl[c]);
+                for (int v = 0; v < 4; ++v) {
+                    pf[c][v] = ldgb(src0, o);
+                    o += sbp[c];
+                }
+                sbo[c] = o;
             }
         }
     };
-    prefetch(0);
+    prefetch();
 
     // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
     T dq[MF ? 1 : (NS > 0 ? NS : 1)][4];
@@ -368,8 +376,8 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // the table (and, without the MFMA phase, everything else) must be
     // visible before the snapshot loop
     if (!(MF && ns > 1)) __syncthreads();
-    const FaceGeo<T> gI = face_geo<T>(rI[0], rI[1], rI[2], rI[3]);
-    const FaceGeo<T> gJ = face_geo<T>(rJ[0], rJ[1], rJ[2], rJ[3]);
+    const FaceGeo<T> gI = face_geo<T>(rI[0], rI[1], rI[2], rI[3], a.mu, a.kappa);
+    const FaceGeo<T> gJ = face_geo<T>(rJ[0], rJ[1], rJ[2], rJ[3], a.mu, a.kappa);
 
     // ---- C: snapshot loop -----------------------------------------------
     double nacc = 0.0;
@@ -402,9 +410,8 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 T d[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    if (sff[c]) d[v] = T(0);
-                    else if constexpr (FIRST) d[v] = (T)(pf[c][v] - fq[v]);
-                    else d[v] = pf[c][v];
+                    if constexpr (FIRST) d[v] = sff[c] ? T(0) : (T)(pf[c][v] - fq[v]);
+                    else d[v] = pf[c][v];       // far-field sources keep their zero
                 }
                 T tp;
                 W4<T> w = pert_prim_t<T>(d[0], d[1], d[2], d[3], f.u, f.v, gm1, g, tp);
@@ -418,7 +425,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 P[3 * G::EXT + e] = w.p;
                 P[4 * G::EXT + e] = tp;
             }
-            if (n + 1 < ns) prefetch(n + 1);
+            if (n + 1 < ns) prefetch();
         }
         __syncthreads();
         // C2: node averages of (u', v', T')
