@@ -76,7 +76,7 @@ struct Geo {
 };
 
 // Flux of one face of the tile (perturbation form, times the face length),
-// written to F[v * NFMAX + k].  IFACE: i-face k = fj*(TI+1) + fi between
+// written to F[v * fs + k].  IFACE: i-face k = fj*(TI+1) + fi between
 // cells fi-1 and fi of row fj; else j-face k = fj*TI + fi between rows fj-1
 // and fj of column fi.  Returns without writing for faces outside the block.
 // Uniform per-tile data used by the face loops.
@@ -90,7 +90,7 @@ struct TileU {
 // geometry fg held in registers for the whole tile.
 template <class T, int TI, int TJ, bool IFACE>
 __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T *P, const T *Nd,
-                                          T *F, const FS<T> &f, const FaceGeo<T> &fg) {
+                                          T *F, int fs, const FS<T> &f, const FaceGeo<T> &fg) {
     using G = Geo<TI, TJ>;
     int e0, es, nA, nB;
     if constexpr (IFACE) {
@@ -122,9 +122,9 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T 
     T fv[3];
     viscous_flux_g(uL, uR, na, nb, fg, fv, f.u, f.v);
     F[k] = fl[0];
-    F[G::NFMAX + k] = fl[1] - fv[0];
-    F[2 * G::NFMAX + k] = fl[2] - fv[1];
-    F[3 * G::NFMAX + k] = fl[3] - fv[2];
+    F[fs + k] = fl[1] - fv[0];
+    F[2 * fs + k] = fl[2] - fv[1];
+    F[3 * fs + k] = fl[3] - fv[2];
 }
 
 // Scalar copy of the block descriptor fields the tile body uses.
@@ -175,10 +175,14 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     T *DQs = reinterpret_cast<T *>(smem);
     T *P = reinterpret_cast<T *>(smem + (MF ? a.dq_bytes : 0));   // [5][EXT]: rho', u', v', p', T'
     T *Nd = P + 5 * G::EXT;                                        // [3][NOD]: u', v', T' at nodes
-    T *F = Nd + 3 * G::NOD;                                        // [4][NFMAX]
+    T *F = Nd + 3 * G::NOD;                                        // [4][NFMAX] i-faces
+    // j-face fluxes: FP32 tiles write them into the HB-source slot of the
+    // current snapshot (read into registers before); FP64 tiles, whose HB
+    // source is in registers, have an area of their own after F
+    T *FJ64 = F + 4 * G::NFMAX;
     // per-snapshot constants of the block, loaded once per tile:
     // Tf[n][8] = free-stream (u, v, p, -), D Q_inf (4); Td[n][4] = free-stream Q (FP64)
-    T *Tf = F + 4 * G::NFMAX;
+    T *Tf = F + (MF ? 4 : 8) * G::NFMAX;
     double *Td = reinterpret_cast<double *>(Tf + 8 * kMaxNs);
     if (tid < 8 * ns) {
         const int n = tid >> 3, c = tid & 7;
@@ -439,27 +443,29 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 Nd[c * G::NOD + k] = T(0.25) * (pc[e00] + pc[e00 + 1] + pc[e01] + pc[e01 + 1]);
             }
         }
-        __syncthreads();
-        // C3a: i-face fluxes, each face once
-        if (hasI) face_flux<T, TI, TJ, true>(a, tid, P, Nd, F, f, gI);
-        __syncthreads();
-        T rs[4];
+        // this snapshot's HB source into registers (the MFMA results of the
+        // tile are ordered before these reads by the barrier above); its LDS
+        // slot then receives the j-face fluxes
+        T dqv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            rs[v] = valid ? F[v * G::NFMAX + iw + 1] - F[v * G::NFMAX + iw] : T(0);
+        for (int v = 0; v < 4; ++v) {
+            if constexpr (MF) dqv[v] = (ns > 1) ? DQs[(n * 4 + v) * kDqS + tid] : T(0);
+            else dqv[v] = dq[0][v];
+        }
+        T *FJ = MF ? DQs + n * 4 * kDqS : FJ64;
+        constexpr int fjs = MF ? kDqS : G::NFMAX;
         __syncthreads();
-        // C3b: j-face fluxes
-        if (hasJ) face_flux<T, TI, TJ, false>(a, tid, P, Nd, F, f, gJ);
+        // C3: i-face and j-face fluxes, each face once
+        if (hasI) face_flux<T, TI, TJ, true>(a, tid, P, Nd, F, G::NFMAX, f, gI);
+        if (hasJ) face_flux<T, TI, TJ, false>(a, tid, P, Nd, FJ, fjs, f, gJ);
         __syncthreads();
         // C4: cell residual and update
         if (valid) {
+            T rs[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                T dqv;
-                if constexpr (MF) dqv = (ns > 1) ? DQs[(n * 4 + v) * kDqS + tid] : T(0);
-                else dqv = dq[0][v];
-                rs[v] += (F[v * G::NFMAX + js + TI] - F[v * G::NFMAX + js]) +
-                         vol * (dqv + fw[4 + v]);
+                rs[v] = F[v * G::NFMAX + iw + 1] - F[v * G::NFMAX + iw];
+                rs[v] += (FJ[v * fjs + js + TI] - FJ[v * fjs + js]) + vol * (dqv[v] + fw[4 + v]);
             }
             if constexpr (MODE == 0) {
                 double *ob = a.qout + B.q_off + so;
@@ -549,15 +555,21 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.status, 1);
 }
 
+// FP32: the HB-source slots, one per snapshot (at least one: it also holds
+// the j-face fluxes of the snapshot being computed)
 template <class T, int TI, int TJ>
 size_t dq_bytes(int ns_max) {
-    return std::is_same<T, float>::value && ns_max > 1 ? sizeof(float) * (size_t)ns_max * 4 * kDqS : 0;
+    static_assert(Geo<TI, TJ>::NFJ <= kDqS, "j-face fluxes fit a HB-source slot");
+    return std::is_same<T, float>::value ? sizeof(float) * (size_t)std::max(ns_max, 1) * 4 * kDqS : 0;
 }
 
 template <class T, int TI, int TJ>
 size_t smem_bytes(int ns_max) {
-    // scratch, then the per-snapshot table (8 T + 4 doubles per snapshot)
-    return dq_bytes<T, TI, TJ>(ns_max) + sizeof(T) * ((size_t)Geo<TI, TJ>::SCRATCH + 8 * kMaxNs) +
+    // HB-source slots (FP32), scratch, the FP64 j-face area, then the
+    // per-snapshot table (8 T + 4 doubles per snapshot)
+    using G = Geo<TI, TJ>;
+    const size_t fj = std::is_same<T, float>::value ? 0 : 4 * (size_t)G::NFMAX;
+    return dq_bytes<T, TI, TJ>(ns_max) + sizeof(T) * ((size_t)G::SCRATCH + fj + 8 * kMaxNs) +
            sizeof(double) * 4 * kMaxNs;
 }
 
