@@ -50,7 +50,7 @@ struct FusedArgs {
     double alpha;
     int norm;
     int dq_bytes;          // FP32: bytes of the LDS HB-source area before the scratch
-    int xcd;               // 1: XCD-aware workgroup renumbering
+    int xcd;               // XCD-aware renumbering: tiles per XCD chunk (0: off)
     T h2d;                 // 1 / (2 delta_frac) (Harten width), 0 without the fix
 };
 
@@ -283,9 +283,18 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             sff[c] = gs.ff;
             smir[c] = gs.mir;
             if (!gs.ff) {
-                const BlockDesc &S = a.blks[gs.b];
-                sbo[c] = (unsigned)(S.q_off + gs.j * S.ni + gs.i) * (unsigned)sizeof(LT);
-                sbp[c] = (unsigned)(S.ni * S.nj) * (unsigned)sizeof(LT);
+                // a source in this block (all but the cut sides) needs no
+                // descriptor load
+                int64_t sq = B.q_off;
+                int sni = ni, snj = nj;
+                if (gs.b != tl.blk) {
+                    const BlockDesc &S = a.blks[gs.b];
+                    sq = S.q_off;
+                    sni = S.ni;
+                    snj = S.nj;
+                }
+                sbo[c] = (unsigned)(sq + gs.j * sni + gs.i) * (unsigned)sizeof(LT);
+                sbp[c] = (unsigned)(sni * snj) * (unsigned)sizeof(LT);
             }
         }
     }
@@ -528,11 +537,17 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its
     // own L2).  Renumber them so that the workgroups of one XCD take
     // consecutive tiles of the list at the same time: neighbouring tiles,
-    // whose halos overlap, then share an L2.  (Only when the grid is a
-    // multiple of 8, where the renumbering is a permutation.)
+    // whose halos overlap, then share an L2.  The list is cut into rounds of
+    // 8 chunks of C = a.xcd tiles; the k-th workgroup of XCD x takes tile
+    // k % C of chunk x of round k / C, so that all XCDs move through the
+    // list (sorted by snapshot count) together.  A permutation when the
+    // grid is a multiple of 8 C, which the host ensures.
     const int G = gridDim.x;
     int v0 = blockIdx.x;
-    if (a.xcd && G % 8 == 0) v0 = (blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+    if (a.xcd > 0 && G % (8 * a.xcd) == 0) {
+        const int C = a.xcd, x = blockIdx.x % 8, k = blockIdx.x / 8;
+        v0 = (k / C) * 8 * C + x * C + k % C;
+    }
     int bad = 0;          // a cell of any of this workgroup's tiles went bad
     for (int t = v0; t < a.n_tiles; t += G) {
         const Tile tg = a.tiles[t];
@@ -611,6 +626,9 @@ int ns_max(const hb_grid *g) {
     return m;
 }
 
+// tiles per XCD chunk of a one-workgroup-per-tile grid with the XCD renumbering
+constexpr int kXcdChunk = 32;
+
 template <class T, int TI, int TJ, bool FIRST, int MODE>
 int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
     const size_t sm = smem_bytes<T, TI, TJ>(ns_max(g));
@@ -629,11 +647,21 @@ int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
         cached_sm[FIRST][MODE == 2] = sm;
     }
     // wg_per_cu < 0: one workgroup per tile (the dispatcher starts a tile
-    // whenever a workgroup slot frees); else a persistent grid
+    // whenever a workgroup slot frees), the grid rounded up to a multiple of
+    // 8 when the XCD renumbering is on (the extra workgroups find no tile);
+    // else a persistent grid
     const int per_cu = g->tune_wg_per_cu > 0 ? std::min(g->tune_wg_per_cu, occ) : occ;
-    const int grid = g->tune_wg_per_cu < 0 ? std::max(1, g->n_tiles)
-                                           : std::max(1, std::min(g->n_tiles, g->n_cu * per_cu));
-    b.xcd = g->tune_xcd;
+    int grid = g->tune_wg_per_cu < 0 ? std::max(1, g->n_tiles)
+                                     : std::max(1, std::min(g->n_tiles, g->n_cu * per_cu));
+    b.xcd = 0;
+    if (g->tune_xcd) {
+        if (g->tune_wg_per_cu < 0) {
+            b.xcd = kXcdChunk;
+            grid = (grid + 8 * kXcdChunk - 1) / (8 * kXcdChunk) * (8 * kXcdChunk);
+        } else if (grid % 8 == 0) {
+            b.xcd = grid / 8;        // persistent grid: one chunk per XCD and round
+        }
+    }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), sm, s, b);
     return check_hip(hipGetLastError(), "fused launch");
 }
