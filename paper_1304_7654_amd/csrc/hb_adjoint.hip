@@ -742,54 +742,6 @@ __global__ void __launch_bounds__(kBS) k_adj_norm(const double *part, int64_t n,
     if (threadIdx.x == 0) *out = sqrt(red[0] * inv_count);
 }
 
-// ---- host: inverse of the ghost rules ----------------------------------------
-struct GSrc {
-    int cell;    // 1: an interior cell, 0: the far field
-    int b, i, j;
-    int mir;     // number of wall mirrors, mod 2
-};
-
-GSrc res_i(const std::vector<BlockDesc> &B, int b, int i, int j) {
-    const BlockDesc &K = B[b];
-    if (i >= 0 && i < K.ni) return GSrc{1, b, i, j, 0};
-    const int side = i < 0 ? 0 : 1;
-    const int k = i < 0 ? -1 - i : i - K.ni;
-    switch (K.bc[side]) {
-        case HB_BC_PERIODIC: return GSrc{1, b, i < 0 ? i + K.ni : i - K.ni, j, 0};
-        case HB_BC_WALL: return GSrc{1, b, side == 0 ? k : K.ni - 1 - k, j, 1};
-        case HB_BC_CUT: {
-            const int a = K.cut_blk[side];
-            return GSrc{1, a, side == 0 ? B[a].ni - 1 - k : k, j, 0};
-        }
-        default: return GSrc{0, b, 0, 0, 0};
-    }
-}
-
-GSrc res_ij(const std::vector<BlockDesc> &B, int b, int i, int j) {
-    const BlockDesc &K = B[b];
-    if (j >= 0 && j < K.nj) return res_i(B, b, i, j);
-    const int side = j < 0 ? 2 : 3;
-    const int k = j < 0 ? -1 - j : j - K.nj;
-    GSrc s;
-    switch (K.bc[side]) {
-        case HB_BC_PERIODIC: return res_i(B, b, i, j < 0 ? j + K.nj : j - K.nj);
-        case HB_BC_WALL:
-            s = res_i(B, b, i, side == 2 ? k : K.nj - 1 - k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_WAKECUT:
-            if (i < K.wake || i >= K.ni - K.wake) return res_i(B, b, K.ni - 1 - i, k);
-            s = res_i(B, b, i, k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_CUT: {
-            const int a = K.cut_blk[side];
-            return res_i(B, a, i, side == 2 ? B[a].nj - 1 - k : k);
-        }
-        default: return GSrc{0, b, 0, 0, 0};
-    }
-}
-
 template <class T>
 int upload(T **d, const std::vector<T> &h) {
     *d = nullptr;
@@ -811,7 +763,7 @@ int adjoint_setup(hb_grid *g) {
             for (int ie = 0; ie < we; ++ie) {
                 const int i = ie - 2, j = je - 2;
                 if (i >= 0 && i < K.ni && j >= 0 && j < K.nj) continue;
-                const GSrc s = res_ij(g->blk, b, i, j);
+                const GSrc s = ghost_src(g->blk, b, i, j);
                 const int p = je * we + ie;
                 if (s.cell) {
                     const BlockDesc &S = g->blk[s.b];

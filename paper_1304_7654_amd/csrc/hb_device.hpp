@@ -130,54 +130,6 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
     }
 }
 
-// The same rules as value_i / value_ij, resolved to where the value comes
-// from: an interior cell (b, i, j) of some block, or the far field (ff = 1),
-// with the parity of the wall mirrors met on the way (mir).
-struct GhostSrc {
-    int b, i, j, mir, ff;
-};
-
-__device__ __forceinline__ GhostSrc resolve_i(const BlockDesc *blks, int b, int i, int j) {
-    const BlockDesc &B = blks[b];
-    if (i >= 0 && i < B.ni) return GhostSrc{b, i, j, 0, 0};
-    const int side = i < 0 ? 0 : 1;
-    const int k = i < 0 ? -1 - i : i - B.ni;
-    switch (B.bc[side]) {
-        case HB_BC_PERIODIC: return GhostSrc{b, i < 0 ? i + B.ni : i - B.ni, j, 0, 0};
-        case HB_BC_WALL: return GhostSrc{b, side == 0 ? k : B.ni - 1 - k, j, 1, 0};
-        case HB_BC_CUT: {
-            const int a = B.cut_blk[side];
-            return GhostSrc{a, side == 0 ? blks[a].ni - 1 - k : k, j, 0, 0};
-        }
-        default: return GhostSrc{b, 0, 0, 0, 1};
-    }
-}
-
-__device__ __forceinline__ GhostSrc resolve_ij(const BlockDesc *blks, int b, int i, int j) {
-    const BlockDesc &B = blks[b];
-    if (j >= 0 && j < B.nj) return resolve_i(blks, b, i, j);
-    const int side = j < 0 ? 2 : 3;
-    const int k = j < 0 ? -1 - j : j - B.nj;
-    GhostSrc s;
-    switch (B.bc[side]) {
-        case HB_BC_PERIODIC: return resolve_i(blks, b, i, j < 0 ? j + B.nj : j - B.nj);
-        case HB_BC_WALL:
-            s = resolve_i(blks, b, i, side == 2 ? k : B.nj - 1 - k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_WAKECUT:
-            if (i < B.wake || i >= B.ni - B.wake) return resolve_i(blks, b, B.ni - 1 - i, k);
-            s = resolve_i(blks, b, i, k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_CUT: {
-            const int a = B.cut_blk[side];
-            return resolve_i(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k);
-        }
-        default: return GhostSrc{b, 0, 0, 0, 1};
-    }
-}
-
 // Load through a uniform base pointer and an unsigned 32-bit byte offset
 // (scalar base plus one VGPR in the address).
 template <class T>

@@ -34,6 +34,7 @@ template <class T>
 struct FusedArgs {
     const BlockDesc *blks;
     const Tile *tiles;
+    const uint32_t *gtab;  // halo source tables of the tiles at block sides
     int n_tiles;
     const double *q0;      // FP64 base state Q(0); also the stencil input of stage 1
     const T *sin;          // stencil input of later stages (perturbation form)
@@ -259,43 +260,43 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     }
 
     // Sources of this thread's two ghost-extended cells (tid and tid + 256),
-    // the same for every snapshot: resolved once per tile through the ghost
-    // rules to an interior cell of some block or the far field, with the
-    // parity of wall mirrors.  Every snapshot's values are then loaded one
-    // snapshot ahead into registers, for boundary and interior tiles alike.
-    // Each source is a byte offset into the whole state array (below 2 GiB,
-    // checked at grid creation) and its block's plane in bytes; the four
-    // variables of a snapshot are one plane apart, the next snapshot four.
+    // the same for every snapshot.  In a tile away from the block sides
+    // every ext cell is a cell of the block; a tile at a side reads them from
+    // its halo source table, where the ghost rules were applied on the host
+    // (an interior cell of some block, or the far field, with the parity of
+    // wall mirrors).  Every snapshot's values are then loaded one snapshot
+    // ahead into registers.  A source is a byte offset into the whole state
+    // array (below 2 GiB, checked at grid creation) and its block's plane in
+    // bytes; the four variables of a snapshot are one plane apart, the next
+    // snapshot four.
     static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
     using LT = std::conditional_t<FIRST, double, T>;
     LT pf[2][4] = {};         // never loaded for far-field sources
     const int e1 = tid, e2 = tid + kThreads;
     const bool has2 = e2 < G::EXT;
     unsigned sbo[2] = {0u, 0u}, sbp[2] = {0u, 0u};
-    int sff[2] = {1, 1}, smir[2] = {0, 0};       // far field (or beyond the halo): no load
+    int sff[2] = {1, 1}, smir[2] = {0, 0};       // far field: no load
+    if (tl.gtab < 0) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int e = c ? e2 : e1;
-        if (c && !has2) break;
-        const int gi = tl.i0 + e % G::WE - 2, gj = tl.j0 + e / G::WE - 2;
-        if (gi < ni + 2 && gj < nj + 2) {
-            const GhostSrc gs = resolve_ij(a.blks, tl.blk, gi, gj);
-            sff[c] = gs.ff;
-            smir[c] = gs.mir;
-            if (!gs.ff) {
-                // a source in this block (all but the cut sides) needs no
-                // descriptor load
-                int64_t sq = B.q_off;
-                int sni = ni, snj = nj;
-                if (gs.b != tl.blk) {
-                    const BlockDesc &S = a.blks[gs.b];
-                    sq = S.q_off;
-                    sni = S.ni;
-                    snj = S.nj;
-                }
-                sbo[c] = (unsigned)(sq + gs.j * sni + gs.i) * (unsigned)sizeof(LT);
-                sbp[c] = (unsigned)(sni * snj) * (unsigned)sizeof(LT);
-            }
+        for (int c = 0; c < 2; ++c) {
+            const int e = c ? e2 : e1;
+            if (c && !has2) break;
+            const int gi = tl.i0 + e % G::WE - 2, gj = tl.j0 + e / G::WE - 2;
+            sff[c] = 0;
+            sbo[c] = (unsigned)(B.q_off + gj * ni + gi) * (unsigned)sizeof(LT);
+            sbp[c] = (unsigned)plane * (unsigned)sizeof(LT);
+        }
+    } else {
+        const uint2 *gt = reinterpret_cast<const uint2 *>(a.gtab) + tl.gtab;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int e = c ? e2 : e1;
+            if (c && !has2) break;
+            const uint2 en = gt[e];
+            sff[c] = en.y == 0u;
+            smir[c] = (int)(en.x >> 31);
+            sbo[c] = (en.x & 0x7fffffffu) * (unsigned)sizeof(LT);
+            sbp[c] = en.y * (unsigned)sizeof(LT);
         }
     }
     const LT *src0;
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     int bad = 0;          // a cell of any of this workgroup's tiles went bad
     for (int t = v0; t < a.n_tiles; t += G) {
         const Tile tg = a.tiles[t];
-        const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns)};
+        const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns), uni(tg.gtab)};
         if constexpr (std::is_same<T, float>::value) {
             tile_body<T, TI, TJ, FIRST, MODE, 0>(a, tl, t, smem, bad);
         } else {
@@ -595,7 +596,7 @@ template <>
 FusedArgs<float> make_args<float>(hb_grid *g) {
     FusedArgs<float> a{};
     const Consts &c = g->consts;
-    a.blks = g->blk_d; a.tiles = g->tiles_d; a.n_tiles = g->n_tiles;
+    a.blks = g->blk_d; a.tiles = g->tiles_d; a.gtab = g->gtab_d; a.n_tiles = g->n_tiles;
     a.SI = g->SI_f; a.dI = g->dI_f; a.SJ = g->SJ_f; a.dJ = g->dJ_f; a.V = g->V_f;
     a.D = g->D_f; a.ffw = g->ffw_f; a.dqinf = g->dqinf_f; a.ffq = g->ffq_d;
     a.partials = g->partials_d; a.status = g->status_d;
@@ -610,7 +611,7 @@ template <>
 FusedArgs<double> make_args<double>(hb_grid *g) {
     FusedArgs<double> a{};
     const Consts &c = g->consts;
-    a.blks = g->blk_d; a.tiles = g->tiles_d; a.n_tiles = g->n_tiles;
+    a.blks = g->blk_d; a.tiles = g->tiles_d; a.gtab = g->gtab_d; a.n_tiles = g->n_tiles;
     a.SI = g->SI_d; a.dI = g->dI_d; a.SJ = g->SJ_d; a.dJ = g->dJ_d; a.V = g->V_d;
     a.D = g->D_d; a.ffw = g->ffw_d; a.dqinf = g->dqinf_d; a.ffq = g->ffq_d;
     a.partials = g->partials_d; a.status = g->status_d;
@@ -761,10 +762,10 @@ std::vector<Tile> make_tiles(const hb_grid *g, int ti, int order) {
         const BlockDesc &B = g->blk[b];
         if (order == 0) {
             for (int j0 = 0; j0 < B.nj; j0 += tj)
-                for (int i0 = 0; i0 < B.ni; i0 += ti) tiles.push_back(Tile{b, i0, j0, B.ns});
+                for (int i0 = 0; i0 < B.ni; i0 += ti) tiles.push_back(Tile{b, i0, j0, B.ns, -1});
         } else {
             for (int i0 = 0; i0 < B.ni; i0 += ti)
-                for (int j0 = 0; j0 < B.nj; j0 += tj) tiles.push_back(Tile{b, i0, j0, B.ns});
+                for (int j0 = 0; j0 < B.nj; j0 += tj) tiles.push_back(Tile{b, i0, j0, B.ns, -1});
         }
     }
     // heavier tiles first: the static stride then hands every workgroup a
@@ -792,7 +793,35 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
         return fail(HB_ERR_UNSUPPORTED, "the fused path needs at least two Runge-Kutta stages");
     if ((tile_i != 16 && tile_i != 32) || (order != 0 && order != 1))
         return fail(HB_ERR_ARG, "tile_i must be 16 or 32 and tile_order 0 or 1");
-    const std::vector<Tile> tiles = make_tiles(g, tile_i, order);
+    std::vector<Tile> tiles = make_tiles(g, tile_i, order);
+    // halo source tables of the tiles whose ghost-extended region leaves the
+    // block: entry e of a tile describes ext cell e (row-major over the
+    // (TI + 4) x (OJ + 4) region, two entries per thread); cells beyond the
+    // second ghost layer of a partial tile, and the entries past the region,
+    // are far field
+    const int ti = tile_i, oj = kThreads / tile_i - 1;
+    const int we = ti + 4, ext = (ti + 4) * (oj + 4);
+    std::vector<uint32_t> tab;
+    for (Tile &t : tiles) {
+        const BlockDesc &K = g->blk[t.blk];
+        if (t.i0 >= 2 && t.i0 + ti + 2 <= K.ni && t.j0 >= 2 && t.j0 + oj + 2 <= K.nj) continue;
+        t.gtab = (int)(tab.size() / 2);
+        for (int e = 0; e < 2 * kThreads; ++e) {
+            uint32_t x = 0, y = 0;
+            const int gi = t.i0 + e % we - 2, gj = t.j0 + e / we - 2;
+            if (e < ext && gi < K.ni + 2 && gj < K.nj + 2) {
+                const GSrc src = ghost_src(g->blk, t.blk, gi, gj);
+                if (src.cell) {
+                    const BlockDesc &S = g->blk[src.b];
+                    x = (uint32_t)(S.q_off + (int64_t)src.j * S.ni + src.i);
+                    y = (uint32_t)(S.ni * S.nj);
+                }
+                x |= (uint32_t)src.mir << 31;
+            }
+            tab.push_back(x);
+            tab.push_back(y);
+        }
+    }
     hipDeviceProp_t prop;
     int rc = check_hip(hipGetDeviceProperties(&prop, g->device), "device properties");
     if (rc) return rc;
@@ -806,6 +835,15 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
     if (rc) return rc;
     rc = check_hip(hipMemcpy(g->tiles_d, tiles.data(), sizeof(Tile) * tiles.size(),
                              hipMemcpyHostToDevice), "tiles upload");
+    if (rc) return rc;
+    if (g->gtab_d) (void)hipFree(g->gtab_d);
+    g->gtab_d = nullptr;
+    rc = check_hip(hipMalloc((void **)&g->gtab_d, sizeof(uint32_t) * std::max<size_t>(2, tab.size())),
+                   "halo table alloc");
+    if (rc) return rc;
+    if (!tab.empty())
+        rc = check_hip(hipMemcpy(g->gtab_d, tab.data(), sizeof(uint32_t) * tab.size(),
+                                 hipMemcpyHostToDevice), "halo table upload");
     if (rc) return rc;
     g->tile_ti = tile_i;
     g->tile_tj = kThreads / tile_i - 1;

@@ -42,11 +42,23 @@ struct BlockDesc {
     double omega_nh;         // omega * N_H (time-step bound of the HB term)
 };
 
-// One fused-kernel work item: a tile of cells of one block.
+// One fused-kernel work item: a tile of cells of one block.  gtab: first
+// entry of the tile's halo source table, -1 when every cell of the
+// ghost-extended tile is a cell of the block itself.
 struct Tile {
     int32_t blk;
     int32_t i0, j0;
     int32_t ns;
+    int32_t gtab;
+};
+
+// Source of a ghost-extended cell: an interior cell (b, i, j) of some block
+// (cell = 1) or the far field (cell = 0), with the parity of the wall
+// mirrors met on the way.
+struct GSrc {
+    int cell;
+    int b, i, j;
+    int mir;
 };
 
 // Geometry and flow constants passed by value to kernels.
@@ -114,6 +126,10 @@ struct hb_grid {
     // fused path
     hb::Tile *tiles_d = nullptr;
     int n_tiles = 0;
+    // halo source table of the tiles that touch a block side: per tile 512
+    // entries (two per thread), each (source element index | mirror << 31,
+    // source plane; plane 0 = far field)
+    uint32_t *gtab_d = nullptr;
     int tile_ti = 16, tile_tj = 15;
     int n_cu = 0;
     // tuning of the fused path (hb_set_tuning / hb_autotune)
@@ -149,6 +165,10 @@ struct hb_grid {
 };
 
 namespace hb {
+
+// ghost.cpp: host-side ghost rules
+GSrc ghost_src_i(const std::vector<BlockDesc> &B, int b, int i, int j);
+GSrc ghost_src(const std::vector<BlockDesc> &B, int b, int i, int j);
 
 // error helpers (capi.cpp)
 int upload_snapshot_tables(hb_grid *g);
