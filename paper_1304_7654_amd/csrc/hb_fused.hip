@@ -185,12 +185,43 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // Tf[n][8] = free-stream (u, v, p, -), D Q_inf (4); Td[n][4] = free-stream Q (FP64)
     T *Tf = F + (MF ? 4 : 8) * G::NFMAX;
     double *Td = reinterpret_cast<double *>(Tf + 8 * kMaxNs);
-    if (tid < 8 * ns) {
+    // (loaded here into registers, written to LDS after the other set-up
+    // loads have been issued)
+    const bool wtf = tid < 8 * ns, wtd = tid >= 128 && tid < 128 + 4 * ns;
+    T tfv = T(0);
+    double tdv = 0.0;
+    if (wtf) {
         const int n = tid >> 3, c = tid & 7;
         const int sn = 4 * (B.snap_off + n);
-        Tf[tid] = c < 3 ? a.ffw[sn + 1 + c] : (c == 3 ? T(0) : a.dqinf[sn + c - 4]);
-    } else if (tid >= 128 && tid < 128 + 4 * ns) {
-        Td[tid - 128] = a.ffq[4 * B.snap_off + tid - 128];
+        if (c < 3) tfv = a.ffw[sn + 1 + c];
+        else if (c > 3) tfv = a.dqinf[sn + c - 4];
+    } else if (wtd) {
+        tdv = a.ffq[4 * B.snap_off + tid - 128];
+    }
+    // halo source table entries of this thread's two ghost-extended cells
+    // (tiles at block sides), issued first: the halo prefetch depends on them
+    static_assert(Geo<TI, TJ>::EXT <= 2 * kThreads, "two ext cells per thread");
+    const int e1 = tid, e2 = tid + kThreads;
+    const bool has2 = e2 < G::EXT;
+    uint2 gen[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+    if (tl.gtab >= 0) {
+        const uint2 *gt = reinterpret_cast<const uint2 *>(a.gtab) + tl.gtab;
+        gen[0] = gt[e1];
+        if (has2) gen[1] = gt[e2];
+    }
+    // FP32: this lane's B operands of the MFMA phase (D^T, K = m in steps of
+    // 4), loaded before the other set-up loads so that the MFMA phase waits
+    // for them and the loads issued before it, not for the halo prefetch
+    float bD[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (MF) {
+        if (ns > 1) {
+            const int row = tid & 15, kq = (tid & 63) >> 4;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int m = 4 * s + kq;
+                if (row < ns && m < ns) bD[s] = a.D[B.d_off + row * kNsPad + m];
+            }
+        }
     }
     // geometry of this thread's i-face and j-face (one of each per thread):
     // the loads are issued here, the derived quantities formed after the
@@ -269,11 +300,8 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     // array (below 2 GiB, checked at grid creation) and its block's plane in
     // bytes; the four variables of a snapshot are one plane apart, the next
     // snapshot four.
-    static_assert(G::EXT <= 2 * kThreads, "two ext cells per thread");
     using LT = std::conditional_t<FIRST, double, T>;
     LT pf[2][4] = {};         // never loaded for far-field sources
-    const int e1 = tid, e2 = tid + kThreads;
-    const bool has2 = e2 < G::EXT;
     unsigned sbo[2] = {0u, 0u}, sbp[2] = {0u, 0u};
     int sff[2] = {1, 1}, smir[2] = {0, 0};       // far field: no load
     if (tl.gtab < 0) {
@@ -287,12 +315,10 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             sbp[c] = (unsigned)plane * (unsigned)sizeof(LT);
         }
     } else {
-        const uint2 *gt = reinterpret_cast<const uint2 *>(a.gtab) + tl.gtab;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const int e = c ? e2 : e1;
             if (c && !has2) break;
-            const uint2 en = gt[e];
+            const uint2 en = gen[c];
             sff[c] = en.y == 0u;
             smir[c] = (int)(en.x >> 31);
             sbo[c] = (en.x & 0x7fffffffu) * (unsigned)sizeof(LT);
@@ -319,6 +345,9 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     };
     prefetch();
 
+    if (wtf) Tf[tid] = tfv;
+    else if (wtd) Td[tid - 128] = tdv;
+
     // ---- A + B: HB source D (Q - Q_inf) of the tile ----------------------
     T dq[MF ? 1 : (NS > 0 ? NS : 1)][4];
     if constexpr (MF) {
@@ -341,12 +370,6 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             const int lane = tid & 63, wave = tid >> 6;
             const int row = lane & 15, kq = lane >> 4;
             const int KS = (ns + 3) / 4;            // <= 3
-            float bD[3];
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const int m = 4 * s + kq;
-                bD[s] = (row < ns && m < ns) ? a.D[B.d_off + row * kNsPad + m] : 0.0f;
-            }
             for (int grp = wave; grp < 4 * (kThreads / 16); grp += kThreads / 64) {
                 const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
                 floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -401,10 +424,11 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         const int so = n * 4 * plane;     // snapshot offset (uniform)
         double b0[4] = {0.0, 0.0, 0.0, 0.0};
         if constexpr (MODE != 0) {
-            if (valid) {
+            // unconditional (cidx = 0 for the helper row and cells outside
+            // the block): a fixed count of loads lets the halo values of
+            // this snapshot be consumed without waiting for these
 #pragma unroll
-                for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
-            }
+            for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
         }
         const T *fw = Tf + 8 * n;
         FS<T> f;
