@@ -31,9 +31,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# VALU issue capacity: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a 64-wide
+# wave's non-packed FP32 instruction occupies its SIMD for 4 cycles)
+PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 METRIC = ("cell-snapshot RK-stage updates/s (FP32+batched vs FP64 plain); "
           "adjoint/primal time")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_sq_counters.txt")
 TUNE_CACHE = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
 KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
 
@@ -46,14 +50,14 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(tuning):
-    """HBM bytes per fused stage launch from the committed counter summary,
-    or None when it is missing or was taken on another kernel source or
-    launch configuration."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_profile_value(path, key, tuning):
+    """A per-launch figure of the fused stage kernel from a committed counter
+    summary, or None when it is missing or was taken on another kernel
+    source or launch configuration."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -64,9 +68,14 @@ def read_traffic(tuning):
     if kv.get("tuning") != t:
         return None
     try:
-        return float(kv["bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(tuning):
+    """HBM bytes per fused stage launch (FETCH_SIZE / WRITE_SIZE summary)."""
+    return read_profile_value(TRAFFIC_FILE, "bytes_per_launch", tuning)
 
 
 def algorithmic_bytes_per_iteration(problem) -> float:
@@ -251,6 +260,7 @@ def main():
     bytes_launch = algorithmic_bytes_per_iteration(problem) / stages
     achieved = bytes_launch / stage_s / 1e9
     traffic = read_traffic(tuning)
+    valu = read_profile_value(SQ_FILE, "valu_wave_instructions_per_launch", tuning)
     g.close()
 
     # ---- plain FP64, per-block launches (baseline on the same GPU) ---------
@@ -294,6 +304,12 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,
                      "algorithmic_bytes_per_launch": bytes_launch},
+        # the bound the shader counters show: VALU issue (64 lanes per
+        # wave-instruction) over the same live launch time
+        "roofline_alu": None if valu is None else {
+            "bound": "alu", "achieved": 64.0 * valu / stage_s, "peak": PEAK_VALU_LANE_INSTR,
+            "unit": "VALU lane-instructions/s", "frac": 64.0 * valu / stage_s / PEAK_VALU_LANE_INSTR,
+            "valu_wave_instructions_per_launch": valu},
         "adjoint_over_primal": None if args.no_adjoint else {
             name: adjoint_over_primal(torch, hb, synth, name, reps)
             for name, reps in (("naca256x128_hh64", 50), ("naca1024x512_nh4", 10))},
