@@ -67,6 +67,7 @@ void free_all(hb_grid *g) {
     dfree(g->ext_d); dfree(g->FI_d); dfree(g->FJ_d);
     dfree(g->q0_d); dfree(g->qa_d); dfree(g->qb_d);
     dfree(g->sa_f); dfree(g->sb_f);
+    dfree(g->dtau_f); dfree(g->dtau_d);
     dfree(g->partials_d); dfree(g->fpart_d); dfree(g->norm_tmp_d);
     dfree(g->status_d); dfree(g->ctr_d);
     dfree(g->body_off_d); dfree(g->body_ns_d);
@@ -387,9 +388,11 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     if (!f32) {
         rc = rc ? rc : dalloc(&g->qa_d, g->n_state);
         rc = rc ? rc : dalloc(&g->qb_d, g->n_state);
+        if (!plain) rc = rc ? rc : dalloc(&g->dtau_d, g->n_state / 4);
     } else {
         rc = rc ? rc : dalloc(&g->sa_f, g->n_state);
         rc = rc ? rc : dalloc(&g->sb_f, g->n_state);
+        if (!plain) rc = rc ? rc : dalloc(&g->dtau_f, g->n_state / 4);
     }
     rc = rc ? rc : dalloc(&g->fpart_d, (int64_t)nblocks * kMaxNs * 3);
     rc = rc ? rc : dalloc(&g->status_d, 1);

@@ -46,6 +46,7 @@ struct FusedArgs {
     const T *dqinf;        // sum_m D[n][m] Q_inf(m) per snapshot
     const double *ffq;     // free-stream conserved variables per snapshot (FP64)
     double *partials;      // per tile
+    T *dtau;               // local time step per cell-snapshot: written by the first stage
     int *status;
     T gamma, mu, kappa, mu_pr, cfl, delta, eps;
     double alpha;
@@ -274,21 +275,23 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             for (int v = 0; v < 4; ++v) own[m][v] = (m < ns && ns > 1) ? load_own(m, v) : T(0);
     }
 
-    // geometry of the own cell (time step): mean face normals and area
-    T vol = T(1), sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
-    double ivol = 1.0;
-    if (valid) {
+    // geometry of the own cell: the area and, for the time step (formed by
+    // the first stage of an iteration), the mean face normals.  Loaded by
+    // every lane (cell 0 for the helper row and cells outside the block).
+    T sxi = T(0), syi = T(0), sxj = T(0), syj = T(0);
+    if constexpr (FIRST && MODE != 0) {
         const int nfi = (ni + 1) * nj, nfj = ni * (nj + 1);
-        const unsigned fi0 = (unsigned)(j * (ni + 1) + i);
+        const unsigned fi0 = valid ? (unsigned)(j * (ni + 1) + i) : 0u;
         const T *SIx = a.SI + 2 * B.fi_off, *SIy = SIx + nfi;
         const T *SJx = a.SJ + 2 * B.fj_off, *SJy = SJx + nfj;
         sxi = T(0.5) * (ldg(SIx, fi0) + ldg(SIx + 1, fi0));
         syi = T(0.5) * (ldg(SIy, fi0) + ldg(SIy + 1, fi0));
         sxj = T(0.5) * (ldg(SJx, cidx) + ldg(SJx + ni, cidx));
         syj = T(0.5) * (ldg(SJy, cidx) + ldg(SJy + ni, cidx));
-        vol = ldg(a.V + B.cell_off, cidx);
-        ivol = 1.0 / (double)vol;
     }
+    const T vraw = ldg(a.V + B.cell_off, cidx);
+    const T vol = valid ? vraw : T(1);
+    const double ivol = 1.0 / (double)vol;
 
     // Sources of this thread's two ghost-extended cells (tid and tid + 256),
     // the same for every snapshot.  In a tile away from the block sides
@@ -423,12 +426,17 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         // base state of this snapshot for the update (loaded early)
         const int so = n * 4 * plane;     // snapshot offset (uniform)
         double b0[4] = {0.0, 0.0, 0.0, 0.0};
+        // local time step: formed from the base state by the first stage,
+        // which stores it; later stages load it (it is frozen over the stages)
+        T* const dtb = a.dtau + B.q_off / 4 + n * plane;
+        T dt = T(0);
         if constexpr (MODE != 0) {
             // unconditional (cidx = 0 for the helper row and cells outside
             // the block): a fixed count of loads lets the halo values of
             // this snapshot be consumed without waiting for these
 #pragma unroll
             for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
+            if constexpr (!FIRST) dt = ldg(dtb, cidx);
         }
         const T *fw = Tf + 8 * n;
         FS<T> f;
@@ -507,11 +515,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 for (int v = 0; v < 4; ++v) stg(ob + v * plane, cidx, (double)rs[v]);
             } else {
                 const double *fq = Td + 4 * n;
-                const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
-                                              (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
-                const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
-                const T dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl,
-                                         (T)B.omega_nh);
+                if constexpr (FIRST) {
+                    const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
+                                                  (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
+                    const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
+                    dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl, (T)B.omega_nh);
+                    stg(dtb, cidx, dt);
+                }
                 const double fac = a.alpha * (double)dt * ivol;
                 double nq[4];
 #pragma unroll
@@ -623,7 +633,7 @@ FusedArgs<float> make_args<float>(hb_grid *g) {
     a.blks = g->blk_d; a.tiles = g->tiles_d; a.gtab = g->gtab_d; a.n_tiles = g->n_tiles;
     a.SI = g->SI_f; a.dI = g->dI_f; a.SJ = g->SJ_f; a.dJ = g->dJ_f; a.V = g->V_f;
     a.D = g->D_f; a.ffw = g->ffw_f; a.dqinf = g->dqinf_f; a.ffq = g->ffq_d;
-    a.partials = g->partials_d; a.status = g->status_d;
+    a.partials = g->partials_d; a.status = g->status_d; a.dtau = g->dtau_f;
     a.gamma = (float)c.gamma; a.mu = (float)c.mu; a.kappa = (float)c.kappa;
     a.mu_pr = (float)(c.mu / c.prandtl); a.cfl = (float)c.cfl; a.delta = (float)c.delta_frac;
     a.eps = (float)c.eps;
@@ -638,7 +648,7 @@ FusedArgs<double> make_args<double>(hb_grid *g) {
     a.blks = g->blk_d; a.tiles = g->tiles_d; a.gtab = g->gtab_d; a.n_tiles = g->n_tiles;
     a.SI = g->SI_d; a.dI = g->dI_d; a.SJ = g->SJ_d; a.dJ = g->dJ_d; a.V = g->V_d;
     a.D = g->D_d; a.ffw = g->ffw_d; a.dqinf = g->dqinf_d; a.ffq = g->ffq_d;
-    a.partials = g->partials_d; a.status = g->status_d;
+    a.partials = g->partials_d; a.status = g->status_d; a.dtau = g->dtau_d;
     a.gamma = c.gamma; a.mu = c.mu; a.kappa = c.kappa; a.mu_pr = c.mu / c.prandtl; a.cfl = c.cfl;
     a.delta = c.delta_frac; a.eps = c.eps;
     a.h2d = c.delta_frac > 0.0 ? 0.5 / c.delta_frac : 0.0;

@@ -117,6 +117,8 @@ struct hb_grid {
     double *q0_d = nullptr;       // RK base state copy (plain path)
     double *qa_d = nullptr, *qb_d = nullptr;   // stage ping-pong (FP64)
     float *sa_f = nullptr, *sb_f = nullptr;    // stage ping-pong shadows (FP32 bulk)
+    float *dtau_f = nullptr;      // fused path: local time step of every cell-snapshot (FP32 bulk)
+    double *dtau_d = nullptr;     // the same for the fused FP64 path
     double *partials_d = nullptr; int64_t n_partials = 0;
     double *fpart_d = nullptr;    // force partials [block][kMaxNs][3]
     double *norm_tmp_d = nullptr;
