@@ -70,19 +70,38 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
                                 const UVT<double> &Q, double sx, double sy, double dx, double dy,
                                 const double Fb[4], const Consts &c, double *out, int64_t nf) {
     const double g = c.gamma;
+    // viscous part first (net flux = Roe - viscous: it sees -Fb, its mass
+    // term is 0): its node adjoints are final at once and are stored, which
+    // keeps fewer values live across the Roe reverse
+    double sxb = 0.0, syb = 0.0, dxb = 0.0, dyb = 0.0;
+    UVT<double> uLb{0, 0, 0}, uRb{0, 0, 0};
+    {
+        const double fvb[3] = {-Fb[1], -Fb[2], -Fb[3]};
+        const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
+        UVT<double> Pb{0, 0, 0}, Qb{0, 0, 0};
+        viscous_flux_rev(uL, uR, P, Q, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
+                         dxb, dyb);
+        out[16 * nf] = Pb.u;
+        out[17 * nf] = Pb.v;
+        out[18 * nf] = Pb.t;
+        out[19 * nf] = Qb.u;
+        out[20 * nf] = Qb.v;
+        out[21 * nf] = Qb.t;
+    }
+    W4<double> Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
+    {
+        const W4<double> m2 = ldw(e, plane, x[0]), m1 = ldw(e, plane, x[1]);
+        const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
+        W4<double> L, R;
+        muscl(m2, m1, p0, p1, c.eps, L, R);
+        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb);
+    }
+    out[22 * nf] = sxb;
+    out[23 * nf] = syb;
+    out[24 * nf] = dxb;
+    out[25 * nf] = dyb;
     const W4<double> m2 = ldw(e, plane, x[0]), m1 = ldw(e, plane, x[1]);
     const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
-    W4<double> L, R;
-    muscl(m2, m1, p0, p1, c.eps, L, R);
-    W4<double> Lb{0, 0, 0, 0}, Rb{0, 0, 0, 0};
-    double sxb = 0.0, syb = 0.0, dxb = 0.0, dyb = 0.0;
-    roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb);
-    // net flux = Roe - viscous: the viscous part sees -Fb (its mass term is 0)
-    const double fvb[3] = {-Fb[1], -Fb[2], -Fb[3]};
-    const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
-    UVT<double> uLb{0, 0, 0}, uRb{0, 0, 0}, Pb{0, 0, 0}, Qb{0, 0, 0};
-    viscous_flux_rev(uL, uR, P, Q, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
-                     dxb, dyb);
     double cb[4][4] = {{0}};
     const double Lv[4] = {Lb.r, Lb.u, Lb.v, Lb.p}, Rv[4] = {Rb.r, Rb.u, Rb.v, Rb.p};
     const double M2[4] = {m2.r, m2.u, m2.v, m2.p}, M1[4] = {m1.r, m1.u, m1.v, m1.p};
@@ -98,16 +117,6 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
     cb[2][0] = w2.r; cb[2][1] = w2.u; cb[2][2] = w2.v; cb[2][3] = w2.p;
     for (int r = 0; r < 4; ++r)
         for (int v = 0; v < 4; ++v) out[(r * 4 + v) * nf] = cb[r][v];
-    out[16 * nf] = Pb.u;
-    out[17 * nf] = Pb.v;
-    out[18 * nf] = Pb.t;
-    out[19 * nf] = Qb.u;
-    out[20 * nf] = Qb.v;
-    out[21 * nf] = Qb.t;
-    out[22 * nf] = sxb;
-    out[23 * nf] = syb;
-    out[24 * nf] = dxb;
-    out[25 * nf] = dyb;
 }
 
 // Node slots: i-faces store node (i, j) [edge start] in slot 0 (components
