@@ -197,12 +197,18 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
 }
 
 // node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
+// Also clears this block's node-coordinate adjoints (xyb, may be null),
+// which the fold and coordinate kernels then accumulate.
 __global__ void __launch_bounds__(kBS) k_adj_nodes(const BlockDesc *blks, int b, const double *AFI, const double *AFJ,
-                            double *NB) {
+                            double *NB, double *xyb) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nn = (int64_t)W * (B.nj + 1);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (xyb) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t k = t; k < 2 * nn; k += stride) xyb[2 * B.node_off + k] = 0.0;
+    }
     if (t >= nn * B.ns) return;
     const int n = (int)(t / nn);
     const int64_t k = t % nn;
@@ -231,14 +237,14 @@ __global__ void __launch_bounds__(kBS) k_adj_nodes(const BlockDesc *blks, int b,
     for (int v = 0; v < 3; ++v) o[v * nn] = s[v];
 }
 
-// primitive adjoints of every ghost-extended cell: [ns][4][nj+4][ni+4]
-__global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
-                            const double *AFJ, const double *NB, Consts c, double *WB) {
-    const BlockDesc &B = blks[b];
-    const int we = B.ni + 4;
-    const int64_t plane = (int64_t)we * (B.nj + 4);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= plane * B.ns) return;
+// Primitive adjoint of ghost-extended cell t of a block (all snapshots
+// flattened: [ns][4][nj+4][ni+4]); returns this cell's alpha0 adjoint term
+// when it is a far-field ghost (ffc != 0) and alpha is asked for:
+// d(u, v)/d alpha = (-v_inf, u_inf), a mirrored ghost flips both.
+__device__ __forceinline__ double adj_cell(const BlockDesc &B, int64_t t, int we, int64_t plane,
+                                           const double *ext, const double *AFI, const double *AFJ,
+                                           const double *NB, const Consts &c, double *WB,
+                                           const int8_t *ffc, const double *ffw, bool alpha) {
     const int n = (int)(t / plane);
     const int64_t r = t % plane;
     const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
@@ -285,6 +291,33 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
     o[plane] = wb.u;
     o[2 * plane] = wb.v;
     o[3 * plane] = wb.p;
+    if (!alpha || ffc[r] == 0) return 0.0;
+    const double *w = ffw + 4 * (B.snap_off + n);
+    return (double)ffc[r] * (wb.u * -w[2] + wb.v * w[1]);
+}
+
+// primitive adjoints of every ghost-extended cell; with apart (may be null)
+// also the alpha0 adjoint of the far-field ghosts as one partial per
+// workgroup (fixed-order tree sum)
+__global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
+                            const double *AFJ, const double *NB, Consts c, double *WB,
+                            const int8_t *ffc, const double *ffw, double *apart) {
+    const BlockDesc &B = blks[b];
+    const int we = B.ni + 4;
+    const int64_t plane = (int64_t)we * (B.nj + 4);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (t < plane * B.ns) acc = adj_cell(B, t, we, plane, ext, AFI, AFJ, NB, c, WB, ffc, ffw, apart != nullptr);
+    if (apart) {
+        __shared__ double red[kBS];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = kBS / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) apart[blockIdx.x] = red[0];
+    }
 }
 
 // interior cells: own adjoint + ghost copies -> conserved adjoint + HB
@@ -295,7 +328,22 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
                                                   const int *fptr, const int *fb, const int *fp,
                                                   const int *fm, const double *V, const double *D,
                                                   const double *xy, Consts c, double *qbar,
-                                                  double *xyb) {
+                                                  double *xyb, const double *apart, int64_t napart,
+                                                  double *flowbar) {
+    // workgroup 0 (of the first block's launch) first sums the alpha0
+    // partials of the cell-adjoint kernels, in a fixed order
+    if (flowbar && blockIdx.x == 0) {
+        __shared__ double red[kBS];
+        double acc = 0.0;
+        for (int64_t k = threadIdx.x; k < napart; k += kBS) acc += apart[k];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s2 = kBS / 2; s2 > 0; s2 >>= 1) {
+            if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *flowbar = red[0];
+    }
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -765,9 +813,13 @@ int adjoint_setup(hb_grid *g) {
     // inverse ghost map (CSR over global cells) and far-field ghost lists
     std::vector<std::vector<int>> eb(g->n_cells), ep(g->n_cells), em(g->n_cells);
     std::vector<int> ffptr(1, 0), ffp, ffm;
+    std::vector<int8_t> ffc;
+    g->ffc_off.assign(g->nblocks, 0);
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &K = g->blk[b];
         const int we = K.ni + 4;
+        g->ffc_off[b] = (int64_t)ffc.size();
+        ffc.resize(ffc.size() + (size_t)we * (K.nj + 4), 0);
         for (int je = 0; je < K.nj + 4; ++je)
             for (int ie = 0; ie < we; ++ie) {
                 const int i = ie - 2, j = je - 2;
@@ -783,6 +835,7 @@ int adjoint_setup(hb_grid *g) {
                 } else {
                     ffp.push_back(p);
                     ffm.push_back(s.mir);
+                    ffc[g->ffc_off[b] + p] = s.mir ? -1 : 1;
                 }
             }
         ffptr.push_back((int)ffp.size());
@@ -801,6 +854,7 @@ int adjoint_setup(hb_grid *g) {
     rc = rc ? rc : upload(&g->ff_ptr_d, ffptr);
     rc = rc ? rc : upload(&g->ff_p_d, ffp);
     rc = rc ? rc : upload(&g->ff_m_d, ffm);
+    rc = rc ? rc : upload(&g->ffc_d, ffc);
     if (rc) return rc;
     auto alloc = [&](double **p, int64_t n) {
         return check_hip(hipMalloc((void **)p, sizeof(double) * std::max<int64_t>(1, n)), "adjoint alloc");
@@ -818,6 +872,15 @@ int adjoint_setup(hb_grid *g) {
     }
     g->n_apart = np;
     rc = rc ? rc : alloc(&g->adj_part_d, np + 1);
+    // alpha0 partials of the residual adjoint: one per cell-adjoint workgroup
+    g->cpart_off.assign(g->nblocks, 0);
+    int64_t nc = 0;
+    for (int b = 0; b < g->nblocks; ++b) {
+        g->cpart_off[b] = nc;
+        nc += nblk((int64_t)(g->blk[b].ni + 4) * (g->blk[b].nj + 4) * g->blk[b].ns);
+    }
+    g->n_cpart = nc;
+    rc = rc ? rc : alloc(&g->cpart_d, nc);
     rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
     return rc;
@@ -840,32 +903,31 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     if (rc) return rc;
     double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
     const Consts c = g->consts;
-    if (xybar)
-        hipLaunchKernelGGL(k_zero, dim3(nblk(2 * g->n_nodes)), dim3(kBS), 0, s, xybar, 2 * g->n_nodes);
     for (int b = 0; b < g->nblocks; ++b) {
         rc = plain_ghost_fill(g, b, q, ext, s);
         if (rc) return rc;
     }
+    // the node kernels clear xybar; the cell kernels leave the alpha0
+    // partials, which the first fold launch sums
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
         hipLaunchKernelGGL(k_adj_faces, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d,
                            g->dI_d, g->SJ_d, g->dJ_d, rbar, c, g->AFI_d, g->AFJ_d, nI);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
-                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d);
+                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
         hipLaunchKernelGGL(k_adj_cells, dim3(nblk((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
-                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d);
+                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d,
+                           g->ffc_d + g->ffc_off[b], g->ffw_d,
+                           flowbar ? g->cpart_d + g->cpart_off[b] : (double *)nullptr);
     }
     // every block's extended adjoints exist before any fold (cuts read neighbours)
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
-                           g->V_d, g->D_d, g->xy_d, c, qbar, xybar);
-    }
-    if (flowbar) {
-        launch_alpha(g, s);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->n_apart, flowbar);
+                           g->V_d, g->D_d, g->xy_d, c, qbar, xybar, g->cpart_d, g->n_cpart,
+                           b == 0 ? flowbar : (double *)nullptr);
     }
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {
@@ -955,16 +1017,17 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
         hipLaunchKernelGGL(k_adj_force_face, dim3(nblk((int64_t)B.ni * B.ns)), dim3(kBS), 0, s,
                            g->blk_d, b, ext, g->xy_d, g->SJ_d, g->dJ_d, fa, c, g->AFJ_d, xybar);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
-                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d);
+                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, (double *)nullptr);
         hipLaunchKernelGGL(k_adj_cells, dim3(nblk((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
-                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d);
+                           s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d,
+                           g->ffc_d + g->ffc_off[b], g->ffw_d, (double *)nullptr);
     }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
                            g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, g->xy_d, c, qbar,
-                           (double *)nullptr);
+                           (double *)nullptr, (const double *)nullptr, (int64_t)0, (double *)nullptr);
     }
     if (flowbar) {
         launch_alpha(g, s);

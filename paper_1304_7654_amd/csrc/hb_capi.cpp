@@ -73,6 +73,8 @@ void free_all(hb_grid *g) {
     dfree(g->body_off_d); dfree(g->body_ns_d);
     dfree(g->tiles_d);
     dfree(g->gtab_d);
+    dfree(g->ffc_d);
+    dfree(g->cpart_d);
     dfree(g->adj_d);
     dfree(g->AFI_d); dfree(g->AFJ_d); dfree(g->NB_d); dfree(g->WBext_d); dfree(g->adj_part_d);
     dfree(g->fold_ptr_d); dfree(g->fold_b_d); dfree(g->fold_p_d); dfree(g->fold_m_d);

@@ -156,6 +156,13 @@ struct hb_grid {
     std::vector<int> apart_off;           // first alpha0 partial of each block
     int n_apart = 0;
     double *cf_adj_d = nullptr;           // forward force coefficients (forces adjoint)
+    // residual adjoint: far-field code of every ghost-extended cell (0: not a
+    // far-field ghost, 1: far field, -1: mirrored far field), blocks at
+    // ffc_off; alpha0 partials of the cell-adjoint workgroups at cpart_off
+    int8_t *ffc_d = nullptr;
+    std::vector<int64_t> ffc_off, cpart_off;
+    int64_t n_cpart = 0;
+    double *cpart_d = nullptr;
     // adjoint pseudo-time iteration scratch (allocated on first use)
     double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
     int64_t n_it_part = 0;
