@@ -44,6 +44,27 @@ namespace {
 constexpr int kBS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
 
+// forward pieces recomputed by the reverse sweeps, with adj_rcp in place of
+// the exact division: (u, v, T = gamma p / rho) of a primitive state and
+// the MUSCL / van Albada face states
+__device__ __forceinline__ UVT<double> uvt_a(const W4<double> &w, double g) {
+    return UVT<double>{w.u, w.v, g * w.p * adj_rcp(w.r)};
+}
+__device__ __forceinline__ double va_a(double a, double b, double eps) {
+    return (a + b) * (a * b + eps) * adj_rcp(a * a + b * b + 2.0 * eps);
+}
+__device__ __forceinline__ void muscl_a(const W4<double> &m2, const W4<double> &m1, const W4<double> &p0,
+                                        const W4<double> &p1, double eps, W4<double> &L, W4<double> &R) {
+    L.r = m1.r + 0.5 * va_a(m1.r - m2.r, p0.r - m1.r, eps);
+    L.u = m1.u + 0.5 * va_a(m1.u - m2.u, p0.u - m1.u, eps);
+    L.v = m1.v + 0.5 * va_a(m1.v - m2.v, p0.v - m1.v, eps);
+    L.p = m1.p + 0.5 * va_a(m1.p - m2.p, p0.p - m1.p, eps);
+    R.r = p0.r - 0.5 * va_a(p0.r - m1.r, p1.r - p0.r, eps);
+    R.u = p0.u - 0.5 * va_a(p0.u - m1.u, p1.u - p0.u, eps);
+    R.v = p0.v - 0.5 * va_a(p0.v - m1.v, p1.v - p0.v, eps);
+    R.p = p0.p - 0.5 * va_a(p0.p - m1.p, p1.p - p0.p, eps);
+}
+
 __device__ inline W4<double> ldw(const double *e, int64_t plane, int64_t idx) {
     return W4<double>{e[idx], e[plane + idx], e[2 * plane + idx], e[3 * plane + idx]};
 }
@@ -77,7 +98,7 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
     UVT<double> uLb{0, 0, 0}, uRb{0, 0, 0};
     {
         const double fvb[3] = {-Fb[1], -Fb[2], -Fb[3]};
-        const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
+        const UVT<double> uL = uvt_a(ldw(e, plane, x[1]), g), uR = uvt_a(ldw(e, plane, x[2]), g);
         UVT<double> Pb{0, 0, 0}, Qb{0, 0, 0};
         viscous_flux_rev(uL, uR, P, Q, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
                          dxb, dyb);
@@ -93,7 +114,7 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
         const W4<double> m2 = ldw(e, plane, x[0]), m1 = ldw(e, plane, x[1]);
         const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
         W4<double> L, R;
-        muscl(m2, m1, p0, p1, c.eps, L, R);
+        muscl_a(m2, m1, p0, p1, c.eps, L, R);
         roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb);
     }
     out[22 * nf] = sxb;
@@ -139,9 +160,9 @@ __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const d
     const int x[4] = {(int)(row + i), (int)(row + i + 1), (int)(row + i + 2), (int)(row + i + 3)};
     const double g = c.gamma;
     const int64_t lo = (int64_t)(j + 1) * we, hi = (int64_t)(j + 3) * we;
-    const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
-    const UVT<double> nA = avg4(uvt(ldw(e, plane, lo + i + 1), g), uvt(ldw(e, plane, lo + i + 2), g), uL, uR);
-    const UVT<double> nB = avg4(uL, uR, uvt(ldw(e, plane, hi + i + 1), g), uvt(ldw(e, plane, hi + i + 2), g));
+    const UVT<double> uL = uvt_a(ldw(e, plane, x[1]), g), uR = uvt_a(ldw(e, plane, x[2]), g);
+    const UVT<double> nA = avg4(uvt_a(ldw(e, plane, lo + i + 1), g), uvt_a(ldw(e, plane, lo + i + 2), g), uL, uR);
+    const UVT<double> nB = avg4(uL, uR, uvt_a(ldw(e, plane, hi + i + 1), g), uvt_a(ldw(e, plane, hi + i + 2), g));
     double rl[4], rr[4];
     rbar_cell(B, rbar, n, i - 1, j, rl);
     rbar_cell(B, rbar, n, i, j, rr);
@@ -168,12 +189,12 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
     const int x[4] = {(int)((int64_t)j * we + col), (int)((int64_t)(j + 1) * we + col),
                       (int)((int64_t)(j + 2) * we + col), (int)((int64_t)(j + 3) * we + col)};
     const double g = c.gamma;
-    const UVT<double> uL = uvt(ldw(e, plane, x[1]), g), uR = uvt(ldw(e, plane, x[2]), g);
+    const UVT<double> uL = uvt_a(ldw(e, plane, x[1]), g), uR = uvt_a(ldw(e, plane, x[2]), g);
     const int64_t r1 = (int64_t)(j + 1) * we, r2 = (int64_t)(j + 2) * we;
-    const UVT<double> nA = avg4(uvt(ldw(e, plane, r1 + col - 1), g), uL,
-                                uvt(ldw(e, plane, r2 + col - 1), g), uR);          // node (i, j)
-    const UVT<double> nB = avg4(uL, uvt(ldw(e, plane, r1 + col + 1), g), uR,
-                                uvt(ldw(e, plane, r2 + col + 1), g));              // node (i+1, j)
+    const UVT<double> nA = avg4(uvt_a(ldw(e, plane, r1 + col - 1), g), uL,
+                                uvt_a(ldw(e, plane, r2 + col - 1), g), uR);          // node (i, j)
+    const UVT<double> nB = avg4(uL, uvt_a(ldw(e, plane, r1 + col + 1), g), uR,
+                                uvt_a(ldw(e, plane, r2 + col + 1), g));              // node (i+1, j)
     double rl[4], rr[4];
     rbar_cell(B, rbar, n, i, j - 1, rl);
     rbar_cell(B, rbar, n, i, j, rr);

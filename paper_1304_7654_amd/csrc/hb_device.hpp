@@ -461,12 +461,24 @@ __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, 
 // adjoint of the outputs, and ADDS the adjoints of the inputs.
 // ---------------------------------------------------------------------------
 
+// Reciprocal for the reverse-mode code: the hardware estimate v_rcp_f64
+// refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which
+// squares the relative error; within an ulp or two of 1/x for the normal,
+// finite arguments met here (not correctly rounded, unlike 1.0 / x, and
+// about half its instructions).
+__device__ __forceinline__ double adj_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 // van Albada: returns v = VA(a, b) and its partial derivatives.
 __device__ __forceinline__ double van_albada_d(double a, double b, double eps, double &da,
                                                double &db) {
     const double N = (a + b) * (a * b + eps);
     const double Dn = a * a + b * b + 2.0 * eps;
-    const double iD = 1.0 / Dn;
+    const double iD = adj_rcp(Dn);
     const double v = N * iD;
     da = ((a * b + eps) + (a + b) * b - v * 2.0 * a) * iD;
     db = ((a * b + eps) + (a + b) * a - v * 2.0 * b) * iD;
@@ -499,14 +511,14 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
                                     W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb) {
     // ---- forward recomputation
     const double area = sqrt(sx * sx + sy * sy);
-    const double ia = 1.0 / area;
+    const double ia = adj_rcp(area);
     const double nx = sx * ia, ny = sy * ia;
-    const double gg = g / (g - 1.0);
-    const double irl = 1.0 / L.r, irr = 1.0 / R.r;
+    const double gg = g * adj_rcp(g - 1.0);
+    const double irl = adj_rcp(L.r), irr = adj_rcp(R.r);
     const double hl = gg * L.p * irl + 0.5 * (L.u * L.u + L.v * L.v);
     const double hr = gg * R.p * irr + 0.5 * (R.u * R.u + R.v * R.v);
     const double sl = sqrt(L.r), sr = sqrt(R.r);
-    const double iw = 1.0 / (sl + sr);
+    const double iw = adj_rcp(sl + sr);
     const double rt = sl * sr;
     const double ut = (sl * L.u + sr * R.u) * iw;
     const double vt = (sl * L.v + sr * R.v) * iw;
@@ -516,7 +528,8 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double qnt = ut * nx + vt * ny;
     const double dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
     const double dqn = du * nx + dv * ny;
-    const double ic2 = 1.0 / (ct * ct);
+    const double ict = adj_rcp(ct);
+    const double ic2 = ict * ict;
     const double X = rt * ct * dqn;
     const double a1 = (dp - X) * 0.5 * ic2;
     const double a4 = (dp + X) * 0.5 * ic2;
@@ -525,9 +538,10 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double r1 = fabs(lam1), r4 = fabs(lam4);
     double l1 = r1, l4 = r4;
     const double dd = delta_frac * ct;
+    const double idd = delta_frac > 0.0 ? adj_rcp(dd) : 0.0;
     const bool fix1 = delta_frac > 0.0 && r1 < dd, fix4 = delta_frac > 0.0 && r4 < dd;
-    if (fix1) l1 = (r1 * r1 + dd * dd) / (2.0 * dd);
-    if (fix4) l4 = (r4 * r4 + dd * dd) / (2.0 * dd);
+    if (fix1) l1 = (r1 * r1 + dd * dd) * (0.5 * idd);
+    if (fix4) l4 = (r4 * r4 + dd * dd) * (0.5 * idd);
     const double l2 = fabs(qnt);
     const double b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
     const double d0 = b1 + b4 + b2;
@@ -596,12 +610,12 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     double ddb = 0.0;
     double r1b = l1b, r4b = l4b;
     if (fix1) {
-        r1b = l1b * r1 / dd;
-        ddb += l1b * (dd * dd - r1 * r1) / (2.0 * dd * dd);
+        r1b = l1b * r1 * idd;
+        ddb += l1b * (dd * dd - r1 * r1) * (0.5 * idd * idd);
     }
     if (fix4) {
-        r4b = l4b * r4 / dd;
-        ddb += l4b * (dd * dd - r4 * r4) / (2.0 * dd * dd);
+        r4b = l4b * r4 * idd;
+        ddb += l4b * (dd * dd - r4 * r4) * (0.5 * idd * idd);
     }
     // d|x|/dx taken as sign(x) with sign(0) = 0, the average of the one-sided
     // derivatives (a wall face has q~_n = 0 exactly by symmetry)
@@ -618,7 +632,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     ctb += Xb * rt * dqn;
     dqnb += Xb * rt * ct;
     const double ic2b = 0.5 * (dp - X) * a1b + 0.5 * (dp + X) * a4b - dp * a2b;
-    ctb += ic2b * (-2.0 * ic2 / ct);
+    ctb += ic2b * (-2.0 * ic2 * ict);
     // qnt, dqn
     utb += qntb * nx;
     vtb += qntb * ny;
@@ -635,7 +649,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     Rb.p += dpb;
     Lb.p -= dpb;
     // ct = sqrt((g-1)(ht - q2t/2))
-    const double c2b = ctb / (2.0 * ct);
+    const double c2b = ctb * (0.5 * ict);
     htb += (g - 1.0) * c2b;
     q2tb -= 0.5 * (g - 1.0) * c2b;
     utb += 2.0 * ut * q2tb;
@@ -654,8 +668,9 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     hrb += htb * sr * iw;
     slb += htb * (hl - ht) * iw;
     srb += htb * (hr - ht) * iw;
-    Lb.r += slb / (2.0 * sl);
-    Rb.r += srb / (2.0 * sr);
+    // d sqrt(r) / dr = 1 / (2 sqrt(r)) = sqrt(r) / (2 r)
+    Lb.r += slb * (0.5 * sl * irl);
+    Rb.r += srb * (0.5 * sr * irr);
     // enthalpies
     Lb.p += hlb * gg * irl;
     Lb.r -= hlb * gg * L.p * irl * irl;
@@ -679,7 +694,7 @@ __device__ inline void viscous_flux_rev(const UVT<double> &L, const UVT<double> 
                                         UVT<double> &Pb, UVT<double> &Qb, double &sxb, double &syb,
                                         double &dxb, double &dyb) {
     const double den = dx * sx + dy * sy;
-    const double iden = 1.0 / den;
+    const double iden = adj_rcp(den);
     const double ax = sx * iden, ay = sy * iden, bx = dy * iden, by = -dx * iden;
     const double du = R.u - L.u, dv = R.v - L.v, dt = R.t - L.t;
     const double eu = P.u - Q.u, ev = P.v - Q.v, et = P.t - Q.t;
@@ -749,7 +764,7 @@ __device__ __forceinline__ void uvt_rev(const W4<double> &w, const UVT<double> &
                                         W4<double> &wb) {
     wb.u += b.u;
     wb.v += b.v;
-    const double ir = 1.0 / w.r;
+    const double ir = adj_rcp(w.r);
     wb.p += b.t * g * ir;
     wb.r -= b.t * g * w.p * ir * ir;
 }
@@ -757,7 +772,7 @@ __device__ __forceinline__ void uvt_rev(const W4<double> &w, const UVT<double> &
 // primitive adjoint -> conserved adjoint (rho, rho u, rho v, rho E)
 __device__ __forceinline__ void prim_rev(const W4<double> &w, const W4<double> &wb, double gm1,
                                          double qb[4]) {
-    const double ir = 1.0 / w.r;
+    const double ir = adj_rcp(w.r);
     qb[0] = wb.r - wb.u * w.u * ir - wb.v * w.v * ir + wb.p * gm1 * 0.5 * (w.u * w.u + w.v * w.v);
     qb[1] = wb.u * ir - wb.p * gm1 * w.u;
     qb[2] = wb.v * ir - wb.p * gm1 * w.v;
