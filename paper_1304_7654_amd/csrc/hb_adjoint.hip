@@ -366,6 +366,11 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
         if (threadIdx.x == 0) *flowbar = red[0];
     }
     const BlockDesc &B = blks[b];
+    // the block's D (N_s x N_s of the kNsPad x kNsPad table) in LDS: every
+    // thread reads all of it
+    __shared__ double dm[kMaxNs * kNsPad];
+    for (int k = threadIdx.x; k < kMaxNs * kNsPad; k += blockDim.x) dm[k] = D[B.d_off + k];
+    __syncthreads();
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= plane) return;
@@ -375,7 +380,6 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
     const int64_t own = (int64_t)(j + 2) * we + i + 2;
     const int64_t gc = B.cell_off + t;
     const double vol = V[gc];
-    const double *dm = D + B.d_off;
     const double gm1 = c.gamma - 1.0;
     const int ns = B.ns;
     // rbar of this cell, all snapshots, in registers (static indices only)
@@ -402,7 +406,9 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
         }
         const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
         const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
-        const W4<double> w = prim_from_cons<double>(qn[0], qn[1], qn[2], qn[3], gm1);
+        const double irq = adj_rcp(qn[0]);
+        const W4<double> w{qn[0], qn[1] * irq, qn[2] * irq,
+                           gm1 * (qn[3] - 0.5 * qn[0] * (qn[1] * irq * qn[1] * irq + qn[2] * irq * qn[2] * irq))};
         double qb[4];
         prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
         // HB source: d/dQ_n of sum_m rbar_m V (D Q)_m = V (D^T rbar)_n
