@@ -167,19 +167,23 @@ def cpu_baseline(problem, q_host, target_s=12.0):
            "sample": "%d of %d blocks (%d cell-snapshots), %d iteration(s), %.1f s"
                      % (len(sel), len(blocks), cs, iters, dt),
            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
-    # the same oracle on one thread, first sampled block only, one iteration
+    # the same oracle on one thread, first sampled block only, iterations
+    # repeated for about 2 s
     nt = torch.get_num_threads()
     torch.set_num_threads(1)
     b1 = [blocks[sel[0]]]
     q1 = qs[sel[0]].reshape(-1)
-    t0 = time.perf_counter()
-    O.rk_iterate(b1, q1, flow, solver, 1)
-    d1 = time.perf_counter() - t0
+    its, d1 = 0, 0.0
+    while d1 < 2.0:
+        t0 = time.perf_counter()
+        O.rk_iterate(b1, q1, flow, solver, 1)
+        d1 += time.perf_counter() - t0
+        its += 1
     torch.set_num_threads(nt)
     c1 = b1[0].ns * b1[0].ni * b1[0].nj
-    out["single_thread"] = {"value": c1 * len(solver.rk_alpha) / d1,
-                            "sample": "block %d (%d cell-snapshots), 1 iteration, %.1f s"
-                                      % (sel[0], c1, d1)}
+    out["single_thread"] = {"value": c1 * len(solver.rk_alpha) * its / d1,
+                            "sample": "block %d (%d cell-snapshots), %d iteration(s), %.1f s"
+                                      % (sel[0], c1, its, d1)}
     return out
 
 
