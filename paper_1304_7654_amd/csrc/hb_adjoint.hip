@@ -342,15 +342,15 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
 }
 
 // interior cells: own adjoint + ghost copies -> conserved adjoint + HB
-// source D^T rbar; with xyb also the cell-area term of the HB source,
-// rbar . V (D Q) -> dV, as node adjoints (rbar == nullptr: no HB source).
+// source D^T rbar; with VB also the adjoint of the cell area from the HB
+// source, rbar . (D Q), stored per cell for the coordinate node gather
+// (rbar == nullptr: no HB source).
 __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, const double *q,
                                                   const double *rbar, const double *WB,
                                                   const int *fptr, const int *fb, const int *fp,
                                                   const int *fm, const double *V, const double *D,
-                                                  const double *xy, Consts c, double *qbar,
-                                                  double *xyb, const double *apart, int64_t napart,
-                                                  double *flowbar) {
+                                                  Consts c, double *qbar, const double *apart,
+                                                  int64_t napart, double *flowbar, double *VB) {
     // workgroup 0 (of the first block's launch) first sums the alpha0
     // partials of the cell-adjoint kernels, in a fixed order
     if (flowbar && blockIdx.x == 0) {
@@ -427,24 +427,9 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
             vb += qn[v] * hw[v];
         }
     }
-    if (xyb && rbar) {
-        // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over the cell's nodes
-        const int W = B.ni + 1;
-        const int64_t nn = (int64_t)W * (B.nj + 1);
-        const double *x = xy + 2 * B.node_off, *y = x + nn;
-        double *xb = xyb + 2 * B.node_off;
-        double *yb = xb + nn;
-        const int64_t k1 = (int64_t)j * W + i, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
-        const double h = 0.5 * vb;
-        unsafeAtomicAdd(xb + k3, h * (y[k4] - y[k2]));
-        unsafeAtomicAdd(xb + k1, -h * (y[k4] - y[k2]));
-        unsafeAtomicAdd(yb + k4, h * (x[k3] - x[k1]));
-        unsafeAtomicAdd(yb + k2, -h * (x[k3] - x[k1]));
-        unsafeAtomicAdd(yb + k3, -h * (x[k4] - x[k2]));
-        unsafeAtomicAdd(yb + k1, h * (x[k4] - x[k2]));
-        unsafeAtomicAdd(xb + k4, -h * (y[k3] - y[k1]));
-        unsafeAtomicAdd(xb + k2, h * (y[k3] - y[k1]));
-    }
+    // adjoint of the cell area (its node derivatives are taken by the
+    // coordinate node gather)
+    if (VB) VB[gc] = rbar ? vb : 0.0;
 }
 
 // alpha0: far-field ghost adjoints . d w_inf / d alpha0; one thread per
@@ -576,10 +561,19 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
     }
 }
 
+// Coordinate adjoints, in two steps.  Per face: the adjoints of S and d
+// summed over the snapshots are stored (G), and the ghost side of a face on
+// a block side goes through ghost_centre_rev (atomic adds, possibly into a
+// neighbour block).  Per node: the face-length parts of the (up to) four
+// faces at the node, the centre parts of the (up to) four cells around it
+// (a cell centre is the mean of its nodes; its adjoint is the sum over its
+// faces of +d for the faces where it is R and -d where it is L) and the cell
+// areas' adjoints (VB, from the HB source) are gathered and added, without
+// atomics.
 // i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
 // d = centre(R) - centre(L)
 __device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb, int64_t tid_) {
+                           const double *C, double *xyb, double *G, int64_t n_fi, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
@@ -594,24 +588,19 @@ __device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const dou
         dxb += a[24 * nf];
         dyb += a[25 * nf];
     }
-    const int64_t nn = (int64_t)W * (B.nj + 1);
-    double *xb = xyb + 2 * B.node_off;
-    double *yb = xb + nn;
+    double *g = G + B.fi_off + f;
+    g[0] = sxb;
+    g[n_fi] = syb;
+    g[2 * n_fi] = dxb;
+    g[3 * n_fi] = dyb;
     const int64_t kA = (int64_t)j * W + i, kB = kA + W;
-    xadd(yb, kB, sxb);
-    xadd(yb, kA, -sxb);
-    xadd(xb, kA, syb);
-    xadd(xb, kB, -syb);
-    // d = C_R - C_L
-    if (i < B.ni) centre_to_nodes(blks, b, i, j, dxb, dyb, xyb);
-    else ghost_centre_rev(blks, b, 1, B.ni - 1, j, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
-    if (i > 0) centre_to_nodes(blks, b, i - 1, j, -dxb, -dyb, xyb);
-    else ghost_centre_rev(blks, b, 0, 0, j, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
+    if (i == B.ni) ghost_centre_rev(blks, b, 1, B.ni - 1, j, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
+    if (i == 0) ghost_centre_rev(blks, b, 0, 0, j, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
 // j-faces: S_J = (yA - yB, xB - xA), A = node (i, j), B = node (i+1, j)
 __device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb, int64_t tid_) {
+                           const double *C, double *xyb, double *G, int64_t n_fj, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
@@ -626,27 +615,76 @@ __device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const dou
         dxb += a[24 * nf];
         dyb += a[25 * nf];
     }
-    const int64_t nn = (int64_t)W * (B.nj + 1);
-    double *xb = xyb + 2 * B.node_off;
-    double *yb = xb + nn;
+    double *g = G + B.fj_off + f;
+    g[0] = sxb;
+    g[n_fj] = syb;
+    g[2 * n_fj] = dxb;
+    g[3 * n_fj] = dyb;
     const int64_t kA = (int64_t)j * W + i, kB = kA + 1;
-    xadd(yb, kA, sxb);
-    xadd(yb, kB, -sxb);
-    xadd(xb, kB, syb);
-    xadd(xb, kA, -syb);
-    if (j < B.nj) centre_to_nodes(blks, b, i, j, dxb, dyb, xyb);
-    else ghost_centre_rev(blks, b, 3, i, B.nj - 1, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
-    if (j > 0) centre_to_nodes(blks, b, i, j - 1, -dxb, -dyb, xyb);
-    else ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
+    if (j == B.nj) ghost_centre_rev(blks, b, 3, i, B.nj - 1, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
+    if (j == 0) ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
-// one launch for the node-coordinate adjoints of both face families
+// per-face step for both face families of block b in one launch
 __global__ void __launch_bounds__(kBS) k_adj_xy(const BlockDesc *blks, int b, const double *AFI,
                                                 const double *AFJ, const double *xy, const double *C,
-                                                double *xyb, int64_t nI) {
+                                                double *xyb, double *G, int64_t n_fi, int64_t n_fj,
+                                                int64_t nI) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nI) adj_xy_i(blks, b, AFI, xy, C, xyb, t);
-    else adj_xy_j(blks, b, AFJ, xy, C, xyb, t - nI);
+    if (t < nI) adj_xy_i(blks, b, AFI, xy, C, xyb, G, n_fi, t);
+    else adj_xy_j(blks, b, AFJ, xy, C, xyb, G + 4 * n_fi, n_fj, t - nI);
+}
+
+// per-node step: one thread per node of block b
+__global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int b, const double *G,
+                                                      int64_t n_fi, int64_t n_fj, const double *VB,
+                                                      const double *xy, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int ni = B.ni, nj = B.nj, W = ni + 1;
+    const int64_t nn = (int64_t)W * (nj + 1);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    const int i = (int)(k % W), j = (int)(k / W);
+    const double *gi = G + B.fi_off, *gj = G + 4 * n_fi + B.fj_off;
+    auto GI = [&](int fi, int fj, int c) { return gi[c * n_fi + (int64_t)fj * W + fi]; };
+    auto GJ = [&](int fi, int fj, int c) { return gj[c * n_fj + (int64_t)fj * ni + fi]; };
+    double ax = 0.0, ay = 0.0;
+    // face lengths: i-face (i, j) has this node as A, i-face (i, j-1) as B;
+    // j-face (i, j) as A, j-face (i-1, j) as B
+    if (j < nj) { ay -= GI(i, j, 0); ax += GI(i, j, 1); }
+    if (j > 0) { ay += GI(i, j - 1, 0); ax -= GI(i, j - 1, 1); }
+    if (i < ni) { ay += GJ(i, j, 0); ax -= GJ(i, j, 1); }
+    if (i > 0) { ay -= GJ(i - 1, j, 0); ax += GJ(i - 1, j, 1); }
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    for (int dj = -1; dj <= 0; ++dj)
+        for (int di = -1; di <= 0; ++di) {
+            const int ci = i + di, cj = j + dj;
+            if (ci < 0 || ci >= ni || cj < 0 || cj >= nj) continue;
+            ax += 0.25 * (GI(ci, cj, 2) - GI(ci + 1, cj, 2) + GJ(ci, cj, 2) - GJ(ci, cj + 1, 2));
+            ay += 0.25 * (GI(ci, cj, 3) - GI(ci + 1, cj, 3) + GJ(ci, cj, 3) - GJ(ci, cj + 1, 3));
+            if (VB) {
+                // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over nodes
+                // 1 = (ci, cj), 2 = (ci+1, cj), 3 = (ci+1, cj+1), 4 = (ci, cj+1)
+                const double h = 0.5 * VB[B.cell_off + (int64_t)cj * ni + ci];
+                const int64_t k1 = (int64_t)cj * W + ci, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
+                if (di == 0 && dj == 0) {          // node 1
+                    ax -= h * (y[k4] - y[k2]);
+                    ay += h * (x[k4] - x[k2]);
+                } else if (di == -1 && dj == 0) {  // node 2
+                    ax += h * (y[k3] - y[k1]);
+                    ay -= h * (x[k3] - x[k1]);
+                } else if (di == -1) {             // node 3
+                    ax += h * (y[k4] - y[k2]);
+                    ay -= h * (x[k4] - x[k2]);
+                } else {                           // node 4
+                    ax -= h * (y[k3] - y[k1]);
+                    ay += h * (x[k3] - x[k1]);
+                }
+            }
+        }
+    double *xb = xyb + 2 * B.node_off;
+    xb[k] += ax;
+    xb[nn + k] += ay;
 }
 
 // ---- force coefficients ------------------------------------------------------
@@ -908,6 +946,8 @@ int adjoint_setup(hb_grid *g) {
     }
     g->n_cpart = nc;
     rc = rc ? rc : alloc(&g->cpart_d, nc);
+    rc = rc ? rc : alloc(&g->geo_d, 4 * (g->n_fi + g->n_fj));
+    rc = rc ? rc : alloc(&g->vb_d, g->n_cells);
     rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
     return rc;
@@ -953,15 +993,17 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
-                           g->V_d, g->D_d, g->xy_d, c, qbar, xybar, g->cpart_d, g->n_cpart,
-                           b == 0 ? flowbar : (double *)nullptr);
+                           g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
+                           b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr);
     }
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
             const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
-                               g->AFJ_d, g->xy_d, g->C_d, xybar, nI);
+                               g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
+            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
+                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d, g->xy_d, xybar);
         }
     }
     return check_hip(hipGetLastError(), "adjoint launch");
@@ -1053,8 +1095,8 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
-                           g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, g->xy_d, c, qbar,
-                           (double *)nullptr, (const double *)nullptr, (int64_t)0, (double *)nullptr);
+                           g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, c, qbar,
+                           (const double *)nullptr, (int64_t)0, (double *)nullptr, (double *)nullptr);
     }
     if (flowbar) {
         launch_alpha(g, s);
@@ -1069,7 +1111,10 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
             const BlockDesc &B = g->blk[b];
             const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
-                               g->AFJ_d, g->xy_d, g->C_d, xybar, nI);
+                               g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
+            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
+                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, g->xy_d,
+                               xybar);
         }
     }
     return check_hip(hipGetLastError(), "forces adjoint launch");

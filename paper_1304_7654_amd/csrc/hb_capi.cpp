@@ -75,6 +75,8 @@ void free_all(hb_grid *g) {
     dfree(g->gtab_d);
     dfree(g->ffc_d);
     dfree(g->cpart_d);
+    dfree(g->geo_d);
+    dfree(g->vb_d);
     dfree(g->adj_d);
     dfree(g->AFI_d); dfree(g->AFJ_d); dfree(g->NB_d); dfree(g->WBext_d); dfree(g->adj_part_d);
     dfree(g->fold_ptr_d); dfree(g->fold_b_d); dfree(g->fold_p_d); dfree(g->fold_m_d);

@@ -163,6 +163,10 @@ struct hb_grid {
     std::vector<int64_t> ffc_off, cpart_off;
     int64_t n_cpart = 0;
     double *cpart_d = nullptr;
+    // coordinate adjoint: per-face sums over snapshots of (S_x, S_y, d_x, d_y)
+    // adjoints (i-faces [4][n_fi], then j-faces [4][n_fj]) and the per-cell
+    // adjoint of the cell area from the HB source
+    double *geo_d = nullptr, *vb_d = nullptr;
     // adjoint pseudo-time iteration scratch (allocated on first use)
     double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
     int64_t n_it_part = 0;
