@@ -89,6 +89,28 @@ def algorithmic_bytes_per_iteration(problem) -> float:
     return cs * (48 + 64 + 64 + 80) + 4 * 36 * cells
 
 
+def stream_probe(torch, mib=1024, reps=10):
+    """Device copy bandwidth (read + write bytes per second) of a plain
+    torch copy of `mib` MiB, the practical HBM peak the traffic is also set
+    against."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def time_steps(torch, g, q, steps, forces=True):
     cf = torch.empty(g.n_forces, dtype=torch.float64, device=q.device) if forces else None
     norms = torch.empty(steps, dtype=torch.float64, device=q.device)
@@ -266,6 +288,7 @@ def main():
     traffic = read_traffic(tuning)
     valu = read_profile_value(SQ_FILE, "valu_wave_instructions_per_launch", tuning)
     g.close()
+    probe = stream_probe(torch)
 
     # ---- plain FP64, per-block launches (baseline on the same GPU) ---------
     gp = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=0)
@@ -307,7 +330,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     # measured HBM traffic (counters) over the live launch time, against
+                     # the 8 TB/s peak and against a 1 GiB device copy measured here
+                     "traffic_gbs": None if traffic is None else traffic / stage_s / 1e9,
+                     "traffic_frac": None if traffic is None else traffic / stage_s / 1e9 / PEAK_HBM_GBS,
+                     "stream_probe_gbs": probe,
+                     "frac_of_stream_probe": achieved / probe,
+                     "traffic_frac_of_stream_probe": None if traffic is None else traffic / stage_s / 1e9 / probe},
         # the bound the shader counters show: VALU issue (64 lanes per
         # wave-instruction) over the same live launch time
         "roofline_alu": None if valu is None else {
