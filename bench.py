@@ -127,7 +127,8 @@ def time_steps(torch, g, q, steps, forces=True):
 
 def adjoint_over_primal(torch, hb, synth, name, reps):
     """t(hb_residual_adjoint with state, coordinate and incidence bars) over
-    t(hb_residual), both FP64 on the same grid and state, HIP events."""
+    t(hb_residual), both FP64 on the same grid and state, HIP events (median
+    of three interleaved trials each)."""
     p = synth.make_problem(name)
     g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
     dev = torch.device("cuda:0")
@@ -151,8 +152,12 @@ def adjoint_over_primal(torch, hb, synth, name, reps):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    tp = timed(lambda: g.residual(q, r))
-    ta = timed(lambda: g.residual_adjoint(q, rbar, qb, xyb, ab))
+    # three interleaved trials of each, medians
+    tps, tas = [], []
+    for _ in range(3):
+        tps.append(timed(lambda: g.residual(q, r)))
+        tas.append(timed(lambda: g.residual_adjoint(q, rbar, qb, xyb, ab)))
+    tp, ta = sorted(tps)[1], sorted(tas)[1]
     g.close()
     return {"primal_ms": tp, "adjoint_ms": ta, "ratio": ta / tp,
             "cell_snapshots": p.cell_snapshots}
