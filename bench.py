@@ -42,11 +42,22 @@ TUNE_CACHE = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
 KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
 
 
+def code_text(src: str) -> str:
+    """Source text without comments and blank-space differences, so that a
+    comment edit does not count as a kernel change."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_hash() -> str:
+    """Hash of the stage kernel's code (comments excluded), recorded in the
+    counter summaries taken on it."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -107,9 +107,10 @@ typedef struct {
  *     FP32; state, update, norms and forces in FP64)
  *   entropy_delta: Harten fix width as a fraction of the Roe sound speed
  *   limiter_eps: van Albada epsilon
- *   batched: 1 = all blocks in one persistent launch per stage (fused
- *     line-tile kernel); 0 = plain per-block launches (separate ghost,
- *     face-flux and update kernels, FP64 only)
+ *   batched: 1 = all blocks in one launch per stage (fused tile kernel,
+ *     launch configuration from hb_set_tuning / hb_autotune); 0 = plain
+ *     per-block launches (separate ghost, face-flux and update kernels,
+ *     FP64 only)
  *   graph_iters: iterations captured per HIP graph replay (>= 1) */
 typedef struct {
     double cfl;
@@ -127,7 +128,8 @@ typedef struct {
  *               (0 = the occupancy maximum; larger values are capped by it;
  *               -1 = no persistent grid, one workgroup per tile)
  *   xcd_order:  1 = renumber workgroups so that the workgroups of one XCD
- *               (one L2) take consecutive tiles
+ *               (one L2) take consecutive tiles (chunks of grid/8 tiles for
+ *               a persistent grid, of 32 tiles for one workgroup per tile)
  *   tile_order: 0 = tiles of a block row by row, 1 = column by column
  *   stage_ms:   measured mean stage time (output; 0 when not measured)
  * The tuning changes which workgroup computes which tile, never a cell's

@@ -1,22 +1,24 @@
 // Fused, batched residual / Runge-Kutta stage kernel.
 //
-// One persistent launch per stage covers every block of the grid: the
-// blocks are cut into tiles of 16 x 15 cells (256 threads, one per cell of a
-// 16 x 16 thread grid whose last row only helps),
-// listed in a flat tile table; each workgroup walks the table with a fixed
-// stride.  Per tile:
+// One launch per stage covers every block of the grid: the blocks are cut
+// into tiles of 16 x 15 (or 32 x 7) cells (256 threads, one per cell of a
+// 16 x 16 or 32 x 8 thread grid whose last row only helps), listed in a
+// flat tile table sorted by snapshot count; the grid is one workgroup per
+// tile or a persistent grid walking the table with a fixed stride (chosen
+// by the autotuner, with an optional XCD-aware order).  Per tile:
 //   A. every thread loads its cell's state for all N_s snapshots (as the
 //      deviation from each snapshot's free stream);
 //   B. the HB source D (Q - Q_inf) of the tile, a [cells x N_s] x [N_s x N_s]
 //      product, runs on the matrix cores (FP32: v_mfma 16x16x4, operands
 //      staged through LDS); FP64 tiles use FMA;
-//   C. for each snapshot: the ghost-extended tile (2-cell halo, boundary
-//      rules applied on the fly) is staged in LDS as primitive perturbations,
-//      node averages of (u, v, T) are formed, each i- and j-face flux
-//      (MUSCL/van Albada + Roe, diamond-path viscous) is computed once, and
-//      each cell sums its four faces, adds V (D Q), and either writes R* or
-//      performs the Runge-Kutta update in FP64 from the iteration's base
-//      state, with the local time step recomputed from that base state.
+//   C. for each snapshot: the ghost-extended tile (2-cell halo; the sources
+//      of a tile at a block side come from its host-built halo table) is
+//      staged in LDS as primitive perturbations, node averages of (u, v, T)
+//      are formed, each i- and j-face flux (MUSCL/van Albada + Roe,
+//      diamond-path viscous) is computed once, and each cell sums its four
+//      faces, adds V (D Q), and either writes R* or performs the Runge-Kutta
+//      update in FP64 from the iteration's base state, with the local time
+//      step formed from that base state by the iteration's first stage.
 // The per-tile partial of sum (R*_rho / V)^2 goes to partials[tile]; a second
 // kernel sums the partials in a fixed order (deterministic norm).
 #include "hb_device.hpp"
