@@ -345,12 +345,18 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
 // source D^T rbar; with VB also the adjoint of the cell area from the HB
 // source, rbar . (D Q), stored per cell for the coordinate node gather
 // (rbar == nullptr: no HB source).
+// PER_SNAP: one thread per cell and snapshot (small blocks, which would
+// otherwise leave CUs idle), each writing its snapshot's share of the
+// cell-area adjoint to VB[n * vbs + cell]; else one thread per cell looping
+// over the snapshots, writing VB[cell].
+template <bool PER_SNAP>
 __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, const double *q,
                                                   const double *rbar, const double *WB,
                                                   const int *fptr, const int *fb, const int *fp,
                                                   const int *fm, const double *V, const double *D,
                                                   Consts c, double *qbar, const double *apart,
-                                                  int64_t napart, double *flowbar, double *VB) {
+                                                  int64_t napart, double *flowbar, double *VB,
+                                                  int64_t vbs) {
     // workgroup 0 (of the first block's launch) first sums the alpha0
     // partials of the cell-adjoint kernels, in a fixed order
     if (flowbar && blockIdx.x == 0) {
@@ -372,8 +378,11 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
     for (int k = threadIdx.x; k < kMaxNs * kNsPad; k += blockDim.x) dm[k] = D[B.d_off + k];
     __syncthreads();
     const int64_t plane = (int64_t)B.ni * B.nj;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= plane) return;
+    const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tt >= (PER_SNAP ? plane * B.ns : plane)) return;
+    const int64_t t = PER_SNAP ? tt % plane : tt;
+    const int nlo = PER_SNAP ? (int)(tt / plane) : 0;
+    const int nhi = PER_SNAP ? nlo + 1 : B.ns;
     const int i = (int)(t % B.ni), j = (int)(t / B.ni);
     const int we = B.ni + 4;
     const int64_t eplane = (int64_t)we * (B.nj + 4);
@@ -390,7 +399,7 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
         for (int v = 0; v < 4; ++v)
             rb[m][v] = (rbar && m < ns) ? rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t] : 0.0;
     double vb = 0.0;
-    for (int n = 0; n < ns; ++n) {
+    for (int n = nlo; n < nhi; ++n) {
         const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
         double wbv[4];
         for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
@@ -429,7 +438,7 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
     }
     // adjoint of the cell area (its node derivatives are taken by the
     // coordinate node gather)
-    if (VB) VB[gc] = rbar ? vb : 0.0;
+    if (VB) VB[(int64_t)nlo * vbs + gc] = rbar ? vb : 0.0;
 }
 
 // alpha0: far-field ghost adjoints . d w_inf / d alpha0; one thread per
@@ -638,7 +647,8 @@ __global__ void __launch_bounds__(kBS) k_adj_xy(const BlockDesc *blks, int b, co
 // per-node step: one thread per node of block b
 __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int b, const double *G,
                                                       int64_t n_fi, int64_t n_fj, const double *VB,
-                                                      const double *xy, double *xyb) {
+                                                      int nvb, int64_t vbs, const double *xy,
+                                                      double *xyb) {
     const BlockDesc &B = blks[b];
     const int ni = B.ni, nj = B.nj, W = ni + 1;
     const int64_t nn = (int64_t)W * (nj + 1);
@@ -665,7 +675,9 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int
             if (VB) {
                 // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over nodes
                 // 1 = (ci, cj), 2 = (ci+1, cj), 3 = (ci+1, cj+1), 4 = (ci, cj+1)
-                const double h = 0.5 * VB[B.cell_off + (int64_t)cj * ni + ci];
+                double vsum = 0.0;
+                for (int m = 0; m < nvb; ++m) vsum += VB[(int64_t)m * vbs + B.cell_off + (int64_t)cj * ni + ci];
+                const double h = 0.5 * vsum;
                 const int64_t k1 = (int64_t)cj * W + ci, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
                 if (di == 0 && dj == 0) {          // node 1
                     ax -= h * (y[k4] - y[k2]);
@@ -947,11 +959,15 @@ int adjoint_setup(hb_grid *g) {
     g->n_cpart = nc;
     rc = rc ? rc : alloc(&g->cpart_d, nc);
     rc = rc ? rc : alloc(&g->geo_d, 4 * (g->n_fi + g->n_fj));
-    rc = rc ? rc : alloc(&g->vb_d, g->n_cells);
+    rc = rc ? rc : alloc(&g->vb_d, (int64_t)kMaxNs * g->n_cells);
     rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
     return rc;
 }
+
+// fold one thread per cell and snapshot when one per cell would leave most
+// CUs idle (fewer than 256 workgroups)
+bool fold_per_snap(const BlockDesc &B) { return (int64_t)B.ni * B.nj < 256 * (int64_t)kBS; }
 
 void launch_alpha(hb_grid *g, hipStream_t s) {
     for (int b = 0; b < g->nblocks; ++b) {
@@ -991,10 +1007,19 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
     // every block's extended adjoints exist before any fold (cuts read neighbours)
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
-        hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
-                           q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
-                           g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
-                           b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr);
+        const int64_t nc = (int64_t)B.ni * B.nj;
+        if (fold_per_snap(B))
+            hipLaunchKernelGGL(k_adj_fold<true>, dim3(nblk(nc * B.ns)), dim3(kBS), 0, s, g->blk_d, b,
+                               q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
+                               g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
+                               b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr,
+                               g->n_cells);
+        else
+            hipLaunchKernelGGL(k_adj_fold<false>, dim3(nblk(nc)), dim3(kBS), 0, s, g->blk_d, b,
+                               q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
+                               g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
+                               b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr,
+                               g->n_cells);
     }
     if (xybar) {
         for (int b = 0; b < g->nblocks; ++b) {
@@ -1003,7 +1028,8 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
                                g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
             hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d, g->xy_d, xybar);
+                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d,
+                               fold_per_snap(B) ? B.ns : 1, g->n_cells, g->xy_d, xybar);
         }
     }
     return check_hip(hipGetLastError(), "adjoint launch");
@@ -1093,10 +1119,11 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
     }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
-        hipLaunchKernelGGL(k_adj_fold, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+        hipLaunchKernelGGL(k_adj_fold<false>, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
                            g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, c, qbar,
-                           (const double *)nullptr, (int64_t)0, (double *)nullptr, (double *)nullptr);
+                           (const double *)nullptr, (int64_t)0, (double *)nullptr, (double *)nullptr,
+                           (int64_t)0);
     }
     if (flowbar) {
         launch_alpha(g, s);
@@ -1113,8 +1140,8 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
                                g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
             hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, g->xy_d,
-                               xybar);
+                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, 0,
+                               (int64_t)0, g->xy_d, xybar);
         }
     }
     return check_hip(hipGetLastError(), "forces adjoint launch");
