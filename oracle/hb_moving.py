@@ -1,0 +1,244 @@
+"""FP64 CPU oracle of the HB residual, pseudo-time iteration and loads on a
+rigidly heaving and pitching grid (the paper's test case 1 is a heaving and
+pitching wing, §Experimental Setup, Test case 1; the paper gives no moving-
+grid equations).
+
+TEST INFRASTRUCTURE ONLY, like hb_oracle (same import rules; it shares no
+code with the HIP library).
+
+Reading (the textbook arbitrary Lagrangian-Eulerian finite-volume form):
+  * the whole grid moves rigidly.  Snapshot n (omega t_n = 2 pi n / N_s)
+    holds the body-frame nodes x0 rotated counter-clockwise by theta_n about
+    the pivot p and raised by h_n:  x_n = R(theta_n)(x0 - p) + p + (0, h_n),
+    theta(t) = A_theta sin(omega t + phi), h(t) = A_h sin(omega t);
+  * a grid point moves with the rigid velocity
+    x_t = theta_dot k x (x - p - (0, h)) + (0, h_dot);
+  * face flux F.S - (x_t . S) U with x_t at the face midpoint, Roe's
+    dissipation on the eigenvalues relative to the face (roe_flux with vg);
+    the viscous flux is the fixed-grid one on the snapshot's grid;
+  * cell areas do not change, so the HB term stays V (D Q)_n, and the
+    midpoint face speeds of a linear velocity field sum to zero around every
+    cell (the discrete geometric conservation law holds exactly);
+  * no-slip walls move: a wall ghost mirrors the velocity about the wall
+    velocity, u_g = 2 u_w - u, u_w = x_t at the midpoint of the wall face
+    of the mirrored cell's column (for corner ghosts: the i-periodic partner
+    column, else the nearest column);
+  * far field: the free stream at the (fixed) incidence alpha0 (plus any
+    alpha_amp forcing, unchanged);
+  * local time step: the fixed-grid formula on the snapshot's grid with the
+    velocity relative to the grid at the cell centre;
+  * loads: fixed-grid loads on the snapshot's grid, the moment about the
+    reference point carried with the body; lift and drag along the mean
+    free stream.
+Grids with i-side walls or cuts are outside this reading (ValueError).
+
+Parity status: pinned in tests/test_oracle_moving.py (zero motion, heave as
+a Galilean shift, rotation equivariance, free-stream preservation on a
+pitching and heaving grid, grid velocity against differenced positions,
+no-slip wall images).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import torch
+
+from oracle import hb_oracle as O
+
+DT = torch.float64
+
+
+@dataclass
+class OMotion:
+    pitch_amp: float = 0.0      # A_theta, radians, counter-clockwise positive
+    pitch_phase: float = 0.0    # phi, radians (pitch leads heave by phi)
+    heave_amp: float = 0.0      # A_h, in the length unit of the grid, +y
+    x_pivot: float = 0.0
+    y_pivot: float = 0.0
+
+
+def motion_at(m: OMotion, omega: float, phase: float):
+    """(theta, theta_dot, h, h_dot) at omega t = phase."""
+    th = m.pitch_amp * math.sin(phase + m.pitch_phase)
+    thd = omega * m.pitch_amp * math.cos(phase + m.pitch_phase)
+    h = m.heave_amp * math.sin(phase)
+    hd = omega * m.heave_amp * math.cos(phase)
+    return th, thd, h, hd
+
+
+def snapshot_motion(m: OMotion, flow: O.OFlow, ns: int, n: int):
+    return motion_at(m, flow.omega, 2.0 * math.pi * n / ns)
+
+
+def place(m: OMotion, th: float, h: float, x: torch.Tensor, y: torch.Tensor):
+    """Body-frame points (x, y) after the rotation by th about the pivot and
+    the rise h."""
+    c, s = math.cos(th), math.sin(th)
+    dx, dy = x - m.x_pivot, y - m.y_pivot
+    return m.x_pivot + c * dx - s * dy, m.y_pivot + h + s * dx + c * dy
+
+
+def rigid_velocity(m: OMotion, thd: float, h: float, hd: float, x: torch.Tensor,
+                   y: torch.Tensor):
+    """Velocity of the grid point that is now at (x, y)."""
+    rx, ry = x - m.x_pivot, y - (m.y_pivot + h)
+    return -thd * ry, thd * rx + hd
+
+
+def snapshot_xy(b: O.OBlock, m: OMotion, flow: O.OFlow, n: int) -> torch.Tensor:
+    th, _, h, _ = snapshot_motion(m, flow, b.ns, n)
+    x, y = place(m, th, h, b.xy[0], b.xy[1])
+    return torch.stack([x, y])
+
+
+def face_speeds(xy: torch.Tensor, m: OMotion, thd: float, h: float, hd: float):
+    """x_t . S of every i-face [nj][ni+1] and j-face [nj+1][ni] of a grid
+    (x_t at the face midpoint)."""
+    SI, SJ, _, _ = O.metrics(xy)
+    x, y = xy[0], xy[1]
+    ux, uy = rigid_velocity(m, thd, h, hd, 0.5 * (x[:-1, :] + x[1:, :]), 0.5 * (y[:-1, :] + y[1:, :]))
+    vgi = ux * SI[..., 0] + uy * SI[..., 1]
+    ux, uy = rigid_velocity(m, thd, h, hd, 0.5 * (x[:, :-1] + x[:, 1:]), 0.5 * (y[:, :-1] + y[:, 1:]))
+    vgj = ux * SJ[..., 0] + uy * SJ[..., 1]
+    return vgi, vgj
+
+
+def check_block(b: O.OBlock):
+    if b.bc[0] in (O.WALL, O.CUT) or b.bc[1] in (O.WALL, O.CUT) or O.CUT in b.bc:
+        raise ValueError("moving grids: walls only on j sides, no cuts")
+
+
+def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Tensor,
+                  m: OMotion, thd: float, h: float, hd: float) -> torch.Tensor:
+    """Ghost-extended primitives of one snapshot (w[1][4][nj][ni], winf[1][4])
+    on the moved grid xy: the fixed-grid rules (hb_oracle.extend), then the
+    moving-wall images  u_g = 2 u_w - u  (the fixed rule gives -u)."""
+    check_block(b)
+    we = O.extend(b, w, winf).clone()
+    ni, nj = b.ni, b.nj
+    x, y = xy[0], xy[1]
+    for side in (2, 3):
+        kind = b.bc[side]
+        if kind not in (O.WALL, O.WAKECUT):
+            continue
+        jw = 0 if side == 2 else nj
+        uwx, uwy = rigid_velocity(m, thd, h, hd, 0.5 * (x[jw, :-1] + x[jw, 1:]),
+                                  0.5 * (y[jw, :-1] + y[jw, 1:]))
+        for ie in range(ni + 4):
+            i = ie - 2
+            if kind == O.WAKECUT and (i < b.wake_ncells or i >= ni - b.wake_ncells):
+                continue                       # wake ghosts are real cells
+            if 0 <= i < ni:
+                col = i
+            elif b.bc[0 if i < 0 else 1] == O.PERIODIC:
+                col = i % ni
+            else:
+                col = min(max(i, 0), ni - 1)
+            for k in (0, 1):
+                row = (-1 - k if side == 2 else nj + k) + 2
+                we[:, 1, row, ie] += 2.0 * uwx[col]
+                we[:, 2, row, ie] += 2.0 * uwy[col]
+    return we
+
+
+def _snapshot(b, w, winf, m, flow, n):
+    th, thd, h, hd = snapshot_motion(m, flow, b.ns, n)
+    xy = snapshot_xy(b, m, flow, n)
+    we = moving_extend(b, w[n:n + 1], winf[n:n + 1], xy, m, thd, h, hd)
+    return xy, we, (th, thd, h, hd)
+
+
+def moving_residual(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
+                    m: OMotion) -> torch.Tensor:
+    """R*_n = sum over faces of the moving-face fluxes on grid n + V (D Q)_n."""
+    w = O.primitives(q, flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    parts = []
+    for n in range(b.ns):
+        xy, we, (_, thd, h, hd) = _snapshot(b, w, winf, m, flow, n)
+        vg = face_speeds(xy, m, thd, h, hd)
+        FI, FJ = O.face_fluxes(b, q[n:n + 1], flow, solver, xy=xy, we=we, vg=vg)
+        parts.append((FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :]))
+    return torch.cat(parts) + O.hb_source(b, q, flow)
+
+
+def moving_residual_all(blocks: Sequence[O.OBlock], q: torch.Tensor, flow, solver,
+                        m: OMotion) -> torch.Tensor:
+    return O.join([moving_residual(b, qb, flow, solver, m)
+                   for b, qb in zip(blocks, O.split(blocks, q))])
+
+
+def moving_local_dt(b: O.OBlock, q0: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
+                    m: OMotion) -> torch.Tensor:
+    """hb_oracle.local_dt on snapshot n's grid with u - x_t(centre) in the
+    convective spectral radii."""
+    g = flow.gamma
+    w = O.primitives(q0, g)
+    out = []
+    for n in range(b.ns):
+        _, thd, h, hd = snapshot_motion(m, flow, b.ns, n)
+        SI, SJ, V, C = O.metrics(snapshot_xy(b, m, flow, n))
+        gx, gy = rigid_velocity(m, thd, h, hd, C[..., 0], C[..., 1])
+        rho, u, v, p = w[n, 0], w[n, 1] - gx, w[n, 2] - gy, w[n, 3]
+        c = torch.sqrt(g * p / rho)
+        si = 0.5 * (SI[:, :-1, :] + SI[:, 1:, :])
+        sj = 0.5 * (SJ[:-1, :, :] + SJ[1:, :, :])
+        ai = torch.sqrt(si[..., 0] ** 2 + si[..., 1] ** 2)
+        aj = torch.sqrt(sj[..., 0] ** 2 + sj[..., 1] ** 2)
+        li = torch.abs(u * si[..., 0] + v * si[..., 1]) + c * ai
+        lj = torch.abs(u * sj[..., 0] + v * sj[..., 1]) + c * aj
+        fac = torch.maximum(4.0 / (3.0 * rho), g / rho) * (flow.mu / flow.prandtl)
+        lam = li + lj + 4.0 * (fac * ai * ai / V + fac * aj * aj / V) + V * flow.omega * b.n_harm
+        out.append(solver.cfl * V / lam)
+    return torch.stack(out)
+
+
+def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter: int):
+    """hb_oracle.rk_iterate with the moving-grid residual and time step."""
+    q = q.clone()
+    norms = []
+    total = sum(b.ns * b.ni * b.nj for b in blocks)
+    vols = [O.metrics(b.xy)[2] for b in blocks]
+    for _ in range(n_iter):
+        q0 = O.split(blocks, q)
+        dtv = O.join([(moving_local_dt(b, qb, flow, solver, m) / V)[:, None].expand(-1, 4, -1, -1)
+                      for b, qb, V in zip(blocks, q0, vols)])
+        resid = lambda x: moving_residual_all(blocks, x, flow, solver, m)
+        q, r0 = O.rk_stages(q, dtv, resid, solver.rk_alpha)
+        s = sum(float(((r[:, 0] / V) ** 2).sum()) for r, V in zip(O.split(blocks, r0), vols))
+        norms.append(math.sqrt(s / total))
+    return q, torch.tensor(norms, dtype=DT)
+
+
+def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
+                  m: OMotion) -> List[torch.Tensor]:
+    """hb_oracle.forces on the moved grids: per snapshot the wall loads of
+    grid n (moving-wall ghosts), the moment about the moved reference point,
+    lift and drag along the mean free stream.  [body][ns][3] = (cl, cd, cm)."""
+    a0 = flow.alpha0
+    qinf = 0.5 * flow.mach ** 2
+    nbody = max(b.body_id for b in blocks) + 1
+    acc = [None] * nbody
+    for b, qb in zip(blocks, O.split(blocks, q)):
+        w = O.primitives(qb, flow.gamma)
+        winf = O.freestream_prim(flow, b.ns)
+        rows = []
+        for n in range(b.ns):
+            xy, we, (th, _, h, _) = _snapshot(b, w, winf, m, flow, n)
+            xm, ym = place(m, th, h, torch.tensor(flow.x_mom, dtype=DT),
+                           torch.tensor(flow.y_mom, dtype=DT))
+            fn = dataclasses.replace(flow, x_mom=float(xm), y_mom=float(ym))
+            rows.append(O.block_loads(b, qb[n:n + 1], fn, xy=xy, we=we)[0])
+        L = torch.stack(rows)
+        acc[b.body_id] = L if acc[b.body_id] is None else acc[b.body_id] + L
+    out = []
+    for L in acc:
+        fx, fy, mz = L[:, 0], L[:, 1], L[:, 2]
+        cd = (fx * math.cos(a0) + fy * math.sin(a0)) / (qinf * flow.l_ref)
+        cl = (-fx * math.sin(a0) + fy * math.cos(a0)) / (qinf * flow.l_ref)
+        cm = -mz / (qinf * flow.l_ref ** 2)
+        out.append(torch.stack([cl, cd, cm], dim=-1))
+    return out

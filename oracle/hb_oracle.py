@@ -406,8 +406,14 @@ def euler_normal_flux(w: torch.Tensor, nx, ny, gamma):
                         (rhoE + p) * qn])
 
 
+def conserved(w: torch.Tensor, gamma: float) -> torch.Tensor:
+    """(rho, u, v, p) on dim 0 -> (rho, rho u, rho v, rho E) on dim 0."""
+    rho, u, v, p = w[0], w[1], w[2], w[3]
+    return torch.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
 def roe_flux(wl: torch.Tensor, wr: torch.Tensor, S: torch.Tensor, gamma: float,
-             delta_frac: float) -> torch.Tensor:
+             delta_frac: float, vg: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Roe's approximate Riemann solver (textbook form) times the face length.
 
     wl, wr: primitives with the variable on dim 0; S: face normal vector with
@@ -417,6 +423,12 @@ def roe_flux(wl: torch.Tensor, wr: torch.Tensor, S: torch.Tensor, gamma: float,
     entropy fix on the acoustic eigenvalues: |l| -> (l^2 + d^2)/(2 d) when
     |l| < d, d = delta_frac * c~ (delta_frac = 0 switches it off).
     F = |S| [ (F(L) + F(R))/2 - (1/2) sum_k |l_k| a_k r_k ].
+
+    Moving face (arbitrary Lagrangian-Eulerian form): vg = x_t . S, the
+    face's grid velocity times its length-weighted normal.  The flux through
+    the moving face is F.n - (vg/|S|) U, and every eigenvalue is measured
+    relative to the face, q_n - vg/|S| (the eigenvectors do not change).
+    vg = None is the fixed face.
     """
     area = torch.sqrt(S[0] * S[0] + S[1] * S[1])
     nx, ny = S[0] / area, S[1] / area
@@ -433,15 +445,16 @@ def roe_flux(wl: torch.Tensor, wr: torch.Tensor, S: torch.Tensor, gamma: float,
     q2t = ut * ut + vt * vt
     ct = torch.sqrt((g - 1.0) * (ht - 0.5 * q2t))
     qnt = ut * nx + vt * ny
+    qrel = qnt if vg is None else qnt - vg / area
     dr, du, dv, dp = rr - rl, ur - ul, vr - vl, pr - pl
     dqn = du * nx + dv * ny
     # wave strengths
     a1 = (dp - rt * ct * dqn) / (2.0 * ct * ct)
     a4 = (dp + rt * ct * dqn) / (2.0 * ct * ct)
     a2 = dr - dp / (ct * ct)
-    l1 = torch.abs(qnt - ct)
-    l4 = torch.abs(qnt + ct)
-    l2 = torch.abs(qnt)
+    l1 = torch.abs(qrel - ct)
+    l4 = torch.abs(qrel + ct)
+    l2 = torch.abs(qrel)
     if delta_frac > 0.0:
         d = delta_frac * ct
         l1 = torch.where(l1 < d, (l1 * l1 + d * d) / (2.0 * d), l1)
@@ -456,6 +469,9 @@ def roe_flux(wl: torch.Tensor, wr: torch.Tensor, S: torch.Tensor, gamma: float,
     diss = l1 * a1 * r1 + l4 * a4 * r4 + l2 * (a2 * r2 + shear)
     fl = euler_normal_flux(wl, nx, ny, g)
     fr = euler_normal_flux(wr, nx, ny, g)
+    if vg is not None:
+        fl = fl - vg / area * conserved(wl, g)
+        fr = fr - vg / area * conserved(wr, g)
     return area * (0.5 * (fl + fr) - 0.5 * diss)
 
 
@@ -520,14 +536,17 @@ def uvt(w: torch.Tensor, gamma: float) -> torch.Tensor:
 def face_fluxes(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver,
                 alpha0: Optional[torch.Tensor] = None, xy: Optional[torch.Tensor] = None,
                 winf: Optional[torch.Tensor] = None, we: Optional[torch.Tensor] = None,
-                nbrC=None):
+                nbrC=None, vg=None):
     """Net face fluxes (inviscid minus viscous, times face length) of every
     i-face FI[ns][4][nj][ni+1] and j-face FJ[ns][4][nj+1][ni] of one block,
     for all snapshots; q is the conserved state q[ns][4][nj][ni].  `winf`
     overrides the far-field primitives per snapshot ([ns][4]); a block with
     cuts passes its ghost-extended primitives `we` and the glued blocks'
-    centres `nbrC` (extend_all)."""
+    centres `nbrC` (extend_all).  `vg` = (vg_I [nj][ni+1], vg_J [nj+1][ni]):
+    grid velocity times face normal of moving faces (roe_flux), None for a
+    fixed grid."""
     g = flow.gamma
+    vgi, vgj = (None, None) if vg is None else vg
     xy = b.xy if xy is None else xy
     SI, SJ, V, C = metrics(xy)
     ns, _, nj, ni = q.shape
@@ -544,13 +563,13 @@ def face_fluxes(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver,
                    row[..., 3:ni + 4], eps)
     SIt = SI.permute(2, 0, 1)                         # [2][nj][ni+1]
     FI = roe_flux(wl.transpose(0, 1), wr.transpose(0, 1), SIt, g,
-                  solver.entropy_delta).transpose(0, 1)
+                  solver.entropy_delta, vgi).transpose(0, 1)
     col = we[:, :, :, 2:ni + 2]
     wl, wr = muscl(col[:, :, 0:nj + 1], col[:, :, 1:nj + 2], col[:, :, 2:nj + 3],
                    col[:, :, 3:nj + 4], eps)
     SJt = SJ.permute(2, 0, 1)                         # [2][nj+1][ni]
     FJ = roe_flux(wl.transpose(0, 1), wr.transpose(0, 1), SJt, g,
-                  solver.entropy_delta).transpose(0, 1)
+                  solver.entropy_delta, vgj).transpose(0, 1)
     # ---- viscous ---------------------------------------------------------
     t = uvt(we, g)                                    # [ns][3][nj+4][ni+4]
     # node (i, j), i = 0..ni, j = 0..nj: mean of cells (i-1..i, j-1..j)

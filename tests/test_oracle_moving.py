@@ -1,0 +1,252 @@
+"""Pins of the moving-grid oracle (rigid heave and pitch, arbitrary
+Lagrangian-Eulerian form) against what the mathematics fixes (CPU only):
+zero motion is the fixed grid, a heave is a Galilean shift of the fixed-grid
+residual, the scheme is rotation-equivariant, a uniform stream is preserved
+on a moving grid (discrete geometric conservation), the grid velocity is the
+time derivative of the node positions, and wall images satisfy no-slip on
+the moving wall."""
+import math
+
+import pytest
+import torch
+
+from oracle import hb_moving as M
+from oracle import hb_oracle as O
+from paper_1304_7654_amd import synth
+
+DT = torch.float64
+FF, PER, WALL, WAKE = O.FARFIELD, O.PERIODIC, O.WALL, O.WAKECUT
+
+
+def _flow():
+    return O.OFlow(mach=0.3, reynolds=500.0, k_red=0.4, x_mom=0.25, y_mom=0.1)
+
+
+def _state(b, flow, seed, amp=2e-2):
+    g = torch.Generator().manual_seed(seed)
+    ns = b.ns
+    xi = torch.randn(ns, 4, b.nj, b.ni, generator=g, dtype=DT)
+    w = torch.empty_like(xi)
+    w[:, 0] = 1.0 + amp * xi[:, 0]
+    w[:, 1] = flow.mach + amp * flow.mach * xi[:, 1]
+    w[:, 2] = amp * flow.mach * xi[:, 2]
+    w[:, 3] = 1.0 / flow.gamma + amp / flow.gamma * xi[:, 3]
+    return O.conserved(w.transpose(0, 1), flow.gamma).transpose(0, 1).contiguous()
+
+
+def _cyl(ni=24, nj=10, nh=2):
+    return O.OBlock(ni, nj, nh, torch.as_tensor(synth.o_grid(ni, nj)), (PER, PER, WALL, FF))
+
+
+def _cgrid(nh=1):
+    return O.OBlock(72, 12, nh, torch.as_tensor(synth.c_grid(72, 12)), (FF, FF, WAKE, FF), 18)
+
+
+def _rel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+@pytest.mark.parametrize("blk", ["cyl", "cgrid"])
+def test_zero_motion_is_fixed_grid(blk):
+    """With zero amplitudes every moving-grid function reduces to its
+    fixed-grid counterpart."""
+    b = _cyl() if blk == "cyl" else _cgrid()
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 1)
+    m = M.OMotion(x_pivot=0.3, y_pivot=-0.2)
+    assert _rel(M.moving_residual(b, q, flow, solver, m), O.residual(b, q, flow, solver)) < 1e-12
+    assert _rel(M.moving_local_dt(b, q, flow, solver, m), O.local_dt(b, q, flow, solver)) < 1e-13
+    fm = M.moving_forces([b], q, flow, solver, m)[0]
+    fs = O.forces([b], q, flow, solver)[0]
+    assert (fm - fs).abs().max() < 1e-12 * max(1.0, float(fs.abs().max()))
+
+
+def _galilean(r, v):
+    """Conserved residual of the fixed frame from the one of a frame moving
+    with velocity v: mass unchanged, momentum + v mass, energy + v.momentum
+    + |v|^2/2 mass."""
+    out = r.clone()
+    out[1] = r[1] + v[0] * r[0]
+    out[2] = r[2] + v[1] * r[0]
+    out[3] = r[3] + v[0] * r[1] + v[1] * r[2] + 0.5 * (v[0] ** 2 + v[1] ** 2) * r[0]
+    return out
+
+
+@pytest.mark.parametrize("blk", ["cyl", "cgrid"])
+def test_heave_is_galilean_shift(blk):
+    """A heaving grid moves with the uniform velocity (0, h_dot): snapshot
+    n's flux balance equals the fixed-grid balance of the state seen from the
+    grid (velocities and free stream shifted by -(0, h_dot), wall at rest),
+    transformed back.  Catches the sign or size of the face-speed term, a
+    Roe dissipation without the eigenvalue shift and a wrong wall image."""
+    b = _cyl() if blk == "cyl" else _cgrid()
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 2)
+    m = M.OMotion(heave_amp=0.4)
+    spatial = M.moving_residual(b, q, flow, solver, m) - O.hb_source(b, q, flow)
+    w = O.primitives(q, flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    for n in range(b.ns):
+        _, _, _, hd = M.snapshot_motion(m, flow, b.ns, n)
+        assert abs(hd) > 1e-3 or n > 0
+        ws = w[n:n + 1].clone()
+        ws[:, 2] -= hd
+        fs = winf[n:n + 1].clone()
+        fs[:, 2] -= hd
+        qs = O.conserved(ws.transpose(0, 1), flow.gamma).transpose(0, 1)
+        rs = O.spatial_residual(b, qs, flow, solver, we=O.extend(b, ws, fs))[0]
+        assert _rel(spatial[n], _galilean(rs, (0.0, hd))) < 1e-11, n
+
+
+def _rotate_uv(w, c, s):
+    out = w.clone()
+    out[:, 1] = c * w[:, 1] - s * w[:, 2]
+    out[:, 2] = s * w[:, 1] + c * w[:, 2]
+    return out
+
+
+def test_pitch_is_rotation_equivariant():
+    """Snapshot n of a pitching grid (rotated by theta_n, turning at
+    theta_dot_n) equals the body-frame evaluation (grid at theta = 0 with the
+    same rotation rate, state and free stream rotated back by theta_n) with
+    its momentum balance rotated forward.  The van Albada limiter acts on u
+    and v separately and is not rotation-equivariant; a huge epsilon turns it
+    into the linear mean slope, which is."""
+    b = _cyl(20, 8, 1)
+    flow, solver = _flow(), O.OSolver(limiter_eps=1e30)
+    flow.alpha0 = 0.1
+    q = _state(b, flow, 3)
+    m = M.OMotion(pitch_amp=0.35, pitch_phase=0.4, x_pivot=0.25, y_pivot=0.05)
+    spatial = M.moving_residual(b, q, flow, solver, m) - O.hb_source(b, q, flow)
+    w = O.primitives(q, flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    for n in range(b.ns):
+        th, thd, _, _ = M.snapshot_motion(m, flow, b.ns, n)
+        c, s = math.cos(th), math.sin(th)
+        wb = _rotate_uv(w[n:n + 1], c, -s)
+        fb = _rotate_uv(winf[n:n + 1][:, :, None, None], c, -s)[:, :, 0, 0]
+        xy0 = torch.stack(M.place(m, 0.0, 0.0, b.xy[0], b.xy[1]))
+        we = M.moving_extend(b, wb, fb, xy0, m, thd, 0.0, 0.0)
+        vg = M.face_speeds(xy0, m, thd, 0.0, 0.0)
+        qb = O.conserved(wb.transpose(0, 1), flow.gamma).transpose(0, 1)
+        FI, FJ = O.face_fluxes(b, qb, flow, solver, xy=xy0, we=we, vg=vg)
+        rb = ((FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :]))[0]
+        rf = rb.clone()
+        rf[1] = c * rb[1] - s * rb[2]
+        rf[2] = s * rb[1] + c * rb[2]
+        assert abs(th) > 1e-3
+        assert _rel(spatial[n], rf) < 1e-11, n
+
+
+def test_uniform_stream_preserved_on_moving_grid():
+    """An annulus with far field on both sides in a uniform stream: the face
+    speeds of a rigid motion sum to zero around every cell, the Roe
+    dissipation and the HB term vanish, so R* = 0 to round-off."""
+    b = O.OBlock(32, 12, 2, torch.as_tensor(synth.o_grid(32, 12)), (PER, PER, FF, FF))
+    flow, solver = _flow(), O.OSolver()
+    flow.alpha0 = 0.2
+    w = O.freestream_prim(flow, b.ns)[:, :, None, None].expand(b.ns, 4, b.nj, b.ni)
+    q = O.conserved(w.transpose(0, 1), flow.gamma).transpose(0, 1).contiguous()
+    m = M.OMotion(pitch_amp=0.3, pitch_phase=1.1, heave_amp=0.5, x_pivot=0.4, y_pivot=-0.3)
+    r = M.moving_residual(b, q, flow, solver, m)
+    SI, SJ, _, _ = O.metrics(b.xy)
+    scale = float(SI.abs().max()) * flow.mach
+    assert float(r.abs().max()) < 1e-12 * scale
+    # the grid-speed term alone is not small: its sum is what cancels
+    _, thd, h, hd = M.snapshot_motion(m, flow, b.ns, 1)
+    vgi, vgj = M.face_speeds(M.snapshot_xy(b, m, flow, 1), m, thd, h, hd)
+    assert float(vgi.abs().max()) > 1e-2 * scale / flow.mach
+    net = (vgi[:, 1:] - vgi[:, :-1]) + (vgj[1:, :] - vgj[:-1, :])
+    assert float(net.abs().max()) < 1e-13 * float(vgi.abs().max())
+
+
+def test_grid_velocity_is_time_derivative_of_positions():
+    """x_t of a node equals the central difference in time of its position
+    (fourth-order differences, step 1e-3 in omega t)."""
+    b = _cyl(16, 6, 1)
+    flow = _flow()
+    m = M.OMotion(pitch_amp=0.3, pitch_phase=0.7, heave_amp=0.25, x_pivot=0.3, y_pivot=0.1)
+    om = flow.omega
+    for ph in (0.0, 1.3, 4.0):
+        e = 1e-3
+
+        def pos(p):
+            th, _, h, _ = M.motion_at(m, om, p)
+            return M.place(m, th, h, b.xy[0], b.xy[1])
+
+        xs = [pos(ph + k * e) for k in (-2, -1, 1, 2)]
+        dt = e / om
+        vx = (xs[0][0] - 8 * xs[1][0] + 8 * xs[2][0] - xs[3][0]) / (12 * dt)
+        vy = (xs[0][1] - 8 * xs[1][1] + 8 * xs[2][1] - xs[3][1]) / (12 * dt)
+        th, thd, h, hd = M.motion_at(m, om, ph)
+        x, y = M.place(m, th, h, b.xy[0], b.xy[1])
+        ux, uy = M.rigid_velocity(m, thd, h, hd, x, y)
+        assert float((ux - vx).abs().max()) < 1e-8
+        assert float((uy - vy).abs().max()) < 1e-8
+
+
+def test_wall_images_are_no_slip_on_the_moving_wall():
+    """On the wall, the mean of the first ghost and the first cell is the
+    wall face's velocity (interior columns), and the corner ghosts of an
+    O-grid equal the ghosts of their periodic partner columns."""
+    b = _cyl(20, 8, 1)
+    flow = _flow()
+    q = _state(b, flow, 4)
+    m = M.OMotion(pitch_amp=0.3, pitch_phase=0.2, heave_amp=0.2, x_pivot=0.1)
+    w = O.primitives(q, flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    for n in range(b.ns):
+        xy, we, (_, thd, h, hd) = M._snapshot(b, w, winf, m, flow, n)
+        x, y = xy[0], xy[1]
+        ux, uy = M.rigid_velocity(m, thd, h, hd, 0.5 * (x[0, :-1] + x[0, 1:]),
+                                  0.5 * (y[0, :-1] + y[0, 1:]))
+        ni = b.ni
+        assert float((0.5 * (we[0, 1, 1, 2:ni + 2] + we[0, 1, 2, 2:ni + 2]) - ux).abs().max()) < 1e-14
+        assert float((0.5 * (we[0, 2, 1, 2:ni + 2] + we[0, 2, 2, 2:ni + 2]) - uy).abs().max()) < 1e-14
+        # second layer mirrors the second cell
+        assert float((0.5 * (we[0, 1, 0, 2:ni + 2] + we[0, 1, 3, 2:ni + 2]) - ux).abs().max()) < 1e-14
+        for k in (0, 1):
+            assert torch.equal(we[0, :, k, 0:2], we[0, :, k, ni:ni + 2])
+            assert torch.equal(we[0, :, k, ni + 2:ni + 4], we[0, :, k, 2:4])
+
+
+def test_heave_loads_are_galilean_invariant():
+    """Pressure and viscous stress do not change under a uniform shift of
+    the velocity, and the moment reference point moves with the body: the
+    loads of a heaving grid equal the fixed-grid loads of the state seen from
+    the grid."""
+    b = _cyl()
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 5)
+    m = M.OMotion(heave_amp=0.4)
+    cf = M.moving_forces([b], q, flow, solver, m)[0]
+    w = O.primitives(q, flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    qinf = 0.5 * flow.mach ** 2
+    for n in range(b.ns):
+        _, _, _, hd = M.snapshot_motion(m, flow, b.ns, n)
+        ws = w[n:n + 1].clone()
+        ws[:, 2] -= hd
+        fs = winf[n:n + 1].clone()
+        fs[:, 2] -= hd
+        qs = O.conserved(ws.transpose(0, 1), flow.gamma).transpose(0, 1)
+        L = O.block_loads(b, qs, flow, we=O.extend(b, ws, fs))[0]
+        ref = torch.stack([L[1] / qinf, L[0] / qinf, -L[2] / qinf])   # alpha0 = 0
+        assert float((cf[n] - ref).abs().max()) < 1e-11 * float(ref.abs().max()), n
+
+
+def test_moving_grid_rejects_i_walls_and_cuts():
+    b = O.OBlock(16, 8, 0, torch.as_tensor(synth.o_grid(16, 8)), (WALL, PER, FF, FF))
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 6)
+    with pytest.raises(ValueError):
+        M.moving_residual(b, q, flow, solver, M.OMotion(heave_amp=0.1))
+
+
+def test_moving_rk_iterate_zero_motion_matches_fixed():
+    b = _cyl(16, 6, 1)
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 7).reshape(-1)
+    qa, na = M.moving_rk_iterate([b], q, flow, solver, M.OMotion(), 2)
+    qb, nb = O.rk_iterate([b], q, flow, solver, 2)
+    assert _rel(qa, qb) < 1e-13 and _rel(na, nb) < 1e-12
