@@ -140,6 +140,22 @@ typedef struct {
     double stage_ms;
 } hb_tuning;
 
+/* Rigid motion of the whole grid (the paper's test case 1 is a heaving and
+ * pitching wing, Experimental Setup, Test case 1; the moving-grid equations
+ * are the arbitrary Lagrangian-Eulerian finite-volume form).  Snapshot n
+ * (omega t_n = 2 pi n / N_s) holds the grid rotated counter-clockwise by
+ * theta_n about (x_pivot, y_pivot) and raised by h_n:
+ *   theta(t) = pitch_amp sin(omega t + pitch_phase),  h(t) = heave_amp sin(omega t)
+ * (radians; heave in grid length units, +y).  Faces carry the flux
+ * F.S - (x_t.S) U with the rigid grid velocity x_t at the face midpoint and
+ * Roe eigenvalues relative to the face; no-slip walls move with the grid
+ * (ghost velocity 2 u_wall - u); the local step uses the velocity relative
+ * to the grid; loads are taken on the moved grid with the moment about the
+ * reference point carried by the body, lift and drag along alpha0. */
+typedef struct {
+    double pitch_amp, pitch_phase, heave_amp, x_pivot, y_pivot;
+} hb_motion;
+
 /* Build a grid: copies the host arrays, computes the metrics on the device
  * (FP64), allocates all scratch.  Validation (HB_ERR_ARG): nblocks >= 1,
  * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
@@ -273,6 +289,15 @@ int hb_set_xy(hb_grid *g, const double *xy, void *stream);
 /* Replace the mean incidence alpha0 (radians); takes effect for work
  * enqueued afterwards. */
 int hb_set_alpha0(hb_grid *g, double alpha0);
+
+/* Set (m non-NULL with a non-zero amplitude) or clear (NULL, or both
+ * amplitudes zero) the rigid grid motion described at hb_motion.  It then
+ * applies to hb_residual, hb_rk_iterate and hb_forces.  HB_ERR_UNSUPPORTED
+ * for batched grids, for blocks with walls on an i side or with cuts; while
+ * a motion is set the adjoints, hb_td_march and hb_set_xy return
+ * HB_ERR_UNSUPPORTED.  HB_ERR_ARG for non-finite values.  Synchronises the
+ * current device. */
+int hb_set_motion(hb_grid *g, const hb_motion *m);
 
 /* Synchronise and return HB_ERR_NONFINITE if any iteration since the last
  * call met a non-finite residual or a non-positive density or pressure

@@ -64,7 +64,7 @@ void free_all(hb_grid *g) {
     dfree(g->D_d); dfree(g->D_f);
     dfree(g->ffw_d); dfree(g->ffq_d); dfree(g->dqinf_d);
     dfree(g->ffw_f); dfree(g->ffq_f); dfree(g->dqinf_f);
-    dfree(g->ext_d); dfree(g->FI_d); dfree(g->FJ_d);
+    dfree(g->ext_d); dfree(g->FI_d); dfree(g->FJ_d); dfree(g->mot_d);
     dfree(g->q0_d); dfree(g->qa_d); dfree(g->qb_d);
     dfree(g->sa_f); dfree(g->sb_f);
     dfree(g->dtau_f); dfree(g->dtau_d);
@@ -489,6 +489,7 @@ int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double 
     if (qbar == q || qbar == rbar) return fail(HB_ERR_ARG, "qbar must not alias q or rbar");
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
     return launch_residual_adjoint(g, q, rbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 
@@ -497,6 +498,7 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *
     g_err.clear();
     if (!g || !q || !cfbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
     if (qbar == q) return fail(HB_ERR_ARG, "qbar must not alias q");
+    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
     return launch_forces_adjoint(g, q, cfbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 
@@ -508,6 +510,7 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     if (lambda == q || lambda == gq) return fail(HB_ERR_ARG, "lambda must not alias q or gq");
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
+    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
 }
 
@@ -530,6 +533,7 @@ int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, vo
         return fail(HB_ERR_ARG, "need n_steps >= 0, finite t0 and dt > 0");
     for (const BlockDesc &B : g->blk)
         if (B.nh != 0) return fail(HB_ERR_UNSUPPORTED, "the time-domain march needs n_harm = 0 in every block");
+    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no time-domain march on a moving grid");
     return launch_td_march(g, q, t0, dt, n_steps, (hipStream_t)stream);
 }
 
@@ -558,6 +562,7 @@ int hb_get_tuning(const hb_grid *g, hb_tuning *t) {
 int hb_set_xy(hb_grid *g, const double *xy, void *stream) {
     g_err.clear();
     if (!g || !xy) return fail(HB_ERR_ARG, "NULL argument");
+    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "hb_set_xy on a moving grid");
     hipStream_t s = (hipStream_t)stream;
     int rc = check_hip(hipMemcpyAsync(g->xy_d, xy, sizeof(double) * 2 * g->n_nodes,
                                       hipMemcpyDeviceToDevice, s), "xy copy");
@@ -571,6 +576,48 @@ int hb_set_alpha0(hb_grid *g, double alpha0) {
     if (rc) return rc;
     g->flow.alpha0 = alpha0;
     return upload_snapshot_tables(g);
+}
+
+int hb_set_motion(hb_grid *g, const hb_motion *m) {
+    g_err.clear();
+    if (!g) return fail(HB_ERR_ARG, "NULL grid");
+    if (m && !(std::isfinite(m->pitch_amp) && std::isfinite(m->pitch_phase) &&
+               std::isfinite(m->heave_amp) && std::isfinite(m->x_pivot) && std::isfinite(m->y_pivot)))
+        return fail(HB_ERR_ARG, "non-finite motion");
+    int rc = check_hip(hipDeviceSynchronize(), "sync");
+    if (rc) return rc;
+    if (!m || (m->pitch_amp == 0.0 && m->heave_amp == 0.0)) {
+        g->motion = Motion{nullptr, 0.0, 0.0};
+        return HB_OK;
+    }
+    if (g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "a moving grid needs batched = 0");
+    for (const BlockDesc &B : g->blk)
+        for (int side = 0; side < 4; ++side)
+            if (B.bc[side] == HB_BC_CUT || (side < 2 && B.bc[side] == HB_BC_WALL))
+                return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides, no cuts");
+    if (!g->mot_d) {
+        rc = dalloc(&g->mot_d, (int64_t)kMotionW * g->n_snap);
+        if (rc) return rc;
+    }
+    const hb_flow &f = g->flow;
+    const double omega = 2.0 * f.k_red * f.mach / f.l_ref;
+    std::vector<double> tab((size_t)kMotionW * g->n_snap, 0.0);
+    for (const BlockDesc &B : g->blk)
+        for (int n = 0; n < B.ns; ++n) {
+            const double ph = 2.0 * M_PI * n / B.ns;
+            const double th = m->pitch_amp * std::sin(ph + m->pitch_phase);
+            double *t = &tab[(size_t)kMotionW * (B.snap_off + n)];
+            t[0] = std::cos(th);
+            t[1] = std::sin(th);
+            t[2] = omega * m->pitch_amp * std::cos(ph + m->pitch_phase);
+            t[3] = m->heave_amp * std::sin(ph);
+            t[4] = omega * m->heave_amp * std::cos(ph);
+        }
+    rc = check_hip(hipMemcpy(g->mot_d, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice),
+                   "motion upload");
+    if (rc) return rc;
+    g->motion = Motion{g->mot_d, m->x_pivot, m->y_pivot};
+    return HB_OK;
 }
 
 int hb_profile_stages(hb_grid *g, int32_t enable) {

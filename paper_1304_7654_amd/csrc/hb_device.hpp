@@ -130,6 +130,61 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rigid grid motion (plain FP64 path).  Body-frame vectors rotate by theta;
+// the grid point whose body-frame position is x0 moves with
+// theta_dot k x R(theta)(x0 - p) + (0, h_dot).
+// ---------------------------------------------------------------------------
+struct MotionSnap {
+    double c, s, thd, h, hd;
+};
+
+__device__ __forceinline__ MotionSnap motion_snap(const Motion &mo, const BlockDesc &B, int n) {
+    const double *t = mo.tab + (int64_t)kMotionW * (B.snap_off + n);
+    return MotionSnap{t[0], t[1], t[2], t[3], t[4]};
+}
+
+__device__ __forceinline__ void rot2(const MotionSnap &m, double &x, double &y) {
+    const double a = m.c * x - m.s * y;
+    y = m.s * x + m.c * y;
+    x = a;
+}
+
+__device__ __forceinline__ void grid_velocity(const MotionSnap &m, const Motion &mo, double x0,
+                                              double y0, double &gx, double &gy) {
+    double rx = x0 - mo.xp, ry = y0 - mo.yp;
+    rot2(m, rx, ry);
+    gx = -m.thd * ry;
+    gy = m.thd * rx + m.hd;
+}
+
+// A ghost (i, j) of block B that is a no-slip wall image (j side wall, or
+// the wall part of a wake cut) gets 2 u_wall added to the mirrored velocity,
+// u_wall = grid velocity at the midpoint of the wall face of the mirrored
+// cell's column (corner ghosts: the i-periodic partner column, else the
+// nearest column).  xy: body-frame nodes of all blocks.
+__device__ __forceinline__ void wall_image_motion(const BlockDesc &B, int i, int j,
+                                                  const MotionSnap &m, const Motion &mo,
+                                                  const double *xy, W4<double> &w) {
+    int side;
+    if (j < 0) side = 2;
+    else if (j >= B.nj) side = 3;
+    else return;
+    const int kind = B.bc[side];
+    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return;
+    if (kind == HB_BC_WAKECUT && (i < B.wake || i >= B.ni - B.wake)) return;
+    int col = i;
+    if (i < 0) col = B.bc[0] == HB_BC_PERIODIC ? i + B.ni : 0;
+    else if (i >= B.ni) col = B.bc[1] == HB_BC_PERIODIC ? i - B.ni : B.ni - 1;
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    const int64_t k = (int64_t)(side == 2 ? 0 : B.nj) * (B.ni + 1) + col;
+    double gx, gy;
+    grid_velocity(m, mo, 0.5 * (x[k] + x[k + 1]), 0.5 * (y[k] + y[k + 1]), gx, gy);
+    w.u += 2.0 * gx;
+    w.v += 2.0 * gy;
+}
+
 // Load through a uniform base pointer and an unsigned 32-bit byte offset
 // (scalar base plus one VGPR in the address).
 template <class T>
@@ -168,9 +223,12 @@ __device__ __forceinline__ void muscl(const W4<T> &m2, const W4<T> &m1, const W4
 // ---------------------------------------------------------------------------
 // Roe flux on full primitive states, times the face length.
 // ---------------------------------------------------------------------------
+// A moving face passes vg = x_t . S (grid velocity times the length-weighted
+// normal): the flux becomes F.n - (vg/|S|) U and the eigenvalues are taken
+// relative to the face; vg = 0 is the fixed face.
 template <class T>
 __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T sy, T g,
-                                         T delta_frac, T f[4]) {
+                                         T delta_frac, T f[4], T vg = T(0)) {
     const T area = fsqrt(sx * sx + sy * sy);
     const T ia = frcp(area);
     const T nx = sx * ia, ny = sy * ia;
@@ -186,14 +244,15 @@ __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T
     const T q2t = ut * ut + vt * vt;
     const T ct = fsqrt((g - T(1)) * (ht - T(0.5) * q2t));
     const T qnt = ut * nx + vt * ny;
+    const T qrel = qnt - vg * ia;
     const T dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
     const T dqn = du * nx + dv * ny;
     const T ic2 = frcp(ct * ct);
     const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
     const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
     const T a2 = dr - dp * ic2;
-    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
-    const T l2 = fabs(qnt);
+    T l1 = fabs(qrel - ct), l4 = fabs(qrel + ct);
+    const T l2 = fabs(qrel);
     if (delta_frac > T(0)) {
         const T d = delta_frac * ct;
         const T i2d = frcp(T(2) * d);
@@ -212,10 +271,13 @@ __device__ __forceinline__ void roe_flux(const W4<T> &L, const W4<T> &R, T sx, T
     const T f1 = ml * L.u + mr * R.u + (L.p + R.p) * nx;
     const T f2 = ml * L.v + mr * R.v + (L.p + R.p) * ny;
     const T f3 = ml * hl + mr * hr;
-    f[0] = T(0.5) * area * (f0 - d0);
-    f[1] = T(0.5) * area * (f1 - d1);
-    f[2] = T(0.5) * area * (f2 - d2);
-    f[3] = T(0.5) * area * (f3 - d3);
+    // conserved sums U_L + U_R (rho E = rho H - p) for the face-speed term
+    const T u0 = L.r + R.r, u1 = L.r * L.u + R.r * R.u, u2 = L.r * L.v + R.r * R.v;
+    const T u3 = L.r * hl - L.p + R.r * hr - R.p;
+    f[0] = T(0.5) * (area * (f0 - d0) - vg * u0);
+    f[1] = T(0.5) * (area * (f1 - d1) - vg * u1);
+    f[2] = T(0.5) * (area * (f2 - d2) - vg * u2);
+    f[3] = T(0.5) * (area * (f3 - d3) - vg * u3);
 }
 
 // ---------------------------------------------------------------------------

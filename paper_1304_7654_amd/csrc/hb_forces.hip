@@ -44,21 +44,31 @@ __device__ inline bool is_wall_face(const BlockDesc &B, int i) {
 __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, const double *q,
                                  const double *ffw, const double *xy, const double *SJ,
                                  const double *dJ, const Consts &c, double xm, double ym,
-                                 double out[3]) {
+                                 const Motion &mo, double out[3]) {
     const BlockDesc &B = blks[b];
     CellQ cell{blks, q, n, c.gamma - 1.0};
     FF ff{blks, ffw, n};
     const double g = c.gamma;
-    const W4<double> wR = value_ij<W4<double>>(blks, b, i, 0, cell, ff, MirrorFull<double>());
-    const W4<double> wL = value_ij<W4<double>>(blks, b, i, -1, cell, ff, MirrorFull<double>());
+    MotionSnap ms{1.0, 0.0, 0.0, 0.0, 0.0};
+    if (mo.tab) ms = motion_snap(mo, B, n);
+    // (i', j') resolved like every ghost, moving-wall images with a motion set
+    auto val = [&](int ii, int jj) {
+        W4<double> w = value_ij<W4<double>>(blks, b, ii, jj, cell, ff, MirrorFull<double>());
+        if (mo.tab) wall_image_motion(B, ii, jj, ms, mo, xy, w);
+        return w;
+    };
+    const W4<double> wR = val(i, 0);
+    const W4<double> wL = val(i, -1);
     const UVT<double> uL = uvt(wL, g), uR = uvt(wR, g);
-    const UVT<double> nA = avg4(uvt(value_ij<W4<double>>(blks, b, i - 1, -1, cell, ff, MirrorFull<double>()), g), uL,
-                                uvt(value_ij<W4<double>>(blks, b, i - 1, 0, cell, ff, MirrorFull<double>()), g), uR);
-    const UVT<double> nB = avg4(uL, uvt(value_ij<W4<double>>(blks, b, i + 1, -1, cell, ff, MirrorFull<double>()), g), uR,
-                                uvt(value_ij<W4<double>>(blks, b, i + 1, 0, cell, ff, MirrorFull<double>()), g));
+    const UVT<double> nA = avg4(uvt(val(i - 1, -1), g), uL, uvt(val(i - 1, 0), g), uR);
+    const UVT<double> nB = avg4(uL, uvt(val(i + 1, -1), g), uR, uvt(val(i + 1, 0), g));
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
-    const double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
-    const double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
+    double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    if (mo.tab) {   // the snapshot's grid: body-frame vectors rotated by theta_n
+        rot2(ms, sx, sy);
+        rot2(ms, dx, dy);
+    }
     double fv[3];
     viscous_flux(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fv);
     const double dp = wR.p - c.pinf;
@@ -67,8 +77,10 @@ __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, con
     const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
     const double *x = xy + 2 * B.node_off;
     const double *y = x + nn;
-    const double mx = 0.5 * (x[i] + x[i + 1]) - xm;
-    const double my = 0.5 * (y[i] + y[i + 1]) - ym;
+    // moment arm: a body-frame difference, rotated with the body
+    double mx = 0.5 * (x[i] + x[i + 1]) - xm;
+    double my = 0.5 * (y[i] + y[i + 1]) - ym;
+    if (mo.tab) rot2(ms, mx, my);
     out[0] = fx;
     out[1] = fy;
     out[2] = mx * fy - my * fx;
@@ -76,7 +88,7 @@ __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, con
 
 __global__ void k_block_loads(const BlockDesc *blks, const double *q, const double *ffw,
                               const double *xy, const double *SJ, const double *dJ, Consts c,
-                              double xm, double ym, double *part) {
+                              double xm, double ym, Motion mo, double *part) {
     const int b = blockIdx.x;
     const int n = blockIdx.y;
     const BlockDesc &B = blks[b];
@@ -85,7 +97,7 @@ __global__ void k_block_loads(const BlockDesc *blks, const double *q, const doub
         for (int i = threadIdx.x; i < B.ni; i += kBS) {
             if (!is_wall_face(B, i)) continue;
             double l[3];
-            face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, l);
+            face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, mo, l);
             acc[0] += l[0];
             acc[1] += l[1];
             acc[2] += l[2];
@@ -133,7 +145,7 @@ __global__ void k_body_coeffs(const BlockDesc *blks, int nblocks, const int *bod
 int launch_forces(hb_grid *g, const double *q, double *cf, hipStream_t s) {
     hipLaunchKernelGGL(k_block_loads, dim3(g->nblocks, kMaxNs), dim3(kBS), 0, s, g->blk_d, q,
                        g->ffw_d, g->xy_d, g->SJ_d, g->dJ_d, g->consts, g->flow.x_mom,
-                       g->flow.y_mom, g->fpart_d);
+                       g->flow.y_mom, g->motion, g->fpart_d);
     const int total = (int)(g->n_forces / 3);
     const double qinf = 0.5 * g->flow.mach * g->flow.mach;
     const double L = g->flow.l_ref;

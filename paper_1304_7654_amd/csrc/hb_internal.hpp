@@ -66,6 +66,15 @@ struct Consts {
     double gamma, mu, kappa, prandtl, cfl, delta_frac, eps, pinf;
 };
 
+// Rigid grid motion for the plain FP64 kernels: per snapshot (block
+// snapshot offset + n) kMotionW doubles {cos theta, sin theta, theta_dot,
+// h, h_dot, 0, 0, 0}; tab == nullptr is the fixed grid.
+constexpr int kMotionW = 8;
+struct Motion {
+    const double *tab;
+    double xp, yp;
+};
+
 // Pointers to the FP64 metrics (see metrics kernels for layouts).
 template <class T>
 struct Metrics {
@@ -113,6 +122,8 @@ struct hb_grid {
     float *ffw_f = nullptr, *ffq_f = nullptr, *dqinf_f = nullptr;
     // scratch
     double *ext_d = nullptr;      // plain path ghost-extended primitives
+    double *mot_d = nullptr;      // motion table [snap][kMotionW]
+    hb::Motion motion{};          // tab = mot_d while a motion is set
     double *FI_d = nullptr, *FJ_d = nullptr;   // plain path face fluxes [ns][4][faces]
     double *q0_d = nullptr;       // RK base state copy (plain path)
     double *qa_d = nullptr, *qb_d = nullptr;   // stage ping-pong (FP64)

@@ -35,9 +35,10 @@ struct FreeStream {
     }
 };
 
-// Ghost-extended primitives ext[n][4][nj+4][ni+4] of one block.
+// Ghost-extended primitives ext[n][4][nj+4][ni+4] of one block (moving
+// walls with a motion set).
 __global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const double *ffw,
-                        double gm1, double *ext) {
+                        double gm1, double *ext, Motion mo, const double *xy) {
     const BlockDesc &B = blks[b];
     const int we = B.ni + 4, he = B.nj + 4;
     const int64_t plane = (int64_t)we * he;
@@ -48,7 +49,8 @@ __global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const dou
     const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
     CellFromState cell{blks, q, n, gm1};
     FreeStream ff{blks, ffw, n};
-    const W4<double> w = value_ij<W4<double>>(blks, b, i, j, cell, ff, MirrorFull<double>());
+    W4<double> w = value_ij<W4<double>>(blks, b, i, j, cell, ff, MirrorFull<double>());
+    if (mo.tab) wall_image_motion(B, i, j, motion_snap(mo, B, n), mo, xy, w);
     double *e = ext + B.ext_off + (int64_t)n * 4 * plane + r;
     e[0] = w.r;
     e[plane] = w.u;
@@ -60,8 +62,23 @@ __device__ inline W4<double> ld(const double *e, int64_t plane, int64_t idx) {
     return W4<double>{e[idx], e[plane + idx], e[2 * plane + idx], e[3 * plane + idx]};
 }
 
+// With a motion set, S and d of snapshot n are the body-frame ones rotated
+// by theta_n, and the face moves with the grid velocity at its midpoint.
+__device__ inline double moving_face(const Motion &mo, const BlockDesc &B, int n, const double *xy,
+                                     int64_t kA, int64_t kB, double &sx, double &sy, double &dx,
+                                     double &dy) {
+    const MotionSnap m = motion_snap(mo, B, n);
+    rot2(m, sx, sy);
+    rot2(m, dx, dy);
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    double gx, gy;
+    grid_velocity(m, mo, 0.5 * (x[kA] + x[kB]), 0.5 * (y[kA] + y[kB]), gx, gy);
+    return gx * sx + gy * sy;
+}
+
 __global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
-                         const double *dI, Consts c, double *FI) {
+                         const double *dI, Consts c, double *FI, Motion mo, const double *xy) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
@@ -78,10 +95,12 @@ __global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const 
     const W4<double> p0 = ld(e, plane, row + i + 2), p1 = ld(e, plane, row + i + 3);
     W4<double> L, R;
     muscl(m2, m1, p0, p1, c.eps, L, R);
-    const double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
-    const double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
+    double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    double vg = 0.0;
+    if (mo.tab) vg = moving_face(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy);
     double fl[4];
-    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl);
+    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl, vg);
     // viscous: L = cell (i-1, j), R = cell (i, j); edge from node (i, j) to (i, j+1)
     const double g = c.gamma;
     const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
@@ -100,7 +119,7 @@ __global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const 
 }
 
 __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
-                         const double *dJ, Consts c, double *FJ) {
+                         const double *dJ, Consts c, double *FJ, Motion mo, const double *xy) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,10 +137,15 @@ __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const 
     const W4<double> p1 = ld(e, plane, (int64_t)(j + 3) * we + col);
     W4<double> L, R;
     muscl(m2, m1, p0, p1, c.eps, L, R);
-    const double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
-    const double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
+    double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    double vg = 0.0;
+    if (mo.tab) {
+        const int64_t kA = (int64_t)j * (B.ni + 1) + i;
+        vg = moving_face(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy);
+    }
     double fl[4];
-    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl);
+    roe_flux(L, R, sx, sy, c.gamma, c.delta_frac, fl, vg);
     // viscous: L = cell (i, j-1), R = cell (i, j); edge from node (i+1, j) to (i, j)
     const double g = c.gamma;
     const UVT<double> uL = uvt(m1, g), uR = uvt(p0, g);
@@ -145,7 +169,8 @@ __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const 
 __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const double *FJ,
                          const double *SI, const double *SJ, const double *V, const double *D,
                          const double *qin, const double *q0, double *out, int mode, double alpha,
-                         int norm, double *partials, int *status, Consts c) {
+                         int norm, double *partials, int *status, Consts c, Motion mo,
+                         const double *C) {
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,9 +203,20 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
                 for (int v = 0; v < 4; ++v) out[o + v * plane] = rs[v];
             } else {
                 const double *b0 = q0 + o;
-                const W4<double> w0 = prim_from_cons<double>(b0[0], b0[plane], b0[2 * plane],
-                                                             b0[3 * plane], c.gamma - 1.0);
-                const double dt = local_dt<double>(w0, sxi, syi, sxj, syj, vol, c.gamma,
+                W4<double> w0 = prim_from_cons<double>(b0[0], b0[plane], b0[2 * plane],
+                                                       b0[3 * plane], c.gamma - 1.0);
+                double ax = sxi, ay = syi, bx = sxj, by = syj;
+                if (mo.tab) {   // snapshot's normals, velocity relative to the grid at the centre
+                    const MotionSnap m = motion_snap(mo, B, n);
+                    rot2(m, ax, ay);
+                    rot2(m, bx, by);
+                    const int64_t nc = (int64_t)B.ni * B.nj;
+                    double gx, gy;
+                    grid_velocity(m, mo, C[2 * B.cell_off + t], C[2 * B.cell_off + nc + t], gx, gy);
+                    w0.u -= gx;
+                    w0.v -= gy;
+                }
+                const double dt = local_dt<double>(w0, ax, ay, bx, by, vol, c.gamma,
                                                    c.mu / c.prandtl, c.cfl, B.omega_nh);
                 const double fac = alpha * dt / vol;
                 double nq[4];
@@ -217,14 +253,14 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
         const BlockDesc &B = g->blk[b];
         const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
         hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
-                           c.gamma - 1.0, g->ext_d);
+                           c.gamma - 1.0, g->ext_d, g->motion, g->xy_d);
         hipLaunchKernelGGL(k_flux_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
-                           g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d);
+                           g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d, g->motion, g->xy_d);
         hipLaunchKernelGGL(k_flux_j, dim3(nblk((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
-                           g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d);
+                           g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d, g->motion, g->xy_d);
         hipLaunchKernelGGL(k_update, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
-                           alpha, norm, g->partials_d, g->status_d, c);
+                           alpha, norm, g->partials_d, g->status_d, c, g->motion, g->C_d);
     }
     return check_hip(hipGetLastError(), "plain stage launch");
 }
@@ -236,7 +272,7 @@ int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_
     const BlockDesc &B = g->blk[b];
     const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
     hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
-                       g->consts.gamma - 1.0, ext);
+                       g->consts.gamma - 1.0, ext, Motion{nullptr, 0.0, 0.0}, g->xy_d);
     return check_hip(hipGetLastError(), "ghost launch");
 }
 

@@ -23,7 +23,7 @@ HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
            "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_save_state", "hb_load_state", "hb_autotune", "hb_set_tuning",
-           "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_get_status",
+           "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_set_motion", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
 
@@ -57,6 +57,11 @@ class c_flow(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("mach", "reynolds", "prandtl", "gamma", "alpha0", "alpha_amp", "k_red", "l_ref",
                  "x_mom", "y_mom")]
+
+
+class c_motion(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("pitch_amp", "pitch_phase", "heave_amp", "x_pivot", "y_pivot")]
 
 
 class c_solver(ctypes.Structure):
@@ -99,6 +104,7 @@ def lib() -> ctypes.CDLL:
     L.hb_get_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
     L.hb_set_xy.argtypes = [vp, vp, vp]
     L.hb_set_alpha0.argtypes = [vp, dp]
+    L.hb_set_motion.argtypes = [vp, ctypes.POINTER(c_motion)]
     L.hb_get_status.argtypes = [vp]
     L.hb_profile_stages.argtypes = [vp, i32]
     L.hb_stage_stats.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i64)]
@@ -276,6 +282,14 @@ class Grid:
 
     def set_alpha0(self, a: float):
         _check(lib().hb_set_alpha0(self.h, float(a)))
+
+    def set_motion(self, pitch_amp: float = 0.0, pitch_phase: float = 0.0, heave_amp: float = 0.0,
+                   x_pivot: float = 0.0, y_pivot: float = 0.0):
+        """Rigid heave and pitch of the whole grid (hb_set_motion); all zero
+        amplitudes clear it."""
+        m = c_motion(float(pitch_amp), float(pitch_phase), float(heave_amp), float(x_pivot),
+                     float(y_pivot))
+        _check(lib().hb_set_motion(self.h, ctypes.byref(m)))
 
     def status(self) -> int:
         return lib().hb_get_status(self.h)
