@@ -100,6 +100,63 @@ def algorithmic_bytes_per_iteration(problem) -> float:
     return cs * (48 + 64 + 64 + 80) + 4 * 36 * cells
 
 
+# rigid motion of the moving-grid leg: 0.3 rad of pitch about the quarter
+# chord, leading a heave of 1.5 length units by 0.5 rad
+MOTION = dict(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_pivot=0.0)
+
+
+def plain_stage_bytes(problem, moving) -> float:
+    """Bytes one stage of the plain FP64 path (every intermediate in HBM)
+    must move: the ghost fill reads Q and writes the ghost-extended
+    primitives E; the i- and j-face kernels each read E and their face
+    metrics (S, d) and write the face fluxes; the update reads both flux
+    arrays, the stage input, the base state, the face normals and the cell
+    area, and writes the new state.  A moving grid adds the node coordinates
+    (both face kernels) and the cell centres (update).  FP64 words."""
+    tot = 0
+    for b in problem.blocks:
+        ni, nj, ns = b.ni, b.nj, b.ns
+        q = 4 * ni * nj * ns
+        ext = 4 * (ni + 4) * (nj + 4) * ns
+        fi, fj = 4 * (ni + 1) * nj * ns, 4 * ni * (nj + 1) * ns
+        mi, mj = 4 * (ni + 1) * nj, 4 * ni * (nj + 1)
+        words = ((q + ext) + (ext + mi + fi) + (ext + mj + fj)
+                 + (fi + fj + 3 * q + mi // 2 + mj // 2 + ni * nj))
+        if moving:
+            words += 4 * (ni + 1) * (nj + 1) + 2 * ni * nj
+        tot += 8 * words
+    return float(tot)
+
+
+def plain_leg(torch, hb, problem, q0, steps, motion=None):
+    """Plain FP64 per-block path: throughput with loads every iteration, and
+    its stage time from HIP events around every stage (on the launch
+    stream) for the roofline over plain_stage_bytes."""
+    cs = problem.cell_snapshots
+    stages = len(problem.solver.rk_alpha)
+    g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=0)
+    if motion:
+        g.set_motion(**motion)
+    q = q0.clone()
+    time_steps(torch, g, q, 1)
+    q = q0.clone()
+    t, _ = time_steps(torch, g, q, steps)
+    assert g.status() == hb.HB_OK, "non-finite state in the plain FP64 run"
+    q = q0.clone()
+    g.profile_stages(True)
+    time_steps(torch, g, q, steps, forces=False)
+    ms, n = g.stage_stats()
+    g.profile_stages(False)
+    g.close()
+    stage_s = ms / 1000.0 / n
+    nbytes = plain_stage_bytes(problem, bool(motion))
+    return {"value": cs * stages * steps / t, "ms_per_step": 1000.0 * t / steps,
+            "roofline": {"bound": "hbm", "achieved": nbytes / stage_s / 1e9, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": nbytes / stage_s / 1e9 / PEAK_HBM_GBS,
+                         "kernels": "per block: k_ghost, k_flux_i, k_flux_j, k_update",
+                         "avg_stage_ms": 1000.0 * stage_s, "algorithmic_bytes_per_stage": nbytes}}
+
+
 def stream_probe(torch, mib=1024, reps=10):
     """Device copy bandwidth (read + write bytes per second) of a plain
     torch copy of `mib` MiB, the practical HBM peak the traffic is also set
@@ -241,7 +298,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch32_mixed")
-    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=5,
+                    help="iterations of the fixed-grid FP64 legs (0 skips them)")
+    ap.add_argument("--moving-steps", type=int, default=5,
+                    help="iterations of the moving-grid leg (0 skips it)")
+    ap.add_argument("--moving-only", action="store_true",
+                    help="run only the moving-grid leg (for a kernel profile of it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/primal timing")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -279,6 +341,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.moving_only:
+        print(json.dumps({"moving_grid": plain_leg(torch, hb, problem, q0, args.moving_steps, MOTION)}))
+        return
+
     # ---- FP32-bulk batched (the product path) ------------------------------
     g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=1, batched=1)
     if args.tuning:
@@ -307,21 +373,26 @@ def main():
     probe = stream_probe(torch)
 
     # ---- plain FP64, per-block launches (baseline on the same GPU) ---------
-    gp = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=0)
-    q = q0.clone()
-    time_steps(torch, gp, q, 1)
-    q = q0.clone()
-    tp, _ = time_steps(torch, gp, q, args.plain_steps)
-    plain = cs * stages * args.plain_steps / tp
-    gp.close()
-    # ---- fused FP64 (same kernel design, FP64 arithmetic) ------------------
-    gf = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=1)
-    q = q0.clone()
-    time_steps(torch, gf, q, 1)
-    q = q0.clone()
-    tf, _ = time_steps(torch, gf, q, args.plain_steps)
-    fused64 = cs * stages * args.plain_steps / tf
-    gf.close()
+    plain = fused = None
+    if args.plain_steps > 0:
+        plain = plain_leg(torch, hb, problem, q0, args.plain_steps)
+        plain["speedup_of_value"] = value / plain["value"]
+        # ---- fused FP64 (same kernel design, FP64 arithmetic) --------------
+        gf = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=1)
+        q = q0.clone()
+        time_steps(torch, gf, q, 1)
+        q = q0.clone()
+        tf, _ = time_steps(torch, gf, q, args.plain_steps)
+        fused = {"value": cs * stages * args.plain_steps / tf,
+                 "ms_per_step": 1000.0 * tf / args.plain_steps}
+        gf.close()
+    # ---- the plain FP64 path on the rigidly heaving and pitching grid ------
+    moving = None
+    if args.moving_steps > 0:
+        moving = plain_leg(torch, hb, problem, q0, args.moving_steps, MOTION)
+        moving["motion"] = MOTION
+        if plain:
+            moving["vs_fixed_grid_plain"] = moving["value"] / plain["value"]
 
     out = {
         "metric": METRIC,
@@ -340,9 +411,9 @@ def main():
                    "cell_snapshots": cs, "stages_per_step": stages,
                    "parallelism": "single GPU, one persistent launch per stage",
                    "tuning": tuning},
-        "fp64_plain_per_block": {"value": plain, "ms_per_step": 1000.0 * tp / args.plain_steps,
-                                 "speedup_of_value": value / plain},
-        "fp64_fused_batched": {"value": fused64, "ms_per_step": 1000.0 * tf / args.plain_steps},
+        "fp64_plain_per_block": plain,
+        "fp64_fused_batched": fused,
+        "moving_grid": moving,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,

@@ -12,6 +12,19 @@ constexpr int kBS = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
 
+// Workgroups are dealt round-robin to the 8 XCDs (one L2 each).  The plain
+// kernels launch 8 ceil(W/8) workgroups for W logical ones and take logical
+// workgroup (w mod 8) ceil(W/8) + w / 8, so that each XCD walks a contiguous
+// range of rows and the stencil rows shared by neighbouring rows stay in
+// its L2.  -1: a padding workgroup.
+inline unsigned nblk_xcd(int64_t n) { return 8 * ((nblk(n) + 7) / 8); }
+
+__device__ __forceinline__ int64_t xcd_group(int64_t n) {
+    const int64_t wg = (n + kBS - 1) / kBS, per = (wg + 7) / 8;
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    return L < wg ? L : -1;
+}
+
 struct CellFromState {
     const BlockDesc *blks;
     const double *q;
@@ -42,8 +55,9 @@ __global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const dou
     const BlockDesc &B = blks[b];
     const int we = B.ni + 4, he = B.nj + 4;
     const int64_t plane = (int64_t)we * he;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= plane * B.ns) return;
+    const int64_t L = xcd_group(plane * B.ns);
+    const int64_t t = L < 0 ? -1 : L * kBS + threadIdx.x;
+    if (t < 0 || t >= plane * B.ns) return;
     const int n = (int)(t / plane);
     const int64_t r = t % plane;
     const int i = (int)(r % we) - 2, j = (int)(r / we) - 2;
@@ -82,8 +96,9 @@ __global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const 
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nf * B.ns) return;
+    const int64_t lw = xcd_group(nf * B.ns);
+    const int64_t t = lw < 0 ? -1 : lw * kBS + threadIdx.x;
+    if (t < 0 || t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
     const int i = (int)(f % W), j = (int)(f / W);
@@ -122,8 +137,9 @@ __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const 
                          const double *dJ, Consts c, double *FJ, Motion mo, const double *xy) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nf * B.ns) return;
+    const int64_t lw = xcd_group(nf * B.ns);
+    const int64_t t = lw < 0 ? -1 : lw * kBS + threadIdx.x;
+    if (t < 0 || t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
     const int i = (int)(f % B.ni), j = (int)(f / B.ni);
@@ -163,17 +179,26 @@ __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const 
     o[3 * nf] = fl[3] - fv[2];
 }
 
-// Cell update.  mode 0: out = R*(qin).  mode 1: out = q0 - alpha (dtau/V) R*(qin),
-// dtau from q0; with `norm` set, the block's partial sums of (R*_rho/V)^2
-// go to partials[part_off + blockIdx.x].
-__global__ void k_update(const BlockDesc *blks, int b, const double *FI, const double *FJ,
-                         const double *SI, const double *SJ, const double *V, const double *D,
-                         const double *qin, const double *q0, double *out, int mode, double alpha,
-                         int norm, double *partials, int *status, Consts c, Motion mo,
-                         const double *C) {
+// Cell update, one thread per cell and snapshot.  mode 0: out = R*(qin).
+// mode 1: out = q0 - alpha (dtau/V) R*(qin), dtau from q0; with `norm` set,
+// each workgroup's partial sum of (R*_rho/V)^2 goes to
+// partials[part_off + logical workgroup].  Logical workgroup L takes
+// snapshot L mod N_s of the cell group L / N_s (256 cells), so the N_s
+// workgroups that read the same cells for the HB source are neighbours (one
+// XCD, one L2); each thread reads its cell's stage input of every snapshot
+// into registers.
+__global__ void __launch_bounds__(kBS) k_update(const BlockDesc *blks, int b, const double *FI,
+                                               const double *FJ, const double *SI, const double *SJ,
+                                               const double *V, const double *D, const double *qin,
+                                               const double *q0, double *out, int mode, double alpha,
+                                               int norm, double *partials, int *status, Consts c,
+                                               Motion mo, const double *C) {
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t L = xcd_group(((plane + kBS - 1) / kBS) * B.ns * kBS);
+    if (L < 0) return;                     // a whole padding workgroup
+    const int n = (int)(L % B.ns);
+    const int64_t t = (L / B.ns) * kBS + threadIdx.x;
     double acc = 0.0;
     int bad = 0;
     if (t < plane) {
@@ -182,52 +207,55 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
         const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
         const int64_t fi0 = (int64_t)j * W + i, fj0 = t;
         const double vol = V[B.cell_off + t];
-        const double *dm = D + B.d_off;
+        const double *dm = D + B.d_off + n * kNsPad;
         const double *qi = qin + B.q_off + t;
-        const double sxi = 0.5 * (SI[2 * B.fi_off + fi0] + SI[2 * B.fi_off + fi0 + 1]);
-        const double syi = 0.5 * (SI[2 * B.fi_off + nfi + fi0] + SI[2 * B.fi_off + nfi + fi0 + 1]);
-        const double sxj = 0.5 * (SJ[2 * B.fj_off + fj0] + SJ[2 * B.fj_off + fj0 + B.ni]);
-        const double syj = 0.5 * (SJ[2 * B.fj_off + nfj + fj0] + SJ[2 * B.fj_off + nfj + fj0 + B.ni]);
-        for (int n = 0; n < B.ns; ++n) {
-            double rs[4];
-            for (int v = 0; v < 4; ++v) {
-                const double *fi = FI + B.fiq_off + ((int64_t)n * 4 + v) * nfi;
-                const double *fj = FJ + B.fjq_off + ((int64_t)n * 4 + v) * nfj;
-                double src = 0.0;
-                for (int m = 0; m < B.ns; ++m)
-                    src += dm[n * kNsPad + m] * qi[((int64_t)m * 4 + v) * plane];
-                rs[v] = (fi[fi0 + 1] - fi[fi0]) + (fj[fj0 + B.ni] - fj[fj0]) + vol * src;
-            }
-            const int64_t o = B.q_off + (int64_t)n * 4 * plane + t;
-            if (mode == 0) {
-                for (int v = 0; v < 4; ++v) out[o + v * plane] = rs[v];
-            } else {
-                const double *b0 = q0 + o;
-                W4<double> w0 = prim_from_cons<double>(b0[0], b0[plane], b0[2 * plane],
-                                                       b0[3 * plane], c.gamma - 1.0);
-                double ax = sxi, ay = syi, bx = sxj, by = syj;
-                if (mo.tab) {   // snapshot's normals, velocity relative to the grid at the centre
-                    const MotionSnap m = motion_snap(mo, B, n);
-                    rot2(m, ax, ay);
-                    rot2(m, bx, by);
-                    const int64_t nc = (int64_t)B.ni * B.nj;
-                    double gx, gy;
-                    grid_velocity(m, mo, C[2 * B.cell_off + t], C[2 * B.cell_off + nc + t], gx, gy);
-                    w0.u -= gx;
-                    w0.v -= gy;
-                }
-                const double dt = local_dt<double>(w0, ax, ay, bx, by, vol, c.gamma,
-                                                   c.mu / c.prandtl, c.cfl, B.omega_nh);
-                const double fac = alpha * dt / vol;
-                double nq[4];
-                for (int v = 0; v < 4; ++v) nq[v] = b0[v * plane] - fac * rs[v];
-                for (int v = 0; v < 4; ++v) out[o + v * plane] = nq[v];
-                const double pn = (c.gamma - 1.0) * (nq[3] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]) / nq[0]);
-                if (!(nq[0] > 0.0) || !(pn > 0.0) || !isfinite(rs[0] + rs[1] + rs[2] + rs[3])) bad = 1;
-            }
-            const double rr = rs[0] / vol;
-            acc += rr * rr;
+        double qm[kMaxNs][4];
+#pragma unroll
+        for (int m = 0; m < kMaxNs; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) qm[m][v] = m < B.ns ? qi[((int64_t)m * 4 + v) * plane] : 0.0;
+        double rs[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double *fi = FI + B.fiq_off + ((int64_t)n * 4 + v) * nfi;
+            const double *fj = FJ + B.fjq_off + ((int64_t)n * 4 + v) * nfj;
+            double src = 0.0;
+#pragma unroll
+            for (int m = 0; m < kMaxNs; ++m)
+                if (m < B.ns) src += dm[m] * qm[m][v];
+            rs[v] = (fi[fi0 + 1] - fi[fi0]) + (fj[fj0 + B.ni] - fj[fj0]) + vol * src;
         }
+        const int64_t o = B.q_off + (int64_t)n * 4 * plane + t;
+        if (mode == 0) {
+            for (int v = 0; v < 4; ++v) out[o + v * plane] = rs[v];
+        } else {
+            const double *b0 = q0 + o;
+            W4<double> w0 = prim_from_cons<double>(b0[0], b0[plane], b0[2 * plane], b0[3 * plane],
+                                                   c.gamma - 1.0);
+            double ax = 0.5 * (SI[2 * B.fi_off + fi0] + SI[2 * B.fi_off + fi0 + 1]);
+            double ay = 0.5 * (SI[2 * B.fi_off + nfi + fi0] + SI[2 * B.fi_off + nfi + fi0 + 1]);
+            double bx = 0.5 * (SJ[2 * B.fj_off + fj0] + SJ[2 * B.fj_off + fj0 + B.ni]);
+            double by = 0.5 * (SJ[2 * B.fj_off + nfj + fj0] + SJ[2 * B.fj_off + nfj + fj0 + B.ni]);
+            if (mo.tab) {   // snapshot's normals, velocity relative to the grid at the centre
+                const MotionSnap m = motion_snap(mo, B, n);
+                rot2(m, ax, ay);
+                rot2(m, bx, by);
+                double gx, gy;
+                grid_velocity(m, mo, C[2 * B.cell_off + t], C[2 * B.cell_off + plane + t], gx, gy);
+                w0.u -= gx;
+                w0.v -= gy;
+            }
+            const double dt = local_dt<double>(w0, ax, ay, bx, by, vol, c.gamma, c.mu / c.prandtl,
+                                               c.cfl, B.omega_nh);
+            const double fac = alpha * dt / vol;
+            double nq[4];
+            for (int v = 0; v < 4; ++v) nq[v] = b0[v * plane] - fac * rs[v];
+            for (int v = 0; v < 4; ++v) out[o + v * plane] = nq[v];
+            const double pn = (c.gamma - 1.0) * (nq[3] - 0.5 * (nq[1] * nq[1] + nq[2] * nq[2]) / nq[0]);
+            if (!(nq[0] > 0.0) || !(pn > 0.0) || !isfinite(rs[0] + rs[1] + rs[2] + rs[3])) bad = 1;
+        }
+        const double rr = rs[0] / vol;
+        acc = rr * rr;
     }
     // one atomic per wave that met a bad cell
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, 1);
@@ -239,7 +267,7 @@ __global__ void k_update(const BlockDesc *blks, int b, const double *FI, const d
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[B.part_off + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partials[B.part_off + L] = red[0];
 }
 
 Metrics<double> fp64_metrics(hb_grid *g) {
@@ -252,13 +280,14 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
-        hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
+        hipLaunchKernelGGL(k_ghost, dim3(nblk_xcd(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
                            c.gamma - 1.0, g->ext_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_i, dim3(nblk((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_i, dim3(nblk_xcd((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
                            g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_j, dim3(nblk((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_j, dim3(nblk_xcd((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
                            g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_update, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
+        hipLaunchKernelGGL(k_update, dim3(nblk_xcd((int64_t)nblk((int64_t)B.ni * B.nj) * B.ns * kBS)),
+                           dim3(kBS), 0, s, g->blk_d, b,
                            g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
                            alpha, norm, g->partials_d, g->status_d, c, g->motion, g->C_d);
     }
@@ -271,13 +300,13 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
 int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_t s) {
     const BlockDesc &B = g->blk[b];
     const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
-    hipLaunchKernelGGL(k_ghost, dim3(nblk(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
+    hipLaunchKernelGGL(k_ghost, dim3(nblk_xcd(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
                        g->consts.gamma - 1.0, ext, Motion{nullptr, 0.0, 0.0}, g->xy_d);
     return check_hip(hipGetLastError(), "ghost launch");
 }
 
 // Number of norm partials the plain path writes for a block.
-int64_t plain_partials(const BlockDesc &B) { return nblk((int64_t)B.ni * B.nj); }
+int64_t plain_partials(const BlockDesc &B) { return (int64_t)nblk((int64_t)B.ni * B.nj) * B.ns; }
 
 int plain_residual(hb_grid *g, const double *q, double *r, hipStream_t s) {
     return stage(g, q, q, r, 0, 0.0, 0, s);
