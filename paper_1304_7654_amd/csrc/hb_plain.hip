@@ -4,26 +4,15 @@
 // the fused batched kernel is measured against, and a second, independently
 // structured GPU evaluation of the same residual.
 #include "hb_device.hpp"
+#include "hb_xcd.hpp"
 
 namespace hb {
 namespace {
 
 constexpr int kBS = 256;
+static_assert(kBS == kXcdBS, "one-thread-per-item kernels use 256-thread workgroups");
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
-
-// Workgroups are dealt round-robin to the 8 XCDs (one L2 each).  The plain
-// kernels launch 8 ceil(W/8) workgroups for W logical ones and take logical
-// workgroup (w mod 8) ceil(W/8) + w / 8, so that each XCD walks a contiguous
-// range of rows and the stencil rows shared by neighbouring rows stay in
-// its L2.  -1: a padding workgroup.
-inline unsigned nblk_xcd(int64_t n) { return 8 * ((nblk(n) + 7) / 8); }
-
-__device__ __forceinline__ int64_t xcd_group(int64_t n) {
-    const int64_t wg = (n + kBS - 1) / kBS, per = (wg + 7) / 8;
-    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    return L < wg ? L : -1;
-}
 
 struct CellFromState {
     const BlockDesc *blks;
@@ -280,13 +269,13 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
-        hipLaunchKernelGGL(k_ghost, dim3(nblk_xcd(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
+        hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
                            c.gamma - 1.0, g->ext_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_i, dim3(nblk_xcd((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_i, dim3(xcd_grid((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
                            g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_j, dim3(nblk_xcd((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_j, dim3(xcd_grid((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
                            g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_update, dim3(nblk_xcd((int64_t)nblk((int64_t)B.ni * B.nj) * B.ns * kBS)),
+        hipLaunchKernelGGL(k_update, dim3(xcd_grid((int64_t)nblk((int64_t)B.ni * B.nj) * B.ns * kBS)),
                            dim3(kBS), 0, s, g->blk_d, b,
                            g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
                            alpha, norm, g->partials_d, g->status_d, c, g->motion, g->C_d);
@@ -300,7 +289,7 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
 int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_t s) {
     const BlockDesc &B = g->blk[b];
     const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
-    hipLaunchKernelGGL(k_ghost, dim3(nblk_xcd(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
+    hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
                        g->consts.gamma - 1.0, ext, Motion{nullptr, 0.0, 0.0}, g->xy_d);
     return check_hip(hipGetLastError(), "ghost launch");
 }
