@@ -46,6 +46,7 @@ int main(void) {
          offsetof(hb_solver, limiter_eps), offsetof(hb_solver, graph_iters));
   printf("%zu %zu %zu\n", sizeof(hb_tuning), offsetof(hb_tuning, tile_order),
          offsetof(hb_tuning, stage_ms));
+  printf("%zu %zu\n", sizeof(hb_motion), offsetof(hb_motion, y_pivot));
   return 0;
 }
 '''
@@ -62,7 +63,8 @@ int main(void) {
            hb.c_block.body_id.offset,
            hb.c_solver.rk_alpha.offset, hb.c_solver.precision.offset,
            hb.c_solver.limiter_eps.offset, hb.c_solver.graph_iters.offset,
-           ctypes.sizeof(hb.c_tuning), hb.c_tuning.tile_order.offset, hb.c_tuning.stage_ms.offset]
+           ctypes.sizeof(hb.c_tuning), hb.c_tuning.tile_order.offset, hb.c_tuning.stage_ms.offset,
+           ctypes.sizeof(hb.c_motion), hb.c_motion.y_pivot.offset]
     assert got == ref
 
 
@@ -119,3 +121,5 @@ def test_null_handles():
     assert L.hb_grid_destroy(None) == 0
     assert L.hb_residual(None, None, None, None) == hb.HB_ERR_ARG
     assert L.hb_get_status(None) == hb.HB_ERR_ARG
+    m = hb.c_motion(0.1, 0.0, 0.2, 0.0, 0.0)
+    assert L.hb_set_motion(None, ctypes.byref(m)) == hb.HB_ERR_ARG
