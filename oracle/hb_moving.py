@@ -35,7 +35,8 @@ Grids with i-side walls or cuts are outside this reading (ValueError).
 Parity status: pinned in tests/test_oracle_moving.py (zero motion, heave as
 a Galilean shift, rotation equivariance, free-stream preservation on a
 pitching and heaving grid, grid velocity against differenced positions,
-no-slip wall images).
+no-slip wall images, converged N_H = 1 snapshots against the moving-grid
+time-domain march).
 """
 from __future__ import annotations
 
@@ -151,18 +152,50 @@ def _snapshot(b, w, winf, m, flow, n):
     return xy, we, (th, thd, h, hd)
 
 
+def moving_flux_balance(b: O.OBlock, q1: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
+                        m: OMotion, phase: float, winf1: torch.Tensor) -> torch.Tensor:
+    """Net moving-face outflow of each cell for a one-snapshot state
+    q1[1][4][nj][ni] on the grid at omega t = phase, far field winf1[1][4]."""
+    th, thd, h, hd = motion_at(m, flow.omega, phase)
+    xy = torch.stack(place(m, th, h, b.xy[0], b.xy[1]))
+    we = moving_extend(b, O.primitives(q1, flow.gamma), winf1, xy, m, thd, h, hd)
+    vg = face_speeds(xy, m, thd, h, hd)
+    FI, FJ = O.face_fluxes(b, q1, flow, solver, xy=xy, we=we, vg=vg)
+    return (FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :])
+
+
 def moving_residual(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
                     m: OMotion) -> torch.Tensor:
     """R*_n = sum over faces of the moving-face fluxes on grid n + V (D Q)_n."""
-    w = O.primitives(q, flow.gamma)
     winf = O.freestream_prim(flow, b.ns)
-    parts = []
-    for n in range(b.ns):
-        xy, we, (_, thd, h, hd) = _snapshot(b, w, winf, m, flow, n)
-        vg = face_speeds(xy, m, thd, h, hd)
-        FI, FJ = O.face_fluxes(b, q[n:n + 1], flow, solver, xy=xy, we=we, vg=vg)
-        parts.append((FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :]))
+    parts = [moving_flux_balance(b, q[n:n + 1], flow, solver, m, 2.0 * math.pi * n / b.ns,
+                                 winf[n:n + 1]) for n in range(b.ns)]
     return torch.cat(parts) + O.hb_source(b, q, flow)
+
+
+def moving_td_march(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver, m: OMotion,
+                    dt: float, n_steps: int, t0: float = 0.0) -> torch.Tensor:
+    """Time-domain reference on the moving grid: hb_oracle.td_march (classical
+    fourth-order Runge-Kutta in physical time on V dQ/dt = -R(Q, t)) with R
+    the moving-face flux balance on the grid of time t (the cell areas do not
+    change under the rigid motion).  q is a single-snapshot state."""
+    V = O.metrics(b.xy)[2]
+
+    def f(x, t):
+        a = flow.alpha0 + flow.alpha_amp * math.sin(flow.omega * t)
+        winf = torch.tensor([[1.0, flow.mach * math.cos(a), flow.mach * math.sin(a),
+                              1.0 / flow.gamma]], dtype=DT)
+        return -moving_flux_balance(b, x, flow, solver, m, flow.omega * t, winf) / V
+
+    t = t0
+    for _ in range(n_steps):
+        k1 = f(q, t)
+        k2 = f(q + 0.5 * dt * k1, t + 0.5 * dt)
+        k3 = f(q + 0.5 * dt * k2, t + 0.5 * dt)
+        k4 = f(q + dt * k3, t + dt)
+        q = q + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        t += dt
+    return q
 
 
 def moving_residual_all(blocks: Sequence[O.OBlock], q: torch.Tensor, flow, solver,

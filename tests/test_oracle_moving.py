@@ -250,3 +250,13 @@ def test_moving_rk_iterate_zero_motion_matches_fixed():
     qa, na = M.moving_rk_iterate([b], q, flow, solver, M.OMotion(), 2)
     qb, nb = O.rk_iterate([b], q, flow, solver, 2)
     assert _rel(qa, qb) < 1e-13 and _rel(na, nb) < 1e-12
+
+
+def test_moving_td_march_zero_motion_matches_fixed():
+    b = O.OBlock(16, 6, 0, torch.as_tensor(synth.o_grid(16, 6)), (PER, PER, WALL, FF))
+    flow, solver = _flow(), O.OSolver()
+    q = _state(b, flow, 8)
+    dt = 0.5 * float(O.local_dt(b, q, flow, solver).min())
+    qa = M.moving_td_march(b, q, flow, solver, M.OMotion(x_pivot=0.2), dt, 4, 0.3)
+    qb = O.td_march(b, q, flow, solver, dt, 4, 0.3)
+    assert _rel(qa - q, qb - q) < 1e-12
