@@ -151,7 +151,8 @@ typedef struct {
  * Roe eigenvalues relative to the face; no-slip walls move with the grid
  * (ghost velocity 2 u_wall - u); the local step uses the velocity relative
  * to the grid; loads are taken on the moved grid with the moment about the
- * reference point carried by the body, lift and drag along alpha0. */
+ * reference point carried by the body, lift and drag along alpha0.
+ * hb_td_march moves the grid continuously (the motion at each stage time). */
 typedef struct {
     double pitch_amp, pitch_phase, heave_amp, x_pivot, y_pivot;
 } hb_motion;
@@ -292,9 +293,9 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
 
 /* Set (m non-NULL with a non-zero amplitude) or clear (NULL, or both
  * amplitudes zero) the rigid grid motion described at hb_motion.  It then
- * applies to hb_residual, hb_rk_iterate and hb_forces.  HB_ERR_UNSUPPORTED
- * for batched grids, for blocks with walls on an i side or with cuts; while
- * a motion is set the adjoints, hb_td_march and hb_set_xy return
+ * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march.
+ * HB_ERR_UNSUPPORTED for batched grids, for blocks with walls on an i side or
+ * with cuts; while a motion is set the adjoints and hb_set_xy return
  * HB_ERR_UNSUPPORTED.  HB_ERR_ARG for non-finite values.  Synchronises the
  * current device. */
 int hb_set_motion(hb_grid *g, const hb_motion *m);

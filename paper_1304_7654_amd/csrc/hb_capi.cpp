@@ -533,7 +533,6 @@ int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, vo
         return fail(HB_ERR_ARG, "need n_steps >= 0, finite t0 and dt > 0");
     for (const BlockDesc &B : g->blk)
         if (B.nh != 0) return fail(HB_ERR_UNSUPPORTED, "the time-domain march needs n_harm = 0 in every block");
-    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no time-domain march on a moving grid");
     return launch_td_march(g, q, t0, dt, n_steps, (hipStream_t)stream);
 }
 
@@ -617,6 +616,7 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
                    "motion upload");
     if (rc) return rc;
     g->motion = Motion{g->mot_d, m->x_pivot, m->y_pivot};
+    g->motion_par = *m;
     return HB_OK;
 }
 

@@ -124,6 +124,7 @@ struct hb_grid {
     double *ext_d = nullptr;      // plain path ghost-extended primitives
     double *mot_d = nullptr;      // motion table [snap][kMotionW]
     hb::Motion motion{};          // tab = mot_d while a motion is set
+    hb_motion motion_par{};       // the motion last set (time-domain march)
     double *FI_d = nullptr, *FJ_d = nullptr;   // plain path face fluxes [ns][4][faces]
     double *q0_d = nullptr;       // RK base state copy (plain path)
     double *qa_d = nullptr, *qb_d = nullptr;   // stage ping-pong (FP64)

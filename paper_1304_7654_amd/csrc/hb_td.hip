@@ -9,7 +9,9 @@
 //   Q_1 = Q + dt/2 k_0,  Q_2 = Q + dt/2 k_1,  Q_3 = Q + dt k_2,
 //   Q <- Q + dt/6 (k_0 + 2 k_1 + 2 k_2 + k_3).
 // Every residual is the grid's own residual path (batched or per-block,
-// FP64 or FP32 bulk); the stage combinations are FP64.
+// FP64 or FP32 bulk); the stage combinations are FP64.  On a moving grid
+// (plain path) the motion table is set to the rigid motion at each stage
+// time, as the far field is, and the cell areas stay constant.
 #include "hb_device.hpp"
 
 namespace hb {
@@ -33,6 +35,19 @@ __global__ void k_set_far_field(int n_snap, double mach, double gamma, double al
         ffw_f[4 * k + c] = (float)w[c];
         ffq_f[4 * k + c] = (float)q[c];
     }
+}
+
+// motion table of every snapshot at one time (one snapshot per block here)
+__global__ void k_set_motion(int n_snap, double c, double s, double thd, double h, double hd,
+                             double *tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_snap) return;
+    double *t = tab + (int64_t)kMotionW * k;
+    t[0] = c;
+    t[1] = s;
+    t[2] = thd;
+    t[3] = h;
+    t[4] = hd;
 }
 
 // stage s of one block: acc (+)= w_s R; s < 3: Qs = Q - a_s dt R / V;
@@ -65,6 +80,16 @@ int set_far_field(hb_grid *g, double alpha, hipStream_t s) {
     return check_hip(hipGetLastError(), "far-field launch");
 }
 
+// rigid motion at time t: theta = A sin(omega t + phi), h = A_h sin(omega t)
+int set_motion_at(hb_grid *g, double omega, double t, hipStream_t s) {
+    const hb_motion &m = g->motion_par;
+    const double th = m.pitch_amp * sin(omega * t + m.pitch_phase);
+    hipLaunchKernelGGL(k_set_motion, dim3(nblk(g->n_snap)), dim3(kBS), 0, s, (int)g->n_snap, cos(th),
+                       sin(th), omega * m.pitch_amp * cos(omega * t + m.pitch_phase),
+                       m.heave_amp * sin(omega * t), omega * m.heave_amp * cos(omega * t), g->mot_d);
+    return check_hip(hipGetLastError(), "motion launch");
+}
+
 int residual_any(hb_grid *g, const double *q, double *r, hipStream_t s) {
     return g->solver.batched ? fused_residual(g, q, r, s) : plain_residual(g, q, r, s);
 }
@@ -86,6 +111,7 @@ int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hi
         for (int st = 0; st < 4 && !rc; ++st) {
             const double ts = t + c[st] * dt;
             rc = set_far_field(g, g->flow.alpha0 + g->flow.alpha_amp * sin(omega * ts), s);
+            if (!rc && g->motion.tab) rc = set_motion_at(g, omega, ts, s);
             rc = rc ? rc : residual_any(g, st == 0 ? q : g->td_qs_d, g->td_r_d, s);
             for (int b = 0; b < g->nblocks && !rc; ++b) {
                 const BlockDesc &B = g->blk[b];
@@ -94,8 +120,9 @@ int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hi
             }
         }
     }
-    // the grid's own snapshot (phase 0) far field again
-    const int rc2 = set_far_field(g, g->flow.alpha0, s);
+    // the grid's own snapshot (phase 0) far field and motion again
+    int rc2 = set_far_field(g, g->flow.alpha0, s);
+    if (!rc2 && g->motion.tab) rc2 = set_motion_at(g, omega, 0.0, s);
     rc = rc ? rc : rc2;
     return rc ? rc : check_hip(hipGetLastError(), "td launch");
 }
