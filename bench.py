@@ -36,8 +36,6 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 METRIC = ("cell-snapshot RK-stage updates/s (FP32+batched vs FP64 plain); "
           "adjoint/primal time")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_traffic.txt")
-SQ_FILE = os.path.join(ROOT, "profiles", "fused_stage_batch32_mixed_sq_counters.txt")
 TUNE_CACHE = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
 KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
 
@@ -61,10 +59,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_profile_value(path, key, tuning):
+def read_profile_value(path, key, tuning, workload):
     """A per-launch figure of the fused stage kernel from a committed counter
-    summary, or None when it is missing or was taken on another kernel
-    source or launch configuration."""
+    summary, or None when it is missing or was taken on another workload,
+    kernel source or launch configuration."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -72,7 +70,7 @@ def read_profile_value(path, key, tuning):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_hash():
+    if kv.get("workload") != workload or kv.get("kernel_source_hash") != kernel_hash():
         return None
     t = "%d,%d,%d,%d" % (tuning["tile_i"], tuning["wg_per_cu"], tuning["xcd_order"],
                          tuning["tile_order"])
@@ -84,9 +82,14 @@ def read_profile_value(path, key, tuning):
         return None
 
 
-def read_traffic(tuning):
+def profile_file(workload, what):
+    """Committed counter summary of the fused stage kernel on a workload."""
+    return os.path.join(ROOT, "profiles", "fused_stage_%s_%s.txt" % (workload, what))
+
+
+def read_traffic(tuning, workload):
     """HBM bytes per fused stage launch (FETCH_SIZE / WRITE_SIZE summary)."""
-    return read_profile_value(TRAFFIC_FILE, "bytes_per_launch", tuning)
+    return read_profile_value(profile_file(workload, "traffic"), "bytes_per_launch", tuning, workload)
 
 
 def algorithmic_bytes_per_iteration(problem) -> float:
@@ -367,8 +370,9 @@ def main():
     stage_s = st_ms / 1000.0 / st_n
     bytes_launch = algorithmic_bytes_per_iteration(problem) / stages
     achieved = bytes_launch / stage_s / 1e9
-    traffic = read_traffic(tuning)
-    valu = read_profile_value(SQ_FILE, "valu_wave_instructions_per_launch", tuning)
+    traffic = read_traffic(tuning, args.workload)
+    valu = read_profile_value(profile_file(args.workload, "sq_counters"),
+                              "valu_wave_instructions_per_launch", tuning, args.workload)
     g.close()
     probe = stream_probe(torch)
 
