@@ -123,3 +123,23 @@ def test_null_handles():
     assert L.hb_get_status(None) == hb.HB_ERR_ARG
     m = hb.c_motion(0.1, 0.0, 0.2, 0.0, 0.0)
     assert L.hb_set_motion(None, ctypes.byref(m)) == hb.HB_ERR_ARG
+
+
+def test_committed_tuning_cache_matches_the_reader_format():
+    """The library reads its tuning cache one entry per line with a fixed
+    field order (hb_tune.cpp); every entry of the committed cache must be in
+    that form, or a lookup silently misses and the autotuner runs again."""
+    import json
+    path = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
+    text = open(path).read()
+    entries = json.loads(text)
+    pat = re.compile(r'^  "([^"]+)": \{"tile_i": (-?\d+), "wg_per_cu": (-?\d+), "xcd_order": (-?\d+), '
+                     r'"tile_order": (-?\d+), "stage_ms": ([0-9.eE+-]+)\},?$')
+    lines = [l for l in text.splitlines() if l not in ("{", "}")]
+    assert len(lines) == len(entries) >= 1
+    for l in lines:
+        m = pat.match(l)
+        assert m, l
+        t = entries[m.group(1)]
+        assert [t["tile_i"], t["wg_per_cu"], t["xcd_order"], t["tile_order"]] == \
+            [int(m.group(k)) for k in range(2, 6)]
