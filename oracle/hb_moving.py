@@ -30,7 +30,7 @@ Reading (the textbook arbitrary Lagrangian-Eulerian finite-volume form):
   * loads: fixed-grid loads on the snapshot's grid, the moment about the
     reference point carried with the body; lift and drag along the mean
     free stream.
-Grids with i-side walls or cuts are outside this reading (ValueError).
+Grids with i-side walls are outside this reading (ValueError).
 
 Parity status: pinned in tests/test_oracle_moving.py (zero motion, heave as
 a Galilean shift, rotation equivariance, free-stream preservation on a
@@ -108,41 +108,82 @@ def face_speeds(xy: torch.Tensor, m: OMotion, thd: float, h: float, hd: float):
 
 
 def check_block(b: O.OBlock):
-    if b.bc[0] in (O.WALL, O.CUT) or b.bc[1] in (O.WALL, O.CUT) or O.CUT in b.bc:
-        raise ValueError("moving grids: walls only on j sides, no cuts")
+    if b.bc[0] == O.WALL or b.bc[1] == O.WALL:
+        raise ValueError("moving grids: walls only on j sides")
+
+
+def wall_images(b: O.OBlock, we: torch.Tensor, xy: torch.Tensor, m: OMotion, thd: float,
+                h: float, hd: float, nbr_xy=None):
+    """Add 2 u_w to the velocity of the no-slip wall images of the extended
+    field we (in place; the fixed-grid rule gave -u).  u_w = grid velocity at
+    the midpoint of the wall face of the mirrored cell's column: a ghost
+    column takes its i-periodic partner column, the glued block's column
+    across an i cut (nbr_xy: side -> that block's moved nodes), else the
+    nearest column of this block."""
+    ni, nj = b.ni, b.nj
+    for side in (2, 3):
+        kind = b.bc[side]
+        if kind not in (O.WALL, O.WAKECUT):
+            continue
+        for ie in range(ni + 4):
+            i = ie - 2
+            if kind == O.WAKECUT and (i < b.wake_ncells or i >= ni - b.wake_ncells):
+                continue                       # wake ghosts are real cells
+            src, col = xy, min(max(i, 0), ni - 1)
+            if 0 <= i < ni:
+                col = i
+            elif b.bc[0 if i < 0 else 1] == O.PERIODIC:
+                col = i % ni
+            elif b.bc[0 if i < 0 else 1] == O.CUT:
+                src = nbr_xy[0 if i < 0 else 1]
+                col = src.shape[-1] - 1 + i if i < 0 else i - ni
+            jw = 0 if side == 2 else src.shape[-2] - 1
+            ux, uy = rigid_velocity(m, thd, h, hd, 0.5 * (src[0, jw, col] + src[0, jw, col + 1]),
+                                    0.5 * (src[1, jw, col] + src[1, jw, col + 1]))
+            for k in (0, 1):
+                row = (-1 - k if side == 2 else nj + k) + 2
+                we[:, 1, row, ie] += 2.0 * ux
+                we[:, 2, row, ie] += 2.0 * uy
+    return we
 
 
 def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Tensor,
                   m: OMotion, thd: float, h: float, hd: float) -> torch.Tensor:
     """Ghost-extended primitives of one snapshot (w[1][4][nj][ni], winf[1][4])
-    on the moved grid xy: the fixed-grid rules (hb_oracle.extend), then the
-    moving-wall images  u_g = 2 u_w - u  (the fixed rule gives -u)."""
+    of a block without cuts on the moved grid xy: the fixed-grid rules
+    (hb_oracle.extend), then the moving-wall images  u_g = 2 u_w - u."""
     check_block(b)
-    we = O.extend(b, w, winf).clone()
-    ni, nj = b.ni, b.nj
-    x, y = xy[0], xy[1]
-    for side in (2, 3):
-        kind = b.bc[side]
-        if kind not in (O.WALL, O.WAKECUT):
-            continue
-        jw = 0 if side == 2 else nj
-        uwx, uwy = rigid_velocity(m, thd, h, hd, 0.5 * (x[jw, :-1] + x[jw, 1:]),
-                                  0.5 * (y[jw, :-1] + y[jw, 1:]))
-        for ie in range(ni + 4):
-            i = ie - 2
-            if kind == O.WAKECUT and (i < b.wake_ncells or i >= ni - b.wake_ncells):
-                continue                       # wake ghosts are real cells
-            if 0 <= i < ni:
-                col = i
-            elif b.bc[0 if i < 0 else 1] == O.PERIODIC:
-                col = i % ni
-            else:
-                col = min(max(i, 0), ni - 1)
-            for k in (0, 1):
-                row = (-1 - k if side == 2 else nj + k) + 2
-                we[:, 1, row, ie] += 2.0 * uwx[col]
-                we[:, 2, row, ie] += 2.0 * uwy[col]
-    return we
+    if O.CUT in b.bc:
+        raise ValueError("moving_extend: a block with cuts needs its neighbours (moving_snapshots)")
+    return wall_images(b, O.extend(b, w, winf).clone(), xy, m, thd, h, hd)
+
+
+def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, cuts=()):
+    """For every block k and snapshot n: (k, n, moved nodes, ghost-extended
+    primitives with moving-wall images, moved centres of the glued blocks,
+    (theta, theta_dot, h, h_dot)).  Cut ghosts are the glued block's cells of
+    the same snapshot (hb_oracle.extend_all); glued blocks share N_s."""
+    P = O.cut_partners(blocks, cuts) if cuts else {}
+    for b in blocks:
+        check_block(b)
+    ws = [O.primitives(qb, flow.gamma) for qb in qs]
+    winfs = [O.freestream_prim(flow, b.ns) for b in blocks]
+    for n in range(max(b.ns for b in blocks)):
+        # a block with fewer snapshots stands in with its last one; no block
+        # glued to it reads that (glued blocks share N_s)
+        sel = [min(n, b.ns - 1) for b in blocks]
+        wes = O.extend_all(blocks, [w[s:s + 1] for w, s in zip(ws, sel)],
+                           [f[s:s + 1] for f, s in zip(winfs, sel)], P)
+        mot = [snapshot_motion(m, flow, b.ns, s) for b, s in zip(blocks, sel)]
+        xys = [torch.stack(place(m, mt[0], mt[2], b.xy[0], b.xy[1])) for b, mt in zip(blocks, mot)]
+        for k, b in enumerate(blocks):
+            if n >= b.ns:
+                continue
+            _, thd, h, hd = mot[k]
+            nbr_xy = {s: xys[P[(k, s)][0]] for s in (0, 1) if (k, s) in P}
+            we = wall_images(b, wes[k].clone(), xys[k], m, thd, h, hd, nbr_xy)
+            nbrC = {s: O.metrics(xys[P[(k, s)][0]])[3] for s in range(4) if (k, s) in P} or None
+            yield k, n, xys[k], we, nbrC, mot[k]
 
 
 def _snapshot(b, w, winf, m, flow, n):
@@ -199,9 +240,16 @@ def moving_td_march(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolv
 
 
 def moving_residual_all(blocks: Sequence[O.OBlock], q: torch.Tensor, flow, solver,
-                        m: OMotion) -> torch.Tensor:
-    return O.join([moving_residual(b, qb, flow, solver, m)
-                   for b, qb in zip(blocks, O.split(blocks, q))])
+                        m: OMotion, cuts=()) -> torch.Tensor:
+    """R* of all blocks on the moving grid; `cuts` glue block sides."""
+    qs = O.split(blocks, q)
+    parts = [[None] * b.ns for b in blocks]
+    for k, n, xy, we, nbrC, (_, thd, h, hd) in moving_snapshots(blocks, qs, flow, m, cuts):
+        vg = face_speeds(xy, m, thd, h, hd)
+        FI, FJ = O.face_fluxes(blocks[k], qs[k][n:n + 1], flow, solver, xy=xy, we=we, vg=vg,
+                               nbrC=nbrC)
+        parts[k][n] = (FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :])
+    return O.join([torch.cat(p) + O.hb_source(b, qb, flow) for p, b, qb in zip(parts, blocks, qs)])
 
 
 def moving_local_dt(b: O.OBlock, q0: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
@@ -229,7 +277,7 @@ def moving_local_dt(b: O.OBlock, q0: torch.Tensor, flow: O.OFlow, solver: O.OSol
     return torch.stack(out)
 
 
-def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter: int):
+def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter: int, cuts=()):
     """hb_oracle.rk_iterate with the moving-grid residual and time step."""
     q = q.clone()
     norms = []
@@ -239,7 +287,7 @@ def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter:
         q0 = O.split(blocks, q)
         dtv = O.join([(moving_local_dt(b, qb, flow, solver, m) / V)[:, None].expand(-1, 4, -1, -1)
                       for b, qb, V in zip(blocks, q0, vols)])
-        resid = lambda x: moving_residual_all(blocks, x, flow, solver, m)
+        resid = lambda x: moving_residual_all(blocks, x, flow, solver, m, cuts)
         q, r0 = O.rk_stages(q, dtv, resid, solver.rk_alpha)
         s = sum(float(((r[:, 0] / V) ** 2).sum()) for r, V in zip(O.split(blocks, r0), vols))
         norms.append(math.sqrt(s / total))
@@ -247,7 +295,7 @@ def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter:
 
 
 def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
-                  m: OMotion) -> List[torch.Tensor]:
+                  m: OMotion, cuts=()) -> List[torch.Tensor]:
     """hb_oracle.forces on the moved grids: per snapshot the wall loads of
     grid n (moving-wall ghosts), the moment about the moved reference point,
     lift and drag along the mean free stream.  [body][ns][3] = (cl, cd, cm)."""
@@ -255,17 +303,14 @@ def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
     qinf = 0.5 * flow.mach ** 2
     nbody = max(b.body_id for b in blocks) + 1
     acc = [None] * nbody
-    for b, qb in zip(blocks, O.split(blocks, q)):
-        w = O.primitives(qb, flow.gamma)
-        winf = O.freestream_prim(flow, b.ns)
-        rows = []
-        for n in range(b.ns):
-            xy, we, (th, _, h, _) = _snapshot(b, w, winf, m, flow, n)
-            xm, ym = place(m, th, h, torch.tensor(flow.x_mom, dtype=DT),
-                           torch.tensor(flow.y_mom, dtype=DT))
-            fn = dataclasses.replace(flow, x_mom=float(xm), y_mom=float(ym))
-            rows.append(O.block_loads(b, qb[n:n + 1], fn, xy=xy, we=we)[0])
-        L = torch.stack(rows)
+    qs = O.split(blocks, q)
+    rows = [[None] * b.ns for b in blocks]
+    for k, n, xy, we, nbrC, (th, _, h, _) in moving_snapshots(blocks, qs, flow, m, cuts):
+        xm, ym = place(m, th, h, torch.tensor(flow.x_mom, dtype=DT), torch.tensor(flow.y_mom, dtype=DT))
+        fn = dataclasses.replace(flow, x_mom=float(xm), y_mom=float(ym))
+        rows[k][n] = O.block_loads(blocks[k], qs[k][n:n + 1], fn, xy=xy, we=we, nbrC=nbrC)[0]
+    for b, r in zip(blocks, rows):
+        L = torch.stack(r)
         acc[b.body_id] = L if acc[b.body_id] is None else acc[b.body_id] + L
     out = []
     for L in acc:
