@@ -294,10 +294,11 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
 /* Set (m non-NULL with a non-zero amplitude) or clear (NULL, or both
  * amplitudes zero) the rigid grid motion described at hb_motion.  It then
  * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march.
- * HB_ERR_UNSUPPORTED for batched grids, for blocks with walls on an i side or
- * with cuts; while a motion is set the adjoints and hb_set_xy return
- * HB_ERR_UNSUPPORTED.  HB_ERR_ARG for non-finite values.  Synchronises the
- * current device. */
+ * HB_ERR_UNSUPPORTED for batched grids and for blocks with walls on an i
+ * side; while a motion is set the adjoints and hb_set_xy return
+ * HB_ERR_UNSUPPORTED.  Across a cut, the wall image of a corner ghost takes
+ * the glued block's wall face.  HB_ERR_ARG for non-finite values.
+ * Synchronises the current device. */
 int hb_set_motion(hb_grid *g, const hb_motion *m);
 
 /* Synchronise and return HB_ERR_NONFINITE if any iteration since the last

@@ -591,9 +591,8 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
     }
     if (g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "a moving grid needs batched = 0");
     for (const BlockDesc &B : g->blk)
-        for (int side = 0; side < 4; ++side)
-            if (B.bc[side] == HB_BC_CUT || (side < 2 && B.bc[side] == HB_BC_WALL))
-                return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides, no cuts");
+        if (B.bc[0] == HB_BC_WALL || B.bc[1] == HB_BC_WALL)
+            return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides");
     if (!g->mot_d) {
         rc = dalloc(&g->mot_d, (int64_t)kMotionW * g->n_snap);
         if (rc) return rc;

@@ -5,6 +5,7 @@
 // adds the blocks of each body in block order and rotates to wind axes.
 // No atomics: results are bitwise reproducible.
 #include "hb_device.hpp"
+#include "hb_motion.hpp"
 
 namespace hb {
 namespace {
@@ -54,7 +55,7 @@ __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, con
     // (i', j') resolved like every ghost, moving-wall images with a motion set
     auto val = [&](int ii, int jj) {
         W4<double> w = value_ij<W4<double>>(blks, b, ii, jj, cell, ff, MirrorFull<double>());
-        if (mo.tab) wall_image_motion(B, ii, jj, ms, mo, xy, w);
+        if (mo.tab) wall_image_motion(blks, b, ii, jj, ms, mo, xy, w);
         return w;
     };
     const W4<double> wR = val(i, 0);

@@ -4,6 +4,7 @@
 // the fused batched kernel is measured against, and a second, independently
 // structured GPU evaluation of the same residual.
 #include "hb_device.hpp"
+#include "hb_motion.hpp"
 #include "hb_xcd.hpp"
 
 namespace hb {
@@ -53,7 +54,7 @@ __global__ void k_ghost(const BlockDesc *blks, int b, const double *q, const dou
     CellFromState cell{blks, q, n, gm1};
     FreeStream ff{blks, ffw, n};
     W4<double> w = value_ij<W4<double>>(blks, b, i, j, cell, ff, MirrorFull<double>());
-    if (mo.tab) wall_image_motion(B, i, j, motion_snap(mo, B, n), mo, xy, w);
+    if (mo.tab) wall_image_motion(blks, b, i, j, motion_snap(mo, B, n), mo, xy, w);
     double *e = ext + B.ext_off + (int64_t)n * 4 * plane + r;
     e[0] = w.r;
     e[plane] = w.u;
