@@ -85,7 +85,8 @@ typedef struct {
  * block blk_a to the whole side side_b of block blk_b: the ghosts of each
  * side are the other block's interior cells (Jacobi: both read the same
  * stage input).  Supported: imax<->imin with equal nj and jmax<->jmin with
- * equal ni, both with `reversed` = 0. */
+ * equal ni, both with `reversed` = 0 (other pairings, unequal lengths and
+ * reversed cuts: HB_ERR_UNSUPPORTED). */
 typedef struct {
     int32_t blk_a, side_a, blk_b, side_b, reversed;
 } hb_cut;

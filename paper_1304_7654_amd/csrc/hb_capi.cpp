@@ -259,8 +259,9 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     for (int c = 0; c < ncuts; ++c) {
         hb_cut k = cuts[c];
         if (k.blk_a < 0 || k.blk_a >= nblocks || k.blk_b < 0 || k.blk_b >= nblocks ||
-            k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3 || k.reversed != 0)
+            k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3)
             return fail(HB_ERR_ARG, "bad cut");
+        if (k.reversed != 0) return fail(HB_ERR_UNSUPPORTED, "reversed cuts are not supported");
         if (k.side_a % 2 == 0) {   // normalise to (max side of a) <-> (min side of b)
             std::swap(k.blk_a, k.blk_b);
             std::swap(k.side_a, k.side_b);

@@ -105,6 +105,11 @@ def test_validation_rejects_before_device_work():
     cut = synth.Block(b.ni, b.nj, 1, b.xy, (3, 3, synth.CUT, 2))
     assert _try([cut]) == hb.HB_ERR_ARG                      # CUT side without a cut
     assert "n_harm" in hb.lib().hb_last_error().decode() or True
+    sp, _ = synth.split_problem(p, 2, 1)
+    rev = [tuple(c[:4]) + (1,) for c in sp.cuts]
+    with pytest.raises(hb.HBError) as e:
+        hb.Grid(sp.blocks, sp.flow, sp.solver, rev)
+    assert e.value.code == hb.HB_ERR_UNSUPPORTED                # reversed cut
 
 
 def test_binding_rejects_bad_tensors():
