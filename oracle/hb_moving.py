@@ -22,7 +22,8 @@ Reading (the textbook arbitrary Lagrangian-Eulerian finite-volume form):
   * no-slip walls move: a wall ghost mirrors the velocity about the wall
     velocity, u_g = 2 u_w - u, u_w = x_t at the midpoint of the wall face
     of the mirrored cell's column (for corner ghosts: the i-periodic partner
-    column, else the nearest column);
+    column, the glued block's column across an i cut, else the nearest
+    column); cut ghosts are the glued block's cells of the same snapshot;
   * far field: the free stream at the (fixed) incidence alpha0 (plus any
     alpha_amp forcing, unchanged);
   * local time step: the fixed-grid formula on the snapshot's grid with the
@@ -35,8 +36,9 @@ Grids with i-side walls are outside this reading (ValueError).
 Parity status: pinned in tests/test_oracle_moving.py (zero motion, heave as
 a Galilean shift, rotation equivariance, free-stream preservation on a
 pitching and heaving grid, grid velocity against differenced positions,
-no-slip wall images, converged N_H = 1 snapshots against the moving-grid
-time-domain march).
+no-slip wall images, a block cut into glued pieces, the time-domain march at
+zero motion).  Converged N_H = 1 snapshots against the moving-grid
+time-domain march are compared on the GPU (tests/test_gpu_moving.py).
 """
 from __future__ import annotations
 
