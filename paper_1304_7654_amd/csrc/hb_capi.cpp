@@ -56,6 +56,14 @@ void free_all(hb_grid *g) {
     g->graph_exec = nullptr;
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
+    for (int k = 0; k < hb_grid::kSide; ++k) {
+        if (g->side[k]) (void)hipStreamDestroy(g->side[k]);
+        if (g->join_ev[k]) (void)hipEventDestroy(g->join_ev[k]);
+        g->side[k] = nullptr;
+        g->join_ev[k] = nullptr;
+    }
+    if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
+    g->fork_ev = nullptr;
     dfree(g->blk_d);
     dfree(g->xy_d);
     dfree(g->SI_d); dfree(g->dI_d); dfree(g->SJ_d); dfree(g->dJ_d);

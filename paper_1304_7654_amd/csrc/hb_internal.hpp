@@ -152,6 +152,11 @@ struct hb_grid {
     int tune_order = 0;          // 0: tiles row by row (j outer), 1: column by column
     double tune_ms = 0.0;        // measured stage time of the applied tuning (0 = not measured)
     hipStream_t cap_stream = nullptr;
+    // plain path: the blocks of a stage run on side streams forked from
+    // and joined back to the caller's stream (default priority)
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
     hipGraphExec_t graph_exec = nullptr;
     double *graph_q = nullptr, *graph_norm = nullptr;
     int graph_iters = 0;

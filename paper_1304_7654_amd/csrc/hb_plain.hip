@@ -264,24 +264,55 @@ Metrics<double> fp64_metrics(hb_grid *g) {
     return Metrics<double>{g->SI_d, g->dI_d, g->SJ_d, g->dJ_d, g->V_d};
 }
 
+// Side streams and their events, created on first use.
+int side_streams(hb_grid *g) {
+    if (g->fork_ev) return HB_OK;
+    for (int k = 0; k < hb_grid::kSide; ++k) {
+        int rc = check_hip(hipStreamCreateWithFlags(&g->side[k], hipStreamNonBlocking), "side stream");
+        rc = rc ? rc : check_hip(hipEventCreateWithFlags(&g->join_ev[k], hipEventDisableTiming), "event");
+        if (rc) return rc;
+    }
+    return check_hip(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming), "event");
+}
+
+// One stage over all blocks.  A block's four kernels only write its own
+// regions of the ghost-extended field, the face fluxes and `out`, and read
+// the stage input `qin` (also the glued blocks' cells) and `q0`, which no
+// kernel of the stage writes (`out` may be `q0` itself, read and written
+// pointwise by the block's own update).  So the blocks run on side streams
+// (block b on stream b mod kSide), forked from and joined back to `s`.
 int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode, double alpha,
           int norm, hipStream_t s) {
     const Consts c = g->consts;
+    const bool fork = g->nblocks > 1;
+    if (fork) {
+        int rc = side_streams(g);
+        rc = rc ? rc : check_hip(hipEventRecord(g->fork_ev, s), "fork");
+        for (int k = 0; k < hb_grid::kSide && !rc; ++k)
+            rc = check_hip(hipStreamWaitEvent(g->side[k], g->fork_ev, 0), "fork");
+        if (rc) return rc;
+    }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
+        hipStream_t st = fork ? g->side[b % hb_grid::kSide] : s;
         const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
-        hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, s, g->blk_d, b, qin, g->ffw_d,
+        hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, st, g->blk_d, b, qin, g->ffw_d,
                            c.gamma - 1.0, g->ext_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_i, dim3(xcd_grid((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_i, dim3(xcd_grid((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, st,
                            g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_j, dim3(xcd_grid((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, s,
+        hipLaunchKernelGGL(k_flux_j, dim3(xcd_grid((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, st,
                            g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d, g->motion, g->xy_d);
         hipLaunchKernelGGL(k_update, dim3(xcd_grid((int64_t)nblk((int64_t)B.ni * B.nj) * B.ns * kBS)),
-                           dim3(kBS), 0, s, g->blk_d, b,
+                           dim3(kBS), 0, st, g->blk_d, b,
                            g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
                            alpha, norm, g->partials_d, g->status_d, c, g->motion, g->C_d);
     }
-    return check_hip(hipGetLastError(), "plain stage launch");
+    int rc = check_hip(hipGetLastError(), "plain stage launch");
+    for (int k = 0; fork && k < hb_grid::kSide && !rc; ++k) {
+        rc = check_hip(hipEventRecord(g->join_ev[k], g->side[k]), "join");
+        rc = rc ? rc : check_hip(hipStreamWaitEvent(s, g->join_ev[k], 0), "join");
+    }
+    return rc;
 }
 
 }  // namespace
