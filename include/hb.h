@@ -163,8 +163,8 @@ typedef struct {
  * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
  * [0, ni/2] and only with a WAKECUT jmin, cut sides consistent, bodies
  * numbered without gaps with one n_harm each, every cell area > 0.
- * At most 2^24 cells per block; a batched grid's state must stay below 2 GiB
- * (HB_ERR_UNSUPPORTED otherwise).  Synchronises the current device.  *out is
+ * At most 2^24 cells per block (HB_ERR_ARG otherwise); a batched grid's state
+ * must stay below 2 GiB (HB_ERR_UNSUPPORTED otherwise).  Synchronises the current device.  *out is
  * NULL on failure. */
 int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts,
                    int32_t ncuts, const hb_flow *flow, const hb_solver *solver,

@@ -148,3 +148,20 @@ def test_committed_tuning_cache_matches_the_reader_format():
         t = entries[m.group(1)]
         assert [t["tile_i"], t["wg_per_cu"], t["xcd_order"], t["tile_order"]] == \
             [int(m.group(k)) for k in range(2, 6)]
+
+
+def test_size_limits_rejected_before_device_work():
+    """More than 2^24 cells in a block is a bad argument; a batched grid whose
+    state reaches 2 GiB is unsupported (the batched kernel addresses the state
+    with 32-bit byte offsets).  Both are refused on the host."""
+    p = synth.make_problem("cyl_tiny")
+    n = 4097                                   # n * n > 2^24; the nodes are never read
+    big = synth.Block(n, n, 0, np.zeros((2, n + 1, n + 1)), (synth.PERIODIC, synth.PERIODIC,
+                                                              synth.WALL, synth.FARFIELD))
+    assert _try([big]) == hb.HB_ERR_ARG
+    ni, nj = 4096, 2048                        # N_H = 4: 2.4 GB of state
+    blk = synth.Block(ni, nj, 4, synth.o_grid(ni, nj), (synth.PERIODIC, synth.PERIODIC,
+                                                       synth.WALL, synth.FARFIELD))
+    with pytest.raises(hb.HBError) as e:
+        hb.Grid([blk], p.flow, p.solver, precision=1, batched=1)
+    assert e.value.code == hb.HB_ERR_UNSUPPORTED
