@@ -154,7 +154,7 @@ struct hb_grid {
     hipStream_t cap_stream = nullptr;
     // plain path: the blocks of a stage run on side streams forked from
     // and joined back to the caller's stream (default priority)
-    static constexpr int kSide = 4;
+    static constexpr int kSide = 8;
     hipStream_t side[kSide] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
     hipGraphExec_t graph_exec = nullptr;

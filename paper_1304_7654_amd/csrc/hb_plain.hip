@@ -280,7 +280,8 @@ int side_streams(hb_grid *g) {
 // the stage input `qin` (also the glued blocks' cells) and `q0`, which no
 // kernel of the stage writes (`out` may be `q0` itself, read and written
 // pointwise by the block's own update).  So the blocks run on side streams
-// (block b on stream b mod kSide), forked from and joined back to `s`.
+// (block b on stream b mod kSide; 8 measured faster than 4, 12 or 16 on a
+// 32-block batch), forked from and joined back to `s`.
 int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode, double alpha,
           int norm, hipStream_t s) {
     const Consts c = g->consts;
