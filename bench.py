@@ -111,8 +111,8 @@ MOTION = dict(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_piv
 def plain_stage_bytes(problem, moving) -> float:
     """Bytes one stage of the plain FP64 path (every intermediate in HBM)
     must move: the ghost fill reads Q and writes the ghost-extended
-    primitives E; the i- and j-face kernels each read E and their face
-    metrics (S, d) and write the face fluxes; the update reads both flux
+    primitives E; each face family (one kernel for both) reads E and its face
+    metrics (S, d) and writes its face fluxes; the update reads both flux
     arrays, the stage input, the base state, the face normals and the cell
     area, and writes the new state.  A moving grid adds the node coordinates
     (both face kernels) and the cell centres (update).  FP64 words."""
@@ -156,7 +156,7 @@ def plain_leg(torch, hb, problem, q0, steps, motion=None):
     return {"value": cs * stages * steps / t, "ms_per_step": 1000.0 * t / steps,
             "roofline": {"bound": "hbm", "achieved": nbytes / stage_s / 1e9, "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": nbytes / stage_s / 1e9 / PEAK_HBM_GBS,
-                         "kernels": "per block: k_ghost, k_flux_i, k_flux_j, k_update",
+                         "kernels": "per block: k_ghost, k_flux (i- and j-faces), k_update",
                          "avg_stage_ms": 1000.0 * stage_s, "algorithmic_bytes_per_stage": nbytes}}
 
 

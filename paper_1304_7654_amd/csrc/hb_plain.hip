@@ -1,6 +1,6 @@
 // Plain FP64 path: one block per launch, separate kernels for ghost
-// synthesis, i-face fluxes, j-face fluxes and the cell update.  Every
-// intermediate goes through HBM.  It is the straightforward baseline that
+// synthesis, face fluxes (both families in one launch) and the cell
+// update.  Every intermediate goes through HBM.  It is the straightforward baseline that
 // the fused batched kernel is measured against, and a second, independently
 // structured GPU evaluation of the same residual.
 #include "hb_device.hpp"
@@ -81,13 +81,12 @@ __device__ inline double moving_face(const Motion &mo, const BlockDesc &B, int n
     return gx * sx + gy * sy;
 }
 
-__global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
-                         const double *dI, Consts c, double *FI, Motion mo, const double *xy) {
+__device__ __forceinline__ void flux_i(const BlockDesc *blks, int b, const double *ext,
+                                       const double *SI, const double *dI, Consts c, double *FI,
+                                       Motion mo, const double *xy, int64_t t) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
-    const int64_t lw = xcd_group(nf * B.ns);
-    const int64_t t = lw < 0 ? -1 : lw * kBS + threadIdx.x;
     if (t < 0 || t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
@@ -123,12 +122,11 @@ __global__ void k_flux_i(const BlockDesc *blks, int b, const double *ext, const 
     o[3 * nf] = fl[3] - fv[2];
 }
 
-__global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
-                         const double *dJ, Consts c, double *FJ, Motion mo, const double *xy) {
+__device__ __forceinline__ void flux_j(const BlockDesc *blks, int b, const double *ext,
+                                       const double *SJ, const double *dJ, Consts c, double *FJ,
+                                       Motion mo, const double *xy, int64_t t) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
-    const int64_t lw = xcd_group(nf * B.ns);
-    const int64_t t = lw < 0 ? -1 : lw * kBS + threadIdx.x;
     if (t < 0 || t >= nf * B.ns) return;
     const int n = (int)(t / nf);
     const int64_t f = t % nf;
@@ -167,6 +165,19 @@ __global__ void k_flux_j(const BlockDesc *blks, int b, const double *ext, const 
     o[nf] = fl[1] - fv[0];
     o[2 * nf] = fl[2] - fv[1];
     o[3 * nf] = fl[3] - fv[2];
+}
+
+// Both face families of block b in one launch: items [0, nI) are the
+// i-faces of all snapshots, the rest the j-faces.
+__global__ void __launch_bounds__(kBS) k_flux(const BlockDesc *blks, int b, const double *ext,
+                                              const double *SI, const double *dI, const double *SJ,
+                                              const double *dJ, Consts c, double *FI, double *FJ,
+                                              Motion mo, const double *xy, int64_t nI, int64_t nJ) {
+    const int64_t lw = xcd_group(nI + nJ);
+    if (lw < 0) return;
+    const int64_t t = lw * kBS + threadIdx.x;
+    if (t < nI) flux_i(blks, b, ext, SI, dI, c, FI, mo, xy, t);
+    else flux_j(blks, b, ext, SJ, dJ, c, FJ, mo, xy, t - nI);
 }
 
 // Cell update, one thread per cell and snapshot.  mode 0: out = R*(qin).
@@ -299,10 +310,10 @@ int stage(hb_grid *g, const double *qin, const double *q0, double *out, int mode
         const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
         hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, st, g->blk_d, b, qin, g->ffw_d,
                            c.gamma - 1.0, g->ext_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_i, dim3(xcd_grid((int64_t)(B.ni + 1) * B.nj * B.ns)), dim3(kBS), 0, st,
-                           g->blk_d, b, g->ext_d, g->SI_d, g->dI_d, c, g->FI_d, g->motion, g->xy_d);
-        hipLaunchKernelGGL(k_flux_j, dim3(xcd_grid((int64_t)B.ni * (B.nj + 1) * B.ns)), dim3(kBS), 0, st,
-                           g->blk_d, b, g->ext_d, g->SJ_d, g->dJ_d, c, g->FJ_d, g->motion, g->xy_d);
+        const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
+        hipLaunchKernelGGL(k_flux, dim3(xcd_grid(nI + nJ)), dim3(kBS), 0, st, g->blk_d, b, g->ext_d,
+                           g->SI_d, g->dI_d, g->SJ_d, g->dJ_d, c, g->FI_d, g->FJ_d, g->motion, g->xy_d,
+                           nI, nJ);
         hipLaunchKernelGGL(k_update, dim3(xcd_grid((int64_t)nblk((int64_t)B.ni * B.nj) * B.ns * kBS)),
                            dim3(kBS), 0, st, g->blk_d, b,
                            g->FI_d, g->FJ_d, g->SI_d, g->SJ_d, g->V_d, g->D_d, qin, q0, out, mode,
