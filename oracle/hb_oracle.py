@@ -722,17 +722,27 @@ def rk_iterate(blocks, q: torch.Tensor, flow, solver, n_iter: int, cuts=()):
 
 
 def td_march(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver, dt: float,
-             n_steps: int, t0: float = 0.0):
+             n_steps: int, t0: float = 0.0, alpha_amps: Optional[Sequence[float]] = None):
     """Time-domain reference: classical fourth-order Runge-Kutta in physical
     time on V dQ/dt = -R(Q, t) (no HB term), with the far field at the
     instantaneous incidence alpha(t) = alpha0 + A sin(omega t).  q is a
-    single-snapshot state [1][4][nj][ni].  Returns the state at t0 + n dt."""
+    single-snapshot state [1][4][nj][ni].  Returns the state at t0 + n dt.
+
+    Independent marches of the same block may share the call: q[r] is then
+    the state of march r, forced with amplitude alpha_amps[r] (the rows do
+    not interact: the spatial operator treats each row on its own)."""
     V = metrics(b.xy)[2]
+    amps = [flow.alpha_amp] * q.shape[0] if alpha_amps is None else list(alpha_amps)
+    if len(amps) != q.shape[0]:
+        raise ValueError("one forcing amplitude per state row")
 
     def f(x, t):
-        a = flow.alpha0 + flow.alpha_amp * math.sin(flow.omega * t)
-        winf = torch.tensor([[1.0, flow.mach * math.cos(a), flow.mach * math.sin(a),
-                              1.0 / flow.gamma]], dtype=DT)
+        rows = []
+        for A in amps:
+            a = flow.alpha0 + A * math.sin(flow.omega * t)
+            rows.append([1.0, flow.mach * math.cos(a), flow.mach * math.sin(a),
+                         1.0 / flow.gamma])
+        winf = torch.tensor(rows, dtype=DT)
         return -spatial_residual(b, x, flow, solver, winf=winf) / V
 
     t = t0

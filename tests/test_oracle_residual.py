@@ -260,6 +260,94 @@ def test_forces_signs():
     assert cl > 0 and cm > 0
 
 
+def _cartesian_block(xs, ys, n_harm=0):
+    """Cartesian block with nodes (xs[i], ys[j]): the jmin side is the wall
+    y = ys[0], i runs along +x and j along +y (right-handed)."""
+    X, Y = torch.meshgrid(torch.as_tensor(ys, dtype=DT), torch.as_tensor(xs, dtype=DT),
+                          indexing="ij")
+    return torch.stack([Y, X])
+
+
+def test_forces_couette_wall_shear():
+    """Linear shear over a no-slip wall (u = a y, v = b y, uniform rho and
+    p = p_inf) on a stretched Cartesian block: the mirrored wall ghost
+    continues the linear field exactly, so the wall-face diamond gradient is
+    exact and the wall stress is the continuum one, tau_xy = mu a and
+    tau_yy = (4/3) mu b (Stokes hypothesis).  Both the residual's wall-face
+    viscous flux and the loads must reproduce it to round-off: the force
+    (mu a L, (4/3) mu b L), and the moment about an off-wall point from the
+    exact integral of the face-midpoint arm."""
+    xs = torch.tensor([0.0, 0.1, 0.25, 0.45, 0.7, 1.0, 1.4, 1.9, 2.5], dtype=DT) + 0.3
+    ys = torch.tensor([0.0, 0.05, 0.12, 0.22, 0.36, 0.55, 0.8], dtype=DT)
+    xy = _cartesian_block(xs, ys)
+    ni, nj = len(xs) - 1, len(ys) - 1
+    b = O.OBlock(ni, nj, 0, xy, (PER, PER, WALL, FF))
+    a, bb = 0.37, -0.21
+    x0, y0, a0 = 0.8, 0.45, 0.1
+    flow = O.OFlow(mach=0.4, reynolds=80.0, alpha0=a0, x_mom=x0, y_mom=y0)
+    C = O.metrics(xy)[3]
+    w = torch.zeros(1, 4, nj, ni, dtype=DT)
+    w[:, 0] = 1.0
+    w[:, 1] = a * C[..., 1]
+    w[:, 2] = bb * C[..., 1]
+    w[:, 3] = 1 / 1.4
+    q = _cons(w)
+    mu, L = flow.mu, float(xs[-1] - xs[0])
+    # residual path: the viscous part of the wall-face flux is the difference
+    # of the fluxes at this Reynolds number and at a vanishing viscosity
+    inviscid = O.OFlow(mach=0.4, reynolds=1e300, alpha0=a0)
+    FJ = O.face_fluxes(b, q, flow, O.OSolver())[1]
+    FJ0 = O.face_fluxes(b, q, inviscid, O.OSolver())[1]
+    G = FJ0[0, :, 0, :] - FJ[0, :, 0, :]                 # [4][ni] wall faces
+    dx = xs[1:] - xs[:-1]
+    assert torch.allclose(G[0], torch.zeros_like(dx), atol=0)
+    assert torch.allclose(G[1], mu * a * dx, rtol=1e-13, atol=0)
+    assert torch.allclose(G[2], 4.0 / 3.0 * mu * bb * dx, rtol=1e-13, atol=0)
+    assert G[3].abs().max() < 1e-16                       # no-slip: no work, adiabatic
+    # loads: force and moment about (x0, y0), counter-clockwise positive
+    fx, fy, mz = O.block_loads(b, q, flow)[0]
+    Fx, Fy = mu * a * L, 4.0 / 3.0 * mu * bb * L
+    xe, xb = float(xs[-1]), float(xs[0])
+    Mz = Fy * ((xe * xe - xb * xb) / (2 * L) - x0) + y0 * Fx
+    assert abs(fx - Fx) <= 1e-13 * abs(Fx)
+    assert abs(fy - Fy) <= 1e-13 * abs(Fy)
+    assert abs(mz - Mz) <= 1e-13 * abs(Mz)
+    # coefficients in the mean free-stream axes, nose-up moment
+    cl, cd, cm = O.forces([b], q.reshape(-1), flow, O.OSolver())[0][0]
+    qinf = 0.5 * 0.4 ** 2
+    assert abs(cd - (Fx * math.cos(a0) + Fy * math.sin(a0)) / qinf) <= 1e-13
+    assert abs(cl - (-Fx * math.sin(a0) + Fy * math.cos(a0)) / qinf) <= 1e-13
+    assert abs(cm + Mz / qinf) <= 1e-13
+
+
+def test_forces_pressure_moment_closed_form():
+    """Pressure loads on the regular-polygon body of the O-grid.  With the
+    first-layer pressure p_inf + e cos(theta) + h sin(theta) at each cell's
+    polar angle (the wall pressure is that of the adjacent cell, and the
+    first-layer centres sit on the bisectors of the wall faces), the wall
+    forces are radial and sum in closed form to
+    -ni sin(pi/ni) (e, h); the moment about (x0, y0) is then
+    -x0 Fy + y0 Fx, because a radial force has no moment about the centre."""
+    ni, nj = 48, 6
+    b = O.OBlock(ni, nj, 0, torch.as_tensor(synth.o_grid(ni, nj)), (PER, PER, WALL, FF))
+    e, h, x0, y0 = 0.013, -0.007, 0.31, -0.22
+    flow = O.OFlow(mach=0.4, reynolds=100.0, x_mom=x0, y_mom=y0)
+    C = O.metrics(b.xy)[3]
+    th = torch.atan2(C[..., 1], C[..., 0])
+    w = torch.zeros(1, 4, nj, ni, dtype=DT)
+    w[:, 0] = 1.0
+    w[:, 3] = 1 / 1.4
+    w[:, 3, 0] += e * torch.cos(th[0]) + h * torch.sin(th[0])   # first layer only
+    fx, fy, mz = O.block_loads(b, _cons(w), flow)[0]
+    s = ni * math.sin(math.pi / ni)
+    Fx, Fy = -s * e, -s * h
+    assert abs(fx - Fx) <= 1e-14 and abs(fy - Fy) <= 1e-14
+    assert abs(mz - (-x0 * Fy + y0 * Fx)) <= 1e-14
+    # the same loads with the moment taken about the centre vanish
+    flow0 = O.OFlow(mach=0.4, reynolds=100.0)
+    assert abs(O.block_loads(b, _cons(w), flow0)[0][2]) <= 1e-15
+
+
 def test_rk_iteration_reduces_residual():
     """The pseudo-time iteration with the local time step is stable at CFL
     1.5 on the cylinder workload: the residual norm decreases."""
@@ -270,7 +358,7 @@ def test_rk_iteration_reduces_residual():
     assert torch.isfinite(norms).all() and norms[-1] < 0.5 * norms[0]
 
 
-def _hb_converge(b, flow, q, tol, max_iter=6000):
+def _hb_converge(b, flow, q, tol, max_iter=8000):
     solver = O.OSolver()
     done = 0
     while done < max_iter:
@@ -281,40 +369,71 @@ def _hb_converge(b, flow, q, tol, max_iter=6000):
     raise AssertionError("HB iteration did not converge: %g" % nrm[-1])
 
 
+def _td_periodic(b, flow, q0, amps, steps, samples, tol, max_periods=60):
+    """Time-domain reference marched period by period from q0 (one row per
+    forcing amplitude) until the state at phase 0 changes by less than tol
+    over a period; returns the last period sampled at phases k/samples,
+    [samples][rows][4][nj][ni]."""
+    T = 2 * math.pi / flow.omega
+    dt, per = T / steps, steps // samples
+    q, t = q0.clone(), 0.0
+    for _ in range(max_periods):
+        start, snaps = q.clone(), []
+        for _ in range(samples):
+            snaps.append(q.clone())
+            q = O.td_march(b, q, flow, O.OSolver(), dt, per, t, alpha_amps=amps)
+            t += dt * per
+        if (q - start).abs().max().item() < tol:
+            return torch.stack(snaps)
+    raise AssertionError("time-domain march not periodic after %d periods" % max_periods)
+
+
 @pytest.mark.slow
 def test_hb_matches_time_domain_march():
-    """Check (e): on a tiny N_H = 1 case (16x8 O-grid, Re 20 so the mean flow
-    is steady, M 0.3, incidence oscillating with amplitude A), the converged
-    HB snapshots agree with a fourth-order time-domain march sampled at the
-    same phases.  The disagreement is the nonlinear second-harmonic content
-    that N_H = 1 truncates, so it is a small fraction of the unsteady
-    response and shrinks like A^2 (about four-fold when A halves)."""
+    """Check (e): on a tiny case (16x8 O-grid, Re 20 so that the mean flow is
+    steady, M 0.3, incidence oscillating with amplitude A) the converged HB
+    snapshots agree with a fourth-order time-domain march, marched until it
+    is periodic (period-to-period change below 1e-12) and sampled at the
+    same phases.  The HB solution with N_H harmonics misses the response's
+    harmonics above N_H, whose size in a weakly nonlinear response is of
+    order A^(N_H+1): so the difference is a small fraction of the unsteady
+    response at N_H = 1, falls by more than an order of magnitude per added
+    harmonic, and shrinks about 2^(N_H+1)-fold when A halves (4, 8 and 16
+    for N_H = 1, 2, 3)."""
     ni, nj = 16, 8
     xy = torch.as_tensor(synth.o_grid(ni, nj, r_out=6.0))
     bc = (PER, PER, WALL, FF)
-    steady_b = O.OBlock(ni, nj, 0, xy, bc)
     flow0 = O.OFlow(mach=0.3, reynolds=20.0, k_red=1.0)
     w = torch.zeros(1, 4, nj, ni, dtype=DT)
     w[:, 0], w[:, 1], w[:, 3] = 1.0, 0.3, 1 / 1.4
-    qs = _hb_converge(steady_b, flow0, _cons(w).reshape(-1), 1e-11)
-    errs, amps = [], []
-    for A in (1e-3, 5e-4):
-        b = O.OBlock(ni, nj, 1, xy, bc)
+    qs = _hb_converge(O.OBlock(ni, nj, 0, xy, bc), flow0, _cons(w).reshape(-1), 1e-11)
+    qs = qs.reshape(1, 4, nj, ni)
+    amps_a = (1e-3, 5e-4)
+    # global step: half the smallest local step at CFL 1 (no HB term), and a
+    # whole number of steps between the phases of 3, 5 and 7 snapshots
+    T = 2 * math.pi / flow0.omega
+    dtmin = 0.5 * float(O.local_dt(O.OBlock(ni, nj, 0, xy, bc), qs, flow0,
+                                   O.OSolver(cfl=1.0)).min())
+    steps = 105 * int(math.ceil(T / dtmin / 105))
+    td = _td_periodic(O.OBlock(ni, nj, 0, xy, bc), flow0, qs.repeat(2, 1, 1, 1), amps_a,
+                      steps, 105, 1e-12)
+    err = {}
+    for r, A in enumerate(amps_a):
         flow = O.OFlow(mach=0.3, reynolds=20.0, alpha_amp=A, k_red=1.0)
-        q = _hb_converge(b, flow, qs.reshape(1, -1).repeat(3, 1).reshape(-1), 1e-12)
-        qh = q.reshape(3, 4, nj, ni)
-        T = 2 * math.pi / flow.omega
-        dtmin = 0.5 * float(O.local_dt(b, qh, flow, O.OSolver(cfl=1.0)).min())
-        nsteps = int(math.ceil(T / 3 / dtmin))
-        qt, t = qh[0:1].clone(), 0.0
-        for _ in range(2):                      # transient, then one compared period
-            snaps = []
-            for k in range(3):
-                qt = O.td_march(b, qt, flow, O.OSolver(), T / 3 / nsteps, nsteps, t)
-                t += T / 3
-                snaps.append(qt[0])
-        td = torch.stack([snaps[2], snaps[0], snaps[1]])     # phases 0, 1/3, 2/3
-        errs.append((td - qh).abs().max().item())
-        amps.append((qh - qh.mean(0, keepdim=True)).abs().max().item())
-    assert errs[0] < 0.05 * amps[0] and errs[1] < 0.05 * amps[1], (errs, amps)
-    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+        for nh in (1, 2, 3):
+            ns = 2 * nh + 1
+            b = O.OBlock(ni, nj, nh, xy, bc)
+            q = _hb_converge(b, flow, qs.reshape(1, -1).repeat(ns, 1).reshape(-1), 1e-12)
+            qh = q.reshape(ns, 4, nj, ni)
+            ref = td[[n * 105 // ns for n in range(ns)], r]
+            err[(A, nh)] = (ref - qh).abs().max().item()
+            if nh == 1:
+                amp = (qh - qh.mean(0, keepdim=True)).abs().max().item()
+                assert err[(A, 1)] < 0.05 * amp, (A, err, amp)
+    for A in amps_a:
+        assert err[(A, 2)] < err[(A, 1)] / 10, err
+        assert err[(A, 3)] < err[(A, 2)] / 5, err
+    a, b_ = amps_a
+    assert 3.0 < err[(a, 1)] / err[(b_, 1)] < 5.0, err
+    assert 6.0 < err[(a, 2)] / err[(b_, 2)] < 10.0, err
+    assert 11.0 < err[(a, 3)] / err[(b_, 3)] < 22.0, err
