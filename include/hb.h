@@ -81,14 +81,26 @@ typedef struct {
     int32_t body_id;
 } hb_block;
 
-/* A cut glues the whole side `side_a` (0..3 = imin, imax, jmin, jmax) of
- * block blk_a to the whole side side_b of block blk_b: the ghosts of each
- * side are the other block's interior cells (Jacobi: both read the same
- * stage input).  Supported: imax<->imin with equal nj and jmax<->jmin with
- * equal ni, both with `reversed` = 0 (other pairings, unequal lengths and
- * reversed cuts: HB_ERR_UNSUPPORTED). */
+/* A cut (the paper's "cuts": block edges whose data are exchanged with the
+ * neighbouring block every Runge-Kutta step; the paragraph on the MPI
+ * parallelisation that follows the Introduction, and the cut pseudo code of
+ * §MPI Optimisations, which loops over a cut's boundary length) glues `len`
+ * cells of side `side_a` (0..3 = imin, imax, jmin, jmax) of block blk_a,
+ * starting at cell start_a along that side, to `len` cells of side side_b
+ * of block blk_b starting at start_b (in the opposite direction along
+ * side_b when `reversed` is non-zero).  The ghosts of each glued cell are
+ * the other block's interior cells (Jacobi: both read the same stage input).
+ *
+ * This build glues whole sides only: start_a = start_b = 0, len = the
+ * length of both sides (nj for an i side, ni for a j side), imax<->imin or
+ * jmax<->jmin, reversed = 0, equal n_harm.  A segment (partial side), a
+ * reversed cut or another pairing of sides returns HB_ERR_UNSUPPORTED;
+ * indices outside the blocks, len < 1 or a segment running past the end of
+ * a side return HB_ERR_ARG. */
 typedef struct {
-    int32_t blk_a, side_a, blk_b, side_b, reversed;
+    int32_t blk_a, side_a, start_a;
+    int32_t blk_b, side_b, start_b;
+    int32_t len, reversed;
 } hb_cut;
 
 /* Free stream and forcing.  alpha(t) = alpha0 + alpha_amp sin(omega t),
@@ -158,7 +170,11 @@ typedef struct {
     double pitch_amp, pitch_phase, heave_amp, x_pivot, y_pivot;
 } hb_motion;
 
-/* Build a grid: copies the host arrays, computes the metrics on the device
+/* Build a grid (the paper's problem statement: a structured multi-block
+ * grid whose blocks meet at cuts, the paragraph on the MPI parallelisation
+ * after the Introduction; N_H harmonics per block, the nharms of the
+ * §MPI Optimisations pseudo code, whose snapshots n = 0..2*nharms each
+ * carry npde = 4 variables): copies the host arrays, computes the metrics on the device
  * (FP64), allocates all scratch.  Validation (HB_ERR_ARG): nblocks >= 1,
  * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
  * [0, ni/2] and only with a WAKECUT jmin, cut sides consistent, bodies
@@ -182,11 +198,22 @@ int64_t hb_forces_size(const hb_grid *g);
 /* Doubles in the node-coordinate array: sum over blocks 2 (nj+1)(ni+1). */
 int64_t hb_xy_size(const hb_grid *g);
 
-/* r = R*(q), the HB residual of every cell and snapshot (public layout).
+/* r = R*(q), the HB residual of every cell and snapshot (public layout):
+ * the operator that the paper's Runge-Kutta step (§MPI Optimisations)
+ * evaluates over all blocks and harmonics after the cut (halo) exchange.
+ * The paper does not print its formula (its HB-formulation section is
+ * missing); here R*_n = R(Q_n) + V (D Q)_n with R the net MUSCL/Roe inviscid
+ * minus central viscous face flux of the cell and D the time-collocation
+ * spectral derivative over the N_s snapshots.
  * q, r: device, hb_state_size() doubles each, must not overlap. */
 int hb_residual(hb_grid *g, const double *q, double *r, void *stream);
 
-/* n_iter pseudo-time iterations in place on q (device, public layout).
+/* n_iter pseudo-time iterations in place on q (device, public layout): the
+ * paper's Runge-Kutta steps (§MPI Optimisations: each step exchanges the cut
+ * halos and reduces the loads of every body and harmonic once), here the
+ * four-stage scheme Q(k) = Q(0) - a_k (dtau/V) R*(Q(k-1)) with the local
+ * pseudo-time step dtau of each cell and snapshot (coefficients and step
+ * are not given in the paper; hb_solver sets them).
  * resnorm (device, n_iter doubles, may be NULL): RMS of R*_rho / V over all
  * cells and snapshots at the first stage of each iteration.
  * forces (device, hb_forces_size() doubles, may be NULL): cl, cd, cm of the
@@ -196,14 +223,21 @@ int hb_residual(hb_grid *g, const double *q, double *r, void *stream);
 int hb_rk_iterate(hb_grid *g, double *q, int32_t n_iter, double *resnorm,
                   double *forces, void *stream);
 
-/* cf = (cl, cd, cm) per body and snapshot, layout [body][n][3] (bodies in
+/* The loads of the paper's force reduction (§MPI Optimisations: cl, cd and
+ * cm of every body and harmonic, gathered into one buffer and reduced once
+ * per Runge-Kutta step; the paper packs it harmonic-major, here it is
+ * body-major because bodies may differ in N_s):
+ * cf = (cl, cd, cm) per body and snapshot, layout [body][n][3] (bodies in
  * id order, each with its own N_s); drag along the mean free stream
  * (cos alpha0, sin alpha0), lift normal to it, cm positive nose-up, all on
  * q_inf = mach^2/2 and l_ref.  Wall faces: -(p_w - p_inf) S + tau.S with
  * p_w the adjacent cell's pressure.  FP64. */
 int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
 
-/* Reverse-mode (Jacobian-transpose) products of the residual R* = hb_residual:
+/* Reverse-mode (Jacobian-transpose) products of the residual R* = hb_residual.
+ * The paper does not define or use an adjoint; this is the transpose of the
+ * linearisation of hb_residual's operator, for gradients of HB-averaged loads
+ * with respect to grid and flow parameters:
  *   qbar    = J_Q^T rbar,  J_Q = d R* / d Q        (state size, overwritten)
  *   xybar   = J_X^T rbar,  X = node coordinates    (hb_xy_size(), may be NULL)
  *   flowbar = J_a^T rbar,  a = alpha0              (1 double, may be NULL)
@@ -241,7 +275,7 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
                        int32_t n_iter, double *resnorm, void *stream);
 
 /* Restart files (the paper's aggregated output of all blocks and harmonics,
- * §I/O Optimisations): hb_save_state writes the whole state q (device,
+ * §MPI Optimisations, the part on MPI I/O): hb_save_state writes the whole state q (device,
  * state size) and the caller's iteration counter to `path` in one write
  * (header with a workload signature and the block table, the state in the
  * public layout, a checksum; written to path.tmp, then renamed).

@@ -269,6 +269,16 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         if (k.blk_a < 0 || k.blk_a >= nblocks || k.blk_b < 0 || k.blk_b >= nblocks ||
             k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3)
             return fail(HB_ERR_ARG, "bad cut");
+        {
+            const int la = k.side_a < 2 ? blocks[k.blk_a].nj : blocks[k.blk_a].ni;
+            const int lb = k.side_b < 2 ? blocks[k.blk_b].nj : blocks[k.blk_b].ni;
+            if (k.len < 1 || k.start_a < 0 || k.start_b < 0 ||
+                (int64_t)k.start_a + k.len > la || (int64_t)k.start_b + k.len > lb)
+                return fail(HB_ERR_ARG, "cut segment outside its block sides");
+            if (k.start_a != 0 || k.start_b != 0 || k.len != la || k.len != lb)
+                return fail(HB_ERR_UNSUPPORTED, "segment cuts are not supported: a cut glues "
+                                                "whole sides (start 0, len = side length)");
+        }
         if (k.reversed != 0) return fail(HB_ERR_UNSUPPORTED, "reversed cuts are not supported");
         if (k.side_a % 2 == 0) {   // normalise to (max side of a) <-> (min side of b)
             std::swap(k.blk_a, k.blk_b);

@@ -1,6 +1,6 @@
 // Restart files: the whole state of a grid (every block and snapshot, the
 // public FP64 layout) in one aggregated write, in the spirit of the paper's
-// I/O optimisation (§I/O Optimisations: one collective write of all blocks
+// I/O optimisation (§MPI Optimisations, the part on MPI I/O: one collective write of all blocks
 // and harmonics instead of one file per process).  Layout (little endian):
 //   char[8]  "HBSTATE1"
 //   uint64   workload signature (FNV-1a over block sizes, N_H, boundary kinds)

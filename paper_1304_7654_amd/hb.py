@@ -40,8 +40,8 @@ class c_block(ctypes.Structure):
 
 
 class c_cut(ctypes.Structure):
-    _fields_ = [("blk_a", ctypes.c_int32), ("side_a", ctypes.c_int32), ("blk_b", ctypes.c_int32),
-                ("side_b", ctypes.c_int32), ("reversed", ctypes.c_int32)]
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("blk_a", "side_a", "start_a", "blk_b", "side_b", "start_b", "len", "reversed")]
 
 
 class c_tuning(ctypes.Structure):
@@ -154,8 +154,15 @@ class Grid:
             cb[k].body_id = int(b.body_id)
         cc = (c_cut * max(1, len(cuts)))()
         for k, c in enumerate(cuts):
-            cc[k].blk_a, cc[k].side_a, cc[k].blk_b, cc[k].side_b = c[0], c[1], c[2], c[3]
-            cc[k].reversed = c[4] if len(c) > 4 else 0
+            if len(c) == 8:      # (blk_a, side_a, start_a, blk_b, side_b, start_b, len, reversed)
+                vals = [int(x) for x in c]
+            else:                # (blk_a, side_a, blk_b, side_b[, reversed]): whole sides
+                a, sa, b, sb = (int(x) for x in c[:4])
+                side = blocks[a].nj if sa < 2 else blocks[a].ni
+                vals = [a, sa, 0, b, sb, 0, side, int(c[4]) if len(c) > 4 else 0]
+            for name, v in zip(("blk_a", "side_a", "start_a", "blk_b", "side_b", "start_b",
+                                "len", "reversed"), vals):
+                setattr(cc[k], name, v)
         cf = c_flow(flow.mach, flow.reynolds, flow.prandtl, flow.gamma, flow.alpha0,
                     flow.alpha_amp, flow.k_red, flow.l_ref, flow.x_mom, flow.y_mom)
         cs = c_solver()

@@ -110,6 +110,18 @@ def test_validation_rejects_before_device_work():
     with pytest.raises(hb.HBError) as e:
         hb.Grid(sp.blocks, sp.flow, sp.solver, rev)
     assert e.value.code == hb.HB_ERR_UNSUPPORTED                # reversed cut
+    # segments: the interface carries start/len; this build glues whole sides
+    a, sa, b2_, sb = sp.cuts[0][:4]
+    side = sp.blocks[a].nj if sa < 2 else sp.blocks[a].ni
+    others = list(sp.cuts[1:])
+    for seg, code in (((a, sa, 0, b2_, sb, 0, side - 2, 0), hb.HB_ERR_UNSUPPORTED),
+                      ((a, sa, 1, b2_, sb, 1, side - 1, 0), hb.HB_ERR_UNSUPPORTED),
+                      ((a, sa, 0, b2_, sb, 0, side + 1, 0), hb.HB_ERR_ARG),
+                      ((a, sa, -1, b2_, sb, 0, side, 0), hb.HB_ERR_ARG),
+                      ((a, sa, 0, b2_, sb, 0, 0, 0), hb.HB_ERR_ARG)):
+        with pytest.raises(hb.HBError) as e:
+            hb.Grid(sp.blocks, sp.flow, sp.solver, [seg] + others)
+        assert e.value.code == code, seg
 
 
 def test_binding_rejects_bad_tensors():
