@@ -93,14 +93,37 @@ def read_traffic(tuning, workload):
 
 
 def algorithmic_bytes_per_iteration(problem) -> float:
-    """Bytes the FP32-bulk iteration must move (4 stages): stage 1 reads Q (FP64, 32 B/cs) and writes the FP32 stage state (16);
-    stages 2-3 read the stage state (16) and Q (32) and write (16); stage 4
-    reads the stage state (16) and Q (32) and writes Q (32).  Each stage also
-    reads 9 FP32 metric words per cell (two face normals, two centre
-    offsets, the area)."""
+    """Bytes the method must move per FP32-bulk iteration (4 stages), the
+    FP32-stage-shadow variant of the algorithmic count: stage 1 reads Q (FP64,
+    32 B per cell-snapshot) and writes the FP32 stage state (16); stages 2-3
+    read the stage state (16) and Q (32) and write (16); stage 4 reads the
+    stage state (16) and Q (32) and writes Q (32): 64 B per cell-snapshot
+    and stage on average.  Metrics: 5 FP32 words per cell and stage (two face
+    normals and the area; the face normals of the far sides belong to the
+    neighbours), so 64 + 20/N_s B per unit."""
+    cs = problem.cell_snapshots
+    cells = sum(b.ni * b.nj for b in problem.blocks)
+    return cs * (48 + 64 + 64 + 80) + 4 * 20 * cells
+
+
+def design_bytes_per_iteration(problem) -> float:
+    """The same with the 9 FP32 metric words per cell that the fused kernel
+    reads (it also reads the two centre offsets of the viscous diamonds
+    instead of forming them from the nodes): 64 + 36/N_s B per unit."""
     cs = problem.cell_snapshots
     cells = sum(b.ni * b.nj for b in problem.blocks)
     return cs * (48 + 64 + 64 + 80) + 4 * 36 * cells
+
+
+def plain_algorithmic_stage_bytes(problem) -> float:
+    """Bytes one FP64 stage must move by the method (FP64 stage states): read
+    the stage input (32 B per cell-snapshot), read Q(0) (32, stages 2-4) and
+    write the new state (32): (64 + 3 x 96)/4 = 88 B per cell-snapshot and
+    stage on average, plus 5 FP64 metric words per cell (40 B), so
+    88 + 40/N_s B per unit."""
+    cs = problem.cell_snapshots
+    cells = sum(b.ni * b.nj for b in problem.blocks)
+    return 88.0 * cs + 40.0 * cells
 
 
 # rigid motion of the moving-grid leg: 0.3 rad of pitch about the quarter
@@ -109,8 +132,8 @@ MOTION = dict(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_piv
 
 
 def plain_stage_bytes(problem, moving) -> float:
-    """Bytes one stage of the plain FP64 path (every intermediate in HBM)
-    must move: the ghost fill reads Q and writes the ghost-extended
+    """Bytes one stage of the plain FP64 path's own design moves (every
+    intermediate in HBM; not the method's algorithmic bytes): the ghost fill reads Q and writes the ghost-extended
     primitives E; each face family (one kernel for both) reads E and its face
     metrics (S, d) and writes its face fluxes; the update reads both flux
     arrays, the stage input, the base state, the face normals and the cell
@@ -134,7 +157,8 @@ def plain_stage_bytes(problem, moving) -> float:
 def plain_leg(torch, hb, problem, q0, steps, motion=None):
     """Plain FP64 per-block path: throughput with loads every iteration, and
     its stage time from HIP events around every stage (on the launch
-    stream) for the roofline over plain_stage_bytes."""
+    stream) for the roofline over the method's algorithmic bytes
+    (plain_algorithmic_stage_bytes; the design's own traffic beside it)."""
     cs = problem.cell_snapshots
     stages = len(problem.solver.rk_alpha)
     g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=0, batched=0)
@@ -152,12 +176,17 @@ def plain_leg(torch, hb, problem, q0, steps, motion=None):
     g.profile_stages(False)
     g.close()
     stage_s = ms / 1000.0 / n
-    nbytes = plain_stage_bytes(problem, bool(motion))
+    abytes = plain_algorithmic_stage_bytes(problem)
+    dbytes = plain_stage_bytes(problem, bool(motion))
     return {"value": cs * stages * steps / t, "ms_per_step": 1000.0 * t / steps,
-            "roofline": {"bound": "hbm", "achieved": nbytes / stage_s / 1e9, "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": nbytes / stage_s / 1e9 / PEAK_HBM_GBS,
+            "roofline": {"bound": "hbm", "achieved": abytes / stage_s / 1e9, "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": abytes / stage_s / 1e9 / PEAK_HBM_GBS,
                          "kernels": "per block: k_ghost, k_flux (i- and j-faces), k_update",
-                         "avg_stage_ms": 1000.0 * stage_s, "algorithmic_bytes_per_stage": nbytes}}
+                         "avg_stage_ms": 1000.0 * stage_s, "algorithmic_bytes_per_stage": abytes,
+                         # the plain design's own HBM intermediates (ghost-extended
+                         # primitives, face fluxes) on top of the method's bytes
+                         "design_bytes_per_stage": dbytes,
+                         "design_gbs": dbytes / stage_s / 1e9}}
 
 
 def stream_probe(torch, mib=1024, reps=10):
@@ -422,6 +451,8 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_fused (FP32 bulk stage)", "avg_launch_ms": 1000.0 * stage_s,
                      "algorithmic_bytes_per_launch": bytes_launch,
+                     # the 9 metric words per cell the kernel reads (5 by the method)
+                     "design_bytes_per_launch": design_bytes_per_iteration(problem) / stages,
                      # measured HBM traffic (counters) over the live launch time, against
                      # the 8 TB/s peak and against a 1 GiB device copy measured here
                      "traffic_gbs": None if traffic is None else traffic / stage_s / 1e9,

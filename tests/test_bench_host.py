@@ -48,3 +48,17 @@ def test_plain_stage_bytes():
     # at least Q in and out, E written once and read twice, both flux arrays out and in
     assert fixed > 8 * 4 * p.cell_snapshots * 2 * 5
     assert moving > fixed
+
+
+def test_algorithmic_bytes_follow_the_unit_counts():
+    """64 + 20/N_s B per unit for the FP32-shadow path and 88 + 40/N_s for
+    FP64 stage states, summed over the blocks of the batch."""
+    p = synth.make_problem("batch32_mixed")
+    cs = p.cell_snapshots
+    cells = sum(b.ni * b.nj for b in p.blocks)
+    per_launch = bench.algorithmic_bytes_per_iteration(p) / 4
+    assert abs(per_launch - (64 * cs + 20 * cells)) < 1e-6 * per_launch
+    assert bench.design_bytes_per_iteration(p) / 4 - per_launch == 16 * cells
+    plain = bench.plain_algorithmic_stage_bytes(p)
+    assert abs(plain - (88 * cs + 40 * cells)) < 1e-6 * plain
+    assert bench.plain_stage_bytes(p, False) > plain
