@@ -13,8 +13,10 @@ Prints one JSON line: the FP32-bulk batched rate (value), the plain FP64
 per-block rate beside it, the live roofline of the fused stage kernel
 (HIP events around each stage launch on the launch stream), the HBM traffic
 of that kernel from the committed rocprofv3 counter summary (when it was
-taken on the current kernel source), and the FP64 CPU oracle timed on a
-bounded sample on the host cores.
+taken on the current kernel source), the same kernel's ALU roofline on the
+method's operation count per unit (counted on the oracle's own evaluation
+in the CPU leg), and the FP64 CPU oracle timed on a bounded sample on the
+host cores.
 """
 from __future__ import annotations
 
@@ -31,6 +33,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# FP32 vector peak (packed FP32 counted; packed FP32 instructions are not
+# used by this build, so half of it is the reachable vector rate)
+PEAK_FP32_TFLOPS = 157.3
 # VALU issue capacity: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a 64-wide
 # wave's non-packed FP32 instruction occupies its SIMD for 4 cycles)
 PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
@@ -311,6 +316,10 @@ def cpu_baseline(problem, q_host, target_s=12.0):
     out["single_thread"] = {"value": c1 * len(solver.rk_alpha) * its / d1,
                             "sample": "block %d (%d cell-snapshots), %d iteration(s), %.1f s"
                                       % (sel[0], c1, its, d1)}
+    # the method's floating-point operations per unit, counted on the
+    # oracle's own evaluation of one iteration of the whole workload
+    from oracle import hb_opcount
+    out["oracle_ops"] = hb_opcount.ops_per_unit(blocks, torch.as_tensor(q_host), flow, solver)
     return out
 
 
@@ -460,10 +469,10 @@ def main():
                      "stream_probe_gbs": probe,
                      "frac_of_stream_probe": achieved / probe,
                      "traffic_frac_of_stream_probe": None if traffic is None else traffic / stage_s / 1e9 / probe},
-        # the bound the shader counters show: VALU issue (64 lanes per
-        # wave-instruction) over the same live launch time
-        "roofline_alu": None if valu is None else {
-            "bound": "alu", "achieved": 64.0 * valu / stage_s, "peak": PEAK_VALU_LANE_INSTR,
+        # VALU issue (64 lanes per wave-instruction, from the committed shader
+        # counters) over the same live launch time: a utilisation figure
+        "valu_issue": None if valu is None else {
+            "achieved": 64.0 * valu / stage_s, "peak": PEAK_VALU_LANE_INSTR,
             "unit": "VALU lane-instructions/s", "frac": 64.0 * valu / stage_s / PEAK_VALU_LANE_INSTR,
             "valu_wave_instructions_per_launch": valu},
         "adjoint_over_primal": None if args.no_adjoint else {
@@ -473,6 +482,15 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem, q_host)
+        # ALU roofline of the same kernel: the method's operations per unit
+        # (counted on the oracle) times the units of one launch, over the
+        # live launch time, against the FP32 vector peak
+        opu = out["cpu_baseline"]["oracle_ops"]["per_unit"]
+        flops = opu * cs / stage_s
+        out["roofline_alu"] = {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP32_TFLOPS,
+                               "unit": "TFLOP/s", "frac": flops / 1e12 / PEAK_FP32_TFLOPS,
+                               "ops_per_unit": opu,
+                               "frac_of_unpacked_fp32": flops / 1e12 / (PEAK_FP32_TFLOPS / 2)}
     print(json.dumps(out))
 
 
