@@ -286,6 +286,24 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
 int hb_save_state(hb_grid *g, const double *q, int64_t iteration, const char *path, void *stream);
 int hb_load_state(hb_grid *g, double *q, int64_t *iteration, const char *path, void *stream);
 
+/* Solution files, one per snapshot (the paper writes one solution file per
+ * real harmonic at the end of a run, beside the restart file, and makes
+ * each an aggregated parallel write, §MPI Optimisations, the part on MPI
+ * I/O): for k = 0 .. max N_s - 1, `<prefix>.snap<k>` holds, in one write,
+ * every block with more than k snapshots: its nodes at snapshot k (moved by
+ * the rigid motion when one is set) and the primitives (rho, u, v, p) of
+ * its cells at snapshot k.  Layout (little endian):
+ *   char[8] "HBSOLN01", int32 k, int32 number of blocks in the file,
+ *   per block: int32 block index, ni, nj, n_harm; double phase
+ *     omega t_k = 2 pi k / N_s; double x[nj+1][ni+1], y[nj+1][ni+1];
+ *     double rho[nj][ni], u[nj][ni], v[nj][ni], p[nj][ni],
+ *   uint64 FNV-1a of every byte after the magic.
+ * q: device, state size.  Each file is written to `<file>.tmp` and renamed.
+ * Allocates (and frees) a device staging buffer of the records of all
+ * blocks and snapshots; synchronises `stream`.  HB_ERR_ARG for NULL or an
+ * empty prefix or a file that cannot be written. */
+int hb_save_solution(hb_grid *g, const double *q, const char *prefix, void *stream);
+
 /* Time-domain march: the time-domain counterpart of the HB system (the
  * paper's code solves unsteady flows in the time domain as well as by HB,
  * §Introduction).  n_steps classical fourth-order Runge-Kutta steps of size

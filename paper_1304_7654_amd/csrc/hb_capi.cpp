@@ -545,6 +545,12 @@ int hb_load_state(hb_grid *g, double *q, int64_t *iteration, const char *path, v
     return io_load(g, q, iteration, path, (hipStream_t)stream);
 }
 
+int hb_save_solution(hb_grid *g, const double *q, const char *prefix, void *stream) {
+    g_err.clear();
+    if (!g || !q || !prefix || !prefix[0]) return fail(HB_ERR_ARG, "NULL argument");
+    return io_save_solution(g, q, prefix, (hipStream_t)stream);
+}
+
 int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream) {
     g_err.clear();
     if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");

@@ -221,6 +221,7 @@ void fused_drop_graph(hb_grid *g);
 // io.cpp
 int io_save(hb_grid *g, const double *q, int64_t iteration, const char *path, hipStream_t s);
 int io_load(hb_grid *g, double *q, int64_t *iteration, const char *path, hipStream_t s);
+int io_save_solution(hb_grid *g, const double *q, const char *prefix, hipStream_t s);
 // td.hip
 int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s);
 // tune.cpp

@@ -1,3 +1,5 @@
+// Restart files and per-snapshot solution files.
+//
 // Restart files: the whole state of a grid (every block and snapshot, the
 // public FP64 layout) in one aggregated write, in the spirit of the paper's
 // I/O optimisation (§MPI Optimisations, the part on MPI I/O: one collective write of all blocks
@@ -11,8 +13,10 @@
 //   uint64   FNV-1a of the state bytes
 #include "hb_internal.hpp"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 namespace hb {
@@ -113,6 +117,112 @@ int io_load(hb_grid *g, double *q, int64_t *iteration, const char *path, hipStre
     rc = rc ? rc : check_hip(hipStreamSynchronize(s), "sync");
     if (!rc && iteration) *iteration = it;
     return rc;
+}
+
+namespace {
+
+// One solution record per (block, snapshot n): the nodes of snapshot n
+// (the body-frame nodes moved by the rigid motion when one is set) and the
+// primitives (rho, u, v, p) of every cell:
+//   [x (nj+1)(ni+1)][y (nj+1)(ni+1)][rho nj ni][u][v][p]
+// grid.y = snapshot; one thread per node (and per cell, cells < nodes).
+__global__ void k_sol_record(const BlockDesc *blks, int b, const double *q, const double *xy,
+                             Motion mo, double gamma, double *out) {
+    const BlockDesc &B = blks[b];
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1), nc = (int64_t)B.ni * B.nj;
+    const int n = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double *rec = out + (int64_t)n * (2 * nn + 4 * nc);
+    if (t < nn) {
+        double x = xy[2 * B.node_off + t], y = xy[2 * B.node_off + nn + t];
+        if (mo.tab) {
+            const double *m = mo.tab + (int64_t)kMotionW * (B.snap_off + n);
+            const double rx = x - mo.xp, ry = y - mo.yp;
+            x = mo.xp + m[0] * rx - m[1] * ry;
+            y = mo.yp + m[3] + m[1] * rx + m[0] * ry;
+        }
+        rec[t] = x;
+        rec[nn + t] = y;
+    }
+    if (t < nc) {
+        const double *qn = q + B.q_off + (int64_t)n * 4 * nc;
+        const double rho = qn[t], u = qn[nc + t] / rho, v = qn[2 * nc + t] / rho;
+        const double pr = (gamma - 1.0) * (qn[3 * nc + t] - 0.5 * rho * (u * u + v * v));
+        double *w = rec + 2 * nn;
+        w[t] = rho;
+        w[nc + t] = u;
+        w[2 * nc + t] = v;
+        w[3 * nc + t] = pr;
+    }
+}
+
+const char kSolMagic[8] = {'H', 'B', 'S', 'O', 'L', 'N', '0', '1'};
+
+}  // namespace
+
+int io_save_solution(hb_grid *g, const double *q, const char *prefix, hipStream_t s) {
+    // staging: the records of every block and snapshot, blocks in order
+    std::vector<int64_t> off(g->nblocks + 1, 0);
+    int max_ns = 0;
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1), nc = (int64_t)B.ni * B.nj;
+        off[b + 1] = off[b] + (int64_t)B.ns * (2 * nn + 4 * nc);
+        max_ns = std::max(max_ns, (int)B.ns);
+    }
+    double *stage = nullptr;
+    int rc = check_hip(hipMalloc((void **)&stage, sizeof(double) * off[g->nblocks]), "solution staging");
+    if (rc) return rc;
+    for (int b = 0; b < g->nblocks && !rc; ++b) {
+        const BlockDesc &B = g->blk[b];
+        const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+        hipLaunchKernelGGL(k_sol_record, dim3((unsigned)((nn + 255) / 256), B.ns), dim3(256), 0, s,
+                           g->blk_d, b, q, g->xy_d, g->motion, g->flow.gamma, stage + off[b]);
+        rc = check_hip(hipGetLastError(), "solution launch");
+    }
+    std::vector<double> host(off[g->nblocks]);
+    rc = rc ? rc : check_hip(hipMemcpyAsync(host.data(), stage, sizeof(double) * host.size(),
+                                            hipMemcpyDeviceToHost, s), "solution copy");
+    rc = rc ? rc : check_hip(hipStreamSynchronize(s), "sync");
+    (void)hipFree(stage);
+    if (rc) return rc;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < max_ns; ++k) {
+        // file k: every block with more than k snapshots, one write
+        std::vector<unsigned char> buf;
+        auto put = [&buf](const void *p, size_t n) {
+            const unsigned char *c = static_cast<const unsigned char *>(p);
+            buf.insert(buf.end(), c, c + n);
+        };
+        int32_t nb = 0;
+        for (const BlockDesc &B : g->blk) nb += B.ns > k;
+        const int32_t kk = k;
+        put(kSolMagic, 8);
+        put(&kk, 4);
+        put(&nb, 4);
+        for (int b = 0; b < g->nblocks; ++b) {
+            const BlockDesc &B = g->blk[b];
+            if (B.ns <= k) continue;
+            const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1), nc = (int64_t)B.ni * B.nj;
+            const int32_t v[4] = {b, B.ni, B.nj, B.nh};
+            const double phase = two_pi * k / B.ns;
+            put(v, sizeof v);
+            put(&phase, 8);
+            put(host.data() + off[b] + (int64_t)k * (2 * nn + 4 * nc), sizeof(double) * (2 * nn + 4 * nc));
+        }
+        const uint64_t sum = fnv(buf.data() + 8, buf.size() - 8);
+        put(&sum, 8);
+        const std::string path = std::string(prefix) + ".snap" + std::to_string(k);
+        const std::string tmp = path + ".tmp";
+        FILE *f = std::fopen(tmp.c_str(), "wb");
+        if (!f) return fail(HB_ERR_ARG, "cannot open the solution file for writing");
+        const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);       // one aggregated write
+        const int cl = std::fclose(f);
+        if (w != buf.size() || cl != 0) return fail(HB_ERR_ARG, "solution file write failed");
+        if (std::rename(tmp.c_str(), path.c_str()) != 0)
+            return fail(HB_ERR_ARG, "cannot replace the solution file");
+    }
+    return HB_OK;
 }
 
 }  // namespace hb

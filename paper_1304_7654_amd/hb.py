@@ -22,7 +22,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORT
 HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_save_state", "hb_load_state", "hb_autotune", "hb_set_tuning",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_save_state", "hb_load_state", "hb_save_solution", "hb_autotune", "hb_set_tuning",
            "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_set_motion", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.hb_td_march.argtypes = [vp, vp, dp, dp, i32, vp]
     L.hb_save_state.argtypes = [vp, vp, i64, ctypes.c_char_p, vp]
     L.hb_load_state.argtypes = [vp, vp, ctypes.POINTER(i64), ctypes.c_char_p, vp]
+    L.hb_save_solution.argtypes = [vp, vp, ctypes.c_char_p, vp]
     L.hb_autotune.argtypes = [vp, vp, ctypes.c_char_p, i32, ctypes.POINTER(c_tuning), vp]
     L.hb_set_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
     L.hb_get_tuning.argtypes = [vp, ctypes.POINTER(c_tuning)]
@@ -257,6 +258,12 @@ class Grid:
         _check(lib().hb_load_state(self.h, _ptr(q, self.n_state, "q"), ctypes.byref(it),
                                    str(path).encode(), _stream()))
         return it.value
+
+    def save_solution(self, q: torch.Tensor, prefix: str):
+        """Per-snapshot solution files <prefix>.snap<k> (nodes and primitives
+        of every block with more than k snapshots, one write per file)."""
+        _check(lib().hb_save_solution(self.h, _ptr(q, self.n_state, "q"), str(prefix).encode(),
+                                      _stream()))
 
     def td_march(self, q: torch.Tensor, t0: float, dt: float, n_steps: int):
         """n_steps fourth-order Runge-Kutta steps in physical time from t0,

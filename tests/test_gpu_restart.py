@@ -1,15 +1,20 @@
 """Restart files (hb_save_state / hb_load_state): a run killed after 2
 iterations and resumed from its file in a new process reproduces 5
-uninterrupted iterations bit for bit; corrupted files and files of another
-workload are refused."""
+uninterrupted iterations bit for bit and the oracle's 5 iterations;
+corrupted files and files of another workload are refused.  Per-snapshot
+solution files (hb_save_solution): nodes and primitives of every block and
+snapshot against the oracle's, on a fixed and on a moving grid."""
 import os
 import subprocess
 import sys
 import tempfile
 
+import numpy as np
 import pytest
 import torch
 
+from oracle import hb_moving as M
+from oracle import hb_oracle as O
 from paper_1304_7654_amd import hb, synth
 
 pytestmark = pytest.mark.gpu
@@ -51,6 +56,21 @@ def test_kill_and_resume_in_a_new_process_is_bitwise(prec, batched):
         assert g.load_state(out, b) == 5
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+    # the resumed state against the oracle's five uninterrupted iterations
+    blocks, flow, solver = O.from_synth(p)
+    q0h = torch.as_tensor(synth.initial_state(p))
+    qref, _ = O.rk_iterate(blocks, q0h, flow, solver, 5)
+    tol = 1e-12 if prec == 0 else 1e-5
+    for v, (a, r) in enumerate(zip(_per_var(blocks, out.cpu() - q0h), _per_var(blocks, qref - q0h))):
+        rel = float((a - r).norm() / r.norm())
+        print("  change of variable", v, "rel error", rel, flush=True)
+        assert rel <= tol
+
+
+def _per_var(blocks, x):
+    """Per conserved variable, all blocks, cells and snapshots."""
+    parts = O.split(blocks, x)
+    return [torch.cat([q[:, v].reshape(-1) for q in parts]) for v in range(4)]
 
 
 def test_corrupt_and_foreign_files_are_refused():
@@ -77,3 +97,61 @@ def test_corrupt_and_foreign_files_are_refused():
             g.load_state(back, f2)
         with pytest.raises(hb.HBError):
             g.load_state(back, os.path.join(d, "missing.hbq"))
+
+
+def _read_solution(path):
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"HBSOLN01"
+    k, nb = np.frombuffer(raw, np.int32, 2, 8)
+    pos, out = 16, {}
+    for _ in range(nb):
+        b, ni, nj, nh = (int(x) for x in np.frombuffer(raw, np.int32, 4, pos))
+        phase = float(np.frombuffer(raw, np.float64, 1, pos + 16)[0])
+        pos += 24
+        nn, nc = (ni + 1) * (nj + 1), ni * nj
+        rec = np.frombuffer(raw, np.float64, 2 * nn + 4 * nc, pos)
+        pos += 8 * (2 * nn + 4 * nc)
+        out[b] = (nh, phase, rec[:2 * nn].reshape(2, nj + 1, ni + 1),
+                  rec[2 * nn:].reshape(4, nj, ni))
+    assert pos + 8 == len(raw)
+    # FNV-1a of every byte after the magic
+    h = 1469598103934665603
+    for c in raw[8:pos]:
+        h = ((h ^ c) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    assert h == int(np.frombuffer(raw, np.uint64, 1, pos)[0])
+    return int(k), out
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_solution_files_per_snapshot(moving):
+    """One file per snapshot index k holding every block with more than k
+    snapshots: nodes (moved for snapshot k on a moving grid) and primitives
+    equal the oracle's."""
+    p = synth.make_problem("batch_tiny")
+    blocks, flow, solver = O.from_synth(p)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    mot = M.OMotion(pitch_amp=0.3, pitch_phase=0.5, heave_amp=0.7, x_pivot=0.25, y_pivot=0.05)
+    if moving:
+        g.set_motion(mot.pitch_amp, mot.pitch_phase, mot.heave_amp, mot.x_pivot, mot.y_pivot)
+    q = torch.as_tensor(synth.initial_state(p)).to(DEV)
+    g.rk_iterate(q, 2)
+    qh = q.cpu()
+    prims = [O.primitives(x, flow.gamma) for x in O.split(blocks, qh)]
+    max_ns = max(b.ns for b in blocks)
+    with tempfile.TemporaryDirectory() as d:
+        g.save_solution(q, os.path.join(d, "sol"))
+        assert sorted(os.listdir(d)) == ["sol.snap%d" % k for k in range(max_ns)]
+        for k in range(max_ns):
+            kk, recs = _read_solution(os.path.join(d, "sol.snap%d" % k))
+            assert kk == k
+            assert sorted(recs) == [b for b, blk in enumerate(blocks) if blk.ns > k]
+            for b, (nh, phase, xy, w) in recs.items():
+                blk = blocks[b]
+                assert nh == blk.n_harm and abs(phase - 2 * np.pi * k / blk.ns) < 1e-15
+                ref_xy = M.snapshot_xy(blk, mot, flow, k) if moving else blk.xy
+                exy = float(np.abs(xy - ref_xy.numpy()).max())
+                assert exy <= (1e-14 * float(ref_xy.abs().max()) if moving else 0.0), exy
+                ref_w = prims[b][k].numpy()
+                for v in range(4):
+                    rel = np.linalg.norm(w[v] - ref_w[v]) / np.linalg.norm(ref_w[v])
+                    assert rel <= 1e-14, (b, k, v, rel)
