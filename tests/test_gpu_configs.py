@@ -1,0 +1,98 @@
+"""Parity at the configurations' own sizes and iteration counts: the
+64x32 N_H = 1 cylinder after its 100 iterations and the four-block N_H = 2
+airfoil (256x64, 128x64, 192x96, 64x64) after its 500, on the per-block
+plain FP64 path and the batched FP64 path, against the FP64 oracle run
+through the same iterations.
+
+- State after N iterations: the change from the initial state per
+  variable within 1e-10 (relative 2-norm over all blocks, cells and
+  snapshots); the residual norm of every iteration within 1e-10.
+- Residual on the oracle's states after 1, 10 and N iterations: per
+  variable within 1e-12, or four times the FP64 rounding floor of the
+  residual on that state where that is larger (parity_util.fp64_floor).
+
+The oracle trajectory is computed once per configuration, one worker
+process per block."""
+import multiprocessing as mp
+import os
+import time
+
+import pytest
+import torch
+
+from oracle import hb_oracle as O
+from paper_1304_7654_amd import hb, synth
+from parity_util import block_trajectory, fp64_floor, fp64_tolerance, per_var_errors
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+_TRAJ = {}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _trajectory(name):
+    """Oracle states after 0, 1, 10 and N iterations and all N norms.  The
+    blocks of these configurations have no cuts, so each block's iterations
+    run on their own in a worker process, and the norm of an iteration is
+    put together from the blocks' sums of squares."""
+    if name in _TRAJ:
+        return _TRAJ[name]
+    p = synth.make_problem(name)
+    blocks, flow, solver = O.from_synth(p)
+    assert not p.cuts
+    q = torch.as_tensor(synth.initial_state(p))
+    marks = (1, 10, p.n_iter)
+    nb = len(blocks)
+    threads = max(1, (os.cpu_count() or 1) // nb)
+    t0 = time.time()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(nb) as pool:
+        res = pool.map(block_trajectory, [(name, k, marks, threads) for k in range(nb)])
+    _say("  oracle %s: %d iterations of %d blocks (%.0f s)" % (name, p.n_iter, nb, time.time() - t0))
+    total = sum(b.ns * b.ni * b.nj for b in blocks)
+    states = {0: q}
+    for m in marks:
+        states[m] = O.join([r[0][m] for r in res])
+    norms = torch.sqrt(sum(r[1] for r in res) / total)
+    _TRAJ[name] = (p, blocks, flow, solver, states, norms)
+    return _TRAJ[name]
+
+
+@pytest.mark.parametrize("name", ["cyl64x32_nh1", "naca4blk_nh2"])
+@pytest.mark.parametrize("batched", [0, 1])
+def test_state_after_full_iteration_count(name, batched):
+    p, blocks, flow, solver, states, nref = _trajectory(name)
+    n = p.n_iter
+    _say("case", name, "batched", batched, n, "iterations")
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=batched)
+    q0 = states[0]
+    qd = q0.to(DEV)
+    norms = torch.zeros(n, dtype=torch.float64, device=DEV)
+    g.rk_iterate(qd, n, norms)
+    torch.cuda.synchronize()
+    assert g.status() == hb.HB_OK
+    e = per_var_errors(blocks, qd.cpu() - q0, states[n] - q0)
+    en = float(((norms.cpu() - nref).abs() / nref).max())
+    _say("  state change rel per variable", e, "norms rel (max)", en,
+         "norm drop", float(nref[-1] / nref[0]))
+    assert max(e) <= 1e-10 and en <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["cyl64x32_nh1", "naca4blk_nh2"])
+@pytest.mark.parametrize("batched", [0, 1])
+def test_residual_on_oracle_states(name, batched):
+    p, blocks, flow, solver, states, _ = _trajectory(name)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=batched)
+    for it in (1, 10, p.n_iter):
+        q = states[it]
+        floor, ref = fp64_floor(blocks, q, flow, solver)
+        tol = fp64_tolerance(floor)
+        r = g.residual(q.to(DEV)).cpu()
+        torch.cuda.synchronize()
+        e = per_var_errors(blocks, r, ref)
+        _say("  %s batched %d after %d: rel %s floor %s" % (name, batched, it,
+             ["%.2e" % x for x in e], ["%.2e" % x for x in floor]))
+        assert all(a <= t for a, t in zip(e, tol))

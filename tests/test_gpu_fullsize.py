@@ -2,15 +2,17 @@
 benchmark times (batched FP32 bulk with the cached autotuner choice): the
 residual and one pseudo-time iteration of the 32-block mixed batch (about
 8 M cell-snapshots) and of the 1024x512 N_H = 4 airfoil, element by element
-against the FP64 oracle.  FP64 batched at 1024x512 as well.
+against the FP64 oracle; the FP64 batched and per-block plain paths (the
+latter is the baseline the benchmark compares with) at both sizes too.
 
-Where the residual is small against the face fluxes (here |R*| is about
-2e-3 of sum |F||S| at the 1024x512 initial state), FP64 rounding in either
-implementation is amplified by that cancellation: both GPU FP64 paths (the
-batched perturbation form and the per-block plain form, which share only
-the metric kernels) differ from the oracle by the same 3.8e-12 relative,
-1e-14 of the flux scale.  The FP64 criterion is then applied against the
-flux scale, as for FP32 when |R*| < 1e-2 |F||S|."""
+FP64 tolerance: 1e-12 per variable, or four times the residual's FP64
+rounding floor where that is larger (parity_util.fp64_floor: the relative
+change of the oracle's own residual when its node coordinates and state
+move by one unit in the last place).  At the 1024x512 initial state the
+residual is about 2e-3 of the face fluxes that form it, and the floor of
+the energy residual is 3.0e-12 (momentum 1.6e-12): a correct FP64
+evaluation that rounds its metrics differently lands that far from the
+oracle, so 1e-12 is below what the problem allows."""
 import os
 
 import pytest
@@ -18,6 +20,7 @@ import torch
 
 from oracle import hb_oracle as O
 from paper_1304_7654_amd import hb, synth
+from parity_util import fp64_floor, fp64_tolerance, per_var_errors
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -29,38 +32,22 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def flux_scale(blocks, q, flow, solver):
-    """Per variable, the 2-norm over cells of |F_i+1| + |F_i| + |G_j+1| + |G_j|
-    (the face fluxes whose differences form R)."""
-    out = [0.0] * 4
-    for b, qb in zip(blocks, O.split(blocks, q)):
-        FI, FJ = O.face_fluxes(b, qb, flow, solver)
-        s = (FI[..., :, 1:].abs() + FI[..., :, :-1].abs() + FJ[..., 1:, :].abs()
-             + FJ[..., :-1, :].abs())
-        for v in range(4):
-            out[v] += float((s[:, v] ** 2).sum())
-    return [x ** 0.5 for x in out]
-
-
-def per_var_rel(blocks, x, ref):
-    xs, rs = O.split(blocks, x), O.split(blocks, ref)
-    out = []
-    for v in range(4):
-        num = sum(float(((a[:, v] - b[:, v]) ** 2).sum()) for a, b in zip(xs, rs))
-        den = sum(float((b[:, v] ** 2).sum()) for b in rs)
-        out.append((num / den) ** 0.5)
-    return max(out)
-
-
-@pytest.mark.parametrize("name,prec", [("batch32_mixed", 1), ("naca1024x512_nh4", 1),
-                                       ("naca1024x512_nh4", 0)])
-def test_full_size_residual_and_iteration(name, prec):
-    _say("full size", name, "precision", prec)
+@pytest.mark.parametrize("name,prec,batched", [("batch32_mixed", 1, 1),
+                                               ("naca1024x512_nh4", 1, 1),
+                                               ("naca1024x512_nh4", 0, 1),
+                                               ("naca1024x512_nh4", 0, 0),
+                                               ("batch32_mixed", 0, 1),
+                                               ("batch32_mixed", 0, 0)])
+def test_full_size_residual_and_iteration(name, prec, batched):
+    """FP32 bulk: residual, update and norm within 1e-5 per variable.  FP64
+    (batched and per-block plain): residual within the FP64 tolerance,
+    update within 1e-10, norm within 1e-12."""
+    _say("full size", name, "precision", prec, "batched", batched)
     torch.set_num_threads(min(16, os.cpu_count() or 1))
     p = synth.make_problem(name)
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=1)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     if prec == 1:
         t = g.autotune(q.to(DEV), CACHE)
         _say("  tuning", t)
@@ -71,24 +58,22 @@ def test_full_size_residual_and_iteration(name, prec):
     g.rk_iterate(q1, 1, n1)
     torch.cuda.synchronize()
     assert g.status() == hb.HB_OK
-    ref = O.residual_all(blocks, q, flow, solver)
-    er = per_var_rel(blocks, r, ref)
-    _say("  residual rel (max over variables)", er)
+    if prec == 1:
+        ref = O.residual_all(blocks, q, flow, solver)
+        er = per_var_errors(blocks, r, ref)
+        tol = [1e-5] * 4
+    else:
+        floor, ref = fp64_floor(blocks, q, flow, solver)
+        er = per_var_errors(blocks, r, ref)
+        tol = fp64_tolerance(floor)
+        _say("  FP64 rounding floor per variable", floor)
+    _say("  residual rel per variable", er, "tolerance", tol)
     qref, nref = O.rk_iterate(blocks, q, flow, solver, 1)
-    eq = per_var_rel(blocks, q1.cpu() - q, qref - q)
+    eq = max(per_var_errors(blocks, q1.cpu() - q, qref - q))
     en = abs(float(n1[0]) - float(nref[0])) / float(nref[0])
     _say("  iteration: update rel", eq, "norm rel", en)
+    assert all(e <= t for e, t in zip(er, tol))
     if prec == 1:
-        assert er <= 1e-5 and eq <= 1e-5 and en <= 1e-5
+        assert eq <= 1e-5 and en <= 1e-5
     else:
-        assert en <= 1e-12
-        if er > 1e-12:
-            sc = flux_scale(blocks, q, flow, solver)
-            xs, rs = O.split(blocks, r), O.split(blocks, ref)
-            ef = max((sum(float(((a[:, v] - b[:, v]) ** 2).sum()) for a, b in zip(xs, rs)) ** 0.5)
-                     / sc[v] for v in range(4))
-            small = max((sum(float((b[:, v] ** 2).sum()) for b in rs) ** 0.5) / sc[v]
-                        for v in range(4))
-            _say("  |R*| / flux scale", small, "error / flux scale", ef)
-            assert small < 1e-2 and ef <= 1e-13
-        assert eq <= 1e-10
+        assert eq <= 1e-10 and en <= 1e-12
