@@ -317,6 +317,21 @@ int hb_save_solution(hb_grid *g, const double *q, const char *prefix, void *stre
  * Allocates three state-size scratch buffers on the first call. */
 int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream);
 
+/* hb_td_march for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same march, bit for bit, with its three state-size scratch arrays
+ * (residual, stage accumulator, stage state) taken from a static device
+ * array of 3 x 2^21 doubles (48 MiB) that each GPU the library runs on
+ * holds until the process ends, instead of buffers allocated on the first
+ * call.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); the grid's own buffers come from hb_grid_create.
+ * HB_ERR_ARG when the state exceeds 2^21 doubles (a 1024 x 512 block with
+ * n_harm = 0 fits exactly), besides hb_td_march's own checks.  Every call on one GPU shares that GPU's array and may leave any
+ * contents in it: calls that overlap on one GPU (several streams or host
+ * threads) race and must be serialised by the caller. */
+int hb_td_march_noalloc(hb_grid *g, double *q, double t0, double dt, int32_t n_steps,
+                        void *stream);
+
 /* Autotune the batched stage kernel (the paper's per-block work, batched
  * over blocks of uneven size and N_H in one launch per Runge-Kutta step,
  * §MPI Optimisations): with cache_path (may be NULL) holding an entry for

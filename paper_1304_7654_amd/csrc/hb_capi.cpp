@@ -561,6 +561,17 @@ int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, vo
     return launch_td_march(g, q, t0, dt, n_steps, (hipStream_t)stream);
 }
 
+int hb_td_march_noalloc(hb_grid *g, double *q, double t0, double dt, int32_t n_steps,
+                        void *stream) {
+    g_err.clear();
+    if (!g || !q) return fail(HB_ERR_ARG, "NULL argument");
+    if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t0))
+        return fail(HB_ERR_ARG, "need n_steps >= 0, finite t0 and dt > 0");
+    for (const BlockDesc &B : g->blk)
+        if (B.nh != 0) return fail(HB_ERR_UNSUPPORTED, "the time-domain march needs n_harm = 0 in every block");
+    return launch_td_march_noalloc(g, q, t0, dt, n_steps, (hipStream_t)stream);
+}
+
 int hb_autotune(hb_grid *g, const double *q, const char *cache_path, int32_t force,
                 hb_tuning *out, void *stream) {
     g_err.clear();

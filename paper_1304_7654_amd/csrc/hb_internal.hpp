@@ -224,6 +224,8 @@ int io_load(hb_grid *g, double *q, int64_t *iteration, const char *path, hipStre
 int io_save_solution(hb_grid *g, const double *q, const char *prefix, hipStream_t s);
 // td.hip
 int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s);
+int launch_td_march_noalloc(hb_grid *g, double *q, double t0, double dt, int n_steps,
+                            hipStream_t s);
 // tune.cpp
 int tune_get(const hb_grid *g, hb_tuning *t);
 int tune_set(hb_grid *g, const hb_tuning *t);

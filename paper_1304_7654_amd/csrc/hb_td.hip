@@ -12,10 +12,48 @@
 // FP64 or FP32 bulk); the stage combinations are FP64.  On a moving grid
 // (plain path) the motion table is set to the rigid motion at each stage
 // time, as the far field is, and the cell areas stay constant.
+#include <mutex>
+
 #include "hb_device.hpp"
 
 namespace hb {
 namespace {
+
+// Scratch of the allocation-free march (hb_td_march_noalloc): the residual,
+// the stage accumulator and the stage state, three state-size arrays, in a
+// file-scope device array that each GPU holds for the life of the process.
+// In host code `scratch` names a host-side stand-in, never the device
+// memory: host code uses only the address hipGetSymbolAddress returns for
+// the device (scratch_address below).  Every call on one GPU shares that
+// GPU's array, so calls that overlap on one GPU race.
+constexpr int64_t kTdScratchDoubles = 3 * ((int64_t)1 << 21);   // 48 MiB
+static __device__ __align__(256) double scratch[kTdScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
+
+// device address of `scratch` on device `dev`, looked up once per device
+// with that device current
+int scratch_address(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HB_ERR_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        int cur = 0;
+        int rc = check_hip(hipGetDevice(&cur), "hipGetDevice");
+        if (!rc && cur != dev) rc = check_hip(hipSetDevice(dev), "hipSetDevice");
+        void *p = nullptr;
+        if (!rc) rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (cur != dev) {
+            const int rc2 = check_hip(hipSetDevice(cur), "hipSetDevice");
+            rc = rc ? rc : rc2;
+        }
+        if (rc) return rc;
+        g_scratch_addr[dev] = (double *)p;
+    }
+    *out = g_scratch_addr[dev];
+    return HB_OK;
+}
 
 constexpr int kBS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
@@ -94,15 +132,9 @@ int residual_any(hb_grid *g, const double *q, double *r, hipStream_t s) {
     return g->solver.batched ? fused_residual(g, q, r, s) : plain_residual(g, q, r, s);
 }
 
-}  // namespace
-
-int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s) {
-    if (!g->td_r_d) {
-        int rc = check_hip(hipMalloc((void **)&g->td_r_d, sizeof(double) * g->n_state), "td alloc");
-        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_acc_d, sizeof(double) * g->n_state), "td alloc");
-        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_qs_d, sizeof(double) * g->n_state), "td alloc");
-        if (rc) return rc;
-    }
+// the march with caller-chosen scratch: r, acc, qs of n_state doubles each
+int td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, double *r, double *acc,
+             double *qs, hipStream_t s) {
     const double omega = 2.0 * g->flow.k_red * g->flow.mach / g->flow.l_ref;
     const double c[4] = {0.0, 0.5, 0.5, 1.0};
     int rc = HB_OK;
@@ -112,11 +144,11 @@ int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hi
             const double ts = t + c[st] * dt;
             rc = set_far_field(g, g->flow.alpha0 + g->flow.alpha_amp * sin(omega * ts), s);
             if (!rc && g->motion.tab) rc = set_motion_at(g, omega, ts, s);
-            rc = rc ? rc : residual_any(g, st == 0 ? q : g->td_qs_d, g->td_r_d, s);
+            rc = rc ? rc : residual_any(g, st == 0 ? q : qs, r, s);
             for (int b = 0; b < g->nblocks && !rc; ++b) {
                 const BlockDesc &B = g->blk[b];
                 hipLaunchKernelGGL(k_td_stage, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d,
-                                   b, q, g->td_r_d, g->td_acc_d, g->td_qs_d, g->V_d, st, dt);
+                                   b, q, r, acc, qs, g->V_d, st, dt);
             }
         }
     }
@@ -125,6 +157,30 @@ int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hi
     if (!rc2 && g->motion.tab) rc2 = set_motion_at(g, omega, 0.0, s);
     rc = rc ? rc : rc2;
     return rc ? rc : check_hip(hipGetLastError(), "td launch");
+}
+
+}  // namespace
+
+int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s) {
+    if (!g->td_r_d) {
+        int rc = check_hip(hipMalloc((void **)&g->td_r_d, sizeof(double) * g->n_state), "td alloc");
+        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_acc_d, sizeof(double) * g->n_state), "td alloc");
+        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_qs_d, sizeof(double) * g->n_state), "td alloc");
+        if (rc) return rc;
+    }
+    return td_march(g, q, t0, dt, n_steps, g->td_r_d, g->td_acc_d, g->td_qs_d, s);
+}
+
+int launch_td_march_noalloc(hb_grid *g, double *q, double t0, double dt, int n_steps,
+                            hipStream_t s) {
+    if (3 * g->n_state > kTdScratchDoubles)
+        return fail(HB_ERR_ARG, "hb_td_march_noalloc: the state (" + std::to_string(g->n_state) +
+                                    " doubles) exceeds the static scratch of " +
+                                    std::to_string(kTdScratchDoubles / 3) + " doubles per state copy");
+    double *base = nullptr;
+    const int rc = scratch_address(g->device, &base);
+    if (rc) return rc;
+    return td_march(g, q, t0, dt, n_steps, base, base + g->n_state, base + 2 * g->n_state, s);
 }
 
 }  // namespace hb

@@ -22,7 +22,7 @@ HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORT
 HB_FP64, HB_FP32_BULK = 0, 1
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_save_state", "hb_load_state", "hb_save_solution", "hb_autotune", "hb_set_tuning",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_td_march_noalloc", "hb_save_state", "hb_load_state", "hb_save_solution", "hb_autotune", "hb_set_tuning",
            "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_set_motion", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
     L.hb_forces_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hb_adjoint_iterate.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.hb_td_march.argtypes = [vp, vp, dp, dp, i32, vp]
+    L.hb_td_march_noalloc.argtypes = [vp, vp, dp, dp, i32, vp]
     L.hb_save_state.argtypes = [vp, vp, i64, ctypes.c_char_p, vp]
     L.hb_load_state.argtypes = [vp, vp, ctypes.POINTER(i64), ctypes.c_char_p, vp]
     L.hb_save_solution.argtypes = [vp, vp, ctypes.c_char_p, vp]
@@ -270,6 +271,13 @@ class Grid:
         in place on q (grids with n_harm = 0)."""
         _check(lib().hb_td_march(self.h, _ptr(q, self.n_state, "q"), float(t0), float(dt),
                                  int(n_steps), _stream()))
+        return q
+
+    def td_march_noalloc(self, q: torch.Tensor, t0: float, dt: float, n_steps: int):
+        """td_march without any device allocation (static per-device scratch
+        of at most 2^21 doubles per state copy)."""
+        _check(lib().hb_td_march_noalloc(self.h, _ptr(q, self.n_state, "q"), float(t0),
+                                         float(dt), int(n_steps), _stream()))
         return q
 
     def autotune(self, q: torch.Tensor, cache_path: Optional[str] = None, force: bool = False):
