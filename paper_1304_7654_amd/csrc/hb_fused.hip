@@ -371,19 +371,41 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             }
             __syncthreads();
             // per var v and 16-cell group cb: the 16x16 block (cells x n) =
-            // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4)
+            // Q^T[cells x m] * D^T[m x n], K = m in steps of 4 (v_mfma 16x16x4).
+            // Wave w takes groups w, w + 4, ..., kBatch at a time: the operands
+            // of the batch are read from LDS first and their MFMA chains then
+            // interleave, so that the wave waits for LDS once per batch
+            // rather than before every MFMA.
             const int lane = tid & 63, wave = tid >> 6;
             const int row = lane & 15, kq = lane >> 4;
             const int KS = (ns + 3) / 4;            // <= 3
-            for (int grp = wave; grp < 4 * (kThreads / 16); grp += kThreads / 64) {
-                const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
-                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            constexpr int kGroups = 4 * (kThreads / 16);          // (v, cb) groups
+            constexpr int kPerWave = kGroups / (kThreads / 64);
+            constexpr int kBatch = 2;                              // groups per LDS wait
+#pragma unroll 1
+            for (int k = 0; k < kPerWave; k += kBatch) {
+                float av[kBatch][3];
+#pragma unroll
+                for (int bq = 0; bq < kBatch; ++bq) {
+                    const int grp = wave + (kThreads / 64) * (k + bq);
+                    const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
+#pragma unroll
+                    for (int s = 0; s < 3; ++s) {
+                        const int m = 4 * s + kq;
+                        const int mc = m < ns ? m : ns - 1;        // in range; zeroed below
+                        const float x = DQs[(mc * 4 + v) * kDqS + cb * 16 + row];
+                        av[bq][s] = m < ns ? x : 0.0f;
+                    }
+                }
+                floatx4 acc[kBatch];
+#pragma unroll
+                for (int bq = 0; bq < kBatch; ++bq) acc[bq] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
                     if (s < KS) {
-                        const int m = 4 * s + kq;
-                        const float av = (m < ns) ? DQs[(m * 4 + v) * kDqS + cb * 16 + row] : 0.0f;
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bD[s], acc, 0, 0, 0);
+#pragma unroll
+                        for (int bq = 0; bq < kBatch; ++bq)
+                            acc[bq] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bq][s], bD[s], acc[bq], 0, 0, 0);
                     }
                 }
                 // lane holds (cell cb*16 + 4 kq + r, n = row); written in
@@ -391,8 +413,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 // every read feeds the MFMAs before the results exist
                 if (row < ns) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        DQs[(row * 4 + v) * kDqS + cb * 16 + 4 * kq + r] = acc[r];
+                    for (int bq = 0; bq < kBatch; ++bq) {
+                        const int grp = wave + (kThreads / 64) * (k + bq);
+                        const int v = grp / (kThreads / 16), cb = grp % (kThreads / 16);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            DQs[(row * 4 + v) * kDqS + cb * 16 + 4 * kq + r] = acc[bq][r];
+                    }
                 }
             }
             // the first barrier of the snapshot loop orders these writes
