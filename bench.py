@@ -194,6 +194,31 @@ def plain_leg(torch, hb, problem, q0, steps, motion=None):
                          "design_gbs": dbytes / stage_s / 1e9}}
 
 
+def moving_leg(torch, hb, problem, q0, steps, tuning, motion):
+    """The product path (FP32 bulk, batched fused kernel) on the rigidly
+    heaving and pitching grid, with the fixed-grid run's tuning: throughput
+    with loads every iteration, and the mean stage launch time from HIP
+    events around every stage (on the launch stream)."""
+    cs = problem.cell_snapshots
+    stages = len(problem.solver.rk_alpha)
+    g = hb.Grid(problem.blocks, problem.flow, problem.solver, precision=1, batched=1)
+    g.set_tuning(tuning["tile_i"], tuning["wg_per_cu"], tuning["xcd_order"], tuning["tile_order"])
+    g.set_motion(**motion)
+    q = q0.clone()
+    time_steps(torch, g, q, 1)
+    q = q0.clone()
+    t, _ = time_steps(torch, g, q, steps)
+    assert g.status() == hb.HB_OK, "non-finite state in the moving-grid run"
+    q = q0.clone()
+    g.profile_stages(True)
+    time_steps(torch, g, q, steps, forces=False)
+    ms, n = g.stage_stats()
+    g.profile_stages(False)
+    g.close()
+    return {"value": cs * stages * steps / t, "ms_per_step": 1000.0 * t / steps,
+            "avg_stage_ms": ms / n, "path": "fused FP32 bulk, batched", "motion": motion}
+
+
 def stream_probe(torch, mib=1024, reps=10):
     """Device copy bandwidth (read + write bytes per second) of a plain
     torch copy of `mib` MiB, the practical HBM peak the traffic is also set
@@ -344,7 +369,8 @@ def main():
     ap.add_argument("--moving-steps", type=int, default=5,
                     help="iterations of the moving-grid leg (0 skips it)")
     ap.add_argument("--moving-only", action="store_true",
-                    help="run only the moving-grid leg (for a kernel profile of it)")
+                    help="run only the moving-grid leg (for a kernel profile of it; "
+                         "needs --tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/primal timing")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -383,7 +409,12 @@ def main():
         del src, dst
 
     if args.moving_only:
-        print(json.dumps({"moving_grid": plain_leg(torch, hb, problem, q0, args.moving_steps, MOTION)}))
+        if not args.tuning:
+            sys.exit("bench.py: --moving-only needs --tuning")
+        tu = dict(zip(("tile_i", "wg_per_cu", "xcd_order", "tile_order"),
+                      (int(x) for x in args.tuning.split(","))))
+        print(json.dumps({"moving_grid": moving_leg(torch, hb, problem, q0, args.moving_steps, tu,
+                                                    MOTION)}))
         return
 
     # ---- FP32-bulk batched (the product path) ------------------------------
@@ -428,13 +459,11 @@ def main():
         fused = {"value": cs * stages * args.plain_steps / tf,
                  "ms_per_step": 1000.0 * tf / args.plain_steps}
         gf.close()
-    # ---- the plain FP64 path on the rigidly heaving and pitching grid ------
+    # ---- the product path on the rigidly heaving and pitching grid --------
     moving = None
     if args.moving_steps > 0:
-        moving = plain_leg(torch, hb, problem, q0, args.moving_steps, MOTION)
-        moving["motion"] = MOTION
-        if plain:
-            moving["vs_fixed_grid_plain"] = moving["value"] / plain["value"]
+        moving = moving_leg(torch, hb, problem, q0, args.moving_steps, tuning, MOTION)
+        moving["vs_fixed_grid"] = moving["value"] / value
 
     out = {
         "metric": METRIC,

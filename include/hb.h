@@ -361,12 +361,14 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
 
 /* Set (m non-NULL with a non-zero amplitude) or clear (NULL, or both
  * amplitudes zero) the rigid grid motion described at hb_motion.  It then
- * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march.
- * HB_ERR_UNSUPPORTED for batched grids and for blocks with walls on an i
- * side; while a motion is set the adjoints and hb_set_xy return
- * HB_ERR_UNSUPPORTED.  Across a cut, the wall image of a corner ghost takes
- * the glued block's wall face.  HB_ERR_ARG for non-finite values.
- * Synchronises the current device. */
+ * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march, on the
+ * per-block and on the batched path (FP64 and FP32 bulk).
+ * HB_ERR_UNSUPPORTED for blocks with walls on an i side; while a motion is
+ * set the adjoints and hb_set_xy return HB_ERR_UNSUPPORTED.  Across a cut,
+ * the wall image of a corner ghost takes the glued block's wall face.
+ * HB_ERR_ARG for non-finite values.  Drops the batched path's captured
+ * iterations (the next hb_rk_iterate captures them again).  Synchronises
+ * the current device. */
 int hb_set_motion(hb_grid *g, const hb_motion *m);
 
 /* Synchronise and return HB_ERR_NONFINITE if any iteration since the last

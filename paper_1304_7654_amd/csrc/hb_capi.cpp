@@ -81,6 +81,7 @@ void free_all(hb_grid *g) {
     dfree(g->body_off_d); dfree(g->body_ns_d);
     dfree(g->tiles_d);
     dfree(g->gtab_d);
+    dfree(g->wtab_d);
     dfree(g->ffc_d);
     dfree(g->cpart_d);
     dfree(g->geo_d);
@@ -622,10 +623,10 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
     int rc = check_hip(hipDeviceSynchronize(), "sync");
     if (rc) return rc;
     if (!m || (m->pitch_amp == 0.0 && m->heave_amp == 0.0)) {
+        fused_drop_graph(g);     // a captured iteration holds the moving-grid kernels
         g->motion = Motion{nullptr, 0.0, 0.0};
         return HB_OK;
     }
-    if (g->solver.batched) return fail(HB_ERR_UNSUPPORTED, "a moving grid needs batched = 0");
     for (const BlockDesc &B : g->blk)
         if (B.bc[0] == HB_BC_WALL || B.bc[1] == HB_BC_WALL)
             return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides");
@@ -650,6 +651,7 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
     rc = check_hip(hipMemcpy(g->mot_d, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice),
                    "motion upload");
     if (rc) return rc;
+    fused_drop_graph(g);         // a captured iteration holds the old kernels and pivot
     g->motion = Motion{g->mot_d, m->x_pivot, m->y_pivot};
     g->motion_par = *m;
     return HB_OK;

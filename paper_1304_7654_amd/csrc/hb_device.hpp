@@ -404,10 +404,14 @@ __device__ __forceinline__ void viscous_flux_g(const UVT<T> &L, const UVT<T> &R,
 // is regrouped around s14 = b1 + b4 and k = c~ (b4 - b1) - bs (dq_n):
 //   d0 = s14 + b2,  d_u = u~ d0 + n_x k + bs du,  d_v = v~ d0 + n_y k + bs dv,
 //   d_E = h~ s14 + q~_n k + b2 |u~|^2 / 2 + bs (u~ du + v~ dv).
-template <class T>
+// MV: a face moving with normal speed vgn (x_t . n): the eigenvalues are
+// taken relative to the face, and -vgn (dU_L + dU_R) (conserved
+// perturbations; the free-stream part -vgn 2 U_inf sums to zero around a
+// cell, since the midpoint face speeds of a rigid motion do) joins the flux.
+template <class T, bool MV = false>
 __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, const FS<T> &f,
                                                 T nx, T ny, T ha, T g, T delta_frac, T h2d,
-                                                T out[4]) {
+                                                T out[4], T vgn = T(0)) {
     const T gg = f.gg;
     const T rl = T(1) + L.r, rr = T(1) + R.r;
     const T irl = frcp(rl), irr = frcp(rr);
@@ -433,8 +437,9 @@ __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, 
     const T a1 = (dp - rt * ct * dqn) * T(0.5) * ic2;
     const T a4 = (dp + rt * ct * dqn) * T(0.5) * ic2;
     const T a2 = dr - dp * ic2;
-    T l1 = fabs(qnt - ct), l4 = fabs(qnt + ct);
-    const T l2 = fabs(qnt);
+    const T qrel = MV ? qnt - vgn : qnt;
+    T l1 = fabs(qrel - ct), l4 = fabs(qrel + ct);
+    const T l2 = fabs(qrel);
     if (delta_frac > T(0)) {
         const T d = delta_frac * ct;
         const T i2d = h2d * ct * ic2;           // 1 / (2 d)
@@ -456,10 +461,23 @@ __device__ __forceinline__ void roe_flux_pert_n(const W4<T> &L, const W4<T> &R, 
     const T f1 = dml * ul + dmr * ur + qni * (L.u + R.u) + (L.p + R.p) * nx;
     const T f2 = dml * vl + dmr * vr + qni * (L.v + R.v) + (L.p + R.p) * ny;
     const T f3 = dml * hl + dmr * hr + qni * (dhl + dhr);
-    out[0] = ha * (f0 - d0);
-    out[1] = ha * (f1 - d1);
-    out[2] = ha * (f2 - d2);
-    out[3] = ha * (f3 - d3);
+    if constexpr (MV) {
+        // conserved perturbations: d(rho u) = d rho u + du (rho_inf = 1),
+        // d(rho E) = d(rho H) - dp = d rho h_inf + rho dh - dp
+        const T e0 = L.r + R.r;
+        const T e1 = L.r * ul + L.u + R.r * ur + R.u;
+        const T e2 = L.r * vl + L.v + R.r * vr + R.v;
+        const T e3 = (L.r + R.r) * f.h + rl * dhl + rr * dhr - (L.p + R.p);
+        out[0] = ha * (f0 - d0 - vgn * e0);
+        out[1] = ha * (f1 - d1 - vgn * e1);
+        out[2] = ha * (f2 - d2 - vgn * e2);
+        out[3] = ha * (f3 - d3 - vgn * e3);
+    } else {
+        out[0] = ha * (f0 - d0);
+        out[1] = ha * (f1 - d1);
+        out[2] = ha * (f2 - d2);
+        out[3] = ha * (f3 - d3);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -56,6 +56,17 @@ struct FusedArgs {
     int dq_bytes;          // FP32: bytes of the LDS HB-source area before the scratch
     int xcd;               // XCD-aware renumbering: tiles per XCD chunk (0: off)
     T h2d;                 // 1 / (2 delta_frac) (Harten width), 0 without the fix
+    // rigid grid motion (the moving-grid kernels only): per-snapshot table
+    // of kMotionW doubles {cos theta, sin theta, theta_dot, h, h_dot, ..},
+    // the pivot, the body-frame nodes and cell centres, and per ext cell of
+    // the tiles at block sides the wall face of a moving no-slip image
+    // (index of its first node's x in xy, and the node count of that
+    // block; 0 = not a wall image)
+    const double *mot;
+    const double *xy;
+    const double *C;
+    const uint32_t *wtab;
+    double xp, yp;
 };
 
 // Row stride (floats) of the LDS HB-source array DQs[N_s][4][cells].  (A
@@ -92,9 +103,11 @@ struct TileU {
 
 // Face k of the tile (the caller has checked that it lies in the block),
 // geometry fg held in registers for the whole tile.
-template <class T, int TI, int TJ, bool IFACE>
+// MV: a moving face with normal speed vgn.
+template <class T, int TI, int TJ, bool IFACE, bool MV>
 __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T *P, const T *Nd,
-                                          T *F, int fs, const FS<T> &f, const FaceGeo<T> &fg) {
+                                          T *F, int fs, const FS<T> &f, const FaceGeo<T> &fg,
+                                          T vgn) {
     using G = Geo<TI, TJ>;
     int e0, es, nA, nB;
     if constexpr (IFACE) {
@@ -118,7 +131,7 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T 
     W4<T> L, R;
     muscl(m2, m1, p0, p1, a.eps, L, R);
     T fl[4];
-    roe_flux_pert_n(L, R, f, fg.nx, fg.ny, fg.ha, a.gamma, a.delta, a.h2d, fl);
+    roe_flux_pert_n<T, MV>(L, R, f, fg.nx, fg.ny, fg.ha, a.gamma, a.delta, a.h2d, fl, vgn);
     const UVT<T> uL{m1.u, m1.v, P[4 * G::EXT + x1]};
     const UVT<T> uR{p0.u, p0.v, P[4 * G::EXT + x2]};
     const UVT<T> na{Nd[nA], Nd[G::NOD + nA], Nd[2 * G::NOD + nA]};
@@ -134,14 +147,29 @@ __device__ __forceinline__ void face_flux(const FusedArgs<T> &a, int k, const T 
 // Scalar copy of the block descriptor fields the tile body uses.
 struct BlockU {
     int ni, nj, snap_off, d_off;
-    int64_t q_off, cell_off, fi_off, fj_off;
+    int64_t q_off, cell_off, node_off, fi_off, fj_off;
     double omega_nh;
 };
 
+// Face geometry of snapshot n on a rigidly rotated grid: the body-frame
+// normal and diamond vector b turn with the grid (c, s = cos, sin theta_n);
+// |S|, g1 and b.n do not change.
+template <class T>
+__device__ __forceinline__ FaceGeo<T> rotate_geo(const FaceGeo<T> &g, T c, T s) {
+    FaceGeo<T> r = g;
+    r.nx = c * g.nx - s * g.ny;
+    r.ny = s * g.nx + c * g.ny;
+    r.mbx = c * g.mbx - s * g.mby;
+    r.mby = s * g.mbx + c * g.mby;
+    return r;
+}
+
 // NS > 0: snapshot count fixed at compile time (FP64 tiles, whose HB source
 // lives in registers); NS = 0: taken from the tile at run time (FP32 tiles:
-// one body serves every snapshot count).
-template <class T, int TI, int TJ, bool FIRST, int MODE, int NS>
+// one body serves every snapshot count).  MV: the grid moves rigidly (ALE
+// form: moving faces, moving no-slip wall images, the time step relative to
+// the grid).
+template <class T, int TI, int TJ, bool FIRST, int MODE, int NS, bool MV>
 __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, unsigned char *smem,
                           int &bad) {
     using G = Geo<TI, TJ>;
@@ -160,6 +188,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     B.d_off = uni(Bg.d_off);
     B.q_off = uni(Bg.q_off);
     B.cell_off = uni(Bg.cell_off);
+    B.node_off = MV ? uni(Bg.node_off) : 0;
     B.fi_off = uni(Bg.fi_off);
     B.fj_off = uni(Bg.fj_off);
     B.omega_nh = Bg.omega_nh;
@@ -233,6 +262,11 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     static_assert(G::NFI <= kThreads && G::NFJ <= kThreads, "one face per thread and pass");
     T rI[4] = {T(1), T(0), T(1), T(0)}, rJ[4] = {T(1), T(0), T(1), T(0)};
     bool hasI, hasJ;
+    // moving grid: body-frame midpoints of the two faces relative to the
+    // pivot (the face speed of snapshot n follows from them)
+    const int64_t nnod = (int64_t)(ni + 1) * (nj + 1);
+    const double *X = MV ? a.xy + 2 * B.node_off : nullptr;
+    T mIx = T(0), mIy = T(0), mJx = T(0), mJy = T(0);
     {
         const int fi = tid % (TI + 1), fj = tid / (TI + 1);
         const int gi = tl.i0 + fi, gj = tl.j0 + fj;
@@ -242,6 +276,11 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             const int nf = (ni + 1) * nj;
             rI[0] = ldg(tu.SI, fg); rI[1] = ldg(tu.SI + nf, fg);
             rI[2] = ldg(tu.dI, fg); rI[3] = ldg(tu.dI + nf, fg);
+            if constexpr (MV) {     // edge from node (gi, gj) to (gi, gj + 1)
+                const unsigned k0 = (unsigned)(gj * (ni + 1) + gi), k1 = k0 + (unsigned)(ni + 1);
+                mIx = (T)(0.5 * (ldg(X, k0) + ldg(X, k1)) - a.xp);
+                mIy = (T)(0.5 * (ldg(X + nnod, k0) + ldg(X + nnod, k1)) - a.yp);
+            }
         }
     }
     {
@@ -253,6 +292,39 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
             const int nf = ni * (nj + 1);
             rJ[0] = ldg(tu.SJ, fg); rJ[1] = ldg(tu.SJ + nf, fg);
             rJ[2] = ldg(tu.dJ, fg); rJ[3] = ldg(tu.dJ + nf, fg);
+            if constexpr (MV) {     // edge from node (gi, gj) to (gi + 1, gj)
+                const unsigned k0 = (unsigned)(gj * (ni + 1) + gi), k1 = k0 + 1u;
+                mJx = (T)(0.5 * (ldg(X, k0) + ldg(X, k1)) - a.xp);
+                mJy = (T)(0.5 * (ldg(X + nnod, k0) + ldg(X + nnod, k1)) - a.yp);
+            }
+        }
+    }
+    // moving grid: the cell centre relative to the pivot (time step of the
+    // first stage), and for each of this thread's ghost-extended cells that
+    // is a moving no-slip wall image, the body-frame midpoint of its wall
+    // face relative to the pivot
+    T cxr = T(0), cyr = T(0);
+    T wmx[2] = {T(0), T(0)}, wmy[2] = {T(0), T(0)};
+    bool wimg[2] = {false, false};
+    if constexpr (MV) {
+        if constexpr (FIRST && MODE != 0) {
+            const double *Cx = a.C + 2 * B.cell_off;
+            cxr = (T)(ldg(Cx, cidx) - a.xp);
+            cyr = (T)(ldg(Cx + plane, cidx) - a.yp);
+        }
+        if (tl.gtab >= 0) {
+            const uint2 *wt = reinterpret_cast<const uint2 *>(a.wtab) + tl.gtab;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (c && !has2) break;
+                const uint2 w = wt[c ? e2 : e1];
+                if (w.y != 0u) {
+                    wimg[c] = true;
+                    const double *x = a.xy + w.x, *y = x + w.y;
+                    wmx[c] = (T)(0.5 * (x[0] + x[1]) - a.xp);
+                    wmy[c] = (T)(0.5 * (y[0] + y[1]) - a.yp);
+                }
+            }
         }
     }
 
@@ -447,6 +519,12 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     if (!(MF && ns > 1)) __syncthreads();
     const FaceGeo<T> gI = face_geo<T>(rI[0], rI[1], rI[2], rI[3], a.mu, a.kappa);
     const FaceGeo<T> gJ = face_geo<T>(rJ[0], rJ[1], rJ[2], rJ[3], a.mu, a.kappa);
+    // moving grid: the rigid velocity theta_dot k x R (x0 - p) + (0, h_dot)
+    // at a face midpoint x0, dotted with the rotated normal R n, is
+    // theta_dot (k x (x0 - p)) . n + h_dot (R n)_y: the first factor is the
+    // same for every snapshot
+    const T wI = MV ? mIx * gI.ny - mIy * gI.nx : T(0);
+    const T wJ = MV ? mJx * gJ.ny - mJy * gJ.nx : T(0);
 
     // ---- C: snapshot loop -----------------------------------------------
     double nacc = 0.0;
@@ -466,6 +544,15 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 #pragma unroll
             for (int v = 0; v < 4; ++v) b0[v] = ldg(q0b + so + v * plane, cidx);
             if constexpr (!FIRST) dt = ldg(dtb, cidx);
+        }
+        // moving grid: this snapshot's rotation and rates (uniform loads)
+        T mc = T(1), ms = T(0), mthd = T(0), mhd = T(0);
+        if constexpr (MV) {
+            const double *mt = a.mot + kMotionW * (B.snap_off + n);
+            mc = (T)mt[0];
+            ms = (T)mt[1];
+            mthd = (T)mt[2];
+            mhd = (T)mt[4];
         }
         const T *fw = Tf + 8 * n;
         FS<T> f;
@@ -493,6 +580,13 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 if (smir[c]) {                  // no-slip wall image: velocity reversed
                     w.u = -w.u - T(2) * f.u;
                     w.v = -w.v - T(2) * f.v;
+                }
+                if constexpr (MV) {
+                    if (wimg[c]) {              // moving wall: u_g = 2 u_wall - u
+                        const T rx = mc * wmx[c] - ms * wmy[c], ry = ms * wmx[c] + mc * wmy[c];
+                        w.u += T(2) * (-mthd * ry);
+                        w.v += T(2) * (mthd * rx + mhd);
+                    }
                 }
                 P[e] = w.r;
                 P[G::EXT + e] = w.u;
@@ -527,8 +621,16 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
         constexpr int fjs = MF ? kDqS : G::NFMAX;
         __syncthreads();
         // C3: i-face and j-face fluxes, each face once
-        if (hasI) face_flux<T, TI, TJ, true>(a, tid, P, Nd, F, G::NFMAX, f, gI);
-        if (hasJ) face_flux<T, TI, TJ, false>(a, tid, P, Nd, FJ, fjs, f, gJ);
+        if constexpr (MV) {
+            const FaceGeo<T> hI = rotate_geo(gI, mc, ms), hJ = rotate_geo(gJ, mc, ms);
+            if (hasI) face_flux<T, TI, TJ, true, true>(a, tid, P, Nd, F, G::NFMAX, f, hI,
+                                                       mthd * wI + mhd * hI.ny);
+            if (hasJ) face_flux<T, TI, TJ, false, true>(a, tid, P, Nd, FJ, fjs, f, hJ,
+                                                        mthd * wJ + mhd * hJ.ny);
+        } else {
+            if (hasI) face_flux<T, TI, TJ, true, false>(a, tid, P, Nd, F, G::NFMAX, f, gI, T(0));
+            if (hasJ) face_flux<T, TI, TJ, false, false>(a, tid, P, Nd, FJ, fjs, f, gJ, T(0));
+        }
         __syncthreads();
         // C4: cell residual and update
         if (valid) {
@@ -547,8 +649,19 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
                 if constexpr (FIRST) {
                     const W4<T> wp = pert_prim<T>((T)(b0[0] - fq[0]), (T)(b0[1] - fq[1]),
                                                   (T)(b0[2] - fq[2]), (T)(b0[3] - fq[3]), f.u, f.v, gm1);
-                    const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
-                    dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl, (T)B.omega_nh);
+                    if constexpr (MV) {
+                        // the snapshot's mean normals; velocity relative to
+                        // the grid at the cell centre
+                        const T rx = mc * cxr - ms * cyr, ry = ms * cxr + mc * cyr;
+                        const W4<T> wf{T(1) + wp.r, f.u + wp.u + mthd * ry,
+                                       f.v + wp.v - (mthd * rx + mhd), f.p + wp.p};
+                        dt = local_dt<T>(wf, mc * sxi - ms * syi, ms * sxi + mc * syi,
+                                         mc * sxj - ms * syj, ms * sxj + mc * syj, vol, g, a.mu_pr,
+                                         a.cfl, (T)B.omega_nh);
+                    } else {
+                        const W4<T> wf{T(1) + wp.r, f.u + wp.u, f.v + wp.v, f.p + wp.p};
+                        dt = local_dt<T>(wf, sxi, syi, sxj, syj, vol, g, a.mu_pr, a.cfl, (T)B.omega_nh);
+                    }
                     stg(dtb, cidx, dt);
                 }
                 const double fac = a.alpha * (double)dt * ivol;
@@ -595,7 +708,7 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
     }
 }
 
-template <class T, int TI, int TJ, bool FIRST, int MODE>
+template <class T, int TI, int TJ, bool FIRST, int MODE, bool MV>
 __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its
@@ -617,14 +730,14 @@ __global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
         const Tile tg = a.tiles[t];
         const Tile tl{uni(tg.blk), uni(tg.i0), uni(tg.j0), uni(tg.ns), uni(tg.gtab)};
         if constexpr (std::is_same<T, float>::value) {
-            tile_body<T, TI, TJ, FIRST, MODE, 0>(a, tl, t, smem, bad);
+            tile_body<T, TI, TJ, FIRST, MODE, 0, MV>(a, tl, t, smem, bad);
         } else {
             switch (tl.ns) {
-                case 1: tile_body<T, TI, TJ, FIRST, MODE, 1>(a, tl, t, smem, bad); break;
-                case 3: tile_body<T, TI, TJ, FIRST, MODE, 3>(a, tl, t, smem, bad); break;
-                case 5: tile_body<T, TI, TJ, FIRST, MODE, 5>(a, tl, t, smem, bad); break;
-                case 7: tile_body<T, TI, TJ, FIRST, MODE, 7>(a, tl, t, smem, bad); break;
-                default: tile_body<T, TI, TJ, FIRST, MODE, 9>(a, tl, t, smem, bad); break;
+                case 1: tile_body<T, TI, TJ, FIRST, MODE, 1, MV>(a, tl, t, smem, bad); break;
+                case 3: tile_body<T, TI, TJ, FIRST, MODE, 3, MV>(a, tl, t, smem, bad); break;
+                case 5: tile_body<T, TI, TJ, FIRST, MODE, 5, MV>(a, tl, t, smem, bad); break;
+                case 7: tile_body<T, TI, TJ, FIRST, MODE, 7, MV>(a, tl, t, smem, bad); break;
+                default: tile_body<T, TI, TJ, FIRST, MODE, 9, MV>(a, tl, t, smem, bad); break;
             }
         }
         __syncthreads();
@@ -667,6 +780,8 @@ FusedArgs<float> make_args<float>(hb_grid *g) {
     a.mu_pr = (float)(c.mu / c.prandtl); a.cfl = (float)c.cfl; a.delta = (float)c.delta_frac;
     a.eps = (float)c.eps;
     a.h2d = c.delta_frac > 0.0 ? (float)(0.5 / c.delta_frac) : 0.0f;
+    a.mot = g->motion.tab; a.xp = g->motion.xp; a.yp = g->motion.yp;
+    a.xy = g->xy_d; a.C = g->C_d; a.wtab = g->wtab_d;
     return a;
 }
 
@@ -681,6 +796,8 @@ FusedArgs<double> make_args<double>(hb_grid *g) {
     a.gamma = c.gamma; a.mu = c.mu; a.kappa = c.kappa; a.mu_pr = c.mu / c.prandtl; a.cfl = c.cfl;
     a.delta = c.delta_frac; a.eps = c.eps;
     a.h2d = c.delta_frac > 0.0 ? 0.5 / c.delta_frac : 0.0;
+    a.mot = g->motion.tab; a.xp = g->motion.xp; a.yp = g->motion.yp;
+    a.xy = g->xy_d; a.C = g->C_d; a.wtab = g->wtab_d;
     return a;
 }
 
@@ -693,12 +810,12 @@ int ns_max(const hb_grid *g) {
 // tiles per XCD chunk of a one-workgroup-per-tile grid with the XCD renumbering
 constexpr int kXcdChunk = 32;
 
-template <class T, int TI, int TJ, bool FIRST, int MODE>
+template <class T, int TI, int TJ, bool FIRST, int MODE, bool MV>
 int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
     const size_t sm = smem_bytes<T, TI, TJ>(ns_max(g));
     FusedArgs<T> b = a;
     b.dq_bytes = (int)dq_bytes<T, TI, TJ>(ns_max(g));
-    auto kern = k_fused<T, TI, TJ, FIRST, MODE>;
+    auto kern = k_fused<T, TI, TJ, FIRST, MODE, MV>;
     // persistent grid: as many workgroups as can be resident at once
     static int cached_occ[2][2] = {{0, 0}, {0, 0}};
     static size_t cached_sm[2][2] = {{0, 0}, {0, 0}};
@@ -732,8 +849,12 @@ int launch_t(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
 
 template <class T, bool FIRST, int MODE>
 int launch_shape(hb_grid *g, const FusedArgs<T> &a, hipStream_t s) {
-    if (g->tile_ti == 32) return launch_t<T, 32, 8, FIRST, MODE>(g, a, s);
-    return launch_t<T, 16, 16, FIRST, MODE>(g, a, s);
+    if (a.mot) {
+        if (g->tile_ti == 32) return launch_t<T, 32, 8, FIRST, MODE, true>(g, a, s);
+        return launch_t<T, 16, 16, FIRST, MODE, true>(g, a, s);
+    }
+    if (g->tile_ti == 32) return launch_t<T, 32, 8, FIRST, MODE, false>(g, a, s);
+    return launch_t<T, 16, 16, FIRST, MODE, false>(g, a, s);
 }
 
 // one stage: k = stage index, input/output buffers chosen by the caller
@@ -864,7 +985,7 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
     // are far field
     const int ti = tile_i, oj = kThreads / tile_i - 1;
     const int we = ti + 4, ext = (ti + 4) * (oj + 4);
-    std::vector<uint32_t> tab;
+    std::vector<uint32_t> tab, wtab;
     for (Tile &t : tiles) {
         const BlockDesc &K = g->blk[t.blk];
         if (t.i0 >= 2 && t.i0 + ti + 2 <= K.ni && t.j0 >= 2 && t.j0 + oj + 2 <= K.nj) continue;
@@ -883,8 +1004,22 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
             }
             tab.push_back(x);
             tab.push_back(y);
+            // moving no-slip wall image: its wall face (moving grids)
+            uint32_t wx = 0, wy = 0;
+            if (e < ext && gi < K.ni + 2 && gj < K.nj + 2) {
+                const WallFace wf = wall_face(g->blk, t.blk, gi, gj);
+                if (wf.node >= 0) {
+                    const BlockDesc &S = g->blk[wf.blk];
+                    wx = (uint32_t)(2 * S.node_off + wf.node);
+                    wy = (uint32_t)((S.ni + 1) * (S.nj + 1));
+                }
+            }
+            wtab.push_back(wx);
+            wtab.push_back(wy);
         }
     }
+    if (2 * g->n_nodes >= ((int64_t)1 << 32))
+        return fail(HB_ERR_UNSUPPORTED, "node arrays too large for the batched halo tables");
     hipDeviceProp_t prop;
     int rc = check_hip(hipGetDeviceProperties(&prop, g->device), "device properties");
     if (rc) return rc;
@@ -907,6 +1042,15 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
     if (!tab.empty())
         rc = check_hip(hipMemcpy(g->gtab_d, tab.data(), sizeof(uint32_t) * tab.size(),
                                  hipMemcpyHostToDevice), "halo table upload");
+    if (rc) return rc;
+    if (g->wtab_d) (void)hipFree(g->wtab_d);
+    g->wtab_d = nullptr;
+    rc = check_hip(hipMalloc((void **)&g->wtab_d, sizeof(uint32_t) * std::max<size_t>(2, wtab.size())),
+                   "wall table alloc");
+    if (rc) return rc;
+    if (!wtab.empty())
+        rc = check_hip(hipMemcpy(g->wtab_d, wtab.data(), sizeof(uint32_t) * wtab.size(),
+                                 hipMemcpyHostToDevice), "wall table upload");
     if (rc) return rc;
     g->tile_ti = tile_i;
     g->tile_tj = kThreads / tile_i - 1;

@@ -49,4 +49,34 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, int b, int i, int j) {
     }
 }
 
+// Moving no-slip wall image (ghost (i, j) of block b on a rigidly moving
+// grid): the node index (within the block's node arrays) of the first node
+// of the wall face whose midpoint velocity the image takes, and the block
+// owning it; {-1, ..} when the ghost is no wall image.  The same column
+// rule as the plain kernels' wall_image_motion: a ghost column takes its
+// i-periodic partner column, the glued block's column across an i cut, else
+// the nearest column.
+WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j) {
+    const BlockDesc &K = B[b];
+    int side;
+    if (j < 0) side = 2;
+    else if (j >= K.nj) side = 3;
+    else return WallFace{-1, 0};
+    const int kind = K.bc[side];
+    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return WallFace{-1, 0};
+    if (kind == HB_BC_WAKECUT && (i < K.wake || i >= K.ni - K.wake)) return WallFace{-1, 0};
+    int col = i, src = b;
+    if (i < 0) {
+        if (K.bc[0] == HB_BC_PERIODIC) col = i + K.ni;
+        else if (K.bc[0] == HB_BC_CUT) src = K.cut_blk[0], col = B[src].ni + i;
+        else col = 0;
+    } else if (i >= K.ni) {
+        if (K.bc[1] == HB_BC_PERIODIC) col = i - K.ni;
+        else if (K.bc[1] == HB_BC_CUT) src = K.cut_blk[1], col = i - K.ni;
+        else col = K.ni - 1;
+    }
+    const BlockDesc &S = B[src];
+    return WallFace{(int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col, src};
+}
+
 }  // namespace hb

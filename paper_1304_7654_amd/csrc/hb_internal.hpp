@@ -144,6 +144,10 @@ struct hb_grid {
     // entries (two per thread), each (source element index | mirror << 31,
     // source plane; plane 0 = far field)
     uint32_t *gtab_d = nullptr;
+    // the same entries for a rigidly moving grid: (index in xy_d of the x
+    // of the wall face's first node, node count of its block) for a moving
+    // no-slip wall image, (0, 0) otherwise
+    uint32_t *wtab_d = nullptr;
     int tile_ti = 16, tile_tj = 15;
     int n_cu = 0;
     // tuning of the fused path (hb_set_tuning / hb_autotune)
@@ -199,6 +203,11 @@ namespace hb {
 // ghost.cpp: host-side ghost rules
 GSrc ghost_src_i(const std::vector<BlockDesc> &B, int b, int i, int j);
 GSrc ghost_src(const std::vector<BlockDesc> &B, int b, int i, int j);
+struct WallFace {
+    int64_t node;    // first node of the wall face in block `blk`, -1: no wall image
+    int blk;
+};
+WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j);
 
 // error helpers (capi.cpp)
 int upload_snapshot_tables(hb_grid *g);

@@ -1,7 +1,10 @@
-"""GPU parity of the rigidly heaving and pitching grid (plain FP64 path,
-hb_set_motion) against the moving-grid oracle on the same seeded inputs:
-residual, pseudo-time iterations and loads, plus the entry points' refusal
-of what a moving grid does not support."""
+"""GPU parity of the rigidly heaving and pitching grid (hb_set_motion)
+against the moving-grid oracle on the same seeded inputs, on the three
+paths: the plain FP64 per-block kernels, the batched fused kernel in FP64
+and in FP32 bulk arithmetic (FP64 within 1e-12 relative per variable, FP32
+bulk within 1e-5): residual, pseudo-time iterations, loads, glued blocks and
+the time-domain march, plus the entry points' refusal of what a moving grid
+does not support."""
 import math
 import sys
 
@@ -16,6 +19,13 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 # large enough that the motion terms are a sizeable part of every flux
 MOT = dict(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_pivot=0.05)
+# (batched, precision): plain FP64, fused FP64, fused FP32 bulk
+PATHS = [(0, 0), (1, 0), (1, 1)]
+PATH_IDS = ["plain64", "fused64", "fused32"]
+
+
+def _tol(prec, fp64):
+    return fp64 if prec == 0 else 1e-5
 
 
 def _say(*a):
@@ -49,44 +59,53 @@ def _setup(name):
     return p, blocks, flow, solver, q
 
 
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("name", ["cyl_tiny", "naca_tiny", "batch_tiny"])
-def test_moving_residual(name):
-    _say("case", name, "moving-grid residual")
+def test_moving_residual(name, batched, prec):
+    _say("case", name, "moving-grid residual, batched", batched, "precision", prec)
     p, blocks, flow, solver, q = _setup(name)
     ref = M.moving_residual_all(blocks, q, flow, solver, M.OMotion(**MOT))
     fixed = O.residual_all(blocks, q, flow, solver)
     assert _rel(blocks, fixed, ref) > 1e-2          # the motion matters
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     g.set_motion(**MOT)
     r = g.residual(q.to(DEV)).cpu()
     torch.cuda.synchronize()
-    assert _rel(blocks, r, ref) <= 1e-12
-    assert _elem(blocks, r, ref) <= 1e-11
+    err = _rel(blocks, r, ref)
+    _say("  rel error", err)
+    assert err <= _tol(prec, 1e-12)
+    if prec == 0:
+        assert _elem(blocks, r, ref) <= 1e-11
 
 
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("name", ["cyl_tiny", "batch_tiny"])
-def test_moving_rk_iterate(name):
-    _say("case", name, "moving-grid RK")
+def test_moving_rk_iterate(name, batched, prec):
+    _say("case", name, "moving-grid RK, batched", batched, "precision", prec)
     p, blocks, flow, solver, q = _setup(name)
     n_it = 3
     qref, nref = M.moving_rk_iterate(blocks, q, flow, solver, M.OMotion(**MOT), n_it)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     g.set_motion(**MOT)
     qd = q.to(DEV)
     norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
     g.rk_iterate(qd, n_it, norms)
     torch.cuda.synchronize()
     assert g.status() == hb.HB_OK
-    assert _rel(blocks, qd.cpu() - q, qref - q) <= 1e-11
-    assert torch.allclose(norms.cpu(), nref, rtol=1e-12, atol=0)
+    err = _rel(blocks, qd.cpu() - q, qref - q)
+    nerr = float(((norms.cpu() - nref).abs() / nref).max())
+    _say("  state-change rel error", err, "norm rel error", nerr)
+    assert err <= _tol(prec, 1e-11)
+    assert nerr <= _tol(prec, 1e-12)
 
 
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("name", ["cyl_tiny", "naca_tiny", "batch_tiny"])
-def test_moving_forces(name):
-    _say("case", name, "moving-grid loads")
+def test_moving_forces(name, batched, prec):
+    _say("case", name, "moving-grid loads, batched", batched, "precision", prec)
     p, blocks, flow, solver, q = _setup(name)
     ref = torch.cat([c.reshape(-1) for c in M.moving_forces(blocks, q, flow, solver, M.OMotion(**MOT))])
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     g.set_motion(**MOT)
     cf = g.forces(q.to(DEV)).cpu()
     torch.cuda.synchronize()
@@ -95,14 +114,17 @@ def test_moving_forces(name):
     assert float((cf - ref).abs().max()) <= 1e-11 * float(ref.abs().max())
 
 
-def test_moving_full_size_sampled_block():
-    """The bench's moving-grid configuration (all 32 blocks of the batch, one
-    plain-path call): blocks without cuts are independent, so the smallest
-    block's residual is checked against the oracle element by element."""
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
+def test_moving_full_size_sampled_block(batched, prec):
+    """The bench's moving-grid configuration (all 32 blocks of the batch in
+    one call; the bench times the fused FP32 path): blocks without cuts are
+    independent, so the smallest block's residual is checked against the
+    oracle."""
     p = synth.make_problem("batch32_mixed")
-    _say("case batch32_mixed moving-grid residual, sampled block")
+    _say("case batch32_mixed moving-grid residual, sampled block, batched", batched,
+         "precision", prec)
     q = torch.as_tensor(synth.initial_state(p))
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     g.set_motion(**MOT)
     r = g.residual(q.to(DEV)).cpu()
     torch.cuda.synchronize()
@@ -113,30 +135,50 @@ def test_moving_full_size_sampled_block():
     n = b.ns * 4 * b.ni * b.nj
     qb = q[off:off + n].reshape(b.ns, 4, b.nj, b.ni)
     ref = M.moving_residual(b, qb, flow, solver, M.OMotion(**MOT)).reshape(-1)
-    assert _rel([b], r[off:off + n], ref) <= 1e-12
+    err = _rel([b], r[off:off + n], ref)
+    _say("  rel error", err)
+    assert err <= _tol(prec, 1e-12)
     assert bool(torch.isfinite(r).all())
 
 
-def test_clearing_motion_restores_fixed_grid_bitwise():
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
+def test_clearing_motion_restores_fixed_grid_bitwise(batched, prec):
+    """Residual and captured iterations: setting a motion changes them,
+    clearing it gives the fixed grid's results bit for bit (the captured
+    iteration of the batched path is rebuilt each time)."""
     p, blocks, flow, solver, q = _setup("cyl_tiny")
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    p.solver.graph_iters = 2
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     qd = q.to(DEV)
-    r0 = g.residual(qd).clone()
+
+    def run():
+        r = g.residual(qd).clone()
+        qi = qd.clone()
+        g.rk_iterate(qi, 4)
+        return r, qi
+
+    r0, q0 = run()
     g.set_motion(**MOT)
-    r1 = g.residual(qd).clone()
+    r1, q1 = run()
     g.set_motion()
-    r2 = g.residual(qd).clone()
+    r2, q2 = run()
     torch.cuda.synchronize()
-    assert not torch.equal(r0, r1)
-    assert torch.equal(r0, r2)
+    assert not torch.equal(r0, r1) and not torch.equal(q0, q1)
+    assert torch.equal(r0, r2) and torch.equal(q0, q2)
 
 
 def test_moving_grid_refusals():
     p, blocks, flow, solver, q = _setup("cyl_tiny")
-    gb = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
-    with pytest.raises(hb.HBError) as e:
-        gb.set_motion(**MOT)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
+    iw = synth.Problem("iwall", [synth.Block(16, 8, 0, synth.o_grid(16, 8),
+                                             (synth.WALL, synth.WALL, synth.FARFIELD,
+                                              synth.FARFIELD))],
+                       p.flow, synth.Solver(batched=1), 0, 21)
+    for batched in (0, 1):
+        gi = hb.Grid(iw.blocks, iw.flow, iw.solver, precision=0, batched=batched)
+        with pytest.raises(hb.HBError) as e:
+            gi.set_motion(**MOT)
+        assert e.value.code == hb.HB_ERR_UNSUPPORTED
+        gi.close()
     g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
     with pytest.raises(hb.HBError) as e:
         g.set_motion(pitch_amp=float("nan"))
@@ -164,11 +206,12 @@ def _td_problem(kind, n_harm, ni, nj):
     return p
 
 
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("kind", ["o", "c"])
-def test_moving_td_march_matches_oracle(kind):
+def test_moving_td_march_matches_oracle(kind, batched, prec):
     """hb_td_march on a heaving and pitching grid (the motion at every stage
     time) against the oracle's moving-grid fourth-order march."""
-    _say("moving td march", kind)
+    _say("moving td march", kind, "batched", batched, "precision", prec)
     p = _td_problem(kind, 0, 24 if kind == "o" else 72, 12 if kind == "o" else 20)
     blocks, flow, solver = O.from_synth(p)
     q0 = torch.as_tensor(synth.initial_state(p))
@@ -180,18 +223,18 @@ def test_moving_td_march_matches_oracle(kind):
     ref = M.moving_td_march(b, qb, flow, solver, M.OMotion(**mot), dt, n, t0).reshape(-1)
     fixed = O.td_march(b, qb, flow, solver, dt, n, t0).reshape(-1)
     assert float((fixed - ref).norm() / (ref - q0).norm()) > 1e-2       # the motion matters
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
     g.set_motion(**mot)
     q = q0.to(DEV)
     g.td_march(q, t0, dt, n)
     torch.cuda.synchronize()
     rel = float(((q.cpu() - q0) - (ref - q0)).norm() / (ref - q0).norm())
     _say("  rel error of the change", rel)
-    assert rel <= 1e-11
+    assert rel <= _tol(prec, 1e-11)
     # the grid's own (phase 0) motion is restored: its residual is unchanged
     r1 = g.residual(q0.to(DEV)).cpu()
     rref = M.moving_residual_all(blocks, q0, flow, solver, M.OMotion(**mot))
-    assert float((r1 - rref).norm() / rref.norm()) <= 1e-12
+    assert float((r1 - rref).norm() / rref.norm()) <= _tol(prec, 1e-12)
 
 
 def test_moving_hb_matches_time_domain_march_on_gpu():
@@ -259,18 +302,19 @@ def test_moving_hb_matches_time_domain_march_on_gpu():
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
 
 
+@pytest.mark.parametrize("batched,prec", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("name,pi,pj", [("cyl_tiny", 2, 2), ("naca_tiny", 1, 2)])
-def test_moving_cuts(name, pi, pj):
+def test_moving_cuts(name, pi, pj, batched, prec):
     """Glued blocks on the moving grid: the cut-aware oracle's residual,
     loads and iterations (corner wall images across an i cut take the glued
     block's wall face)."""
-    _say("case", name, pi, pj, "moving grid with cuts")
+    _say("case", name, pi, pj, "moving grid with cuts, batched", batched, "precision", prec)
     p = synth.make_problem(name)
     sp, perm = synth.split_problem(p, pi, pj)
     sblocks, flow, solver = O.from_synth(sp)
     q = torch.as_tensor(synth.initial_state(p))[torch.as_tensor(perm)].contiguous()
     m = M.OMotion(**MOT)
-    g = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=0, batched=0)
+    g = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=prec, batched=batched)
     g.set_motion(**MOT)
     ref = M.moving_residual_all(sblocks, q, flow, solver, m, sp.cuts)
     r = g.residual(q.to(DEV)).cpu()
@@ -282,8 +326,12 @@ def test_moving_cuts(name, pi, pj):
     g.rk_iterate(qd, 2, norms)
     torch.cuda.synchronize()
     assert g.status() == hb.HB_OK
-    assert _rel(sblocks, r, ref) <= 1e-12
-    assert _elem(sblocks, r, ref) <= 1e-11
+    err, qerr = _rel(sblocks, r, ref), _rel(sblocks, qd.cpu() - q, qref - q)
+    nerr = float(((norms.cpu() - nref).abs() / nref).max())
+    _say("  residual", err, "state change", qerr, "norms", nerr)
+    assert err <= _tol(prec, 1e-12)
+    if prec == 0:
+        assert _elem(sblocks, r, ref) <= 1e-11
     assert float((cf - ref_cf).abs().max()) <= 1e-11 * float(ref_cf.abs().max())
-    assert _rel(sblocks, qd.cpu() - q, qref - q) <= 1e-11
-    assert torch.allclose(norms.cpu(), nref, rtol=1e-12, atol=0)
+    assert qerr <= _tol(prec, 1e-11)
+    assert nerr <= _tol(prec, 1e-12)
