@@ -42,7 +42,7 @@ PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 METRIC = ("cell-snapshot RK-stage updates/s (FP32+batched vs FP64 plain); "
           "adjoint/primal time")
 TUNE_CACHE = os.path.join(ROOT, "paper_1304_7654_amd", "tune_cache.json")
-KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused.hip", "paper_1304_7654_amd/csrc/hb_device.hpp"]
+KERNEL_SOURCES = ["paper_1304_7654_amd/csrc/hb_fused_kernel.hpp", "paper_1304_7654_amd/csrc/hb_device.hpp"]
 
 
 def code_text(src: str) -> str:

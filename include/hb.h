@@ -121,7 +121,10 @@ typedef struct {
  *   entropy_delta: Harten fix width as a fraction of the Roe sound speed
  *   limiter_eps: van Albada epsilon
  *   batched: 1 = all blocks in one launch per stage (fused tile kernel,
- *     launch configuration from hb_set_tuning / hb_autotune); 0 = plain
+ *     launch configuration from hb_set_tuning / hb_autotune; its halo
+ *     loads use 32-bit byte offsets while the state is below 4 GiB and
+ *     64-bit element offsets from 4 GiB on); 2 = the same with 64-bit
+ *     offsets at any size (the large-state code on small grids); 0 = plain
  *     per-block launches (separate ghost, face-flux and update kernels,
  *     FP64 only)
  *   graph_iters: iterations captured per HIP graph replay (>= 1) */
@@ -179,8 +182,7 @@ typedef struct {
  * ni, nj >= 4, n_harm in [0, 4], known boundary kinds, wake_ncells in
  * [0, ni/2] and only with a WAKECUT jmin, cut sides consistent, bodies
  * numbered without gaps with one n_harm each, every cell area > 0.
- * At most 2^24 cells per block (HB_ERR_ARG otherwise); a batched grid's state
- * must stay below 2 GiB (HB_ERR_UNSUPPORTED otherwise).  Synchronises the current device.  *out is
+ * At most 2^24 cells per block (HB_ERR_ARG otherwise).  Synchronises the current device.  *out is
  * NULL on failure. */
 int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts,
                    int32_t ncuts, const hb_flow *flow, const hb_solver *solver,

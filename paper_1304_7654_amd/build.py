@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhb.so")
 SOURCES = ["hb_capi.cpp", "hb_metrics.hip", "hb_plain.hip", "hb_reduce.hip", "hb_forces.hip",
-           "hb_fused.hip", "hb_adjoint.hip", "hb_tune.cpp", "hb_td.hip", "hb_io.cpp",
+           "hb_fused.hip", "hb_fused_k_fixed.hip", "hb_fused_k_moving.hip", "hb_fused_k_fixed64.hip",
+           "hb_fused_k_moving64.hip", "hb_adjoint.hip", "hb_tune.cpp", "hb_td.hip", "hb_io.cpp",
            "hb_ghost.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

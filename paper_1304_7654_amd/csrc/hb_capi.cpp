@@ -82,6 +82,7 @@ void free_all(hb_grid *g) {
     dfree(g->tiles_d);
     dfree(g->gtab_d);
     dfree(g->wtab_d);
+    dfree(g->gtab64_d);
     dfree(g->ffc_d);
     dfree(g->cpart_d);
     dfree(g->geo_d);
@@ -193,7 +194,7 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     if (solver->n_stages < 1 || solver->n_stages > 8 || !(solver->cfl > 0) ||
         (solver->precision != HB_FP64 && solver->precision != HB_FP32_BULK) ||
         !(solver->entropy_delta >= 0) || !(solver->limiter_eps > 0) || solver->graph_iters < 1 ||
-        (solver->batched != 0 && solver->batched != 1))
+        (solver->batched < 0 || solver->batched > 2))
         return fail(HB_ERR_ARG, "invalid solver settings");
     if (solver->precision == HB_FP32_BULK && !solver->batched)
         return fail(HB_ERR_ARG, "FP32-bulk precision needs the batched (fused) path");
@@ -304,14 +305,6 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         for (int s = 0; s < 4; ++s)
             if (blocks[b].bc[s] == HB_BC_CUT && cut_blk[4 * b + s] < 0)
                 return fail(HB_ERR_ARG, "a HB_BC_CUT side has no cut");
-    if (solver->batched) {
-        // the batched kernel addresses the state with 32-bit byte offsets
-        int64_t total = 0;
-        for (int b = 0; b < nblocks; ++b)
-            total += (int64_t)(2 * blocks[b].n_harm + 1) * 4 * blocks[b].ni * blocks[b].nj;
-        if (total * (int64_t)sizeof(double) >= ((int64_t)1 << 31))
-            return fail(HB_ERR_UNSUPPORTED, "state of 2 GiB or more: use batched = 0");
-    }
 
     // ---- device work starts here --------------------------------------
     hb_grid *g = new (std::nothrow) hb_grid();
@@ -383,6 +376,9 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     }
     const bool plain = !solver->batched;
     const bool f32 = solver->precision == HB_FP32_BULK;
+    // the batched kernel's halo loads: 32-bit byte offsets while every byte
+    // offset into the FP64 state fits, else (or on request) 64-bit
+    g->big = !plain && (solver->batched == 2 || g->n_state * (int64_t)sizeof(double) >= ((int64_t)1 << 32));
     rc = dalloc(&g->blk_d, nblocks);
     rc = rc ? rc : dalloc(&g->xy_d, 2 * g->n_nodes);
     rc = rc ? rc : dalloc(&g->SI_d, 2 * g->n_fi);

@@ -148,6 +148,10 @@ struct hb_grid {
     // of the wall face's first node, node count of its block) for a moving
     // no-slip wall image, (0, 0) otherwise
     uint32_t *wtab_d = nullptr;
+    // 64-bit halo addressing (states of 4 GiB or more, or batched = 2): the
+    // source element offset of every halo table entry (0 for far field)
+    bool big = false;
+    uint64_t *gtab64_d = nullptr;
     int tile_ti = 16, tile_tj = 15;
     int n_cu = 0;
     // tuning of the fused path (hb_set_tuning / hb_autotune)

@@ -163,17 +163,16 @@ def test_committed_tuning_cache_matches_the_reader_format():
 
 
 def test_size_limits_rejected_before_device_work():
-    """More than 2^24 cells in a block is a bad argument; a batched grid whose
-    state reaches 2 GiB is unsupported (the batched kernel addresses the state
-    with 32-bit byte offsets).  Both are refused on the host."""
+    """More than 2^24 cells in a block is a bad argument, and so is a batched
+    mode other than 0, 1 and 2; both are refused on the host.  (The state
+    size is not limited: a batched grid of 4 GiB or more addresses its halo
+    with 64-bit offsets.)"""
     p = synth.make_problem("cyl_tiny")
     n = 4097                                   # n * n > 2^24; the nodes are never read
     big = synth.Block(n, n, 0, np.zeros((2, n + 1, n + 1)), (synth.PERIODIC, synth.PERIODIC,
                                                               synth.WALL, synth.FARFIELD))
     assert _try([big]) == hb.HB_ERR_ARG
-    ni, nj = 4096, 2048                        # N_H = 4: 2.4 GB of state
-    blk = synth.Block(ni, nj, 4, synth.o_grid(ni, nj), (synth.PERIODIC, synth.PERIODIC,
-                                                       synth.WALL, synth.FARFIELD))
-    with pytest.raises(hb.HBError) as e:
-        hb.Grid([blk], p.flow, p.solver, precision=1, batched=1)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
+    for mode in (-1, 3):
+        with pytest.raises(hb.HBError) as e:
+            hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=mode)
+        assert e.value.code == hb.HB_ERR_ARG
