@@ -244,7 +244,10 @@ int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
  *   xybar   = J_X^T rbar,  X = node coordinates    (hb_xy_size(), may be NULL)
  *   flowbar = J_a^T rbar,  a = alpha0              (1 double, may be NULL)
  * The reconstruction is recomputed, nothing is stored between calls.
- * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid). */
+ * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid).  The adjoints'
+ * scratch (the inverse ghost map, per-face adjoint terms: 26 doubles per
+ * face and snapshot) is allocated by the first adjoint call unless
+ * hb_prepare allocated it before. */
 int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar,
                         double *qbar, double *xybar, double *flowbar, void *stream);
 
@@ -272,9 +275,29 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
  * (must alias neither); resnorm (device, n_iter doubles, may be NULL): RMS
  * over cells, snapshots and variables of (J_Q^T lambda + gq)/V at the first
  * stage of each iteration.  FP64 grids only (HB_ERR_UNSUPPORTED otherwise).
- * Scratch of 2.25 state sizes is allocated on the first call. */
+ * Scratch of 2.25 state sizes (and the adjoints' own) is allocated on the
+ * first call unless hb_prepare allocated it before. */
 int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
                        int32_t n_iter, double *resnorm, void *stream);
+
+/* Scratch that the calls below allocate on their first use, allocated now
+ * (synchronously, on the grid's device), so that the later calls allocate
+ * nothing: for callers that enqueue them into a HIP graph capture or a
+ * serving loop.  The paper defines no such call (it has no device
+ * allocator).  what: a bitwise OR of
+ *   HB_PREPARE_ADJOINT          hb_residual_adjoint, hb_forces_adjoint
+ *   HB_PREPARE_ADJOINT_ITERATE  hb_adjoint_iterate (includes the above;
+ *                               FP64 grids only, HB_ERR_UNSUPPORTED otherwise)
+ *   HB_PREPARE_TD               hb_td_march
+ * Scratch already allocated is kept.  HB_ERR_ARG for NULL or unknown bits,
+ * HB_ERR_OOM when the device memory runs out (what was allocated stays
+ * with the grid). */
+enum {
+    HB_PREPARE_ADJOINT = 1,
+    HB_PREPARE_ADJOINT_ITERATE = 2,
+    HB_PREPARE_TD = 4
+};
+int hb_prepare(hb_grid *g, int32_t what);
 
 /* Restart files (the paper's aggregated output of all blocks and harmonics,
  * §MPI Optimisations, the part on MPI I/O): hb_save_state writes the whole state q (device,
@@ -316,7 +339,8 @@ int hb_save_solution(hb_grid *g, const double *q, const char *prefix, void *stre
  * every block only (one snapshot per cell; HB_ERR_UNSUPPORTED otherwise).
  * q: device, state size, advanced in place.  dt > 0 is the caller's
  * (stability needs dt below about the smallest local step at CFL 1).
- * Allocates three state-size scratch buffers on the first call. */
+ * Allocates three state-size scratch buffers on the first call, unless
+ * hb_prepare allocated them before. */
 int hb_td_march(hb_grid *g, double *q, double t0, double dt, int32_t n_steps, void *stream);
 
 /* hb_td_march for callers that cannot allocate device memory (code under

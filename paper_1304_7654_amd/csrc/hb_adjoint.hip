@@ -1074,24 +1074,27 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
 // whose iteration matrix has the eigenvalues of the forward linearisation.
 // resnorm[it] = RMS over cells, snapshots and variables of (J^T lam + gq)/V
 // at the first stage.
+int adjoint_prepare(hb_grid *g, bool iterate) {
+    int rc = adjoint_setup(g);
+    if (rc || !iterate || g->it_lam0_d) return rc;
+    int64_t np = 0;
+    for (int b = 0; b < g->nblocks; ++b) np += nblk((int64_t)g->blk[b].ni * g->blk[b].nj);
+    g->n_it_part = np;
+    auto alloc = [&](double **p, int64_t n) {
+        return check_hip(hipMalloc((void **)p, sizeof(double) * std::max<int64_t>(1, n)),
+                         "adjoint iteration alloc");
+    };
+    rc = alloc(&g->it_lam0_d, g->n_state);
+    rc = rc ? rc : alloc(&g->it_qbar_d, g->n_state);
+    rc = rc ? rc : alloc(&g->it_dtv_d, g->n_state / 4);
+    rc = rc ? rc : alloc(&g->it_part_d, np);
+    return rc;
+}
+
 int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const double *gq,
                            int n_iter, double *resnorm, hipStream_t s) {
-    int rc = adjoint_setup(g);
+    int rc = adjoint_prepare(g, true);
     if (rc) return rc;
-    if (!g->it_lam0_d) {
-        int64_t np = 0;
-        for (int b = 0; b < g->nblocks; ++b) np += nblk((int64_t)g->blk[b].ni * g->blk[b].nj);
-        g->n_it_part = np;
-        auto alloc = [&](double **p, int64_t n) {
-            return check_hip(hipMalloc((void **)p, sizeof(double) * std::max<int64_t>(1, n)),
-                             "adjoint iteration alloc");
-        };
-        rc = alloc(&g->it_lam0_d, g->n_state);
-        rc = rc ? rc : alloc(&g->it_qbar_d, g->n_state);
-        rc = rc ? rc : alloc(&g->it_dtv_d, g->n_state / 4);
-        rc = rc ? rc : alloc(&g->it_part_d, np);
-        if (rc) return rc;
-    }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_dtv, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,

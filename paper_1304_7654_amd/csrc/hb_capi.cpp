@@ -530,6 +530,20 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
 }
 
+int hb_prepare(hb_grid *g, int32_t what) {
+    g_err.clear();
+    if (!g) return fail(HB_ERR_ARG, "NULL grid");
+    const int32_t known = HB_PREPARE_ADJOINT | HB_PREPARE_ADJOINT_ITERATE | HB_PREPARE_TD;
+    if (what & ~known) return fail(HB_ERR_ARG, "unknown hb_prepare bits");
+    if ((what & HB_PREPARE_ADJOINT_ITERATE) && g->solver.precision != HB_FP64)
+        return fail(HB_ERR_UNSUPPORTED, "the adjoint iteration is FP64 only");
+    int rc = HB_OK;
+    if (what & (HB_PREPARE_ADJOINT | HB_PREPARE_ADJOINT_ITERATE))
+        rc = adjoint_prepare(g, (what & HB_PREPARE_ADJOINT_ITERATE) != 0);
+    if (!rc && (what & HB_PREPARE_TD)) rc = td_prepare(g);
+    return rc;
+}
+
 int hb_save_state(hb_grid *g, const double *q, int64_t iteration, const char *path, void *stream) {
     g_err.clear();
     if (!g || !q || !path) return fail(HB_ERR_ARG, "NULL argument");

@@ -237,6 +237,7 @@ int io_load(hb_grid *g, double *q, int64_t *iteration, const char *path, hipStre
 int io_save_solution(hb_grid *g, const double *q, const char *prefix, hipStream_t s);
 // td.hip
 int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s);
+int td_prepare(hb_grid *g);                       // the march's scratch (hb_prepare)
 int launch_td_march_noalloc(hb_grid *g, double *q, double t0, double dt, int n_steps,
                             hipStream_t s);
 // tune.cpp
@@ -257,6 +258,7 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
                           double *xybar, double *flowbar, hipStream_t s);
 int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const double *gq,
                            int n_iter, double *resnorm, hipStream_t s);
+int adjoint_prepare(hb_grid *g, bool iterate);    // the adjoints' scratch (hb_prepare)
 
 // instrumentation (capi.cpp): event pair around one stage, or no-op
 int prof_begin(hb_grid *g, hipStream_t s, hipEvent_t *end);

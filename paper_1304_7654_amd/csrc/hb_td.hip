@@ -161,13 +161,17 @@ int td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, double *r
 
 }  // namespace
 
+int td_prepare(hb_grid *g) {
+    if (g->td_r_d) return HB_OK;
+    int rc = check_hip(hipMalloc((void **)&g->td_r_d, sizeof(double) * g->n_state), "td alloc");
+    rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_acc_d, sizeof(double) * g->n_state), "td alloc");
+    rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_qs_d, sizeof(double) * g->n_state), "td alloc");
+    return rc;
+}
+
 int launch_td_march(hb_grid *g, double *q, double t0, double dt, int n_steps, hipStream_t s) {
-    if (!g->td_r_d) {
-        int rc = check_hip(hipMalloc((void **)&g->td_r_d, sizeof(double) * g->n_state), "td alloc");
-        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_acc_d, sizeof(double) * g->n_state), "td alloc");
-        rc = rc ? rc : check_hip(hipMalloc((void **)&g->td_qs_d, sizeof(double) * g->n_state), "td alloc");
-        if (rc) return rc;
-    }
+    const int rc = td_prepare(g);
+    if (rc) return rc;
     return td_march(g, q, t0, dt, n_steps, g->td_r_d, g->td_acc_d, g->td_qs_d, s);
 }
 

@@ -20,9 +20,12 @@ LIB_PATH = os.path.join(HERE, "libhb.so")
 HB_OK, HB_ERR_ARG, HB_ERR_DEVICE, HB_ERR_OOM, HB_ERR_NONFINITE, HB_ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 HB_FP64, HB_FP32_BULK = 0, 1
+HB_PREPARE_ADJOINT, HB_PREPARE_ADJOINT_ITERATE, HB_PREPARE_TD = 1, 2, 4
 EXPORTS = ["hb_grid_create", "hb_grid_destroy", "hb_state_size", "hb_forces_size",
            "hb_xy_size", "hb_residual", "hb_rk_iterate", "hb_forces", "hb_residual_adjoint",
-           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_td_march_noalloc", "hb_save_state", "hb_load_state", "hb_save_solution", "hb_autotune", "hb_set_tuning",
+           "hb_forces_adjoint", "hb_adjoint_iterate", "hb_td_march", "hb_td_march_noalloc",
+           "hb_prepare", "hb_save_state", "hb_load_state", "hb_save_solution", "hb_autotune",
+           "hb_set_tuning",
            "hb_get_tuning", "hb_set_xy", "hb_set_alpha0", "hb_set_motion", "hb_get_status",
            "hb_profile_stages", "hb_stage_stats", "hb_last_error"]
 
@@ -272,6 +275,11 @@ class Grid:
         _check(lib().hb_td_march(self.h, _ptr(q, self.n_state, "q"), float(t0), float(dt),
                                  int(n_steps), _stream()))
         return q
+
+    def prepare(self, what: int):
+        """Allocate now the scratch of the calls named by `what` (a bitwise
+        OR of HB_PREPARE_ADJOINT, HB_PREPARE_ADJOINT_ITERATE, HB_PREPARE_TD)."""
+        _check(lib().hb_prepare(self.h, int(what)))
 
     def td_march_noalloc(self, q: torch.Tensor, t0: float, dt: float, n_steps: int):
         """td_march without any device allocation (static per-device scratch

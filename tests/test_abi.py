@@ -140,6 +140,15 @@ def test_null_handles():
     assert L.hb_get_status(None) == hb.HB_ERR_ARG
     m = hb.c_motion(0.1, 0.0, 0.2, 0.0, 0.0)
     assert L.hb_set_motion(None, ctypes.byref(m)) == hb.HB_ERR_ARG
+    assert L.hb_prepare(None, hb.HB_PREPARE_TD) == hb.HB_ERR_ARG
+
+
+def test_prepare_flags_match_header():
+    """The hb_prepare bits of the binding are the header's."""
+    src = open(os.path.join(ROOT, "include", "hb.h")).read()
+    for name in ("HB_PREPARE_ADJOINT", "HB_PREPARE_ADJOINT_ITERATE", "HB_PREPARE_TD"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, src)
+        assert m and int(m.group(1)) == getattr(hb, name), name
 
 
 def test_committed_tuning_cache_matches_the_reader_format():
