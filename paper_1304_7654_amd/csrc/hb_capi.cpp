@@ -79,6 +79,7 @@ void free_all(hb_grid *g) {
     dfree(g->partials_d); dfree(g->fpart_d); dfree(g->norm_tmp_d);
     dfree(g->status_d); dfree(g->ctr_d);
     dfree(g->body_off_d); dfree(g->body_ns_d);
+    dfree(g->body_ptr_d); dfree(g->body_blk_d);
     dfree(g->tiles_d);
     dfree(g->gtab_d);
     dfree(g->wtab_d);
@@ -414,11 +415,14 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         rc = rc ? rc : dalloc(&g->sb_f, g->n_state);
         if (!plain) rc = rc ? rc : dalloc(&g->dtau_f, g->n_state / 4);
     }
-    rc = rc ? rc : dalloc(&g->fpart_d, (int64_t)nblocks * kMaxNs * 3);
+    for (const BlockDesc &B : g->blk) g->fchunks = std::max(g->fchunks, (B.ni + 255) / 256);
+    rc = rc ? rc : dalloc(&g->fpart_d, (int64_t)nblocks * kMaxNs * g->fchunks * 3);
     rc = rc ? rc : dalloc(&g->status_d, 1);
     rc = rc ? rc : dalloc(&g->ctr_d, 1);
     rc = rc ? rc : dalloc(&g->body_off_d, nbody);
     rc = rc ? rc : dalloc(&g->body_ns_d, nbody);
+    rc = rc ? rc : dalloc(&g->body_ptr_d, nbody + 1);
+    rc = rc ? rc : dalloc(&g->body_blk_d, nblocks);
     if (!rc && !plain) rc = fused_build_tiles(g, 16, 0);
     g->n_partials = plain ? part : fused_max_tiles(g);
     rc = rc ? rc : dalloc(&g->partials_d, g->n_partials);
@@ -443,8 +447,18 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     rc = rc ? rc : check_hip(hipMemcpy(g->D_f, Df.data(), sizeof(float) * Df.size(), hipMemcpyHostToDevice), "upload");
     rc = rc ? rc : check_hip(hipMemcpy(g->body_off_d, g->body_off.data(), sizeof(int) * nbody, hipMemcpyHostToDevice), "upload");
     rc = rc ? rc : check_hip(hipMemcpy(g->body_ns_d, g->body_ns.data(), sizeof(int) * nbody, hipMemcpyHostToDevice), "upload");
+    {
+        std::vector<int> ptr(nbody + 1, 0), blk;
+        for (int k = 0; k < nbody; ++k) {
+            for (int b = 0; b < nblocks; ++b)
+                if (g->blk[b].body == k) blk.push_back(b);
+            ptr[k + 1] = (int)blk.size();
+        }
+        rc = rc ? rc : check_hip(hipMemcpy(g->body_ptr_d, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice), "upload");
+        rc = rc ? rc : check_hip(hipMemcpy(g->body_blk_d, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice), "upload");
+    }
     rc = rc ? rc : check_hip(hipMemset(g->status_d, 0, sizeof(int)), "memset");
-    rc = rc ? rc : check_hip(hipMemset(g->fpart_d, 0, sizeof(double) * nblocks * kMaxNs * 3), "memset");
+    rc = rc ? rc : check_hip(hipMemset(g->fpart_d, 0, sizeof(double) * nblocks * kMaxNs * g->fchunks * 3), "memset");
     rc = rc ? rc : upload_snapshot_tables(g);
     rc = rc ? rc : launch_metrics(g, nullptr);
     rc = rc ? rc : check_hip(hipDeviceSynchronize(), "metrics");

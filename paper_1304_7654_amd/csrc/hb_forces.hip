@@ -87,23 +87,18 @@ __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, con
     out[2] = mx * fy - my * fx;
 }
 
+// Workgroup (block b, snapshot n, chunk k): the wall faces i = 256 k + tid,
+// one per thread; the chunk's sum goes to part[((b kMaxNs + n) nch + k)].
 __global__ void k_block_loads(const BlockDesc *blks, const double *q, const double *ffw,
                               const double *xy, const double *SJ, const double *dJ, Consts c,
-                              double xm, double ym, Motion mo, double *part) {
+                              double xm, double ym, Motion mo, int nch, double *part) {
     const int b = blockIdx.x;
     const int n = blockIdx.y;
+    const int i = blockIdx.z * kBS + threadIdx.x;
     const BlockDesc &B = blks[b];
     double acc[3] = {0.0, 0.0, 0.0};
-    if (n < B.ns) {
-        for (int i = threadIdx.x; i < B.ni; i += kBS) {
-            if (!is_wall_face(B, i)) continue;
-            double l[3];
-            face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, mo, l);
-            acc[0] += l[0];
-            acc[1] += l[1];
-            acc[2] += l[2];
-        }
-    }
+    if (n < B.ns && i < B.ni && is_wall_face(B, i))
+        face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, mo, acc);
     __shared__ double red[3][kBS];
     for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
@@ -113,13 +108,15 @@ __global__ void k_block_loads(const BlockDesc *blks, const double *q, const doub
         __syncthreads();
     }
     if (threadIdx.x == 0 && n < B.ns)
-        for (int k = 0; k < 3; ++k) part[((int64_t)b * kMaxNs + n) * 3 + k] = red[k][0];
+        for (int k = 0; k < 3; ++k)
+            part[(((int64_t)b * kMaxNs + n) * nch + blockIdx.z) * 3 + k] = red[k][0];
 }
 
-// One thread per (body, snapshot) entry of the output.
-__global__ void k_body_coeffs(const BlockDesc *blks, int nblocks, const int *body_off,
-                              const int *body_ns, int nbody, const double *part, double ca,
-                              double sa, double qinf_l, double qinf_l2, double *cf) {
+// One thread per (body, snapshot) entry of the output; the blocks of a body
+// (body_blk[body_ptr[body] ..], in block order) are summed in block order.
+__global__ void k_body_coeffs(const int *body_ptr, const int *body_blk, const int *body_off,
+                              const int *body_ns, int nbody, const double *part, int nch,
+                              double ca, double sa, double qinf_l, double qinf_l2, double *cf) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int body = 0, n = t;
     while (body < nbody && n >= body_ns[body]) {
@@ -128,12 +125,13 @@ __global__ void k_body_coeffs(const BlockDesc *blks, int nblocks, const int *bod
     }
     if (body >= nbody) return;
     double fx = 0.0, fy = 0.0, mz = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        if (blks[b].body != body) continue;
-        const double *p = part + ((int64_t)b * kMaxNs + n) * 3;
-        fx += p[0];
-        fy += p[1];
-        mz += p[2];
+    for (int k = body_ptr[body]; k < body_ptr[body + 1]; ++k) {
+        const double *p = part + ((int64_t)body_blk[k] * kMaxNs + n) * nch * 3;
+        for (int h = 0; h < nch; ++h) {
+            fx += p[3 * h];
+            fy += p[3 * h + 1];
+            mz += p[3 * h + 2];
+        }
     }
     double *o = cf + body_off[body] + 3 * n;
     o[0] = (-fx * sa + fy * ca) / qinf_l;
@@ -144,14 +142,14 @@ __global__ void k_body_coeffs(const BlockDesc *blks, int nblocks, const int *bod
 }  // namespace
 
 int launch_forces(hb_grid *g, const double *q, double *cf, hipStream_t s) {
-    hipLaunchKernelGGL(k_block_loads, dim3(g->nblocks, kMaxNs), dim3(kBS), 0, s, g->blk_d, q,
-                       g->ffw_d, g->xy_d, g->SJ_d, g->dJ_d, g->consts, g->flow.x_mom,
-                       g->flow.y_mom, g->motion, g->fpart_d);
+    hipLaunchKernelGGL(k_block_loads, dim3(g->nblocks, kMaxNs, g->fchunks), dim3(kBS), 0, s, g->blk_d,
+                       q, g->ffw_d, g->xy_d, g->SJ_d, g->dJ_d, g->consts, g->flow.x_mom,
+                       g->flow.y_mom, g->motion, g->fchunks, g->fpart_d);
     const int total = (int)(g->n_forces / 3);
     const double qinf = 0.5 * g->flow.mach * g->flow.mach;
     const double L = g->flow.l_ref;
-    hipLaunchKernelGGL(k_body_coeffs, dim3((total + 63) / 64), dim3(64), 0, s, g->blk_d,
-                       g->nblocks, g->body_off_d, g->body_ns_d, g->nbody, g->fpart_d,
+    hipLaunchKernelGGL(k_body_coeffs, dim3((total + 63) / 64), dim3(64), 0, s, g->body_ptr_d,
+                       g->body_blk_d, g->body_off_d, g->body_ns_d, g->nbody, g->fpart_d, g->fchunks,
                        cos(g->flow.alpha0), sin(g->flow.alpha0), qinf * L, qinf * L * L, cf);
     return check_hip(hipGetLastError(), "forces launch");
 }

@@ -132,10 +132,12 @@ struct hb_grid {
     float *dtau_f = nullptr;      // fused path: local time step of every cell-snapshot (FP32 bulk)
     double *dtau_d = nullptr;     // the same for the fused FP64 path
     double *partials_d = nullptr; int64_t n_partials = 0;
-    double *fpart_d = nullptr;    // force partials [block][kMaxNs][3]
+    double *fpart_d = nullptr;    // force partials [block][kMaxNs][fchunks][3]
+    int fchunks = 1;              // 256-face chunks of the longest jmin side
     double *norm_tmp_d = nullptr;
     int *status_d = nullptr;
     int *body_off_d = nullptr, *body_ns_d = nullptr;
+    int *body_ptr_d = nullptr, *body_blk_d = nullptr;   // blocks of each body, in block order
     int *ctr_d = nullptr;
     // fused path
     hb::Tile *tiles_d = nullptr;
