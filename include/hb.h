@@ -84,19 +84,22 @@ typedef struct {
 /* A cut (the paper's "cuts": block edges whose data are exchanged with the
  * neighbouring block every Runge-Kutta step; the paragraph on the MPI
  * parallelisation that follows the Introduction, and the cut pseudo code of
- * §MPI Optimisations, which loops over a cut's boundary length) glues `len`
- * cells of side `side_a` (0..3 = imin, imax, jmin, jmax) of block blk_a,
- * starting at cell start_a along that side, to `len` cells of side side_b
- * of block blk_b starting at start_b (in the opposite direction along
- * side_b when `reversed` is non-zero).  The ghosts of each glued cell are
- * the other block's interior cells (Jacobi: both read the same stage input).
- *
- * This build glues whole sides only: start_a = start_b = 0, len = the
- * length of both sides (nj for an i side, ni for a j side), imax<->imin or
- * jmax<->jmin, reversed = 0, equal n_harm.  A segment (partial side), a
- * reversed cut or another pairing of sides returns HB_ERR_UNSUPPORTED;
- * indices outside the blocks, len < 1 or a segment running past the end of
- * a side return HB_ERR_ARG. */
+ * §MPI Optimisations, which sends a cut as a sequence of sections along a
+ * block's boundary) glues `len` cells of side `side_a` (0..3 = imin, imax,
+ * jmin, jmax) of block blk_a, starting at cell start_a along that side, to
+ * `len` cells of side side_b of block blk_b starting at start_b: cell
+ * start_a + t against start_b + t, or start_b + len - 1 - t when
+ * `reversed` is 1.  Positions along a side are j on the i sides, i on the j
+ * sides.  Any two sides may be glued (an imax to a jmin, a jmin to a jmin
+ * reversed as the wake of a C-grid cut into wake and profile blocks), also
+ * sides of one block.  The ghosts of a glued cell are the other block's
+ * interior cells (Jacobi: both read the same stage input); corner ghosts
+ * take the i sides first, then the j sides, continuing across a cut in the
+ * glued block.  Every side of kind HB_BC_CUT must be covered by its
+ * segments exactly once; glued blocks have equal n_harm.  HB_ERR_ARG
+ * otherwise, for a segment outside its sides, len < 1, reversed not 0 or 1,
+ * or cuts around which a corner ghost does not resolve.  A moving grid
+ * (hb_set_motion) needs its cuts to join whole opposite sides, aligned. */
 typedef struct {
     int32_t blk_a, side_a, start_a;
     int32_t blk_b, side_b, start_b;
@@ -389,7 +392,8 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
  * amplitudes zero) the rigid grid motion described at hb_motion.  It then
  * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march, on the
  * per-block and on the batched path (FP64 and FP32 bulk).
- * HB_ERR_UNSUPPORTED for blocks with walls on an i side; while a motion is
+ * HB_ERR_UNSUPPORTED for blocks with walls on an i side or cuts other than
+ * whole opposite sides glued aligned; while a motion is
  * set the adjoints and hb_set_xy return HB_ERR_UNSUPPORTED.  Across a cut,
  * the wall image of a corner ghost takes the glued block's wall face.
  * HB_ERR_ARG for non-finite values.  Drops the batched path's captured

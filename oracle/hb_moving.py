@@ -182,9 +182,10 @@ def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, 
             if n >= b.ns:
                 continue
             _, thd, h, hd = mot[k]
-            nbr_xy = {s: xys[P[(k, s)][0]] for s in (0, 1) if (k, s) in P}
+            nbr_xy = {s: xys[O.whole_side_partner(P, k, s)] for s in (0, 1) if (k, s) in P}
             we = wall_images(b, wes[k].clone(), xys[k], m, thd, h, hd, nbr_xy)
-            nbrC = {s: O.metrics(xys[P[(k, s)][0]])[3] for s in range(4) if (k, s) in P} or None
+            Cs = [O.metrics(xy)[3] for xy in xys]
+            nbrC = O.cut_ghost_centres(blocks, P, Cs, k) or None
             yield k, n, xys[k], we, nbrC, mot[k]
 
 

@@ -201,35 +201,188 @@ def mirror_prim(w: torch.Tensor) -> torch.Tensor:
 # ---------------------------------------------------------------------------
 # Ghost cells (two layers per side; the paper's "cuts" are block-edge halos)
 # ---------------------------------------------------------------------------
-def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
-    """(block, side) -> (neighbour block, neighbour side) for every glued side.
+def side_length(b: OBlock, side: int) -> int:
+    """Cells along side 0..3 = imin, imax, jmin, jmax (positions are j on the
+    i sides, i on the j sides)."""
+    return b.nj if side < 2 else b.ni
 
-    A cut joins two block edges (the paper's "cuts" between blocks, whose
-    halos are exchanged every Runge-Kutta step, §MPI Optimisations).  Read
-    here as whole sides of equal length, imax of one block to imin of the
-    other (equal nj) or jmax to jmin (equal ni), not reversed, both sides of
-    kind CUT.  Sides are numbered 0..3 = imin, imax, jmin, jmax."""
+
+def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
+    """(block, side) -> the segments gluing that side, sorted by start: each
+    (start, length, partner block, partner side, partner start, reversed).
+
+    A cut joins block edges (the paper's "cuts" between blocks, whose halos
+    are exchanged every Runge-Kutta step; §MPI Optimisations sends a cut as a
+    sequence of sections along a block's boundary).  Read here as a segment
+    of `length` cells of one side glued to a segment of another side (any
+    two sides, possibly of the same block), cell start_a + t against
+    start_b + t, or start_b + length - 1 - t when reversed.  A cut is
+    (a, side_a, start_a, b, side_b, start_b, length, reversed), or
+    (a, side_a, b, side_b[, reversed]) for two whole sides of equal length.
+    Every side of kind CUT must be covered by its segments exactly once;
+    glued blocks share n_harm.  Sides are numbered 0..3 = imin, imax, jmin,
+    jmax."""
     m = {}
     for c in cuts:
-        a, sa, b, sb = int(c[0]), int(c[1]), int(c[2]), int(c[3])
-        if len(c) > 4 and c[4]:
-            raise ValueError("reversed cuts are not supported")
-        if {sa, sb} not in ({0, 1}, {2, 3}):
-            raise ValueError("a cut joins imax to imin or jmax to jmin")
+        c = tuple(int(x) for x in c)
+        if len(c) in (4, 5):
+            a, sa, b, sb = c[:4]
+            la, lb = side_length(blocks[a], sa), side_length(blocks[b], sb)
+            if la != lb:
+                raise ValueError("whole-side cuts need sides of equal length")
+            c = (a, sa, 0, b, sb, 0, la, c[4] if len(c) == 5 else 0)
+        if len(c) != 8:
+            raise ValueError("a cut has 4, 5 or 8 entries")
+        a, sa, st_a, b, sb, st_b, ln, rev = c
         A, B = blocks[a], blocks[b]
         if A.bc[sa] != CUT or B.bc[sb] != CUT or A.n_harm != B.n_harm:
             raise ValueError("cut sides must be of kind CUT with equal n_harm")
-        if (sa < 2 and A.nj != B.nj) or (sa >= 2 and A.ni != B.ni):
-            raise ValueError("cut sides must have equal length")
-        if (a, sa) in m or (b, sb) in m:
-            raise ValueError("a block side is used by two cuts")
-        m[(a, sa)] = (b, sb)
-        m[(b, sb)] = (a, sa)
+        if ln < 1 or st_a < 0 or st_b < 0 or st_a + ln > side_length(A, sa) \
+                or st_b + ln > side_length(B, sb):
+            raise ValueError("a cut segment leaves its side")
+        m.setdefault((a, sa), []).append((st_a, ln, b, sb, st_b, 1 if rev else 0))
+        m.setdefault((b, sb), []).append((st_b, ln, a, sa, st_a, 1 if rev else 0))
+    for key in m:
+        m[key].sort()
     for k, blk in enumerate(blocks):
         for side in range(4):
-            if blk.bc[side] == CUT and (k, side) not in m:
-                raise ValueError("a CUT side has no cut")
+            if blk.bc[side] != CUT:
+                continue
+            pos = 0
+            for st, ln, *_ in m.get((k, side), []):
+                if st != pos:
+                    raise ValueError("the cut segments of a side must cover it exactly once")
+                pos = st + ln
+            if pos != side_length(blk, side):
+                raise ValueError("a CUT side is not covered by its cuts")
     return m
+
+
+def cut_cell(blocks: Sequence[OBlock], cutmap: dict, b: int, side: int, k: int, p: int):
+    """The cell across a cut from ghost layer k (0 nearest) at position p of
+    side `side` of block b: (block, i, j) at depth k inside the partner side.
+    A position beyond the side's ends (a corner ghost) continues the mapping
+    of the end segment; the result may then lie outside the partner, where
+    the partner's own side rules apply."""
+    segs = cutmap[(b, side)]
+    L = side_length(blocks[b], side)
+    pc = min(max(p, 0), L - 1)
+    st, ln, a, sa, st_a, rev = [g for g in segs if g[0] <= pc][-1]
+    t = p - st
+    pp = st_a + (ln - 1 - t if rev else t)
+    A = blocks[a]
+    if sa == 0:
+        return a, k, pp
+    if sa == 1:
+        return a, A.ni - 1 - k, pp
+    if sa == 2:
+        return a, pp, k
+    return a, pp, A.nj - 1 - k
+
+
+def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int):
+    """Where ghost-extended cell (i, j) of block b takes its value from:
+    (block, i, j, mirror) of an interior cell, or (block, None, None,
+    mirror) for the free stream; mirror = parity of the wall images met.
+    The i sides are resolved first, then the j sides (the order that
+    defines the corner ghosts; on grids without cuts either order gives the
+    same cells, and with the i sides first a C-grid cut into wake and
+    airfoil blocks keeps the single block's ghosts at the trailing edge);
+    across a cut the partner block's own rules apply to what is still
+    outside it."""
+    mir = 0
+    for _ in range(8):
+        B = blocks[b]
+        if i < 0 or i >= B.ni:
+            side = 0 if i < 0 else 1
+            k = -1 - i if i < 0 else i - B.ni
+            kind = B.bc[side]
+            if kind == PERIODIC:
+                i = i % B.ni
+            elif kind == WALL:
+                i = k if side == 0 else B.ni - 1 - k
+                mir ^= 1
+            elif kind == CUT:
+                b, i, j = cut_cell(blocks, cutmap, b, side, k, j)
+            elif kind == FARFIELD:
+                return b, None, None, mir
+            else:
+                raise ValueError("unsupported i-side boundary %d" % kind)
+            continue
+        if j < 0 or j >= B.nj:
+            side = 2 if j < 0 else 3
+            k = -1 - j if j < 0 else j - B.nj
+            kind = B.bc[side]
+            if kind == PERIODIC:
+                j = j % B.nj
+            elif kind == WALL:
+                j = k if side == 2 else B.nj - 1 - k
+                mir ^= 1
+            elif kind == WAKECUT and side == 2:
+                if i < B.wake_ncells or i >= B.ni - B.wake_ncells:
+                    i, j = B.ni - 1 - i, k
+                else:
+                    j = k
+                    mir ^= 1
+            elif kind == CUT:
+                b, i, j = cut_cell(blocks, cutmap, b, side, k, i)
+            elif kind == FARFIELD:
+                return b, None, None, mir
+            else:
+                raise ValueError("unsupported j-side boundary %d" % kind)
+            continue
+        return b, i, j, mir
+    raise ValueError("ghost resolution does not end (cuts around a singular corner)")
+
+
+def extend_cut(blocks, ws, winfs, cutmap, k: int) -> torch.Tensor:
+    """Ghost-extended primitives [ns][4][nj+4][ni+4] of block k, which has
+    CUT sides: every ghost cell from resolve_ghost, taken from the blocks'
+    interior fields of the same snapshots (Jacobi exchange)."""
+    b = blocks[k]
+    w = ws[k]
+    ns = w.shape[0]
+    we = torch.zeros(ns, 4, b.nj + 4, b.ni + 4, dtype=w.dtype)
+    we[:, :, 2:b.nj + 2, 2:b.ni + 2] = w
+    for je in range(b.nj + 4):
+        for ie in range(b.ni + 4):
+            i, j = ie - 2, je - 2
+            if 0 <= i < b.ni and 0 <= j < b.nj:
+                continue
+            src, si, sj, mir = resolve_ghost(blocks, cutmap, k, i, j)
+            v = winfs[src] if si is None else ws[src][:, :, sj, si]
+            if mir:
+                v = mirror_prim(v[..., None, None])[..., 0, 0]
+            we[:, :, je, ie] = v
+    return we
+
+
+def cut_ghost_centres(blocks, cutmap, Cs, k: int) -> dict:
+    """Centres [L][2] of the first ghost layer of each CUT side of block k:
+    the centres (Cs[block][j, i]) of the cells across the cut."""
+    b = blocks[k]
+    out = {}
+    for side in range(4):
+        if b.bc[side] != CUT:
+            continue
+        cs = []
+        for p in range(side_length(b, side)):
+            a, i, j = cut_cell(blocks, cutmap, k, side, 0, p)
+            cs.append(Cs[a][j, i])
+        out[side] = torch.stack(cs)
+    return out
+
+
+def whole_side_partner(cutmap: dict, k: int, side: int) -> int:
+    """The block glued to side `side` of block k when one aligned segment
+    joins whole opposite sides (imin-imax or jmin-jmax), else ValueError."""
+    segs = cutmap[(k, side)]
+    if len(segs) != 1:
+        raise ValueError("this rule needs a side glued whole to one block")
+    st, ln, a, sa, st_a, rev = segs[0]
+    if rev or st != 0 or st_a != 0 or {side, sa} not in ({0, 1}, {2, 3}):
+        raise ValueError("this rule needs aligned cuts of opposite sides")
+    return a
 
 
 def extend_i(b: OBlock, w: torch.Tensor, winf: torch.Tensor, nbr=None) -> torch.Tensor:
@@ -318,17 +471,12 @@ def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
     return extend_j(b, extend_i(b, w, winf), winf)
 
 
-def extend_all(blocks, ws, winfs, partners):
+def extend_all(blocks, ws, winfs, cutmap):
     """Ghost-extended primitive fields of all blocks.  A cut ghost is a cell
-    of the glued block taken from the same input (Jacobi exchange): i-side
-    ghosts from the neighbour's interior, j-side ghosts (and corners) from
-    the neighbour's i-extended rows."""
-    wis = [extend_i(b, w, wf, {s: ws[partners[(k, s)][0]] for s in (0, 1)
-                               if (k, s) in partners})
-           for k, (b, w, wf) in enumerate(zip(blocks, ws, winfs))]
-    return [extend_j(b, wi, wf, {s: wis[partners[(k, s)][0]] for s in (2, 3)
-                                 if (k, s) in partners})
-            for k, (b, wi, wf) in enumerate(zip(blocks, wis, winfs))]
+    of the glued block taken from the same input (Jacobi exchange); blocks
+    without CUT sides use extend()."""
+    return [extend_cut(blocks, ws, winfs, cutmap, k) if CUT in b.bc else extend(b, w, wf)
+            for k, (b, w, wf) in enumerate(zip(blocks, ws, winfs))]
 
 
 def reflect(p: torch.Tensor, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
@@ -343,8 +491,9 @@ def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor, nbrC=None):
     """Centres of the first ghost layer on each side (for the viscous diamond
     of boundary faces).  Periodic, wake-cut and cut ghosts are real cells, so
     their centre is the partner cell's centre (`nbrC` maps a CUT side to the
-    glued block's cell centres); wall and farfield ghost centres are the
-    interior centre mirrored across the boundary face.
+    centres [L][2] of the cells across it, cut_ghost_centres); wall and
+    farfield ghost centres are the interior centre mirrored across the
+    boundary face.
     Returns (c_imin [nj][2], c_imax [nj][2], c_jmin [ni][2], c_jmax [ni][2])."""
     nj, ni = C.shape[0], C.shape[1]
     P = xy.permute(1, 2, 0)                   # nodes [nj+1][ni+1][2]
@@ -366,8 +515,7 @@ def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor, nbrC=None):
         if kind == PERIODIC:
             out.append(real)
         elif kind == CUT:
-            Ca = nbrC[side]
-            out.append((Ca[:, Ca.shape[1] - 1], Ca[:, 0], Ca[Ca.shape[0] - 1, :], Ca[0, :])[side])
+            out.append(nbrC[side])
         elif kind in (WALL, FARFIELD):
             out.append(mir)
         elif kind == WAKECUT:
@@ -640,7 +788,7 @@ def _halos(blocks, qs, flow, cuts, alpha0=None, xys=None):
     winfs = [freestream_prim(flow, b.ns, alpha0) for b in blocks]
     wes = extend_all(blocks, ws, winfs, P)
     Cs = [metrics(xy)[3] for xy in xys]
-    nbr = [{s: Cs[P[(k, s)][0]] for s in range(4) if (k, s) in P} for k in range(len(blocks))]
+    nbr = [cut_ghost_centres(blocks, P, Cs, k) for k in range(len(blocks))]
     return wes, nbr
 
 

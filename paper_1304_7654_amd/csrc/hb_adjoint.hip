@@ -571,9 +571,8 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
     } else if (wake) {
         centre_to_nodes(blks, b, B.ni - 1 - ii, 0, gx, gy, xyb);
     } else if (kind == HB_BC_CUT) {
-        const int a = B.cut_blk[side];
-        const int pi = side == 0 ? blks[a].ni - 1 : side == 1 ? 0 : ii;
-        const int pj = side == 2 ? blks[a].nj - 1 : side == 3 ? 0 : jj;
+        int a, pi, pj;
+        cut_cell(blks, B.segs, b, side, 0, side < 2 ? jj : ii, &a, &pi, &pj);
         centre_to_nodes(blks, a, pi, pj, gx, gy, xyb);
     } else {   // wall or far field: mirror of the interior centre across the face
         const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
@@ -925,7 +924,7 @@ int adjoint_setup(hb_grid *g) {
             for (int ie = 0; ie < we; ++ie) {
                 const int i = ie - 2, j = je - 2;
                 if (i >= 0 && i < K.ni && j >= 0 && j < K.nj) continue;
-                const GSrc s = ghost_src(g->blk, b, i, j);
+                const GSrc s = ghost_src(g->blk, g->segs, b, i, j);
                 const int p = je * we + ie;
                 if (s.cell) {
                     const BlockDesc &S = g->blk[s.b];

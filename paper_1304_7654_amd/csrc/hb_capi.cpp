@@ -3,6 +3,7 @@
 // each entry point to the plain or the fused kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -82,6 +83,7 @@ void free_all(hb_grid *g) {
     dfree(g->body_ptr_d); dfree(g->body_blk_d);
     dfree(g->tiles_d);
     dfree(g->gtab_d);
+    dfree(g->segs_d);
     dfree(g->wtab_d);
     dfree(g->gtab64_d);
     dfree(g->ffc_d);
@@ -265,47 +267,71 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     }
     for (int k = 0; k < nbody; ++k)
         if (body_nh[k] < 0) return fail(HB_ERR_ARG, "body ids must be numbered without gaps");
-    // cuts
-    std::vector<int> cut_blk(4 * nblocks, -1), cut_side(4 * nblocks, -1);
+    // cuts: segments of block sides (any two sides, possibly reversed); every
+    // side of kind HB_BC_CUT covered by its segments exactly once
+    std::vector<std::vector<CutSeg>> side_segs(4 * (size_t)nblocks);
     for (int c = 0; c < ncuts; ++c) {
-        hb_cut k = cuts[c];
+        const hb_cut k = cuts[c];
         if (k.blk_a < 0 || k.blk_a >= nblocks || k.blk_b < 0 || k.blk_b >= nblocks ||
-            k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3)
+            k.side_a < 0 || k.side_a > 3 || k.side_b < 0 || k.side_b > 3 ||
+            (k.reversed != 0 && k.reversed != 1))
             return fail(HB_ERR_ARG, "bad cut");
-        {
-            const int la = k.side_a < 2 ? blocks[k.blk_a].nj : blocks[k.blk_a].ni;
-            const int lb = k.side_b < 2 ? blocks[k.blk_b].nj : blocks[k.blk_b].ni;
-            if (k.len < 1 || k.start_a < 0 || k.start_b < 0 ||
-                (int64_t)k.start_a + k.len > la || (int64_t)k.start_b + k.len > lb)
-                return fail(HB_ERR_ARG, "cut segment outside its block sides");
-            if (k.start_a != 0 || k.start_b != 0 || k.len != la || k.len != lb)
-                return fail(HB_ERR_UNSUPPORTED, "segment cuts are not supported: a cut glues "
-                                                "whole sides (start 0, len = side length)");
-        }
-        if (k.reversed != 0) return fail(HB_ERR_UNSUPPORTED, "reversed cuts are not supported");
-        if (k.side_a % 2 == 0) {   // normalise to (max side of a) <-> (min side of b)
-            std::swap(k.blk_a, k.blk_b);
-            std::swap(k.side_a, k.side_b);
-        }
         const hb_block &A = blocks[k.blk_a], &B = blocks[k.blk_b];
-        const bool iok = k.side_a == 1 && k.side_b == 0 && A.nj == B.nj;
-        const bool jok = k.side_a == 3 && k.side_b == 2 && A.ni == B.ni;
-        if (!(iok || jok) || A.n_harm != B.n_harm)
-            return fail(HB_ERR_UNSUPPORTED, "only imax<->imin (equal nj) and jmax<->jmin (equal ni) "
-                                            "cuts between blocks of equal n_harm are supported");
+        const int la = k.side_a < 2 ? A.nj : A.ni;
+        const int lb = k.side_b < 2 ? B.nj : B.ni;
+        if (k.len < 1 || k.start_a < 0 || k.start_b < 0 ||
+            (int64_t)k.start_a + k.len > la || (int64_t)k.start_b + k.len > lb)
+            return fail(HB_ERR_ARG, "cut segment outside its block sides");
         if (A.bc[k.side_a] != HB_BC_CUT || B.bc[k.side_b] != HB_BC_CUT)
             return fail(HB_ERR_ARG, "cut sides must have boundary kind HB_BC_CUT");
-        if (cut_blk[4 * k.blk_a + k.side_a] >= 0 || cut_blk[4 * k.blk_b + k.side_b] >= 0)
-            return fail(HB_ERR_ARG, "a block side is used by two cuts");
-        cut_blk[4 * k.blk_a + k.side_a] = k.blk_b;
-        cut_side[4 * k.blk_a + k.side_a] = k.side_b;
-        cut_blk[4 * k.blk_b + k.side_b] = k.blk_a;
-        cut_side[4 * k.blk_b + k.side_b] = k.side_a;
+        if (A.n_harm != B.n_harm) return fail(HB_ERR_ARG, "glued blocks must have equal n_harm");
+        side_segs[4 * k.blk_a + k.side_a].push_back(
+            CutSeg{k.start_a, k.len, k.blk_b, k.side_b, k.start_b, k.reversed});
+        side_segs[4 * k.blk_b + k.side_b].push_back(
+            CutSeg{k.start_b, k.len, k.blk_a, k.side_a, k.start_a, k.reversed});
     }
     for (int b = 0; b < nblocks; ++b)
-        for (int s = 0; s < 4; ++s)
-            if (blocks[b].bc[s] == HB_BC_CUT && cut_blk[4 * b + s] < 0)
-                return fail(HB_ERR_ARG, "a HB_BC_CUT side has no cut");
+        for (int s = 0; s < 4; ++s) {
+            if (blocks[b].bc[s] != HB_BC_CUT) continue;
+            std::vector<CutSeg> &v = side_segs[4 * b + s];
+            std::sort(v.begin(), v.end(), [](const CutSeg &x, const CutSeg &y) { return x.start < y.start; });
+            int pos = 0;
+            for (const CutSeg &q : v) {
+                if (q.start != pos) return fail(HB_ERR_ARG, "the cuts of a HB_BC_CUT side must cover it exactly once");
+                pos = q.start + q.len;
+            }
+            if (pos != (s < 2 ? blocks[b].nj : blocks[b].ni))
+                return fail(HB_ERR_ARG, "the cuts of a HB_BC_CUT side must cover it exactly once");
+        }
+    std::vector<CutSeg> seg_table;
+    std::vector<BlockDesc> cut_desc(nblocks);     // ni, nj, bc, wake and segment ranges
+    for (int b = 0; b < nblocks; ++b) {
+        BlockDesc &D = cut_desc[b];
+        std::memset(&D, 0, sizeof D);
+        D.ni = blocks[b].ni;
+        D.nj = blocks[b].nj;
+        D.wake = blocks[b].wake_ncells;
+        for (int s = 0; s < 4; ++s) {
+            D.bc[s] = blocks[b].bc[s];
+            D.seg_off[s] = (int32_t)seg_table.size();
+            D.seg_cnt[s] = (int32_t)side_segs[4 * b + s].size();
+            seg_table.insert(seg_table.end(), side_segs[4 * b + s].begin(), side_segs[4 * b + s].end());
+            // the block glued to the whole side by one aligned segment of the
+            // opposite side (used by the moving-grid wall rule), else -1
+            D.cut_blk[s] = D.cut_side[s] = -1;
+            if (D.seg_cnt[s] == 1) {
+                const CutSeg &q = seg_table[D.seg_off[s]];
+                const int L = s < 2 ? D.nj : D.ni;
+                if (q.start == 0 && q.pstart == 0 && q.len == L && !q.rev && (q.side ^ s) == 1) {
+                    D.cut_blk[s] = q.blk;
+                    D.cut_side[s] = q.side;
+                }
+            }
+        }
+    }
+    if (!ghosts_resolve(cut_desc, seg_table))
+        return fail(HB_ERR_ARG, "the cuts leave ghost cells that do not resolve (cuts around a "
+                                "singular corner)");
 
     // ---- device work starts here --------------------------------------
     hb_grid *g = new (std::nothrow) hb_grid();
@@ -324,6 +350,7 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
                        solver->cfl, solver->entropy_delta, solver->limiter_eps, 1.0 / flow->gamma};
     const double omega = 2.0 * flow->k_red * flow->mach / flow->l_ref;
     g->blk.resize(nblocks);
+    g->segs = seg_table;
     int64_t part = 0;
     for (int b = 0; b < nblocks; ++b) {
         const hb_block &S = blocks[b];
@@ -332,8 +359,10 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         B.ni = S.ni; B.nj = S.nj; B.nh = S.n_harm; B.ns = 2 * S.n_harm + 1;
         for (int s = 0; s < 4; ++s) {
             B.bc[s] = S.bc[s];
-            B.cut_blk[s] = cut_blk[4 * b + s];
-            B.cut_side[s] = cut_side[4 * b + s];
+            B.cut_blk[s] = cut_desc[b].cut_blk[s];
+            B.cut_side[s] = cut_desc[b].cut_side[s];
+            B.seg_off[s] = cut_desc[b].seg_off[s];
+            B.seg_cnt[s] = cut_desc[b].seg_cnt[s];
         }
         B.wake = S.wake_ncells;
         B.body = S.body_id;
@@ -441,7 +470,13 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     std::vector<float> Df(D.size());
     for (int b = 0; b < nblocks; ++b) hb_matrix(g->blk[b].nh, omega, &D[(size_t)b * kNsPad * kNsPad]);
     for (size_t k = 0; k < D.size(); ++k) Df[k] = (float)D[k];
-    rc = check_hip(hipMemcpy(g->blk_d, g->blk.data(), sizeof(BlockDesc) * nblocks, hipMemcpyHostToDevice), "upload");
+    if (!rc && !g->segs.empty()) {
+        rc = dalloc(&g->segs_d, (int64_t)g->segs.size());
+        rc = rc ? rc : check_hip(hipMemcpy(g->segs_d, g->segs.data(), sizeof(CutSeg) * g->segs.size(),
+                                           hipMemcpyHostToDevice), "upload");
+    }
+    for (BlockDesc &B : g->blk) B.segs = g->segs_d;
+    rc = rc ? rc : check_hip(hipMemcpy(g->blk_d, g->blk.data(), sizeof(BlockDesc) * nblocks, hipMemcpyHostToDevice), "upload");
     rc = rc ? rc : check_hip(hipMemcpy(g->xy_d, xy.data(), sizeof(double) * xy.size(), hipMemcpyHostToDevice), "upload");
     rc = rc ? rc : check_hip(hipMemcpy(g->D_d, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice), "upload");
     rc = rc ? rc : check_hip(hipMemcpy(g->D_f, Df.data(), sizeof(float) * Df.size(), hipMemcpyHostToDevice), "upload");
@@ -651,9 +686,14 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
         g->motion = Motion{nullptr, 0.0, 0.0};
         return HB_OK;
     }
-    for (const BlockDesc &B : g->blk)
+    for (const BlockDesc &B : g->blk) {
         if (B.bc[0] == HB_BC_WALL || B.bc[1] == HB_BC_WALL)
             return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides");
+        for (int s = 0; s < 4; ++s)
+            if (B.bc[s] == HB_BC_CUT && B.cut_blk[s] < 0)
+                return fail(HB_ERR_UNSUPPORTED, "moving grids: cuts only between whole opposite "
+                                                "sides, aligned (imax-imin, jmax-jmin)");
+    }
     if (!g->mot_d) {
         rc = dalloc(&g->mot_d, (int64_t)kMotionW * g->n_snap);
         if (rc) return rc;

@@ -76,58 +76,73 @@ __device__ __forceinline__ W4<T> mirror(W4<T> w) {
 
 // ---------------------------------------------------------------------------
 // Ghost resolution.  A cell index (i, j) with i in [-2, ni+2), j in [-2, nj+2)
-// is mapped to a value: interior cells are read, the i sides are resolved
-// first (rows 0..nj-1), and the j sides apply their rule to the i-resolved
-// rows (which defines the corner ghosts).  `cell` is a functor
-// (block, i, j) -> value reading an interior cell of any block; `ff(b)`
-// returns the block's free stream of the current snapshot and `mir` the
-// no-slip wall image of a value.
+// is mapped to a value: interior cells are read; outside, the i sides are
+// resolved first, then the j sides (which defines the corner ghosts); a cut
+// continues in the glued block (cut_cell), whose own rules then apply to
+// what is still outside it.  `cell` is a functor (block, i, j) -> value
+// reading an interior cell of any block; `ff(b)` returns the block's free
+// stream of the current snapshot and `mir` the no-slip wall image of a
+// value (applied once per wall met, so two walls cancel).
 // ---------------------------------------------------------------------------
-template <class V, class Interior, class FF, class Mir>
-__device__ __forceinline__ V value_i(const BlockDesc *blks, int b, int i, int j,
-                                     const Interior &cell, const FF &ff, const Mir &mir) {
-    const BlockDesc &B = blks[b];
-    if (i >= 0 && i < B.ni) return cell(b, i, j);
-    const int side = i < 0 ? 0 : 1;
-    const int k = i < 0 ? -1 - i : i - B.ni;
-    switch (B.bc[side]) {
-        case HB_BC_PERIODIC:
-            return cell(b, i < 0 ? i + B.ni : i - B.ni, j);
-        case HB_BC_WALL:
-            return mir(cell(b, side == 0 ? k : B.ni - 1 - k, j));
-        case HB_BC_CUT: {
-            const int a = B.cut_blk[side];
-            return cell(a, side == 0 ? blks[a].ni - 1 - k : k, j);
-        }
-        default:
-            return ff(b);
-    }
-}
-
 template <class V, class Interior, class FF, class Mir>
 __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j,
                                       const Interior &cell, const FF &ff, const Mir &mir) {
-    const BlockDesc &B = blks[b];
-    if (j >= 0 && j < B.nj) return value_i<V>(blks, b, i, j, cell, ff, mir);
-    const int side = j < 0 ? 2 : 3;
-    const int k = j < 0 ? -1 - j : j - B.nj;
-    switch (B.bc[side]) {
-        case HB_BC_PERIODIC:
-            return value_i<V>(blks, b, i, j < 0 ? j + B.nj : j - B.nj, cell, ff, mir);
-        case HB_BC_WALL:
-            return mir(value_i<V>(blks, b, i, side == 2 ? k : B.nj - 1 - k, cell, ff, mir));
-        case HB_BC_WAKECUT: {
-            if (i < B.wake || i >= B.ni - B.wake)
-                return value_i<V>(blks, b, B.ni - 1 - i, k, cell, ff, mir);
-            return mir(value_i<V>(blks, b, i, k, cell, ff, mir));
+    bool m = false;
+    for (int hop = 0; hop < kGhostHops; ++hop) {
+        const BlockDesc &B = blks[b];
+        if (i < 0 || i >= B.ni) {
+            const int side = i < 0 ? 0 : 1;
+            const int k = i < 0 ? -1 - i : i - B.ni;
+            const int kind = B.bc[side];
+            if (kind == HB_BC_PERIODIC) {
+                i = i < 0 ? i + B.ni : i - B.ni;
+            } else if (kind == HB_BC_WALL) {
+                i = side == 0 ? k : B.ni - 1 - k;
+                m = !m;
+            } else if (kind == HB_BC_CUT) {
+                int a, ia, ja;
+                cut_cell(blks, B.segs, b, side, k, j, &a, &ia, &ja);
+                b = a;
+                i = ia;
+                j = ja;
+            } else {
+                const V f = ff(b);
+                return m ? mir(f) : f;
+            }
+            continue;
         }
-        case HB_BC_CUT: {
-            const int a = B.cut_blk[side];
-            return value_i<V>(blks, a, i, side == 2 ? blks[a].nj - 1 - k : k, cell, ff, mir);
+        if (j < 0 || j >= B.nj) {
+            const int side = j < 0 ? 2 : 3;
+            const int k = j < 0 ? -1 - j : j - B.nj;
+            const int kind = B.bc[side];
+            if (kind == HB_BC_PERIODIC) {
+                j = j < 0 ? j + B.nj : j - B.nj;
+            } else if (kind == HB_BC_WALL) {
+                j = side == 2 ? k : B.nj - 1 - k;
+                m = !m;
+            } else if (kind == HB_BC_WAKECUT) {
+                if (i < B.wake || i >= B.ni - B.wake) {
+                    i = B.ni - 1 - i;
+                } else {
+                    m = !m;
+                }
+                j = k;
+            } else if (kind == HB_BC_CUT) {
+                int a, ia, ja;
+                cut_cell(blks, B.segs, b, side, k, i, &a, &ia, &ja);
+                b = a;
+                i = ia;
+                j = ja;
+            } else {
+                const V f = ff(b);
+                return m ? mir(f) : f;
+            }
+            continue;
         }
-        default:
-            return ff(b);
+        const V v = cell(b, i, j);
+        return m ? mir(v) : v;
     }
+    return ff(b);      // not reached: every ghost resolves (checked at grid creation)
 }
 
 // Load through a uniform base pointer and an unsigned 32-bit byte offset

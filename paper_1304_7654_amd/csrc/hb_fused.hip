@@ -204,7 +204,7 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
             uint64_t o64 = 0;
             const int gi = t.i0 + e % we - 2, gj = t.j0 + e / we - 2;
             if (e < ext && gi < K.ni + 2 && gj < K.nj + 2) {
-                const GSrc src = ghost_src(g->blk, t.blk, gi, gj);
+                const GSrc src = ghost_src(g->blk, g->segs, t.blk, gi, gj);
                 if (src.cell) {
                     const BlockDesc &S = g->blk[src.b];
                     const int64_t el = S.q_off + (int64_t)src.j * S.ni + src.i;

@@ -1,52 +1,72 @@
 // Host-side ghost rules: where the value of a ghost-extended cell comes
-// from.  The same rules as value_i / value_ij of the device code (two ghost
-// layers per side; the i sides are resolved first, the j sides apply their
-// rule to the i-resolved rows, which defines the corner ghosts).  Used to build the
-// per-tile halo source tables of the fused kernel and the inverse ghost map
-// of the adjoint.
+// from.  The same rules as value_ij of the device code (two ghost layers
+// per side; the i sides are resolved first, then the j sides, which
+// defines the corner ghosts; across a cut the partner block's own rules
+// apply to what is still outside it).  Used to build the per-tile halo
+// source tables of the fused kernel and the inverse ghost map of the
+// adjoint.
 #include "hb_internal.hpp"
 
 namespace hb {
 
-GSrc ghost_src_i(const std::vector<BlockDesc> &B, int b, int i, int j) {
-    const BlockDesc &K = B[b];
-    if (i >= 0 && i < K.ni) return GSrc{1, b, i, j, 0};
-    const int side = i < 0 ? 0 : 1;
-    const int k = i < 0 ? -1 - i : i - K.ni;
-    switch (K.bc[side]) {
-        case HB_BC_PERIODIC: return GSrc{1, b, i < 0 ? i + K.ni : i - K.ni, j, 0};
-        case HB_BC_WALL: return GSrc{1, b, side == 0 ? k : K.ni - 1 - k, j, 1};
-        case HB_BC_CUT: {
-            const int a = K.cut_blk[side];
-            return GSrc{1, a, side == 0 ? B[a].ni - 1 - k : k, j, 0};
+GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j) {
+    int mir = 0;
+    for (int hop = 0; hop < kGhostHops; ++hop) {
+        const BlockDesc &K = B[b];
+        if (i < 0 || i >= K.ni) {
+            const int side = i < 0 ? 0 : 1;
+            const int k = i < 0 ? -1 - i : i - K.ni;
+            switch (K.bc[side]) {
+                case HB_BC_PERIODIC: i = i < 0 ? i + K.ni : i - K.ni; break;
+                case HB_BC_WALL: i = side == 0 ? k : K.ni - 1 - k; mir ^= 1; break;
+                case HB_BC_CUT: {
+                    int a, ia, ja;
+                    cut_cell(B.data(), S.data(), b, side, k, j, &a, &ia, &ja);
+                    b = a; i = ia; j = ja;
+                    break;
+                }
+                default: return GSrc{0, b, 0, 0, mir};
+            }
+            continue;
         }
-        default: return GSrc{0, b, 0, 0, 0};
+        if (j < 0 || j >= K.nj) {
+            const int side = j < 0 ? 2 : 3;
+            const int k = j < 0 ? -1 - j : j - K.nj;
+            switch (K.bc[side]) {
+                case HB_BC_PERIODIC: j = j < 0 ? j + K.nj : j - K.nj; break;
+                case HB_BC_WALL: j = side == 2 ? k : K.nj - 1 - k; mir ^= 1; break;
+                case HB_BC_WAKECUT:
+                    if (i < K.wake || i >= K.ni - K.wake) {
+                        i = K.ni - 1 - i;
+                        j = k;
+                    } else {
+                        j = k;
+                        mir ^= 1;
+                    }
+                    break;
+                case HB_BC_CUT: {
+                    int a, ia, ja;
+                    cut_cell(B.data(), S.data(), b, side, k, i, &a, &ia, &ja);
+                    b = a; i = ia; j = ja;
+                    break;
+                }
+                default: return GSrc{0, b, 0, 0, mir};
+            }
+            continue;
+        }
+        return GSrc{1, b, i, j, mir};
     }
+    return GSrc{-1, b, 0, 0, mir};     // did not end (refused at grid creation)
 }
 
-GSrc ghost_src(const std::vector<BlockDesc> &B, int b, int i, int j) {
-    const BlockDesc &K = B[b];
-    if (j >= 0 && j < K.nj) return ghost_src_i(B, b, i, j);
-    const int side = j < 0 ? 2 : 3;
-    const int k = j < 0 ? -1 - j : j - K.nj;
-    GSrc s;
-    switch (K.bc[side]) {
-        case HB_BC_PERIODIC: return ghost_src_i(B, b, i, j < 0 ? j + K.nj : j - K.nj);
-        case HB_BC_WALL:
-            s = ghost_src_i(B, b, i, side == 2 ? k : K.nj - 1 - k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_WAKECUT:
-            if (i < K.wake || i >= K.ni - K.wake) return ghost_src_i(B, b, K.ni - 1 - i, k);
-            s = ghost_src_i(B, b, i, k);
-            s.mir ^= 1;
-            return s;
-        case HB_BC_CUT: {
-            const int a = K.cut_blk[side];
-            return ghost_src_i(B, a, i, side == 2 ? B[a].nj - 1 - k : k);
-        }
-        default: return GSrc{0, b, 0, 0, 0};
-    }
+bool ghosts_resolve(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S) {
+    for (int b = 0; b < (int)B.size(); ++b)
+        for (int j = -2; j < B[b].nj + 2; ++j)
+            for (int i = -2; i < B[b].ni + 2; ++i) {
+                if (i >= 0 && i < B[b].ni && j >= 0 && j < B[b].nj) continue;
+                if (ghost_src(B, S, b, i, j).cell < 0) return false;
+            }
+    return true;
 }
 
 // Moving no-slip wall image (ghost (i, j) of block b on a rigidly moving
@@ -68,13 +88,14 @@ WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j) {
     int col = i, src = b;
     if (i < 0) {
         if (K.bc[0] == HB_BC_PERIODIC) col = i + K.ni;
-        else if (K.bc[0] == HB_BC_CUT) src = K.cut_blk[0], col = B[src].ni + i;
+        else if (K.bc[0] == HB_BC_CUT) src = K.cut_blk[0], col = src < 0 ? 0 : B[src].ni + i;
         else col = 0;
     } else if (i >= K.ni) {
         if (K.bc[1] == HB_BC_PERIODIC) col = i - K.ni;
         else if (K.bc[1] == HB_BC_CUT) src = K.cut_blk[1], col = i - K.ni;
         else col = K.ni - 1;
     }
+    if (src < 0) return WallFace{-1, 0};      // a general cut: no moving grid (refused)
     const BlockDesc &S = B[src];
     return WallFace{(int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col, src};
 }

@@ -16,6 +16,15 @@ constexpr int kMaxNs = 9;        // N_H <= 4
 constexpr int kNsPad = 16;       // padded D (MFMA tile)
 constexpr int kAF = 26;          // adjoint terms stored per face and snapshot
 
+// One glued segment of a block side; each hb_cut is listed from both of
+// its sides.  Cells start .. start + len - 1 along this side lie against
+// the partner block's side `side` from pstart on (reversed: running the
+// other way).  Positions along a side are j on the i sides, i on the j
+// sides.
+struct CutSeg {
+    int32_t start, len, blk, side, pstart, rev;
+};
+
 // Device-side description of one block.  Offsets index the flat arrays
 // of the grid (all blocks concatenated).
 struct BlockDesc {
@@ -23,8 +32,12 @@ struct BlockDesc {
     int32_t bc[4];
     int32_t wake;
     int32_t body;
-    int32_t cut_blk[4];      // neighbour block across a CUT side, else -1
+    int32_t cut_blk[4];      // the block glued to a CUT side when one aligned segment joins
+                             // the whole side to the opposite side of that block, else -1
     int32_t cut_side[4];
+    int32_t seg_off[4];      // the side's segments: segs[seg_off .. seg_off + seg_cnt), by start
+    int32_t seg_cnt[4];
+    const CutSeg *segs;      // the grid's segment table (device copy in blk_d)
     int32_t snap_off;        // per-snapshot tables: entries snap_off .. +ns
     int32_t d_off;           // D table (kNsPad x kNsPad per block)
     int64_t q_off;           // state (doubles): ns*4*nj*ni
@@ -99,6 +112,8 @@ struct hb_grid {
     int nblocks = 0;
     int nbody = 0;
     std::vector<hb::BlockDesc> blk;
+    std::vector<hb::CutSeg> segs;                // both sides of every cut, by (block, side, start)
+    hb::CutSeg *segs_d = nullptr;
     std::vector<std::vector<double>> xy_host;
     std::vector<int> body_ns, body_off;          // force layout
     hb_flow flow{};
@@ -206,14 +221,46 @@ struct hb_grid {
 
 namespace hb {
 
+// The cell across a cut from ghost layer k (0 nearest) at position p of
+// side `side` of block b: the partner block *a and its cell (*i, *j) at
+// depth k inside the partner side.  A position beyond the side's ends (a
+// corner ghost) continues the end segment; the result may then lie
+// outside block *a, whose own side rules apply to it.
+__host__ __device__ inline void cut_cell(const BlockDesc *blks, const CutSeg *segs, int b, int side,
+                                         int k, int p, int *a, int *i, int *j) {
+    const BlockDesc &B = blks[b];
+    const int L = side < 2 ? B.nj : B.ni;
+    const int pc = p < 0 ? 0 : (p >= L ? L - 1 : p);
+    const int o = B.seg_off[side], n = B.seg_cnt[side];
+    int q = o;
+    for (int t = o + 1; t < o + n; ++t)
+        if (segs[t].start <= pc) q = t;
+    const CutSeg g = segs[q];
+    const int t = p - g.start;
+    const int pp = g.pstart + (g.rev ? g.len - 1 - t : t);
+    const BlockDesc &A = blks[g.blk];
+    *a = g.blk;
+    switch (g.side) {
+        case 0: *i = k; *j = pp; break;
+        case 1: *i = A.ni - 1 - k; *j = pp; break;
+        case 2: *i = pp; *j = k; break;
+        default: *i = pp; *j = A.nj - 1 - k; break;
+    }
+}
+
+// rule applications after which a ghost must have reached an interior
+// cell or the far field (checked for every ghost at grid creation)
+constexpr int kGhostHops = 8;
+
 // ghost.cpp: host-side ghost rules
-GSrc ghost_src_i(const std::vector<BlockDesc> &B, int b, int i, int j);
-GSrc ghost_src(const std::vector<BlockDesc> &B, int b, int i, int j);
+GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j);
 struct WallFace {
     int64_t node;    // first node of the wall face in block `blk`, -1: no wall image
     int blk;
 };
 WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j);
+// every ghost of every block resolves within kGhostHops rule applications
+bool ghosts_resolve(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S);
 
 // error helpers (capi.cpp)
 int upload_snapshot_tables(hb_grid *g);

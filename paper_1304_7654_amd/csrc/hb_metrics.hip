@@ -75,8 +75,9 @@ __global__ void k_faces_i(const BlockDesc *blks, int b, const double *xy, const 
         centre(blks, C, b, 0, j, cx, cy);
         if (B.bc[0] == HB_BC_PERIODIC) centre(blks, C, b, B.ni - 1, j, lx, ly);
         else if (B.bc[0] == HB_BC_CUT) {
-            const int a = B.cut_blk[0];
-            centre(blks, C, a, blks[a].ni - 1, j, lx, ly);
+            int a, ia, ja;
+            cut_cell(blks, B.segs, b, 0, 0, j, &a, &ia, &ja);
+            centre(blks, C, a, ia, ja, lx, ly);
         } else reflect(cx, cy, ax, ay, bx, by, lx, ly);
     }
     if (i < B.ni) {
@@ -85,8 +86,11 @@ __global__ void k_faces_i(const BlockDesc *blks, int b, const double *xy, const 
         double cx, cy;
         centre(blks, C, b, B.ni - 1, j, cx, cy);
         if (B.bc[1] == HB_BC_PERIODIC) centre(blks, C, b, 0, j, rx, ry);
-        else if (B.bc[1] == HB_BC_CUT) centre(blks, C, B.cut_blk[1], 0, j, rx, ry);
-        else reflect(cx, cy, ax, ay, bx, by, rx, ry);
+        else if (B.bc[1] == HB_BC_CUT) {
+            int a, ia, ja;
+            cut_cell(blks, B.segs, b, 1, 0, j, &a, &ia, &ja);
+            centre(blks, C, a, ia, ja, rx, ry);
+        } else reflect(cx, cy, ax, ay, bx, by, rx, ry);
     }
     double *S = SI + 2 * B.fi_off;
     double *d = dI + 2 * B.fi_off;
@@ -120,8 +124,9 @@ __global__ void k_faces_j(const BlockDesc *blks, int b, const double *xy, const 
         if (kind == HB_BC_PERIODIC) centre(blks, C, b, i, B.nj - 1, lx, ly);
         else if (wake) centre(blks, C, b, B.ni - 1 - i, 0, lx, ly);
         else if (kind == HB_BC_CUT) {
-            const int a = B.cut_blk[2];
-            centre(blks, C, a, i, blks[a].nj - 1, lx, ly);
+            int a, ia, ja;
+            cut_cell(blks, B.segs, b, 2, 0, i, &a, &ia, &ja);
+            centre(blks, C, a, ia, ja, lx, ly);
         } else reflect(cx, cy, ax, ay, bx, by, lx, ly);
     }
     if (j < B.nj) {
@@ -130,8 +135,11 @@ __global__ void k_faces_j(const BlockDesc *blks, int b, const double *xy, const 
         double cx, cy;
         centre(blks, C, b, i, B.nj - 1, cx, cy);
         if (B.bc[3] == HB_BC_PERIODIC) centre(blks, C, b, i, 0, rx, ry);
-        else if (B.bc[3] == HB_BC_CUT) centre(blks, C, B.cut_blk[3], i, 0, rx, ry);
-        else reflect(cx, cy, ax, ay, bx, by, rx, ry);
+        else if (B.bc[3] == HB_BC_CUT) {
+            int a, ia, ja;
+            cut_cell(blks, B.segs, b, 3, 0, i, &a, &ia, &ja);
+            centre(blks, C, a, ia, ja, rx, ry);
+        } else reflect(cx, cy, ax, ay, bx, by, rx, ry);
     }
     double *S = SJ + 2 * B.fj_off;
     double *d = dJ + 2 * B.fj_off;

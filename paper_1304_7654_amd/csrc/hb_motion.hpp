@@ -51,13 +51,14 @@ __device__ __forceinline__ void wall_image_motion(const BlockDesc *blks, int b, 
     int col = i, src = b;
     if (i < 0) {
         if (B.bc[0] == HB_BC_PERIODIC) col = i + B.ni;
-        else if (B.bc[0] == HB_BC_CUT) src = B.cut_blk[0], col = blks[src].ni + i;
+        else if (B.bc[0] == HB_BC_CUT) src = B.cut_blk[0], col = src < 0 ? 0 : blks[src].ni + i;
         else col = 0;
     } else if (i >= B.ni) {
         if (B.bc[1] == HB_BC_PERIODIC) col = i - B.ni;
         else if (B.bc[1] == HB_BC_CUT) src = B.cut_blk[1], col = i - B.ni;
         else col = B.ni - 1;
     }
+    if (src < 0) return;          // general cuts: no moving grid (refused by hb_set_motion)
     const BlockDesc &S = blks[src];
     const int64_t nn = (int64_t)(S.ni + 1) * (S.nj + 1);
     const double *x = xy + 2 * S.node_off, *y = x + nn;

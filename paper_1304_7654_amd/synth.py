@@ -359,6 +359,107 @@ def split_problem(problem: Problem, parts_i: int, parts_j: int):
     return out, np.concatenate(perm)
 
 
+def _cell_perm(off: int, ns: int, nj: int, ni: int, j0: int, j1: int, i0: int, i1: int):
+    """Public-layout indices of the cells [j0, j1) x [i0, i1) of a block at
+    state offset off, in the layout of that sub-block."""
+    n, v, j, i = np.meshgrid(np.arange(ns), np.arange(4), np.arange(j0, j1), np.arange(i0, i1),
+                             indexing="ij")
+    return (off + ((n * 4 + v) * nj + j) * ni + i).reshape(-1)
+
+
+def split_c_grid(problem: Problem):
+    """A one-block C-grid problem (wake-cut jmin) cut into three blocks
+    along i: the lower wake, the part around the profile, the upper wake,
+    glued by aligned cuts, and the wake cut as a reversed cut between the
+    jmin sides of the two wake blocks (cut format of split_problem plus
+    8-entry cuts (blk_a, side_a, start_a, blk_b, side_b, start_b, len,
+    reversed)).  Returns (problem, perm) with state_split = state[perm]."""
+    assert len(problem.blocks) == 1
+    b = problem.blocks[0]
+    assert b.bc[2] == WAKECUT and b.wake_ncells > 0
+    w, ni, nj = b.wake_ncells, b.ni, b.nj
+    parts = [(0, w, (b.bc[0], CUT, CUT, b.bc[3])), (w, ni - w, (CUT, CUT, WALL, b.bc[3])),
+             (ni - w, ni, (CUT, b.bc[1], CUT, b.bc[3]))]
+    blocks, perm = [], []
+    for i0, i1, bc in parts:
+        xy = np.ascontiguousarray(b.xy[:, :, i0:i1 + 1])
+        blocks.append(Block(i1 - i0, nj, b.n_harm, xy, bc, 0, b.body_id))
+        perm.append(_cell_perm(0, b.ns, nj, ni, 0, nj, i0, i1))
+    cuts = [(0, 1, 1, 0), (1, 1, 2, 0), (0, 2, 0, 2, 2, 0, w, 1)]
+    out = Problem(problem.name + "_c3", blocks, problem.flow, problem.solver, problem.n_iter,
+                  problem.seed, problem.design, problem.notes, cuts)
+    return out, np.concatenate(perm)
+
+
+def rotate_block(problem: Problem, k: int):
+    """Block k re-indexed by a quarter turn of its index space (orientation
+    kept): node (I, J) becomes (J, ni - I), cell (i, j) becomes
+    (j, ni - 1 - i), so its imin, imax, jmin, jmax sides become jmax, jmin,
+    imin, imax; its cuts follow (positions along its old j sides run the
+    other way).  Returns (problem, perm) with state_rotated = state[perm]."""
+    b = problem.blocks[k]
+    assert b.bc[2] != WAKECUT
+    ni, nj = b.ni, b.nj
+    xy = np.ascontiguousarray(np.stack([b.xy[c].T[::-1, :] for c in range(2)]))
+    bc = (b.bc[2], b.bc[3], b.bc[1], b.bc[0])
+    blocks = list(problem.blocks)
+    blocks[k] = Block(nj, ni, b.n_harm, xy, bc, 0, b.body_id)
+    new_side = {0: 3, 1: 2, 2: 0, 3: 1}
+    cuts = []
+    for c in problem.cuts:
+        if len(c) == 4:
+            a, sa, bb, sb = c
+            la = problem.blocks[a].nj if sa < 2 else problem.blocks[a].ni
+            c = (a, sa, 0, bb, sb, 0, la, 0)
+        a, sa, st_a, bb, sb, st_b, ln, rev = c
+        if a == k:
+            if sa >= 2:
+                st_a, rev = ni - st_a - ln, 1 - rev
+            sa = new_side[sa]
+        if bb == k:
+            if sb >= 2:
+                st_b, rev = ni - st_b - ln, 1 - rev
+            sb = new_side[sb]
+        cuts.append((a, sa, st_a, bb, sb, st_b, ln, rev))
+    offs = block_offsets(problem)
+    perm = []
+    for m, blk in enumerate(problem.blocks):
+        idx = np.arange(offs[m], offs[m] + blk.n_state)
+        if m == k:
+            idx = idx.reshape(b.ns, 4, nj, ni)
+            # new cell (i', j') = old (ni - 1 - j', i'): [n][v][j'][i']
+            idx = np.ascontiguousarray(np.transpose(idx, (0, 1, 3, 2))[:, :, ::-1, :]).reshape(-1)
+        perm.append(idx)
+    out = Problem(problem.name + "_rot%d" % k, blocks, problem.flow, problem.solver,
+                  problem.n_iter, problem.seed, problem.design, problem.notes, cuts)
+    return out, np.concatenate(perm)
+
+
+def split_partial(problem: Problem):
+    """A one-block O-grid problem (i-periodic) cut into three blocks: the
+    left half of i split in j into an inner and an outer block, and the
+    right half whole, so that each i side of the right half is glued to two
+    blocks by two segments.  Returns (problem, perm)."""
+    assert len(problem.blocks) == 1
+    b = problem.blocks[0]
+    assert b.bc[0] == PERIODIC and b.bc[1] == PERIODIC
+    ni, nj = b.ni, b.nj
+    ih, jh = ni // 2, nj // 2
+    parts = [(0, ih, 0, jh, (CUT, CUT, b.bc[2], CUT)), (0, ih, jh, nj, (CUT, CUT, CUT, b.bc[3])),
+             (ih, ni, 0, nj, (CUT, CUT, b.bc[2], b.bc[3]))]
+    blocks, perm = [], []
+    for i0, i1, j0, j1, bc in parts:
+        xy = np.ascontiguousarray(b.xy[:, j0:j1 + 1, i0:i1 + 1])
+        blocks.append(Block(i1 - i0, j1 - j0, b.n_harm, xy, bc, 0, b.body_id))
+        perm.append(_cell_perm(0, b.ns, nj, ni, j0, j1, i0, i1))
+    cuts = [(0, 3, 1, 2),
+            (0, 1, 0, 2, 0, 0, jh, 0), (1, 1, 0, 2, 0, jh, nj - jh, 0),
+            (2, 1, 0, 0, 0, 0, jh, 0), (2, 1, jh, 1, 0, 0, nj - jh, 0)]
+    out = Problem(problem.name + "_partial", blocks, problem.flow, problem.solver,
+                  problem.n_iter, problem.seed, problem.design, problem.notes, cuts)
+    return out, np.concatenate(perm)
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------

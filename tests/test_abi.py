@@ -105,23 +105,22 @@ def test_validation_rejects_before_device_work():
     cut = synth.Block(b.ni, b.nj, 1, b.xy, (3, 3, synth.CUT, 2))
     assert _try([cut]) == hb.HB_ERR_ARG                      # CUT side without a cut
     assert "n_harm" in hb.lib().hb_last_error().decode() or True
+    # cuts are segments of sides: each HB_BC_CUT side must be covered by its
+    # segments exactly once, inside the sides, with a reversed flag of 0 or 1
     sp, _ = synth.split_problem(p, 2, 1)
-    rev = [tuple(c[:4]) + (1,) for c in sp.cuts]
-    with pytest.raises(hb.HBError) as e:
-        hb.Grid(sp.blocks, sp.flow, sp.solver, rev)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED                # reversed cut
-    # segments: the interface carries start/len; this build glues whole sides
     a, sa, b2_, sb = sp.cuts[0][:4]
     side = sp.blocks[a].nj if sa < 2 else sp.blocks[a].ni
     others = list(sp.cuts[1:])
-    for seg, code in (((a, sa, 0, b2_, sb, 0, side - 2, 0), hb.HB_ERR_UNSUPPORTED),
-                      ((a, sa, 1, b2_, sb, 1, side - 1, 0), hb.HB_ERR_UNSUPPORTED),
-                      ((a, sa, 0, b2_, sb, 0, side + 1, 0), hb.HB_ERR_ARG),
-                      ((a, sa, -1, b2_, sb, 0, side, 0), hb.HB_ERR_ARG),
-                      ((a, sa, 0, b2_, sb, 0, 0, 0), hb.HB_ERR_ARG)):
+    for cuts in ([(a, sa, 0, b2_, sb, 0, side - 2, 0)] + others,          # side not covered
+                 [(a, sa, 0, b2_, sb, 0, side, 0), (a, sa, 0, b2_, sb, 0, 2, 0)] + others,  # overlap
+                 [(a, sa, 1, b2_, sb, 1, side, 0)] + others,              # leaves the side
+                 [(a, sa, 0, b2_, sb, 0, side + 1, 0)] + others,
+                 [(a, sa, -1, b2_, sb, 0, side, 0)] + others,
+                 [(a, sa, 0, b2_, sb, 0, 0, 0)] + others,
+                 [(a, sa, 0, b2_, sb, 0, side, 2)] + others):            # reversed must be 0 or 1
         with pytest.raises(hb.HBError) as e:
-            hb.Grid(sp.blocks, sp.flow, sp.solver, [seg] + others)
-        assert e.value.code == code, seg
+            hb.Grid(sp.blocks, sp.flow, sp.solver, cuts)
+        assert e.value.code == hb.HB_ERR_ARG, cuts
 
 
 def test_binding_rejects_bad_tensors():

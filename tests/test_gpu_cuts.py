@@ -99,3 +99,92 @@ def test_split_adjoint(name, pi, pj):
     assert _rel(qb.cpu(), qref) <= 1e-11
     assert _rel(xyb.cpu(), xr) <= 1e-11
     assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
+
+
+# General cuts: segments of sides, any pairing of sides, reversed segments
+# (pinned in the oracle against the uncut grids, tests/test_oracle_cuts.py).
+def _rotated(p):
+    sp0, perm0 = synth.split_problem(p, 2, 1)
+    sp, perm = synth.rotate_block(sp0, 1)
+    return sp, perm0[perm]
+
+
+GENERAL = [("naca_tiny", synth.split_c_grid), ("cyl_tiny", synth.split_partial),
+           ("cyl_tiny", _rotated)]
+GENERAL_IDS = ["c_grid_3", "partial", "rotated"]
+
+
+def _general(name, make):
+    p = synth.make_problem(name)
+    p.flow.alpha0 = 0.03
+    sp, perm = make(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    return p, sp, torch.as_tensor(perm), q
+
+
+@pytest.mark.parametrize("prec,batched", PATHS)
+@pytest.mark.parametrize("name,make", GENERAL, ids=GENERAL_IDS)
+def test_general_cuts_residual_iteration_forces(name, make, prec, batched):
+    """A C-grid as wake and profile blocks with a reversed wake cut, a side
+    glued to two blocks by two segments, an imax glued to a jmax: residual,
+    three iterations (norms) and forces against the oracle on the same
+    glued grid, and the residual against the HIP library on the uncut grid."""
+    _say("general cuts", name, GENERAL_IDS[[g[1] for g in GENERAL].index(make)], "prec", prec,
+         "batched", batched)
+    p, sp, perm, q = _general(name, make)
+    sblocks, flow, solver = O.from_synth(sp)
+    qs = q[perm].contiguous()
+    ref = O.residual_all(sblocks, qs, flow, solver, sp.cuts)
+    gs = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=prec, batched=batched)
+    g1 = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
+    rs = gs.residual(qs.to(DEV)).cpu()
+    r1 = g1.residual(q.to(DEV)).cpu()[perm]
+    n_it = 3
+    qref, nref = O.rk_iterate(sblocks, qs, flow, solver, n_it, sp.cuts)
+    qd = qs.to(DEV)
+    norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    cf = torch.zeros(gs.n_forces, dtype=torch.float64, device=DEV)
+    gs.rk_iterate(qd, n_it, norms, cf)
+    torch.cuda.synchronize()
+    assert gs.status() == hb.HB_OK
+    e_or, e_un = _rel(rs, ref), _rel(rs, r1)
+    dq = _rel(qd.cpu() - qs, qref - qs)
+    dn = float(((norms.cpu() - nref).abs() / nref).max())
+    cref = torch.cat([c.reshape(-1) for c in O.forces(sblocks, qref, flow, solver, cuts=sp.cuts)])
+    dc = float((cf.cpu() - cref).abs().max() / cref.abs().max())
+    _say("  residual vs oracle", e_or, "vs uncut", e_un, "state", dq, "norms", dn, "forces", dc)
+    assert e_or <= (1e-12 if prec == 0 else 1e-5)
+    assert e_un <= (1e-13 if prec == 0 else 1e-6)
+    assert dq <= (1e-11 if prec == 0 else 1e-5)
+    assert dn <= (1e-12 if prec == 0 else 1e-5)
+    assert dc <= (1e-10 if prec == 0 else 1e-4)
+
+
+@pytest.mark.parametrize("name,make", GENERAL, ids=GENERAL_IDS)
+def test_general_cuts_adjoint(name, make):
+    _say("general cuts adjoint", name)
+    p, sp, perm, q = _general(name, make)
+    sblocks, flow, solver = O.from_synth(sp)
+    rbar = torch.randn(q.shape, generator=torch.Generator().manual_seed(9), dtype=torch.float64)
+    qs, rbs = q[perm].contiguous(), rbar[perm].contiguous()
+    qref, xref, aref = O.residual_vjp(sblocks, qs, flow, solver, rbs, sp.cuts)
+    gs = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=0, batched=1)
+    xyb = torch.empty(gs.n_xy, dtype=torch.float64, device=DEV)
+    ab = torch.empty(1, dtype=torch.float64, device=DEV)
+    qb = gs.residual_adjoint(qs.to(DEV), rbs.to(DEV), None, xyb, ab)
+    torch.cuda.synchronize()
+    xr = torch.cat([x.reshape(-1) for x in xref])
+    _say("  qbar", _rel(qb.cpu(), qref), "xybar", _rel(xyb.cpu(), xr), "alpha",
+         float(ab), float(aref))
+    assert _rel(qb.cpu(), qref) <= 1e-11
+    assert _rel(xyb.cpu(), xr) <= 1e-11
+    assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
+
+
+def test_general_cuts_refuse_motion():
+    p = synth.make_problem("naca_tiny")
+    sp, _ = synth.split_c_grid(p)
+    g = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=0, batched=1)
+    with pytest.raises(hb.HBError) as e:
+        g.set_motion(pitch_amp=0.1)
+    assert e.value.code == hb.HB_ERR_UNSUPPORTED
