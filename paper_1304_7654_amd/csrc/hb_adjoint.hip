@@ -222,9 +222,11 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
              AF + B.afj_off + (int64_t)n * kAF * nf + f, nf);
 }
 
-// one launch for both face families of block b: threads [0, nI) take the
-// i-faces (all snapshots), the rest the j-faces; xcd: XCD-aware workgroup
-// order (launched with xcd_grid workgroups), else the launch order
+// one launch for both face families of block b: workgroup w takes i-face
+// items [128 w, 128 w + 128) with its first half and the j-face items of the
+// same range with its second (items snapshot-major, so both halves read the
+// same rows of the same snapshot); xcd: XCD-aware workgroup order
+// (launched with xcd_grid workgroups), else the launch order
 template <bool NT>
 __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b, const double *ext,
                                                    const double *SI, const double *dI,
@@ -232,11 +234,17 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
                                                    const double *rbar, Consts c, double *AFI,
                                                    double *AFJ, int64_t nI, int xcd) {
     const BlockDesc &B = blks[b];
-    const int64_t L = xcd ? xcd_group(nI + (int64_t)B.ni * (B.nj + 1) * B.ns) : (int64_t)blockIdx.x;
+    const int64_t nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
+    constexpr int kHalf = kBS / 2;
+    const int64_t W = ((nI > nJ ? nI : nJ) + kHalf - 1) / kHalf;
+    const int64_t L = xcd ? xcd_group(W * kBS) : (int64_t)blockIdx.x;
     if (L < 0) return;
-    const int64_t t = L * kBS + threadIdx.x;
-    if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, t);
-    else adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, t - nI);
+    const int64_t t = L * kHalf + (threadIdx.x % kHalf);
+    if (threadIdx.x < kHalf) {
+        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, t);
+    } else if (t < nJ) {
+        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, t);
+    }
 }
 
 // node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
@@ -1025,9 +1033,10 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const BlockDesc &B = g->blk[b];
         const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
         const bool nt = (double)kAF * 8.0 * (double)(nI + nJ) > 256.0 * (1 << 20);
-        hipLaunchKernelGGL(nt ? k_adj_faces<true> : k_adj_faces<false>, dim3(adj_grid(nI + nJ)),
+        const int64_t nw = 256 * (((nI > nJ ? nI : nJ) + 127) / 128);
+        hipLaunchKernelGGL(nt ? k_adj_faces<true> : k_adj_faces<false>, dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
-                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nI + nJ));
+                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw));
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
         hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
