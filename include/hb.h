@@ -247,7 +247,11 @@ int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
  *   xybar   = J_X^T rbar,  X = node coordinates    (hb_xy_size(), may be NULL)
  *   flowbar = J_a^T rbar,  a = alpha0              (1 double, may be NULL)
  * The reconstruction is recomputed, nothing is stored between calls.
- * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid).  The adjoints'
+ * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid).  With a motion set
+ * (hb_set_motion) the products are those of the moving-grid R* (snapshot
+ * n's rotated face vectors, face speeds, moving-wall images), the motion
+ * and the body-frame nodes held fixed; xybar must then be NULL
+ * (HB_ERR_UNSUPPORTED otherwise).  The adjoints'
  * scratch (the inverse ghost map, per-face adjoint terms: 26 doubles per
  * face and snapshot) is allocated by the first adjoint call unless
  * hb_prepare allocated it before. */
@@ -261,7 +265,8 @@ int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar,
  * (device, 1 double: d/d alpha0, may be NULL) receive (d cf / d .)^T cfbar,
  * overwritten.  Only wall faces contribute; alpha0 enters through the wind
  * axes and the far-field ghosts.  FP64 arithmetic on any grid.  qbar must
- * not alias q. */
+ * not alias q.  With a motion set: the moving-grid loads of hb_forces,
+ * xybar NULL (HB_ERR_UNSUPPORTED otherwise). */
 int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
                       double *qbar, double *xybar, double *flowbar, void *stream);
 
@@ -278,6 +283,7 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
  * (must alias neither); resnorm (device, n_iter doubles, may be NULL): RMS
  * over cells, snapshots and variables of (J_Q^T lambda + gq)/V at the first
  * stage of each iteration.  FP64 grids only (HB_ERR_UNSUPPORTED otherwise).
+ * With a motion set: the moving-grid products and local steps.
  * Scratch of 2.25 state sizes (and the adjoints' own) is allocated on the
  * first call unless hb_prepare allocated it before. */
 int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double *gq,
@@ -391,10 +397,12 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
 /* Set (m non-NULL with a non-zero amplitude) or clear (NULL, or both
  * amplitudes zero) the rigid grid motion described at hb_motion.  It then
  * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march, on the
- * per-block and on the batched path (FP64 and FP32 bulk).
+ * per-block and on the batched path (FP64 and FP32 bulk), and to the
+ * adjoints (FP64).
  * HB_ERR_UNSUPPORTED for blocks with walls on an i side or cuts other than
  * whole opposite sides glued aligned; while a motion is
- * set the adjoints and hb_set_xy return HB_ERR_UNSUPPORTED.  Across a cut,
+ * set hb_set_xy and coordinate adjoints (xybar non-NULL) return
+ * HB_ERR_UNSUPPORTED; the adjoints take the motion.  Across a cut,
  * the wall image of a corner ghost takes the glued block's wall face.
  * HB_ERR_ARG for non-finite values.  Drops the batched path's captured
  * iterations (the next hb_rk_iterate captures them again).  Synchronises

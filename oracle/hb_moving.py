@@ -160,16 +160,18 @@ def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Te
     return wall_images(b, O.extend(b, w, winf).clone(), xy, m, thd, h, hd)
 
 
-def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, cuts=()):
+def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, cuts=(),
+                     alpha0=None):
     """For every block k and snapshot n: (k, n, moved nodes, ghost-extended
     primitives with moving-wall images, moved centres of the glued blocks,
     (theta, theta_dot, h, h_dot)).  Cut ghosts are the glued block's cells of
-    the same snapshot (hb_oracle.extend_all); glued blocks share N_s."""
+    the same snapshot (hb_oracle.extend_all); glued blocks share N_s.
+    `alpha0` (a 0-d tensor) overrides the mean incidence of the far field."""
     P = O.cut_partners(blocks, cuts) if cuts else {}
     for b in blocks:
         check_block(b)
     ws = [O.primitives(qb, flow.gamma) for qb in qs]
-    winfs = [O.freestream_prim(flow, b.ns) for b in blocks]
+    winfs = [O.freestream_prim(flow, b.ns, alpha0) for b in blocks]
     for n in range(max(b.ns for b in blocks)):
         # a block with fewer snapshots stands in with its last one; no block
         # glued to it reads that (glued blocks share N_s)
@@ -243,11 +245,12 @@ def moving_td_march(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolv
 
 
 def moving_residual_all(blocks: Sequence[O.OBlock], q: torch.Tensor, flow, solver,
-                        m: OMotion, cuts=()) -> torch.Tensor:
-    """R* of all blocks on the moving grid; `cuts` glue block sides."""
+                        m: OMotion, cuts=(), alpha0=None) -> torch.Tensor:
+    """R* of all blocks on the moving grid; `cuts` glue block sides;
+    `alpha0` (a 0-d tensor) overrides the mean incidence."""
     qs = O.split(blocks, q)
     parts = [[None] * b.ns for b in blocks]
-    for k, n, xy, we, nbrC, (_, thd, h, hd) in moving_snapshots(blocks, qs, flow, m, cuts):
+    for k, n, xy, we, nbrC, (_, thd, h, hd) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0):
         vg = face_speeds(xy, m, thd, h, hd)
         FI, FJ = O.face_fluxes(blocks[k], qs[k][n:n + 1], flow, solver, xy=xy, we=we, vg=vg,
                                nbrC=nbrC)
@@ -298,17 +301,18 @@ def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter:
 
 
 def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
-                  m: OMotion, cuts=()) -> List[torch.Tensor]:
+                  m: OMotion, cuts=(), alpha0=None) -> List[torch.Tensor]:
     """hb_oracle.forces on the moved grids: per snapshot the wall loads of
     grid n (moving-wall ghosts), the moment about the moved reference point,
-    lift and drag along the mean free stream.  [body][ns][3] = (cl, cd, cm)."""
-    a0 = flow.alpha0
+    lift and drag along the mean free stream.  [body][ns][3] = (cl, cd, cm).
+    `alpha0` (a 0-d tensor) overrides the mean incidence."""
+    a0 = torch.as_tensor(flow.alpha0 if alpha0 is None else alpha0, dtype=DT)
     qinf = 0.5 * flow.mach ** 2
     nbody = max(b.body_id for b in blocks) + 1
     acc = [None] * nbody
     qs = O.split(blocks, q)
     rows = [[None] * b.ns for b in blocks]
-    for k, n, xy, we, nbrC, (th, _, h, _) in moving_snapshots(blocks, qs, flow, m, cuts):
+    for k, n, xy, we, nbrC, (th, _, h, _) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0):
         xm, ym = place(m, th, h, torch.tensor(flow.x_mom, dtype=DT), torch.tensor(flow.y_mom, dtype=DT))
         fn = dataclasses.replace(flow, x_mom=float(xm), y_mom=float(ym))
         rows[k][n] = O.block_loads(blocks[k], qs[k][n:n + 1], fn, xy=xy, we=we, nbrC=nbrC)[0]
@@ -318,8 +322,33 @@ def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
     out = []
     for L in acc:
         fx, fy, mz = L[:, 0], L[:, 1], L[:, 2]
-        cd = (fx * math.cos(a0) + fy * math.sin(a0)) / (qinf * flow.l_ref)
-        cl = (-fx * math.sin(a0) + fy * math.cos(a0)) / (qinf * flow.l_ref)
+        cd = (fx * torch.cos(a0) + fy * torch.sin(a0)) / (qinf * flow.l_ref)
+        cl = (-fx * torch.sin(a0) + fy * torch.cos(a0)) / (qinf * flow.l_ref)
         cm = -mz / (qinf * flow.l_ref ** 2)
         out.append(torch.stack([cl, cd, cm], dim=-1))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode on the moving grid (for checking the adjoint)
+# ---------------------------------------------------------------------------
+def moving_residual_vjp(blocks, q: torch.Tensor, flow, solver, m: OMotion, rbar: torch.Tensor,
+                        cuts=()):
+    """Products of the transposed Jacobians of the moving-grid R* with rbar,
+    by automatic differentiation of moving_residual_all: (qbar, alpha0bar).
+    The motion and the body-frame nodes are held fixed."""
+    qv = q.detach().clone().requires_grad_(True)
+    a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
+    (moving_residual_all(blocks, qv, flow, solver, m, cuts, a0) * rbar).sum().backward()
+    return qv.grad.detach(), a0.grad.detach()
+
+
+def moving_forces_vjp(blocks, q: torch.Tensor, flow, solver, m: OMotion, cfbar: torch.Tensor,
+                      cuts=()):
+    """Products of the transposed Jacobians of the moving-grid force
+    coefficients (flattened [body][n][3]) with cfbar: (qbar, alpha0bar)."""
+    qv = q.detach().clone().requires_grad_(True)
+    a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
+    cf = torch.cat([c.reshape(-1) for c in moving_forces(blocks, qv, flow, solver, m, cuts, a0)])
+    (cf * cfbar).sum().backward()
+    return qv.grad.detach(), a0.grad.detach()

@@ -32,6 +32,7 @@
 // area terms.  The incidence also enters through the wind axes:
 // d cd / d alpha0 = cl and d cl / d alpha0 = -cd.
 #include "hb_device.hpp"
+#include "hb_motion.hpp"
 #include "hb_xcd.hpp"
 
 #include <vector>
@@ -104,7 +105,8 @@ __device__ inline void rbar_cell(const BlockDesc &B, const double *rbar, int n, 
 template <bool NT>
 __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], const UVT<double> &P,
                                 const UVT<double> &Q, double sx, double sy, double dx, double dy,
-                                const double Fb[4], const Consts &c, double *out, int64_t nf) {
+                                const double Fb[4], const Consts &c, double *out, int64_t nf,
+                                double vg) {
     const double g = c.gamma;
     // viscous part first (net flux = Roe - viscous: it sees -Fb, its mass
     // term is 0): its node adjoints are final at once and are stored, which
@@ -130,7 +132,7 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
         const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
         W4<double> L, R;
         muscl_a(m2, m1, p0, p1, c.eps, L, R);
-        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb);
+        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb, vg);
     }
     ntst<NT>(out + 22 * nf, sxb);
     ntst<NT>(out + 23 * nf, syb);
@@ -158,9 +160,26 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
 // Node slots: i-faces store node (i, j) [edge start] in slot 0 (components
 // 16..18) and node (i, j+1) [end] in slot 1 (19..21); j-faces store node
 // (i+1, j) [start] in slot 0 and node (i, j) [end] in slot 1.
+// On a moving grid (mo.tab) the face's S and d are those of snapshot n (the
+// body-frame vectors rotated by theta_n) and it moves with the grid velocity
+// at its midpoint (the forward flux of the plain kernels).
+__device__ __forceinline__ double moving_geo(const Motion &mo, const BlockDesc &B, int n, const double *xy,
+                                             int64_t kA, int64_t kB, double &sx, double &sy, double &dx,
+                                             double &dy) {
+    const MotionSnap m = motion_snap(mo, B, n);
+    rot2(m, sx, sy);
+    rot2(m, dx, dy);
+    const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
+    const double *x = xy + 2 * B.node_off, *y = x + nn;
+    double gx, gy;
+    grid_velocity(m, mo, 0.5 * (x[kA] + x[kB]), 0.5 * (y[kA] + y[kB]), gx, gy);
+    return gx * sx + gy * sy;
+}
+
 template <bool NT>
 __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
-                             const double *dI, const double *rbar, Consts c, double *AF, int64_t tid_) {
+                             const double *dI, const double *rbar, Consts c, double *AF, Motion mo,
+                             const double *xy, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
@@ -183,15 +202,18 @@ __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const d
     rbar_cell(B, rbar, n, i - 1, j, rl);
     rbar_cell(B, rbar, n, i, j, rr);
     const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
-    const double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
-    const double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
+    double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
+    double vg = 0.0;
+    if (mo.tab) vg = moving_geo(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy);
     face_rev<NT>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
-             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf);
+             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg);
 }
 
 template <bool NT>
 __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
-                             const double *dJ, const double *rbar, Consts c, double *AF, int64_t tid_) {
+                             const double *dJ, const double *rbar, Consts c, double *AF, Motion mo,
+                             const double *xy, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const int64_t t = tid_;
@@ -216,10 +238,15 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
     rbar_cell(B, rbar, n, i, j - 1, rl);
     rbar_cell(B, rbar, n, i, j, rr);
     const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
-    const double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
-    const double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
+    double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
+    double vg = 0.0;
+    if (mo.tab) {
+        const int64_t kA = (int64_t)j * (B.ni + 1) + i;
+        vg = moving_geo(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy);
+    }
     face_rev<NT>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
-             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf);
+             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg);
 }
 
 // one launch for both face families of block b: workgroup w takes i-face
@@ -232,7 +259,8 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
                                                    const double *SI, const double *dI,
                                                    const double *SJ, const double *dJ,
                                                    const double *rbar, Consts c, double *AFI,
-                                                   double *AFJ, int64_t nI, int xcd) {
+                                                   double *AFJ, int64_t nI, int xcd, Motion mo,
+                                                   const double *xy) {
     const BlockDesc &B = blks[b];
     const int64_t nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
     constexpr int kHalf = kBS / 2;
@@ -241,9 +269,9 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
     if (L < 0) return;
     const int64_t t = L * kHalf + (threadIdx.x % kHalf);
     if (threadIdx.x < kHalf) {
-        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, t);
+        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, t);
     } else if (t < nJ) {
-        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, t);
+        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, t);
     }
 }
 
@@ -751,7 +779,7 @@ struct ForceAdj {
 // (i, 1); slot 0 = node (i+1, 0), slot 1 = node (i, 0), as in adj_face_j.
 __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, int b, const double *ext, const double *xy,
                                  const double *SJ, const double *dJ, ForceAdj fa, Consts c,
-                                 double *AF, double *xyb) {
+                                 double *AF, double *xyb, Motion mo) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -770,15 +798,22 @@ __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, i
                                 uvt(ldw(e, plane, r2 + col - 1), g), uR);          // node (i, 0)
     const UVT<double> nB = avg4(uL, uvt(ldw(e, plane, r1 + col + 1), g), uR,
                                 uvt(ldw(e, plane, r2 + col + 1), g));              // node (i+1, 0)
-    const double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
-    const double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    double sx = SJ[2 * B.fj_off + i], sy = SJ[2 * B.fj_off + nf + i];
+    double dx = dJ[2 * B.fj_off + i], dy = dJ[2 * B.fj_off + nf + i];
+    MotionSnap ms{1.0, 0.0, 0.0, 0.0, 0.0};
+    if (mo.tab) {   // the snapshot's grid: body-frame vectors rotated by theta_n
+        ms = motion_snap(mo, B, n);
+        rot2(ms, sx, sy);
+        rot2(ms, dx, dy);
+    }
     double fv[3];
     viscous_flux(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fv);
     const double dp = wR.p - c.pinf;
     const double fx = -dp * sx + fv[0], fy = -dp * sy + fv[1];
     const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
     const double *x = xy + 2 * B.node_off, *y = x + nn;
-    const double mx = 0.5 * (x[i] + x[i + 1]) - fa.xm, my = 0.5 * (y[i] + y[i + 1]) - fa.ym;
+    double mx = 0.5 * (x[i] + x[i + 1]) - fa.xm, my = 0.5 * (y[i] + y[i + 1]) - fa.ym;
+    if (mo.tab) rot2(ms, mx, my);   // coordinate adjoints are refused on a moving grid
     // coefficient adjoints -> (Fx, Fy, Mz) adjoints of this body and snapshot
     const double *cb = fa.cfbar + fa.body_off[B.body] + 3 * n;
     const double Fxb = (-cb[0] * fa.sa + cb[1] * fa.ca) / fa.qinf_l;
@@ -838,7 +873,8 @@ __global__ void __launch_bounds__(kBS) k_adj_force_axes(const double *cf, const 
 // dtau / V per cell and snapshot of the (fixed) state q: the forward
 // iteration's local step, laid out like one variable of the state.
 __global__ void __launch_bounds__(kBS) k_adj_dtv(const BlockDesc *blks, int b, const double *q, const double *SI,
-                          const double *SJ, const double *V, Consts c, double *dtv) {
+                          const double *SJ, const double *V, Consts c, double *dtv, Motion mo,
+                          const double *C) {
     const BlockDesc &B = blks[b];
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -854,9 +890,19 @@ __global__ void __launch_bounds__(kBS) k_adj_dtv(const BlockDesc *blks, int b, c
     const double syj = 0.5 * (SJ[2 * B.fj_off + nfj + t] + SJ[2 * B.fj_off + nfj + t + B.ni]);
     for (int n = 0; n < B.ns; ++n) {
         const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
-        const W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane],
-                                                    c.gamma - 1.0);
-        const double dt = local_dt<double>(w, sxi, syi, sxj, syj, vol, c.gamma, c.mu / c.prandtl,
+        W4<double> w = prim_from_cons<double>(qc[0], qc[plane], qc[2 * plane], qc[3 * plane],
+                                              c.gamma - 1.0);
+        double ax = sxi, ay = syi, bx = sxj, by = syj;
+        if (mo.tab) {   // snapshot's normals, velocity relative to the grid at the centre
+            const MotionSnap m = motion_snap(mo, B, n);
+            rot2(m, ax, ay);
+            rot2(m, bx, by);
+            double gx, gy;
+            grid_velocity(m, mo, C[2 * B.cell_off + t], C[2 * B.cell_off + plane + t], gx, gy);
+            w.u -= gx;
+            w.v -= gy;
+        }
+        const double dt = local_dt<double>(w, ax, ay, bx, by, vol, c.gamma, c.mu / c.prandtl,
                                            c.cfl, B.omega_nh);
         dtv[B.q_off / 4 + (int64_t)n * plane + t] = dt / vol;
     }
@@ -1036,7 +1082,7 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const int64_t nw = 256 * (((nI > nJ ? nI : nJ) + 127) / 128);
         hipLaunchKernelGGL(nt ? k_adj_faces<true> : k_adj_faces<false>, dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
-                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw));
+                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
         hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
@@ -1106,7 +1152,7 @@ int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const doubl
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_dtv, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
-                           q, g->SI_d, g->SJ_d, g->V_d, g->consts, g->it_dtv_d);
+                           q, g->SI_d, g->SJ_d, g->V_d, g->consts, g->it_dtv_d, g->motion, g->C_d);
     }
     const int ns = g->solver.n_stages;
     for (int it = 0; it < n_iter; ++it) {
@@ -1154,7 +1200,7 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         hipLaunchKernelGGL(k_adj_force_face, dim3(nblk((int64_t)B.ni * B.ns)), dim3(kBS), 0, s,
-                           g->blk_d, b, ext, g->xy_d, g->SJ_d, g->dJ_d, fa, c, g->AFJ_d, xybar);
+                           g->blk_d, b, ext, g->xy_d, g->SJ_d, g->dJ_d, fa, c, g->AFJ_d, xybar, g->motion);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, (double *)nullptr);
         hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,

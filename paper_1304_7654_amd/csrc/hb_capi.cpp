@@ -554,7 +554,8 @@ int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double 
     if (qbar == q || qbar == rbar) return fail(HB_ERR_ARG, "qbar must not alias q or rbar");
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
-    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
+    if (g->motion.tab && xybar)
+        return fail(HB_ERR_UNSUPPORTED, "no coordinate adjoint on a moving grid (pass xybar = NULL)");
     return launch_residual_adjoint(g, q, rbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 
@@ -563,7 +564,8 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *
     g_err.clear();
     if (!g || !q || !cfbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
     if (qbar == q) return fail(HB_ERR_ARG, "qbar must not alias q");
-    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
+    if (g->motion.tab && xybar)
+        return fail(HB_ERR_UNSUPPORTED, "no coordinate adjoint on a moving grid (pass xybar = NULL)");
     return launch_forces_adjoint(g, q, cfbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 
@@ -575,7 +577,6 @@ int hb_adjoint_iterate(hb_grid *g, const double *q, double *lambda, const double
     if (lambda == q || lambda == gq) return fail(HB_ERR_ARG, "lambda must not alias q or gq");
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
-    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "no adjoint on a moving grid");
     return launch_adjoint_iterate(g, q, lambda, gq, n_iter, resnorm, (hipStream_t)stream);
 }
 

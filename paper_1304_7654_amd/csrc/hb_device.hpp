@@ -545,10 +545,14 @@ __device__ __forceinline__ void muscl_rev1(double m2, double m1, double p0, doub
 }
 
 // Roe flux reverse (full primitive states, FP64).  Fb: adjoint of the 4 flux
-// components; adds to Lb, Rb (primitive adjoints) and sxb, syb.
+// components; adds to Lb, Rb (primitive adjoints) and sxb, syb.  vg: the face
+// speed x_t . S of a moving face (roe_flux), held fixed (its dependence on
+// the nodes is not taken: coordinate adjoints are not formed on a moving
+// grid).
 __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, double sx,
                                     double sy, double g, double delta_frac, const double Fb[4],
-                                    W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb) {
+                                    W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb,
+                                    double vg = 0.0) {
     // ---- forward recomputation
     const double area = sqrt(sx * sx + sy * sy);
     const double ia = adj_rcp(area);
@@ -566,6 +570,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double q2t = ut * ut + vt * vt;
     const double ct = sqrt((g - 1.0) * (ht - 0.5 * q2t));
     const double qnt = ut * nx + vt * ny;
+    const double qrel = qnt - vg * ia;
     const double dr = R.r - L.r, du = R.u - L.u, dv = R.v - L.v, dp = R.p - L.p;
     const double dqn = du * nx + dv * ny;
     const double ict = adj_rcp(ct);
@@ -574,7 +579,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double a1 = (dp - X) * 0.5 * ic2;
     const double a4 = (dp + X) * 0.5 * ic2;
     const double a2 = dr - dp * ic2;
-    const double lam1 = qnt - ct, lam4 = qnt + ct;
+    const double lam1 = qrel - ct, lam4 = qrel + ct;
     const double r1 = fabs(lam1), r4 = fabs(lam4);
     double l1 = r1, l4 = r4;
     const double dd = delta_frac * ct;
@@ -582,7 +587,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const bool fix1 = delta_frac > 0.0 && r1 < dd, fix4 = delta_frac > 0.0 && r4 < dd;
     if (fix1) l1 = (r1 * r1 + dd * dd) * (0.5 * idd);
     if (fix4) l4 = (r4 * r4 + dd * dd) * (0.5 * idd);
-    const double l2 = fabs(qnt);
+    const double l2 = fabs(qrel);
     const double b1 = l1 * a1, b4 = l4 * a4, b2 = l2 * a2, bs = l2 * rt;
     const double d0 = b1 + b4 + b2;
     const double d1 = b1 * (ut - ct * nx) + b4 * (ut + ct * nx) + b2 * ut + bs * (du - nx * dqn);
@@ -602,6 +607,21 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double d0b = -f0b, d1b = -f1b, d2b = -f2b, d3b = -f3b;
     double nxb = 0.0, nyb = 0.0;
     double hlb = 0.0, hrb = 0.0;
+    if (vg != 0.0) {
+        // -vg (U_L + U_R) / 2 with U = (rho, rho u, rho v, rho H - p)
+        const double u0 = -0.5 * vg * Fb[0], u1 = -0.5 * vg * Fb[1];
+        const double u2 = -0.5 * vg * Fb[2], u3 = -0.5 * vg * Fb[3];
+        Lb.r += u0 + u1 * L.u + u2 * L.v + u3 * hl;
+        Rb.r += u0 + u1 * R.u + u2 * R.v + u3 * hr;
+        Lb.u += u1 * L.r;
+        Rb.u += u1 * R.r;
+        Lb.v += u2 * L.r;
+        Rb.v += u2 * R.r;
+        Lb.p -= u3;
+        Rb.p -= u3;
+        hlb += u3 * L.r;
+        hrb += u3 * R.r;
+    }
     // central part
     const double mlb = f0b + f1b * L.u + f2b * L.v + f3b * hl;
     const double mrb = f0b + f1b * R.u + f2b * R.v + f3b * hr;
@@ -662,7 +682,9 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     auto sgn = [](double x) { return (double)((x > 0.0) - (x < 0.0)); };
     const double lam1b = r1b * sgn(lam1);
     const double lam4b = r4b * sgn(lam4);
-    qntb += lam1b + lam4b + l2b * sgn(qnt);
+    const double qrelb = lam1b + lam4b + l2b * sgn(qrel);
+    qntb += qrelb;
+    areab += qrelb * vg * ia * ia;          // qrel = qnt - vg / |S|
     ctb += -lam1b + lam4b + delta_frac * ddb;
     // wave strengths
     double dpb = 0.5 * ic2 * (a1b + a4b) - ic2 * a2b;

@@ -334,7 +334,7 @@ int plain_ghost_fill(hb_grid *g, int b, const double *q, double *ext, hipStream_
     const BlockDesc &B = g->blk[b];
     const int64_t next = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
     hipLaunchKernelGGL(k_ghost, dim3(xcd_grid(next)), dim3(kBS), 0, s, g->blk_d, b, q, g->ffw_d,
-                       g->consts.gamma - 1.0, ext, Motion{nullptr, 0.0, 0.0}, g->xy_d);
+                       g->consts.gamma - 1.0, ext, g->motion, g->xy_d);
     return check_hip(hipGetLastError(), "ghost launch");
 }
 

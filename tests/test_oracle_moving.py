@@ -286,3 +286,40 @@ def test_moving_split_equals_uncut(name, pi, pj):
     q2, n2 = M.moving_rk_iterate(sblocks, q[perm], flow, solver, m, 1, sp.cuts)
     assert float((q2 - q1[perm]).abs().max()) <= 1e-14 * float(q1.abs().max())
     assert abs(float(n1[0]) - float(n2[0])) <= 1e-13 * float(n1[0])
+
+
+def test_moving_vjps_match_central_differences():
+    """The reverse products of the moving-grid residual and loads (used to
+    check the adjoint kernels) against central differences of the forward
+    oracle along a random direction of the state and in alpha0."""
+    b = _cyl(16, 6, 1)
+    flow, solver = _flow(), O.OSolver()
+    flow.alpha0 = 0.03
+    m = M.OMotion(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_pivot=0.05)
+    q = _state(b, flow, 9).reshape(-1)
+    g = torch.Generator().manual_seed(4)
+    rbar = torch.randn(q.shape, generator=g, dtype=DT)
+    v = torch.randn(q.shape, generator=g, dtype=DT) * q.abs()
+    h = 1e-6
+
+    def r_at(x, a=None):
+        return M.moving_residual_all([b], x, flow, solver, m, (), None if a is None else torch.tensor(a, dtype=DT))
+
+    qb, ab = M.moving_residual_vjp([b], q, flow, solver, m, rbar)
+    fd = float((rbar * (r_at(q + h * v) - r_at(q - h * v))).sum()) / (2 * h)
+    assert abs(fd - float((qb * v).sum())) <= 1e-7 * abs(fd)
+    fa = float((rbar * (r_at(q, flow.alpha0 + h) - r_at(q, flow.alpha0 - h))).sum()) / (2 * h)
+    assert abs(fa - float(ab)) <= 1e-7 * abs(fa)
+
+    ns = b.ns
+    cfbar = torch.randn(3 * ns, generator=g, dtype=DT)
+
+    def cf_at(x, a=None):
+        a = None if a is None else torch.tensor(a, dtype=DT)
+        return torch.cat([c.reshape(-1) for c in M.moving_forces([b], x, flow, solver, m, (), a)])
+
+    qb, ab = M.moving_forces_vjp([b], q, flow, solver, m, cfbar)
+    fd = float((cfbar * (cf_at(q + h * v) - cf_at(q - h * v))).sum()) / (2 * h)
+    assert abs(fd - float((qb * v).sum())) <= 1e-7 * abs(fd)
+    fa = float((cfbar * (cf_at(q, flow.alpha0 + h) - cf_at(q, flow.alpha0 - h))).sum()) / (2 * h)
+    assert abs(fa - float(ab)) <= 1e-7 * abs(fa)
