@@ -59,9 +59,12 @@ enum {
     HB_BC_FARFIELD = 2,   /* both ghost layers = free stream at alpha(t_n)    */
     HB_BC_PERIODIC = 3,   /* the block wraps onto itself (O-grid in i)        */
     HB_BC_CUT = 4,        /* glued to another block side (see hb_cut)         */
-    HB_BC_WAKECUT = 5     /* jmin only: C-grid wake (cells i < wake_ncells and
+    HB_BC_WAKECUT = 5,    /* jmin only: C-grid wake (cells i < wake_ncells and
                              i >= ni - wake_ncells face each other), wall in
                              between                                         */
+    HB_BC_CUT_WALL = 6,   /* partly glued: the cells covered by cut segments
+                             are glued, the others are a no-slip wall        */
+    HB_BC_CUT_FARFIELD = 7 /* partly glued, the others far field             */
 };
 
 enum { HB_FP64 = 0, HB_FP32_BULK = 1 };
@@ -96,7 +99,11 @@ typedef struct {
  * interior cells (Jacobi: both read the same stage input); corner ghosts
  * take the i sides first, then the j sides, continuing across a cut in the
  * glued block.  Every side of kind HB_BC_CUT must be covered by its
- * segments exactly once; glued blocks have equal n_harm.  HB_ERR_ARG
+ * segments exactly once; a side of kind HB_BC_CUT_WALL or
+ * HB_BC_CUT_FARFIELD at most once (a block edge made of sections, some
+ * glued, the rest wall or far field: the C-grid of several blocks whose
+ * wake sections and profile sections share a side); glued blocks have
+ * equal n_harm.  HB_ERR_ARG
  * otherwise, for a segment outside its sides, len < 1, reversed not 0 or 1,
  * or cuts around which a corner ghost does not resolve.  A moving grid
  * (hb_set_motion) needs its cuts to join whole opposite sides, aligned. */

@@ -112,6 +112,8 @@ def face_speeds(xy: torch.Tensor, m: OMotion, thd: float, h: float, hd: float):
 def check_block(b: O.OBlock):
     if b.bc[0] == O.WALL or b.bc[1] == O.WALL:
         raise ValueError("moving grids: walls only on j sides")
+    if O.CUT_WALL in b.bc or O.CUT_FARFIELD in b.bc:
+        raise ValueError("moving grids: no partly glued sides")
 
 
 def wall_images(b: O.OBlock, we: torch.Tensor, xy: torch.Tensor, m: OMotion, thd: float,
@@ -155,7 +157,7 @@ def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Te
     of a block without cuts on the moved grid xy: the fixed-grid rules
     (hb_oracle.extend), then the moving-wall images  u_g = 2 u_w - u."""
     check_block(b)
-    if O.CUT in b.bc:
+    if any(k in O.GLUED for k in b.bc):
         raise ValueError("moving_extend: a block with cuts needs its neighbours (moving_snapshots)")
     return wall_images(b, O.extend(b, w, winf).clone(), xy, m, thd, h, hd)
 

@@ -33,7 +33,10 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 DT = torch.float64
-WALL, FARFIELD, PERIODIC, CUT, WAKECUT = 1, 2, 3, 4, 5
+WALL, FARFIELD, PERIODIC, CUT, WAKECUT, CUT_WALL, CUT_FARFIELD = 1, 2, 3, 4, 5, 6, 7
+# sides glued by cut segments: CUT (covered exactly once), or partly glued
+# with the rest of the side a wall (CUT_WALL) or far field (CUT_FARFIELD)
+GLUED = (CUT, CUT_WALL, CUT_FARFIELD)
 
 
 # ---------------------------------------------------------------------------
@@ -219,7 +222,9 @@ def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
     start_b + t, or start_b + length - 1 - t when reversed.  A cut is
     (a, side_a, start_a, b, side_b, start_b, length, reversed), or
     (a, side_a, b, side_b[, reversed]) for two whole sides of equal length.
-    Every side of kind CUT must be covered by its segments exactly once;
+    Every side of kind CUT must be covered by its segments exactly once; a
+    side of kind CUT_WALL or CUT_FARFIELD at most once (a block edge made of
+    sections of which some are glued and the rest are wall or far field);
     glued blocks share n_harm.  Sides are numbered 0..3 = imin, imax, jmin,
     jmax."""
     m = {}
@@ -235,8 +240,8 @@ def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
             raise ValueError("a cut has 4, 5 or 8 entries")
         a, sa, st_a, b, sb, st_b, ln, rev = c
         A, B = blocks[a], blocks[b]
-        if A.bc[sa] != CUT or B.bc[sb] != CUT or A.n_harm != B.n_harm:
-            raise ValueError("cut sides must be of kind CUT with equal n_harm")
+        if A.bc[sa] not in GLUED or B.bc[sb] not in GLUED or A.n_harm != B.n_harm:
+            raise ValueError("cut sides must be of a glued kind with equal n_harm")
         if ln < 1 or st_a < 0 or st_b < 0 or st_a + ln > side_length(A, sa) \
                 or st_b + ln > side_length(B, sb):
             raise ValueError("a cut segment leaves its side")
@@ -246,16 +251,27 @@ def cut_partners(blocks: Sequence[OBlock], cuts) -> dict:
         m[key].sort()
     for k, blk in enumerate(blocks):
         for side in range(4):
-            if blk.bc[side] != CUT:
+            if blk.bc[side] not in GLUED:
                 continue
             pos = 0
             for st, ln, *_ in m.get((k, side), []):
-                if st != pos:
+                if st < pos or (blk.bc[side] == CUT and st != pos):
                     raise ValueError("the cut segments of a side must cover it exactly once")
                 pos = st + ln
-            if pos != side_length(blk, side):
+            if blk.bc[side] == CUT and pos != side_length(blk, side):
                 raise ValueError("a CUT side is not covered by its cuts")
     return m
+
+
+def cut_segment(blocks: Sequence[OBlock], cutmap: dict, b: int, side: int, p: int):
+    """The segment of side `side` of block b that covers position p (a
+    position beyond the side's ends counts as its end cell), or None."""
+    L = side_length(blocks[b], side)
+    pc = min(max(p, 0), L - 1)
+    for g in cutmap.get((b, side), []):
+        if g[0] <= pc < g[0] + g[1]:
+            return g
+    return None
 
 
 def cut_cell(blocks: Sequence[OBlock], cutmap: dict, b: int, side: int, k: int, p: int):
@@ -264,10 +280,7 @@ def cut_cell(blocks: Sequence[OBlock], cutmap: dict, b: int, side: int, k: int, 
     A position beyond the side's ends (a corner ghost) continues the mapping
     of the end segment; the result may then lie outside the partner, where
     the partner's own side rules apply."""
-    segs = cutmap[(b, side)]
-    L = side_length(blocks[b], side)
-    pc = min(max(p, 0), L - 1)
-    st, ln, a, sa, st_a, rev = [g for g in segs if g[0] <= pc][-1]
+    st, ln, a, sa, st_a, rev = cut_segment(blocks, cutmap, b, side, p)
     t = p - st
     pp = st_a + (ln - 1 - t if rev else t)
     A = blocks[a]
@@ -289,7 +302,8 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
     same cells, and with the i sides first a C-grid cut into wake and
     airfoil blocks keeps the single block's ghosts at the trailing edge);
     across a cut the partner block's own rules apply to what is still
-    outside it."""
+    outside it.  On a partly glued side the cells no segment covers follow
+    the side's rest kind (wall or far field)."""
     mir = 0
     for _ in range(8):
         B = blocks[b]
@@ -302,9 +316,12 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
             elif kind == WALL:
                 i = k if side == 0 else B.ni - 1 - k
                 mir ^= 1
-            elif kind == CUT:
+            elif kind in GLUED and cut_segment(blocks, cutmap, b, side, j) is not None:
                 b, i, j = cut_cell(blocks, cutmap, b, side, k, j)
-            elif kind == FARFIELD:
+            elif kind == CUT_WALL:
+                i = k if side == 0 else B.ni - 1 - k
+                mir ^= 1
+            elif kind in (FARFIELD, CUT_FARFIELD):
                 return b, None, None, mir
             else:
                 raise ValueError("unsupported i-side boundary %d" % kind)
@@ -324,9 +341,12 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
                 else:
                     j = k
                     mir ^= 1
-            elif kind == CUT:
+            elif kind in GLUED and cut_segment(blocks, cutmap, b, side, i) is not None:
                 b, i, j = cut_cell(blocks, cutmap, b, side, k, i)
-            elif kind == FARFIELD:
+            elif kind == CUT_WALL:
+                j = k if side == 2 else B.nj - 1 - k
+                mir ^= 1
+            elif kind in (FARFIELD, CUT_FARFIELD):
                 return b, None, None, mir
             else:
                 raise ValueError("unsupported j-side boundary %d" % kind)
@@ -335,38 +355,72 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
     raise ValueError("ghost resolution does not end (cuts around a singular corner)")
 
 
+_GHOST_MAPS = {}
+
+
+def ghost_map(blocks, cutmap, k: int) -> dict:
+    """resolve_ghost for every ghost cell of block k, grouped by source:
+    (source block, far field?, mirror) -> index tensors (je, ie, sj, si) of
+    the ghost cells (ghost-extended indices) and of their source cells (0
+    for the far field).  The map depends only on the grid's topology and is
+    kept per topology."""
+    key = (k, tuple((b.ni, b.nj, tuple(b.bc), b.wake_ncells) for b in blocks),
+           tuple(sorted((kk, tuple(v)) for kk, v in cutmap.items())))
+    if key not in _GHOST_MAPS:
+        b = blocks[k]
+        groups = {}
+        for je in range(b.nj + 4):
+            for ie in range(b.ni + 4):
+                i, j = ie - 2, je - 2
+                if 0 <= i < b.ni and 0 <= j < b.nj:
+                    continue
+                src, si, sj, mir = resolve_ghost(blocks, cutmap, k, i, j)
+                g = groups.setdefault((src, si is None, mir), ([], [], [], []))
+                g[0].append(je)
+                g[1].append(ie)
+                g[2].append(0 if si is None else sj)
+                g[3].append(0 if si is None else si)
+        _GHOST_MAPS[key] = {kk: tuple(torch.tensor(x, dtype=torch.long) for x in v)
+                            for kk, v in groups.items()}
+    return _GHOST_MAPS[key]
+
+
 def extend_cut(blocks, ws, winfs, cutmap, k: int) -> torch.Tensor:
     """Ghost-extended primitives [ns][4][nj+4][ni+4] of block k, which has
-    CUT sides: every ghost cell from resolve_ghost, taken from the blocks'
-    interior fields of the same snapshots (Jacobi exchange)."""
+    glued sides: every ghost cell from resolve_ghost (ghost_map), taken from
+    the blocks' interior fields of the same snapshots (Jacobi exchange)."""
     b = blocks[k]
     w = ws[k]
     ns = w.shape[0]
     we = torch.zeros(ns, 4, b.nj + 4, b.ni + 4, dtype=w.dtype)
     we[:, :, 2:b.nj + 2, 2:b.ni + 2] = w
-    for je in range(b.nj + 4):
-        for ie in range(b.ni + 4):
-            i, j = ie - 2, je - 2
-            if 0 <= i < b.ni and 0 <= j < b.nj:
-                continue
-            src, si, sj, mir = resolve_ghost(blocks, cutmap, k, i, j)
-            v = winfs[src] if si is None else ws[src][:, :, sj, si]
-            if mir:
-                v = mirror_prim(v[..., None, None])[..., 0, 0]
-            we[:, :, je, ie] = v
+    for (src, ff, mir), (je, ie, sj, si) in ghost_map(blocks, cutmap, k).items():
+        if ff:
+            v = winfs[src][:, :, None].expand(ns, 4, len(je))
+        else:
+            v = ws[src][:, :, sj, si]
+        if mir:
+            v = mirror_prim(v[..., None])[..., 0]
+        we[:, :, je, ie] = v
     return we
 
 
 def cut_ghost_centres(blocks, cutmap, Cs, k: int) -> dict:
-    """Centres [L][2] of the first ghost layer of each CUT side of block k:
-    the centres (Cs[block][j, i]) of the cells across the cut."""
+    """Centres [L][2] of the first ghost layer of each glued side of block k:
+    the centres (Cs[block][j, i]) of the cells across the cut; NaN for the
+    cells of a partly glued side that no segment covers (their ghost centre
+    is the mirrored one, ghost_centres)."""
     b = blocks[k]
     out = {}
+    nan = torch.full((2,), float("nan"), dtype=DT)
     for side in range(4):
-        if b.bc[side] != CUT:
+        if b.bc[side] not in GLUED:
             continue
         cs = []
         for p in range(side_length(b, side)):
+            if cut_segment(blocks, cutmap, k, side, p) is None:
+                cs.append(nan)
+                continue
             a, i, j = cut_cell(blocks, cutmap, k, side, 0, p)
             cs.append(Cs[a][j, i])
         out[side] = torch.stack(cs)
@@ -474,9 +528,9 @@ def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
 def extend_all(blocks, ws, winfs, cutmap):
     """Ghost-extended primitive fields of all blocks.  A cut ghost is a cell
     of the glued block taken from the same input (Jacobi exchange); blocks
-    without CUT sides use extend()."""
-    return [extend_cut(blocks, ws, winfs, cutmap, k) if CUT in b.bc else extend(b, w, wf)
-            for k, (b, w, wf) in enumerate(zip(blocks, ws, winfs))]
+    without glued sides use extend()."""
+    return [extend_cut(blocks, ws, winfs, cutmap, k) if any(s in GLUED for s in b.bc)
+            else extend(b, w, wf) for k, (b, w, wf) in enumerate(zip(blocks, ws, winfs))]
 
 
 def reflect(p: torch.Tensor, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
@@ -490,10 +544,10 @@ def reflect(p: torch.Tensor, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor, nbrC=None):
     """Centres of the first ghost layer on each side (for the viscous diamond
     of boundary faces).  Periodic, wake-cut and cut ghosts are real cells, so
-    their centre is the partner cell's centre (`nbrC` maps a CUT side to the
-    centres [L][2] of the cells across it, cut_ghost_centres); wall and
-    farfield ghost centres are the interior centre mirrored across the
-    boundary face.
+    their centre is the partner cell's centre (`nbrC` maps a glued side to
+    the centres [L][2] of the cells across it, cut_ghost_centres, NaN where
+    no segment covers the cell); wall and farfield ghost centres are the
+    interior centre mirrored across the boundary face.
     Returns (c_imin [nj][2], c_imax [nj][2], c_jmin [ni][2], c_jmax [ni][2])."""
     nj, ni = C.shape[0], C.shape[1]
     P = xy.permute(1, 2, 0)                   # nodes [nj+1][ni+1][2]
@@ -514,8 +568,9 @@ def ghost_centres(b: OBlock, xy: torch.Tensor, C: torch.Tensor, nbrC=None):
             mir = reflect(C[nj - 1, :], P[nj, :-1], P[nj, 1:])
         if kind == PERIODIC:
             out.append(real)
-        elif kind == CUT:
-            out.append(nbrC[side])
+        elif kind in GLUED:
+            c = nbrC[side]
+            out.append(torch.where(torch.isnan(c), mir, c))
         elif kind in (WALL, FARFIELD):
             out.append(mir)
         elif kind == WAKECUT:
@@ -907,14 +962,17 @@ def td_march(b: OBlock, q: torch.Tensor, flow: OFlow, solver: OSolver, dt: float
 # ---------------------------------------------------------------------------
 # Forces
 # ---------------------------------------------------------------------------
-def wall_face_mask(b: OBlock) -> torch.Tensor:
+def wall_face_mask(b: OBlock, nbrC=None) -> torch.Tensor:
     """jmin faces that are solid wall (all of them for WALL, the profile part
-    for WAKECUT).  Only jmin walls carry loads in these grids."""
+    for WAKECUT, the cells no segment covers for CUT_WALL: `nbrC` as in
+    ghost_centres).  Only jmin walls carry loads in these grids."""
     i = torch.arange(b.ni)
     if b.bc[2] == WALL:
         return torch.ones(b.ni, dtype=torch.bool)
     if b.bc[2] == WAKECUT:
         return (i >= b.wake_ncells) & (i < b.ni - b.wake_ncells)
+    if b.bc[2] == CUT_WALL:
+        return torch.isnan(nbrC[2][:, 0])
     return torch.zeros(b.ni, dtype=torch.bool)
 
 
@@ -958,7 +1016,7 @@ def block_loads(b: OBlock, q: torch.Tensor, flow: OFlow,
     mx = 0.5 * (pA[0] + pB[0]) - flow.x_mom
     my = 0.5 * (pA[1] + pB[1]) - flow.y_mom
     mz = mx * fy - my * fx
-    m = wall_face_mask(b).to(DT)
+    m = wall_face_mask(b, nbrC).to(DT)
     return torch.stack([(fx * m).sum(-1), (fy * m).sum(-1), (mz * m).sum(-1)], dim=-1)
 
 

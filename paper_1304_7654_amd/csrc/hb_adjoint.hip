@@ -606,7 +606,7 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
         centre_to_nodes(blks, b, pi, pj, gx, gy, xyb);
     } else if (wake) {
         centre_to_nodes(blks, b, B.ni - 1 - ii, 0, gx, gy, xyb);
-    } else if (kind == HB_BC_CUT) {
+    } else if (glued_at(B, B.segs, side, side < 2 ? jj : ii)) {
         int a, pi, pj;
         cut_cell(blks, B.segs, b, side, 0, side < 2 ? jj : ii, &a, &pi, &pj);
         centre_to_nodes(blks, a, pi, pj, gx, gy, xyb);
@@ -759,11 +759,6 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int
 }
 
 // ---- force coefficients ------------------------------------------------------
-__device__ inline bool wall_face(const BlockDesc &B, int i) {
-    if (B.bc[2] == HB_BC_WALL) return true;
-    if (B.bc[2] == HB_BC_WAKECUT) return i >= B.wake && i < B.ni - B.wake;
-    return false;
-}
 
 struct ForceAdj {
     const double *cfbar;      // [body][n][3] = (cl, cd, cm) adjoints
@@ -785,7 +780,7 @@ __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, i
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)B.ni * B.ns) return;
     const int n = (int)(t / B.ni), i = (int)(t % B.ni);
-    if (!wall_face(B, i)) return;
+    if (!jmin_wall(B, i)) return;
     const int we = B.ni + 4;
     const int64_t plane = (int64_t)we * (B.nj + 4);
     const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;

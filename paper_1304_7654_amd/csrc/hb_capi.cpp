@@ -100,7 +100,15 @@ void free_all(hb_grid *g) {
     dfree(g->td_r_d); dfree(g->td_acc_d); dfree(g->td_qs_d);
 }
 
-bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_WAKECUT; }
+bool known_bc(int k) { return k >= HB_BC_WALL && k <= HB_BC_CUT_FARFIELD; }
+
+// sides glued by cut segments: wholly (HB_BC_CUT) or partly
+bool glued_kind(int k) { return k == HB_BC_CUT || k == HB_BC_CUT_WALL || k == HB_BC_CUT_FARFIELD; }
+
+// kind of the cells of a glued side that no segment covers (0: none may be)
+int rest_kind(int k) {
+    return k == HB_BC_CUT_WALL ? HB_BC_WALL : k == HB_BC_CUT_FARFIELD ? HB_BC_FARFIELD : 0;
+}
 
 // HB time-derivative matrix, closed form of the odd-N spectral
 // differentiation matrix: D[n][m] = (omega/2) (-1)^(n-m) / sin(pi (n-m) / N).
@@ -268,7 +276,8 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     for (int k = 0; k < nbody; ++k)
         if (body_nh[k] < 0) return fail(HB_ERR_ARG, "body ids must be numbered without gaps");
     // cuts: segments of block sides (any two sides, possibly reversed); every
-    // side of kind HB_BC_CUT covered by its segments exactly once
+    // side of kind HB_BC_CUT covered by its segments exactly once, the partly
+    // glued kinds at most once
     std::vector<std::vector<CutSeg>> side_segs(4 * (size_t)nblocks);
     for (int c = 0; c < ncuts; ++c) {
         const hb_cut k = cuts[c];
@@ -282,8 +291,9 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         if (k.len < 1 || k.start_a < 0 || k.start_b < 0 ||
             (int64_t)k.start_a + k.len > la || (int64_t)k.start_b + k.len > lb)
             return fail(HB_ERR_ARG, "cut segment outside its block sides");
-        if (A.bc[k.side_a] != HB_BC_CUT || B.bc[k.side_b] != HB_BC_CUT)
-            return fail(HB_ERR_ARG, "cut sides must have boundary kind HB_BC_CUT");
+        if (!glued_kind(A.bc[k.side_a]) || !glued_kind(B.bc[k.side_b]))
+            return fail(HB_ERR_ARG, "cut sides must have boundary kind HB_BC_CUT, HB_BC_CUT_WALL or "
+                                    "HB_BC_CUT_FARFIELD");
         if (A.n_harm != B.n_harm) return fail(HB_ERR_ARG, "glued blocks must have equal n_harm");
         side_segs[4 * k.blk_a + k.side_a].push_back(
             CutSeg{k.start_a, k.len, k.blk_b, k.side_b, k.start_b, k.reversed});
@@ -292,15 +302,19 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
     }
     for (int b = 0; b < nblocks; ++b)
         for (int s = 0; s < 4; ++s) {
-            if (blocks[b].bc[s] != HB_BC_CUT) continue;
+            const int kind = blocks[b].bc[s];
+            if (!glued_kind(kind)) continue;
             std::vector<CutSeg> &v = side_segs[4 * b + s];
             std::sort(v.begin(), v.end(), [](const CutSeg &x, const CutSeg &y) { return x.start < y.start; });
             int pos = 0;
             for (const CutSeg &q : v) {
-                if (q.start != pos) return fail(HB_ERR_ARG, "the cuts of a HB_BC_CUT side must cover it exactly once");
+                if (q.start < pos || (kind == HB_BC_CUT && q.start != pos))
+                    return fail(HB_ERR_ARG, kind == HB_BC_CUT
+                                                ? "the cuts of a HB_BC_CUT side must cover it exactly once"
+                                                : "the cuts of a partly glued side overlap");
                 pos = q.start + q.len;
             }
-            if (pos != (s < 2 ? blocks[b].nj : blocks[b].ni))
+            if (kind == HB_BC_CUT && pos != (s < 2 ? blocks[b].nj : blocks[b].ni))
                 return fail(HB_ERR_ARG, "the cuts of a HB_BC_CUT side must cover it exactly once");
         }
     std::vector<CutSeg> seg_table;
@@ -312,14 +326,16 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         D.nj = blocks[b].nj;
         D.wake = blocks[b].wake_ncells;
         for (int s = 0; s < 4; ++s) {
-            D.bc[s] = blocks[b].bc[s];
+            // glued sides are HB_BC_CUT below, with the kind of their uncovered cells
+            D.bc[s] = glued_kind(blocks[b].bc[s]) ? HB_BC_CUT : blocks[b].bc[s];
+            D.rest[s] = rest_kind(blocks[b].bc[s]);
             D.seg_off[s] = (int32_t)seg_table.size();
             D.seg_cnt[s] = (int32_t)side_segs[4 * b + s].size();
             seg_table.insert(seg_table.end(), side_segs[4 * b + s].begin(), side_segs[4 * b + s].end());
             // the block glued to the whole side by one aligned segment of the
             // opposite side (used by the moving-grid wall rule), else -1
             D.cut_blk[s] = D.cut_side[s] = -1;
-            if (D.seg_cnt[s] == 1) {
+            if (D.seg_cnt[s] == 1 && D.rest[s] == 0) {
                 const CutSeg &q = seg_table[D.seg_off[s]];
                 const int L = s < 2 ? D.nj : D.ni;
                 if (q.start == 0 && q.pstart == 0 && q.len == L && !q.rev && (q.side ^ s) == 1) {
@@ -358,7 +374,8 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         std::memset(&B, 0, sizeof B);
         B.ni = S.ni; B.nj = S.nj; B.nh = S.n_harm; B.ns = 2 * S.n_harm + 1;
         for (int s = 0; s < 4; ++s) {
-            B.bc[s] = S.bc[s];
+            B.bc[s] = cut_desc[b].bc[s];
+            B.rest[s] = cut_desc[b].rest[s];
             B.cut_blk[s] = cut_desc[b].cut_blk[s];
             B.cut_side[s] = cut_desc[b].cut_side[s];
             B.seg_off[s] = cut_desc[b].seg_off[s];
@@ -693,7 +710,8 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
         for (int s = 0; s < 4; ++s)
             if (B.bc[s] == HB_BC_CUT && B.cut_blk[s] < 0)
                 return fail(HB_ERR_UNSUPPORTED, "moving grids: cuts only between whole opposite "
-                                                "sides, aligned (imax-imin, jmax-jmin)");
+                                                "sides, aligned (imax-imin, jmax-jmin), no partly "
+                                                "glued sides");
     }
     if (!g->mot_d) {
         rc = dalloc(&g->mot_d, (int64_t)kMotionW * g->n_snap);

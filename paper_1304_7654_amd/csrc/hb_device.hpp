@@ -79,7 +79,8 @@ __device__ __forceinline__ W4<T> mirror(W4<T> w) {
 // is mapped to a value: interior cells are read; outside, the i sides are
 // resolved first, then the j sides (which defines the corner ghosts); a cut
 // continues in the glued block (cut_cell), whose own rules then apply to
-// what is still outside it.  `cell` is a functor (block, i, j) -> value
+// what is still outside it; on a partly glued side the cells no segment
+// covers follow the side's rest kind (wall or far field).  `cell` is a functor (block, i, j) -> value
 // reading an interior cell of any block; `ff(b)` returns the block's free
 // stream of the current snapshot and `mir` the no-slip wall image of a
 // value (applied once per wall met, so two walls cancel).
@@ -99,12 +100,15 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
             } else if (kind == HB_BC_WALL) {
                 i = side == 0 ? k : B.ni - 1 - k;
                 m = !m;
-            } else if (kind == HB_BC_CUT) {
+            } else if (glued_at(B, B.segs, side, j)) {
                 int a, ia, ja;
                 cut_cell(blks, B.segs, b, side, k, j, &a, &ia, &ja);
                 b = a;
                 i = ia;
                 j = ja;
+            } else if (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL) {
+                i = side == 0 ? k : B.ni - 1 - k;
+                m = !m;
             } else {
                 const V f = ff(b);
                 return m ? mir(f) : f;
@@ -127,12 +131,15 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
                     m = !m;
                 }
                 j = k;
-            } else if (kind == HB_BC_CUT) {
+            } else if (glued_at(B, B.segs, side, i)) {
                 int a, ia, ja;
                 cut_cell(blks, B.segs, b, side, k, i, &a, &ia, &ja);
                 b = a;
                 i = ia;
                 j = ja;
+            } else if (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL) {
+                j = side == 2 ? k : B.nj - 1 - k;
+                m = !m;
             } else {
                 const V f = ff(b);
                 return m ? mir(f) : f;
@@ -143,6 +150,16 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
         return m ? mir(v) : v;
     }
     return ff(b);      // not reached: every ghost resolves (checked at grid creation)
+}
+
+// jmin face i of block B is a solid wall (carries loads): a WALL side, the
+// profile part of a WAKECUT side, or a cell of a partly glued side with a
+// wall rest that no segment covers.
+__device__ __forceinline__ bool jmin_wall(const BlockDesc &B, int i) {
+    if (B.bc[2] == HB_BC_WALL) return true;
+    if (B.bc[2] == HB_BC_WAKECUT) return i >= B.wake && i < B.ni - B.wake;
+    if (B.bc[2] == HB_BC_CUT && B.rest[2] == HB_BC_WALL) return cut_seg_at(B, B.segs, 2, i) < 0;
+    return false;
 }
 
 // Load through a uniform base pointer and an unsigned 32-bit byte offset

@@ -35,12 +35,6 @@ struct FF {
     }
 };
 
-__device__ inline bool is_wall_face(const BlockDesc &B, int i) {
-    if (B.bc[2] == HB_BC_WALL) return true;
-    if (B.bc[2] == HB_BC_WAKECUT) return i >= B.wake && i < B.ni - B.wake;
-    return false;
-}
-
 // Loads of one jmin wall face: (Fx, Fy, Mz).
 __device__ inline void face_load(const BlockDesc *blks, int b, int n, int i, const double *q,
                                  const double *ffw, const double *xy, const double *SJ,
@@ -97,7 +91,7 @@ __global__ void k_block_loads(const BlockDesc *blks, const double *q, const doub
     const int i = blockIdx.z * kBS + threadIdx.x;
     const BlockDesc &B = blks[b];
     double acc[3] = {0.0, 0.0, 0.0};
-    if (n < B.ns && i < B.ni && is_wall_face(B, i))
+    if (n < B.ns && i < B.ni && jmin_wall(B, i))
         face_load(blks, b, n, i, q, ffw, xy, SJ, dJ, c, xm, ym, mo, acc);
     __shared__ double red[3][kBS];
     for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];

@@ -20,6 +20,12 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, in
                 case HB_BC_PERIODIC: i = i < 0 ? i + K.ni : i - K.ni; break;
                 case HB_BC_WALL: i = side == 0 ? k : K.ni - 1 - k; mir ^= 1; break;
                 case HB_BC_CUT: {
+                    if (!glued_at(K, S.data(), side, j)) {
+                        if (K.rest[side] != HB_BC_WALL) return GSrc{0, b, 0, 0, mir};
+                        i = side == 0 ? k : K.ni - 1 - k;
+                        mir ^= 1;
+                        break;
+                    }
                     int a, ia, ja;
                     cut_cell(B.data(), S.data(), b, side, k, j, &a, &ia, &ja);
                     b = a; i = ia; j = ja;
@@ -45,6 +51,12 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, in
                     }
                     break;
                 case HB_BC_CUT: {
+                    if (!glued_at(K, S.data(), side, i)) {
+                        if (K.rest[side] != HB_BC_WALL) return GSrc{0, b, 0, 0, mir};
+                        j = side == 2 ? k : K.nj - 1 - k;
+                        mir ^= 1;
+                        break;
+                    }
                     int a, ia, ja;
                     cut_cell(B.data(), S.data(), b, side, k, i, &a, &ia, &ja);
                     b = a; i = ia; j = ja;

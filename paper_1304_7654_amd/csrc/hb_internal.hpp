@@ -37,6 +37,8 @@ struct BlockDesc {
     int32_t cut_side[4];
     int32_t seg_off[4];      // the side's segments: segs[seg_off .. seg_off + seg_cnt), by start
     int32_t seg_cnt[4];
+    int32_t rest[4];         // kind of the cells of a CUT side that no segment covers:
+                             // 0 (the side is covered), HB_BC_WALL or HB_BC_FARFIELD
     const CutSeg *segs;      // the grid's segment table (device copy in blk_d)
     int32_t snap_off;        // per-snapshot tables: entries snap_off .. +ns
     int32_t d_off;           // D table (kNsPad x kNsPad per block)
@@ -221,20 +223,34 @@ struct hb_grid {
 
 namespace hb {
 
+// The segment of side `side` of block B that covers position p (a position
+// beyond the side's ends counts as its end cell), or -1.
+__host__ __device__ inline int cut_seg_at(const BlockDesc &B, const CutSeg *segs, int side, int p) {
+    const int L = side < 2 ? B.nj : B.ni;
+    const int pc = p < 0 ? 0 : (p >= L ? L - 1 : p);
+    const int o = B.seg_off[side], n = B.seg_cnt[side];
+    for (int t = o; t < o + n; ++t)
+        if (segs[t].start <= pc && pc < segs[t].start + segs[t].len) return t;
+    return -1;
+}
+
+// Position p of side `side` of block B is glued: a CUT side covered there
+// by a segment (every position of a side with rest[side] == 0).
+__host__ __device__ inline bool glued_at(const BlockDesc &B, const CutSeg *segs, int side, int p) {
+    return B.bc[side] == HB_BC_CUT && (B.rest[side] == 0 || cut_seg_at(B, segs, side, p) >= 0);
+}
+
 // The cell across a cut from ghost layer k (0 nearest) at position p of
 // side `side` of block b: the partner block *a and its cell (*i, *j) at
 // depth k inside the partner side.  A position beyond the side's ends (a
 // corner ghost) continues the end segment; the result may then lie
-// outside block *a, whose own side rules apply to it.
+// outside block *a, whose own side rules apply to it.  On a partly glued
+// side the caller checks glued_at first.
 __host__ __device__ inline void cut_cell(const BlockDesc *blks, const CutSeg *segs, int b, int side,
                                          int k, int p, int *a, int *i, int *j) {
     const BlockDesc &B = blks[b];
-    const int L = side < 2 ? B.nj : B.ni;
-    const int pc = p < 0 ? 0 : (p >= L ? L - 1 : p);
-    const int o = B.seg_off[side], n = B.seg_cnt[side];
-    int q = o;
-    for (int t = o + 1; t < o + n; ++t)
-        if (segs[t].start <= pc) q = t;
+    int q = cut_seg_at(B, segs, side, p);
+    if (q < 0) q = B.seg_off[side];
     const CutSeg g = segs[q];
     const int t = p - g.start;
     const int pp = g.pstart + (g.rev ? g.len - 1 - t : t);

@@ -74,7 +74,7 @@ __global__ void k_faces_i(const BlockDesc *blks, int b, const double *xy, const 
         double cx, cy;
         centre(blks, C, b, 0, j, cx, cy);
         if (B.bc[0] == HB_BC_PERIODIC) centre(blks, C, b, B.ni - 1, j, lx, ly);
-        else if (B.bc[0] == HB_BC_CUT) {
+        else if (glued_at(B, B.segs, 0, j)) {
             int a, ia, ja;
             cut_cell(blks, B.segs, b, 0, 0, j, &a, &ia, &ja);
             centre(blks, C, a, ia, ja, lx, ly);
@@ -86,7 +86,7 @@ __global__ void k_faces_i(const BlockDesc *blks, int b, const double *xy, const 
         double cx, cy;
         centre(blks, C, b, B.ni - 1, j, cx, cy);
         if (B.bc[1] == HB_BC_PERIODIC) centre(blks, C, b, 0, j, rx, ry);
-        else if (B.bc[1] == HB_BC_CUT) {
+        else if (glued_at(B, B.segs, 1, j)) {
             int a, ia, ja;
             cut_cell(blks, B.segs, b, 1, 0, j, &a, &ia, &ja);
             centre(blks, C, a, ia, ja, rx, ry);
@@ -123,7 +123,7 @@ __global__ void k_faces_j(const BlockDesc *blks, int b, const double *xy, const 
         const bool wake = (kind == HB_BC_WAKECUT) && (i < B.wake || i >= B.ni - B.wake);
         if (kind == HB_BC_PERIODIC) centre(blks, C, b, i, B.nj - 1, lx, ly);
         else if (wake) centre(blks, C, b, B.ni - 1 - i, 0, lx, ly);
-        else if (kind == HB_BC_CUT) {
+        else if (glued_at(B, B.segs, 2, i)) {
             int a, ia, ja;
             cut_cell(blks, B.segs, b, 2, 0, i, &a, &ia, &ja);
             centre(blks, C, a, ia, ja, lx, ly);
@@ -135,7 +135,7 @@ __global__ void k_faces_j(const BlockDesc *blks, int b, const double *xy, const 
         double cx, cy;
         centre(blks, C, b, i, B.nj - 1, cx, cy);
         if (B.bc[3] == HB_BC_PERIODIC) centre(blks, C, b, i, 0, rx, ry);
-        else if (B.bc[3] == HB_BC_CUT) {
+        else if (glued_at(B, B.segs, 3, i)) {
             int a, ia, ja;
             cut_cell(blks, B.segs, b, 3, 0, i, &a, &ia, &ja);
             centre(blks, C, a, ia, ja, rx, ry);

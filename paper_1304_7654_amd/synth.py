@@ -18,7 +18,9 @@ Conventions
   The grid is right-handed: i runs along the body (clockwise), j outward.
 * Boundary tags per side (imin, imax, jmin, jmax): WALL, FARFIELD, PERIODIC,
   CUT, WAKECUT (C-grid wake on jmin; cells i < wake_ncells and
-  i >= ni - wake_ncells face each other across the cut, the rest is wall).
+  i >= ni - wake_ncells face each other across the cut, the rest is wall),
+  CUT_WALL and CUT_FARFIELD (partly glued: the cells that cut segments cover
+  are glued, the rest is wall or far field).
 * Snapshot n of N_s = 2*N_H+1 sits at phase 2*pi*n/N_s of the period.
 * State layout of one block: ``q[N_s][4][nj][ni]`` FP64, conserved
   (rho, rho*u, rho*v, rho*E); blocks are concatenated in order.
@@ -31,7 +33,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-WALL, FARFIELD, PERIODIC, CUT, WAKECUT = 1, 2, 3, 4, 5
+WALL, FARFIELD, PERIODIC, CUT, WAKECUT, CUT_WALL, CUT_FARFIELD = 1, 2, 3, 4, 5, 6, 7
 
 
 # --------------------------------------------------------------------------
@@ -391,6 +393,84 @@ def split_c_grid(problem: Problem):
     return out, np.concatenate(perm)
 
 
+def c_grid_pieces(b: Block, ib: Sequence[int], jb: Sequence[int]):
+    """A C-grid block (wake-cut jmin) cut at i positions ib and j positions
+    jb (both including 0 and the size) into glued pieces, numbered j-layer
+    major: (blocks, cuts, perm).  Neighbouring pieces are glued along whole
+    sides; on the bottom layer the wake cells of a piece are glued (reversed)
+    to the pieces holding their partners i <-> ni - 1 - i, so that a piece
+    holding wake and profile cells has a partly glued jmin (CUT_WALL), one
+    holding wake cells only a CUT jmin and one holding profile cells only a
+    WALL jmin."""
+    assert b.bc[2] == WAKECUT and b.wake_ncells > 0
+    ni, nj, w = b.ni, b.nj, b.wake_ncells
+    npi, npj = len(ib) - 1, len(jb) - 1
+    idx = lambda pi, pj: pj * npi + pi
+    blocks, cuts, perm = [], [], []
+    for pj in range(npj):
+        for pi in range(npi):
+            i0, i1, j0, j1 = ib[pi], ib[pi + 1], jb[pj], jb[pj + 1]
+            bc = [b.bc[0] if pi == 0 else CUT, b.bc[1] if pi == npi - 1 else CUT,
+                  CUT, b.bc[3] if pj == npj - 1 else CUT]
+            if pj == 0:
+                nwake = sum(1 for i in range(i0, i1) if i < w or i >= ni - w)
+                bc[2] = WALL if nwake == 0 else (CUT if nwake == i1 - i0 else CUT_WALL)
+            xy = np.ascontiguousarray(b.xy[:, j0:j1 + 1, i0:i1 + 1])
+            blocks.append(Block(i1 - i0, j1 - j0, b.n_harm, xy, tuple(bc), 0, b.body_id))
+            perm.append(_cell_perm(0, b.ns, nj, ni, j0, j1, i0, i1))
+            if pi + 1 < npi:
+                cuts.append((idx(pi, pj), 1, idx(pi + 1, pj), 0))
+            if pj + 1 < npj:
+                cuts.append((idx(pi, pj), 3, idx(pi, pj + 1), 2))
+    # wake: lower-wake cells [lo, hi) of piece p face cells [ni - hi, ni - lo) of piece q
+    for p in range(npi):
+        for q in range(npi):
+            lo = max(ib[p], ni - ib[q + 1], 0)
+            hi = min(ib[p + 1], ni - ib[q], w)
+            if lo < hi:
+                cuts.append((p, 2, lo - ib[p], q, 2, ni - hi - ib[q], hi - lo, 1))
+    return blocks, cuts, np.concatenate(perm)
+
+
+def split_c_grid_at(problem: Problem, ib: Sequence[int], jb: Sequence[int] = ()):
+    """A one-block C-grid problem cut by c_grid_pieces at i positions ib and
+    j positions jb (interior positions only).  Returns (problem, perm) with
+    state_split = state[perm]."""
+    assert len(problem.blocks) == 1
+    b = problem.blocks[0]
+    blocks, cuts, perm = c_grid_pieces(b, [0] + list(ib) + [b.ni], [0] + list(jb) + [b.nj])
+    out = Problem(problem.name + "_cpieces", blocks, problem.flow, problem.solver, problem.n_iter,
+                  problem.seed, problem.design, problem.notes, cuts)
+    return out, perm
+
+
+def c_grid_l(n_harm: int, scale: int = 1, body_id: int = 0):
+    """Four uneven blocks of one C-grid of (448 x 160) / scale cells: the
+    bottom layer (64 / scale rows) in three blocks of 256, 128 and 64
+    columns (the lower wake and lower surface; the upper surface and the
+    start of the upper wake; the rest of the upper wake), and one block of
+    192 x 96 over the last two.  The wake is glued across the jmin sides of
+    the bottom blocks (c_grid_pieces); the sides that face the part of the
+    C-grid left out (the top of the first block, the imin side of the upper
+    block) and the outer boundary are far field.  Returns (blocks, cuts)."""
+    assert scale in (1, 2, 4, 8)
+    ni, nj, h = 448 // scale, 160 // scale, 64 // scale
+    big = Block(ni, nj, n_harm, c_grid(ni, nj), (FARFIELD, FARFIELD, WAKECUT, FARFIELD),
+                ni // 4, body_id)
+    ib = [0, 256 // scale, 384 // scale, ni]
+    bottom, cuts, _ = c_grid_pieces(Block(ni, h, n_harm, np.ascontiguousarray(big.xy[:, :h + 1, :]),
+                                          big.bc, big.wake_ncells, body_id), ib, [0, h])
+    A, B, D = bottom
+    bottom[0] = Block(A.ni, A.nj, n_harm, A.xy, (A.bc[0], A.bc[1], A.bc[2], FARFIELD), 0, body_id)
+    bottom[1] = Block(B.ni, B.nj, n_harm, B.xy, (B.bc[0], B.bc[1], B.bc[2], CUT), 0, body_id)
+    bottom[2] = Block(D.ni, D.nj, n_harm, D.xy, (D.bc[0], D.bc[1], D.bc[2], CUT), 0, body_id)
+    top = Block(ni - ib[1], nj - h, n_harm, np.ascontiguousarray(big.xy[:, h:, ib[1]:]),
+                (FARFIELD, FARFIELD, CUT, FARFIELD), 0, body_id)
+    nb = ib[2] - ib[1]
+    cuts = cuts + [(1, 3, 0, 3, 2, 0, nb, 0), (2, 3, 0, 3, 2, nb, ni - ib[2], 0)]
+    return bottom + [top], cuts
+
+
 def rotate_block(problem: Problem, k: int):
     """Block k re-indexed by a quarter turn of its index space (orientation
     kept): node (I, J) becomes (J, ni - I), cell (i, j) becomes
@@ -509,7 +589,8 @@ def make_problem(name: str) -> Problem:
     """The workloads (names describe what they are):
 
     cyl64x32_nh1      O-grid 64x32 around a unit circle, N_H=1, 100 iterations, FP64
-    naca4blk_nh2      4 independent C-grid blocks (256x64, 128x64, 192x96, 64x64), N_H=2,
+    naca4blk_nh2      4 glued blocks of one C-grid (256x64, 128x64, 64x64 in the
+                      bottom layer, 192x96 above the last two; c_grid_l), N_H=2,
                       500 iterations, FP64
     naca1024x512_nh4  C-grid 1024x512, N_H=4, FP32 bulk vs FP64 (converged forces)
     naca256x128_hh64  C-grid 256x128, N_H=2, 64 Hicks-Henne bumps + inflow angle (adjoint)
@@ -522,9 +603,8 @@ def make_problem(name: str) -> Problem:
     if name == "cyl64x32_nh1":
         return Problem(name, [o_block(64, 32, 1)], flow_cylinder(), Solver(cfl=1.5), 100, 1304)
     if name == "naca4blk_nh2":
-        sizes = [(256, 64), (128, 64), (192, 96), (64, 64)]
-        return Problem(name, [c_block(a, b, 2, k) for k, (a, b) in enumerate(sizes)],
-                       flow_airfoil(), Solver(), 500, 1305)
+        blocks, cuts = c_grid_l(2)
+        return Problem(name, blocks, flow_airfoil(), Solver(), 500, 1305, cuts=cuts)
     if name == "naca1024x512_nh4":
         return Problem(name, [c_block(1024, 512, 4)], flow_airfoil(), Solver(precision=1),
                        100000, 1306)

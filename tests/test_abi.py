@@ -121,6 +121,17 @@ def test_validation_rejects_before_device_work():
         with pytest.raises(hb.HBError) as e:
             hb.Grid(sp.blocks, sp.flow, sp.solver, cuts)
         assert e.value.code == hb.HB_ERR_ARG, cuts
+    # partly glued sides (HB_BC_CUT_WALL / HB_BC_CUT_FARFIELD): segments may
+    # leave cells uncovered but must not overlap; kinds above 7 are unknown
+    pl = [synth.Block(x.ni, x.nj, x.n_harm, x.xy,
+                      tuple(synth.CUT_WALL if k == synth.CUT else k for k in x.bc), 0, 0)
+          for x in sp.blocks]
+    part = [(a, sa, 0, b2_, sb, 0, side - 2, 0)] + others
+    assert _try(pl, cuts=part) != hb.HB_ERR_ARG               # passes validation
+    assert _try(pl, cuts=[(a, sa, 0, b2_, sb, 0, 3, 0), (a, sa, 2, b2_, sb, 2, 3, 0)] + others) \
+        == hb.HB_ERR_ARG                                       # overlap
+    odd = synth.Block(b.ni, b.nj, 1, b.xy, (3, 3, 8, 2))
+    assert _try([odd]) == hb.HB_ERR_ARG
 
 
 def test_binding_rejects_bad_tensors():

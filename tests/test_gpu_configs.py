@@ -1,8 +1,8 @@
 """Parity at the configurations' own sizes and iteration counts: the
 64x32 N_H = 1 cylinder after its 100 iterations and the four-block N_H = 2
-airfoil (256x64, 128x64, 192x96, 64x64) after its 500, on the per-block
-plain FP64 path and the batched FP64 path, against the FP64 oracle run
-through the same iterations.
+airfoil (256x64, 128x64, 64x64 and 192x96 glued blocks of one C-grid)
+after its 500, on the per-block plain FP64 path and the batched FP64 path,
+against the FP64 oracle run through the same iterations.
 
 - State after N iterations: the change from the initial state per
   variable within 1e-10 (relative 2-norm over all blocks, cells and
@@ -11,8 +11,8 @@ through the same iterations.
   variable within 1e-12, or four times the FP64 rounding floor of the
   residual on that state where that is larger (parity_util.fp64_floor).
 
-The oracle trajectory is computed once per configuration, one worker
-process per block."""
+The oracle trajectory is computed once per configuration: the glued blocks
+together, the blocks of a grid without cuts one worker process each."""
 import multiprocessing as mp
 import os
 import time
@@ -34,29 +34,39 @@ def _say(*a):
 
 
 def _trajectory(name):
-    """Oracle states after 0, 1, 10 and N iterations and all N norms.  The
-    blocks of these configurations have no cuts, so each block's iterations
-    run on their own in a worker process, and the norm of an iteration is
-    put together from the blocks' sums of squares."""
+    """Oracle states after 0, 1, 10 and N iterations and all N norms.
+    Blocks glued by cuts iterate together; the blocks of a grid without
+    cuts run on their own in worker processes, and the norm of an iteration
+    is put together from the blocks' sums of squares."""
     if name in _TRAJ:
         return _TRAJ[name]
     p = synth.make_problem(name)
     blocks, flow, solver = O.from_synth(p)
-    assert not p.cuts
     q = torch.as_tensor(synth.initial_state(p))
     marks = (1, 10, p.n_iter)
     nb = len(blocks)
-    threads = max(1, (os.cpu_count() or 1) // nb)
     t0 = time.time()
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(nb) as pool:
-        res = pool.map(block_trajectory, [(name, k, marks, threads) for k in range(nb)])
-    _say("  oracle %s: %d iterations of %d blocks (%.0f s)" % (name, p.n_iter, nb, time.time() - t0))
-    total = sum(b.ns * b.ni * b.nj for b in blocks)
     states = {0: q}
-    for m in marks:
-        states[m] = O.join([r[0][m] for r in res])
-    norms = torch.sqrt(sum(r[1] for r in res) / total)
+    if p.cuts:
+        torch.set_num_threads(min(16, os.cpu_count() or 1))
+        qq, done, parts = q, 0, []
+        for m in marks:
+            qq, nr = O.rk_iterate(blocks, qq, flow, solver, m - done, p.cuts)
+            states[m] = qq
+            parts.append(nr)
+            done = m
+            _say("  oracle %s: %d iterations (%.0f s)" % (name, m, time.time() - t0))
+        norms = torch.cat(parts)
+    else:
+        threads = max(1, (os.cpu_count() or 1) // nb)
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(nb) as pool:
+            res = pool.map(block_trajectory, [(name, k, marks, threads) for k in range(nb)])
+        total = sum(b.ns * b.ni * b.nj for b in blocks)
+        for m in marks:
+            states[m] = O.join([r[0][m] for r in res])
+        norms = torch.sqrt(sum(r[1] for r in res) / total)
+    _say("  oracle %s: %d iterations of %d blocks (%.0f s)" % (name, p.n_iter, nb, time.time() - t0))
     _TRAJ[name] = (p, blocks, flow, solver, states, norms)
     return _TRAJ[name]
 
@@ -67,7 +77,7 @@ def test_state_after_full_iteration_count(name, batched):
     p, blocks, flow, solver, states, nref = _trajectory(name)
     n = p.n_iter
     _say("case", name, "batched", batched, n, "iterations")
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=batched)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=batched)
     q0 = states[0]
     qd = q0.to(DEV)
     norms = torch.zeros(n, dtype=torch.float64, device=DEV)
@@ -85,10 +95,10 @@ def test_state_after_full_iteration_count(name, batched):
 @pytest.mark.parametrize("batched", [0, 1])
 def test_residual_on_oracle_states(name, batched):
     p, blocks, flow, solver, states, _ = _trajectory(name)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=batched)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=batched)
     for it in (1, 10, p.n_iter):
         q = states[it]
-        floor, ref = fp64_floor(blocks, q, flow, solver)
+        floor, ref = fp64_floor(blocks, q, flow, solver, p.cuts)
         tol = fp64_tolerance(floor)
         r = g.residual(q.to(DEV)).cpu()
         torch.cuda.synchronize()

@@ -109,9 +109,15 @@ def _rotated(p):
     return sp, perm0[perm]
 
 
+def _pieces(p):
+    # jmin sides of wake only (CUT), wake and profile (CUT_WALL, one with
+    # wake segments to two pieces) and profile only (WALL), in two layers
+    return synth.split_c_grid_at(p, [10, 40, 60], [8])
+
+
 GENERAL = [("naca_tiny", synth.split_c_grid), ("cyl_tiny", synth.split_partial),
-           ("cyl_tiny", _rotated)]
-GENERAL_IDS = ["c_grid_3", "partial", "rotated"]
+           ("cyl_tiny", _rotated), ("naca_tiny", _pieces)]
+GENERAL_IDS = ["c_grid_3", "partial", "rotated", "partly_glued"]
 
 
 def _general(name, make):
@@ -188,3 +194,60 @@ def test_general_cuts_refuse_motion():
     with pytest.raises(hb.HBError) as e:
         g.set_motion(pitch_amp=0.1)
     assert e.value.code == hb.HB_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,batched", PATHS)
+def test_four_block_c_grid_layout(prec, batched):
+    """The four-block airfoil layout (synth.c_grid_l) at a quarter of its
+    size: 64 | 32 | 16 columns of 16 rows and 48 x 24 above the last two,
+    the wake glued over two segments of the first block's partly glued
+    jmin.  Residual, three iterations and forces against the oracle on the
+    same blocks (the oracle pins the layout against the whole C-grid)."""
+    _say("four-block C-grid layout, prec", prec, "batched", batched)
+    blocks, cuts = synth.c_grid_l(2, 4)
+    fl = synth.flow_airfoil()
+    fl.alpha0 = 0.03
+    p = synth.Problem("l4", blocks, fl, synth.Solver(), 0, 7, cuts=cuts)
+    ob, flow, solver = O.from_synth(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    ref = O.residual_all(ob, q, flow, solver, cuts)
+    n_it = 3
+    qref, nref = O.rk_iterate(ob, q, flow, solver, n_it, cuts)
+    cref = torch.cat([c.reshape(-1) for c in O.forces(ob, qref, flow, solver, cuts=cuts)])
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=cuts, precision=prec, batched=batched)
+    r = g.residual(q.to(DEV)).cpu()
+    qd = q.to(DEV)
+    norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    cf = torch.zeros(g.n_forces, dtype=torch.float64, device=DEV)
+    g.rk_iterate(qd, n_it, norms, cf)
+    torch.cuda.synchronize()
+    assert g.status() == hb.HB_OK
+    e_or = _rel(r, ref)
+    dq = _rel(qd.cpu() - q, qref - q)
+    dn = float(((norms.cpu() - nref).abs() / nref).max())
+    dc = float((cf.cpu() - cref).abs().max() / cref.abs().max())
+    _say("  residual", e_or, "state", dq, "norms", dn, "forces", dc)
+    assert e_or <= (1e-12 if prec == 0 else 1e-5)
+    assert dq <= (1e-11 if prec == 0 else 1e-5)
+    assert dn <= (1e-12 if prec == 0 else 1e-5)
+    assert dc <= (1e-10 if prec == 0 else 1e-4)
+    if prec == 0 and batched == 1:
+        rbar = torch.randn(q.shape, generator=torch.Generator().manual_seed(4), dtype=torch.float64)
+        qb_ref, xb_ref, ab_ref = O.residual_vjp(ob, q, flow, solver, rbar, cuts)
+        xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
+        ab = torch.empty(1, dtype=torch.float64, device=DEV)
+        qb = g.residual_adjoint(q.to(DEV), rbar.to(DEV), None, xyb, ab)
+        cfbar = torch.randn(g.n_forces, generator=torch.Generator().manual_seed(5), dtype=torch.float64)
+        fq_ref, fx_ref, fa_ref = O.forces_vjp(ob, q, flow, solver, cfbar, cuts)
+        fxb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
+        fab = torch.empty(1, dtype=torch.float64, device=DEV)
+        fqb = g.forces_adjoint(q.to(DEV), cfbar.to(DEV), None, fxb, fab)
+        torch.cuda.synchronize()
+        xr = torch.cat([x.reshape(-1) for x in xb_ref])
+        fxr = torch.cat([x.reshape(-1) for x in fx_ref])
+        _say("  adjoint qbar", _rel(qb.cpu(), qb_ref), "xybar", _rel(xyb.cpu(), xr),
+             "forces qbar", _rel(fqb.cpu(), fq_ref), "xybar", _rel(fxb.cpu(), fxr))
+        assert _rel(qb.cpu(), qb_ref) <= 1e-11 and _rel(xyb.cpu(), xr) <= 1e-11
+        assert abs(float(ab) - float(ab_ref)) <= 1e-11 * abs(float(ab_ref))
+        assert _rel(fqb.cpu(), fq_ref) <= 1e-11 and _rel(fxb.cpu(), fxr) <= 1e-11
+        assert abs(float(fab) - float(fa_ref)) <= 1e-11 * abs(float(fa_ref))

@@ -50,8 +50,8 @@ def test_plain_fp64_residual(name):
     p = synth.make_problem(name)
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
-    ref = O.residual_all(blocks, q, flow, solver)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    ref = O.residual_all(blocks, q, flow, solver, p.cuts)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=0)
     r = g.residual(q.to(DEV)).cpu()
     torch.cuda.synchronize()
     assert per_var_rel(blocks, r, ref) <= 1e-12
@@ -65,8 +65,8 @@ def test_plain_fp64_rk_iterate(name):
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
     n_it = 3
-    qref, nref = O.rk_iterate(blocks, q, flow, solver, n_it)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    qref, nref = O.rk_iterate(blocks, q, flow, solver, n_it, p.cuts)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=0)
     qd = q.to(DEV)
     norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
     g.rk_iterate(qd, n_it, norms)
@@ -83,8 +83,8 @@ def test_forces_fp64(name):
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
     q1, _ = O.rk_iterate(blocks, q, flow, solver, 2)
-    ref = torch.cat([c.reshape(-1) for c in O.forces(blocks, q1, flow, solver)])
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
+    ref = torch.cat([c.reshape(-1) for c in O.forces(blocks, q1, flow, solver, cuts=p.cuts)])
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=0)
     cf = g.forces(q1.to(DEV)).cpu()
     torch.cuda.synchronize()
     assert torch.allclose(cf, ref, rtol=1e-11, atol=1e-13 * float(ref.abs().max()))
@@ -99,8 +99,8 @@ def test_fused_fp64_residual(name):
     p = synth.make_problem(name)
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
-    ref = O.residual_all(blocks, q, flow, solver)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    ref = O.residual_all(blocks, q, flow, solver, p.cuts)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=1)
     r = g.residual(q.to(DEV)).cpu()
     torch.cuda.synchronize()
     assert per_var_rel(blocks, r, ref) <= 1e-12
@@ -115,8 +115,8 @@ def test_fused_fp32_residual(name):
     p = synth.make_problem(name)
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
-    ref = O.residual_all(blocks, q, flow, solver)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+    ref = O.residual_all(blocks, q, flow, solver, p.cuts)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=1, batched=1)
     r = g.residual(q.to(DEV)).cpu()
     torch.cuda.synchronize()
     err = per_var_rel(blocks, r, ref)
@@ -132,8 +132,8 @@ def test_fused_rk_iterate(name, prec):
     blocks, flow, solver = O.from_synth(p)
     q = torch.as_tensor(synth.initial_state(p))
     n_it = 3
-    qref, nref = O.rk_iterate(blocks, q, flow, solver, n_it)
-    g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=1)
+    qref, nref = O.rk_iterate(blocks, q, flow, solver, n_it, p.cuts)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=prec, batched=1)
     qd = q.to(DEV)
     norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
     g.rk_iterate(qd, n_it, norms)
@@ -154,7 +154,7 @@ def test_fused_deterministic_and_tile_independent():
     q = torch.as_tensor(synth.initial_state(p)).to(DEV)
     outs = []
     for tile in (16, 32):
-        g = hb.Grid(p.blocks, p.flow, p.solver, precision=1, batched=1)
+        g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=1, batched=1)
         g.set_tuning(tile_i=tile)
         r1 = g.residual(q).clone()
         r2 = g.residual(q).clone()
@@ -177,8 +177,8 @@ def test_fused_deterministic_and_tile_independent():
 def test_fused_matches_plain_fp64():
     p = synth.make_problem("naca4blk_nh2")
     q = torch.as_tensor(synth.initial_state(p)).to(DEV)
-    gp = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=0)
-    gf = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    gp = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=0)
+    gf = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=1)
     rp, rf = gp.residual(q), gf.residual(q)
     torch.cuda.synchronize()
     assert float((rp - rf).norm() / rp.norm()) <= 1e-13
