@@ -257,8 +257,8 @@ int hb_forces(hb_grid *g, const double *q, double *cf, void *stream);
  * FP64 only (HB_ERR_UNSUPPORTED for an FP32-bulk grid).  With a motion set
  * (hb_set_motion) the products are those of the moving-grid R* (snapshot
  * n's rotated face vectors, face speeds, moving-wall images), the motion
- * and the body-frame nodes held fixed; xybar must then be NULL
- * (HB_ERR_UNSUPPORTED otherwise).  The adjoints'
+ * held fixed; xybar is then the adjoint of the body-frame nodes (through
+ * the face vectors, the face speeds and the wall velocities).  The adjoints'
  * scratch (the inverse ghost map, per-face adjoint terms: 26 doubles per
  * face and snapshot) is allocated by the first adjoint call unless
  * hb_prepare allocated it before. */
@@ -272,8 +272,8 @@ int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar,
  * (device, 1 double: d/d alpha0, may be NULL) receive (d cf / d .)^T cfbar,
  * overwritten.  Only wall faces contribute; alpha0 enters through the wind
  * axes and the far-field ghosts.  FP64 arithmetic on any grid.  qbar must
- * not alias q.  With a motion set: the moving-grid loads of hb_forces,
- * xybar NULL (HB_ERR_UNSUPPORTED otherwise). */
+ * not alias q.  With a motion set: the moving-grid loads of hb_forces
+ * (xybar: body-frame nodes, the moment arm rotating with the body). */
 int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar,
                       double *qbar, double *xybar, double *flowbar, void *stream);
 
@@ -408,8 +408,7 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
  * adjoints (FP64).
  * HB_ERR_UNSUPPORTED for blocks with walls on an i side or cuts other than
  * whole opposite sides glued aligned; while a motion is
- * set hb_set_xy and coordinate adjoints (xybar non-NULL) return
- * HB_ERR_UNSUPPORTED; the adjoints take the motion.  Across a cut,
+ * set hb_set_xy returns HB_ERR_UNSUPPORTED; the adjoints take the motion.  Across a cut,
  * the wall image of a corner ghost takes the glued block's wall face.
  * HB_ERR_ARG for non-finite values.  Drops the batched path's captured
  * iterations (the next hb_rk_iterate captures them again).  Synchronises

@@ -163,12 +163,13 @@ def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Te
 
 
 def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, cuts=(),
-                     alpha0=None):
+                     alpha0=None, body_xys=None):
     """For every block k and snapshot n: (k, n, moved nodes, ghost-extended
     primitives with moving-wall images, moved centres of the glued blocks,
     (theta, theta_dot, h, h_dot)).  Cut ghosts are the glued block's cells of
     the same snapshot (hb_oracle.extend_all); glued blocks share N_s.
-    `alpha0` (a 0-d tensor) overrides the mean incidence of the far field."""
+    `alpha0` (a 0-d tensor) overrides the mean incidence of the far field,
+    `body_xys` the body-frame nodes of the blocks."""
     P = O.cut_partners(blocks, cuts) if cuts else {}
     for b in blocks:
         check_block(b)
@@ -181,7 +182,8 @@ def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, 
         wes = O.extend_all(blocks, [w[s:s + 1] for w, s in zip(ws, sel)],
                            [f[s:s + 1] for f, s in zip(winfs, sel)], P)
         mot = [snapshot_motion(m, flow, b.ns, s) for b, s in zip(blocks, sel)]
-        xys = [torch.stack(place(m, mt[0], mt[2], b.xy[0], b.xy[1])) for b, mt in zip(blocks, mot)]
+        bxy = [b.xy for b in blocks] if body_xys is None else body_xys
+        xys = [torch.stack(place(m, mt[0], mt[2], x[0], x[1])) for x, mt in zip(bxy, mot)]
         for k, b in enumerate(blocks):
             if n >= b.ns:
                 continue
@@ -247,17 +249,21 @@ def moving_td_march(b: O.OBlock, q: torch.Tensor, flow: O.OFlow, solver: O.OSolv
 
 
 def moving_residual_all(blocks: Sequence[O.OBlock], q: torch.Tensor, flow, solver,
-                        m: OMotion, cuts=(), alpha0=None) -> torch.Tensor:
+                        m: OMotion, cuts=(), alpha0=None, body_xys=None) -> torch.Tensor:
     """R* of all blocks on the moving grid; `cuts` glue block sides;
-    `alpha0` (a 0-d tensor) overrides the mean incidence."""
+    `alpha0` (a 0-d tensor) overrides the mean incidence, `body_xys` the
+    body-frame nodes."""
     qs = O.split(blocks, q)
     parts = [[None] * b.ns for b in blocks]
-    for k, n, xy, we, nbrC, (_, thd, h, hd) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0):
+    bxy = [b.xy for b in blocks] if body_xys is None else body_xys
+    for k, n, xy, we, nbrC, (_, thd, h, hd) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0,
+                                                                 body_xys):
         vg = face_speeds(xy, m, thd, h, hd)
         FI, FJ = O.face_fluxes(blocks[k], qs[k][n:n + 1], flow, solver, xy=xy, we=we, vg=vg,
                                nbrC=nbrC)
         parts[k][n] = (FI[..., :, 1:] - FI[..., :, :-1]) + (FJ[..., 1:, :] - FJ[..., :-1, :])
-    return O.join([torch.cat(p) + O.hb_source(b, qb, flow) for p, b, qb in zip(parts, blocks, qs)])
+    return O.join([torch.cat(p) + O.hb_source(b, qb, flow, x)
+                   for p, b, qb, x in zip(parts, blocks, qs, bxy)])
 
 
 def moving_local_dt(b: O.OBlock, q0: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
@@ -303,18 +309,20 @@ def moving_rk_iterate(blocks, q: torch.Tensor, flow, solver, m: OMotion, n_iter:
 
 
 def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
-                  m: OMotion, cuts=(), alpha0=None) -> List[torch.Tensor]:
+                  m: OMotion, cuts=(), alpha0=None, body_xys=None) -> List[torch.Tensor]:
     """hb_oracle.forces on the moved grids: per snapshot the wall loads of
     grid n (moving-wall ghosts), the moment about the moved reference point,
     lift and drag along the mean free stream.  [body][ns][3] = (cl, cd, cm).
-    `alpha0` (a 0-d tensor) overrides the mean incidence."""
+    `alpha0` (a 0-d tensor) overrides the mean incidence, `body_xys` the
+    body-frame nodes."""
     a0 = torch.as_tensor(flow.alpha0 if alpha0 is None else alpha0, dtype=DT)
     qinf = 0.5 * flow.mach ** 2
     nbody = max(b.body_id for b in blocks) + 1
     acc = [None] * nbody
     qs = O.split(blocks, q)
     rows = [[None] * b.ns for b in blocks]
-    for k, n, xy, we, nbrC, (th, _, h, _) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0):
+    for k, n, xy, we, nbrC, (th, _, h, _) in moving_snapshots(blocks, qs, flow, m, cuts, alpha0,
+                                                              body_xys):
         xm, ym = place(m, th, h, torch.tensor(flow.x_mom, dtype=DT), torch.tensor(flow.y_mom, dtype=DT))
         fn = dataclasses.replace(flow, x_mom=float(xm), y_mom=float(ym))
         rows[k][n] = O.block_loads(blocks[k], qs[k][n:n + 1], fn, xy=xy, we=we, nbrC=nbrC)[0]
@@ -337,20 +345,23 @@ def moving_forces(blocks, q: torch.Tensor, flow: O.OFlow, solver: O.OSolver,
 def moving_residual_vjp(blocks, q: torch.Tensor, flow, solver, m: OMotion, rbar: torch.Tensor,
                         cuts=()):
     """Products of the transposed Jacobians of the moving-grid R* with rbar,
-    by automatic differentiation of moving_residual_all: (qbar, alpha0bar).
-    The motion and the body-frame nodes are held fixed."""
+    by automatic differentiation of moving_residual_all: (qbar, [body-frame
+    node bars per block], alpha0bar), the motion held fixed."""
     qv = q.detach().clone().requires_grad_(True)
+    xys = [b.xy.detach().clone().requires_grad_(True) for b in blocks]
     a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
-    (moving_residual_all(blocks, qv, flow, solver, m, cuts, a0) * rbar).sum().backward()
-    return qv.grad.detach(), a0.grad.detach()
+    (moving_residual_all(blocks, qv, flow, solver, m, cuts, a0, xys) * rbar).sum().backward()
+    return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()
 
 
 def moving_forces_vjp(blocks, q: torch.Tensor, flow, solver, m: OMotion, cfbar: torch.Tensor,
                       cuts=()):
     """Products of the transposed Jacobians of the moving-grid force
-    coefficients (flattened [body][n][3]) with cfbar: (qbar, alpha0bar)."""
+    coefficients (flattened [body][n][3]) with cfbar: (qbar, [body-frame
+    node bars per block], alpha0bar)."""
     qv = q.detach().clone().requires_grad_(True)
+    xys = [b.xy.detach().clone().requires_grad_(True) for b in blocks]
     a0 = torch.tensor(flow.alpha0, dtype=DT, requires_grad=True)
-    cf = torch.cat([c.reshape(-1) for c in moving_forces(blocks, qv, flow, solver, m, cuts, a0)])
+    cf = torch.cat([c.reshape(-1) for c in moving_forces(blocks, qv, flow, solver, m, cuts, a0, xys)])
     (cf * cfbar).sum().backward()
-    return qv.grad.detach(), a0.grad.detach()
+    return qv.grad.detach(), [x.grad.detach() for x in xys], a0.grad.detach()

@@ -106,7 +106,8 @@ template <bool NT>
 __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], const UVT<double> &P,
                                 const UVT<double> &Q, double sx, double sy, double dx, double dy,
                                 const double Fb[4], const Consts &c, double *out, int64_t nf,
-                                double vg) {
+                                double vg, const MotionSnap *ms, double gx, double gy, double *mb,
+                                int64_t mbs) {
     const double g = c.gamma;
     // viscous part first (net flux = Roe - viscous: it sees -Fb, its mass
     // term is 0): its node adjoints are final at once and are stored, which
@@ -132,7 +133,22 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
         const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
         W4<double> L, R;
         muscl_a(m2, m1, p0, p1, c.eps, L, R);
-        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb, vg);
+        double vgb = 0.0;
+        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb, vg, ms ? &vgb : nullptr);
+        if (ms) {
+            // vg = (gx, gy) . S, (gx, gy) the grid velocity at the body-frame
+            // midpoint; S and d are the body-frame vectors rotated by theta_n
+            sxb += vgb * gx;
+            syb += vgb * gy;
+            if (mb) {
+                double xb, yb;
+                grid_velocity_rev(*ms, vgb * sx, vgb * sy, xb, yb);
+                mb[0] = xb;
+                mb[mbs] = yb;
+            }
+            rot2_rev(*ms, sxb, syb);
+            rot2_rev(*ms, dxb, dyb);
+        }
     }
     ntst<NT>(out + 22 * nf, sxb);
     ntst<NT>(out + 23 * nf, syb);
@@ -162,16 +178,19 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
 // (i+1, j) [start] in slot 0 and node (i, j) [end] in slot 1.
 // On a moving grid (mo.tab) the face's S and d are those of snapshot n (the
 // body-frame vectors rotated by theta_n) and it moves with the grid velocity
-// at its midpoint (the forward flux of the plain kernels).
+// (gx, gy) at its midpoint (the forward flux of the plain kernels): returns
+// vg = (gx, gy) . S.  The face kernels then store the S and d adjoints taken
+// back to the body frame, and, with Mb, the adjoint of the body-frame
+// midpoint per face and snapshot ([2][nf] per snapshot, offsets afi_off /
+// kAF * 2 and afj_off / kAF * 2).
 __device__ __forceinline__ double moving_geo(const Motion &mo, const BlockDesc &B, int n, const double *xy,
                                              int64_t kA, int64_t kB, double &sx, double &sy, double &dx,
-                                             double &dy) {
-    const MotionSnap m = motion_snap(mo, B, n);
+                                             double &dy, MotionSnap &m, double &gx, double &gy) {
+    m = motion_snap(mo, B, n);
     rot2(m, sx, sy);
     rot2(m, dx, dy);
     const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
     const double *x = xy + 2 * B.node_off, *y = x + nn;
-    double gx, gy;
     grid_velocity(m, mo, 0.5 * (x[kA] + x[kB]), 0.5 * (y[kA] + y[kB]), gx, gy);
     return gx * sx + gy * sy;
 }
@@ -179,7 +198,7 @@ __device__ __forceinline__ double moving_geo(const Motion &mo, const BlockDesc &
 template <bool NT>
 __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
                              const double *dI, const double *rbar, Consts c, double *AF, Motion mo,
-                             const double *xy, int64_t tid_) {
+                             const double *xy, double *Mb, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
@@ -204,16 +223,19 @@ __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const d
     const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
     double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
     double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
-    double vg = 0.0;
-    if (mo.tab) vg = moving_geo(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy);
+    double vg = 0.0, gx = 0.0, gy = 0.0;
+    MotionSnap m;
+    if (mo.tab)
+        vg = moving_geo(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy, m, gx, gy);
     face_rev<NT>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
-             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg);
+             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg, mo.tab ? &m : nullptr, gx, gy,
+             Mb ? Mb + B.afi_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
 
 template <bool NT>
 __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
                              const double *dJ, const double *rbar, Consts c, double *AF, Motion mo,
-                             const double *xy, int64_t tid_) {
+                             const double *xy, double *Mb, int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const int64_t t = tid_;
@@ -240,13 +262,15 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
     const double Fb[4] = {rl[0] - rr[0], rl[1] - rr[1], rl[2] - rr[2], rl[3] - rr[3]};
     double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
     double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
-    double vg = 0.0;
+    double vg = 0.0, gx = 0.0, gy = 0.0;
+    MotionSnap m;
     if (mo.tab) {
         const int64_t kA = (int64_t)j * (B.ni + 1) + i;
-        vg = moving_geo(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy);
+        vg = moving_geo(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy, m, gx, gy);
     }
     face_rev<NT>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
-             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg);
+             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg, mo.tab ? &m : nullptr, gx, gy,
+             Mb ? Mb + B.afj_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
 
 // one launch for both face families of block b: workgroup w takes i-face
@@ -260,7 +284,7 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
                                                    const double *SJ, const double *dJ,
                                                    const double *rbar, Consts c, double *AFI,
                                                    double *AFJ, int64_t nI, int xcd, Motion mo,
-                                                   const double *xy) {
+                                                   const double *xy, double *MbI, double *MbJ) {
     const BlockDesc &B = blks[b];
     const int64_t nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
     constexpr int kHalf = kBS / 2;
@@ -269,9 +293,9 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
     if (L < 0) return;
     const int64_t t = L * kHalf + (threadIdx.x % kHalf);
     if (threadIdx.x < kHalf) {
-        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, t);
+        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, MbI, t);
     } else if (t < nJ) {
-        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, t);
+        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, MbJ, t);
     }
 }
 
@@ -640,67 +664,86 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
 // atomics.
 // i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
 // d = centre(R) - centre(L)
-__device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb, double *G, int64_t n_fi, int64_t tid_) {
+__device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *Mb,
+                           const double *xy, const double *C, double *xyb, double *G, int64_t n_fi,
+                           int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)W * B.nj;
     const int64_t f = tid_;
     if (f >= nf) return;
     const int i = (int)(f % W), j = (int)(f / W);
-    double sxb = 0, syb = 0, dxb = 0, dyb = 0;
+    double sxb = 0, syb = 0, dxb = 0, dyb = 0, mxb = 0, myb = 0;
     for (int n = 0; n < B.ns; ++n) {
         const double *a = AF + B.afi_off + (int64_t)n * kAF * nf + f;
         sxb += a[22 * nf];
         syb += a[23 * nf];
         dxb += a[24 * nf];
         dyb += a[25 * nf];
+        if (Mb) {
+            const double *mb = Mb + B.afi_off / kAF * 2 + (int64_t)n * 2 * nf + f;
+            mxb += mb[0];
+            myb += mb[nf];
+        }
     }
     double *g = G + B.fi_off + f;
     g[0] = sxb;
     g[n_fi] = syb;
     g[2 * n_fi] = dxb;
     g[3 * n_fi] = dyb;
+    g[4 * n_fi] = mxb;
+    g[5 * n_fi] = myb;
     const int64_t kA = (int64_t)j * W + i, kB = kA + W;
     if (i == B.ni) ghost_centre_rev(blks, b, 1, B.ni - 1, j, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
     if (i == 0) ghost_centre_rev(blks, b, 0, 0, j, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
 // j-faces: S_J = (yA - yB, xB - xA), A = node (i, j), B = node (i+1, j)
-__device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *xy,
-                           const double *C, double *xyb, double *G, int64_t n_fj, int64_t tid_) {
+__device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *Mb,
+                           const double *xy, const double *C, double *xyb, double *G, int64_t n_fj,
+                           int64_t tid_) {
     const BlockDesc &B = blks[b];
     const int W = B.ni + 1;
     const int64_t nf = (int64_t)B.ni * (B.nj + 1);
     const int64_t f = tid_;
     if (f >= nf) return;
     const int i = (int)(f % B.ni), j = (int)(f / B.ni);
-    double sxb = 0, syb = 0, dxb = 0, dyb = 0;
+    double sxb = 0, syb = 0, dxb = 0, dyb = 0, mxb = 0, myb = 0;
     for (int n = 0; n < B.ns; ++n) {
         const double *a = AF + B.afj_off + (int64_t)n * kAF * nf + f;
         sxb += a[22 * nf];
         syb += a[23 * nf];
         dxb += a[24 * nf];
         dyb += a[25 * nf];
+        if (Mb) {
+            const double *mb = Mb + B.afj_off / kAF * 2 + (int64_t)n * 2 * nf + f;
+            mxb += mb[0];
+            myb += mb[nf];
+        }
     }
     double *g = G + B.fj_off + f;
     g[0] = sxb;
     g[n_fj] = syb;
     g[2 * n_fj] = dxb;
     g[3 * n_fj] = dyb;
+    g[4 * n_fj] = mxb;
+    g[5 * n_fj] = myb;
     const int64_t kA = (int64_t)j * W + i, kB = kA + 1;
     if (j == B.nj) ghost_centre_rev(blks, b, 3, i, B.nj - 1, (int)kA, (int)kB, dxb, dyb, xy, C, xyb);
     if (j == 0) ghost_centre_rev(blks, b, 2, i, 0, (int)kA, (int)kB, -dxb, -dyb, xy, C, xyb);
 }
 
 // per-face step for both face families of block b in one launch
+// (per face: G holds the S, d and, on a moving grid, midpoint adjoints
+// summed over the snapshots, [6][n_fi] then [6][n_fj])
 __global__ void __launch_bounds__(kBS) k_adj_xy(const BlockDesc *blks, int b, const double *AFI,
-                                                const double *AFJ, const double *xy, const double *C,
+                                                const double *AFJ, const double *MbI,
+                                                const double *MbJ, const double *xy, const double *C,
                                                 double *xyb, double *G, int64_t n_fi, int64_t n_fj,
                                                 int64_t nI) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nI) adj_xy_i(blks, b, AFI, xy, C, xyb, G, n_fi, t);
-    else adj_xy_j(blks, b, AFJ, xy, C, xyb, G + 4 * n_fi, n_fj, t - nI);
+    if (t < nI) adj_xy_i(blks, b, AFI, MbI, xy, C, xyb, G, n_fi, t);
+    else adj_xy_j(blks, b, AFJ, MbJ, xy, C, xyb, G + 6 * n_fi, n_fj, t - nI);
 }
 
 // per-node step: one thread per node of block b
@@ -714,16 +757,17 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nn) return;
     const int i = (int)(k % W), j = (int)(k / W);
-    const double *gi = G + B.fi_off, *gj = G + 4 * n_fi + B.fj_off;
+    const double *gi = G + B.fi_off, *gj = G + 6 * n_fi + B.fj_off;
     auto GI = [&](int fi, int fj, int c) { return gi[c * n_fi + (int64_t)fj * W + fi]; };
     auto GJ = [&](int fi, int fj, int c) { return gj[c * n_fj + (int64_t)fj * ni + fi]; };
     double ax = 0.0, ay = 0.0;
     // face lengths: i-face (i, j) has this node as A, i-face (i, j-1) as B;
     // j-face (i, j) as A, j-face (i-1, j) as B
-    if (j < nj) { ay -= GI(i, j, 0); ax += GI(i, j, 1); }
-    if (j > 0) { ay += GI(i, j - 1, 0); ax -= GI(i, j - 1, 1); }
-    if (i < ni) { ay += GJ(i, j, 0); ax -= GJ(i, j, 1); }
-    if (i > 0) { ay -= GJ(i - 1, j, 0); ax += GJ(i - 1, j, 1); }
+    // (and, on a moving grid, half of each face's midpoint adjoint)
+    if (j < nj) { ay -= GI(i, j, 0); ax += GI(i, j, 1) + 0.5 * GI(i, j, 4); ay += 0.5 * GI(i, j, 5); }
+    if (j > 0) { ay += GI(i, j - 1, 0); ax -= GI(i, j - 1, 1); ax += 0.5 * GI(i, j - 1, 4); ay += 0.5 * GI(i, j - 1, 5); }
+    if (i < ni) { ay += GJ(i, j, 0); ax -= GJ(i, j, 1); ax += 0.5 * GJ(i, j, 4); ay += 0.5 * GJ(i, j, 5); }
+    if (i > 0) { ay -= GJ(i - 1, j, 0); ax += GJ(i - 1, j, 1); ax += 0.5 * GJ(i - 1, j, 4); ay += 0.5 * GJ(i - 1, j, 5); }
     const double *x = xy + 2 * B.node_off, *y = x + nn;
     for (int dj = -1; dj <= 0; ++dj)
         for (int di = -1; di <= 0; ++di) {
@@ -756,6 +800,36 @@ __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int
     double *xb = xyb + 2 * B.node_off;
     xb[k] += ax;
     xb[nn + k] += ay;
+}
+
+// Moving no-slip wall images u_g = 2 u_wall - u, u_wall the grid velocity at
+// the body-frame midpoint of a wall face: the midpoint's adjoint from the
+// ghost's velocity adjoint (WB), half to each node of the face.  One thread
+// per ghost of the j-side ghost rows and snapshot; atomic adds (a wall face
+// serves both ghost layers, and corner ghosts of neighbouring columns).
+__global__ void __launch_bounds__(kBS) k_adj_wall_motion(const BlockDesc *blks, int b, const double *WB,
+                                                         Motion mo, double *xyb) {
+    const BlockDesc &B = blks[b];
+    const int we = B.ni + 4;
+    const int64_t eplane = (int64_t)we * (B.nj + 4);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)4 * we * B.ns) return;
+    const int n = (int)(t / (4 * we)), r = (int)((t / we) % 4), ie = (int)(t % we);
+    const int j = r < 2 ? r - 2 : B.nj + r - 2, i = ie - 2;
+    int s;
+    int64_t k;
+    if (!wall_image_face(blks, b, i, j, &s, &k)) return;
+    const double *wb = WB + B.ext_off + (int64_t)n * 4 * eplane + (int64_t)(j + 2) * we + ie;
+    const MotionSnap m = motion_snap(mo, B, n);
+    double xb, yb;
+    grid_velocity_rev(m, 2.0 * wb[eplane], 2.0 * wb[2 * eplane], xb, yb);
+    const BlockDesc &S = blks[s];
+    const int64_t nn = (int64_t)(S.ni + 1) * (S.nj + 1);
+    double *xs = xyb + 2 * S.node_off, *ys = xs + nn;
+    atomicAdd(xs + k, 0.5 * xb);
+    atomicAdd(xs + k + 1, 0.5 * xb);
+    atomicAdd(ys + k, 0.5 * yb);
+    atomicAdd(ys + k + 1, 0.5 * yb);
 }
 
 // ---- force coefficients ------------------------------------------------------
@@ -808,7 +882,7 @@ __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, i
     const int64_t nn = (int64_t)(B.ni + 1) * (B.nj + 1);
     const double *x = xy + 2 * B.node_off, *y = x + nn;
     double mx = 0.5 * (x[i] + x[i + 1]) - fa.xm, my = 0.5 * (y[i] + y[i + 1]) - fa.ym;
-    if (mo.tab) rot2(ms, mx, my);   // coordinate adjoints are refused on a moving grid
+    if (mo.tab) rot2(ms, mx, my);
     // coefficient adjoints -> (Fx, Fy, Mz) adjoints of this body and snapshot
     const double *cb = fa.cfbar + fa.body_off[B.body] + 3 * n;
     const double Fxb = (-cb[0] * fa.sa + cb[1] * fa.ca) / fa.qinf_l;
@@ -817,7 +891,8 @@ __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, i
     // Mz = mx fy - my fx
     const double fxb = Fxb - my * Mzb, fyb = Fyb + mx * Mzb;
     if (xyb) {
-        const double mxb = 0.5 * Mzb * fy, myb = -0.5 * Mzb * fx;
+        double mxb = 0.5 * Mzb * fy, myb = -0.5 * Mzb * fx;
+        if (mo.tab) rot2_rev(ms, mxb, myb);   // the arm rotates with the body
         double *xb = xyb + 2 * B.node_off, *yb = xb + nn;
         xadd(xb, i, mxb);
         xadd(xb, i + 1, mxb);
@@ -829,6 +904,10 @@ __global__ void __launch_bounds__(kBS) k_adj_force_face(const BlockDesc *blks, i
     double sxb = -dp * fxb, syb = -dp * fyb, dxb = 0.0, dyb = 0.0;
     viscous_flux_rev(uL, uR, nB, nA, sx, sy, dx, dy, c.mu, c.kappa, fvb, uLb, uRb, Pb, Qb, sxb, syb,
                      dxb, dyb);
+    if (mo.tab) {   // S and d adjoints back to the body frame
+        rot2_rev(ms, sxb, syb);
+        rot2_rev(ms, dxb, dyb);
+    }
     W4<double> w1{0, 0, 0, 0}, w2{0, 0, 0, -(fxb * sx + fyb * sy)};
     uvt_rev(wL, uLb, g, w1);
     uvt_rev(wR, uRb, g, w2);
@@ -1030,7 +1109,8 @@ int adjoint_setup(hb_grid *g) {
     }
     g->n_cpart = nc;
     rc = rc ? rc : alloc(&g->cpart_d, nc);
-    rc = rc ? rc : alloc(&g->geo_d, 4 * (g->n_fi + g->n_fj));
+    rc = rc ? rc : alloc(&g->geo_d, 6 * (g->n_fi + g->n_fj));
+    rc = rc ? rc : alloc(&g->mb_d, (g->n_afi + g->n_afj) / kAF * 2);
     rc = rc ? rc : alloc(&g->vb_d, (int64_t)kMaxNs * g->n_cells);
     rc = rc ? rc : alloc(&g->cf_adj_d, g->n_forces);
     if (!rc && !g->ext_d) rc = alloc(&g->ext_adj_d, g->n_ext);
@@ -1046,6 +1126,14 @@ bool fold_per_snap(const BlockDesc &B) { return (int64_t)B.ni * B.nj < 256 * (in
 // at 1024x512 N_H = 4, which keeps the launch order
 int adj_xcd(int64_t n) { return n < ((int64_t)1 << 22); }
 unsigned adj_grid(int64_t n) { return adj_xcd(n) ? xcd_grid(n) : nblk(n); }
+
+void launch_wall_motion(hb_grid *g, double *xybar, hipStream_t s) {
+    for (int b = 0; b < g->nblocks; ++b) {
+        const BlockDesc &B = g->blk[b];
+        hipLaunchKernelGGL(k_adj_wall_motion, dim3(nblk((int64_t)4 * (B.ni + 4) * B.ns)), dim3(kBS), 0, s,
+                           g->blk_d, b, g->WBext_d, g->motion, xybar);
+    }
+}
 
 void launch_alpha(hb_grid *g, hipStream_t s) {
     for (int b = 0; b < g->nblocks; ++b) {
@@ -1069,7 +1157,10 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         if (rc) return rc;
     }
     // the node kernels clear xybar; the cell kernels leave the alpha0
-    // partials, which the first fold launch sums
+    // partials, which the first fold launch sums; on a moving grid the face
+    // kernels store the midpoint adjoints for xybar
+    double *mbi = (g->motion.tab && xybar) ? g->mb_d : nullptr;
+    double *mbj = mbi ? g->mb_d + g->n_afi / kAF * 2 : nullptr;
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
@@ -1077,7 +1168,7 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const int64_t nw = 256 * (((nI > nJ ? nI : nJ) + 127) / 128);
         hipLaunchKernelGGL(nt ? k_adj_faces<true> : k_adj_faces<false>, dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
-                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d);
+                           rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d, mbi, mbj);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
         hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
@@ -1104,11 +1195,12 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
                                g->n_cells);
     }
     if (xybar) {
+        if (g->motion.tab) launch_wall_motion(g, xybar, s);
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
             const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
-                               g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
+                               g->AFJ_d, mbi, mbj, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
             hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
                                g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d,
                                fold_per_snap(B) ? B.ns : 1, g->n_cells, g->xy_d, xybar);
@@ -1220,11 +1312,13 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, g->adj_part_d, g->n_apart + 1, flowbar);
     }
     if (xybar) {
+        if (g->motion.tab) launch_wall_motion(g, xybar, s);
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
             const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
-                               g->AFJ_d, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
+                               g->AFJ_d, (const double *)nullptr, (const double *)nullptr, g->xy_d,
+                               g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
             hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
                                g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, 0,
                                (int64_t)0, g->xy_d, xybar);

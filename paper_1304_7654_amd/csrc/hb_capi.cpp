@@ -90,6 +90,7 @@ void free_all(hb_grid *g) {
     dfree(g->cpart_d);
     dfree(g->geo_d);
     dfree(g->vb_d);
+    dfree(g->mb_d);
     dfree(g->adj_d);
     dfree(g->AFI_d); dfree(g->AFJ_d); dfree(g->NB_d); dfree(g->WBext_d); dfree(g->adj_part_d);
     dfree(g->fold_ptr_d); dfree(g->fold_b_d); dfree(g->fold_p_d); dfree(g->fold_m_d);
@@ -571,8 +572,6 @@ int hb_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double 
     if (qbar == q || qbar == rbar) return fail(HB_ERR_ARG, "qbar must not alias q or rbar");
     if (g->solver.precision != HB_FP64)
         return fail(HB_ERR_UNSUPPORTED, "the adjoint is FP64 only");
-    if (g->motion.tab && xybar)
-        return fail(HB_ERR_UNSUPPORTED, "no coordinate adjoint on a moving grid (pass xybar = NULL)");
     return launch_residual_adjoint(g, q, rbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 
@@ -581,8 +580,6 @@ int hb_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *
     g_err.clear();
     if (!g || !q || !cfbar || !qbar) return fail(HB_ERR_ARG, "NULL argument");
     if (qbar == q) return fail(HB_ERR_ARG, "qbar must not alias q");
-    if (g->motion.tab && xybar)
-        return fail(HB_ERR_UNSUPPORTED, "no coordinate adjoint on a moving grid (pass xybar = NULL)");
     return launch_forces_adjoint(g, q, cfbar, qbar, xybar, flowbar, (hipStream_t)stream);
 }
 

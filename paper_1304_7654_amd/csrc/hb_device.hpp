@@ -563,13 +563,12 @@ __device__ __forceinline__ void muscl_rev1(double m2, double m1, double p0, doub
 
 // Roe flux reverse (full primitive states, FP64).  Fb: adjoint of the 4 flux
 // components; adds to Lb, Rb (primitive adjoints) and sxb, syb.  vg: the face
-// speed x_t . S of a moving face (roe_flux), held fixed (its dependence on
-// the nodes is not taken: coordinate adjoints are not formed on a moving
-// grid).
+// speed x_t . S of a moving face (roe_flux); with vgb non-NULL its adjoint is
+// added to *vgb.
 __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, double sx,
                                     double sy, double g, double delta_frac, const double Fb[4],
                                     W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb,
-                                    double vg = 0.0) {
+                                    double vg = 0.0, double *vgb = nullptr) {
     // ---- forward recomputation
     const double area = sqrt(sx * sx + sy * sy);
     const double ia = adj_rcp(area);
@@ -624,6 +623,9 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double d0b = -f0b, d1b = -f1b, d2b = -f2b, d3b = -f3b;
     double nxb = 0.0, nyb = 0.0;
     double hlb = 0.0, hrb = 0.0;
+    if (vgb)   // -vg (U_L + U_R) / 2
+        *vgb -= 0.5 * (Fb[0] * (L.r + R.r) + Fb[1] * (L.r * L.u + R.r * R.u) +
+                       Fb[2] * (L.r * L.v + R.r * R.v) + Fb[3] * (L.r * hl - L.p + R.r * hr - R.p));
     if (vg != 0.0) {
         // -vg (U_L + U_R) / 2 with U = (rho, rho u, rho v, rho H - p)
         const double u0 = -0.5 * vg * Fb[0], u1 = -0.5 * vg * Fb[1];
@@ -702,6 +704,7 @@ __device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, do
     const double qrelb = lam1b + lam4b + l2b * sgn(qrel);
     qntb += qrelb;
     areab += qrelb * vg * ia * ia;          // qrel = qnt - vg / |S|
+    if (vgb) *vgb -= qrelb * ia;
     ctb += -lam1b + lam4b + delta_frac * ddb;
     // wave strengths
     double dpb = 0.5 * ic2 * (a1b + a4b) - ic2 * a2b;

@@ -211,6 +211,9 @@ struct hb_grid {
     // adjoints (i-faces [4][n_fi], then j-faces [4][n_fj]) and the per-cell
     // adjoint of the cell area from the HB source
     double *geo_d = nullptr, *vb_d = nullptr;
+    // moving grid: per face and snapshot the adjoint of the face's
+    // body-frame midpoint (the face speed's dependence on the nodes)
+    double *mb_d = nullptr;
     // adjoint pseudo-time iteration scratch (allocated on first use)
     double *it_lam0_d = nullptr, *it_qbar_d = nullptr, *it_dtv_d = nullptr, *it_part_d = nullptr;
     int64_t n_it_part = 0;

@@ -32,41 +32,71 @@ __device__ __forceinline__ void grid_velocity(const MotionSnap &m, const Motion 
 }
 
 // A ghost (i, j) of block B = blks[b] that is a no-slip wall image (j side
-// wall, or the wall part of a wake cut) gets 2 u_wall added to the mirrored
-// velocity, u_wall = grid velocity at the midpoint of the wall face of the
-// mirrored cell's column: corner ghosts take the i-periodic partner column,
-// the glued block's column across an i cut (its wall face on the same j
-// side), else the nearest column.  xy: body-frame nodes of all blocks.
-__device__ __forceinline__ void wall_image_motion(const BlockDesc *blks, int b, int i, int j,
-                                                  const MotionSnap &m, const Motion &mo,
-                                                  const double *xy, W4<double> &w) {
+// wall, or the wall part of a wake cut) takes the grid velocity at the
+// midpoint of the wall face of the mirrored cell's column: corner ghosts
+// take the i-periodic partner column, the glued block's column across an i
+// cut (its wall face on the same j side), else the nearest column.  Returns
+// false for a ghost that is no wall image; else *src = the block holding
+// the wall face and *k = the index of its first node (the second is k + 1).
+__device__ __forceinline__ bool wall_image_face(const BlockDesc *blks, int b, int i, int j, int *src,
+                                                int64_t *k) {
     const BlockDesc &B = blks[b];
     int side;
     if (j < 0) side = 2;
     else if (j >= B.nj) side = 3;
-    else return;
+    else return false;
     const int kind = B.bc[side];
-    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return;
-    if (kind == HB_BC_WAKECUT && (i < B.wake || i >= B.ni - B.wake)) return;
-    int col = i, src = b;
+    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return false;
+    if (kind == HB_BC_WAKECUT && (i < B.wake || i >= B.ni - B.wake)) return false;
+    int col = i, s = b;
     if (i < 0) {
         if (B.bc[0] == HB_BC_PERIODIC) col = i + B.ni;
-        else if (B.bc[0] == HB_BC_CUT) src = B.cut_blk[0], col = src < 0 ? 0 : blks[src].ni + i;
+        else if (B.bc[0] == HB_BC_CUT) s = B.cut_blk[0], col = s < 0 ? 0 : blks[s].ni + i;
         else col = 0;
     } else if (i >= B.ni) {
         if (B.bc[1] == HB_BC_PERIODIC) col = i - B.ni;
-        else if (B.bc[1] == HB_BC_CUT) src = B.cut_blk[1], col = i - B.ni;
+        else if (B.bc[1] == HB_BC_CUT) s = B.cut_blk[1], col = i - B.ni;
         else col = B.ni - 1;
     }
-    if (src < 0) return;          // general cuts: no moving grid (refused by hb_set_motion)
-    const BlockDesc &S = blks[src];
+    if (s < 0) return false;      // general cuts: no moving grid (refused by hb_set_motion)
+    const BlockDesc &S = blks[s];
+    *src = s;
+    *k = (int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col;
+    return true;
+}
+
+// The moving-wall image u_g = 2 u_wall - u: adds 2 u_wall to the mirrored
+// velocity of ghost (i, j).  xy: body-frame nodes of all blocks.
+__device__ __forceinline__ void wall_image_motion(const BlockDesc *blks, int b, int i, int j,
+                                                  const MotionSnap &m, const Motion &mo,
+                                                  const double *xy, W4<double> &w) {
+    int s;
+    int64_t k;
+    if (!wall_image_face(blks, b, i, j, &s, &k)) return;
+    const BlockDesc &S = blks[s];
     const int64_t nn = (int64_t)(S.ni + 1) * (S.nj + 1);
     const double *x = xy + 2 * S.node_off, *y = x + nn;
-    const int64_t k = (int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col;
     double gx, gy;
     grid_velocity(m, mo, 0.5 * (x[k] + x[k + 1]), 0.5 * (y[k] + y[k + 1]), gx, gy);
     w.u += 2.0 * gx;
     w.v += 2.0 * gy;
+}
+
+// Adjoint of the rigid grid velocity at a body-frame point with respect to
+// that point: (gx, gy) = theta_dot (-r_y, r_x) + (0, h_dot), r = R (x0 - p),
+// so x0bar = theta_dot R^T (gybar, -gxbar).
+__device__ __forceinline__ void grid_velocity_rev(const MotionSnap &m, double gxb, double gyb,
+                                                  double &xb, double &yb) {
+    const double rx = m.thd * gyb, ry = -m.thd * gxb;
+    xb = m.c * rx + m.s * ry;
+    yb = -m.s * rx + m.c * ry;
+}
+
+// R^T v: a rotated vector's adjoint taken back to the body frame.
+__device__ __forceinline__ void rot2_rev(const MotionSnap &m, double &x, double &y) {
+    const double a = m.c * x + m.s * y;
+    y = -m.s * x + m.c * y;
+    x = a;
 }
 
 }  // namespace hb

@@ -185,12 +185,8 @@ def test_moving_grid_refusals():
     assert e.value.code == hb.HB_ERR_ARG
     g.set_motion(**MOT)
     qd = q.to(DEV)
-    xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)    # coordinate adjoints
-    with pytest.raises(hb.HBError) as e:
-        g.residual_adjoint(qd, torch.ones_like(qd), None, xyb)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
-    with pytest.raises(hb.HBError) as e:
-        g.forces_adjoint(qd, torch.ones(g.n_forces, dtype=torch.float64, device=DEV), None, xyb)
+    with pytest.raises(hb.HBError) as e:                         # the grid moves
+        g.set_xy(torch.as_tensor(p.blocks[0].xy.reshape(-1)).to(DEV))
     assert e.value.code == hb.HB_ERR_UNSUPPORTED
 
 

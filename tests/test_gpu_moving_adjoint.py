@@ -1,11 +1,12 @@
 """Adjoint kernels on a rigidly heaving and pitching grid (hb_set_motion):
 the transposed-Jacobian products of the moving-grid R* and force
-coefficients with respect to the state and the mean incidence against the
-FP64 moving-grid oracle's reverse mode (element by element), the adjoint
-pseudo-time iteration stage by stage against the oracle's products and
-moving-grid local steps, a dot-product check against central differences
-of the GPU's own moving-grid residual, and the refusal of coordinate
-adjoints on a moving grid."""
+coefficients with respect to the state, the body-frame node coordinates
+(through the rotated face vectors, the face speeds, the moving-wall images
+and the moment arm) and the mean incidence against the FP64 moving-grid
+oracle's reverse mode (element by element), the adjoint pseudo-time
+iteration stage by stage against the oracle's products and moving-grid
+local steps, and dot-product checks against central differences of the
+GPU's own moving-grid residual in the state and in the nodes."""
 import sys
 
 import pytest
@@ -57,19 +58,25 @@ def test_moving_residual_adjoint_matches_oracle(name, pi, pj, batched):
     p, blocks, flow, solver, q = _case(name, pi, pj)
     m = M.OMotion(**MOT)
     rbar = torch.randn(q.shape, generator=torch.Generator().manual_seed(3), dtype=torch.float64)
-    qref, aref = M.moving_residual_vjp(blocks, q, flow, solver, m, rbar, p.cuts)
+    qref, xref, aref = M.moving_residual_vjp(blocks, q, flow, solver, m, rbar, p.cuts)
     qfix = O.residual_vjp(blocks, q, flow, solver, rbar, p.cuts)[0]
     assert _rel(qfix, qref) > 1e-3                     # the motion matters
     g = _grid(p, batched)
     qb = torch.empty_like(q, device=DEV)
+    xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
     ab = torch.empty(1, dtype=torch.float64, device=DEV)
-    g.residual_adjoint(q.to(DEV), rbar.to(DEV), qb, None, ab)
+    g.residual_adjoint(q.to(DEV), rbar.to(DEV), qb, xyb, ab)
     torch.cuda.synchronize()
     qb = qb.cpu()
-    _say("  qbar rel", _rel(qb, qref), "alpha", float(ab), float(aref))
+    xr = torch.cat([x.reshape(-1) for x in xref])
+    _say("  qbar rel", _rel(qb, qref), "xybar rel", _rel(xyb.cpu(), xr), "alpha", float(ab), float(aref))
     assert _rel(qb, qref) <= 1e-11
     assert float((qb - qref).abs().max()) <= 1e-10 * float(qref.abs().max())
+    assert _rel(xyb.cpu(), xr) <= 1e-11
     assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
+    qb2 = g.residual_adjoint(q.to(DEV), rbar.to(DEV))          # without coordinates: the same qbar
+    torch.cuda.synchronize()
+    assert torch.equal(qb2.cpu(), qb)
     g.close()
 
 
@@ -80,14 +87,17 @@ def test_moving_forces_adjoint_matches_oracle(name, pi, pj, batched):
     m = M.OMotion(**MOT)
     g = _grid(p, batched)
     cfbar = torch.randn(g.n_forces, generator=torch.Generator().manual_seed(5), dtype=torch.float64)
-    qref, aref = M.moving_forces_vjp(blocks, q, flow, solver, m, cfbar, p.cuts)
+    qref, xref, aref = M.moving_forces_vjp(blocks, q, flow, solver, m, cfbar, p.cuts)
     qb = torch.empty_like(q, device=DEV)
+    xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
     ab = torch.empty(1, dtype=torch.float64, device=DEV)
-    g.forces_adjoint(q.to(DEV), cfbar.to(DEV), qb, None, ab)
+    g.forces_adjoint(q.to(DEV), cfbar.to(DEV), qb, xyb, ab)
     torch.cuda.synchronize()
     qb = qb.cpu()
-    _say("  qbar rel", _rel(qb, qref), "alpha", float(ab), float(aref))
+    xr = torch.cat([x.reshape(-1) for x in xref])
+    _say("  qbar rel", _rel(qb, qref), "xybar rel", _rel(xyb.cpu(), xr), "alpha", float(ab), float(aref))
     assert _rel(qb, qref) <= 1e-11
+    assert _rel(xyb.cpu(), xr) <= 1e-11
     assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
     g.close()
 
@@ -144,18 +154,29 @@ def test_moving_adjoint_dot_product_with_gpu_differences():
     g.close()
 
 
-def test_coordinate_adjoints_refused_on_a_moving_grid():
-    p, blocks, flow, solver, q = _case("cyl_tiny", 1, 1)
+def test_moving_coordinate_adjoint_dot_product_with_gpu_differences():
+    """<rbar, (R(x+hv) - R(x-hv)) / 2h> = <xybar, v> for the body-frame node
+    coordinates on the moving grid (hb_set_xy moves the body-frame grid,
+    the motion cleared and set again around it), using only the GPU."""
+    p, blocks, flow, solver, q = _case("naca_tiny", 1, 1)
+    q = q.to(DEV)
+    gen = torch.Generator().manual_seed(12)
+    rbar = torch.randn(q.shape, generator=gen, dtype=torch.float64).to(DEV)
     g = _grid(p, 1)
-    qd = q.to(DEV)
+    xy0 = torch.as_tensor(p.blocks[0].xy.reshape(-1)).to(DEV)
+    v = torch.randn(xy0.shape, generator=gen, dtype=torch.float64).to(DEV) * 1e-3
     xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
-    with pytest.raises(hb.HBError) as e:
-        g.residual_adjoint(qd, torch.ones_like(qd), torch.empty_like(qd), xyb)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
-    with pytest.raises(hb.HBError) as e:
-        g.forces_adjoint(qd, torch.ones(g.n_forces, dtype=torch.float64, device=DEV),
-                         torch.empty_like(qd), xyb)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
-    g.set_motion()                                   # cleared: the fixed-grid adjoint again
-    g.residual_adjoint(qd, torch.ones_like(qd), torch.empty_like(qd), xyb)
+    g.residual_adjoint(q, rbar, None, xyb)
+    h = 1e-6
+
+    def r_at(xy):
+        g.set_motion()
+        g.set_xy(xy)
+        g.set_motion(**MOT)
+        return g.residual(q)
+
+    fd = float((rbar * (r_at(xy0 + h * v) - r_at(xy0 - h * v))).sum()) / (2 * h)
+    ad = float((xyb * v).sum())
+    _say("  fd", fd, "adjoint", ad)
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
     g.close()

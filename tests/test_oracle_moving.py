@@ -291,7 +291,9 @@ def test_moving_split_equals_uncut(name, pi, pj):
 def test_moving_vjps_match_central_differences():
     """The reverse products of the moving-grid residual and loads (used to
     check the adjoint kernels) against central differences of the forward
-    oracle along a random direction of the state and in alpha0."""
+    oracle along a random direction of the state, of the body-frame nodes
+    (the face speeds, the moving-wall images and the moment arm depend on
+    them) and in alpha0."""
     b = _cyl(16, 6, 1)
     flow, solver = _flow(), O.OSolver()
     flow.alpha0 = 0.03
@@ -302,24 +304,32 @@ def test_moving_vjps_match_central_differences():
     v = torch.randn(q.shape, generator=g, dtype=DT) * q.abs()
     h = 1e-6
 
-    def r_at(x, a=None):
-        return M.moving_residual_all([b], x, flow, solver, m, (), None if a is None else torch.tensor(a, dtype=DT))
+    dx = torch.randn(b.xy.shape, generator=g, dtype=DT) * 1e-2
 
-    qb, ab = M.moving_residual_vjp([b], q, flow, solver, m, rbar)
+    def r_at(x, a=None, xy=None):
+        return M.moving_residual_all([b], x, flow, solver, m, (), None if a is None else torch.tensor(a, dtype=DT),
+                                     None if xy is None else [xy])
+
+    qb, xb, ab = M.moving_residual_vjp([b], q, flow, solver, m, rbar)
     fd = float((rbar * (r_at(q + h * v) - r_at(q - h * v))).sum()) / (2 * h)
     assert abs(fd - float((qb * v).sum())) <= 1e-7 * abs(fd)
+    fx = float((rbar * (r_at(q, xy=b.xy + h * dx) - r_at(q, xy=b.xy - h * dx))).sum()) / (2 * h)
+    assert abs(fx - float((xb[0] * dx).sum())) <= 1e-6 * abs(fx)
     fa = float((rbar * (r_at(q, flow.alpha0 + h) - r_at(q, flow.alpha0 - h))).sum()) / (2 * h)
     assert abs(fa - float(ab)) <= 1e-7 * abs(fa)
 
     ns = b.ns
     cfbar = torch.randn(3 * ns, generator=g, dtype=DT)
 
-    def cf_at(x, a=None):
+    def cf_at(x, a=None, xy=None):
         a = None if a is None else torch.tensor(a, dtype=DT)
-        return torch.cat([c.reshape(-1) for c in M.moving_forces([b], x, flow, solver, m, (), a)])
+        return torch.cat([c.reshape(-1) for c in M.moving_forces([b], x, flow, solver, m, (), a,
+                                                                 None if xy is None else [xy])])
 
-    qb, ab = M.moving_forces_vjp([b], q, flow, solver, m, cfbar)
+    qb, xb, ab = M.moving_forces_vjp([b], q, flow, solver, m, cfbar)
     fd = float((cfbar * (cf_at(q + h * v) - cf_at(q - h * v))).sum()) / (2 * h)
     assert abs(fd - float((qb * v).sum())) <= 1e-7 * abs(fd)
+    fx = float((cfbar * (cf_at(q, xy=b.xy + h * dx) - cf_at(q, xy=b.xy - h * dx))).sum()) / (2 * h)
+    assert abs(fx - float((xb[0] * dx).sum())) <= 1e-6 * abs(fx)
     fa = float((cfbar * (cf_at(q, flow.alpha0 + h) - cf_at(q, flow.alpha0 - h))).sum()) / (2 * h)
     assert abs(fa - float(ab)) <= 1e-7 * abs(fa)
