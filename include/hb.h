@@ -394,7 +394,8 @@ int hb_set_tuning(hb_grid *g, const hb_tuning *t);
 int hb_get_tuning(const hb_grid *g, hb_tuning *t);
 
 /* Replace the node coordinates (device, hb_xy_size() doubles, same layout as
- * the blocks' xy, concatenated) and recompute the metrics on `stream`. */
+ * the blocks' xy, concatenated) and recompute the metrics on `stream`.  On
+ * a moving grid (hb_set_motion) these are the body-frame nodes. */
 int hb_set_xy(hb_grid *g, const double *xy, void *stream);
 
 /* Replace the mean incidence alpha0 (radians); takes effect for work
@@ -407,8 +408,8 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
  * per-block and on the batched path (FP64 and FP32 bulk), and to the
  * adjoints (FP64).
  * HB_ERR_UNSUPPORTED for blocks with walls on an i side or cuts other than
- * whole opposite sides glued aligned; while a motion is
- * set hb_set_xy returns HB_ERR_UNSUPPORTED; the adjoints take the motion.  Across a cut,
+ * whole opposite sides glued aligned; hb_set_xy then sets the body-frame
+ * nodes, and the adjoints take the motion.  Across a cut,
  * the wall image of a corner ghost takes the glued block's wall face.
  * HB_ERR_ARG for non-finite values.  Drops the batched path's captured
  * iterations (the next hb_rk_iterate captures them again).  Synchronises

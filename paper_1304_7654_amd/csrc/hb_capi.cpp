@@ -672,7 +672,6 @@ int hb_get_tuning(const hb_grid *g, hb_tuning *t) {
 int hb_set_xy(hb_grid *g, const double *xy, void *stream) {
     g_err.clear();
     if (!g || !xy) return fail(HB_ERR_ARG, "NULL argument");
-    if (g->motion.tab) return fail(HB_ERR_UNSUPPORTED, "hb_set_xy on a moving grid");
     hipStream_t s = (hipStream_t)stream;
     int rc = check_hip(hipMemcpyAsync(g->xy_d, xy, sizeof(double) * 2 * g->n_nodes,
                                       hipMemcpyDeviceToDevice, s), "xy copy");

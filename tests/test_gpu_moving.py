@@ -185,9 +185,26 @@ def test_moving_grid_refusals():
     assert e.value.code == hb.HB_ERR_ARG
     g.set_motion(**MOT)
     qd = q.to(DEV)
-    with pytest.raises(hb.HBError) as e:                         # the grid moves
-        g.set_xy(torch.as_tensor(p.blocks[0].xy.reshape(-1)).to(DEV))
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
+    # hb_set_xy on a moving grid moves the body-frame nodes: the same as
+    # setting them with the motion cleared and setting the motion again
+    xy = torch.as_tensor(p.blocks[0].xy.reshape(-1)).to(DEV)
+    xy2 = xy * (1.0 + 1e-3 * torch.sin(torch.arange(xy.numel(), device=DEV, dtype=torch.float64)))
+    b0 = blocks[0]
+    ref = M.moving_residual_all(blocks, q, flow, solver, M.OMotion(**MOT), (), None,
+                                [xy2.cpu().reshape(b0.xy.shape)])
+    for batched in (0, 1):
+        gb = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=batched)
+        gb.set_motion(**MOT)
+        gb.set_xy(xy2)
+        r1 = gb.residual(qd)
+        gb.set_motion()
+        gb.set_xy(xy2)
+        gb.set_motion(**MOT)
+        r2 = gb.residual(qd)
+        torch.cuda.synchronize()
+        assert torch.equal(r1, r2)
+        assert _rel(blocks, r1.cpu(), ref) <= 1e-12
+        gb.close()
 
 
 def _td_problem(kind, n_harm, ni, nj):

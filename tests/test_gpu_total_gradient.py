@@ -5,14 +5,18 @@ by hb_adjoint_iterate + hb_residual_adjoint, forces by hb_forces and
 hb_forces_adjoint).  Checked against (i) the FP64 oracle: the converged
 adjoint solves J_Q^T lambda = -dCL/dQ with the oracle's own reverse-mode
 products, and (ii) central differences of the re-converged GPU solution.
-Two cases: the small design airfoil (64x16, 8 bumps, N_H = 1) and the
-adjoint configuration at its own size (256x128, 64 bumps, N_H = 2; bumps
-0, 15, 31, 47, 63 and the incidence by differences)."""
+Three cases: the small design airfoil (64x16, 8 bumps, N_H = 1), the same
+airfoil pitching on a moving grid (the moving-grid residual, loads and
+their adjoints, the oracle check with the moving-grid reverse products),
+and the adjoint configuration at its own size (256x128, 64 bumps, N_H = 2;
+bumps 0, 15, 31, 47, 63 and the incidence by differences)."""
+import math
 import os
 
 import pytest
 import torch
 
+from oracle import hb_moving as M
 from oracle import hb_oracle as O
 from paper_1304_7654_amd import autograd as A
 from paper_1304_7654_amd import hb, synth
@@ -28,20 +32,29 @@ def _say(*a):
 # (workload, primal / adjoint iterations, bumps checked by differences): the
 # iteration counts take the residual to its FP64 floor (drop ~3e-14 at
 # 256x128 after 70,000 iterations)
-CASES = [("naca_tiny_hh8", 12000, (0, 3, 6)), ("naca256x128_hh64", 80000, (0, 15, 31, 47, 63))]
+# The pitching case: the small design airfoil pitching 1 degree about its
+# quarter chord on a moving grid (hb_set_motion) instead of a free stream of
+# oscillating incidence.
+PITCH = dict(pitch_amp=math.radians(1.0), x_pivot=0.25)
+CASES = [("naca_tiny_hh8", 12000, (0, 3, 6), None), ("naca_tiny_hh8", 12000, (0, 3, 6), PITCH),
+         ("naca256x128_hh64", 80000, (0, 15, 31, 47, 63), None)]
 
 
-@pytest.mark.parametrize("name,N_ITER,bumps", CASES)
-def test_total_gradient_of_mean_lift(name, N_ITER, bumps):
-    _say("case", name, N_ITER, "iterations, bumps", bumps)
+@pytest.mark.parametrize("name,N_ITER,bumps,motion", CASES, ids=["small", "small-pitching", "adjoint-config"])
+def test_total_gradient_of_mean_lift(name, N_ITER, bumps, motion):
+    _say("case", name, N_ITER, "iterations, bumps", bumps, "motion", motion)
     torch.set_num_threads(min(16, os.cpu_count() or 1))
     p = synth.make_problem(name)
     p.solver.graph_iters = 50
+    if motion:
+        p.flow.alpha_amp = 0.0
     nb = len(p.design["beta"])
     beta0 = torch.as_tensor(p.design["beta"]).to(DEV)
     D = torch.as_tensor(p.design["dxy"].reshape(nb, -1)).to(DEV)
     xy_base = torch.as_tensor(p.blocks[0].xy.reshape(-1)).to(DEV) - beta0 @ D   # undeformed
     g = hb.Grid(p.blocks, p.flow, p.solver, precision=0, batched=1)
+    if motion:
+        g.set_motion(**motion)
     q_init = torch.as_tensor(synth.initial_state(p)).to(DEV)
 
     def mean_cl(beta, a0, q_start, n):
@@ -64,8 +77,13 @@ def test_total_gradient_of_mean_lift(name, N_ITER, bumps):
     lam = g.last_lambda.cpu()
     cfbar = torch.zeros(g.n_forces, dtype=torch.float64)
     cfbar[0::3] = 1.0 / (g.n_forces // 3)
-    gq = O.forces_vjp(blocks, qs.detach().cpu(), flow, solver, cfbar)[0]
-    jt = O.residual_vjp(blocks, qs.detach().cpu(), flow, solver, lam)[0]
+    if motion:
+        m = M.OMotion(**motion)
+        gq = M.moving_forces_vjp(blocks, qs.detach().cpu(), flow, solver, m, cfbar)[0]
+        jt = M.moving_residual_vjp(blocks, qs.detach().cpu(), flow, solver, m, lam)[0]
+    else:
+        gq = O.forces_vjp(blocks, qs.detach().cpu(), flow, solver, cfbar)[0]
+        jt = O.residual_vjp(blocks, qs.detach().cpu(), flow, solver, lam)[0]
     res = float((jt + gq).norm() / gq.norm())
     _say("  |J^T lam + gq| / |gq| =", res)
     assert res <= 1e-9
