@@ -105,8 +105,7 @@ typedef struct {
  * wake sections and profile sections share a side); glued blocks have
  * equal n_harm.  HB_ERR_ARG
  * otherwise, for a segment outside its sides, len < 1, reversed not 0 or 1,
- * or cuts around which a corner ghost does not resolve.  A moving grid
- * (hb_set_motion) needs its cuts to join whole opposite sides, aligned. */
+ * or cuts around which a corner ghost does not resolve. */
 typedef struct {
     int32_t blk_a, side_a, start_a;
     int32_t blk_b, side_b, start_b;
@@ -407,10 +406,11 @@ int hb_set_alpha0(hb_grid *g, double alpha0);
  * applies to hb_residual, hb_rk_iterate, hb_forces and hb_td_march, on the
  * per-block and on the batched path (FP64 and FP32 bulk), and to the
  * adjoints (FP64).
- * HB_ERR_UNSUPPORTED for blocks with walls on an i side or cuts other than
- * whole opposite sides glued aligned; hb_set_xy then sets the body-frame
- * nodes, and the adjoints take the motion.  Across a cut,
- * the wall image of a corner ghost takes the glued block's wall face.
+ * HB_ERR_UNSUPPORTED for blocks with walls on an i side (also the wall rest
+ * of a partly glued i side); any cuts.  hb_set_xy then sets the body-frame
+ * nodes, and the adjoints take the motion.  A moving-wall image takes the
+ * velocity of the wall face at which its ghost's resolution mirrors (for a
+ * corner ghost across a cut, the glued block's wall face).
  * HB_ERR_ARG for non-finite values.  Drops the batched path's captured
  * iterations (the next hb_rk_iterate captures them again).  Synchronises
  * the current device. */

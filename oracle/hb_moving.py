@@ -110,44 +110,35 @@ def face_speeds(xy: torch.Tensor, m: OMotion, thd: float, h: float, hd: float):
 
 
 def check_block(b: O.OBlock):
-    if b.bc[0] == O.WALL or b.bc[1] == O.WALL:
+    if any(b.bc[s] in (O.WALL, O.CUT_WALL) for s in (0, 1)):
         raise ValueError("moving grids: walls only on j sides")
-    if O.CUT_WALL in b.bc or O.CUT_FARFIELD in b.bc:
-        raise ValueError("moving grids: no partly glued sides")
 
 
-def wall_images(b: O.OBlock, we: torch.Tensor, xy: torch.Tensor, m: OMotion, thd: float,
-                h: float, hd: float, nbr_xy=None):
-    """Add 2 u_w to the velocity of the no-slip wall images of the extended
-    field we (in place; the fixed-grid rule gave -u).  u_w = grid velocity at
-    the midpoint of the wall face of the mirrored cell's column: a ghost
-    column takes its i-periodic partner column, the glued block's column
-    across an i cut (nbr_xy: side -> that block's moved nodes), else the
-    nearest column of this block."""
-    ni, nj = b.ni, b.nj
-    for side in (2, 3):
-        kind = b.bc[side]
-        if kind not in (O.WALL, O.WAKECUT):
-            continue
-        for ie in range(ni + 4):
-            i = ie - 2
-            if kind == O.WAKECUT and (i < b.wake_ncells or i >= ni - b.wake_ncells):
-                continue                       # wake ghosts are real cells
-            src, col = xy, min(max(i, 0), ni - 1)
-            if 0 <= i < ni:
-                col = i
-            elif b.bc[0 if i < 0 else 1] == O.PERIODIC:
-                col = i % ni
-            elif b.bc[0 if i < 0 else 1] == O.CUT:
-                src = nbr_xy[0 if i < 0 else 1]
-                col = src.shape[-1] - 1 + i if i < 0 else i - ni
-            jw = 0 if side == 2 else src.shape[-2] - 1
-            ux, uy = rigid_velocity(m, thd, h, hd, 0.5 * (src[0, jw, col] + src[0, jw, col + 1]),
-                                    0.5 * (src[1, jw, col] + src[1, jw, col + 1]))
-            for k in (0, 1):
-                row = (-1 - k if side == 2 else nj + k) + 2
-                we[:, 1, row, ie] += 2.0 * ux
-                we[:, 2, row, ie] += 2.0 * uy
+def wall_images(blocks, cutmap: dict, k: int, we: torch.Tensor, xys, m: OMotion, thd: float,
+                h: float, hd: float):
+    """Add 2 u_w to the velocity of the no-slip wall images of block k's
+    extended field we (in place; the fixed-grid rule gave -u): u_w = the grid
+    velocity at the midpoint of the wall face at which the ghost's
+    resolution mirrored (hb_oracle.wall_map; for a corner ghost that is the
+    column its i-side rule led to: the i-periodic partner column, or the
+    glued block's column across an i cut), on the moved nodes xys of the
+    block holding that face."""
+    walls = O.wall_map(blocks, cutmap, k)
+    if not walls:
+        return we
+    if any(w[3] < 2 for w in walls):
+        raise ValueError("moving grids: walls only on j sides")
+    for wb in sorted(set(w[2] for w in walls)):
+        sel = [w for w in walls if w[2] == wb]
+        xy = xys[wb]
+        je = torch.tensor([w[0] for w in sel])
+        ie = torch.tensor([w[1] for w in sel])
+        jw = torch.tensor([0 if w[3] == 2 else xy.shape[-2] - 1 for w in sel])
+        pos = torch.tensor([w[4] for w in sel])
+        ux, uy = rigid_velocity(m, thd, h, hd, 0.5 * (xy[0, jw, pos] + xy[0, jw, pos + 1]),
+                                0.5 * (xy[1, jw, pos] + xy[1, jw, pos + 1]))
+        we[:, 1, je, ie] += 2.0 * ux
+        we[:, 2, je, ie] += 2.0 * uy
     return we
 
 
@@ -159,7 +150,7 @@ def moving_extend(b: O.OBlock, w: torch.Tensor, winf: torch.Tensor, xy: torch.Te
     check_block(b)
     if any(k in O.GLUED for k in b.bc):
         raise ValueError("moving_extend: a block with cuts needs its neighbours (moving_snapshots)")
-    return wall_images(b, O.extend(b, w, winf).clone(), xy, m, thd, h, hd)
+    return wall_images([b], {}, 0, O.extend(b, w, winf).clone(), [xy], m, thd, h, hd)
 
 
 def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, cuts=(),
@@ -188,8 +179,7 @@ def moving_snapshots(blocks: Sequence[O.OBlock], qs, flow: O.OFlow, m: OMotion, 
             if n >= b.ns:
                 continue
             _, thd, h, hd = mot[k]
-            nbr_xy = {s: xys[O.whole_side_partner(P, k, s)] for s in (0, 1) if (k, s) in P}
-            we = wall_images(b, wes[k].clone(), xys[k], m, thd, h, hd, nbr_xy)
+            we = wall_images(blocks, P, k, wes[k].clone(), xys, m, thd, h, hd)
             Cs = [O.metrics(xy)[3] for xy in xys]
             nbrC = O.cut_ghost_centres(blocks, P, Cs, k) or None
             yield k, n, xys[k], we, nbrC, mot[k]

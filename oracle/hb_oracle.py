@@ -293,10 +293,12 @@ def cut_cell(blocks: Sequence[OBlock], cutmap: dict, b: int, side: int, k: int, 
     return a, pp, A.nj - 1 - k
 
 
-def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int):
+def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int, wall=None):
     """Where ghost-extended cell (i, j) of block b takes its value from:
     (block, i, j, mirror) of an interior cell, or (block, None, None,
     mirror) for the free stream; mirror = parity of the wall images met.
+    With `wall` a list, the wall faces met are appended to it as (block,
+    side, position along the side).
     The i sides are resolved first, then the j sides (the order that
     defines the corner ghosts; on grids without cuts either order gives the
     same cells, and with the i sides first a C-grid cut into wake and
@@ -313,12 +315,11 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
             kind = B.bc[side]
             if kind == PERIODIC:
                 i = i % B.ni
-            elif kind == WALL:
-                i = k if side == 0 else B.ni - 1 - k
-                mir ^= 1
             elif kind in GLUED and cut_segment(blocks, cutmap, b, side, j) is not None:
                 b, i, j = cut_cell(blocks, cutmap, b, side, k, j)
-            elif kind == CUT_WALL:
+            elif kind in (WALL, CUT_WALL):
+                if wall is not None:
+                    wall.append((b, side, j))
                 i = k if side == 0 else B.ni - 1 - k
                 mir ^= 1
             elif kind in (FARFIELD, CUT_FARFIELD):
@@ -332,18 +333,13 @@ def resolve_ghost(blocks: Sequence[OBlock], cutmap: dict, b: int, i: int, j: int
             kind = B.bc[side]
             if kind == PERIODIC:
                 j = j % B.nj
-            elif kind == WALL:
-                j = k if side == 2 else B.nj - 1 - k
-                mir ^= 1
-            elif kind == WAKECUT and side == 2:
-                if i < B.wake_ncells or i >= B.ni - B.wake_ncells:
-                    i, j = B.ni - 1 - i, k
-                else:
-                    j = k
-                    mir ^= 1
+            elif kind == WAKECUT and side == 2 and (i < B.wake_ncells or i >= B.ni - B.wake_ncells):
+                i, j = B.ni - 1 - i, k
             elif kind in GLUED and cut_segment(blocks, cutmap, b, side, i) is not None:
                 b, i, j = cut_cell(blocks, cutmap, b, side, k, i)
-            elif kind == CUT_WALL:
+            elif kind in (WALL, CUT_WALL) or (kind == WAKECUT and side == 2):
+                if wall is not None:
+                    wall.append((b, side, i))
                 j = k if side == 2 else B.nj - 1 - k
                 mir ^= 1
             elif kind in (FARFIELD, CUT_FARFIELD):
@@ -383,6 +379,33 @@ def ghost_map(blocks, cutmap, k: int) -> dict:
         _GHOST_MAPS[key] = {kk: tuple(torch.tensor(x, dtype=torch.long) for x in v)
                             for kk, v in groups.items()}
     return _GHOST_MAPS[key]
+
+
+_WALL_MAPS = {}
+
+
+def wall_map(blocks, cutmap, k: int) -> list:
+    """The ghost cells of block k that are wall images: (je, ie, block,
+    side, position) with the wall face their resolution mirrored at
+    (resolve_ghost)."""
+    key = (k, tuple((b.ni, b.nj, tuple(b.bc), b.wake_ncells) for b in blocks),
+           tuple(sorted((kk, tuple(v)) for kk, v in cutmap.items())))
+    if key not in _WALL_MAPS:
+        b = blocks[k]
+        out = []
+        for je in range(b.nj + 4):
+            for ie in range(b.ni + 4):
+                i, j = ie - 2, je - 2
+                if 0 <= i < b.ni and 0 <= j < b.nj:
+                    continue
+                walls = []
+                resolve_ghost(blocks, cutmap, k, i, j, walls)
+                if len(walls) > 1:
+                    raise ValueError("a ghost meets more than one wall")
+                if walls:
+                    out.append((je, ie) + walls[0])
+        _WALL_MAPS[key] = out
+    return _WALL_MAPS[key]
 
 
 def extend_cut(blocks, ws, winfs, cutmap, k: int) -> torch.Tensor:
@@ -425,18 +448,6 @@ def cut_ghost_centres(blocks, cutmap, Cs, k: int) -> dict:
             cs.append(Cs[a][j, i])
         out[side] = torch.stack(cs)
     return out
-
-
-def whole_side_partner(cutmap: dict, k: int, side: int) -> int:
-    """The block glued to side `side` of block k when one aligned segment
-    joins whole opposite sides (imin-imax or jmin-jmax), else ValueError."""
-    segs = cutmap[(k, side)]
-    if len(segs) != 1:
-        raise ValueError("this rule needs a side glued whole to one block")
-    st, ln, a, sa, st_a, rev = segs[0]
-    if rev or st != 0 or st_a != 0 or {side, sa} not in ({0, 1}, {2, 3}):
-        raise ValueError("this rule needs aligned cuts of opposite sides")
-    return a
 
 
 def extend_i(b: OBlock, w: torch.Tensor, winf: torch.Tensor, nbr=None) -> torch.Tensor:
@@ -522,7 +533,14 @@ def extend(b: OBlock, w: torch.Tensor, winf: torch.Tensor) -> torch.Tensor:
     The i sides are filled first (rows 0..nj-1); the j sides then apply their
     rule to the i-extended rows, which also defines the corner ghosts.
     """
-    return extend_j(b, extend_i(b, w, winf), winf)
+    we = extend_j(b, extend_i(b, w, winf), winf)
+    # the i sides come first, and the far field ends a ghost's resolution:
+    # the corner ghosts beside a far-field i side are free stream
+    for side, cols in ((0, slice(0, 2)), (1, slice(b.ni + 2, b.ni + 4))):
+        if b.bc[side] == FARFIELD:
+            for rows in (slice(0, 2), slice(b.nj + 2, b.nj + 4)):
+                we[:, :, rows, cols] = winf[:, :, None, None]
+    return we
 
 
 def extend_all(blocks, ws, winfs, cutmap):

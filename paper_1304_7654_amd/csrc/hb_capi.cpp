@@ -333,17 +333,6 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
             D.seg_off[s] = (int32_t)seg_table.size();
             D.seg_cnt[s] = (int32_t)side_segs[4 * b + s].size();
             seg_table.insert(seg_table.end(), side_segs[4 * b + s].begin(), side_segs[4 * b + s].end());
-            // the block glued to the whole side by one aligned segment of the
-            // opposite side (used by the moving-grid wall rule), else -1
-            D.cut_blk[s] = D.cut_side[s] = -1;
-            if (D.seg_cnt[s] == 1 && D.rest[s] == 0) {
-                const CutSeg &q = seg_table[D.seg_off[s]];
-                const int L = s < 2 ? D.nj : D.ni;
-                if (q.start == 0 && q.pstart == 0 && q.len == L && !q.rev && (q.side ^ s) == 1) {
-                    D.cut_blk[s] = q.blk;
-                    D.cut_side[s] = q.side;
-                }
-            }
         }
     }
     if (!ghosts_resolve(cut_desc, seg_table))
@@ -377,8 +366,6 @@ int hb_grid_create(const hb_block *blocks, int32_t nblocks, const hb_cut *cuts, 
         for (int s = 0; s < 4; ++s) {
             B.bc[s] = cut_desc[b].bc[s];
             B.rest[s] = cut_desc[b].rest[s];
-            B.cut_blk[s] = cut_desc[b].cut_blk[s];
-            B.cut_side[s] = cut_desc[b].cut_side[s];
             B.seg_off[s] = cut_desc[b].seg_off[s];
             B.seg_cnt[s] = cut_desc[b].seg_cnt[s];
         }
@@ -700,15 +687,10 @@ int hb_set_motion(hb_grid *g, const hb_motion *m) {
         g->motion = Motion{nullptr, 0.0, 0.0};
         return HB_OK;
     }
-    for (const BlockDesc &B : g->blk) {
-        if (B.bc[0] == HB_BC_WALL || B.bc[1] == HB_BC_WALL)
-            return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides");
-        for (int s = 0; s < 4; ++s)
-            if (B.bc[s] == HB_BC_CUT && B.cut_blk[s] < 0)
-                return fail(HB_ERR_UNSUPPORTED, "moving grids: cuts only between whole opposite "
-                                                "sides, aligned (imax-imin, jmax-jmin), no partly "
-                                                "glued sides");
-    }
+    for (const BlockDesc &B : g->blk)
+        for (int s = 0; s < 2; ++s)
+            if (B.bc[s] == HB_BC_WALL || (B.bc[s] == HB_BC_CUT && B.rest[s] == HB_BC_WALL))
+                return fail(HB_ERR_UNSUPPORTED, "moving grids: walls only on j sides");
     if (!g->mot_d) {
         rc = dalloc(&g->mot_d, (int64_t)kMotionW * g->n_snap);
         if (rc) return rc;

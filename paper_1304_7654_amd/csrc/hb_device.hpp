@@ -83,11 +83,17 @@ __device__ __forceinline__ W4<T> mirror(W4<T> w) {
 // covers follow the side's rest kind (wall or far field).  `cell` is a functor (block, i, j) -> value
 // reading an interior cell of any block; `ff(b)` returns the block's free
 // stream of the current snapshot and `mir` the no-slip wall image of a
-// value (applied once per wall met, so two walls cancel).
+// value (applied once per wall met, so two walls cancel); `onwall(block,
+// side, position)` is told each wall face the resolution mirrors at.
 // ---------------------------------------------------------------------------
-template <class V, class Interior, class FF, class Mir>
+struct NoWall {
+    __device__ void operator()(int, int, int) const {}
+};
+
+template <class V, class Interior, class FF, class Mir, class Wall = NoWall>
 __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j,
-                                      const Interior &cell, const FF &ff, const Mir &mir) {
+                                      const Interior &cell, const FF &ff, const Mir &mir,
+                                      const Wall &onwall = Wall()) {
     bool m = false;
     for (int hop = 0; hop < kGhostHops; ++hop) {
         const BlockDesc &B = blks[b];
@@ -97,16 +103,14 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
             const int kind = B.bc[side];
             if (kind == HB_BC_PERIODIC) {
                 i = i < 0 ? i + B.ni : i - B.ni;
-            } else if (kind == HB_BC_WALL) {
-                i = side == 0 ? k : B.ni - 1 - k;
-                m = !m;
             } else if (glued_at(B, B.segs, side, j)) {
                 int a, ia, ja;
                 cut_cell(blks, B.segs, b, side, k, j, &a, &ia, &ja);
                 b = a;
                 i = ia;
                 j = ja;
-            } else if (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL) {
+            } else if (kind == HB_BC_WALL || (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL)) {
+                onwall(b, side, j);
                 i = side == 0 ? k : B.ni - 1 - k;
                 m = !m;
             } else {
@@ -121,15 +125,8 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
             const int kind = B.bc[side];
             if (kind == HB_BC_PERIODIC) {
                 j = j < 0 ? j + B.nj : j - B.nj;
-            } else if (kind == HB_BC_WALL) {
-                j = side == 2 ? k : B.nj - 1 - k;
-                m = !m;
-            } else if (kind == HB_BC_WAKECUT) {
-                if (i < B.wake || i >= B.ni - B.wake) {
-                    i = B.ni - 1 - i;
-                } else {
-                    m = !m;
-                }
+            } else if (kind == HB_BC_WAKECUT && (i < B.wake || i >= B.ni - B.wake)) {
+                i = B.ni - 1 - i;
                 j = k;
             } else if (glued_at(B, B.segs, side, i)) {
                 int a, ia, ja;
@@ -137,7 +134,9 @@ __device__ __forceinline__ V value_ij(const BlockDesc *blks, int b, int i, int j
                 b = a;
                 i = ia;
                 j = ja;
-            } else if (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL) {
+            } else if (kind == HB_BC_WALL || kind == HB_BC_WAKECUT ||
+                       (kind == HB_BC_CUT && B.rest[side] == HB_BC_WALL)) {
+                onwall(b, side, i);
                 j = side == 2 ? k : B.nj - 1 - k;
                 m = !m;
             } else {

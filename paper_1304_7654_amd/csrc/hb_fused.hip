@@ -221,7 +221,7 @@ int fused_build_tiles(hb_grid *g, int tile_i, int order) {
             // moving no-slip wall image: its wall face (moving grids)
             uint32_t wx = 0, wy = 0;
             if (e < ext && gi < K.ni + 2 && gj < K.nj + 2) {
-                const WallFace wf = wall_face(g->blk, t.blk, gi, gj);
+                const WallFace wf = wall_face(g->blk, g->segs, t.blk, gi, gj);
                 if (wf.node >= 0) {
                     const BlockDesc &S = g->blk[wf.blk];
                     wx = (uint32_t)(2 * S.node_off + wf.node);

@@ -9,8 +9,18 @@
 
 namespace hb {
 
-GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j) {
+GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j,
+               int *wall) {
     int mir = 0;
+    // the last wall face mirrored at: block, side, position along the side
+    auto seen = [&](int side, int p) {
+        if (wall) {
+            wall[0] = b;
+            wall[1] = side;
+            wall[2] = p;
+        }
+    };
+    if (wall) wall[0] = -1;
     for (int hop = 0; hop < kGhostHops; ++hop) {
         const BlockDesc &K = B[b];
         if (i < 0 || i >= K.ni) {
@@ -18,10 +28,11 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, in
             const int k = i < 0 ? -1 - i : i - K.ni;
             switch (K.bc[side]) {
                 case HB_BC_PERIODIC: i = i < 0 ? i + K.ni : i - K.ni; break;
-                case HB_BC_WALL: i = side == 0 ? k : K.ni - 1 - k; mir ^= 1; break;
+                case HB_BC_WALL: seen(side, j); i = side == 0 ? k : K.ni - 1 - k; mir ^= 1; break;
                 case HB_BC_CUT: {
                     if (!glued_at(K, S.data(), side, j)) {
                         if (K.rest[side] != HB_BC_WALL) return GSrc{0, b, 0, 0, mir};
+                        seen(side, j);
                         i = side == 0 ? k : K.ni - 1 - k;
                         mir ^= 1;
                         break;
@@ -40,12 +51,13 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, in
             const int k = j < 0 ? -1 - j : j - K.nj;
             switch (K.bc[side]) {
                 case HB_BC_PERIODIC: j = j < 0 ? j + K.nj : j - K.nj; break;
-                case HB_BC_WALL: j = side == 2 ? k : K.nj - 1 - k; mir ^= 1; break;
+                case HB_BC_WALL: seen(side, i); j = side == 2 ? k : K.nj - 1 - k; mir ^= 1; break;
                 case HB_BC_WAKECUT:
                     if (i < K.wake || i >= K.ni - K.wake) {
                         i = K.ni - 1 - i;
                         j = k;
                     } else {
+                        seen(side, i);
                         j = k;
                         mir ^= 1;
                     }
@@ -53,6 +65,7 @@ GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, in
                 case HB_BC_CUT: {
                     if (!glued_at(K, S.data(), side, i)) {
                         if (K.rest[side] != HB_BC_WALL) return GSrc{0, b, 0, 0, mir};
+                        seen(side, i);
                         j = side == 2 ? k : K.nj - 1 - k;
                         mir ^= 1;
                         break;
@@ -84,32 +97,15 @@ bool ghosts_resolve(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &
 // Moving no-slip wall image (ghost (i, j) of block b on a rigidly moving
 // grid): the node index (within the block's node arrays) of the first node
 // of the wall face whose midpoint velocity the image takes, and the block
-// owning it; {-1, ..} when the ghost is no wall image.  The same column
-// rule as the plain kernels' wall_image_motion: a ghost column takes its
-// i-periodic partner column, the glued block's column across an i cut, else
-// the nearest column.
-WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j) {
-    const BlockDesc &K = B[b];
-    int side;
-    if (j < 0) side = 2;
-    else if (j >= K.nj) side = 3;
-    else return WallFace{-1, 0};
-    const int kind = K.bc[side];
-    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return WallFace{-1, 0};
-    if (kind == HB_BC_WAKECUT && (i < K.wake || i >= K.ni - K.wake)) return WallFace{-1, 0};
-    int col = i, src = b;
-    if (i < 0) {
-        if (K.bc[0] == HB_BC_PERIODIC) col = i + K.ni;
-        else if (K.bc[0] == HB_BC_CUT) src = K.cut_blk[0], col = src < 0 ? 0 : B[src].ni + i;
-        else col = 0;
-    } else if (i >= K.ni) {
-        if (K.bc[1] == HB_BC_PERIODIC) col = i - K.ni;
-        else if (K.bc[1] == HB_BC_CUT) src = K.cut_blk[1], col = i - K.ni;
-        else col = K.ni - 1;
-    }
-    if (src < 0) return WallFace{-1, 0};      // a general cut: no moving grid (refused)
-    const BlockDesc &S = B[src];
-    return WallFace{(int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col, src};
+// owning it; {-1, ..} when the ghost is no wall image.  The face is the one
+// at which the ghost's resolution mirrors (the rule of the plain kernels'
+// wall_image_face); walls lie on j sides only (hb_set_motion).
+WallFace wall_face(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j) {
+    int w[3];
+    ghost_src(B, S, b, i, j, w);
+    if (w[0] < 0 || w[1] < 2) return WallFace{-1, 0};
+    const BlockDesc &K = B[w[0]];
+    return WallFace{(int64_t)(w[1] == 2 ? 0 : K.nj) * (K.ni + 1) + w[2], w[0]};
 }
 
 }  // namespace hb

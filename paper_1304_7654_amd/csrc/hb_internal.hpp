@@ -32,9 +32,6 @@ struct BlockDesc {
     int32_t bc[4];
     int32_t wake;
     int32_t body;
-    int32_t cut_blk[4];      // the block glued to a CUT side when one aligned segment joins
-                             // the whole side to the opposite side of that block, else -1
-    int32_t cut_side[4];
     int32_t seg_off[4];      // the side's segments: segs[seg_off .. seg_off + seg_cnt), by start
     int32_t seg_cnt[4];
     int32_t rest[4];         // kind of the cells of a CUT side that no segment covers:
@@ -272,12 +269,15 @@ __host__ __device__ inline void cut_cell(const BlockDesc *blks, const CutSeg *se
 constexpr int kGhostHops = 8;
 
 // ghost.cpp: host-side ghost rules
-GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j);
+// wall (optional, 3 ints): the last wall face the resolution mirrored at
+// (block, side, position along the side), block -1 for none
+GSrc ghost_src(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j,
+               int *wall = nullptr);
 struct WallFace {
     int64_t node;    // first node of the wall face in block `blk`, -1: no wall image
     int blk;
 };
-WallFace wall_face(const std::vector<BlockDesc> &B, int b, int i, int j);
+WallFace wall_face(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S, int b, int i, int j);
 // every ghost of every block resolves within kGhostHops rule applications
 bool ghosts_resolve(const std::vector<BlockDesc> &B, const std::vector<CutSeg> &S);
 

@@ -31,37 +31,36 @@ __device__ __forceinline__ void grid_velocity(const MotionSnap &m, const Motion 
     gy = m.thd * rx + m.hd;
 }
 
-// A ghost (i, j) of block B = blks[b] that is a no-slip wall image (j side
-// wall, or the wall part of a wake cut) takes the grid velocity at the
-// midpoint of the wall face of the mirrored cell's column: corner ghosts
-// take the i-periodic partner column, the glued block's column across an i
-// cut (its wall face on the same j side), else the nearest column.  Returns
-// false for a ghost that is no wall image; else *src = the block holding
-// the wall face and *k = the index of its first node (the second is k + 1).
+// A ghost (i, j) of block b that is a no-slip wall image takes the grid
+// velocity at the midpoint of the wall face at which its resolution
+// (value_ij) mirrors: for a corner ghost that is the column its i-side rule
+// led to (the i-periodic partner column, the glued block's column across
+// an i cut).  Returns false for a ghost that is no wall image; else *src =
+// the block holding the wall face and *k = the index of its first node
+// (the second is k + 1).  Walls lie on j sides only (hb_set_motion refuses
+// others), so a ghost meets at most one.
+struct WallSeen {
+    int *b, *side, *pos;
+    __device__ void operator()(int bb, int s, int p) const {
+        *b = bb;
+        *side = s;
+        *pos = p;
+    }
+};
+struct NoValue {
+    __device__ int operator()(int, int, int) const { return 0; }
+    __device__ int operator()(int) const { return 0; }
+};
+
 __device__ __forceinline__ bool wall_image_face(const BlockDesc *blks, int b, int i, int j, int *src,
                                                 int64_t *k) {
-    const BlockDesc &B = blks[b];
-    int side;
-    if (j < 0) side = 2;
-    else if (j >= B.nj) side = 3;
-    else return false;
-    const int kind = B.bc[side];
-    if (!(kind == HB_BC_WALL || (kind == HB_BC_WAKECUT && side == 2))) return false;
-    if (kind == HB_BC_WAKECUT && (i < B.wake || i >= B.ni - B.wake)) return false;
-    int col = i, s = b;
-    if (i < 0) {
-        if (B.bc[0] == HB_BC_PERIODIC) col = i + B.ni;
-        else if (B.bc[0] == HB_BC_CUT) s = B.cut_blk[0], col = s < 0 ? 0 : blks[s].ni + i;
-        else col = 0;
-    } else if (i >= B.ni) {
-        if (B.bc[1] == HB_BC_PERIODIC) col = i - B.ni;
-        else if (B.bc[1] == HB_BC_CUT) s = B.cut_blk[1], col = i - B.ni;
-        else col = B.ni - 1;
-    }
-    if (s < 0) return false;      // general cuts: no moving grid (refused by hb_set_motion)
-    const BlockDesc &S = blks[s];
-    *src = s;
-    *k = (int64_t)(side == 2 ? 0 : S.nj) * (S.ni + 1) + col;
+    int wb = -1, ws = 0, wp = 0;
+    const NoValue none;
+    value_ij<int>(blks, b, i, j, none, none, [](int x) { return x; }, WallSeen{&wb, &ws, &wp});
+    if (wb < 0 || ws < 2) return false;
+    const BlockDesc &S = blks[wb];
+    *src = wb;
+    *k = (int64_t)(ws == 2 ? 0 : S.nj) * (S.ni + 1) + wp;
     return true;
 }
 

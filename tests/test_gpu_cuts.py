@@ -187,13 +187,99 @@ def test_general_cuts_adjoint(name, make):
     assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
 
 
-def test_general_cuts_refuse_motion():
-    p = synth.make_problem("naca_tiny")
-    sp, _ = synth.split_c_grid(p)
-    g = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=0, batched=1)
-    with pytest.raises(hb.HBError) as e:
-        g.set_motion(pitch_amp=0.1)
-    assert e.value.code == hb.HB_ERR_UNSUPPORTED
+MOT = dict(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_pivot=0.05)
+
+
+def _l_quarter():
+    blocks, cuts = synth.c_grid_l(2, 4)
+    fl = synth.flow_airfoil()
+    fl.alpha0 = 0.03
+    p = synth.Problem("l4", blocks, fl, synth.Solver(), 0, 7, cuts=cuts)
+    return p, torch.as_tensor(synth.initial_state(p))
+
+
+@pytest.mark.parametrize("prec,batched", PATHS)
+@pytest.mark.parametrize("case", ["c_grid_3", "partly_glued", "four_block"])
+def test_general_cuts_on_a_moving_grid(case, prec, batched):
+    """The pitching and heaving grid (hb_set_motion) on glued blocks with
+    general cuts: the C-grid in wake and profile blocks, the partly glued
+    pieces and the four-block layout.  A moving-wall image takes the wall
+    face its ghost's resolution mirrors at (across the cuts).  Residual,
+    three iterations and loads against the moving-grid oracle on the same
+    blocks; the FP64 adjoint (state, nodes, alpha0) against its reverse
+    products."""
+    from oracle import hb_moving as M
+    _say("moving general cuts", case, "prec", prec, "batched", batched)
+    if case == "four_block":
+        sp, qs = _l_quarter()
+    else:
+        make = dict(zip(GENERAL_IDS, [g[1] for g in GENERAL]))[case]
+        p, sp, perm, q = _general("naca_tiny", make)
+        qs = q[perm].contiguous()
+    sb, flow, solver = O.from_synth(sp)
+    m = M.OMotion(**MOT)
+    ref = M.moving_residual_all(sb, qs, flow, solver, m, sp.cuts)
+    n_it = 3
+    qref, nref = M.moving_rk_iterate(sb, qs, flow, solver, m, n_it, sp.cuts)
+    cref = torch.cat([c.reshape(-1) for c in M.moving_forces(sb, qref, flow, solver, m, sp.cuts)])
+    g = hb.Grid(sp.blocks, sp.flow, sp.solver, cuts=sp.cuts, precision=prec, batched=batched)
+    g.set_motion(**MOT)
+    r = g.residual(qs.to(DEV)).cpu()
+    qd = qs.to(DEV)
+    norms = torch.zeros(n_it, dtype=torch.float64, device=DEV)
+    cf = torch.zeros(g.n_forces, dtype=torch.float64, device=DEV)
+    g.rk_iterate(qd, n_it, norms, cf)
+    torch.cuda.synchronize()
+    assert g.status() == hb.HB_OK
+    e_or = _rel(r, ref)
+    dq = _rel(qd.cpu() - qs, qref - qs)
+    dn = float(((norms.cpu() - nref).abs() / nref).max())
+    dc = float((cf.cpu() - cref).abs().max() / cref.abs().max())
+    _say("  residual", e_or, "state", dq, "norms", dn, "forces", dc)
+    assert e_or <= (1e-12 if prec == 0 else 1e-5)
+    assert dq <= (1e-11 if prec == 0 else 1e-5)
+    assert dn <= (1e-12 if prec == 0 else 1e-5)
+    assert dc <= (1e-10 if prec == 0 else 1e-4)
+    if prec == 0 and batched == 1:
+        rbar = torch.randn(qs.shape, generator=torch.Generator().manual_seed(4), dtype=torch.float64)
+        qb_ref, xb_ref, ab_ref = M.moving_residual_vjp(sb, qs, flow, solver, m, rbar, sp.cuts)
+        xyb = torch.empty(g.n_xy, dtype=torch.float64, device=DEV)
+        ab = torch.empty(1, dtype=torch.float64, device=DEV)
+        qb = g.residual_adjoint(qs.to(DEV), rbar.to(DEV), None, xyb, ab)
+        torch.cuda.synchronize()
+        xr = torch.cat([x.reshape(-1) for x in xb_ref])
+        _say("  adjoint qbar", _rel(qb.cpu(), qb_ref), "xybar", _rel(xyb.cpu(), xr))
+        assert _rel(qb.cpu(), qb_ref) <= 1e-11 and _rel(xyb.cpu(), xr) <= 1e-11
+        assert abs(float(ab) - float(ab_ref)) <= 1e-11 * abs(float(ab_ref))
+
+
+def test_far_field_i_sides_beside_a_wall():
+    """A block with far-field i sides and a wall jmin (its corner ghosts are
+    free stream, not wall images): residual and iteration on all paths
+    against the oracle, fixed and moving."""
+    from oracle import hb_moving as M
+    ni, nj = 24, 10
+    blk = synth.Block(ni, nj, 1, synth.o_grid(ni, nj), (synth.FARFIELD, synth.FARFIELD, synth.WALL,
+                                                        synth.FARFIELD))
+    fl = synth.flow_cylinder()
+    fl.alpha0 = 0.03
+    for prec, batched in PATHS:
+        p = synth.Problem("ffw", [blk], fl, synth.Solver(batched=batched), 0, 5)
+        ob, flow, solver = O.from_synth(p)
+        q = torch.as_tensor(synth.initial_state(p))
+        for motion in (None, MOT):
+            g = hb.Grid(p.blocks, p.flow, p.solver, precision=prec, batched=batched)
+            if motion:
+                g.set_motion(**motion)
+                ref = M.moving_residual_all(ob, q, flow, solver, M.OMotion(**motion))
+            else:
+                ref = O.residual_all(ob, q, flow, solver)
+            r = g.residual(q.to(DEV)).cpu()
+            torch.cuda.synchronize()
+            e = _rel(r, ref)
+            _say("  far-field i sides, prec", prec, "batched", batched, "motion", bool(motion), e)
+            assert e <= (1e-12 if prec == 0 else 1e-5)
+            g.close()
 
 
 @pytest.mark.parametrize("prec,batched", PATHS)

@@ -333,3 +333,43 @@ def test_moving_vjps_match_central_differences():
     assert abs(fx - float((xb[0] * dx).sum())) <= 1e-6 * abs(fx)
     fa = float((cfbar * (cf_at(q, flow.alpha0 + h) - cf_at(q, flow.alpha0 - h))).sum()) / (2 * h)
     assert abs(fa - float(ab)) <= 1e-7 * abs(fa)
+
+
+@pytest.mark.parametrize("make", [synth.split_c_grid, lambda p: synth.split_c_grid_at(p, [10, 40, 60], [8])],
+                         ids=["c_grid_3", "partly_glued"])
+def test_moving_general_cuts_equal_uncut(make):
+    """A moving C-grid cut into wake and profile blocks (the wake cut a
+    reversed cut between two blocks), or into pieces whose jmin sides are
+    partly glued: the moving-wall images take the wall face their ghost's
+    resolution mirrored at, which gives the single block's residual, loads
+    and iteration."""
+    p = synth.make_problem("naca_tiny")
+    sp, perm = make(p)
+    perm = torch.as_tensor(perm)
+    blocks, flow, solver = O.from_synth(p)
+    sblocks, _, _ = O.from_synth(sp)
+    q = torch.as_tensor(synth.initial_state(p))
+    m = M.OMotion(pitch_amp=0.3, pitch_phase=0.5, heave_amp=1.5, x_pivot=0.25, y_pivot=0.05)
+    r = M.moving_residual_all(blocks, q, flow, solver, m)
+    rs = M.moving_residual_all(sblocks, q[perm], flow, solver, m, sp.cuts)
+    assert float((rs - r[perm]).abs().max()) <= 1e-13 * float(r.abs().max())
+    cf = torch.cat([c.reshape(-1) for c in M.moving_forces(blocks, q, flow, solver, m)])
+    cfs = torch.cat([c.reshape(-1) for c in M.moving_forces(sblocks, q[perm], flow, solver, m, sp.cuts)])
+    assert float((cf - cfs).abs().max()) <= 1e-13 * float(cf.abs().max())
+    q1, _ = M.moving_rk_iterate(blocks, q, flow, solver, m, 1)
+    q2, _ = M.moving_rk_iterate(sblocks, q[perm], flow, solver, m, 1, sp.cuts)
+    assert float((q2 - q1[perm]).abs().max()) <= 1e-14 * float(q1.abs().max())
+
+
+def test_far_field_i_side_corners_follow_the_i_first_rule():
+    """Beside a far-field i side the corner ghosts are free stream (the i
+    sides are resolved first and the far field ends the resolution), also
+    next to a wall j side: the single-block extension and the general ghost
+    resolution agree cell for cell, and no such corner is a wall image."""
+    b = O.OBlock(16, 8, 1, torch.as_tensor(synth.o_grid(16, 8)), (FF, FF, WALL, FF))
+    flow = _flow()
+    w = O.primitives(_state(b, flow, 10), flow.gamma)
+    winf = O.freestream_prim(flow, b.ns)
+    assert torch.equal(O.extend(b, w, winf), O.extend_cut([b], [w], [winf], {}, 0))
+    walls = O.wall_map([b], {}, 0)
+    assert sorted((je, ie) for je, ie, *_ in walls) == [(je, ie) for je in (0, 1) for ie in range(2, 18)]
