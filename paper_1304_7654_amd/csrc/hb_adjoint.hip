@@ -102,7 +102,7 @@ __device__ inline void rbar_cell(const BlockDesc &B, const double *rbar, int n, 
 // Reverse sweep of one face.  Line cells m2, m1, p0, p1 (ext indices x0..x3),
 // node values at the edge start P and end Q.  Fb: adjoint of the net face
 // flux.  Writes the kAF adjoint terms to out[k * nf] (k = component).
-template <bool NT>
+template <bool NT, bool MV>
 __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], const UVT<double> &P,
                                 const UVT<double> &Q, double sx, double sy, double dx, double dy,
                                 const double Fb[4], const Consts &c, double *out, int64_t nf,
@@ -134,8 +134,8 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
         W4<double> L, R;
         muscl_a(m2, m1, p0, p1, c.eps, L, R);
         double vgb = 0.0;
-        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb, vg, ms ? &vgb : nullptr);
-        if (ms) {
+        roe_flux_rev(L, R, sx, sy, g, c.delta_frac, Fb, Lb, Rb, sxb, syb, vg, MV ? &vgb : nullptr);
+        if constexpr (MV) {
             // vg = (gx, gy) . S, (gx, gy) the grid velocity at the body-frame
             // midpoint; S and d are the body-frame vectors rotated by theta_n
             sxb += vgb * gx;
@@ -195,7 +195,7 @@ __device__ __forceinline__ double moving_geo(const Motion &mo, const BlockDesc &
     return gx * sx + gy * sy;
 }
 
-template <bool NT>
+template <bool NT, bool MV>
 __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
                              const double *dI, const double *rbar, Consts c, double *AF, Motion mo,
                              const double *xy, double *Mb, int64_t tid_) {
@@ -224,15 +224,15 @@ __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const d
     double sx = SI[2 * B.fi_off + f], sy = SI[2 * B.fi_off + nf + f];
     double dx = dI[2 * B.fi_off + f], dy = dI[2 * B.fi_off + nf + f];
     double vg = 0.0, gx = 0.0, gy = 0.0;
-    MotionSnap m;
-    if (mo.tab)
+    MotionSnap m{1.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (MV)
         vg = moving_geo(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy, m, gx, gy);
-    face_rev<NT>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
-             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg, mo.tab ? &m : nullptr, gx, gy,
+    face_rev<NT, MV>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
+             AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg, &m, gx, gy,
              Mb ? Mb + B.afi_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
 
-template <bool NT>
+template <bool NT, bool MV>
 __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
                              const double *dJ, const double *rbar, Consts c, double *AF, Motion mo,
                              const double *xy, double *Mb, int64_t tid_) {
@@ -263,13 +263,13 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
     double sx = SJ[2 * B.fj_off + f], sy = SJ[2 * B.fj_off + nf + f];
     double dx = dJ[2 * B.fj_off + f], dy = dJ[2 * B.fj_off + nf + f];
     double vg = 0.0, gx = 0.0, gy = 0.0;
-    MotionSnap m;
-    if (mo.tab) {
+    MotionSnap m{1.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (MV) {
         const int64_t kA = (int64_t)j * (B.ni + 1) + i;
         vg = moving_geo(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy, m, gx, gy);
     }
-    face_rev<NT>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
-             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg, mo.tab ? &m : nullptr, gx, gy,
+    face_rev<NT, MV>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
+             AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg, &m, gx, gy,
              Mb ? Mb + B.afj_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
 
@@ -278,7 +278,7 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
 // same range with its second (items snapshot-major, so both halves read the
 // same rows of the same snapshot); xcd: XCD-aware workgroup order
 // (launched with xcd_grid workgroups), else the launch order
-template <bool NT>
+template <bool NT, bool MV>
 __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b, const double *ext,
                                                    const double *SI, const double *dI,
                                                    const double *SJ, const double *dJ,
@@ -293,9 +293,9 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
     if (L < 0) return;
     const int64_t t = L * kHalf + (threadIdx.x % kHalf);
     if (threadIdx.x < kHalf) {
-        if (t < nI) adj_face_i<NT>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, MbI, t);
+        if (t < nI) adj_face_i<NT, MV>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, MbI, t);
     } else if (t < nJ) {
-        adj_face_j<NT>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, MbJ, t);
+        adj_face_j<NT, MV>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, MbJ, t);
     }
 }
 
@@ -1166,7 +1166,10 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const int64_t nI = (int64_t)(B.ni + 1) * B.nj * B.ns, nJ = (int64_t)B.ni * (B.nj + 1) * B.ns;
         const bool nt = (double)kAF * 8.0 * (double)(nI + nJ) > 256.0 * (1 << 20);
         const int64_t nw = 256 * (((nI > nJ ? nI : nJ) + 127) / 128);
-        hipLaunchKernelGGL(nt ? k_adj_faces<true> : k_adj_faces<false>, dim3(adj_grid(nw)),
+        const bool mv = g->motion.tab != nullptr;
+        hipLaunchKernelGGL(mv ? (nt ? k_adj_faces<true, true> : k_adj_faces<false, true>)
+                              : (nt ? k_adj_faces<true, false> : k_adj_faces<false, false>),
+                           dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
                            rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d, mbi, mbj);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,

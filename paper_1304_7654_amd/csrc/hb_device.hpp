@@ -564,7 +564,7 @@ __device__ __forceinline__ void muscl_rev1(double m2, double m1, double p0, doub
 // components; adds to Lb, Rb (primitive adjoints) and sxb, syb.  vg: the face
 // speed x_t . S of a moving face (roe_flux); with vgb non-NULL its adjoint is
 // added to *vgb.
-__device__ inline void roe_flux_rev(const W4<double> &L, const W4<double> &R, double sx,
+__device__ __forceinline__ void roe_flux_rev(const W4<double> &L, const W4<double> &R, double sx,
                                     double sy, double g, double delta_frac, const double Fb[4],
                                     W4<double> &Lb, W4<double> &Rb, double &sxb, double &syb,
                                     double vg = 0.0, double *vgb = nullptr) {
