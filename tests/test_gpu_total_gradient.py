@@ -37,10 +37,12 @@ def _say(*a):
 # oscillating incidence.
 PITCH = dict(pitch_amp=math.radians(1.0), x_pivot=0.25)
 CASES = [("naca_tiny_hh8", 12000, (0, 3, 6), None), ("naca_tiny_hh8", 12000, (0, 3, 6), PITCH),
-         ("naca256x128_hh64", 80000, (0, 15, 31, 47, 63), None)]
+         ("naca256x128_hh64", 80000, (0, 15, 31, 47, 63), None),
+         ("naca256x128_hh64", 80000, (0, 31, 63), PITCH)]
 
 
-@pytest.mark.parametrize("name,N_ITER,bumps,motion", CASES, ids=["small", "small-pitching", "adjoint-config"])
+@pytest.mark.parametrize("name,N_ITER,bumps,motion", CASES,
+                         ids=["small", "small-pitching", "adjoint-config", "adjoint-config-pitching"])
 def test_total_gradient_of_mean_lift(name, N_ITER, bumps, motion):
     _say("case", name, N_ITER, "iterations, bumps", bumps, "motion", motion)
     torch.set_num_threads(min(16, os.cpu_count() or 1))
