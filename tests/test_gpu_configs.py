@@ -106,3 +106,50 @@ def test_residual_on_oracle_states(name, batched):
         _say("  %s batched %d after %d: rel %s floor %s" % (name, batched, it,
              ["%.2e" % x for x in e], ["%.2e" % x for x in floor]))
         assert all(a <= t for a, t in zip(e, tol))
+
+
+_MOVING = {}
+
+
+def _moving_trajectory():
+    """The four-block airfoil pitching 1 degree about its quarter chord on
+    the moving grid (its 'pitching' taken literally: no incidence
+    oscillation): the moving-grid oracle's state and norms after 10
+    iterations."""
+    if not _MOVING:
+        import math
+        from oracle import hb_moving as M
+        torch.set_num_threads(min(16, os.cpu_count() or 1))
+        p = synth.make_problem("naca4blk_nh2")
+        p.flow.alpha_amp = 0.0
+        blocks, flow, solver = O.from_synth(p)
+        motion = dict(pitch_amp=math.radians(1.0), x_pivot=0.25)
+        q = torch.as_tensor(synth.initial_state(p))
+        t0 = time.time()
+        q10, n10 = M.moving_rk_iterate(blocks, q, flow, solver, M.OMotion(**motion), 10, p.cuts)
+        _say("  moving oracle: 10 iterations (%.0f s)" % (time.time() - t0))
+        _MOVING.update(p=p, blocks=blocks, motion=motion, q=q, q10=q10, n10=n10)
+    return _MOVING
+
+
+@pytest.mark.parametrize("prec,batched", [(0, 0), (0, 1), (1, 1)])
+def test_four_block_airfoil_pitching_on_a_moving_grid(prec, batched):
+    """The four glued blocks at their size on the pitching grid: state and
+    norms after 10 iterations against the moving-grid oracle (FP64 within
+    1e-10, FP32 bulk within 1e-5), on the plain and the batched paths."""
+    t = _moving_trajectory()
+    p, blocks = t["p"], t["blocks"]
+    _say("four-block airfoil pitching, prec", prec, "batched", batched)
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=prec, batched=batched)
+    g.set_motion(**t["motion"])
+    qd = t["q"].to(DEV)
+    norms = torch.zeros(10, dtype=torch.float64, device=DEV)
+    g.rk_iterate(qd, 10, norms)
+    torch.cuda.synchronize()
+    assert g.status() == hb.HB_OK
+    e = per_var_errors(blocks, qd.cpu() - t["q"], t["q10"] - t["q"])
+    en = float(((norms.cpu() - t["n10"]).abs() / t["n10"]).max())
+    _say("  state change rel per variable", e, "norms rel (max)", en)
+    tol = 1e-10 if prec == 0 else 1e-5
+    assert max(e) <= tol and en <= tol
+    g.close()
