@@ -722,7 +722,9 @@ __device__ void tile_body(const FusedArgs<T> &a, const Tile &tl, int tile_id, un
 }
 
 template <class T, int TI, int TJ, bool FIRST, int MODE, bool MV, bool BIG>
-__global__ void __launch_bounds__(kThreads) k_fused(FusedArgs<T> a) {
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && MV) ? 3 : 1)))
+k_fused(FusedArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its
     // own L2).  Renumber them so that the workgroups of one XCD take
