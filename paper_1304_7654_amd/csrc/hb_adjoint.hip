@@ -425,14 +425,60 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
     }
 }
 
+// Conserved adjoint of cell (t) and snapshot n: own primitive adjoint plus
+// its ghost copies, through the primitive map; hw: (D^T rbar)_n of the cell.
+// Writes qbar and returns the cell-area adjoint share rbar . (D Q) of n.
+__device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDesc &B, int64_t t, int n,
+                                           const double *q, const double *WB, const int *fptr,
+                                           const int *fb, const int *fp, const int *fm, double vol,
+                                           const Consts &c, const double hw[4], double *qbar) {
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
+    const int we = B.ni + 4;
+    const int64_t eplane = (int64_t)we * (B.nj + 4);
+    const int64_t own = (int64_t)(j + 2) * we + i + 2;
+    const int64_t gc = B.cell_off + t;
+    const double gm1 = c.gamma - 1.0;
+    const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
+    double wbv[4];
+    for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
+    for (int k = fptr[gc]; k < fptr[gc + 1]; ++k) {
+        const BlockDesc &S = blks[fb[k]];
+        const int64_t sp = (int64_t)(S.ni + 4) * (S.nj + 4);
+        const double *ws = WB + S.ext_off + (int64_t)n * 4 * sp + fp[k];
+        const double sg = fm[k] ? -1.0 : 1.0;
+        wbv[0] += ws[0];
+        wbv[1] += sg * ws[sp];
+        wbv[2] += sg * ws[2 * sp];
+        wbv[3] += ws[3 * sp];
+    }
+    const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
+    const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
+    const double irq = adj_rcp(qn[0]);
+    const W4<double> w{qn[0], qn[1] * irq, qn[2] * irq,
+                       gm1 * (qn[3] - 0.5 * qn[0] * (qn[1] * irq * qn[1] * irq + qn[2] * irq * qn[2] * irq))};
+    double qb[4];
+    prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
+    double *o = qbar + B.q_off + (int64_t)n * 4 * plane + t;
+    double vb = 0.0;
+    for (int v = 0; v < 4; ++v) {
+        o[v * plane] = qb[v] + vol * hw[v];
+        vb += qn[v] * hw[v];
+    }
+    return vb;
+}
+
 // interior cells: own adjoint + ghost copies -> conserved adjoint + HB
-// source D^T rbar; with VB also the adjoint of the cell area from the HB
-// source, rbar . (D Q), stored per cell for the coordinate node gather
-// (rbar == nullptr: no HB source).
+// source D^T rbar (d/dQ_n of sum_m rbar_m V (D Q)_m = V (D^T rbar)_n); with
+// VB also the adjoint of the cell area from the HB source, rbar . (D Q),
+// stored per cell for the coordinate node gather (rbar == nullptr: no HB
+// source).
 // PER_SNAP: one thread per cell and snapshot (small blocks, which would
 // otherwise leave CUs idle), each writing its snapshot's share of the
-// cell-area adjoint to VB[n * vbs + cell]; else one thread per cell looping
-// over the snapshots, writing VB[cell].
+// cell-area adjoint to VB[n * vbs + cell]; a workgroup takes all snapshots
+// of C = kBS / N_s consecutive cells (thread n C + c), whose rbar it stages
+// in LDS once for the D^T rbar sums.  Else one thread per cell looping over
+// the snapshots with the cell's rbar in registers, writing VB[cell].
 template <bool PER_SNAP>
 __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, const double *q,
                                                   const double *rbar, const double *WB,
@@ -460,69 +506,58 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
     // thread reads all of it
     __shared__ double dm[kMaxNs * kNsPad];
     for (int k = threadIdx.x; k < kMaxNs * kNsPad; k += blockDim.x) dm[k] = D[B.d_off + k];
-    __syncthreads();
     const int64_t plane = (int64_t)B.ni * B.nj;
-    const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tt >= (PER_SNAP ? plane * B.ns : plane)) return;
-    const int64_t t = PER_SNAP ? tt % plane : tt;
-    const int nlo = PER_SNAP ? (int)(tt / plane) : 0;
-    const int nhi = PER_SNAP ? nlo + 1 : B.ns;
-    const int i = (int)(t % B.ni), j = (int)(t / B.ni);
-    const int we = B.ni + 4;
-    const int64_t eplane = (int64_t)we * (B.nj + 4);
-    const int64_t own = (int64_t)(j + 2) * we + i + 2;
-    const int64_t gc = B.cell_off + t;
-    const double vol = V[gc];
-    const double gm1 = c.gamma - 1.0;
     const int ns = B.ns;
-    // rbar of this cell, all snapshots, in registers (static indices only)
-    double rb[kMaxNs][4];
-#pragma unroll
-    for (int m = 0; m < kMaxNs; ++m)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            rb[m][v] = (rbar && m < ns) ? rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t] : 0.0;
-    double vb = 0.0;
-    for (int n = nlo; n < nhi; ++n) {
-        const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
-        double wbv[4];
-        for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
-        for (int k = fptr[gc]; k < fptr[gc + 1]; ++k) {
-            const BlockDesc &S = blks[fb[k]];
-            const int64_t sp = (int64_t)(S.ni + 4) * (S.nj + 4);
-            const double *ws = WB + S.ext_off + (int64_t)n * 4 * sp + fp[k];
-            const double sg = fm[k] ? -1.0 : 1.0;
-            wbv[0] += ws[0];
-            wbv[1] += sg * ws[sp];
-            wbv[2] += sg * ws[2 * sp];
-            wbv[3] += ws[3 * sp];
-        }
-        const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
-        const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
-        const double irq = adj_rcp(qn[0]);
-        const W4<double> w{qn[0], qn[1] * irq, qn[2] * irq,
-                           gm1 * (qn[3] - 0.5 * qn[0] * (qn[1] * irq * qn[1] * irq + qn[2] * irq * qn[2] * irq))};
-        double qb[4];
-        prim_rev(w, W4<double>{wbv[0], wbv[1], wbv[2], wbv[3]}, gm1, qb);
-        // HB source: d/dQ_n of sum_m rbar_m V (D Q)_m = V (D^T rbar)_n
+    if constexpr (PER_SNAP) {
+        __shared__ double rbs[4 * kBS];            // rbs[(m 4 + v) C + c]
+        const int C = kBS / ns, tid = (int)threadIdx.x;
+        const int cg = tid % C, n = tid / C;
+        const int64_t t = (int64_t)blockIdx.x * C + cg;
+        const bool live = n < ns && t < plane;
+        if (live)
+            for (int v = 0; v < 4; ++v)
+                rbs[(n * 4 + v) * C + cg] = rbar ? rbar[B.q_off + ((int64_t)n * 4 + v) * plane + t] : 0.0;
+        __syncthreads();
+        if (!live) return;
         double hw[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int m = 0; m < ns; ++m) {
+            const double d = dm[m * kNsPad + n];
 #pragma unroll
-        for (int m = 0; m < kMaxNs; ++m) {
-            if (m < ns) {
-                const double d = dm[m * kNsPad + n];
+            for (int v = 0; v < 4; ++v) hw[v] += d * rbs[(m * 4 + v) * C + cg];
+        }
+        const int64_t gc = B.cell_off + t;
+        const double vb = fold_one(blks, B, t, n, q, WB, fptr, fb, fp, fm, V[gc], c, hw, qbar);
+        if (VB) VB[(int64_t)n * vbs + gc] = rbar ? vb : 0.0;
+    } else {
+        __syncthreads();
+        const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (t >= plane) return;
+        const int64_t gc = B.cell_off + t;
+        const double vol = V[gc];
+        // rbar of this cell, all snapshots, in registers (static indices only)
+        double rb[kMaxNs][4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) hw[v] += d * rb[m][v];
+        for (int m = 0; m < kMaxNs; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                rb[m][v] = (rbar && m < ns) ? rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t] : 0.0;
+        double vb = 0.0;
+        for (int n = 0; n < ns; ++n) {
+            double hw[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int m = 0; m < kMaxNs; ++m) {
+                if (m < ns) {
+                    const double d = dm[m * kNsPad + n];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) hw[v] += d * rb[m][v];
+                }
             }
+            vb += fold_one(blks, B, t, n, q, WB, fptr, fb, fp, fm, vol, c, hw, qbar);
         }
-        double *o = qbar + B.q_off + (int64_t)n * 4 * plane + t;
-        for (int v = 0; v < 4; ++v) {
-            o[v * plane] = qb[v] + vol * hw[v];
-            vb += qn[v] * hw[v];
-        }
+        // adjoint of the cell area (its node derivatives are taken by the
+        // coordinate node gather)
+        if (VB) VB[gc] = rbar ? vb : 0.0;
     }
-    // adjoint of the cell area (its node derivatives are taken by the
-    // coordinate node gather)
-    if (VB) VB[(int64_t)nlo * vbs + gc] = rbar ? vb : 0.0;
 }
 
 // alpha0: far-field ghost adjoints . d w_inf / d alpha0; one thread per
@@ -1185,7 +1220,8 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const BlockDesc &B = g->blk[b];
         const int64_t nc = (int64_t)B.ni * B.nj;
         if (fold_per_snap(B))
-            hipLaunchKernelGGL(k_adj_fold<true>, dim3(nblk(nc * B.ns)), dim3(kBS), 0, s, g->blk_d, b,
+            hipLaunchKernelGGL(k_adj_fold<true>, dim3((unsigned)((nc + kBS / B.ns - 1) / (kBS / B.ns))),
+                               dim3(kBS), 0, s, g->blk_d, b,
                                q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
                                g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
                                b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr,
