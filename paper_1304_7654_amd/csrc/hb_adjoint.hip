@@ -319,23 +319,25 @@ __global__ void __launch_bounds__(kBS) k_adj_nodes(const BlockDesc *blks, int b,
     const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
     const double *ai = AFI + B.afi_off + (int64_t)n * kAF * nfi;
     const double *aj = AFJ + B.afj_off + (int64_t)n * kAF * nfj;
+    // the four faces at the node, in a fixed order; every load is issued
+    // (faces outside the block read face 0 and add zero), so that the four
+    // faces cost one memory round trip instead of four
+    const bool has[4] = {j < B.nj, j >= 1, i < B.ni, i >= 1};
+    const double *src[4] = {
+        ai + 16 * nfi + (has[0] ? (int64_t)j * W + i : 0),           // i-face (i, j): slot 0
+        ai + 19 * nfi + (has[1] ? (int64_t)(j - 1) * W + i : 0),     // i-face (i, j-1): slot 1
+        aj + 19 * nfj + (has[2] ? (int64_t)j * B.ni + i : 0),        // j-face (i, j): slot 1
+        aj + 16 * nfj + (has[3] ? (int64_t)j * B.ni + i - 1 : 0)};   // j-face (i-1, j): slot 0
+    double x[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) x[q][v] = src[q][v * (q < 2 ? nfi : nfj)];
     double s[3] = {0.0, 0.0, 0.0};
-    if (j < B.nj) {                          // i-face (i, j): node (i, j) is slot 0
-        const int64_t f = (int64_t)j * W + i;
-        for (int v = 0; v < 3; ++v) s[v] += ai[(16 + v) * nfi + f];
-    }
-    if (j >= 1) {                            // i-face (i, j-1): node (i, j) is slot 1
-        const int64_t f = (int64_t)(j - 1) * W + i;
-        for (int v = 0; v < 3; ++v) s[v] += ai[(19 + v) * nfi + f];
-    }
-    if (i < B.ni) {                          // j-face (i, j): node (i, j) is slot 1
-        const int64_t f = (int64_t)j * B.ni + i;
-        for (int v = 0; v < 3; ++v) s[v] += aj[(19 + v) * nfj + f];
-    }
-    if (i >= 1) {                            // j-face (i-1, j): node (i, j) is slot 0
-        const int64_t f = (int64_t)j * B.ni + i - 1;
-        for (int v = 0; v < 3; ++v) s[v] += aj[(16 + v) * nfj + f];
-    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s[v] += has[q] ? x[q][v] : 0.0;
     double *o = NB + B.nodeq_off + (int64_t)n * 3 * nn + k;
     for (int v = 0; v < 3; ++v) o[v * nn] = s[v];
 }
@@ -440,6 +442,10 @@ __device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDes
     const int64_t gc = B.cell_off + t;
     const double gm1 = c.gamma - 1.0;
     const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
+    // the cell's state and own adjoint are loaded before the ghost-copy
+    // list is walked, so that their loads overlap its round trips
+    const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
+    const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
     double wbv[4];
     for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
     for (int k = fptr[gc]; k < fptr[gc + 1]; ++k) {
@@ -452,8 +458,6 @@ __device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDes
         wbv[2] += sg * ws[2 * sp];
         wbv[3] += ws[3 * sp];
     }
-    const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
-    const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
     const double irq = adj_rcp(qn[0]);
     const W4<double> w{qn[0], qn[1] * irq, qn[2] * irq,
                        gm1 * (qn[3] - 0.5 * qn[0] * (qn[1] * irq * qn[1] * irq + qn[2] * irq * qn[2] * irq))};
@@ -479,6 +483,25 @@ __device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDes
 // of C = kBS / N_s consecutive cells (thread n C + c), whose rbar it stages
 // in LDS once for the D^T rbar sums.  Else one thread per cell looping over
 // the snapshots with the cell's rbar in registers, writing VB[cell].
+__device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *Mb,
+                           const double *xy, const double *C, double *xyb, double *G, int64_t n_fi,
+                           int64_t tid_);
+__device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const double *AF, const double *Mb,
+                           const double *xy, const double *C, double *xyb, double *G, int64_t n_fj,
+                           int64_t tid_);
+
+// The per-face step of the coordinate adjoints (adj_xy_i/j) of one block,
+// run by the workgroups of a fold launch past its fold workgroups: the two
+// are independent (the face step reads the face records and adds into the
+// node adjoints that the node kernel has cleared), so one launch covers both
+// and the short face step fills the fold's tail.
+struct XyStep {
+    const double *AFI, *AFJ, *MbI, *MbJ, *xy, *C;
+    double *xyb, *G;
+    int64_t n_fi, n_fj, nI, n;     // n = i-faces + j-faces of the block; 0: no face step
+    unsigned first;                // first workgroup of the face step
+};
+
 template <bool PER_SNAP>
 __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, const double *q,
                                                   const double *rbar, const double *WB,
@@ -486,7 +509,14 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
                                                   const int *fm, const double *V, const double *D,
                                                   Consts c, double *qbar, const double *apart,
                                                   int64_t napart, double *flowbar, double *VB,
-                                                  int64_t vbs) {
+                                                  int64_t vbs, XyStep xs) {
+    if (xs.n && blockIdx.x >= xs.first) {
+        const int64_t t = (int64_t)(blockIdx.x - xs.first) * kBS + threadIdx.x;
+        if (t < xs.nI) adj_xy_i(blks, b, xs.AFI, xs.MbI, xs.xy, xs.C, xs.xyb, xs.G, xs.n_fi, t);
+        else if (t < xs.n)
+            adj_xy_j(blks, b, xs.AFJ, xs.MbJ, xs.xy, xs.C, xs.xyb, xs.G + 6 * xs.n_fi, xs.n_fj, t - xs.nI);
+        return;
+    }
     // workgroup 0 (of the first block's launch) first sums the alpha0
     // partials of the cell-adjoint kernels, in a fixed order
     if (flowbar && blockIdx.x == 0) {
@@ -697,6 +727,39 @@ __device__ inline void ghost_centre_rev(const BlockDesc *blks, int b, int side, 
 // faces of +d for the faces where it is R and -d where it is L) and the cell
 // areas' adjoints (VB, from the HB source) are gathered and added, without
 // atomics.
+// The S and d adjoints of one face (and, with Mb, its midpoint adjoints)
+// summed over the ns snapshots in snapshot order.  Every snapshot's loads
+// are issued before the first sum: a loop that adds as it loads waits for
+// one memory round trip per snapshot.
+__device__ __forceinline__ void sum_face_snapshots(const double *a, const double *mb, int64_t nf, int ns,
+                                                   double &sxb, double &syb, double &dxb, double &dyb,
+                                                   double &mxb, double &myb) {
+    double v[kMaxNs][4];
+#pragma unroll
+    for (int n = 0; n < kMaxNs; ++n) {
+        if (n < ns) {
+            const double *an = a + (int64_t)n * kAF * nf;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[n][c] = an[(22 + c) * nf];
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < kMaxNs; ++n) {
+        if (n < ns) {
+            sxb += v[n][0];
+            syb += v[n][1];
+            dxb += v[n][2];
+            dyb += v[n][3];
+        }
+    }
+    if (mb) {
+        for (int n = 0; n < ns; ++n) {
+            mxb += mb[(int64_t)n * 2 * nf];
+            myb += mb[(int64_t)n * 2 * nf + nf];
+        }
+    }
+}
+
 // i-faces: S_I = (yB - yA, xA - xB), A = node (i, j), B = node (i, j+1);
 // d = centre(R) - centre(L)
 __device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const double *AF, const double *Mb,
@@ -709,18 +772,8 @@ __device__ __forceinline__ void adj_xy_i(const BlockDesc *blks, int b, const dou
     if (f >= nf) return;
     const int i = (int)(f % W), j = (int)(f / W);
     double sxb = 0, syb = 0, dxb = 0, dyb = 0, mxb = 0, myb = 0;
-    for (int n = 0; n < B.ns; ++n) {
-        const double *a = AF + B.afi_off + (int64_t)n * kAF * nf + f;
-        sxb += a[22 * nf];
-        syb += a[23 * nf];
-        dxb += a[24 * nf];
-        dyb += a[25 * nf];
-        if (Mb) {
-            const double *mb = Mb + B.afi_off / kAF * 2 + (int64_t)n * 2 * nf + f;
-            mxb += mb[0];
-            myb += mb[nf];
-        }
-    }
+    sum_face_snapshots(AF + B.afi_off + f, Mb ? Mb + B.afi_off / kAF * 2 + f : nullptr, nf, B.ns,
+                       sxb, syb, dxb, dyb, mxb, myb);
     double *g = G + B.fi_off + f;
     g[0] = sxb;
     g[n_fi] = syb;
@@ -744,18 +797,8 @@ __device__ __forceinline__ void adj_xy_j(const BlockDesc *blks, int b, const dou
     if (f >= nf) return;
     const int i = (int)(f % B.ni), j = (int)(f / B.ni);
     double sxb = 0, syb = 0, dxb = 0, dyb = 0, mxb = 0, myb = 0;
-    for (int n = 0; n < B.ns; ++n) {
-        const double *a = AF + B.afj_off + (int64_t)n * kAF * nf + f;
-        sxb += a[22 * nf];
-        syb += a[23 * nf];
-        dxb += a[24 * nf];
-        dyb += a[25 * nf];
-        if (Mb) {
-            const double *mb = Mb + B.afj_off / kAF * 2 + (int64_t)n * 2 * nf + f;
-            mxb += mb[0];
-            myb += mb[nf];
-        }
-    }
+    sum_face_snapshots(AF + B.afj_off + f, Mb ? Mb + B.afj_off / kAF * 2 + f : nullptr, nf, B.ns,
+                       sxb, syb, dxb, dyb, mxb, myb);
     double *g = G + B.fj_off + f;
     g[0] = sxb;
     g[n_fj] = syb;
@@ -781,60 +824,87 @@ __global__ void __launch_bounds__(kBS) k_adj_xy(const BlockDesc *blks, int b, co
     else adj_xy_j(blks, b, AFJ, MbJ, xy, C, xyb, G + 6 * n_fi, n_fj, t - nI);
 }
 
-// per-node step: one thread per node of block b
+// per-node step: four lanes per node of block b.  Lane c of a node takes
+// the node's face c (i-face above, i-face below, j-face right, j-face left)
+// and the cell at its corner c (cells (i, j), (i-1, j), (i-1, j-1),
+// (i, j-1), where the node is that cell's corner 1, 2, 3, 4); the four
+// partial sums are combined by two lane exchanges, a fixed order.
 __global__ void __launch_bounds__(kBS) k_adj_xy_nodes(const BlockDesc *blks, int b, const double *G,
                                                       int64_t n_fi, int64_t n_fj, const double *VB,
                                                       int nvb, int64_t vbs, const double *xy,
-                                                      double *xyb) {
+                                                      int mid, double *xyb) {
     const BlockDesc &B = blks[b];
     const int ni = B.ni, nj = B.nj, W = ni + 1;
     const int64_t nn = (int64_t)W * (nj + 1);
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    const int i = (int)(k % W), j = (int)(k / W);
-    const double *gi = G + B.fi_off, *gj = G + 6 * n_fi + B.fj_off;
-    auto GI = [&](int fi, int fj, int c) { return gi[c * n_fi + (int64_t)fj * W + fi]; };
-    auto GJ = [&](int fi, int fj, int c) { return gj[c * n_fj + (int64_t)fj * ni + fi]; };
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = t >> 2;
+    const int c = (int)(t & 3);
+    const bool on = k < nn;
+    const int i = on ? (int)(k % W) : 0, j = on ? (int)(k / W) : 0;
+    // the sign of this lane's face and corner terms: - for lanes 0 and 3
+    const double sg = (c == 0 || c == 3) ? -1.0 : 1.0;
     double ax = 0.0, ay = 0.0;
-    // face lengths: i-face (i, j) has this node as A, i-face (i, j-1) as B;
-    // j-face (i, j) as A, j-face (i-1, j) as B
-    // (and, on a moving grid, half of each face's midpoint adjoint)
-    if (j < nj) { ay -= GI(i, j, 0); ax += GI(i, j, 1) + 0.5 * GI(i, j, 4); ay += 0.5 * GI(i, j, 5); }
-    if (j > 0) { ay += GI(i, j - 1, 0); ax -= GI(i, j - 1, 1); ax += 0.5 * GI(i, j - 1, 4); ay += 0.5 * GI(i, j - 1, 5); }
-    if (i < ni) { ay += GJ(i, j, 0); ax -= GJ(i, j, 1); ax += 0.5 * GJ(i, j, 4); ay += 0.5 * GJ(i, j, 5); }
-    if (i > 0) { ay -= GJ(i - 1, j, 0); ax += GJ(i - 1, j, 1); ax += 0.5 * GJ(i - 1, j, 4); ay += 0.5 * GJ(i - 1, j, 5); }
-    const double *x = xy + 2 * B.node_off, *y = x + nn;
-    for (int dj = -1; dj <= 0; ++dj)
-        for (int di = -1; di <= 0; ++di) {
-            const int ci = i + di, cj = j + dj;
-            if (ci < 0 || ci >= ni || cj < 0 || cj >= nj) continue;
-            ax += 0.25 * (GI(ci, cj, 2) - GI(ci + 1, cj, 2) + GJ(ci, cj, 2) - GJ(ci, cj + 1, 2));
-            ay += 0.25 * (GI(ci, cj, 3) - GI(ci + 1, cj, 3) + GJ(ci, cj, 3) - GJ(ci, cj + 1, 3));
-            if (VB) {
-                // V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over nodes
-                // 1 = (ci, cj), 2 = (ci+1, cj), 3 = (ci+1, cj+1), 4 = (ci, cj+1)
-                double vsum = 0.0;
-                for (int m = 0; m < nvb; ++m) vsum += VB[(int64_t)m * vbs + B.cell_off + (int64_t)cj * ni + ci];
-                const double h = 0.5 * vsum;
-                const int64_t k1 = (int64_t)cj * W + ci, k2 = k1 + 1, k3 = k1 + W + 1, k4 = k1 + W;
-                if (di == 0 && dj == 0) {          // node 1
-                    ax -= h * (y[k4] - y[k2]);
-                    ay += h * (x[k4] - x[k2]);
-                } else if (di == -1 && dj == 0) {  // node 2
-                    ax += h * (y[k3] - y[k1]);
-                    ay -= h * (x[k3] - x[k1]);
-                } else if (di == -1) {             // node 3
-                    ax += h * (y[k4] - y[k2]);
-                    ay -= h * (x[k4] - x[k2]);
-                } else {                           // node 4
-                    ax -= h * (y[k3] - y[k1]);
-                    ay += h * (x[k3] - x[k1]);
-                }
+    // face length (and, on a moving grid, half of the face's midpoint
+    // adjoint): S_I = (yB - yA, xA - xB) with this node as A of i-face
+    // (i, j) and B of i-face (i, j-1); S_J = (yA - yB, xB - xA) with it as A
+    // of j-face (i, j) and B of j-face (i-1, j)
+    {
+        const bool fI = c < 2;
+        const int fi = c == 3 ? i - 1 : i, fj = c == 1 ? j - 1 : j;
+        const bool fin = on && (c == 0 ? j < nj : c == 1 ? j > 0 : c == 2 ? i < ni : i > 0);
+        if (fin) {
+            const int64_t st = fI ? n_fi : n_fj;
+            const double *gf = fI ? G + B.fi_off + (int64_t)fj * W + fi
+                                  : G + 6 * n_fi + B.fj_off + (int64_t)fj * ni + fi;
+            ay += sg * gf[0];
+            ax -= sg * gf[st];
+            if (mid) {
+                ax += 0.5 * gf[4 * st];
+                ay += 0.5 * gf[5 * st];
             }
         }
-    double *xb = xyb + 2 * B.node_off;
-    xb[k] += ax;
-    xb[nn + k] += ay;
+    }
+    // cell at corner c: its centre (the mean of its nodes) and, with VB, its
+    // area V = ((x3 - x1)(y4 - y2) - (y3 - y1)(x4 - x2)) / 2 over its nodes
+    // 1 = (ci, cj), 2 = (ci+1, cj), 3 = (ci+1, cj+1), 4 = (ci, cj+1)
+    {
+        const int ci = (c == 1 || c == 2) ? i - 1 : i, cj = c >= 2 ? j - 1 : j;
+        const bool cin = on && ci >= 0 && ci < ni && cj >= 0 && cj < nj;
+        if (cin) {
+            const double *gi = G + B.fi_off, *gj = G + 6 * n_fi + B.fj_off;
+            const int64_t fa = (int64_t)cj * W + ci, fb = (int64_t)cj * ni + ci;
+            ax += 0.25 * (gi[2 * n_fi + fa] - gi[2 * n_fi + fa + 1] + gj[2 * n_fj + fb] - gj[2 * n_fj + fb + ni]);
+            ay += 0.25 * (gi[3 * n_fi + fa] - gi[3 * n_fi + fa + 1] + gj[3 * n_fj + fb] - gj[3 * n_fj + fb + ni]);
+            if (VB) {
+                const double *vb = VB + B.cell_off + (int64_t)cj * ni + ci;
+                double vs[kMaxNs];
+#pragma unroll
+                for (int m = 0; m < kMaxNs; ++m)
+                    if (m < nvb) vs[m] = vb[(int64_t)m * vbs];
+                double vsum = 0.0;
+#pragma unroll
+                for (int m = 0; m < kMaxNs; ++m)
+                    if (m < nvb) vsum += vs[m];
+                const double h = 0.5 * vsum;
+                // the two other corners this node's term uses: 4 and 2 for
+                // corners 1 and 3, 3 and 1 for corners 2 and 4
+                const double *x = xy + 2 * B.node_off, *y = x + nn;
+                const int64_t k1 = (int64_t)cj * W + ci;
+                const int64_t kp = (c & 1) ? k1 + W + 1 : k1 + W, km = (c & 1) ? k1 : k1 + 1;
+                ax += sg * h * (y[kp] - y[km]);
+                ay -= sg * h * (x[kp] - x[km]);
+            }
+        }
+    }
+    ax += __shfl_xor(ax, 1);
+    ay += __shfl_xor(ay, 1);
+    ax += __shfl_xor(ax, 2);
+    ay += __shfl_xor(ay, 2);
+    if (on && c == 0) {
+        double *xb = xyb + 2 * B.node_off;
+        xb[k] += ax;
+        xb[nn + k] += ay;
+    }
 }
 
 // Moving no-slip wall images u_g = 2 u_wall - u, u_wall the grid velocity at
@@ -1215,34 +1285,43 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
                            flowbar ? g->cpart_d + g->cpart_off[b] : (double *)nullptr,
                            adj_xcd((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns));
     }
-    // every block's extended adjoints exist before any fold (cuts read neighbours)
+    // every block's extended adjoints exist before any fold (cuts read
+    // neighbours); with xybar each fold launch also runs its block's
+    // coordinate face step
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
         const int64_t nc = (int64_t)B.ni * B.nj;
-        if (fold_per_snap(B))
-            hipLaunchKernelGGL(k_adj_fold<true>, dim3((unsigned)((nc + kBS / B.ns - 1) / (kBS / B.ns))),
-                               dim3(kBS), 0, s, g->blk_d, b,
+        const bool ps = fold_per_snap(B);
+        const unsigned nf = ps ? (unsigned)((nc + kBS / B.ns - 1) / (kBS / B.ns)) : nblk(nc);
+        XyStep xs{};
+        if (xybar) {
+            const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
+            xs = XyStep{g->AFI_d, g->AFJ_d, mbi, mbj, g->xy_d, g->C_d, xybar, g->geo_d,
+                        g->n_fi, g->n_fj, nI, nI + nJ, nf};
+        }
+        const dim3 grid(nf + (xybar ? nblk(xs.n) : 0u));
+        if (ps)
+            hipLaunchKernelGGL(k_adj_fold<true>, grid, dim3(kBS), 0, s, g->blk_d, b,
                                q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
                                g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
                                b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr,
-                               g->n_cells);
+                               g->n_cells, xs);
         else
-            hipLaunchKernelGGL(k_adj_fold<false>, dim3(nblk(nc)), dim3(kBS), 0, s, g->blk_d, b,
+            hipLaunchKernelGGL(k_adj_fold<false>, grid, dim3(kBS), 0, s, g->blk_d, b,
                                q, rbar, g->WBext_d, g->fold_ptr_d, g->fold_b_d, g->fold_p_d, g->fold_m_d,
                                g->V_d, g->D_d, c, qbar, g->cpart_d, g->n_cpart,
                                b == 0 ? flowbar : (double *)nullptr, xybar ? g->vb_d : (double *)nullptr,
-                               g->n_cells);
+                               g->n_cells, xs);
     }
     if (xybar) {
+        // every block's face step is done before any node gather (its
+        // ghost-side atomics may reach a neighbour's nodes)
         if (g->motion.tab) launch_wall_motion(g, xybar, s);
         for (int b = 0; b < g->nblocks; ++b) {
             const BlockDesc &B = g->blk[b];
-            const int64_t nI = (int64_t)(B.ni + 1) * B.nj, nJ = (int64_t)B.ni * (B.nj + 1);
-            hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
-                               g->AFJ_d, mbi, mbj, g->xy_d, g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
-            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d,
-                               fold_per_snap(B) ? B.ns : 1, g->n_cells, g->xy_d, xybar);
+            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)4 * (B.ni + 1) * (B.nj + 1))), dim3(kBS), 0,
+                               s, g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, g->vb_d,
+                               fold_per_snap(B) ? B.ns : 1, g->n_cells, g->xy_d, mbi != nullptr, xybar);
         }
     }
     return check_hip(hipGetLastError(), "adjoint launch");
@@ -1340,7 +1419,7 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
                            q, (const double *)nullptr, g->WBext_d, g->fold_ptr_d, g->fold_b_d,
                            g->fold_p_d, g->fold_m_d, g->V_d, g->D_d, c, qbar,
                            (const double *)nullptr, (int64_t)0, (double *)nullptr, (double *)nullptr,
-                           (int64_t)0);
+                           (int64_t)0, XyStep{});
     }
     if (flowbar) {
         launch_alpha(g, s);
@@ -1358,9 +1437,9 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
             hipLaunchKernelGGL(k_adj_xy, dim3(nblk(nI + nJ)), dim3(kBS), 0, s, g->blk_d, b, g->AFI_d,
                                g->AFJ_d, (const double *)nullptr, (const double *)nullptr, g->xy_d,
                                g->C_d, xybar, g->geo_d, g->n_fi, g->n_fj, nI);
-            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1))), dim3(kBS), 0, s,
-                               g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, 0,
-                               (int64_t)0, g->xy_d, xybar);
+            hipLaunchKernelGGL(k_adj_xy_nodes, dim3(nblk((int64_t)4 * (B.ni + 1) * (B.nj + 1))), dim3(kBS), 0,
+                               s, g->blk_d, b, g->geo_d, g->n_fi, g->n_fj, (const double *)nullptr, 0,
+                               (int64_t)0, g->xy_d, 0, xybar);
         }
     }
     return check_hip(hipGetLastError(), "forces adjoint launch");

@@ -70,7 +70,7 @@ def test_total_gradient_of_mean_lift(name, N_ITER, bumps, motion):
     J, qs = mean_cl(b, a0, q_init, N_ITER)
     J.backward()
     pn, an = g.last_norms.cpu(), g.last_adjoint_norms.cpu()
-    _say("  J", float(J), "primal drop", float(pn[-1] / pn[0]), "adjoint drop", float(an[-1] / an[0]))
+    _say("  J", float(J.detach()), "primal drop", float(pn[-1] / pn[0]), "adjoint drop", float(an[-1] / an[0]))
     assert g.status() == hb.HB_OK
     assert float(pn[-1] / pn[0]) <= 1e-12 and float(an[-1] / an[0]) <= 1e-11, (pn[-1], an[-1])
 
