@@ -102,7 +102,7 @@ __device__ inline void rbar_cell(const BlockDesc &B, const double *rbar, int n, 
 // Reverse sweep of one face.  Line cells m2, m1, p0, p1 (ext indices x0..x3),
 // node values at the edge start P and end Q.  Fb: adjoint of the net face
 // flux.  Writes the kAF adjoint terms to out[k * nf] (k = component).
-template <bool NT, bool MV>
+template <bool NT, bool MV, bool GEO>
 __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], const UVT<double> &P,
                                 const UVT<double> &Q, double sx, double sy, double dx, double dy,
                                 const double Fb[4], const Consts &c, double *out, int64_t nf,
@@ -150,10 +150,12 @@ __device__ inline void face_rev(const double *e, int64_t plane, const int x[4], 
             rot2_rev(*ms, dxb, dyb);
         }
     }
-    ntst<NT>(out + 22 * nf, sxb);
-    ntst<NT>(out + 23 * nf, syb);
-    ntst<NT>(out + 24 * nf, dxb);
-    ntst<NT>(out + 25 * nf, dyb);
+    if constexpr (GEO) {        // read only by the coordinate adjoints
+        ntst<NT>(out + 22 * nf, sxb);
+        ntst<NT>(out + 23 * nf, syb);
+        ntst<NT>(out + 24 * nf, dxb);
+        ntst<NT>(out + 25 * nf, dyb);
+    }
     const W4<double> m2 = ldw(e, plane, x[0]), m1 = ldw(e, plane, x[1]);
     const W4<double> p0 = ldw(e, plane, x[2]), p1 = ldw(e, plane, x[3]);
     double cb[4][4] = {{0}};
@@ -195,7 +197,7 @@ __device__ __forceinline__ double moving_geo(const Motion &mo, const BlockDesc &
     return gx * sx + gy * sy;
 }
 
-template <bool NT, bool MV>
+template <bool NT, bool MV, bool GEO>
 __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const double *ext, const double *SI,
                              const double *dI, const double *rbar, Consts c, double *AF, Motion mo,
                              const double *xy, double *Mb, int64_t tid_) {
@@ -227,12 +229,12 @@ __device__ __forceinline__ void adj_face_i(const BlockDesc *blks, int b, const d
     MotionSnap m{1.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (MV)
         vg = moving_geo(mo, B, n, xy, (int64_t)j * W + i, (int64_t)(j + 1) * W + i, sx, sy, dx, dy, m, gx, gy);
-    face_rev<NT, MV>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
+    face_rev<NT, MV, GEO>(e, plane, x, nA, nB, sx, sy, dx, dy, Fb, c,
              AF + B.afi_off + (int64_t)n * kAF * nf + f, nf, vg, &m, gx, gy,
              Mb ? Mb + B.afi_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
 
-template <bool NT, bool MV>
+template <bool NT, bool MV, bool GEO>
 __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const double *ext, const double *SJ,
                              const double *dJ, const double *rbar, Consts c, double *AF, Motion mo,
                              const double *xy, double *Mb, int64_t tid_) {
@@ -268,7 +270,7 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
         const int64_t kA = (int64_t)j * (B.ni + 1) + i;
         vg = moving_geo(mo, B, n, xy, kA, kA + 1, sx, sy, dx, dy, m, gx, gy);
     }
-    face_rev<NT, MV>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
+    face_rev<NT, MV, GEO>(e, plane, x, nB, nA, sx, sy, dx, dy, Fb, c,
              AF + B.afj_off + (int64_t)n * kAF * nf + f, nf, vg, &m, gx, gy,
              Mb ? Mb + B.afj_off / kAF * 2 + (int64_t)n * 2 * nf + f : nullptr, nf);
 }
@@ -277,8 +279,10 @@ __device__ __forceinline__ void adj_face_j(const BlockDesc *blks, int b, const d
 // items [128 w, 128 w + 128) with its first half and the j-face items of the
 // same range with its second (items snapshot-major, so both halves read the
 // same rows of the same snapshot); xcd: XCD-aware workgroup order
-// (launched with xcd_grid workgroups), else the launch order
-template <bool NT, bool MV>
+// (launched with xcd_grid workgroups), else the launch order.  GEO: the S and
+// d adjoints (records 22..25) are formed and stored, for the coordinate
+// adjoints; without them that part of the reverse sweep is not compiled.
+template <bool NT, bool MV, bool GEO>
 __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b, const double *ext,
                                                    const double *SI, const double *dI,
                                                    const double *SJ, const double *dJ,
@@ -293,9 +297,9 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
     if (L < 0) return;
     const int64_t t = L * kHalf + (threadIdx.x % kHalf);
     if (threadIdx.x < kHalf) {
-        if (t < nI) adj_face_i<NT, MV>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, MbI, t);
+        if (t < nI) adj_face_i<NT, MV, GEO>(blks, b, ext, SI, dI, rbar, c, AFI, mo, xy, MbI, t);
     } else if (t < nJ) {
-        adj_face_j<NT, MV>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, MbJ, t);
+        adj_face_j<NT, MV, GEO>(blks, b, ext, SJ, dJ, rbar, c, AFJ, mo, xy, MbJ, t);
     }
 }
 
@@ -1232,6 +1236,19 @@ bool fold_per_snap(const BlockDesc &B) { return (int64_t)B.ni * B.nj < 256 * (in
 int adj_xcd(int64_t n) { return n < ((int64_t)1 << 22); }
 unsigned adj_grid(int64_t n) { return adj_xcd(n) ? xcd_grid(n) : nblk(n); }
 
+typedef void (*FaceKernel)(const BlockDesc *, int, const double *, const double *, const double *,
+                           const double *, const double *, const double *, Consts, double *, double *,
+                           int64_t, int, Motion, const double *, double *, double *);
+
+FaceKernel face_kernel(bool nt, bool mv, bool geo) {
+    if (geo) {
+        if (mv) return nt ? k_adj_faces<true, true, true> : k_adj_faces<false, true, true>;
+        return nt ? k_adj_faces<true, false, true> : k_adj_faces<false, false, true>;
+    }
+    if (mv) return nt ? k_adj_faces<true, true, false> : k_adj_faces<false, true, false>;
+    return nt ? k_adj_faces<true, false, false> : k_adj_faces<false, false, false>;
+}
+
 void launch_wall_motion(hb_grid *g, double *xybar, hipStream_t s) {
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
@@ -1252,12 +1269,12 @@ void launch_alpha(hb_grid *g, hipStream_t s) {
 }  // namespace
 
 int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double *qbar,
-                            double *xybar, double *flowbar, hipStream_t s) {
+                            double *xybar, double *flowbar, hipStream_t s, bool fill) {
     int rc = adjoint_setup(g);
     if (rc) return rc;
     double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
     const Consts c = g->consts;
-    for (int b = 0; b < g->nblocks; ++b) {
+    for (int b = 0; b < g->nblocks && fill; ++b) {
         rc = plain_ghost_fill(g, b, q, ext, s);
         if (rc) return rc;
     }
@@ -1272,8 +1289,7 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         const bool nt = (double)kAF * 8.0 * (double)(nI + nJ) > 256.0 * (1 << 20);
         const int64_t nw = 256 * (((nI > nJ ? nI : nJ) + 127) / 128);
         const bool mv = g->motion.tab != nullptr;
-        hipLaunchKernelGGL(mv ? (nt ? k_adj_faces<true, true> : k_adj_faces<false, true>)
-                              : (nt ? k_adj_faces<true, false> : k_adj_faces<false, false>),
+        hipLaunchKernelGGL(face_kernel(nt, mv, xybar != nullptr),
                            dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
                            rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d, mbi, mbj);
@@ -1359,13 +1375,19 @@ int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const doubl
         hipLaunchKernelGGL(k_adj_dtv, dim3(nblk((int64_t)B.ni * B.nj)), dim3(kBS), 0, s, g->blk_d, b,
                            q, g->SI_d, g->SJ_d, g->V_d, g->consts, g->it_dtv_d, g->motion, g->C_d);
     }
+    // q is fixed over the iteration: its ghost-extended copy is filled once
+    double *ext = g->ext_d ? g->ext_d : g->ext_adj_d;
+    for (int b = 0; b < g->nblocks; ++b) {
+        rc = plain_ghost_fill(g, b, q, ext, s);
+        if (rc) return rc;
+    }
     const int ns = g->solver.n_stages;
     for (int it = 0; it < n_iter; ++it) {
         rc = check_hip(hipMemcpyAsync(g->it_lam0_d, lam, sizeof(double) * g->n_state,
                                       hipMemcpyDeviceToDevice, s), "lambda copy");
         if (rc) return rc;
         for (int k = 0; k < ns; ++k) {
-            rc = launch_residual_adjoint(g, q, lam, g->it_qbar_d, nullptr, nullptr, s);
+            rc = launch_residual_adjoint(g, q, lam, g->it_qbar_d, nullptr, nullptr, s, false);
             if (rc) return rc;
             int64_t po = 0;
             const bool norm = (k == 0) && resnorm;

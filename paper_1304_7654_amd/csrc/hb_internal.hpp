@@ -320,8 +320,10 @@ int fused_rk_iterate(hb_grid *g, double *q, int n_iter, double *resnorm, hipStre
 int launch_forces(hb_grid *g, const double *q, double *cf, hipStream_t s);
 
 // adjoint.hip
+// fill = false: the ghost-extended copy of q is already in place (a caller
+// that evaluates several products at one state)
 int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, double *qbar,
-                            double *xybar, double *flowbar, hipStream_t s);
+                            double *xybar, double *flowbar, hipStream_t s, bool fill = true);
 int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, double *qbar,
                           double *xybar, double *flowbar, hipStream_t s);
 int launch_adjoint_iterate(hb_grid *g, const double *q, double *lam, const double *gq,

@@ -74,9 +74,14 @@ def test_moving_residual_adjoint_matches_oracle(name, pi, pj, batched):
     assert float((qb - qref).abs().max()) <= 1e-10 * float(qref.abs().max())
     assert _rel(xyb.cpu(), xr) <= 1e-11
     assert abs(float(ab) - float(aref)) <= 1e-11 * abs(float(aref))
-    qb2 = g.residual_adjoint(q.to(DEV), rbar.to(DEV))          # without coordinates: the same qbar
+    # without coordinates: the same qbar up to rounding (the face kernel
+    # that skips the coordinate records is compiled separately, and its
+    # shared arithmetic may fuse multiply-adds differently)
+    qb2 = g.residual_adjoint(q.to(DEV), rbar.to(DEV))
     torch.cuda.synchronize()
-    assert torch.equal(qb2.cpu(), qb)
+    _say("  qbar without coordinates: rel to qbar", _rel(qb2.cpu(), qb))
+    assert _rel(qb2.cpu(), qb) <= 1e-13
+    assert _rel(qb2.cpu(), qref) <= 1e-11
     g.close()
 
 
