@@ -3,7 +3,8 @@ allocated ahead, so that the calls themselves allocate nothing.  Checked by
 the device's free memory (unchanged across a prepared call, reduced by an
 unprepared first call) and by capturing prepared calls into a HIP graph,
 whose replays (with eager work in between) must equal the eager results bit
-for bit."""
+for bit; the node-coordinate adjoints to rounding, as their ghost-side terms
+are FP64 atomic adds whose order can differ from run to run."""
 import sys
 
 import pytest
@@ -66,7 +67,10 @@ def test_prepared_adjoint_allocates_nothing_and_captures():
             t.fill_(float("nan"))
         graph.replay()
         torch.cuda.synchronize()
-        assert all(torch.equal(a, b) for a, b in zip((qbar, xybar, fbar), ref)), k
+        assert torch.equal(qbar, ref[0]) and torch.equal(fbar, ref[2]), k
+        d = float((xybar - ref[1]).norm() / ref[1].norm())
+        _say("  replay", k, "xybar rel to the eager call", d)
+        assert d <= 1e-14, (k, d)
         _ = (q * 2.0).sum().item()                  # eager work between replays
     g.close()
 
