@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 # FP32 vector peak (packed FP32 counted; packed FP32 instructions are not
-# used by this build, so half of it is the reachable vector rate)
+# used by this library, so half of it is the reachable vector rate)
 PEAK_FP32_TFLOPS = 157.3
 # VALU issue capacity: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a 64-wide
 # wave's non-packed FP32 instruction occupies its SIMD for 4 cycles)
@@ -383,7 +383,7 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the library runs on one GPU only; --gpus %d is not supported "
               "(the block decomposition over several GPUs is not built)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)

@@ -50,7 +50,7 @@ enum {
     HB_ERR_DEVICE = -2,       /* a HIP call failed                       */
     HB_ERR_OOM = -3,          /* device allocation failed                */
     HB_ERR_NONFINITE = -4,    /* a non-finite or non-physical state seen */
-    HB_ERR_UNSUPPORTED = -5   /* valid request this build does not do    */
+    HB_ERR_UNSUPPORTED = -5   /* valid request the library does not do   */
 };
 
 /* Boundary kinds, per block side (imin, imax, jmin, jmax). */
