@@ -434,25 +434,41 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
 // Conserved adjoint of cell (t) and snapshot n: own primitive adjoint plus
 // its ghost copies, through the primitive map; hw: (D^T rbar)_n of the cell.
 // Writes qbar and returns the cell-area adjoint share rbar . (D Q) of n.
-__device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDesc &B, int64_t t, int n,
-                                           const double *q, const double *WB, const int *fptr,
-                                           const int *fb, const int *fp, const int *fm, double vol,
-                                           const Consts &c, const double hw[4], double *qbar) {
+// The cell's state and own ghost-extended adjoint of snapshot n (t = cell
+// of block B).
+struct FoldIn {
+    double q[4], w[4];
+};
+__device__ __forceinline__ FoldIn fold_load(const BlockDesc &B, int64_t t, int n, const double *q,
+                                            const double *WB) {
     const int64_t plane = (int64_t)B.ni * B.nj;
     const int i = (int)(t % B.ni), j = (int)(t / B.ni);
     const int we = B.ni + 4;
     const int64_t eplane = (int64_t)we * (B.nj + 4);
     const int64_t own = (int64_t)(j + 2) * we + i + 2;
-    const int64_t gc = B.cell_off + t;
-    const double gm1 = c.gamma - 1.0;
-    const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane;
-    // the cell's state and own adjoint are loaded before the ghost-copy
-    // list is walked, so that their loads overlap its round trips
     const double *qc = q + B.q_off + (int64_t)n * 4 * plane + t;
-    const double qn[4] = {qc[0], qc[plane], qc[2 * plane], qc[3 * plane]};
-    double wbv[4];
-    for (int v = 0; v < 4; ++v) wbv[v] = wbn[v * eplane + own];
-    for (int k = fptr[gc]; k < fptr[gc + 1]; ++k) {
+    const double *wbn = WB + B.ext_off + (int64_t)n * 4 * eplane + own;
+    FoldIn r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        r.q[v] = qc[v * plane];
+        r.w[v] = wbn[v * eplane];
+    }
+    return r;
+}
+
+// Snapshot n of cell t: the ghost copies [k0, k1) of the fold list added to
+// the own adjoint, the primitive-to-conserved transpose, plus V (D^T rbar)
+// (hw); stores q-bar and returns the cell-area term Q . hw.
+__device__ __forceinline__ double fold_finish(const BlockDesc *blks, const BlockDesc &B, int64_t t, int n,
+                                              const FoldIn &in, const double *WB, int k0, int k1,
+                                              const int *fb, const int *fp, const int *fm, double vol,
+                                              const Consts &c, const double hw[4], double *qbar) {
+    const int64_t plane = (int64_t)B.ni * B.nj;
+    const double gm1 = c.gamma - 1.0;
+    const double *qn = in.q;
+    double wbv[4] = {in.w[0], in.w[1], in.w[2], in.w[3]};
+    for (int k = k0; k < k1; ++k) {
         const BlockDesc &S = blks[fb[k]];
         const int64_t sp = (int64_t)(S.ni + 4) * (S.nj + 4);
         const double *ws = WB + S.ext_off + (int64_t)n * 4 * sp + fp[k];
@@ -474,6 +490,15 @@ __device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDes
         vb += qn[v] * hw[v];
     }
     return vb;
+}
+
+__device__ __forceinline__ double fold_one(const BlockDesc *blks, const BlockDesc &B, int64_t t, int n,
+                                           const double *q, const double *WB, const int *fptr,
+                                           const int *fb, const int *fp, const int *fm, double vol,
+                                           const Consts &c, const double hw[4], double *qbar) {
+    const int64_t gc = B.cell_off + t;
+    const FoldIn in = fold_load(B, t, n, q, WB);
+    return fold_finish(blks, B, t, n, in, WB, fptr[gc], fptr[gc + 1], fb, fp, fm, vol, c, hw, qbar);
 }
 
 // interior cells: own adjoint + ghost copies -> conserved adjoint + HB
@@ -576,7 +601,14 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
             for (int v = 0; v < 4; ++v)
                 rb[m][v] = (rbar && m < ns) ? rbar[B.q_off + ((int64_t)m * 4 + v) * plane + t] : 0.0;
         double vb = 0.0;
+        // the next snapshot's loads are issued before this snapshot's
+        // arithmetic and stores (one memory round trip per snapshot is
+        // otherwise exposed)
+        const int k0 = fptr[gc], k1 = fptr[gc + 1];
+        FoldIn nx = fold_load(B, t, 0, q, WB);
         for (int n = 0; n < ns; ++n) {
+            const FoldIn cur = nx;
+            if (n + 1 < ns) nx = fold_load(B, t, n + 1, q, WB);
             double hw[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int m = 0; m < kMaxNs; ++m) {
@@ -586,7 +618,7 @@ __global__ void __launch_bounds__(kBS) k_adj_fold(const BlockDesc *blks, int b, 
                     for (int v = 0; v < 4; ++v) hw[v] += d * rb[m][v];
                 }
             }
-            vb += fold_one(blks, B, t, n, q, WB, fptr, fb, fp, fm, vol, c, hw, qbar);
+            vb += fold_finish(blks, B, t, n, cur, WB, k0, k1, fb, fp, fm, vol, c, hw, qbar);
         }
         // adjoint of the cell area (its node derivatives are taken by the
         // coordinate node gather)

@@ -176,3 +176,54 @@ def test_adjoint_large_block_against_gpu_differences():
     _say("  large alpha0", fd, float(ab))
     assert abs(fd - float(ab)) <= 1e-4 * abs(fd), (fd, float(ab))
     g.close()
+
+
+@pytest.mark.parametrize("name", ["cyl_tiny", "naca_tiny"])
+def test_adjoint_iteration_stage_by_stage(name):
+    """Two adjoint iterations lam <- lam0 - alpha_k (dtau/V)(J^T lam + gq)
+    with the frozen local steps, against the same recursion on the oracle's
+    reverse products (the first-stage norms too).  The iteration fills the
+    ghost-extended copy of its fixed state once per call: a residual adjoint
+    at another state run just before it, and a second iteration call after
+    it, must not change its result (bit for bit against a fresh grid)."""
+    p = synth.make_problem(name)
+    p.flow.alpha0 = 0.02
+    blocks, flow, solver = O.from_synth(p)
+    q = torch.as_tensor(synth.initial_state(p))
+    gen = torch.Generator().manual_seed(21)
+    gq = torch.randn(q.shape, generator=gen, dtype=torch.float64)
+    lam0 = 1e-2 * torch.randn(q.shape, generator=gen, dtype=torch.float64)
+    q2 = q * (1.0 + 1e-2 * torch.randn(q.shape, generator=gen, dtype=torch.float64))
+    g = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=1)
+    lg = lam0.to(DEV)
+    norms = torch.zeros(2, dtype=torch.float64, device=DEV)
+    g.residual_adjoint(q2.to(DEV), gq.to(DEV))                 # another state first
+    g.adjoint_iterate(q.to(DEV), lg, gq.to(DEV), 2, norms)
+    torch.cuda.synchronize()
+    vols = [O.metrics(b.xy)[2] for b in blocks]
+    dtv = O.join([(O.local_dt(b, qb, flow, solver) / V)[:, None].expand(-1, 4, -1, -1)
+                  for b, qb, V in zip(blocks, O.split(blocks, q), vols)])
+    lam, ref_norms = lam0.clone(), []
+    for _ in range(2):
+        base = lam.clone()
+        for k, a in enumerate(solver.rk_alpha):
+            r = O.residual_vjp(blocks, q, flow, solver, lam, p.cuts)[0] + gq
+            if k == 0:
+                s = sum(float(((rb / V) ** 2).sum()) for rb, V in zip(O.split(blocks, r), vols))
+                ref_norms.append((s / q.numel()) ** 0.5)
+            lam = base - a * dtv * r
+    err = _rel(lg.cpu(), lam)
+    _say("  lambda rel", err, "norms", norms.cpu().tolist(), ref_norms)
+    assert err <= 1e-11
+    for a, b in zip(norms.cpu().tolist(), ref_norms):
+        assert abs(a - b) <= 1e-11 * b
+    # the same two iterations on a fresh grid, and a second call on this one
+    g2 = hb.Grid(p.blocks, p.flow, p.solver, cuts=p.cuts, precision=0, batched=1)
+    lf = lam0.to(DEV)
+    g2.adjoint_iterate(q.to(DEV), lf, gq.to(DEV), 2)
+    lr = lam0.to(DEV)
+    g.adjoint_iterate(q.to(DEV), lr, gq.to(DEV), 2)
+    torch.cuda.synchronize()
+    assert torch.equal(lf, lg) and torch.equal(lr, lg)
+    g.close()
+    g2.close()
