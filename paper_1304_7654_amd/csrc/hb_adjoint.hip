@@ -303,6 +303,32 @@ __global__ void __launch_bounds__(kBS) k_adj_faces(const BlockDesc *blks, int b,
     }
 }
 
+// (u, v, T) adjoint of node (i, j) of one snapshot (ai, aj: that snapshot's
+// i- and j-face records): the sum over the node's four faces in a fixed
+// order.  Every load is issued (faces outside the block read face 0 and add
+// zero), so that the four faces cost one memory round trip instead of four.
+__device__ __forceinline__ UVT<double> node_adj(const BlockDesc &B, const double *ai, const double *aj,
+                                                int64_t nfi, int64_t nfj, int i, int j) {
+    const int W = B.ni + 1;
+    const bool has[4] = {j < B.nj, j >= 1, i < B.ni, i >= 1};
+    const double *src[4] = {
+        ai + 16 * nfi + (has[0] ? (int64_t)j * W + i : 0),           // i-face (i, j): slot 0
+        ai + 19 * nfi + (has[1] ? (int64_t)(j - 1) * W + i : 0),     // i-face (i, j-1): slot 1
+        aj + 19 * nfj + (has[2] ? (int64_t)j * B.ni + i : 0),        // j-face (i, j): slot 1
+        aj + 16 * nfj + (has[3] ? (int64_t)j * B.ni + i - 1 : 0)};   // j-face (i-1, j): slot 0
+    double x[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) x[q][v] = src[q][v * (q < 2 ? nfi : nfj)];
+    double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) s[v] += has[q] ? x[q][v] : 0.0;
+    return UVT<double>{s[0], s[1], s[2]};
+}
+
 // node (u, v, T) adjoints: [ns][3][nj+1][ni+1]
 // Also clears this block's node-coordinate adjoints (xyb, may be null),
 // which the fold and coordinate kernels then accumulate.
@@ -321,35 +347,19 @@ __global__ void __launch_bounds__(kBS) k_adj_nodes(const BlockDesc *blks, int b,
     const int64_t k = t % nn;
     const int i = (int)(k % W), j = (int)(k / W);
     const int64_t nfi = (int64_t)W * B.nj, nfj = (int64_t)B.ni * (B.nj + 1);
-    const double *ai = AFI + B.afi_off + (int64_t)n * kAF * nfi;
-    const double *aj = AFJ + B.afj_off + (int64_t)n * kAF * nfj;
-    // the four faces at the node, in a fixed order; every load is issued
-    // (faces outside the block read face 0 and add zero), so that the four
-    // faces cost one memory round trip instead of four
-    const bool has[4] = {j < B.nj, j >= 1, i < B.ni, i >= 1};
-    const double *src[4] = {
-        ai + 16 * nfi + (has[0] ? (int64_t)j * W + i : 0),           // i-face (i, j): slot 0
-        ai + 19 * nfi + (has[1] ? (int64_t)(j - 1) * W + i : 0),     // i-face (i, j-1): slot 1
-        aj + 19 * nfj + (has[2] ? (int64_t)j * B.ni + i : 0),        // j-face (i, j): slot 1
-        aj + 16 * nfj + (has[3] ? (int64_t)j * B.ni + i - 1 : 0)};   // j-face (i-1, j): slot 0
-    double x[4][3];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) x[q][v] = src[q][v * (q < 2 ? nfi : nfj)];
-    double s[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 3; ++v) s[v] += has[q] ? x[q][v] : 0.0;
+    const UVT<double> s = node_adj(B, AFI + B.afi_off + (int64_t)n * kAF * nfi,
+                                   AFJ + B.afj_off + (int64_t)n * kAF * nfj, nfi, nfj, i, j);
     double *o = NB + B.nodeq_off + (int64_t)n * 3 * nn + k;
-    for (int v = 0; v < 3; ++v) o[v * nn] = s[v];
+    o[0] = s.u;
+    o[nn] = s.v;
+    o[2 * nn] = s.t;
 }
 
 // Primitive adjoint of ghost-extended cell t of a block (all snapshots
 // flattened: [ns][4][nj+4][ni+4]); returns this cell's alpha0 adjoint term
 // when it is a far-field ghost (ffc != 0) and alpha is asked for:
 // d(u, v)/d alpha = (-v_inf, u_inf), a mirrored ghost flips both.
+template <bool NI>
 __device__ __forceinline__ double adj_cell(const BlockDesc &B, int64_t t, int we, int64_t plane,
                                            const double *ext, const double *AFI, const double *AFJ,
                                            const double *NB, const Consts &c, double *WB,
@@ -380,7 +390,9 @@ __device__ __forceinline__ double adj_cell(const BlockDesc &B, int64_t t, int we
             for (int v = 0; v < 4; ++v) s[v] += aj[(role * 4 + v) * nfj + fj];
         }
     }
-    // nodes (i, j), (i+1, j), (i, j+1), (i+1, j+1) average this cell
+    // nodes (i, j), (i+1, j), (i, j+1), (i+1, j+1) average this cell; their
+    // adjoints from the node kernel's array, or (NI) summed here from the
+    // face records, the same sums in the same order
     UVT<double> nb{0.0, 0.0, 0.0};
     const double *nq = NB + B.nodeq_off + (int64_t)n * 3 * nn;
     for (int dj = 0; dj < 2; ++dj)
@@ -388,9 +400,11 @@ __device__ __forceinline__ double adj_cell(const BlockDesc &B, int64_t t, int we
             const int a = i + di, bb = j + dj;
             if (a < 0 || a > B.ni || bb < 0 || bb > B.nj) continue;
             const int64_t k = (int64_t)bb * W + a;
-            nb.u += 0.25 * nq[k];
-            nb.v += 0.25 * nq[nn + k];
-            nb.t += 0.25 * nq[2 * nn + k];
+            const UVT<double> na = NI ? node_adj(B, ai, aj, nfi, nfj, a, bb)
+                                      : UVT<double>{nq[k], nq[nn + k], nq[2 * nn + k]};
+            nb.u += 0.25 * na.u;
+            nb.v += 0.25 * na.v;
+            nb.t += 0.25 * na.t;
         }
     const double *e = ext + B.ext_off + (int64_t)n * 4 * plane;
     W4<double> wb{s[0], s[1], s[2], s[3]};
@@ -407,18 +421,29 @@ __device__ __forceinline__ double adj_cell(const BlockDesc &B, int64_t t, int we
 
 // primitive adjoints of every ghost-extended cell; with apart (may be null)
 // also the alpha0 adjoint of the far-field ghosts as one partial per
-// (logical) workgroup (fixed-order tree sum); xcd as for k_adj_faces
+// (logical) workgroup (fixed-order tree sum); xcd as for k_adj_faces.
+// NI: the node adjoints are summed from the face records here instead of
+// read from the node kernel's array (blocks whose records stay in the
+// last-level cache; the node kernel's launch is then left out), and this
+// kernel clears the block's node-coordinate adjoints (xyb, may be null).
+template <bool NI>
 __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b, const double *ext, const double *AFI,
                             const double *AFJ, const double *NB, Consts c, double *WB,
-                            const int8_t *ffc, const double *ffw, double *apart, int xcd) {
+                            const int8_t *ffc, const double *ffw, double *apart, int xcd, double *xyb) {
     const BlockDesc &B = blks[b];
     const int we = B.ni + 4;
     const int64_t plane = (int64_t)we * (B.nj + 4);
+    if (NI && xyb) {
+        const int64_t nn2 = 2 * (int64_t)(B.ni + 1) * (B.nj + 1);
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nn2; k += stride)
+            xyb[2 * B.node_off + k] = 0.0;
+    }
     const int64_t L = xcd ? xcd_group(plane * B.ns) : (int64_t)blockIdx.x;
     if (L < 0) return;                     // a whole padding workgroup
     const int64_t t = L * kBS + threadIdx.x;
     double acc = 0.0;
-    if (t < plane * B.ns) acc = adj_cell(B, t, we, plane, ext, AFI, AFJ, NB, c, WB, ffc, ffw, apart != nullptr);
+    if (t < plane * B.ns) acc = adj_cell<NI>(B, t, we, plane, ext, AFI, AFJ, NB, c, WB, ffc, ffw, apart != nullptr);
     if (apart) {
         __shared__ double red[kBS];
         red[threadIdx.x] = acc;
@@ -431,9 +456,6 @@ __global__ void __launch_bounds__(kBS) k_adj_cells(const BlockDesc *blks, int b,
     }
 }
 
-// Conserved adjoint of cell (t) and snapshot n: own primitive adjoint plus
-// its ghost copies, through the primitive map; hw: (D^T rbar)_n of the cell.
-// Writes qbar and returns the cell-area adjoint share rbar . (D Q) of n.
 // The cell's state and own ghost-extended adjoint of snapshot n (t = cell
 // of block B).
 struct FoldIn {
@@ -1310,7 +1332,7 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
         rc = plain_ghost_fill(g, b, q, ext, s);
         if (rc) return rc;
     }
-    // the node kernels clear xybar; the cell kernels leave the alpha0
+    // the node (or cell) kernels clear xybar; the cell kernels leave the alpha0
     // partials, which the first fold launch sums; on a moving grid the face
     // kernels store the midpoint adjoints for xybar
     double *mbi = (g->motion.tab && xybar) ? g->mb_d : nullptr;
@@ -1325,13 +1347,17 @@ int launch_residual_adjoint(hb_grid *g, const double *q, const double *rbar, dou
                            dim3(adj_grid(nw)),
                            dim3(kBS), 0, s, g->blk_d, b, ext, g->SI_d, g->dI_d, g->SJ_d, g->dJ_d,
                            rbar, c, g->AFI_d, g->AFJ_d, nI, adj_xcd(nw), g->motion, g->xy_d, mbi, mbj);
-        hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
-                           s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
-        hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
+        // records that stay in the last-level cache: the cell kernel sums
+        // the node adjoints itself (one launch fewer); else the node kernel
+        const int64_t ne = (int64_t)(B.ni + 4) * (B.nj + 4) * B.ns;
+        if (nt)
+            hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
+                               s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, xybar);
+        hipLaunchKernelGGL(nt ? k_adj_cells<false> : k_adj_cells<true>, dim3(adj_grid(ne)), dim3(kBS), 0,
                            s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d,
                            g->ffc_d + g->ffc_off[b], g->ffw_d,
-                           flowbar ? g->cpart_d + g->cpart_off[b] : (double *)nullptr,
-                           adj_xcd((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns));
+                           flowbar ? g->cpart_d + g->cpart_off[b] : (double *)nullptr, adj_xcd(ne),
+                           nt ? (double *)nullptr : xybar);
     }
     // every block's extended adjoints exist before any fold (cuts read
     // neighbours); with xybar each fold launch also runs its block's
@@ -1462,10 +1488,10 @@ int launch_forces_adjoint(hb_grid *g, const double *q, const double *cfbar, doub
                            g->blk_d, b, ext, g->xy_d, g->SJ_d, g->dJ_d, fa, c, g->AFJ_d, xybar, g->motion);
         hipLaunchKernelGGL(k_adj_nodes, dim3(nblk((int64_t)(B.ni + 1) * (B.nj + 1) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, g->AFI_d, g->AFJ_d, g->NB_d, (double *)nullptr);
-        hipLaunchKernelGGL(k_adj_cells, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
+        hipLaunchKernelGGL(k_adj_cells<false>, dim3(adj_grid((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns)), dim3(kBS), 0,
                            s, g->blk_d, b, ext, g->AFI_d, g->AFJ_d, g->NB_d, c, g->WBext_d,
                            g->ffc_d + g->ffc_off[b], g->ffw_d, (double *)nullptr,
-                           adj_xcd((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns));
+                           adj_xcd((int64_t)(B.ni + 4) * (B.nj + 4) * B.ns), (double *)nullptr);
     }
     for (int b = 0; b < g->nblocks; ++b) {
         const BlockDesc &B = g->blk[b];
